@@ -1,0 +1,379 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every oracle routine is checked here against something other than itself:
+closed forms, brute-force dense linear algebra on tiny grids, identities the
+paper states (eq. A, the convolution identity, translation invariance) and
+the worked example of Fig. 2. CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lsp_oracle as O
+from paper_1607_02560_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PI2 = math.pi ** 2
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def rand_complex(shape, seed=0):
+    r = rng(seed)
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)
+
+
+# ---------------------------------------------------------------- Sec. 2 ----
+@pytest.mark.parametrize("d,n", [(1, 16), (2, 8), (3, 4)])
+def test_plane_waves_are_eigenvectors(d, n):
+    """L e_k = 4 pi^2 |k|^2 e_k for every plane wave e_k(j) = exp(2 pi i k.j/n)."""
+    ks = np.arange(-n // 2, n // 2)
+    grids = np.meshgrid(*([np.arange(n)] * d), indexing="ij")
+    zero = np.zeros((n,) * d)
+    for kvec in np.stack(np.meshgrid(*([ks] * d), indexing="ij"), -1).reshape(-1, d):
+        phase = sum(kvec[a] * grids[a] for a in range(d))
+        e = np.exp(2j * np.pi * phase / n)
+        lam = 4 * PI2 * float(np.sum(kvec.astype(float) ** 2))
+        y = O.ps_apply(zero, e)
+        assert np.allclose(y, lam * e, rtol=1e-12, atol=1e-11 * max(lam, 1.0))
+
+
+def test_laplacian_1d_hand_values():
+    """n = 4 entries worked by hand: diagonal pi^2 (16+2)/3 = 6 pi^2, offset 1
+    gives 2 pi^2 (-1)/sin^2(pi/4) = -4 pi^2, offset 2 gives 2 pi^2 / sin^2(pi/2) = 2 pi^2."""
+    L = O.laplacian_1d_dense(4)
+    assert L[0, 0] == pytest.approx(6 * PI2, rel=1e-15)
+    assert L[0, 1] == pytest.approx(-4 * PI2, rel=1e-14)
+    assert L[0, 3] == pytest.approx(-4 * PI2, rel=1e-14)
+    assert L[0, 2] == pytest.approx(2 * PI2, rel=1e-14)
+    # rows sum to zero: the constant is the k = 0 mode
+    assert np.allclose(L.sum(axis=1), 0.0, atol=1e-11)
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32])
+def test_laplacian_1d_spectrum(n):
+    """The closed-form matrix has exactly the eigenvalues 4 pi^2 k^2, k in K."""
+    L = O.laplacian_1d_dense(n)
+    assert np.allclose(L, L.T)
+    ev = np.sort(np.linalg.eigvalsh(L))
+    k = np.arange(-n // 2, n // 2)
+    ref = np.sort(4 * PI2 * k.astype(float) ** 2)
+    assert np.allclose(ev, ref, rtol=1e-10, atol=1e-9)
+
+
+@pytest.mark.parametrize("d,n,seed", [(1, 16, 0), (2, 8, 1), (3, 4, 2), (2, 6, 3)])
+def test_ps_apply_matches_dense(d, n, seed):
+    """FFT route of eq. (dmodel) equals the dense (L + diag v) u."""
+    v = rng(seed).uniform(-500.0, 100.0, (n,) * d)
+    u = rand_complex((n,) * d, seed + 10)
+    A = O.dense_operator(v)
+    y_dense = (A @ u.reshape(-1)).reshape(u.shape)
+    y = O.ps_apply(v, u)
+    assert np.linalg.norm(y - y_dense) <= 1e-12 * np.linalg.norm(y_dense)
+
+
+def test_ps_apply_maps_real_to_real():
+    v = rng(4).uniform(-10, 10, (8, 8))
+    u = rng(5).standard_normal((8, 8))
+    y = O.ps_apply(v, u.astype(complex))
+    assert np.max(np.abs(y.imag)) < 1e-10 * np.max(np.abs(y.real))
+
+
+# --------------------------------------------------------- Sec. 3 and 4.2 ---
+@pytest.mark.parametrize("d,n,m_shift", [(2, 8, -7), (3, 4, -3), (1, 16, -11), (2, 8, 5)])
+def test_green_kernel_is_first_column_of_inverse(d, n, m_shift):
+    """g_s = (L + s)^-1 [:, 0] and g_s * g_s = (L + s)^-2 [:, 0], dense brute force."""
+    s = (4 * m_shift + 2) * PI2
+    g, gam = O.green_kernels(d, n, s)
+    A = O.dense_laplacian(d, n) + s * np.eye(n ** d)
+    G = np.linalg.inv(A)
+    assert np.allclose(g.reshape(-1), G[:, 0], rtol=1e-10, atol=1e-14 * np.abs(G).max())
+    G2 = G @ G
+    assert np.allclose(gam.reshape(-1), G2[:, 0], rtol=1e-9, atol=1e-13 * np.abs(G2).max())
+
+
+@pytest.mark.parametrize("d,n,m_shift", [(2, 32, -40), (3, 8, -10), (2, 16, 3)])
+def test_green_kernel_sum_rules(d, n, m_shift):
+    """Sum of g_s is its k = 0 coefficient 1/s, sum of g_s*g_s is 1/s^2, and
+    (g_s * g_s)[0] = sum_j g_s[j]^2 because g_s is even (Sec. 4.2)."""
+    s = (4 * m_shift + 2) * PI2
+    g, gam = O.green_kernels(d, n, s)
+    assert g.sum() == pytest.approx(1.0 / s, rel=1e-10)
+    assert gam.sum() == pytest.approx(1.0 / s ** 2, rel=1e-10)
+    assert gam.reshape(-1)[0] == pytest.approx(float(np.sum(g * g)), rel=1e-10)
+    # evenness in every coordinate and symmetry under axis permutation
+    for ax in range(d):
+        assert np.allclose(g, np.roll(np.flip(g, ax), 1, ax), atol=1e-14 * np.abs(g).max())
+    assert np.allclose(g, np.swapaxes(g, 0, 1), atol=1e-14 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("m_shift", [-300, -7, 0, 12])
+def test_shift_form_avoids_resonance(m_shift):
+    """With s = (4m+2) pi^2, lambda_k + s = 2 pi^2 (2(|k|^2 + m) + 1), an odd
+    multiple of 2 pi^2, so |lambda_k + s| >= 2 pi^2 (Sec. 4.1)."""
+    s = (4 * m_shift + 2) * PI2
+    lam = O.symbol(2, 64)
+    q = (lam + s) / (2 * PI2)
+    assert np.allclose(q, np.round(q), atol=1e-6)
+    assert np.all(np.round(q).astype(np.int64) % 2 == 1)
+    assert np.min(np.abs(lam + s)) >= 2 * PI2 * (1 - 1e-9)
+
+
+# ---------------------------------------------------------------- Sec. 4.1 --
+def test_snap_is_nearest_of_form():
+    """snap(x) is the nearest value of {(4m+2) pi^2} (brute force over m)."""
+    r = rng(7)
+    for x in np.concatenate([r.uniform(-2e6, 2e6, 200), r.uniform(-100, 100, 200)]):
+        ms = np.arange(math.floor(x / (4 * PI2)) - 3, math.floor(x / (4 * PI2)) + 4)
+        cands = (4 * ms + 2) * PI2
+        best = cands[np.argmin(np.abs(cands - x))]
+        assert O.snap_shift(float(x)) == pytest.approx(best, rel=1e-15, abs=1e-12)
+
+
+def test_shift_list_spreads_evenly():
+    v = np.linspace(-1000.0, -200.0, 64).reshape(8, 8)
+    S = O.shift_list(v, 4)
+    centres = -1000.0 + (np.arange(4) + 0.5) * 200.0
+    assert np.all(np.diff(S) > 0)
+    for s, c in zip(S, centres):
+        assert abs(s - c) <= 2 * PI2 + 1e-9
+        m = (s / PI2 - 2) / 4
+        assert m == pytest.approx(round(m), abs=1e-9)
+
+
+def test_shift_list_deduplicates_and_constant_v():
+    v = np.full((8, 8), -123.0)
+    S = O.shift_list(v, 16)
+    assert S.shape == (1,)
+    assert S[0] == pytest.approx(O.snap_shift(-123.0))
+    # a range narrower than 4 pi^2 collapses to at most 2 distinct shifts
+    v2 = np.linspace(-100.0, -80.0, 64).reshape(8, 8)
+    assert len(O.shift_list(v2, 32)) <= 2
+
+
+def test_assign_shifts_bruteforce():
+    v = rng(8).uniform(-900, -100, (16, 16))
+    S = O.shift_list(v, 7)
+    idx = O.assign_shifts(v, S)
+    for j, vj in enumerate(v.reshape(-1)):
+        dists = [abs(s - vj) for s in S]
+        best = min(range(len(S)), key=lambda i: (dists[i], i))
+        assert idx.reshape(-1)[j] == best
+    # exact ties go to the lower index (the smaller shift)
+    S_t = np.array([-10.0, -6.0, -2.0])
+    v_t = np.array([[-8.0, -4.0], [-12.0, 0.0]])
+    assert O.assign_shifts(v_t, S_t).tolist() == [[0, 1], [0, 2]]
+
+
+def test_default_shift_counts_match_tables():
+    """The paper's tables use |S| = n/16 in 2D and n/4 in 3D."""
+    with open(os.path.join(GOLDEN, "shift_counts.json")) as fh:
+        gold = json.load(fh)
+    for n, cnt in gold["2d"].items():
+        assert int(n) // 16 == cnt
+    for n, cnt in gold["3d"].items():
+        assert int(n) // 4 == cnt
+
+
+# ------------------------------------------------------- eq. (A), Sec. 4.2 --
+@pytest.mark.parametrize("d,n,t,m_shift", [(2, 16, 1, -20), (2, 16, 2, -30), (3, 8, 1, -9),
+                                           (1, 32, 2, -15)])
+def test_gram_identity(d, n, t, m_shift):
+    """B B^T = A1 - A2 with B = G_s[mu_0, mu_0^c] built explicitly (eq. A)."""
+    s = (4 * m_shift + 2) * PI2
+    g, gam = O.green_kernels(d, n, s)
+    offs = O.offsets(d, t)
+    B = O.offneighbourhood_block(g, offs)
+    assert B.shape == (offs.shape[0], n ** d - offs.shape[0])
+    _, A1, A2, M = O.gram(g, gam, offs)
+    BBt = B @ B.T
+    assert np.allclose(M, BBt, rtol=1e-9, atol=1e-12 * np.abs(A1).max())
+
+
+def test_offsets_order():
+    offs = O.offsets(2, 1)
+    assert offs.tolist() == [[-1, -1], [-1, 0], [-1, 1], [0, -1], [0, 0], [0, 1],
+                             [1, -1], [1, 0], [1, 1]]
+    assert O.offsets(3, 2).shape == (125, 3)
+
+
+@pytest.mark.parametrize("d,n,t,m_shift", [(2, 16, 1, -20), (2, 16, 2, -30), (3, 8, 1, -9)])
+def test_null_vector_is_the_optimal_stencil(d, n, t, m_shift):
+    """alpha from the eigen route is the minimiser of ||alpha^T B||_2 (Sec. 3):
+    it agrees with the last left singular vector of B (the definition route)
+    within the eigenvector sensitivity, attains sigma_min, and beats random
+    unit vectors."""
+    s = (4 * m_shift + 2) * PI2
+    g, gam = O.green_kernels(d, n, s)
+    offs = O.offsets(d, t)
+    _, _, _, M = O.gram(g, gam, offs)
+    alpha, w, smin, kappa = O.null_vector(M)
+    alpha_svd, sv = O.null_vector_svd(g, offs)
+    tol = max(1e-10, 50 * np.finfo(float).eps * kappa)
+    assert np.linalg.norm(alpha - alpha_svd) <= tol
+    B = O.offneighbourhood_block(g, offs)
+    assert np.linalg.norm(alpha @ B) == pytest.approx(sv[-1], rel=1e-6)
+    assert smin == pytest.approx(sv[-1], rel=1e-6)
+    X = rng(9).standard_normal((1000, offs.shape[0]))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    assert np.all(np.linalg.norm(X @ B, axis=1) >= sv[-1] * (1 - 1e-9))
+
+
+def test_normalise_sign():
+    a = O.normalise_sign(np.array([0.1, -0.9, 0.2]))
+    assert np.linalg.norm(a) == pytest.approx(1.0)
+    assert a[1] > 0
+
+
+# ------------------------------------------------- stencils, Sec. 4.1-4.2 --
+def _dense_setup(v, t, num_shifts):
+    d, n = v.ndim, v.shape[0]
+    setup = O.stencil_setup(v, t, num_shifts)
+    L = O.dense_laplacian(d, n)
+    Nn = n ** d
+    Q = np.zeros((Nn, Nn))
+    cols = O.neighbour_columns(d, n, setup["offsets"])
+    for j in range(Nn):
+        Q[j, cols[j]] = setup["alpha"][setup["idx"].reshape(-1)[j]]
+    return setup, L, Q, cols
+
+
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1)])
+def test_C_is_truncated_QG_and_residual_is_sigma(d, n, t):
+    """C[j, mu_j] = (Q G_{s_j})[j, mu_j] and ||(Q G_{s_j})[j, mu_j^c]|| = sigma_min
+    (Sec. 3 truncation, Sec. 4.1 local shifts), dense on a tiny grid."""
+    v = rng(11).uniform(-400, -150, (n,) * d)
+    setup, L, Q, cols = _dense_setup(v, t, 3)
+    Nn = n ** d
+    idx = setup["idx"].reshape(-1)
+    Crow = O.sparse_C(setup, d, n).toarray()
+    for j in range(0, Nn, max(1, Nn // 17)):
+        s = setup["S"][idx[j]]
+        Gs = np.linalg.inv(L + s * np.eye(Nn))
+        qg = Q[j] @ Gs
+        mask = np.zeros(Nn, dtype=bool)
+        mask[cols[j]] = True
+        assert np.allclose(Crow[j, mask], qg[mask], rtol=1e-8, atol=1e-12 * np.abs(qg).max())
+        assert np.all(Crow[j, ~mask] == 0.0)
+        assert np.linalg.norm(qg[~mask]) == pytest.approx(setup["sigma_min"][idx[j]], rel=1e-5)
+
+
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2)])
+def test_CA_minus_P_identity(d, n, t):
+    """Row j of C A - P equals -E_j (L + s_j I), E_j = (Q G_{s_j})[j, mu_j^c]
+    (zero on mu_j): the truncation error of eq. (PC) written exactly."""
+    v = rng(12).uniform(-400, -150, (n,) * d)
+    setup, L, Q, cols = _dense_setup(v, t, 3)
+    Nn = n ** d
+    A = L + np.diag(v.reshape(-1))
+    P = O.sparse_P(setup, d, n).toarray()
+    Cm = O.sparse_C(setup, d, n).toarray()
+    idx = setup["idx"].reshape(-1)
+    lhs = Cm @ A - P
+    for j in range(0, Nn, max(1, Nn // 13)):
+        s = setup["S"][idx[j]]
+        Ls = L + s * np.eye(Nn)
+        E = Q[j] @ np.linalg.inv(Ls)
+        E[cols[j]] = 0.0
+        rhs = -E @ Ls
+        assert np.allclose(lhs[j], rhs, rtol=1e-7, atol=1e-9 * np.abs(Q[j]).max() * np.abs(L).max())
+
+
+def test_P_row_formula_dense():
+    """P = Q + C diag(v - s_j) row by row (Sec. 4.1)."""
+    v = rng(13).uniform(-400, -150, (8, 8))
+    setup, L, Q, cols = _dense_setup(v, 1, 3)
+    P = O.sparse_P(setup, 2, 8).toarray()
+    Cm = O.sparse_C(setup, 2, 8).toarray()
+    s_j = setup["S"][setup["idx"].reshape(-1)]
+    ref = Q + Cm * (v.reshape(1, -1) - s_j.reshape(-1, 1))
+    assert np.allclose(P, ref, rtol=1e-13, atol=1e-15)
+
+
+def test_constant_potential_translation_invariance():
+    """Constant v: one shift, identical rows (Sec. 3, translation invariance),
+    and the preconditioned operator is circulant with the closed-form
+    eigenvalues C_hat(k) (lambda_k + v) / P_hat(k) from the stencil symbols."""
+    d, n, t = 2, 8, 1
+    v0 = -300.0
+    v = np.full((n, n), v0)
+    setup = O.stencil_setup(v, t, 5)
+    assert len(setup["S"]) == 1
+    P = setup["P"]
+    assert np.allclose(P, P[0][None, :], rtol=0, atol=0)
+    offs = setup["offsets"]
+    k = O.wavenumbers(n)
+    K = np.stack(np.meshgrid(k, k, indexing="ij"), -1).reshape(-1, 2)
+    phase = np.exp(2j * np.pi * (K @ offs.T) / n)           # symbol sum_a c_a e^{2 pi i k.a/n}
+    Phat = phase @ P[0]
+    Chat = phase @ setup["C"][0]
+    lam = 4 * PI2 * np.sum(K.astype(float) ** 2, axis=1)
+    pred = np.sort_complex(np.round(Chat * (lam + v0) / Phat, 8))
+    Pm = O.sparse_P(setup, d, n).toarray()
+    Cm = O.sparse_C(setup, d, n).toarray()
+    A = O.dense_operator(v)
+    ev = np.linalg.eigvals(np.linalg.solve(Pm, Cm @ A))
+    assert np.allclose(np.sort_complex(np.round(ev, 8)), pred, rtol=1e-6, atol=1e-6)
+
+
+def test_fig2_row_of_QG_decays():
+    """Fig. 2: 1D, n = 32, row j = 16, s = -62 pi^2, compact stencil. The
+    truncated entries of |QG[16, j_c]| decay away from j_c = 16."""
+    with open(os.path.join(GOLDEN, "fig2_qg_row.json")) as fh:
+        fx = json.load(fh)
+    n, j, t = fx["n"], fx["j"], fx["t"]
+    s = fx["s_over_pi2"] * PI2
+    assert O.snap_shift(s) == pytest.approx(s)            # s has the form (4m+2) pi^2
+    g, gam = O.green_kernels(1, n, s)
+    offs = O.offsets(1, t)
+    _, _, _, M = O.gram(g, gam, offs)
+    alpha, _, smin, _ = O.null_vector(M)
+    G = np.linalg.inv(O.dense_laplacian(1, n) + s * np.eye(n))
+    q = np.zeros(n)
+    q[(j + offs[:, 0]) % n] = alpha
+    row = np.abs(q @ G)
+    dist = np.abs(np.arange(n) - j)
+    near = row[(dist >= 2) & (dist <= 3)].max()
+    far = row[dist >= 8].max()
+    assert far < near
+    # reserved entries dominate the truncated ones; the truncated norm is sigma_min
+    assert row[dist <= 1].min() > far
+    assert np.linalg.norm(row[dist >= 2]) == pytest.approx(smin, rel=1e-6)
+
+
+# ----------------------------------------------------------- Sec. 5 GMRES --
+def test_gmres_identity_preconditioner_small():
+    """gmres_right with M = I solves a random non-symmetric system."""
+    r = rng(14)
+    A = r.standard_normal((40, 40)) + 1j * r.standard_normal((40, 40)) + 10 * np.eye(40)
+    b = r.standard_normal(40) + 1j * r.standard_normal(40)
+    x, it, est, true_rel = O.gmres_right(lambda z: A @ z, lambda z: z, b, 1e-12, 10, 400)
+    assert true_rel < 1e-11
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-10)
+
+
+def test_gmres_exact_preconditioner_one_step():
+    r = rng(15)
+    A = r.standard_normal((30, 30)) + 5 * np.eye(30)
+    Ainv = np.linalg.inv(A)
+    b = r.standard_normal(30).astype(complex)
+    x, it, est, true_rel = O.gmres_right(lambda z: A @ z, lambda z: Ainv @ z, b, 1e-10, 40, 40)
+    assert it == 1 and true_rel < 1e-10
+
+
+@pytest.mark.slow
+def test_precond_solve_helm2d_gauss_matches_dense():
+    """Helmholtz n = 32 (3x3 stencils, |S| = 2): preconditioned GMRES reaches
+    1e-8 and matches the dense solve of eq. (dmodel)."""
+    p = W.helm2d_gauss(32)
+    u, iters, est, true_rel, setup = O.precond_solve(p.v, p.f, p.t, p.num_shifts, rtol=1e-8)
+    assert true_rel <= 1e-8
+    A = O.dense_operator(p.v)
+    u_ref = np.linalg.solve(A, p.f.reshape(-1))
+    assert np.linalg.norm(u.reshape(-1) - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+    assert iters < 60
