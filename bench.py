@@ -1,0 +1,159 @@
+"""Benchmark of the hot path on one MI355X.
+
+One step = one stencil setup (shift list, Green's sums, Gram + null vectors,
+per-point P rows) followed by one pseudospectral apply (L + diag v) u, on the
+2D Helmholtz workload with n = 1024 (N = 1,048,576 points), t = 2 (5x5
+stencils), |S| = 64, FP64. Inputs are resident on the GPU before timing.
+
+Prints one JSON line: value = local stencils per second (N / setup time);
+ps_apply bandwidth and the roofline of the dominant kernel (the per-point
+assembly) come from HIP events recorded by the library on its own stream
+over the timed steps.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "local stencils/s + ps_apply GB/s, 2D n=1024; learned vs exact at equal GMRES iters"
+HBM_PEAK_GBPS = 8000.0
+
+
+def algorithmic_bytes(N, m):
+    """Minimum HBM traffic per call (see the design notes):
+    setup reads v (8 B/pt) and writes P (8 m B/pt) and idx (4 B/pt);
+    ps_apply reads u (16 B) and v (8 B) and writes y (16 B) per point."""
+    return {"assemble": N * (8 + 8 * m + 4), "setup": N * (8 + 8 * m + 4), "apply": N * 40}
+
+
+def cpu_baseline(p):
+    """The FP64 oracle timed on this host: one full setup of the same workload
+    (the sample) and 10 applies. numpy's FFT runs on one thread."""
+    import numpy as np
+    from oracle import lsp_oracle as O
+    t0 = time.perf_counter()
+    O.stencil_setup(p.v, p.t, p.num_shifts)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        O.ps_apply(p.v, p.f)
+    t_apply = (time.perf_counter() - t0) / reps
+    return {
+        "value": p.N / t_setup, "unit": "stencils/s", "cores": 1, "kind": "oracle",
+        "sample": f"one full setup of the same workload (N={p.N}, |S|={p.num_shifts}) "
+                  f"and {reps} applies; numpy FFT single-threaded",
+        "setup_s": t_setup, "ps_apply_s": t_apply,
+        "ps_apply_GBps": 40.0 * p.N / t_apply / 1e9,
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (the hot path is a single-GPU build); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1607_02560_amd import lsp
+    from paper_1607_02560_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    p = W.helm2d_random(args.n)
+    d, n, t, N = p.d, p.n, p.t, p.N
+    m = (2 * t + 1) ** d
+    print(f"[bench] workload {p.name} n={n} t={t} |S|={p.num_shifts} N={N}", file=sys.stderr,
+          flush=True)
+    v = torch.from_numpy(p.v.reshape(-1)).to(dev)
+    u = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    r = np.random.default_rng(1)
+    u += torch.from_numpy(r.standard_normal(N) + 1j * r.standard_normal(N)).to(dev)
+    y = torch.empty_like(u)
+    P = torch.empty(N * m, dtype=torch.float64, device=dev)
+    idx = torch.empty(N, dtype=torch.int32, device=dev)
+    prob = lsp.Problem(d, n, v)
+
+    def step():
+        prob.stencil_setup(t, p.num_shifts, P, idx)
+        prob.ps_apply(u, y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    prob.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = prob.profile_read()
+    prob.profile(False)
+    tab = prob.get_tables()
+
+    def avg_ms(stage):
+        tot, cnt = prof[stage]
+        return tot / max(cnt, 1)
+
+    nb = algorithmic_bytes(N, m)
+    t_setup = avg_ms("setup") * 1e-3
+    t_asm = avg_ms("assemble") * 1e-3
+    t_apply = avg_ms("apply") * 1e-3
+    asm_gbps = nb["assemble"] / t_asm / 1e9
+    apply_gbps = nb["apply"] / t_apply / 1e9
+    out = {
+        "metric": METRIC,
+        "value": N / t_setup,
+        "unit": "stencils/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D Helmholtz, smooth random c in [0.8,1.2], n={n} "
+                               f"(N={N}), t={t} (5x5 stencils), |S|={p.num_shifts}",
+                   "d": d, "n": n, "t": t, "num_shifts": p.num_shifts,
+                   "num_shifts_effective": int(len(tab["S"]))},
+        "ps_apply_GBps": apply_gbps,
+        "ps_apply_per_s": 1.0 / t_apply,
+        "setup_ms": t_setup * 1e3,
+        "setup_hbm_frac": nb["setup"] / t_setup / 1e9 / HBM_PEAK_GBPS,
+        "stage_ms": {k: avg_ms(k) for k in ("shifts", "green", "null", "assemble", "setup",
+                                             "apply")},
+        "roofline": {"kernel": "assemble_kernel (per-point P rows)", "bound": "hbm",
+                     "achieved": asm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": asm_gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "bytes_per_launch": nb["assemble"]},
+        "roofline_ps_apply": {"bound": "hbm", "achieved": apply_gbps, "peak": HBM_PEAK_GBPS,
+                              "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
+                              "bytes_per_call": nb["apply"]},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(p)
+    prob.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * lsp.h -- C ABI of liblsp, the MI355X (gfx950) hot path of the localized
+ * sparsifying preconditioner (F. Liu and L. Ying, arXiv 1607.02560) for the
+ * periodic pseudospectral system (L + diag v) u = f on [0,1)^d.
+ *
+ * Notation follows the paper: d dimensions, n points per axis, h = 1/n,
+ * N = n^d unknowns on the grid J = {0..n-1}^d (Sec. 2). Grid arrays are in
+ * C order: point j = (j_1, ..., j_d) is stored at flat index
+ * ((j_1 n + j_2) n + ...) + j_d, the last axis fastest.
+ * Complex arrays are complex128, interleaved (re, im) doubles.
+ *
+ * Memory: every pointer named *_dev is device memory on the current HIP
+ * device, owned by the caller; the library never frees it and never keeps it
+ * past the call (the potential is copied). Pointers named *_host are host
+ * memory. All device work is ordered on the stream given to lsp_create and
+ * the calls return without waiting for it unless stated otherwise. One
+ * problem object must not be used from two threads at once; separate
+ * objects are independent.
+ *
+ * Errors: every int-returning call returns LSP_OK (0) on success, a negative
+ * LSP_E* code when nothing was computed, or a positive warning code.
+ * Arguments are validated on the host before any launch. lsp_last_error()
+ * returns a message describing the last failure on the calling thread.
+ */
+#ifndef LSP_H
+#define LSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LSP_OK = 0,
+  LSP_NOT_CONVERGED = 1, /* GMRES stopped at maxit; outputs hold the last iterate */
+  LSP_EINVAL = -1,       /* invalid argument (dimension, size, radius, pointer) */
+  LSP_ENONFINITE = -2,   /* NaN or Inf in the potential or right-hand side */
+  LSP_ERESONANT = -3,    /* a shift makes L + s singular (Sec. 3) */
+  LSP_ENOMEM = -4,       /* device or host allocation failed */
+  LSP_EHIP = -5,         /* a HIP runtime call failed */
+  LSP_ESOLVER = -6,      /* the host P-solve callback reported failure */
+  LSP_ESTATE = -7        /* call order violated (e.g. apply before setup) */
+};
+
+enum { LSP_FP64 = 0 };
+
+typedef struct lsp_problem lsp_problem;
+
+/* Host callback solving P x = rhs for the sparse matrix P of eq. (PC).
+ * rhs and x are complex128 interleaved host arrays of N entries.
+ * Returns 0 on success; any other value aborts the solve with LSP_ESOLVER. */
+typedef int (*lsp_host_solve_fn)(void* user, const double* rhs_host, double* x_host, int64_t N);
+
+/* Human-readable name of a status code. */
+const char* lsp_strerror(int code);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* lsp_last_error(void);
+
+/* Library version string. */
+const char* lsp_version(void);
+
+/*
+ * Create a problem for (L + diag v) u = f on the grid J (Sec. 2).
+ *   d       2 or 3.
+ *   n       points per axis: a power of two, 8 <= n <= 1024 for d = 2 and
+ *           8 <= n <= 256 for d = 3.
+ *   v_dev   N float64 potential samples v_j = v(h j) (Sec. 2), device memory;
+ *           copied into the problem. Must be finite (else LSP_ENONFINITE).
+ *   stream  hipStream_t on which every later call enqueues its work
+ *           (NULL = the default stream).
+ *   out     receives the new object; *out is NULL on failure.
+ * Allocates the problem's device workspaces and synchronises the stream once
+ * (to check the potential).
+ */
+int lsp_create(int d, int n, const double* v_dev, void* stream, lsp_problem** out);
+
+/* Replace the potential (same d, n) with N float64 values from v_dev; the
+ * shift tables built by an earlier setup are invalidated. Synchronises. */
+int lsp_set_potential(lsp_problem* p, const double* v_dev);
+
+/* Free the problem and its device memory. NULL is accepted. */
+void lsp_destroy(lsp_problem* p);
+
+/*
+ * Stencil setup of the localized sparsifying preconditioner (Sec. 4.1-4.2):
+ *   1. shift list S: num_shifts bin centres spread evenly over
+ *      [v_min, v_max], each snapped to the nearest (4m+2) pi^2, duplicates
+ *      removed (Sec. 4.1);
+ *   2. for each s in S the Green's kernels g_s = G_s[:,0] and g_s * g_s
+ *      (Sec. 3 and 4.2), evaluated at the offsets [-2t, 2t]^d only;
+ *   3. the Gram matrix M = A1 - A2 of eq. (A) on the neighbourhood mu_0^t;
+ *   4. alpha_s = unit eigenvector of the smallest eigenvalue of M (sign:
+ *      largest-magnitude entry positive), sigma_min, and C_s = G_s[mu,mu] alpha_s;
+ *   5. per grid point j: idx_j = index in S of the shift closest to v_j
+ *      (ties to the lower index) and the P row
+ *      P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j+a] - s_j), a in mu_0^t.
+ *   t           neighbourhood radius, 1 <= t, with m = (2t+1)^d <= 64 and 2t+1 < n.
+ *   num_shifts  requested |S| (1..1024); 0 selects n/16 for d = 2, n/4 for d = 3
+ *               (at least 1). The effective count |S| may be smaller.
+ *   precision   LSP_FP64.
+ *   P_dev       output, N*m float64, row j holds the m offsets of mu_0^t in
+ *               lexicographic order over [-t,t]^d (last axis fastest); the
+ *               column of entry (j, a) is (j + a) mod n per axis.
+ *   idx_dev     output, N int32 shift indices (may be NULL).
+ * Asynchronous: returns once the work is enqueued.
+ */
+int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision,
+                      double* P_dev, int32_t* idx_dev);
+
+/*
+ * Pseudospectral apply y = (L + diag v) u with L = F^-1 diag(4 pi^2 |k|^2) F
+ * (Sec. 2, eq. dmodel). u_dev and y_dev: N complex128, device, must not
+ * overlap. Asynchronous.
+ */
+int lsp_ps_apply(lsp_problem* p, const double* u_dev, double* y_dev);
+
+/*
+ * First half of the preconditioner P^-1 C of eq. (PC): z = C r with
+ * (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n]. Needs a completed setup.
+ * r_dev, z_dev: N complex128, device, must not overlap. Asynchronous.
+ */
+int lsp_c_apply(lsp_problem* p, const double* r_dev, double* z_dev);
+
+/*
+ * Solve (L + diag v) u = f by GMRES(restart) with right preconditioner
+ * P^-1 C (eq. PC; Sec. 5 uses restart 40). The P-solve is done on the host
+ * by solveP (a sparse factorisation of the P rows from the last setup); every
+ * other step runs on the device. x0 = 0; stops when the Arnoldi residual
+ * estimate is <= rtol ||f||. f_dev, u_dev: N complex128 device arrays.
+ * iters receives the number of Arnoldi steps, relres the true relative
+ * residual ||f - A u|| / ||f|| (recomputed at the end). Synchronous.
+ * Returns LSP_NOT_CONVERGED (with u the last iterate) if maxit is reached.
+ */
+int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev,
+                      double rtol, int restart, int maxit,
+                      lsp_host_solve_fn solveP, void* user,
+                      int* iters, double* relres);
+
+/*
+ * Host copies of the per-shift tables of the last setup. Synchronises.
+ * Any pointer may be NULL. Sizes: S_host[nS], alpha_host[nS*m], C_host[nS*m],
+ * sigma_host[nS], g_host[nS*(2t+1)^d], gam_host[nS*(2t+1)^d] (g_s and
+ * g_s * g_s at offsets [0,2t]^d, lexicographic), M_host[nS*m*m].
+ * Pass capacity = the number of shifts the arrays can hold; returns
+ * LSP_EINVAL if it is smaller than the effective |S| (which is stored in *nS
+ * in every case).
+ */
+int lsp_get_tables(lsp_problem* p, int capacity, int* nS, double* S_host,
+                   double* alpha_host, double* C_host, double* sigma_host,
+                   double* g_host, double* gam_host, double* M_host);
+
+/* Default shift-list size used when lsp_stencil_setup gets num_shifts = 0:
+ * n/16 for d = 2 and n/4 for d = 3, at least 1 (the ratios of Tables 2-9,
+ * Sec. 5). Host only; returns LSP_EINVAL for d outside {2, 3} or n < 1. */
+int lsp_default_num_shifts(int d, int n);
+
+/*
+ * Per-stage timing with HIP events on the problem's stream (for measurement;
+ * off by default). Stages: LSP_STAGE_SHIFTS (shift list), LSP_STAGE_GREEN
+ * (Green's kernel sums), LSP_STAGE_NULL (Gram matrix and null vector),
+ * LSP_STAGE_ASSEMBLE (per-point rows), LSP_STAGE_SETUP (the whole
+ * lsp_stencil_setup), LSP_STAGE_APPLY (lsp_ps_apply), LSP_STAGE_CAPPLY
+ * (lsp_c_apply).
+ * lsp_profile(p, 1) starts recording and clears the totals; lsp_profile(p, 0)
+ * stops. lsp_profile_read synchronises the stream and writes, for each stage
+ * s < nstages, the summed milliseconds ms_host[s] and the number of timed
+ * calls count_host[s] since recording started.
+ */
+enum {
+  LSP_STAGE_SHIFTS = 0,
+  LSP_STAGE_GREEN = 1,
+  LSP_STAGE_NULL = 2,
+  LSP_STAGE_ASSEMBLE = 3,
+  LSP_STAGE_SETUP = 4,
+  LSP_STAGE_APPLY = 5,
+  LSP_STAGE_CAPPLY = 6,
+  LSP_NUM_STAGES = 7
+};
+int lsp_profile(lsp_problem* p, int enable);
+int lsp_profile_read(lsp_problem* p, int nstages, double* ms_host, int* count_host);
+
+/* Number of stencil entries m = (2t+1)^d of the last setup (0 before setup). */
+int lsp_stencil_size(const lsp_problem* p);
+
+/*
+ * Column pattern of P and C for radius t: col_host[j*m + a] = flat index of
+ * (j + a) mod n, a in mu_0^t lexicographic. N*m int64 host entries. The
+ * CSR row pointer is j*m.
+ */
+int lsp_export_pattern(int d, int n, int t, int64_t* col_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSP_H */

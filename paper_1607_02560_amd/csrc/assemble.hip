@@ -1,0 +1,306 @@
+// Per-point work of the localized sparsifying preconditioner (Sec. 4.1):
+//   assemble_kernel  s_j and the row P[j, mu_j] = alpha_{s_j} + C_{s_j} (v[mu_j] - s_j)
+//   c_apply_kernel   z = C r, the first half of the preconditioner P^-1 C of eq. (PC)
+#include "setup_common.h"
+
+// The P row formula is evaluated with one rounding per operation.
+#pragma clang fp contract(off)
+
+namespace {
+
+using lsp::nearest_shift;
+using lsp::Pow;
+
+// --------------------------------------------------------------------------
+// Per-point assignment and P rows.
+// A block owns a tile of TR x TW points (TR rows of axis d-2, TW columns of
+// axis d-1, one plane of axis 0 in 3D), one point per thread.
+//   1. The potential on the tile plus a halo of t in every direction and the
+//      shift list are staged in LDS.
+//   2. Each thread picks idx_j = argmin_i |S_i - v_j| (S is sorted: the two
+//      neighbours of the insertion point are compared, ties to the lower
+//      index); the block's range of shift indices is reduced.
+//   3. The (alpha, C) rows of that range are staged in LDS (or read from
+//      global memory when the range is too wide).
+//   4. Each thread evaluates its whole row with compile-time offsets,
+//        P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j),
+//      one rounding per operation, into an LDS staging buffer.
+//   5. The tile's rows are TR contiguous spans of TW*m doubles in P; they are
+//      copied out with coalesced 16-byte stores.
+// --------------------------------------------------------------------------
+template <int D, int W, int TR, int TW>
+__global__ __launch_bounds__(256) void assemble_kernel(
+    const double* __restrict__ v, int n, const double* __restrict__ S,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, double* __restrict__ P,
+    int32_t* __restrict__ idx_out) {
+  using Nb = lsp::Nbhd<D, W>;
+  constexpr int t = (W - 1) / 2;
+  constexpr int M = Pow<D, W>::v;
+  constexpr int PL = (D == 3) ? W : 1;  // halo planes
+  constexpr int HR = TR + 2 * t;
+  constexpr int HC = TW + 2 * t;
+  constexpr int NPT = TR * TW;
+  constexpr int TABCAP = 512;
+  constexpr int OUTD = NPT * M;         // doubles staged for output (even: TW even)
+  constexpr int BUFD = (OUTD > lsp::kMaxShifts) ? OUTD : lsp::kMaxShifts;
+  static_assert(NPT <= 256, "one point per thread");
+  __shared__ double halo[PL * HR * HC];
+  __shared__ double2 stab[TABCAP];
+  __shared__ double2 outb2[BUFD / 2];   // also holds the shift list in steps 1-2
+  __shared__ int sred[8];
+  double* outb = reinterpret_cast<double*>(outb2);
+  double* sS = outb;
+
+  const int tid = threadIdx.x;
+  const int nS = *nS_ptr;
+  const int c0 = blockIdx.x * TW;
+  const int r0 = blockIdx.y * TR;
+  const int p0 = (D == 3) ? (int)blockIdx.z : 0;
+  const int mask = n - 1;
+
+  for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  for (int e = tid; e < PL * HR * HC; e += 256) {
+    const int hc = e % HC;
+    const int hr = (e / HC) % HR;
+    const int hp = e / (HC * HR);
+    const int gc = (c0 - t + hc) & mask;
+    const int gr = (r0 - t + hr) & mask;
+    int64_t g;
+    if constexpr (D == 3) {
+      const int gp = (p0 - t + hp) & mask;
+      g = ((int64_t)gp * n + gr) * n + gc;
+    } else {
+      g = (int64_t)gr * n + gc;
+    }
+    halo[e] = v[g];
+  }
+  __syncthreads();
+
+  // ---- 2. shift assignment ----
+  const bool active = tid < NPT;
+  const int r = tid / TW, c = tid % TW;
+  const int hbase = ((PL / 2) * HR + r + t) * HC + c + t;
+  int id = 0;
+  double sj = 0.0;
+  if (active) {
+    id = nearest_shift(sS, nS, halo[hbase]);
+    sj = sS[id];
+    if (idx_out) {
+      const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
+                                 : ((int64_t)(r0 + r) * n + c0 + c);
+      idx_out[g] = id;
+    }
+  }
+  int lo = active ? id : 0x7fffffff, hi = active ? id : -1;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = min(lo, __shfl_xor(lo, o));
+    hi = max(hi, __shfl_xor(hi, o));
+  }
+  if ((tid & 63) == 0) {
+    sred[2 * (tid >> 6)] = lo;
+    sred[2 * (tid >> 6) + 1] = hi;
+  }
+  __syncthreads();
+  int imin = sred[0], imax = sred[1];
+  for (int w = 1; w < 4; ++w) {
+    imin = min(imin, sred[2 * w]);
+    imax = max(imax, sred[2 * w + 1]);
+  }
+
+  // ---- 3. (alpha, C) rows of the block's shifts ----
+  const bool staged = (imax - imin + 1) * M <= TABCAP;
+  if (staged) {
+    for (int e = tid; e < (imax - imin + 1) * M; e += 256) stab[e] = actab[imin * M + e];
+  }
+  __syncthreads();
+
+  // ---- 4. the row of this point ----
+  if (active) {
+    const double2* tab = staged ? (stab + (id - imin) * M) : (actab + (int64_t)id * M);
+    double* orow = outb + tid * M;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      int off;
+      if constexpr (D == 3) {
+        off = Nb::comp(a, 0) * HR * HC + Nb::comp(a, 1) * HC + Nb::comp(a, 2);
+      } else {
+        off = Nb::comp(a, 0) * HC + Nb::comp(a, 1);
+      }
+      const double2 ac = tab[a];
+      orow[a] = ac.x + ac.y * (halo[hbase + off] - sj);
+    }
+  }
+  __syncthreads();
+
+  // ---- 5. coalesced copy-out ----
+  constexpr int SPAN2 = TW * M / 2;  // double2 per tile row
+  for (int ch = tid; ch < TR * SPAN2; ch += 256) {
+    const int rr = ch / SPAN2;
+    const int e = ch - rr * SPAN2;
+    const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0 + rr) * n + c0) * M)
+                                     : (((int64_t)(r0 + rr) * n + c0) * M);
+    reinterpret_cast<double2*>(P + rowbase)[e] = outb2[ch];
+  }
+}
+
+// --------------------------------------------------------------------------
+// b2: z = C r, (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n] (eq. PC), complex r.
+// Same tiling as assemble_kernel; s_j is recomputed from v and S exactly as
+// the setup assigned it, so no per-point state is kept between calls.
+// --------------------------------------------------------------------------
+template <int D, int W, int TR, int TW>
+__global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict__ rvec,
+                                                      const double* __restrict__ v, int n,
+                                                      const double* __restrict__ S,
+                                                      const int* __restrict__ nS_ptr,
+                                                      const double* __restrict__ Ctab,
+                                                      double2* __restrict__ z) {
+  constexpr int t = (W - 1) / 2;
+  constexpr int M = Pow<D, W>::v;
+  constexpr int PL = (D == 3) ? W : 1;
+  constexpr int HR = TR + 2 * t;
+  constexpr int HC = TW + 2 * t;
+  __shared__ double2 halo[PL * HR * HC];
+  __shared__ double sS[lsp::kMaxShifts];
+  const int tid = threadIdx.x;
+  const int nS = *nS_ptr;
+  const int c0 = blockIdx.x * TW;
+  const int r0 = blockIdx.y * TR;
+  const int p0 = (D == 3) ? (int)blockIdx.z : 0;
+  const int mask = n - 1;
+  for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  for (int e = tid; e < PL * HR * HC; e += 256) {
+    const int hc = e % HC;
+    const int hr = (e / HC) % HR;
+    const int hp = e / (HC * HR);
+    const int gc = (c0 - t + hc) & mask;
+    const int gr = (r0 - t + hr) & mask;
+    int64_t g;
+    if constexpr (D == 3) {
+      const int gp = (p0 - t + hp) & mask;
+      g = ((int64_t)gp * n + gr) * n + gc;
+    } else {
+      g = (int64_t)gr * n + gc;
+    }
+    halo[e] = rvec[g];
+  }
+  __syncthreads();
+  for (int pt = tid; pt < TR * TW; pt += 256) {
+    const int r = pt / TW, c = pt % TW;
+    const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
+                               : ((int64_t)(r0 + r) * n + c0 + c);
+    const int id = nearest_shift(sS, nS, v[g]);
+    const double* crow = Ctab + (int64_t)id * M;
+    double zr = 0.0, zi = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+      int da[D];
+      int rem = a;
+#pragma unroll
+      for (int k = D - 1; k >= 0; --k) {
+        da[k] = rem % W - t;
+        rem /= W;
+      }
+      int hp = 0, hr, hc;
+      if constexpr (D == 3) {
+        hp = t + da[0];
+        hr = r + t + da[1];
+        hc = c + t + da[2];
+      } else {
+        hr = r + t + da[0];
+        hc = c + t + da[1];
+      }
+      const double2 x = halo[(hp * HR + hr) * HC + hc];
+      const double ca = crow[a];
+      zr = fma(ca, x.x, zr);
+      zi = fma(ca, x.y, zi);
+    }
+    z[g] = make_double2(zr, zi);
+  }
+}
+
+template <int D, int W, int TW, int TR>
+hipError_t run_assemble_tile(lsp_problem* p, double* P, int32_t* idx) {
+  const int n = p->n;
+  if (n % TW != 0 || n % TR != 0) return hipErrorInvalidValue;
+  dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
+  hipLaunchKernelGGL((assemble_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream, p->v, n,
+                     p->ws.S, p->ws.nS, reinterpret_cast<const double2*>(p->ws.actab), P, idx);
+  return hipGetLastError();
+}
+
+template <int D, int W, int TW>
+hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
+  constexpr int TR = 4;
+  const int n = p->n;
+  if (n % TW != 0 || n % TR != 0) return hipErrorInvalidValue;
+  dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
+  hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream,
+                     reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS, p->ws.Ctab,
+                     reinterpret_cast<double2*>(z));
+  return hipGetLastError();
+}
+
+// assembly tiles: 256 points (fewer on the smallest grids), as wide as the
+// last axis allows (256 in 2D, 64 in 3D)
+template <int D, int W>
+hipError_t run_assemble(lsp_problem* p, double* P, int32_t* idx) {
+  switch (p->n) {
+    case 8: return run_assemble_tile<D, W, 8, 8>(p, P, idx);
+    case 16: return run_assemble_tile<D, W, 16, 16>(p, P, idx);
+    case 32: return run_assemble_tile<D, W, 32, 8>(p, P, idx);
+    default: break;
+  }
+  if constexpr (D == 2) {
+    if (p->n == 64) return run_assemble_tile<D, W, 64, 4>(p, P, idx);
+    if (p->n == 128) return run_assemble_tile<D, W, 128, 2>(p, P, idx);
+    return run_assemble_tile<D, W, 256, 1>(p, P, idx);
+  } else {
+    return run_assemble_tile<D, W, 64, 4>(p, P, idx);
+  }
+}
+
+template <int D, int W>
+hipError_t run_c_apply(const lsp_problem* p, const double* r, double* z) {
+  const int cap = (D == 2) ? 256 : 64;
+  const int tw = p->n < cap ? p->n : cap;
+  switch (tw) {
+    case 8: return run_c_apply_tw<D, W, 8>(p, r, z);
+    case 16: return run_c_apply_tw<D, W, 16>(p, r, z);
+    case 32: return run_c_apply_tw<D, W, 32>(p, r, z);
+    case 64: return run_c_apply_tw<D, W, 64>(p, r, z);
+    case 128:
+      if constexpr (D == 2) return run_c_apply_tw<D, W, 128>(p, r, z);
+      break;
+    case 256:
+      if constexpr (D == 2) return run_c_apply_tw<D, W, 256>(p, r, z);
+      break;
+  }
+  return hipErrorInvalidValue;
+}
+
+#define LSP_DISPATCH_DW(D_, W_, CALL) \
+  if (p->d == D_ && 2 * p->t + 1 == W_) return CALL;
+
+}  // namespace
+
+namespace lsp {
+
+hipError_t launch_assemble(lsp_problem* p, double* P, int32_t* idx) {
+  LSP_DISPATCH_DW(2, 3, (run_assemble<2, 3>(p, P, idx)))
+  LSP_DISPATCH_DW(2, 5, (run_assemble<2, 5>(p, P, idx)))
+  LSP_DISPATCH_DW(2, 7, (run_assemble<2, 7>(p, P, idx)))
+  LSP_DISPATCH_DW(3, 3, (run_assemble<3, 3>(p, P, idx)))
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z) {
+  LSP_DISPATCH_DW(2, 3, (run_c_apply<2, 3>(p, r, z)))
+  LSP_DISPATCH_DW(2, 5, (run_c_apply<2, 5>(p, r, z)))
+  LSP_DISPATCH_DW(2, 7, (run_c_apply<2, 7>(p, r, z)))
+  LSP_DISPATCH_DW(3, 3, (run_c_apply<3, 3>(p, r, z)))
+  return hipErrorInvalidValue;
+}
+
+}  // namespace lsp

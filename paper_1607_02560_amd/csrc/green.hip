@@ -1,0 +1,276 @@
+// Green's kernel sums (Sec. 3 and 4.2) at the offsets the Gram matrix needs.
+//
+// g_s[delta] = (1/N) sum_{k in K} cos(2 pi k.delta/n) / (lambda_k + s) is the
+// first column of G_s = (L+s)^-1 and (g_s * g_s)[delta] is the same sum with
+// (lambda_k + s)^2, i.e. the inverse DFTs of the symbols 1/(lambda+s) and
+// 1/(lambda+s)^2. Eq. (A) only needs delta in [-2t, 2t]^d; both kernels are
+// even in every coordinate, so delta in [0, 2t]^d suffices. Instead of the
+// paper's full FFT per shift the sums are evaluated directly at those
+// (2t+1)^d offsets (a pruned inverse DFT: same numbers, O(N) work per shift
+// and no memory traffic):
+//   * each axis folds onto k_i in [0, n/2] with weight 1 at 0 and n/2 and 2
+//     elsewhere: cw[k][dl] = w(k) cos(2 pi k dl / n);
+//   * the summand is symmetric in (k_{d-1}, k_d), so only k_d >= k_{d-1} is
+//     visited (half weight on the diagonal) and the two offset axes are
+//     symmetrised: g[.., da, db] = sum_kk cw[kk][da] T[db] + cw[kk][db] T[da],
+//     with T[dl] = sum_{k_d} cw[k_d][dl] r the inner sum of the thread's row;
+//     only the pairs da <= db are accumulated.
+// A block owns OT consecutive outer indices o = (k_1..k_{d-1}) (one per
+// thread) and one segment of SEG values of k_d, whose cw rows are staged in
+// LDS and read as wave-wide broadcasts. Blocks write their partial sums,
+// unscaled: [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
+#include "setup_common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using lsp::Pow;
+
+template <int D, int W>
+struct GreenLayout {
+  static constexpr int NP = W * (W + 1) / 2;  // offset pairs da <= db
+  static constexpr int WO2 = Pow<D - 2, W>::v;
+  static constexpr int NV = 2 * WO2 * NP;     // values per partial
+};
+
+// One term of the sums: r = 1/(lambda_k + s) with lambda_k = 4 pi^2 |k|^2
+// rounded as "4 pi^2 |k|^2, then + s"; K2 = |k|^2 < 2^31 for n <= 1024.
+__device__ __forceinline__ double green_r(int K2, double s) {
+  const double lam = lsp::kFourPi2 * (double)K2;
+  return lsp::rcp_nr(lam + s);
+}
+
+template <int D, int W, int OT, int SEG>
+__global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict__ mm_part,
+                                                        int mm_blocks, int nreq, double* S_out,
+                                                        int* nS_out, double* vrange_out,
+                                                        const double* __restrict__ cw, int n,
+                                                        int otiles, double* __restrict__ part) {
+  using Lay = GreenLayout<D, W>;
+  constexpr int NP = Lay::NP;
+  constexpr int WO2 = Lay::WO2;
+  constexpr int NV = Lay::NV;
+  constexpr int SPL = 4;   // partial sums per value in the block reduction
+  constexpr int RCH = 10;  // values reduced per round (bounds the LDS footprint)
+  __shared__ double cws[SEG * W];
+  __shared__ double red[RCH * (OT + 1)];
+  __shared__ double red2[NV * SPL];
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sNS, sWave[OT / 64];
+  __shared__ double sRange[2], sRed[2 * (OT / 64)];
+
+  // shift list (Sec. 4.1) from the min/max partials; one block publishes it
+  lsp::shift_list_block(mm_part, mm_blocks, nreq, sS, &sNS, sRange, sWave, sRed);
+  const int nS = sNS;
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int i = threadIdx.x; i < nS; i += OT) S_out[i] = sS[i];
+    if (threadIdx.x == 0) {
+      *nS_out = nS;
+      vrange_out[0] = sRange[0];
+      vrange_out[1] = sRange[1];
+    }
+  }
+  const int si = blockIdx.y;
+  if (si >= nS) return;
+  const double s = sS[si];
+  const int H = n / 2 + 1;
+  const int ot = blockIdx.x % otiles;
+  const int q = blockIdx.x / otiles;
+  const int tid = threadIdx.x;
+  int O = 1;
+#pragma unroll
+  for (int i = 0; i < D - 1; ++i) O *= H;
+  const int o = ot * OT + tid;
+  const bool valid = o < O;
+  int ko[D - 1];
+  {
+    int rem = valid ? o : 0;
+#pragma unroll
+    for (int i = D - 2; i >= 0; --i) {
+      ko[i] = rem % H;
+      rem /= H;
+    }
+  }
+  int K2o = 0;
+#pragma unroll
+  for (int i = 0; i < D - 1; ++i) K2o += ko[i] * ko[i];
+  const int kk = ko[D - 2];
+
+  const int k_begin = q * SEG;
+  const int k_end = min(H, k_begin + SEG);
+  for (int e = tid; e < (k_end - k_begin) * W; e += OT) cws[e] = cw[k_begin * W + e];
+  const int any_work = __syncthreads_or(valid && kk < k_end);
+
+  double tg[W], tq[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
+
+  if (any_work) {
+    // A wave whose rows all lie above the diagonal of the segment takes every
+    // term with weight 1; otherwise terms get weight 1 above, 1/2 on and 0
+    // below the diagonal (0 for padding lanes). The branch is wave-uniform.
+    if (__all(valid && kk < k_begin)) {
+      int kd = k_begin;
+      for (; kd + 4 <= k_end; kd += 4) {
+        double r[4], r2[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          r[u] = green_r(K2o + (kd + u) * (kd + u), s);
+          r2[u] = r[u] * r[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* c = cws + (kd + u - k_begin) * W;
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            tg[j] = fma(c[j], r[u], tg[j]);
+            tq[j] = fma(c[j], r2[u], tq[j]);
+          }
+        }
+      }
+      for (; kd < k_end; ++kd) {
+        const double r = green_r(K2o + kd * kd, s);
+        const double r2 = r * r;
+        const double* c = cws + (kd - k_begin) * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          tg[j] = fma(c[j], r, tg[j]);
+          tq[j] = fma(c[j], r2, tq[j]);
+        }
+      }
+    } else {
+      for (int kd = k_begin; kd < k_end; ++kd) {
+        const double r0 = green_r(K2o + kd * kd, s);
+        const double wgt = valid ? ((kd > kk) ? 1.0 : ((kd == kk) ? 0.5 : 0.0)) : 0.0;
+        const double r1 = wgt * r0;
+        const double r2 = r1 * r0;
+        const double* c = cws + (kd - k_begin) * W;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          tg[j] = fma(c[j], r1, tg[j]);
+          tq[j] = fma(c[j], r2, tq[j]);
+        }
+      }
+    }
+  }
+
+  // symmetrised accumulation of the offset pairs (da <= db)
+  double ck[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) ck[j] = cw[kk * W + j];
+  double lead[WO2];
+  if constexpr (D == 3) {
+#pragma unroll
+    for (int x = 0; x < WO2; ++x) lead[x] = cw[ko[0] * W + x];
+  } else {
+    lead[0] = 1.0;
+  }
+  double acc[NV];
+#pragma unroll
+  for (int x = 0; x < WO2; ++x) {
+    int pi = 0;
+#pragma unroll
+    for (int da = 0; da < W; ++da) {
+#pragma unroll
+      for (int db = da; db < W; ++db) {
+        acc[x * NP + pi] = lead[x] * (ck[da] * tg[db] + ck[db] * tg[da]);
+        acc[WO2 * NP + x * NP + pi] = lead[x] * (ck[da] * tq[db] + ck[db] * tq[da]);
+        ++pi;
+      }
+    }
+  }
+
+  // block reduction in a fixed order, RCH values per round
+  constexpr int CH = OT / SPL;
+#pragma unroll
+  for (int v0 = 0; v0 < NV; v0 += RCH) {
+    __syncthreads();
+#pragma unroll
+    for (int vv = 0; vv < RCH; ++vv)
+      if (v0 + vv < NV) red[vv * (OT + 1) + tid] = acc[v0 + vv];
+    __syncthreads();
+    for (int e = tid; e < RCH * SPL; e += OT) {
+      const int vv = e / SPL, sp = e % SPL;
+      if (v0 + vv < NV) {
+        const double* rr = red + vv * (OT + 1) + sp * CH;
+        double sum = 0.0;
+        for (int l = 0; l < CH; ++l) sum += rr[l];
+        red2[(v0 + vv) * SPL + sp] = sum;
+      }
+    }
+  }
+  __syncthreads();
+  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
+  for (int vv = tid; vv < NV; vv += OT) {
+    double sum = 0.0;
+#pragma unroll
+    for (int sp = 0; sp < SPL; ++sp) sum += red2[vv * SPL + sp];
+    out[vv] = sum;
+  }
+}
+
+template <int D>
+struct GreenTiles;
+template <>
+struct GreenTiles<2> {
+  static constexpr int OT = 128, SEG = 128;
+};
+template <>
+struct GreenTiles<3> {
+  static constexpr int OT = 128, SEG = 64;
+};
+
+template <int D, int W>
+hipError_t run_green(lsp_problem* p, int num_shifts, int* blocks_out) {
+  constexpr int OT = GreenTiles<D>::OT;
+  constexpr int SEG = GreenTiles<D>::SEG;
+  const int H = p->n / 2 + 1;
+  int64_t O = 1;
+  for (int i = 0; i < D - 1; ++i) O *= H;
+  const int otiles = (int)((O + OT - 1) / OT);
+  const int nseg = (H + SEG - 1) / SEG;
+  const int blocks = otiles * nseg;
+  const size_t need = (size_t)num_shifts * blocks * GreenLayout<D, W>::NV;
+  if (need > p->ws.green_part_cap) return hipErrorOutOfMemory;
+  *blocks_out = blocks;
+  hipLaunchKernelGGL((green_sums_kernel<D, W, OT, SEG>), dim3(blocks, num_shifts), dim3(OT), 0,
+                     p->stream, p->ws.minmax_part, lsp::minmax_blocks(p->N), num_shifts, p->ws.S,
+                     p->ws.nS, p->ws.vrange, p->cosT, p->n, otiles, p->ws.green_part);
+  return hipGetLastError();
+}
+
+template <int D, int W>
+size_t green_need(int n, int shifts) {
+  constexpr int OT = GreenTiles<D>::OT;
+  constexpr int SEG = GreenTiles<D>::SEG;
+  const int H = n / 2 + 1;
+  int64_t O = 1;
+  for (int i = 0; i < D - 1; ++i) O *= H;
+  const int64_t blocks = ((O + OT - 1) / OT) * ((H + SEG - 1) / SEG);
+  return (size_t)shifts * blocks * GreenLayout<D, W>::NV;
+}
+
+}  // namespace
+
+namespace lsp {
+
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* blocks) {
+  const int W = 2 * p->t + 1;
+  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, blocks);
+  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, blocks);
+  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, blocks);
+  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, blocks);
+  return hipErrorInvalidValue;
+}
+
+size_t green_partial_doubles(int d, int n, int t, int shifts) {
+  const int W = 2 * t + 1;
+  if (d == 2 && W == 3) return green_need<2, 3>(n, shifts);
+  if (d == 2 && W == 5) return green_need<2, 5>(n, shifts);
+  if (d == 2 && W == 7) return green_need<2, 7>(n, shifts);
+  if (d == 3 && W == 3) return green_need<3, 3>(n, shifts);
+  return 0;
+}
+
+}  // namespace lsp

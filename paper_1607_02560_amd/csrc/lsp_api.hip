@@ -1,0 +1,676 @@
+// Host side of liblsp: argument validation, the problem object and its
+// workspaces, the stencil-setup launch sequence and the GMRES driver.
+// Every entry point declared in include/lsp.h is defined here.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <complex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lsp_internal.h"
+
+namespace lsp {
+hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                            double* part, hipStream_t s);
+hipError_t launch_multi_axpy(const double* V, int64_t ldv, int nv, const double* coef,
+                             double sign, double* w, int64_t N, hipStream_t s);
+hipError_t launch_scale(const double* x, double a, double* y, int64_t N, hipStream_t s);
+hipError_t launch_sub(const double* b, const double* x, double* y, int64_t N, hipStream_t s);
+int dot_blocks(int64_t N);
+}  // namespace lsp
+
+namespace {
+thread_local std::string g_last_error;
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Free a device pointer and null it.
+template <typename T>
+void dfree(T*& ptr) {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+}
+
+int dalloc(void** ptr, size_t bytes, const char* what) {
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    (void)hipGetLastError();
+    return lsp::set_error(LSP_ENOMEM, std::string("device allocation failed: ") + what + " (" +
+                                          std::to_string(bytes) + " bytes)");
+  }
+  return LSP_OK;
+}
+
+void free_workspace(lsp_problem* p) {
+  lsp::Workspace& w = p->ws;
+  dfree(w.minmax_part);
+  dfree(w.S);
+  dfree(w.nS);
+  dfree(w.vrange);
+  dfree(w.green_part);
+  dfree(w.gtab);
+  dfree(w.gamtab);
+  dfree(w.Mtab);
+  dfree(w.alpha);
+  dfree(w.Ctab);
+  dfree(w.sigma);
+  dfree(w.actab);
+  dfree(w.status);
+  w.cap_shifts = w.cap_m = w.cap_w = 0;
+  w.green_part_cap = 0;
+}
+
+int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
+  lsp::Workspace& w = p->ws;
+  int rc = LSP_OK;
+  if (!w.minmax_part) {
+    if ((rc = dalloc((void**)&w.minmax_part, sizeof(double) * 2 * lsp::kMinMaxBlocks, "minmax")))
+      return rc;
+    if ((rc = dalloc((void**)&w.S, sizeof(double) * lsp::kMaxShifts, "S"))) return rc;
+    if ((rc = dalloc((void**)&w.nS, sizeof(int), "nS"))) return rc;
+    if ((rc = dalloc((void**)&w.vrange, sizeof(double) * 2, "vrange"))) return rc;
+    if (hipMemsetAsync(w.nS, 0, sizeof(int), p->stream) != hipSuccess)
+      return lsp::set_error(LSP_EHIP, "hipMemsetAsync(nS) failed");
+  }
+  const size_t gneed = lsp::green_partial_doubles(p->d, p->n, t, shifts);
+  if (gneed > w.green_part_cap) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(w.green_part);
+    if ((rc = dalloc((void**)&w.green_part, sizeof(double) * gneed, "green partial sums")))
+      return rc;
+    w.green_part_cap = gneed;
+  }
+  if (shifts > w.cap_shifts || m > w.cap_m || wd > w.cap_w) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(w.gtab);
+    dfree(w.gamtab);
+    dfree(w.Mtab);
+    dfree(w.alpha);
+    dfree(w.Ctab);
+    dfree(w.sigma);
+    dfree(w.actab);
+    dfree(w.status);
+    const int cs = shifts > w.cap_shifts ? shifts : w.cap_shifts;
+    const int cm = m > w.cap_m ? m : w.cap_m;
+    const int cw = wd > w.cap_w ? wd : w.cap_w;
+    if ((rc = dalloc((void**)&w.gtab, sizeof(double) * cs * cw, "g table"))) return rc;
+    if ((rc = dalloc((void**)&w.gamtab, sizeof(double) * cs * cw, "g*g table"))) return rc;
+    if ((rc = dalloc((void**)&w.Mtab, sizeof(double) * cs * cm * cm, "Gram matrices"))) return rc;
+    if ((rc = dalloc((void**)&w.alpha, sizeof(double) * cs * cm, "alpha"))) return rc;
+    if ((rc = dalloc((void**)&w.Ctab, sizeof(double) * cs * cm, "C"))) return rc;
+    if ((rc = dalloc((void**)&w.sigma, sizeof(double) * cs, "sigma"))) return rc;
+    if ((rc = dalloc((void**)&w.actab, sizeof(double) * 2 * cs * cm, "alpha/C"))) return rc;
+    if ((rc = dalloc((void**)&w.status, sizeof(int) * cs, "status"))) return rc;
+    w.cap_shifts = cs;
+    w.cap_m = cm;
+    w.cap_w = cw;
+  }
+  return LSP_OK;
+}
+
+// cw[k][delta] = w(k) cos(2 pi k delta / n), k in [0, n/2], delta in [0, W):
+// the folded cosine weights of the Green's sums (w = 1 at k = 0, n/2; else 2).
+int upload_cos_table(lsp_problem* p, int W) {
+  const int H = p->n / 2 + 1;
+  std::vector<double> cw((size_t)H * W);
+  for (int k = 0; k < H; ++k) {
+    const double wk = (k == 0 || k == p->n / 2) ? 1.0 : 2.0;
+    for (int dl = 0; dl < W; ++dl) {
+      const long j = ((long)k * dl) % p->n;
+      cw[(size_t)k * W + dl] = wk * cos(2.0 * M_PI * (double)j / (double)p->n);
+    }
+  }
+  dfree(p->cosT);
+  int rc = dalloc((void**)&p->cosT, sizeof(double) * cw.size(), "cos table");
+  if (rc) return rc;
+  if (hipMemcpy(p->cosT, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return lsp::set_error(LSP_EHIP, "upload of the cosine table failed");
+  return LSP_OK;
+}
+
+int check_finite_device(lsp_problem* p, const double* x, int64_t count, const char* what) {
+  hipError_t e = lsp::launch_count_nonfinite(x, count, p->flag, p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "non-finite check");
+  int bad = 0;
+  e = hipMemcpyAsync(&bad, p->flag, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "non-finite check readback");
+  if (bad)
+    return lsp::set_error(LSP_ENONFINITE,
+                          std::string(what) + " has " + std::to_string(bad) + " non-finite values");
+  return LSP_OK;
+}
+
+}  // namespace
+
+namespace lsp {
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return LSP_OK;
+  return set_error(LSP_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static hipEvent_t next_event(lsp_problem* p) {
+  if (p->ev_used == p->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    p->ev_pool.push_back(e);
+  }
+  return p->ev_pool[p->ev_used++];
+}
+
+// Fold finished event pairs into the totals and recycle the pool.
+static void drain_events(lsp_problem* p) {
+  (void)hipStreamSynchronize(p->stream);
+  for (const auto& pr : p->ev_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev_pool[pr.second], p->ev_pool[pr.second + 1]) ==
+        hipSuccess) {
+      p->prof_ms[pr.first] += ms;
+      p->prof_count[pr.first] += 1;
+    }
+  }
+  p->ev_pending.clear();
+  p->ev_used = 0;
+}
+
+int stage_begin(lsp_problem* p, int stage) {
+  if (!p->profiling) return -1;
+  const size_t i0 = p->ev_used;
+  hipEvent_t a = next_event(p);
+  hipEvent_t b = next_event(p);
+  if (!a || !b) return -1;
+  (void)hipEventRecord(a, p->stream);
+  p->ev_pending.emplace_back(stage, (int)i0);
+  return (int)p->ev_pending.size() - 1;
+}
+
+void stage_end(lsp_problem* p, int token) {
+  if (token < 0 || !p->profiling) return;
+  const int i0 = p->ev_pending[token].second;
+  (void)hipEventRecord(p->ev_pool[i0 + 1], p->stream);
+}
+
+}  // namespace lsp
+
+extern "C" {
+
+const char* lsp_strerror(int code) {
+  switch (code) {
+    case LSP_OK: return "ok";
+    case LSP_NOT_CONVERGED: return "not converged";
+    case LSP_EINVAL: return "invalid argument";
+    case LSP_ENONFINITE: return "non-finite input";
+    case LSP_ERESONANT: return "resonant shift";
+    case LSP_ENOMEM: return "out of memory";
+    case LSP_EHIP: return "HIP runtime error";
+    case LSP_ESOLVER: return "host P-solve failed";
+    case LSP_ESTATE: return "invalid call order";
+    default: return "unknown status";
+  }
+}
+
+const char* lsp_last_error(void) { return g_last_error.c_str(); }
+
+const char* lsp_version(void) { return "liblsp 0.1 (gfx950)"; }
+
+int lsp_create(int d, int n, const double* v_dev, void* stream, lsp_problem** out) {
+  if (!out) return lsp::set_error(LSP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d != 2 && d != 3) return lsp::set_error(LSP_EINVAL, "d must be 2 or 3");
+  const int nmax = (d == 2) ? 1024 : 256;
+  if (!is_pow2(n) || n < 8 || n > nmax)
+    return lsp::set_error(LSP_EINVAL, "n must be a power of two in [8, " +
+                                          std::to_string(nmax) + "] for d = " + std::to_string(d));
+  if (!v_dev) return lsp::set_error(LSP_EINVAL, "v_dev is NULL");
+  lsp_problem* p = new (std::nothrow) lsp_problem();
+  if (!p) return lsp::set_error(LSP_ENOMEM, "host allocation failed");
+  p->d = d;
+  p->n = n;
+  p->N = 1;
+  for (int i = 0; i < d; ++i) p->N *= n;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  (void)hipGetDevice(&p->device);
+  int rc = LSP_OK;
+  if ((rc = dalloc((void**)&p->v, sizeof(double) * p->N, "potential")) ||
+      (rc = dalloc((void**)&p->z, sizeof(double) * 2 * p->N, "apply scratch")) ||
+      (rc = dalloc((void**)&p->tw, sizeof(double) * 2 * n, "twiddles")) ||
+      (rc = dalloc((void**)&p->flag, sizeof(int), "flag"))) {
+    lsp_destroy(p);
+    return rc;
+  }
+  // twiddles exp(-2 pi i j / n)
+  std::vector<double> tw(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    tw[2 * j] = cos(2.0 * M_PI * j / n);
+    tw[2 * j + 1] = -sin(2.0 * M_PI * j / n);
+  }
+  hipError_t e = hipMemcpy(p->tw, tw.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    rc = lsp::hip_check(e, "twiddle upload");
+    lsp_destroy(p);
+    return rc;
+  }
+  e = hipMemcpyAsync(p->v, v_dev, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) {
+    rc = lsp::hip_check(e, "potential copy");
+    lsp_destroy(p);
+    return rc;
+  }
+  if ((rc = check_finite_device(p, p->v, p->N, "v"))) {
+    lsp_destroy(p);
+    return rc;
+  }
+  *out = p;
+  return LSP_OK;
+}
+
+int lsp_set_potential(lsp_problem* p, const double* v_dev) {
+  if (!p || !v_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  hipError_t e =
+      hipMemcpyAsync(p->v, v_dev, sizeof(double) * p->N, hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "potential copy");
+  p->have_setup = false;
+  return check_finite_device(p, p->v, p->N, "v");
+}
+
+void lsp_destroy(lsp_problem* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->stream);
+  dfree(p->v);
+  dfree(p->z);
+  dfree(p->tw);
+  dfree(p->cosT);
+  dfree(p->flag);
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  p->ev_pool.clear();
+  dfree(p->kry);
+  dfree(p->red);
+  if (p->red_host) (void)hipHostFree(p->red_host);
+  free_workspace(p);
+  delete p;
+}
+
+int lsp_stencil_size(const lsp_problem* p) { return (p && p->have_setup) ? p->m : 0; }
+
+int lsp_profile(lsp_problem* p, int enable) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (enable) {
+    lsp::drain_events(p);
+    for (int i = 0; i < LSP_NUM_STAGES; ++i) {
+      p->prof_ms[i] = 0.0;
+      p->prof_count[i] = 0;
+    }
+    p->profiling = true;
+  } else {
+    lsp::drain_events(p);
+    p->profiling = false;
+  }
+  return LSP_OK;
+}
+
+int lsp_profile_read(lsp_problem* p, int nstages, double* ms_host, int* count_host) {
+  if (!p || nstages < 0) return lsp::set_error(LSP_EINVAL, "invalid argument");
+  lsp::drain_events(p);
+  for (int i = 0; i < nstages && i < LSP_NUM_STAGES; ++i) {
+    if (ms_host) ms_host[i] = p->prof_ms[i];
+    if (count_host) count_host[i] = p->prof_count[i];
+  }
+  return LSP_OK;
+}
+
+int lsp_default_num_shifts(int d, int n) {
+  if ((d != 2 && d != 3) || n < 1) return lsp::set_error(LSP_EINVAL, "invalid d or n");
+  const int s = (d == 2) ? n / 16 : n / 4;
+  return s < 1 ? 1 : s;
+}
+
+int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, double* P_dev,
+                      int32_t* idx_dev) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
+  if (precision != LSP_FP64) return lsp::set_error(LSP_EINVAL, "unsupported precision");
+  if (t < 1) return lsp::set_error(LSP_EINVAL, "t must be >= 1");
+  const int W = 2 * t + 1;
+  int m = 1;
+  for (int i = 0; i < p->d; ++i) m *= W;
+  if (m > lsp::kMaxStencil)
+    return lsp::set_error(LSP_EINVAL, "stencil size (2t+1)^d = " + std::to_string(m) +
+                                          " exceeds " + std::to_string(lsp::kMaxStencil));
+  if (W >= p->n) return lsp::set_error(LSP_EINVAL, "2t+1 must be smaller than n");
+  if (p->N < 2 * (int64_t)m) return lsp::set_error(LSP_EINVAL, "N must be at least 2m");
+  if (p->d == 3 && W != 3) return lsp::set_error(LSP_EINVAL, "d = 3 supports t = 1");
+  if (num_shifts == 0) num_shifts = lsp_default_num_shifts(p->d, p->n);
+  if (num_shifts < 1) return lsp::set_error(LSP_EINVAL, "num_shifts must be >= 0");
+  if (num_shifts > lsp::kMaxShifts)
+    return lsp::set_error(LSP_EINVAL, "num_shifts exceeds " + std::to_string(lsp::kMaxShifts));
+  int rc = ensure_workspace(p, num_shifts, t, m, m);
+  if (rc) return rc;
+  if (p->t != t || !p->cosT) {
+    (void)hipStreamSynchronize(p->stream);
+    if ((rc = upload_cos_table(p, W))) return rc;
+  }
+  p->t = t;
+  p->m = m;
+  p->num_shifts = num_shifts;
+  p->have_setup = false;
+  const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
+  int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
+  hipError_t e = lsp::launch_shift_list(p, num_shifts);
+  if (e != hipSuccess) return lsp::hip_check(e, "shift list launch");
+  lsp::stage_end(p, tk);
+  int chunks = 0;
+  tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
+  e = lsp::launch_green_sums(p, num_shifts, &chunks);
+  if (e != hipSuccess) return lsp::hip_check(e, "Green's sums launch");
+  lsp::stage_end(p, tk);
+  tk = lsp::stage_begin(p, LSP_STAGE_NULL);
+  e = lsp::launch_null_vectors(p, num_shifts, chunks);
+  if (e != hipSuccess) return lsp::hip_check(e, "null vector launch");
+  lsp::stage_end(p, tk);
+  tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
+  e = lsp::launch_assemble(p, P_dev, idx_dev);
+  if (e != hipSuccess) return lsp::hip_check(e, "assembly launch");
+  lsp::stage_end(p, tk);
+  lsp::stage_end(p, tk_all);
+  p->have_setup = true;
+  return LSP_OK;
+}
+
+int lsp_ps_apply(lsp_problem* p, const double* u_dev, double* y_dev) {
+  if (!p || !u_dev || !y_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (u_dev == y_dev) return lsp::set_error(LSP_EINVAL, "u and y must not alias");
+  const int tk = lsp::stage_begin(p, LSP_STAGE_APPLY);
+  const int rc = lsp::hip_check(lsp::launch_ps_apply(p, u_dev, y_dev), "ps_apply launch");
+  lsp::stage_end(p, tk);
+  return rc;
+}
+
+int lsp_c_apply(lsp_problem* p, const double* r_dev, double* z_dev) {
+  if (!p || !r_dev || !z_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (r_dev == z_dev) return lsp::set_error(LSP_EINVAL, "r and z must not alias");
+  if (!p->have_setup) return lsp::set_error(LSP_ESTATE, "c_apply needs a completed setup");
+  const int tk = lsp::stage_begin(p, LSP_STAGE_CAPPLY);
+  const int rc = lsp::hip_check(lsp::launch_c_apply(p, r_dev, z_dev), "c_apply launch");
+  lsp::stage_end(p, tk);
+  return rc;
+}
+
+int lsp_get_tables(lsp_problem* p, int capacity, int* nS, double* S_host, double* alpha_host,
+                   double* C_host, double* sigma_host, double* g_host, double* gam_host,
+                   double* M_host) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!p->have_setup) return lsp::set_error(LSP_ESTATE, "no setup has been run");
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "synchronise");
+  int ns = 0;
+  e = hipMemcpy(&ns, p->ws.nS, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return lsp::hip_check(e, "read |S|");
+  if (nS) *nS = ns;
+  if (capacity < ns) return lsp::set_error(LSP_EINVAL, "capacity smaller than |S|");
+  const int m = p->m;
+  const int W = 2 * p->t + 1;
+  int wd = 1;
+  for (int i = 0; i < p->d; ++i) wd *= W;
+  struct Copy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  } copies[] = {
+      {S_host, p->ws.S, sizeof(double) * ns},
+      {alpha_host, p->ws.alpha, sizeof(double) * ns * m},
+      {C_host, p->ws.Ctab, sizeof(double) * ns * m},
+      {sigma_host, p->ws.sigma, sizeof(double) * ns},
+      {g_host, p->ws.gtab, sizeof(double) * ns * wd},
+      {gam_host, p->ws.gamtab, sizeof(double) * ns * wd},
+  };
+  for (const Copy& c : copies) {
+    if (!c.dst || c.bytes == 0) continue;
+    e = hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lsp::hip_check(e, "table copy");
+  }
+  if (M_host && ns > 0) {
+    // the device keeps the Gram matrices as packed parity blocks
+    std::vector<double> packed((size_t)ns * m * m);
+    e = hipMemcpy(packed.data(), p->ws.Mtab, sizeof(double) * packed.size(),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lsp::hip_check(e, "Gram copy");
+    for (int i = 0; i < ns; ++i)
+      if (lsp::expand_gram_host(p->d, p->t, packed.data() + (size_t)i * m * m,
+                                M_host + (size_t)i * m * m) != 0)
+        return lsp::set_error(LSP_EINVAL, "unsupported stencil for the Gram expansion");
+  }
+  // eigen-solver status: report a failed elimination
+  std::vector<int> st(ns > 0 ? ns : 1);
+  if (ns > 0) {
+    e = hipMemcpy(st.data(), p->ws.status, sizeof(int) * ns, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lsp::hip_check(e, "status copy");
+    for (int i = 0; i < ns; ++i)
+      if (st[i] < 0)
+        return lsp::set_error(LSP_ERESONANT, "Gram matrix of shift " + std::to_string(i) +
+                                                 " could not be factorised");
+  }
+  return LSP_OK;
+}
+
+int lsp_export_pattern(int d, int n, int t, int64_t* col_host) {
+  if (!col_host) return lsp::set_error(LSP_EINVAL, "col_host is NULL");
+  if ((d != 2 && d != 3) || n < 1 || t < 1 || 2 * t + 1 > n)
+    return lsp::set_error(LSP_EINVAL, "invalid d, n or t");
+  const int W = 2 * t + 1;
+  int m = 1;
+  int64_t N = 1;
+  for (int i = 0; i < d; ++i) {
+    m *= W;
+    N *= n;
+  }
+  int64_t out = 0;
+  for (int64_t j = 0; j < N; ++j) {
+    int jc[3] = {0, 0, 0};
+    int64_t rem = j;
+    for (int i = d - 1; i >= 0; --i) {
+      jc[i] = (int)(rem % n);
+      rem /= n;
+    }
+    for (int a = 0; a < m; ++a) {
+      int ra = a;
+      int ac[3] = {0, 0, 0};
+      for (int i = d - 1; i >= 0; --i) {
+        ac[i] = ra % W - t;
+        ra /= W;
+      }
+      int64_t col = 0;
+      for (int i = 0; i < d; ++i) col = col * n + (((jc[i] + ac[i]) % n) + n) % n;
+      col_host[out++] = col;
+    }
+  }
+  return LSP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(restart) with right preconditioner P^-1 C. Basis V and preconditioned
+// vectors Z = P^-1 C V are kept on the device (flexible form, so the update
+// x += Z y needs no second preconditioner application). Orthogonalisation is
+// classical Gram-Schmidt applied twice; the small Hessenberg least-squares
+// problem is updated with Givens rotations on the host.
+// ---------------------------------------------------------------------------
+int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev, double rtol,
+                      int restart, int maxit, lsp_host_solve_fn solveP, void* user, int* iters,
+                      double* relres) {
+  using cplx = std::complex<double>;
+  if (!p || !f_dev || !u_dev || !solveP) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (!(rtol > 0.0) || restart < 1 || restart > 1000 || maxit < 1)
+    return lsp::set_error(LSP_EINVAL, "invalid rtol, restart or maxit");
+  if (!p->have_setup) return lsp::set_error(LSP_ESTATE, "precond_solve needs a completed setup");
+  const int64_t N = p->N;
+  const int64_t N2 = 2 * N;
+  int rc = check_finite_device(p, f_dev, N2, "f");
+  if (rc) return rc;
+  // workspace: V (restart+1), Z (restart), w, tmp; coefficient buffer
+  const size_t need = (size_t)N2 * (2 * (size_t)restart + 3) + 2 * (size_t)(restart + 2);
+  if (need > p->kry_doubles) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(p->kry);
+    if ((rc = dalloc((void**)&p->kry, sizeof(double) * need, "Krylov basis"))) return rc;
+    p->kry_doubles = need;
+    dfree(p->red);
+    if (p->red_host) (void)hipHostFree(p->red_host);
+    p->red_host = nullptr;
+  }
+  const int nblk = lsp::dot_blocks(N);
+  const size_t red_doubles = 2 * (size_t)(restart + 2) * nblk;
+  if (!p->red) {
+    if ((rc = dalloc((void**)&p->red, sizeof(double) * red_doubles, "reduction"))) return rc;
+    if (hipHostMalloc((void**)&p->red_host, sizeof(double) * (red_doubles + 4 * (size_t)N),
+                      hipHostMallocDefault) != hipSuccess)
+      return lsp::set_error(LSP_ENOMEM, "pinned host allocation failed");
+  }
+  double* V = p->kry;
+  double* Z = V + (size_t)N2 * (restart + 1);
+  double* w = Z + (size_t)N2 * restart;
+  double* tmp = w + N2;
+  double* coef = tmp + N2;
+  double* hbuf = p->red_host;                  // reduction results
+  double* rhs_h = p->red_host + red_doubles;   // P-solve right-hand side
+  double* x_h = rhs_h + N2;                    // P-solve solution
+  hipStream_t s = p->stream;
+
+#define LSP_HIP(call, what)                                     \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return lsp::hip_check(e_, what);      \
+  } while (0)
+
+  // dots: out[i] = <V_i, x> for i < nv, summed in block order on the host
+  auto dots = [&](const double* Vb, int nv, const double* x, cplx* out) -> int {
+    LSP_HIP(lsp::launch_multi_dot(Vb, N, nv, x, N, p->red, s), "dot");
+    LSP_HIP(hipMemcpyAsync(hbuf, p->red, sizeof(double) * 2 * nv * nblk, hipMemcpyDeviceToHost,
+                           s),
+            "dot readback");
+    LSP_HIP(hipStreamSynchronize(s), "dot sync");
+    for (int i = 0; i < nv; ++i) {
+      double re = 0.0, im = 0.0;
+      for (int b = 0; b < nblk; ++b) {
+        re += hbuf[2 * ((size_t)i * nblk + b)];
+        im += hbuf[2 * ((size_t)i * nblk + b) + 1];
+      }
+      out[i] = cplx(re, im);
+    }
+    return LSP_OK;
+  };
+  auto axpy = [&](const double* Vb, int nv, const cplx* c, double sign, double* x) -> int {
+    LSP_HIP(hipMemcpyAsync(coef, c, sizeof(double) * 2 * nv, hipMemcpyHostToDevice, s),
+            "coefficient upload");
+    LSP_HIP(lsp::launch_multi_axpy(Vb, N, nv, coef, sign, x, N, s), "axpy");
+    LSP_HIP(hipStreamSynchronize(s), "axpy sync");  // coef is host memory read by the copy
+    return LSP_OK;
+  };
+
+  cplx fn2;
+  if ((rc = dots(f_dev, 1, f_dev, &fn2))) return rc;
+  const double fnorm = sqrt(fn2.real());
+  LSP_HIP(hipMemsetAsync(u_dev, 0, sizeof(double) * N2, s), "zero u");
+  int it = 0;
+  double est = 1.0;
+  if (fnorm == 0.0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return LSP_OK;
+  }
+  std::vector<cplx> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1),
+      h(restart + 1), h2(restart + 1), y(restart);
+  bool first = true;
+  while (it < maxit) {
+    // r = f - A u
+    if (first) {
+      LSP_HIP(hipMemcpyAsync(V, f_dev, sizeof(double) * N2, hipMemcpyDeviceToDevice, s), "copy f");
+    } else {
+      LSP_HIP(lsp::launch_ps_apply(p, u_dev, tmp), "apply");
+      LSP_HIP(lsp::launch_sub(f_dev, tmp, V, N, s), "residual");
+    }
+    first = false;
+    cplx b2;
+    if ((rc = dots(V, 1, V, &b2))) return rc;
+    const double beta = sqrt(b2.real());
+    est = beta / fnorm;
+    if (est <= rtol) break;
+    LSP_HIP(lsp::launch_scale(V, 1.0 / beta, V, N, s), "normalise");
+    std::fill(H.begin(), H.end(), cplx(0.0));
+    std::fill(g.begin(), g.end(), cplx(0.0));
+    g[0] = beta;
+    int k_used = 0;
+    for (int k = 0; k < restart; ++k) {
+      double* vk = V + (size_t)N2 * k;
+      double* zk = Z + (size_t)N2 * k;
+      // z_k = P^-1 (C v_k): C on the device, the P-solve on the host
+      LSP_HIP(lsp::launch_c_apply(p, vk, tmp), "c_apply");
+      LSP_HIP(hipMemcpyAsync(rhs_h, tmp, sizeof(double) * N2, hipMemcpyDeviceToHost, s), "D2H");
+      LSP_HIP(hipStreamSynchronize(s), "D2H sync");
+      if (solveP(user, rhs_h, x_h, N) != 0)
+        return lsp::set_error(LSP_ESOLVER, "host P-solve callback returned an error");
+      LSP_HIP(hipMemcpyAsync(zk, x_h, sizeof(double) * N2, hipMemcpyHostToDevice, s), "H2D");
+      // w = A z_k
+      LSP_HIP(lsp::launch_ps_apply(p, zk, w), "apply");
+      // classical Gram-Schmidt, twice
+      if ((rc = dots(V, k + 1, w, h.data()))) return rc;
+      if ((rc = axpy(V, k + 1, h.data(), -1.0, w))) return rc;
+      if ((rc = dots(V, k + 1, w, h2.data()))) return rc;
+      if ((rc = axpy(V, k + 1, h2.data(), -1.0, w))) return rc;
+      for (int i = 0; i <= k; ++i) h[i] += h2[i];
+      cplx wn2;
+      if ((rc = dots(w, 1, w, &wn2))) return rc;
+      const double hk1 = sqrt(wn2.real());
+      if (hk1 > 0.0) {
+        LSP_HIP(lsp::launch_scale(w, 1.0 / hk1, V + (size_t)N2 * (k + 1), N, s), "normalise");
+      }
+      // apply previous rotations to column k
+      for (int i = 0; i < k; ++i) {
+        const cplx t0 = std::conj(cs[i]) * h[i] + std::conj(sn[i]) * h[i + 1];
+        h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+        h[i] = t0;
+      }
+      const cplx a = h[k];
+      const double bb = hk1;
+      const double rho = hypot(std::abs(a), bb);
+      cs[k] = rho > 0.0 ? a / rho : cplx(1.0);
+      sn[k] = rho > 0.0 ? cplx(bb / rho) : cplx(0.0);
+      h[k] = rho;
+      for (int i = 0; i <= k; ++i) H[(size_t)i * restart + k] = h[i];
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = std::conj(cs[k]) * g[k];
+      ++it;
+      k_used = k + 1;
+      est = std::abs(g[k + 1]) / fnorm;
+      if (est <= rtol || it >= maxit || hk1 == 0.0) break;
+    }
+    // y = H^-1 g (upper triangular), u += Z y
+    for (int i = k_used - 1; i >= 0; --i) {
+      cplx acc = g[i];
+      for (int j = i + 1; j < k_used; ++j) acc -= H[(size_t)i * restart + j] * y[j];
+      y[i] = acc / H[(size_t)i * restart + i];
+    }
+    if ((rc = axpy(Z, k_used, y.data(), 1.0, u_dev))) return rc;
+    if (est <= rtol) break;
+  }
+  // true residual
+  LSP_HIP(lsp::launch_ps_apply(p, u_dev, tmp), "apply");
+  LSP_HIP(lsp::launch_sub(f_dev, tmp, w, N, s), "residual");
+  cplx r2;
+  if ((rc = dots(w, 1, w, &r2))) return rc;
+  if (iters) *iters = it;
+  if (relres) *relres = sqrt(r2.real()) / fnorm;
+#undef LSP_HIP
+  return (est <= rtol) ? LSP_OK : LSP_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the liblsp translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lsp.h"
+
+namespace lsp {
+
+// 4 pi^2: the symbol of -d^2/dx^2 on [0,1) is 4 pi^2 k^2 (Sec. 2).
+constexpr double kFourPi2 = 39.47841760435743;
+constexpr double kPi2 = 9.869604401089358;
+
+// Upper bounds of the build.
+constexpr int kMaxStencil = 64;     // m = (2t+1)^d
+constexpr int kMaxShifts = 1024;    // requested |S|
+constexpr int kMinMaxBlocks = 512;  // blocks of the min/max reduction
+
+struct Workspace {
+  // shift list (Sec. 4.1)
+  double* minmax_part = nullptr;  // [2 * kMinMaxBlocks]
+  double* S = nullptr;            // [kMaxShifts]
+  int* nS = nullptr;              // effective |S|, device resident
+  double* vrange = nullptr;       // [2] v_min, v_max
+  // Green's kernel sums (Sec. 4.2)
+  double* green_part = nullptr;   // [shifts][chunks][2 * W^d]
+  size_t green_part_cap = 0;      // doubles
+  // per-shift tables
+  double* gtab = nullptr;         // [shifts][W^d]   W = 2t+1, offsets [0,2t]^d
+  double* gamtab = nullptr;       // [shifts][W^d]
+  double* Mtab = nullptr;         // [shifts][m*m]
+  double* alpha = nullptr;        // [shifts][m]
+  double* Ctab = nullptr;         // [shifts][m]
+  double* sigma = nullptr;        // [shifts]
+  double* actab = nullptr;        // [shifts][m][2] interleaved (alpha, C)
+  int* status = nullptr;          // [shifts] eigen-solver status
+  int cap_shifts = 0;
+  int cap_m = 0;
+  int cap_w = 0;                  // W^d capacity
+};
+
+}  // namespace lsp
+
+struct lsp_problem {
+  int d = 0;
+  int n = 0;
+  int64_t N = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  double* v = nullptr;        // [N] potential
+  double* tw = nullptr;       // [2n] exp(-2 pi i j / n), interleaved
+  double* cosT = nullptr;     // [n] cos(2 pi j / n)
+  double* z = nullptr;        // [2N] ps_apply partial sums
+  int* flag = nullptr;        // [1] device scratch flag
+  // setup state
+  int t = 0;
+  int m = 0;
+  int num_shifts = 0;         // requested |S| of the last setup
+  bool have_setup = false;
+  lsp::Workspace ws;
+  // per-stage event timing (lsp_profile)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;                 // created events, reused
+  std::vector<std::pair<int, int>> ev_pending;     // (stage, index of start event)
+  size_t ev_used = 0;
+  double prof_ms[LSP_NUM_STAGES] = {0};
+  int prof_count[LSP_NUM_STAGES] = {0};
+  // Krylov workspace (allocated on first precond_solve)
+  double* kry = nullptr;      // basis and temporaries
+  size_t kry_doubles = 0;
+  double* red = nullptr;      // reduction partials
+  double* red_host = nullptr; // pinned host mirror
+};
+
+namespace lsp {
+
+int set_error(int code, const std::string& msg);
+// Record a timing event pair around a stage when profiling is on:
+// stage_begin returns a token passed to stage_end (-1 when off).
+int stage_begin(lsp_problem* p, int stage);
+void stage_end(lsp_problem* p, int token);
+int hip_check(hipError_t e, const char* what);
+
+// ---- kernel launchers (asynchronous, on p->stream) ----
+// ps_apply: y = (L + diag v) u
+hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y);
+// count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
+hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
+// stencil setup stages
+hipError_t launch_shift_list(lsp_problem* p, int num_shifts);
+int minmax_blocks(int64_t N);  // partials written by launch_shift_list
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out);
+// doubles of partial sums the Green's-sum launch writes for (d, n, t, shifts)
+size_t green_partial_doubles(int d, int n, int t, int shifts);
+// full m x m Gram matrix from the packed parity blocks (host)
+int expand_gram_host(int d, int t, const double* packed, double* full);
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks);
+hipError_t launch_assemble(lsp_problem* p, double* P, int32_t* idx);
+// preconditioner halves and Krylov helpers
+hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
+
+}  // namespace lsp

@@ -1,0 +1,493 @@
+// Gram matrix of eq. (A) and the stencil alpha_s (Sec. 3, 4.2), one block
+// per shift.
+//
+// With g = g_s and q = g_s * g_s on the offsets [0, 2t]^d:
+//   G_mu,mu[a][b] = g[|a - b|],  A1[a][b] = q[|a - b|],  M = A1 - G_mu,mu G_mu,mu
+// and alpha_s is the unit eigenvector of the smallest eigenvalue of M
+// (the smallest left singular vector of G_s[mu, mu^c]); sigma_min^2 is that
+// eigenvalue and C_s = G_mu,mu alpha_s.
+//
+// Because g and q are even in every coordinate, all three matrices are block
+// diagonal in the parity basis of the neighbourhood (see Parity): 2^d blocks,
+// e.g. sizes 9, 6, 6, 4 for d = 2, t = 2. Wave c of the block owns parity
+// class c. Lane p holds row p of G_b, A1_b, M_b and X_b = M_b^-1 in
+// registers; rows are shared through readlane broadcasts, so no LDS traffic or
+// barriers sit on the serial path. Per class:
+//   1. rows of G_b and A1_b from the tables, A2_b = G_b G_b, M_b = A1_b - A2_b;
+//   2. X_b = M_b^-1 by Gauss-Jordan elimination (M is positive semi-definite;
+//      a non-positive pivot restarts on M_b + tau I, which has the same
+//      eigenvectors);
+//   3. power iteration with X_b (the smallest eigenvector of M_b is the
+//      dominant one of X_b) until successive normalised iterates differ by
+//      less than 1e-15;
+//   4. two inverse-iteration steps whose solve is refined once against the
+//      FP64 M_b (y0 = X x, y = y0 + X (x - M y0)), removing the forward error
+//      of the explicit inverse;
+//   5. lambda_c = x^T M_b x and G_b x.
+// The class with the smallest lambda_c gives alpha (ties: lowest class);
+// alpha and C are mapped back to the offsets of mu_0^t, normalised to unit
+// norm with the largest-magnitude entry positive (lowest offset on ties).
+#include "setup_common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using lsp::bcast;
+using lsp::Nbhd;
+using lsp::Parity;
+using lsp::Pow;
+
+template <int D, int W>
+struct NullShared {
+  static constexpr int NC = 1 << D;
+  static constexpr int WD = Pow<D, W>::v;
+  static constexpr int BMAX = Parity<D, W>::size(0);
+  double g[WD];
+  double q[WD];
+  double lam[NC];
+  double vec[NC][BMAX];
+  double gv[NC][BMAX];
+  int status[NC];
+  double alpha[WD];
+  double stage[2048];
+};
+
+template <int D, int W, int C>
+__device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab_si) {
+  using Pa = Parity<D, W>;
+  constexpr int B = Pa::size(C);
+  constexpr int NS = 1 << D;  // per-axis term choices of a block entry
+  const int p = (lane < B) ? lane : 0;
+
+  // per-axis 1D indices of row p
+  int jp[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) jp[i] = Pa::coord(C, p, i);
+
+  // ---- rows of G_b and A1_b ----
+  // In the parity basis a block entry factorises over axes: for 1D indices
+  // j (row) and j' (column) of one axis, the reflected pairs collapse to
+  //   odd axis:             f(|j - j'|) - f(j + j')
+  //   even, j, j' > 0:      f(|j - j'|) + f(j + j')
+  //   even, one of them 0:  sqrt2 f(j + j')
+  //   even, both 0:         f(0)
+  // so an entry of G_b (f = g) or A1_b (f = g*g) is a sum over the 2^D
+  // choices of the per-axis terms, each a product of weights times one
+  // table value g[dd_1, ..., dd_D].
+  double grow[B], arow[B];
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) {
+    int dd0[D], dd1[D];
+    double w0[D], w1[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const int jq = Pa::coord(C, qc, i);
+      const int j = jp[i];
+      const int dm = (j > jq) ? j - jq : jq - j;
+      dd0[i] = dm;
+      dd1[i] = j + jq;
+      if (Pa::odd(C, i)) {
+        w0[i] = 1.0;
+        w1[i] = -1.0;
+      } else if (j > 0 && jq > 0) {
+        w0[i] = 1.0;
+        w1[i] = 1.0;
+      } else if (j == 0 && jq == 0) {
+        w0[i] = 1.0;
+        w1[i] = 0.0;
+      } else {
+        dd0[i] = j + jq;
+        w0[i] = 1.4142135623730951;
+        w1[i] = 0.0;
+      }
+    }
+    double sg = 0.0, sq = 0.0;
+#pragma unroll
+    for (int cmb = 0; cmb < NS; ++cmb) {
+      double w = 1.0;
+      int idx = 0;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const bool second = (cmb >> (D - 1 - i)) & 1;
+        w *= second ? w1[i] : w0[i];
+        idx = idx * W + (second ? dd1[i] : dd0[i]);
+      }
+      sg = fma(w, sh.g[idx], sg);
+      sq = fma(w, sh.q[idx], sq);
+    }
+    grow[qc] = sg;
+    arow[qc] = sq;
+  }
+
+  // ---- M_b = A1_b - G_b G_b ----
+  double mrow[B];
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) mrow[qc] = 0.0;
+#pragma unroll
+  for (int r = 0; r < B; ++r) {
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) mrow[qc] = fma(grow[r], bcast(grow[qc], r), mrow[qc]);
+  }
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) mrow[qc] = arow[qc] - mrow[qc];
+  if (lane < B) {
+    double* mo = Mtab_si + Pa::offset(C) + lane * B;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) mo[qc] = mrow[qc];
+  }
+
+  // ---- X_b = (M_b + tau I)^-1 by Gauss-Jordan ----
+  double dmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    double dk = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc)
+      if (qc == k) dk = mrow[qc];
+    dmax = fmax(dmax, fabs(bcast(dk, k)));
+  }
+  double xrow[B];
+  double tau = 0.0;
+  int tries = 0;
+  bool ok = false;
+  while (!ok && tries < 4) {
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) xrow[qc] = mrow[qc] + ((qc == p) ? tau : 0.0);
+    ok = true;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      double rk[B];
+#pragma unroll
+      for (int qc = 0; qc < B; ++qc) rk[qc] = bcast(xrow[qc], k);
+      const double piv = rk[k];
+      if (!(piv > 0.0) || !isfinite(piv)) ok = false;  // uniform: piv is broadcast
+      const double inv = ok ? lsp::rcp_nr(piv) : 0.0;
+      if (lane == k) {
+#pragma unroll
+        for (int qc = 0; qc < B; ++qc) xrow[qc] = (qc == k) ? inv : rk[qc] * inv;
+      } else {
+        double xk = 0.0;
+#pragma unroll
+        for (int qc = 0; qc < B; ++qc)
+          if (qc == k) xk = xrow[qc];
+        const double f = xk * inv;
+#pragma unroll
+        for (int qc = 0; qc < B; ++qc) xrow[qc] = (qc == k) ? -f : fma(-f, rk[qc], xrow[qc]);
+      }
+    }
+    if (!ok) {
+      ++tries;
+      tau = (tau == 0.0) ? 1e-14 * dmax : tau * 100.0;
+    }
+  }
+
+  // ---- power iteration on X_b (vector replicated in every lane) ----
+  double xscale = 0.0;  // 1 / (largest |diagonal| of X_b): keeps iterates O(1)
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    double dk = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc)
+      if (qc == k) dk = xrow[qc];
+    xscale = fmax(xscale, fabs(bcast(dk, k)));
+  }
+  xscale = (xscale > 0.0 && isfinite(xscale)) ? 1.0 / xscale : 1.0;
+  double xa[B], xprev[B];
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) {
+    xa[qc] = 1.0 + 0.37 * (double)((qc * 7 + 3) % 11) / 11.0;  // generic start
+    xprev[qc] = 0.0;
+  }
+  for (int it = 0; it < 100; ++it) {
+#pragma unroll
+    for (int rep = 0; rep < 4; ++rep) {
+      double y = 0.0;
+#pragma unroll
+      for (int qc = 0; qc < B; ++qc) y = fma(xrow[qc], xa[qc], y);
+      y *= xscale;
+#pragma unroll
+      for (int qc = 0; qc < B; ++qc) xa[qc] = bcast(y, qc);
+    }
+    double nrm = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) nrm = fma(xa[qc], xa[qc], nrm);
+    const double sc = lsp::rsqrt_nr(nrm);
+    double dmx = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) {
+      xa[qc] *= sc;
+      dmx = fmax(dmx, fabs(xa[qc] - xprev[qc]));
+      xprev[qc] = xa[qc];
+    }
+    if (dmx < 1e-15) break;
+  }
+
+  // ---- two inverse-iteration steps with one refinement of each solve ----
+  for (int step = 0; step < 2; ++step) {
+    double y0 = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) y0 = fma(xrow[qc], xa[qc], y0);
+    double y0a[B];
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) y0a[qc] = bcast(y0, qc);
+    double my = 0.0, xp = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) {
+      my = fma(mrow[qc], y0a[qc], my);
+      if (qc == p) {
+        my = fma(tau, y0a[qc], my);
+        xp = xa[qc];
+      }
+    }
+    const double rr = xp - my;
+    double ra[B];
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) ra[qc] = bcast(rr, qc);
+    double cy = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) cy = fma(xrow[qc], ra[qc], cy);
+    const double yp = y0 + cy;
+    double nrm = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) {
+      xa[qc] = bcast(yp, qc);
+      nrm = fma(xa[qc], xa[qc], nrm);
+    }
+    const double sc = lsp::rsqrt_nr(nrm);
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) xa[qc] *= sc;
+  }
+
+  // ---- lambda_c = x^T M_b x, G_b x ----
+  double mx = 0.0, gx = 0.0;
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) {
+    mx = fma(mrow[qc], xa[qc], mx);
+    gx = fma(grow[qc], xa[qc], gx);
+  }
+  double lam = 0.0;
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) lam = fma(xa[qc], bcast(mx, qc), lam);
+  if (lane < B) {
+    double xl = 0.0;
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc)
+      if (qc == lane) xl = xa[qc];
+    sh.vec[C][lane] = xl;
+    sh.gv[C][lane] = gx;
+  }
+  if (lane == 0) {
+    sh.lam[C] = ok ? lam : INFINITY;
+    sh.status[C] = ok ? tries : -1;
+  }
+}
+
+template <int D, int W>
+__global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
+    const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
+    double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
+    double* sigma_out, double* actab, int* status) {
+  using Pa = Parity<D, W>;
+  using Nb = Nbhd<D, W>;
+  constexpr int NC = 1 << D;
+  constexpr int WD = Pow<D, W>::v;
+  constexpr int M = WD;
+  constexpr int NP = W * (W + 1) / 2;
+  constexpr int WO2 = Pow<D - 2, W>::v;
+  constexpr int NV = 2 * WO2 * NP;
+  constexpr int T = 64 * NC;
+  __shared__ NullShared<D, W> sh;
+  const int si = blockIdx.x;
+  if (si >= *nS) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+
+  // ---- sum the partial sums of the Green's kernels (staged through LDS) ----
+  const double* ps = part + (int64_t)si * nblk * NV;
+  double acc = 0.0;  // thread tid < NV owns value tid
+  const int total = nblk * NV;
+  constexpr int CHUNK = 2048;
+  for (int c0 = 0; c0 < total; c0 += CHUNK) {
+    const int cn = min(CHUNK, total - c0);
+    for (int e = tid; e < cn; e += T) sh.stage[e] = ps[c0 + e];
+    __syncthreads();
+    if (tid < NV) {
+      // entries of value tid inside this chunk: global index b*NV + tid
+      int e = (c0 / NV) * NV + tid;
+      if (e < c0) e += NV;
+      for (; e < c0 + cn; e += NV) acc += sh.stage[e - c0];
+    }
+    __syncthreads();
+  }
+  // symmetrised pair sums -> full tables, scaled by 1/N
+  if (tid < NV) sh.stage[tid] = acc;
+  __syncthreads();
+  for (int e = tid; e < WD; e += T) {
+    const int db0 = e % W;
+    const int da0 = (e / W) % W;
+    const int x = (D == 3) ? e / (W * W) : 0;
+    const int da = min(da0, db0), db = max(da0, db0);
+    const int pi = da * W - (da * (da - 1)) / 2 + (db - da);
+    const double gval = sh.stage[x * NP + pi] * invN;
+    const double qval = sh.stage[WO2 * NP + x * NP + pi] * invN;
+    sh.g[e] = gval;
+    sh.q[e] = qval;
+    gtab[(int64_t)si * WD + e] = gval;
+    gamtab[(int64_t)si * WD + e] = qval;
+  }
+  __syncthreads();
+
+  // ---- one parity class per wave ----
+  double* Mtab_si = Mtab + (int64_t)si * M * M;
+  switch (wid) {
+    case 0: solve_class<D, W, 0>(sh, lane, si, Mtab_si); break;
+    case 1: solve_class<D, W, 1>(sh, lane, si, Mtab_si); break;
+    case 2: solve_class<D, W, 2>(sh, lane, si, Mtab_si); break;
+    case 3: solve_class<D, W, 3>(sh, lane, si, Mtab_si); break;
+    default:
+      if constexpr (D == 3) {
+        switch (wid) {
+          case 4: solve_class<D, W, 4>(sh, lane, si, Mtab_si); break;
+          case 5: solve_class<D, W, 5>(sh, lane, si, Mtab_si); break;
+          case 6: solve_class<D, W, 6>(sh, lane, si, Mtab_si); break;
+          case 7: solve_class<D, W, 7>(sh, lane, si, Mtab_si); break;
+        }
+      }
+      break;
+  }
+  __syncthreads();
+
+  // ---- pick the class, map back to mu_0^t, normalise the sign ----
+  // (every wave reaches the barrier below; only wave 0 writes results)
+  int cs = 0;
+  for (int c = 1; c < NC; ++c)
+    if (sh.lam[c] < sh.lam[cs]) cs = c;
+  const double lam = sh.lam[cs];
+  double av = 0.0, cv = 0.0;
+  if (wid == 0 && lane < M) {
+    // offset a = lane: block row and coefficient of a in class cs
+    double coef = 1.0;
+    int pidx = 0;
+    for (int i = 0; i < D; ++i) {
+      const int xi = Nb::comp(lane, i);
+      const int ji = xi < 0 ? -xi : xi;
+      const int odd = Pa::odd(cs, i);
+      if (odd && ji == 0) coef = 0.0;
+      if (ji != 0) coef *= (odd && xi < 0) ? -lsp::kInvSqrt2 : lsp::kInvSqrt2;
+      pidx = pidx * Pa::count(cs, i) + (ji - odd < 0 ? 0 : ji - odd);
+    }
+    if (coef != 0.0) {
+      av = coef * sh.vec[cs][pidx];
+      cv = coef * sh.gv[cs][pidx];
+    }
+    sh.alpha[lane] = av;
+  }
+  __syncthreads();
+  if (wid != 0) return;
+  int jm = 0;
+  double am = fabs(sh.alpha[0]);
+  for (int a = 1; a < M; ++a) {
+    const double aa = fabs(sh.alpha[a]);
+    if (aa > am) {
+      am = aa;
+      jm = a;
+    }
+  }
+  const double sgn = (sh.alpha[jm] < 0.0) ? -1.0 : 1.0;
+  if (lane < M) {
+    av *= sgn;
+    cv *= sgn;
+    alpha_out[(int64_t)si * M + lane] = av;
+    C_out[(int64_t)si * M + lane] = cv;
+    reinterpret_cast<double2*>(actab)[(int64_t)si * M + lane] = make_double2(av, cv);
+  }
+  if (lane == 0) {
+    sigma_out[si] = sqrt(fmax(lam, 0.0));
+    status[si] = sh.status[cs];
+  }
+}
+
+template <int D, int W>
+hipError_t run_null(lsp_problem* p, int num_shifts, int nblk) {
+  const double invN = 1.0 / (double)p->N;
+  hipLaunchKernelGGL((null_vector_kernel<D, W>), dim3(num_shifts), dim3(64 * (1 << D)), 0,
+                     p->stream, p->ws.nS, p->ws.green_part, nblk, invN, p->ws.gtab,
+                     p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab, p->ws.sigma,
+                     p->ws.actab, p->ws.status);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace lsp {
+
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk) {
+  const int W = 2 * p->t + 1;
+  if (p->d == 2 && W == 3) return run_null<2, 3>(p, num_shifts, nblk);
+  if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, nblk);
+  if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, nblk);
+  if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, nblk);
+  return hipErrorInvalidValue;
+}
+
+// Dense orthonormal basis of parity class c as an m x b matrix (column p =
+// basis vector p in the offsets of mu_0^t); used on the host to expand the
+// packed Gram blocks back to the full m x m matrix.
+template <int D, int W>
+void parity_basis_host(int c, double* Q) {
+  using Pa = Parity<D, W>;
+  using Nb = Nbhd<D, W>;
+  const int M = Pow<D, W>::v;
+  const int B = Pa::size(c);
+  for (int i = 0; i < M * B; ++i) Q[i] = 0.0;
+  for (int a = 0; a < M; ++a) {
+    double coef = 1.0;
+    int pidx = 0;
+    for (int i = 0; i < D; ++i) {
+      const int xi = Nb::comp(a, i);
+      const int ji = xi < 0 ? -xi : xi;
+      const int odd = Pa::odd(c, i);
+      if (odd && ji == 0) coef = 0.0;
+      if (ji != 0) coef *= (odd && xi < 0) ? -kInvSqrt2 : kInvSqrt2;
+      pidx = pidx * Pa::count(c, i) + (ji - odd < 0 ? 0 : ji - odd);
+    }
+    if (coef != 0.0) Q[a * B + pidx] = coef;
+  }
+}
+
+// M_full = sum_c Q_c M_c Q_c^T from the packed blocks.
+int expand_gram_host(int d, int t, const double* packed, double* full) {
+  const int W = 2 * t + 1;
+  int M = 1;
+  for (int i = 0; i < d; ++i) M *= W;
+  for (int i = 0; i < M * M; ++i) full[i] = 0.0;
+  std::vector<double> Q;
+  int off = 0;
+  for (int c = 0; c < (1 << d); ++c) {
+    int B = 1;
+    for (int i = 0; i < d; ++i) B *= ((c >> (d - 1 - i)) & 1) ? t : t + 1;
+    Q.assign((size_t)M * B, 0.0);
+    if (d == 2 && W == 3) parity_basis_host<2, 3>(c, Q.data());
+    else if (d == 2 && W == 5) parity_basis_host<2, 5>(c, Q.data());
+    else if (d == 2 && W == 7) parity_basis_host<2, 7>(c, Q.data());
+    else if (d == 3 && W == 3) parity_basis_host<3, 3>(c, Q.data());
+    else return -1;
+    const double* Mc = packed + off;
+    for (int a = 0; a < M; ++a)
+      for (int b = 0; b < M; ++b) {
+        double s = 0.0;
+        for (int pp = 0; pp < B; ++pp) {
+          const double qa = Q[(size_t)a * B + pp];
+          if (qa == 0.0) continue;
+          for (int qq = 0; qq < B; ++qq) s += qa * Mc[pp * B + qq] * Q[(size_t)b * B + qq];
+        }
+        full[(size_t)a * M + b] += s;
+      }
+    off += B * B;
+  }
+  return 0;
+}
+
+}  // namespace lsp

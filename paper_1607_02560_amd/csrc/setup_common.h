@@ -1,0 +1,191 @@
+// Compile-time geometry of the neighbourhood mu_0^t and small device helpers
+// shared by the stencil-setup kernels.
+#pragma once
+
+#include "lsp_internal.h"
+
+namespace lsp {
+
+template <int D, int W>
+struct Pow {
+  static constexpr int v = W * Pow<D - 1, W>::v;
+};
+template <int W>
+struct Pow<0, W> {
+  static constexpr int v = 1;
+};
+
+// Offsets of mu_0^t = [-t, t]^D in lexicographic order (last axis fastest),
+// t = (W - 1)/2; the Green's tables hold offsets [0, 2t]^D in the same order.
+template <int D, int W>
+struct Nbhd {
+  static constexpr int t = (W - 1) / 2;
+  static constexpr int M = Pow<D, W>::v;
+  // component i of offset a
+  __host__ __device__ static constexpr int comp(int a, int i) {
+    int rem = a;
+    for (int j = D - 1; j > i; --j) rem /= W;
+    return rem % W - t;
+  }
+  // index in the [0, 2t]^D table of the componentwise |a - b|
+  __host__ __device__ static constexpr int diff_index(int a, int b) {
+    int idx = 0;
+    for (int i = 0; i < D; ++i) {
+      int dd = comp(a, i) - comp(b, i);
+      if (dd < 0) dd = -dd;
+      idx = idx * W + dd;
+    }
+    return idx;
+  }
+};
+
+// Parity classes of the neighbourhood.
+// The Green's kernel is even in every coordinate, so G[mu,mu], A1 and
+// M = A1 - A2 commute with the reflection of any axis. With the orthonormal
+// 1D basis {e_0, (e_j + e_-j)/sqrt2 : j = 1..t} (even) and
+// {(e_j - e_-j)/sqrt2 : j = 1..t} (odd), their tensor products split
+// [-t,t]^D into 2^D classes c (bit D-1-i of c = parity along axis i) and the
+// matrices are block diagonal. Class c has size prod_i (odd_i ? t : t+1);
+// row p of a block is the tensor product of the 1D basis vectors with
+// indices j_i = coord(c, p, i) (1..t for odd axes, 0..t for even ones).
+template <int D, int W>
+struct Parity {
+  static constexpr int t = (W - 1) / 2;
+  static constexpr int NC = 1 << D;
+  __host__ __device__ static constexpr int odd(int c, int i) { return (c >> (D - 1 - i)) & 1; }
+  __host__ __device__ static constexpr int count(int c, int i) { return odd(c, i) ? t : t + 1; }
+  __host__ __device__ static constexpr int size(int c) {
+    int b = 1;
+    for (int i = 0; i < D; ++i) b *= count(c, i);
+    return b;
+  }
+  __host__ __device__ static constexpr int offset(int c) {  // packed block storage
+    int o = 0;
+    for (int k = 0; k < c; ++k) o += size(k) * size(k);
+    return o;
+  }
+  __host__ __device__ static constexpr int coord(int c, int p, int i) {
+    int rem = p;
+    for (int ax = D - 1; ax > i; --ax) rem /= count(c, ax);
+    return rem % count(c, i) + odd(c, i);
+  }
+};
+
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+// 1/x: hardware estimate refined by two Newton steps (within an ulp or two).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate and two Newton steps.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// Broadcast lane `src` (wave-uniform) of a double to every lane.
+__device__ __forceinline__ double bcast(double x, int src) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Index of the shift of the sorted list S closest to vj (Sec. 4.1); the two
+// neighbours of the insertion point are compared and ties go to the lower index.
+__device__ __forceinline__ int nearest_shift(const double* S, int nS, double vj) {
+  int lo = 0, hi = nS;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (S[mid] < vj) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo == 0) return 0;
+  if (lo == nS) return nS - 1;
+  const double d0 = fabs(S[lo - 1] - vj);
+  const double d1 = fabs(S[lo] - vj);
+  return (d1 < d0) ? lo : lo - 1;
+}
+
+// Snapped bin centre i of the shift list (Sec. 4.1):
+// snap(v_min + (i + 1/2) width) with snap(x) = (4 floor(x / (4 pi^2)) + 2) pi^2,
+// the value of the form (4m+2) pi^2 nearest to x. Contraction is off, so every
+// step is one IEEE rounding.
+__device__ __forceinline__ double snapped_centre(double vmin, double width, int i) {
+#pragma clang fp contract(off)
+  const double centre = vmin + ((double)i + 0.5) * width;
+  return (4.0 * floor(centre / kFourPi2) + 2.0) * kPi2;
+}
+
+// Shift list S from the per-block (min, max) partials of v, computed by every
+// thread of a block (nthreads = blockDim.x, a multiple of 64, <= 1024).
+// The bin centres increase with i and snap is monotone, so duplicates are
+// adjacent; they are dropped by a ballot-based stream compaction.
+// Results in LDS: sS[0..*sNS), sRange[0] = v_min, sRange[1] = v_max.
+__device__ inline void shift_list_block(const double* __restrict__ part, int nparts, int nreq,
+                                        double* sS, int* sNS, double* sRange, int* sWave,
+                                        double* sRed) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int b = tid; b < nparts; b += blockDim.x) {
+    lo = fmin(lo, part[2 * b]);
+    hi = fmax(hi, part[2 * b + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+  }
+  if (lane == 0) {
+    sRed[2 * wid] = lo;
+    sRed[2 * wid + 1] = hi;
+  }
+  __syncthreads();
+  double vmin = sRed[0], vmax = sRed[1];
+  for (int w = 1; w < nw; ++w) {
+    vmin = fmin(vmin, sRed[2 * w]);
+    vmax = fmax(vmax, sRed[2 * w + 1]);
+  }
+  const double width = (vmax - vmin) / (double)nreq;
+  int base = 0;
+  for (int c0 = 0; c0 < nreq; c0 += blockDim.x) {
+    const int k = c0 + tid;
+    double s = 0.0;
+    bool keep = false;
+    if (k < nreq) {
+      s = snapped_centre(vmin, width, k);
+      keep = (k == 0) || (s != snapped_centre(vmin, width, k - 1));
+    }
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) sWave[wid] = __popcll(bal);
+    __syncthreads();
+    int off = base, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wid) off += sWave[w];
+      total += sWave[w];
+    }
+    if (keep) sS[off + before] = s;
+    base += total;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *sNS = base;
+    sRange[0] = vmin;
+    sRange[1] = vmax;
+  }
+  __syncthreads();
+}
+
+}  // namespace lsp

@@ -1,0 +1,274 @@
+"""Thin ctypes binding of liblsp (the C ABI in include/lsp.h).
+
+Argument marshalling only: tensors are checked for device, dtype, size and
+contiguity and their device pointers handed to the library, which runs every
+step on the GPU. There is no fallback: if liblsp.so is missing or cannot be
+loaded, every call raises.
+
+Names follow the C ABI: Problem.stencil_setup -> lsp_stencil_setup, etc.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Callable, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsp.so")
+
+LSP_OK = 0
+LSP_NOT_CONVERGED = 1
+LSP_EINVAL = -1
+LSP_ENONFINITE = -2
+LSP_ERESONANT = -3
+LSP_ENOMEM = -4
+LSP_EHIP = -5
+LSP_ESOLVER = -6
+LSP_ESTATE = -7
+LSP_FP64 = 0
+STAGES = ("shifts", "green", "null", "assemble", "setup", "apply", "c_apply")
+
+HOST_SOLVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.c_int64)
+
+_lib = None
+
+
+class LSPError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        lib_ = load()
+        msg = lib_.lsp_last_error().decode()
+        name = lib_.lsp_strerror(code).decode()
+        super().__init__(f"{where}: {name} ({code}): {msg}")
+
+
+def load():
+    """Load liblsp.so (built in-tree by paper_1607_02560_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                           "`python -m paper_1607_02560_amd.build`")
+    lib_ = ctypes.CDLL(LIB_PATH)
+    c_int, c_double, c_void_p, c_int64 = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64
+    P = ctypes.POINTER
+    sig = {
+        "lsp_strerror": (ctypes.c_char_p, [c_int]),
+        "lsp_last_error": (ctypes.c_char_p, []),
+        "lsp_version": (ctypes.c_char_p, []),
+        "lsp_create": (c_int, [c_int, c_int, c_void_p, c_void_p, P(c_void_p)]),
+        "lsp_set_potential": (c_int, [c_void_p, c_void_p]),
+        "lsp_destroy": (None, [c_void_p]),
+        "lsp_stencil_setup": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+        "lsp_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "lsp_c_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "lsp_precond_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
+                                      HOST_SOLVE_FN, c_void_p, P(c_int), P(c_double)]),
+        "lsp_get_tables": (c_int, [c_void_p, c_int, P(c_int), c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p]),
+        "lsp_default_num_shifts": (c_int, [c_int, c_int]),
+        "lsp_stencil_size": (c_int, [c_void_p]),
+        "lsp_export_pattern": (c_int, [c_int, c_int, c_int, c_void_p]),
+        "lsp_profile": (c_int, [c_void_p, c_int]),
+        "lsp_profile_read": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib_, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib_
+    return _lib
+
+
+def _check(code: int, where: str) -> int:
+    if code < 0:
+        raise LSPError(code, where)
+    return code
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _need(t, dtype, numel: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def default_num_shifts(d: int, n: int) -> int:
+    return _check(load().lsp_default_num_shifts(d, n), "lsp_default_num_shifts")
+
+
+def export_pattern(d: int, n: int, t: int) -> np.ndarray:
+    """Column index of every P / C entry: (N, m) int64."""
+    m = (2 * t + 1) ** d
+    out = np.empty((n ** d, m), dtype=np.int64)
+    _check(load().lsp_export_pattern(d, n, t, out.ctypes.data), "lsp_export_pattern")
+    return out
+
+
+class Problem:
+    """A problem (L + diag v) u = f on the periodic grid, resident on one GPU."""
+
+    def __init__(self, d: int, n: int, v, stream=None):
+        import torch
+        self.lib = load()
+        self.d, self.n = d, n
+        self.N = n ** d
+        _need(v, torch.float64, self.N, "v")
+        self.device = v.device
+        if stream is None:
+            stream = torch.cuda.current_stream(v.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(self.lib.lsp_create(d, n, _ptr(v), ctypes.c_void_p(stream.cuda_stream),
+                                   ctypes.byref(h)), "lsp_create")
+        self._h = h
+        self.t = None
+        self.m = None
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lsp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- entry points -----------------------------------------------------
+    def set_potential(self, v):
+        import torch
+        _need(v, torch.float64, self.N, "v")
+        _check(self.lib.lsp_set_potential(self._h, _ptr(v)), "lsp_set_potential")
+
+    def stencil_setup(self, t: int, num_shifts: int, P, idx=None, precision: int = LSP_FP64):
+        import torch
+        m = (2 * t + 1) ** self.d
+        _need(P, torch.float64, self.N * m, "P")
+        if idx is not None:
+            _need(idx, torch.int32, self.N, "idx")
+        _check(self.lib.lsp_stencil_setup(self._h, t, num_shifts, precision, _ptr(P),
+                                          _ptr(idx) if idx is not None else None),
+               "lsp_stencil_setup")
+        self.t, self.m = t, m
+
+    def ps_apply(self, u, y):
+        import torch
+        _need(u, torch.complex128, self.N, "u")
+        _need(y, torch.complex128, self.N, "y")
+        _check(self.lib.lsp_ps_apply(self._h, _ptr(u), _ptr(y)), "lsp_ps_apply")
+
+    def c_apply(self, r, z):
+        import torch
+        _need(r, torch.complex128, self.N, "r")
+        _need(z, torch.complex128, self.N, "z")
+        _check(self.lib.lsp_c_apply(self._h, _ptr(r), _ptr(z)), "lsp_c_apply")
+
+    def precond_solve(self, f, u, solve_P: Callable[[np.ndarray], np.ndarray], rtol=1e-8,
+                      restart=40, maxit=400):
+        """GMRES(restart) with preconditioner P^-1 C. solve_P maps a complex128
+        host vector (N,) to P^-1 of it. Returns (status, iterations, relres)."""
+        import torch
+        _need(f, torch.complex128, self.N, "f")
+        _need(u, torch.complex128, self.N, "u")
+        errors = []
+
+        def cb(user, rhs_p, x_p, N):
+            try:
+                rhs = np.ctypeslib.as_array(rhs_p, shape=(2 * N,)).view(np.complex128)
+                x = np.ctypeslib.as_array(x_p, shape=(2 * N,)).view(np.complex128)
+                x[:] = solve_P(rhs.copy())
+                return 0
+            except Exception as exc:  # reported through LSP_ESOLVER
+                errors.append(exc)
+                return 1
+
+        cfn = HOST_SOLVE_FN(cb)
+        iters = ctypes.c_int(0)
+        relres = ctypes.c_double(0.0)
+        code = self.lib.lsp_precond_solve(self._h, _ptr(f), _ptr(u), rtol, restart, maxit, cfn,
+                                          None, ctypes.byref(iters), ctypes.byref(relres))
+        if code == LSP_ESOLVER and errors:
+            raise LSPError(code, "lsp_precond_solve") from errors[0]
+        _check(code, "lsp_precond_solve")
+        return code, iters.value, relres.value
+
+    def profile(self, enable: bool):
+        """Start (clearing the totals) or stop per-stage HIP-event timing."""
+        _check(self.lib.lsp_profile(self._h, 1 if enable else 0), "lsp_profile")
+
+    def profile_read(self) -> dict:
+        """{stage: (total ms, calls)} since profiling started; synchronises."""
+        ms = np.zeros(len(STAGES))
+        cnt = np.zeros(len(STAGES), dtype=np.int32)
+        _check(self.lib.lsp_profile_read(self._h, len(STAGES), ms.ctypes.data, cnt.ctypes.data),
+               "lsp_profile_read")
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+    def get_tables(self, capacity: int = 1024) -> dict:
+        """Host copies of the per-shift tables of the last setup."""
+        if self.m is None:
+            raise RuntimeError("no setup has been run")
+        m = self.m
+        wd = (2 * self.t + 1) ** self.d
+        S = np.zeros(capacity)
+        alpha = np.zeros(capacity * m)
+        C = np.zeros(capacity * m)
+        sigma = np.zeros(capacity)
+        g = np.zeros(capacity * wd)
+        gam = np.zeros(capacity * wd)
+        M = np.zeros(capacity * m * m)
+        nS = ctypes.c_int(0)
+        _check(self.lib.lsp_get_tables(self._h, capacity, ctypes.byref(nS), S.ctypes.data,
+                                       alpha.ctypes.data, C.ctypes.data, sigma.ctypes.data,
+                                       g.ctypes.data, gam.ctypes.data, M.ctypes.data),
+               "lsp_get_tables")
+        k = nS.value
+        W = 2 * self.t + 1
+        return {
+            "S": S[:k].copy(),
+            "alpha": alpha[:k * m].reshape(k, m).copy(),
+            "C": C[:k * m].reshape(k, m).copy(),
+            "sigma_min": sigma[:k].copy(),
+            "g": g[:k * wd].reshape((k,) + (W,) * self.d).copy(),
+            "gamma": gam[:k * wd].reshape((k,) + (W,) * self.d).copy(),
+            "M": M[:k * m * m].reshape(k, m, m).copy(),
+        }
+
+
+def host_lu_solver(P_rows: np.ndarray, d: int, n: int, t: int):
+    """Plain host-side sparse LU of P (the factorisation step stays on the host,
+    outside the hot path). P_rows: (N, m) float64 rows from stencil_setup.
+    Returns solve(rhs complex128 (N,)) -> complex128 (N,)."""
+    import scipy.sparse
+    import scipy.sparse.linalg
+    N = n ** d
+    m = (2 * t + 1) ** d
+    cols = export_pattern(d, n, t)
+    indptr = np.arange(0, N * m + 1, m)
+    Pm = scipy.sparse.csr_matrix((P_rows.reshape(-1), cols.reshape(-1), indptr), shape=(N, N))
+    lu = scipy.sparse.linalg.splu(Pm.tocsc().astype(np.complex128))
+    return lu.solve

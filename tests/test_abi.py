@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/lsp.h declares, and its pure host logic (validation,
+default shift count, the CSR column pattern) is right."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import lsp_oracle as O
+from paper_1607_02560_amd import lsp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(lsp_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return lsp.load()
+
+
+def test_header_parses():
+    names = declared_functions()
+    for must in ("lsp_create", "lsp_stencil_setup", "lsp_ps_apply", "lsp_precond_solve",
+                 "lsp_c_apply", "lsp_destroy"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    assert lib.lsp_strerror(0) == b"ok"
+    assert lib.lsp_strerror(-1) == b"invalid argument"
+    assert lib.lsp_strerror(12345) == b"unknown status"
+    assert lib.lsp_version().startswith(b"liblsp")
+
+
+def test_default_num_shifts_follow_tables():
+    with open(os.path.join(ROOT, "tests", "golden", "shift_counts.json")) as fh:
+        gold = json.load(fh)
+    for n, cnt in gold["2d"].items():
+        assert lsp.default_num_shifts(2, int(n)) == cnt
+    for n, cnt in gold["3d"].items():
+        assert lsp.default_num_shifts(3, int(n)) == cnt
+    assert lsp.default_num_shifts(2, 8) == 1
+    with pytest.raises(lsp.LSPError):
+        lsp.default_num_shifts(4, 8)
+
+
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 16, 2), (3, 8, 1), (2, 32, 3)])
+def test_export_pattern_matches_oracle(d, n, t):
+    cols = lsp.export_pattern(d, n, t)
+    ref = O.neighbour_columns(d, n, O.offsets(d, t))
+    assert np.array_equal(cols, ref)
+
+
+@pytest.mark.parametrize("d,n", [(4, 8), (1, 8), (2, 7), (2, 4), (2, 2048), (3, 512), (2, 0)])
+def test_create_rejects_bad_sizes(lib, d, n):
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    code = lib.lsp_create(d, n, dummy, None, ctypes.byref(h))
+    assert code == lsp.LSP_EINVAL
+    assert not h.value
+    assert lib.lsp_last_error() != b""
+
+
+def test_create_rejects_null_pointers(lib):
+    h = ctypes.c_void_p()
+    assert lib.lsp_create(2, 8, None, None, ctypes.byref(h)) == lsp.LSP_EINVAL
+    assert lib.lsp_create(2, 8, ctypes.c_void_p(16), None, None) == lsp.LSP_EINVAL
+
+
+def test_calls_reject_null_problem(lib):
+    assert lib.lsp_stencil_setup(None, 1, 0, 0, ctypes.c_void_p(16), None) == lsp.LSP_EINVAL
+    assert lib.lsp_ps_apply(None, ctypes.c_void_p(16), ctypes.c_void_p(32)) == lsp.LSP_EINVAL
+    assert lib.lsp_c_apply(None, ctypes.c_void_p(16), ctypes.c_void_p(32)) == lsp.LSP_EINVAL
+    lib.lsp_destroy(None)
+
+
+def test_export_pattern_rejects(lib):
+    buf = np.zeros(10, dtype=np.int64)
+    assert lib.lsp_export_pattern(2, 4, 2, buf.ctypes.data) == lsp.LSP_EINVAL
+    assert lib.lsp_export_pattern(2, 8, 1, None) == lsp.LSP_EINVAL
