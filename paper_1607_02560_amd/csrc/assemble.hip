@@ -13,44 +13,31 @@ using lsp::Pow;
 
 // --------------------------------------------------------------------------
 // Per-point assignment and P rows.
-// A block owns a tile of TR x TW points (TR rows of axis d-2, TW columns of
-// axis d-1, one plane of axis 0 in 3D), one point per thread.
+// A block owns TR x TW points (TR rows of axis d-2, TW columns of axis d-1,
+// one plane of axis 0 in 3D); small tiles keep many blocks in flight, which
+// is what this store-bound kernel needs.
 //   1. The potential on the tile plus a halo of t in every direction and the
 //      shift list are staged in LDS.
-//   2. Each thread picks idx_j = argmin_i |S_i - v_j| (S is sorted: the two
-//      neighbours of the insertion point are compared, ties to the lower
-//      index); the block's range of shift indices is reduced.
-//   3. The (alpha, C) rows of that range are staged in LDS (or read from
-//      global memory when the range is too wide).
-//   4. Each thread evaluates its whole row with compile-time offsets,
-//        P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j),
-//      one rounding per operation, into an LDS staging buffer.
-//   5. The tile's rows are TR contiguous spans of TW*m doubles in P; they are
-//      copied out with coalesced 16-byte stores.
+//   2. Each point gets idx_j = argmin_i |S_i - v_j| (S is sorted: the two
+//      neighbours of the insertion point are compared, ties to the lower index).
+//   3. The tile's P rows are TR contiguous spans of TW*m doubles; thread k
+//      writes doubles 2k, 2k+1 of the flattened spans with one 16-byte store,
+//      evaluating P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j) for
+//      each with one rounding per operation.
 // --------------------------------------------------------------------------
 template <int D, int W, int TR, int TW>
 __global__ __launch_bounds__(256) void assemble_kernel(
     const double* __restrict__ v, int n, const double* __restrict__ S,
     const int* __restrict__ nS_ptr, const double2* __restrict__ actab, double* __restrict__ P,
     int32_t* __restrict__ idx_out) {
-  using Nb = lsp::Nbhd<D, W>;
   constexpr int t = (W - 1) / 2;
   constexpr int M = Pow<D, W>::v;
   constexpr int PL = (D == 3) ? W : 1;  // halo planes
   constexpr int HR = TR + 2 * t;
   constexpr int HC = TW + 2 * t;
-  constexpr int NPT = TR * TW;
-  constexpr int TABCAP = 512;
-  constexpr int OUTD = NPT * M;         // doubles staged for output (even: TW even)
-  constexpr int BUFD = (OUTD > lsp::kMaxShifts) ? OUTD : lsp::kMaxShifts;
-  static_assert(NPT <= 256, "one point per thread");
   __shared__ double halo[PL * HR * HC];
-  __shared__ double2 stab[TABCAP];
-  __shared__ double2 outb2[BUFD / 2];   // also holds the shift list in steps 1-2
-  __shared__ int sred[8];
-  double* outb = reinterpret_cast<double*>(outb2);
-  double* sS = outb;
-
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sidx[TR * TW];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
   const int c0 = blockIdx.x * TW;
@@ -76,71 +63,47 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   }
   __syncthreads();
 
-  // ---- 2. shift assignment ----
-  const bool active = tid < NPT;
-  const int r = tid / TW, c = tid % TW;
-  const int hbase = ((PL / 2) * HR + r + t) * HC + c + t;
-  int id = 0;
-  double sj = 0.0;
-  if (active) {
-    id = nearest_shift(sS, nS, halo[hbase]);
-    sj = sS[id];
+  for (int pt = tid; pt < TR * TW; pt += 256) {
+    const int r = pt / TW, c = pt % TW;
+    const int best = nearest_shift(sS, nS, halo[((PL / 2) * HR + r + t) * HC + c + t]);
+    sidx[pt] = best;
     if (idx_out) {
       const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
                                  : ((int64_t)(r0 + r) * n + c0 + c);
-      idx_out[g] = id;
+      idx_out[g] = best;
     }
   }
-  int lo = active ? id : 0x7fffffff, hi = active ? id : -1;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = min(lo, __shfl_xor(lo, o));
-    hi = max(hi, __shfl_xor(hi, o));
-  }
-  if ((tid & 63) == 0) {
-    sred[2 * (tid >> 6)] = lo;
-    sred[2 * (tid >> 6) + 1] = hi;
-  }
-  __syncthreads();
-  int imin = sred[0], imax = sred[1];
-  for (int w = 1; w < 4; ++w) {
-    imin = min(imin, sred[2 * w]);
-    imax = max(imax, sred[2 * w + 1]);
-  }
-
-  // ---- 3. (alpha, C) rows of the block's shifts ----
-  const bool staged = (imax - imin + 1) * M <= TABCAP;
-  if (staged) {
-    for (int e = tid; e < (imax - imin + 1) * M; e += 256) stab[e] = actab[imin * M + e];
-  }
   __syncthreads();
 
-  // ---- 4. the row of this point ----
-  if (active) {
-    const double2* tab = staged ? (stab + (id - imin) * M) : (actab + (int64_t)id * M);
-    double* orow = outb + tid * M;
+  constexpr int SPAN = TW * M;  // even: TW is even
+  constexpr int TOTAL = TR * SPAN;
+  for (int pos = 2 * tid; pos < TOTAL; pos += 512) {
+    const int r = pos / SPAN;
+    const int e = pos - r * SPAN;
+    double outv[2];
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      int off;
+    for (int h = 0; h < 2; ++h) {
+      const int eh = e + h;
+      const int p = eh / M;
+      const int a = eh - p * M;
+      const int id = sidx[r * TW + p];
+      const double s = sS[id];
+      const double2 ac = actab[id * M + a];
+      int hp = 0, hr, hc;
       if constexpr (D == 3) {
-        off = Nb::comp(a, 0) * HR * HC + Nb::comp(a, 1) * HC + Nb::comp(a, 2);
+        hp = a / (W * W);
+        hr = r + (a / W) % W;
+        hc = p + a % W;
       } else {
-        off = Nb::comp(a, 0) * HC + Nb::comp(a, 1);
+        hr = r + a / W;
+        hc = p + a % W;
       }
-      const double2 ac = tab[a];
-      orow[a] = ac.x + ac.y * (halo[hbase + off] - sj);
+      const double va = halo[(hp * HR + hr) * HC + hc];
+      outv[h] = ac.x + ac.y * (va - s);
     }
-  }
-  __syncthreads();
-
-  // ---- 5. coalesced copy-out ----
-  constexpr int SPAN2 = TW * M / 2;  // double2 per tile row
-  for (int ch = tid; ch < TR * SPAN2; ch += 256) {
-    const int rr = ch / SPAN2;
-    const int e = ch - rr * SPAN2;
-    const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0 + rr) * n + c0) * M)
-                                     : (((int64_t)(r0 + rr) * n + c0) * M);
-    reinterpret_cast<double2*>(P + rowbase)[e] = outb2[ch];
+    const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0 + r) * n + c0) * M)
+                                     : (((int64_t)(r0 + r) * n + c0) * M);
+    reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(outv[0], outv[1]);
   }
 }
 
@@ -242,22 +205,20 @@ hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
   return hipGetLastError();
 }
 
-// assembly tiles: 256 points (fewer on the smallest grids), as wide as the
-// last axis allows (256 in 2D, 64 in 3D)
+// assembly tiles: one row of up to 128 points (2D) or 64 points (3D)
 template <int D, int W>
 hipError_t run_assemble(lsp_problem* p, double* P, int32_t* idx) {
   switch (p->n) {
-    case 8: return run_assemble_tile<D, W, 8, 8>(p, P, idx);
-    case 16: return run_assemble_tile<D, W, 16, 16>(p, P, idx);
-    case 32: return run_assemble_tile<D, W, 32, 8>(p, P, idx);
+    case 8: return run_assemble_tile<D, W, 8, 1>(p, P, idx);
+    case 16: return run_assemble_tile<D, W, 16, 1>(p, P, idx);
+    case 32: return run_assemble_tile<D, W, 32, 1>(p, P, idx);
     default: break;
   }
   if constexpr (D == 2) {
-    if (p->n == 64) return run_assemble_tile<D, W, 64, 4>(p, P, idx);
-    if (p->n == 128) return run_assemble_tile<D, W, 128, 2>(p, P, idx);
-    return run_assemble_tile<D, W, 256, 1>(p, P, idx);
+    if (p->n == 64) return run_assemble_tile<D, W, 64, 1>(p, P, idx);
+    return run_assemble_tile<D, W, 128, 1>(p, P, idx);
   } else {
-    return run_assemble_tile<D, W, 64, 4>(p, P, idx);
+    return run_assemble_tile<D, W, 64, 1>(p, P, idx);
   }
 }
 

@@ -15,10 +15,11 @@
 //     symmetrised: g[.., da, db] = sum_kk cw[kk][da] T[db] + cw[kk][db] T[da],
 //     with T[dl] = sum_{k_d} cw[k_d][dl] r the inner sum of the thread's row;
 //     only the pairs da <= db are accumulated.
-// A block owns OT consecutive outer indices o = (k_1..k_{d-1}) (one per
-// thread) and one segment of SEG values of k_d, whose cw rows are staged in
-// LDS and read as wave-wide broadcasts. Blocks write their partial sums,
-// unscaled: [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
+// A wave owns 64 consecutive outer indices o = (k_1..k_{d-1}) (one per lane)
+// and 64 consecutive values of k_d, whose cw rows are staged in LDS and read
+// as wave-wide broadcasts; work units are uniform, so the load is balanced.
+// Units write their partial sums, unscaled:
+// [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
 #include "setup_common.h"
 
 #pragma clang fp contract(off)
@@ -41,31 +42,35 @@ __device__ __forceinline__ double green_r(int K2, double s) {
   return lsp::rcp_nr(lam + s);
 }
 
-template <int D, int W, int OT, int SEG>
-__global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict__ mm_part,
-                                                        int mm_blocks, int nreq, double* S_out,
-                                                        int* nS_out, double* vrange_out,
-                                                        const double* __restrict__ cw, int n,
-                                                        int otiles, double* __restrict__ part) {
+constexpr int kTile = 64;  // outer indices per wave = values of k_d per wave
+
+// One wave per work unit (shift, 64 consecutive outer indices, 64 consecutive
+// values of k_d). Units below the diagonal (every k_d < k_{d-1}) write zeros.
+template <int D, int W>
+__global__ __launch_bounds__(kTile) void green_sums_kernel(const double* __restrict__ mm_part,
+                                                           int mm_blocks, int nreq,
+                                                           double* S_out, int* nS_out,
+                                                           double* vrange_out,
+                                                           const double* __restrict__ cw, int n,
+                                                           int ktiles, double* __restrict__ part) {
   using Lay = GreenLayout<D, W>;
   constexpr int NP = Lay::NP;
   constexpr int WO2 = Lay::WO2;
   constexpr int NV = Lay::NV;
-  constexpr int SPL = 4;   // partial sums per value in the block reduction
-  constexpr int RCH = 10;  // values reduced per round (bounds the LDS footprint)
-  __shared__ double cws[SEG * W];
-  __shared__ double red[RCH * (OT + 1)];
-  __shared__ double red2[NV * SPL];
-  __shared__ double sS[lsp::kMaxShifts];
-  __shared__ int sNS, sWave[OT / 64];
-  __shared__ double sRange[2], sRed[2 * (OT / 64)];
+  constexpr int RCH = 15;  // values reduced per round
+  constexpr int SCR = (RCH * (kTile + 1) > lsp::kMaxShifts) ? RCH * (kTile + 1) : lsp::kMaxShifts;
+  __shared__ double cws[kTile * W];
+  __shared__ double scratch[SCR];  // shift list first, then the reduction buffer
+  __shared__ int sNS, sWave[1];
+  __shared__ double sRange[2], sRed[2];
 
   // shift list (Sec. 4.1) from the min/max partials; one block publishes it
-  lsp::shift_list_block(mm_part, mm_blocks, nreq, sS, &sNS, sRange, sWave, sRed);
+  lsp::shift_list_block(mm_part, mm_blocks, nreq, scratch, &sNS, sRange, sWave, sRed);
   const int nS = sNS;
+  const int lane = threadIdx.x;
   if (blockIdx.x == 0 && blockIdx.y == 0) {
-    for (int i = threadIdx.x; i < nS; i += OT) S_out[i] = sS[i];
-    if (threadIdx.x == 0) {
+    for (int i = lane; i < nS; i += kTile) S_out[i] = scratch[i];
+    if (lane == 0) {
       *nS_out = nS;
       vrange_out[0] = sRange[0];
       vrange_out[1] = sRange[1];
@@ -73,15 +78,15 @@ __global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict
   }
   const int si = blockIdx.y;
   if (si >= nS) return;
-  const double s = sS[si];
+  const double s = scratch[si];
+
   const int H = n / 2 + 1;
-  const int ot = blockIdx.x % otiles;
-  const int q = blockIdx.x / otiles;
-  const int tid = threadIdx.x;
+  const int ot = blockIdx.x / ktiles;
+  const int q = blockIdx.x % ktiles;
   int O = 1;
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) O *= H;
-  const int o = ot * OT + tid;
+  const int o = ot * kTile + lane;
   const bool valid = o < O;
   int ko[D - 1];
   {
@@ -96,21 +101,18 @@ __global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) K2o += ko[i] * ko[i];
   const int kk = ko[D - 2];
-
-  const int k_begin = q * SEG;
-  const int k_end = min(H, k_begin + SEG);
-  for (int e = tid; e < (k_end - k_begin) * W; e += OT) cws[e] = cw[k_begin * W + e];
-  const int any_work = __syncthreads_or(valid && kk < k_end);
+  const int k_begin = q * kTile;
+  const int k_end = min(H, k_begin + kTile);
 
   double tg[W], tq[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
-
-  if (any_work) {
-    // A wave whose rows all lie above the diagonal of the segment takes every
-    // term with weight 1; otherwise terms get weight 1 above, 1/2 on and 0
-    // below the diagonal (0 for padding lanes). The branch is wave-uniform.
+  __syncthreads();  // every read of the shift list is done before scratch is reused
+  if (__any(valid && kk < k_end)) {
+    for (int e = lane; e < (k_end - k_begin) * W; e += kTile) cws[e] = cw[k_begin * W + e];
+    __syncthreads();
     if (__all(valid && kk < k_begin)) {
+      // every term of the tile lies above the diagonal: weight 1
       int kd = k_begin;
       for (; kd + 4 <= k_end; kd += 4) {
         double r[4], r2[4];
@@ -140,6 +142,7 @@ __global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict
         }
       }
     } else {
+      // weight 1 above, 1/2 on and 0 below the diagonal; 0 for padding lanes
       for (int kd = k_begin; kd < k_end; ++kd) {
         const double r0 = green_r(K2o + kd * kd, s);
         const double wgt = valid ? ((kd > kk) ? 1.0 : ((kd == kk) ? 0.5 : 0.0)) : 0.0;
@@ -181,73 +184,52 @@ __global__ __launch_bounds__(OT) void green_sums_kernel(const double* __restrict
     }
   }
 
-  // block reduction in a fixed order, RCH values per round
-  constexpr int CH = OT / SPL;
+  // wave reduction through LDS in a fixed order, RCH values per round
+  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
 #pragma unroll
   for (int v0 = 0; v0 < NV; v0 += RCH) {
     __syncthreads();
 #pragma unroll
     for (int vv = 0; vv < RCH; ++vv)
-      if (v0 + vv < NV) red[vv * (OT + 1) + tid] = acc[v0 + vv];
+      if (v0 + vv < NV) scratch[vv * (kTile + 1) + lane] = acc[v0 + vv];
     __syncthreads();
-    for (int e = tid; e < RCH * SPL; e += OT) {
-      const int vv = e / SPL, sp = e % SPL;
-      if (v0 + vv < NV) {
-        const double* rr = red + vv * (OT + 1) + sp * CH;
-        double sum = 0.0;
-        for (int l = 0; l < CH; ++l) sum += rr[l];
-        red2[(v0 + vv) * SPL + sp] = sum;
+    if (lane < RCH && v0 + lane < NV) {
+      const double* rr = scratch + lane * (kTile + 1);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int l = 0; l < kTile; l += 4) {
+        s0 += rr[l];
+        s1 += rr[l + 1];
+        s2 += rr[l + 2];
+        s3 += rr[l + 3];
       }
+      out[v0 + lane] = (s0 + s1) + (s2 + s3);
     }
-  }
-  __syncthreads();
-  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
-  for (int vv = tid; vv < NV; vv += OT) {
-    double sum = 0.0;
-#pragma unroll
-    for (int sp = 0; sp < SPL; ++sp) sum += red2[vv * SPL + sp];
-    out[vv] = sum;
   }
 }
 
-template <int D>
-struct GreenTiles;
-template <>
-struct GreenTiles<2> {
-  static constexpr int OT = 128, SEG = 128;
-};
-template <>
-struct GreenTiles<3> {
-  static constexpr int OT = 128, SEG = 64;
-};
-
 template <int D, int W>
 hipError_t run_green(lsp_problem* p, int num_shifts, int* blocks_out) {
-  constexpr int OT = GreenTiles<D>::OT;
-  constexpr int SEG = GreenTiles<D>::SEG;
   const int H = p->n / 2 + 1;
   int64_t O = 1;
   for (int i = 0; i < D - 1; ++i) O *= H;
-  const int otiles = (int)((O + OT - 1) / OT);
-  const int nseg = (H + SEG - 1) / SEG;
-  const int blocks = otiles * nseg;
+  const int otiles = (int)((O + kTile - 1) / kTile);
+  const int ktiles = (H + kTile - 1) / kTile;
+  const int blocks = otiles * ktiles;
   const size_t need = (size_t)num_shifts * blocks * GreenLayout<D, W>::NV;
   if (need > p->ws.green_part_cap) return hipErrorOutOfMemory;
   *blocks_out = blocks;
-  hipLaunchKernelGGL((green_sums_kernel<D, W, OT, SEG>), dim3(blocks, num_shifts), dim3(OT), 0,
+  hipLaunchKernelGGL((green_sums_kernel<D, W>), dim3(blocks, num_shifts), dim3(kTile), 0,
                      p->stream, p->ws.minmax_part, lsp::minmax_blocks(p->N), num_shifts, p->ws.S,
-                     p->ws.nS, p->ws.vrange, p->cosT, p->n, otiles, p->ws.green_part);
+                     p->ws.nS, p->ws.vrange, p->cosT, p->n, ktiles, p->ws.green_part);
   return hipGetLastError();
 }
 
 template <int D, int W>
 size_t green_need(int n, int shifts) {
-  constexpr int OT = GreenTiles<D>::OT;
-  constexpr int SEG = GreenTiles<D>::SEG;
   const int H = n / 2 + 1;
   int64_t O = 1;
   for (int i = 0; i < D - 1; ++i) O *= H;
-  const int64_t blocks = ((O + OT - 1) / OT) * ((H + SEG - 1) / SEG);
+  const int64_t blocks = ((O + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
   return (size_t)shifts * blocks * GreenLayout<D, W>::NV;
 }
 

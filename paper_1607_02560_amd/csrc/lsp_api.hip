@@ -2,6 +2,7 @@
 // workspaces, the stencil-setup launch sequence and the GMRES driver.
 // Every entry point declared in include/lsp.h is defined here.
 #include <math.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -78,6 +79,7 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
   }
   const size_t gneed = lsp::green_partial_doubles(p->d, p->n, t, shifts);
   if (gneed > w.green_part_cap) {
+    ++p->ws_gen;
     (void)hipStreamSynchronize(p->stream);
     dfree(w.green_part);
     if ((rc = dalloc((void**)&w.green_part, sizeof(double) * gneed, "green partial sums")))
@@ -85,6 +87,7 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
     w.green_part_cap = gneed;
   }
   if (shifts > w.cap_shifts || m > w.cap_m || wd > w.cap_w) {
+    ++p->ws_gen;
     (void)hipStreamSynchronize(p->stream);
     dfree(w.gtab);
     dfree(w.gamtab);
@@ -125,6 +128,7 @@ int upload_cos_table(lsp_problem* p, int W) {
     }
   }
   dfree(p->cosT);
+  ++p->ws_gen;
   int rc = dalloc((void**)&p->cosT, sizeof(double) * cw.size(), "cos table");
   if (rc) return rc;
   if (hipMemcpy(p->cosT, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice) !=
@@ -144,6 +148,49 @@ int check_finite_device(lsp_problem* p, const double* x, int64_t count, const ch
     return lsp::set_error(LSP_ENONFINITE,
                           std::string(what) + " has " + std::to_string(bad) + " non-finite values");
   return LSP_OK;
+}
+
+void drop_graph(lsp_problem::GraphCache& gc) {
+  if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+  gc.exec = nullptr;
+  gc.valid = false;
+}
+
+// Run a launch sequence through a cached HIP graph: replay it when the key
+// (arguments and workspace generation) matches the captured one, otherwise
+// capture it anew. Without graphs (profiling, the legacy default stream, or
+// LSP_NO_GRAPH set) the sequence is launched directly.
+hipError_t run_graph(lsp_problem* p, lsp_problem::GraphCache& gc, const uint64_t (&key)[6],
+                     const std::function<hipError_t()>& launch) {
+  if (!p->use_graphs || p->profiling || p->stream == nullptr) return launch();
+  bool same = gc.valid;
+  for (int i = 0; i < 6 && same; ++i) same = (gc.key[i] == key[i]);
+  if (!same) {
+    drop_graph(gc);
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p->use_graphs = false;
+      return launch();
+    }
+    const hipError_t le = launch();
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->stream, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      gc.exec = nullptr;
+      return e;
+    }
+    for (int i = 0; i < 6; ++i) gc.key[i] = key[i];
+    gc.valid = true;
+  }
+  return hipGraphLaunch(gc.exec, p->stream);
 }
 
 }  // namespace
@@ -240,6 +287,10 @@ int lsp_create(int d, int n, const double* v_dev, void* stream, lsp_problem** ou
   p->N = 1;
   for (int i = 0; i < d; ++i) p->N *= n;
   p->stream = reinterpret_cast<hipStream_t>(stream);
+  {
+    const char* ng = getenv("LSP_NO_GRAPH");
+    p->use_graphs = !(ng && ng[0] && ng[0] != '0');
+  }
   (void)hipGetDevice(&p->device);
   int rc = LSP_OK;
   if ((rc = dalloc((void**)&p->v, sizeof(double) * p->N, "potential")) ||
@@ -292,6 +343,8 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->tw);
   dfree(p->cosT);
   dfree(p->flag);
+  drop_graph(p->g_setup);
+  drop_graph(p->g_apply);
   for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
   p->ev_pool.clear();
   dfree(p->kry);
@@ -364,25 +417,32 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, doub
   p->m = m;
   p->num_shifts = num_shifts;
   p->have_setup = false;
-  const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
-  int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-  hipError_t e = lsp::launch_shift_list(p, num_shifts);
-  if (e != hipSuccess) return lsp::hip_check(e, "shift list launch");
-  lsp::stage_end(p, tk);
-  int chunks = 0;
-  tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
-  e = lsp::launch_green_sums(p, num_shifts, &chunks);
-  if (e != hipSuccess) return lsp::hip_check(e, "Green's sums launch");
-  lsp::stage_end(p, tk);
-  tk = lsp::stage_begin(p, LSP_STAGE_NULL);
-  e = lsp::launch_null_vectors(p, num_shifts, chunks);
-  if (e != hipSuccess) return lsp::hip_check(e, "null vector launch");
-  lsp::stage_end(p, tk);
-  tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
-  e = lsp::launch_assemble(p, P_dev, idx_dev);
-  if (e != hipSuccess) return lsp::hip_check(e, "assembly launch");
-  lsp::stage_end(p, tk);
-  lsp::stage_end(p, tk_all);
+  auto launch = [&]() -> hipError_t {
+    const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
+    int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
+    hipError_t e = lsp::launch_shift_list(p, num_shifts);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    int blocks = 0;
+    tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
+    e = lsp::launch_green_sums(p, num_shifts, &blocks);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    tk = lsp::stage_begin(p, LSP_STAGE_NULL);
+    e = lsp::launch_null_vectors(p, num_shifts, blocks);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
+    e = lsp::launch_assemble(p, P_dev, idx_dev);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    lsp::stage_end(p, tk_all);
+    return hipSuccess;
+  };
+  const uint64_t key[6] = {(uint64_t)t, (uint64_t)num_shifts, (uint64_t)(uintptr_t)P_dev,
+                           (uint64_t)(uintptr_t)idx_dev, p->ws_gen, 0};
+  const hipError_t e = run_graph(p, p->g_setup, key, launch);
+  if (e != hipSuccess) return lsp::hip_check(e, "stencil setup launch");
   p->have_setup = true;
   return LSP_OK;
 }
@@ -390,10 +450,15 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, doub
 int lsp_ps_apply(lsp_problem* p, const double* u_dev, double* y_dev) {
   if (!p || !u_dev || !y_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
   if (u_dev == y_dev) return lsp::set_error(LSP_EINVAL, "u and y must not alias");
-  const int tk = lsp::stage_begin(p, LSP_STAGE_APPLY);
-  const int rc = lsp::hip_check(lsp::launch_ps_apply(p, u_dev, y_dev), "ps_apply launch");
-  lsp::stage_end(p, tk);
-  return rc;
+  auto launch = [&]() -> hipError_t {
+    const int tk = lsp::stage_begin(p, LSP_STAGE_APPLY);
+    const hipError_t e = lsp::launch_ps_apply(p, u_dev, y_dev);
+    lsp::stage_end(p, tk);
+    return e;
+  };
+  const uint64_t key[6] = {(uint64_t)(uintptr_t)u_dev, (uint64_t)(uintptr_t)y_dev, p->ws_gen,
+                           0, 0, 0};
+  return lsp::hip_check(run_graph(p, p->g_apply, key, launch), "ps_apply launch");
 }
 
 int lsp_c_apply(lsp_problem* p, const double* r_dev, double* z_dev) {

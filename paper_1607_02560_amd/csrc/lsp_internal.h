@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -18,7 +19,7 @@ constexpr double kPi2 = 9.869604401089358;
 // Upper bounds of the build.
 constexpr int kMaxStencil = 64;     // m = (2t+1)^d
 constexpr int kMaxShifts = 1024;    // requested |S|
-constexpr int kMinMaxBlocks = 512;  // blocks of the min/max reduction
+constexpr int kMinMaxBlocks = 128;  // blocks of the min/max reduction
 
 struct Workspace {
   // shift list (Sec. 4.1)
@@ -62,6 +63,16 @@ struct lsp_problem {
   int num_shifts = 0;         // requested |S| of the last setup
   bool have_setup = false;
   lsp::Workspace ws;
+  // HIP graphs of the setup and apply launch sequences, replayed while the
+  // arguments and workspaces they captured are unchanged
+  struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    uint64_t key[6] = {0, 0, 0, 0, 0, 0};
+    bool valid = false;
+  };
+  GraphCache g_setup, g_apply;
+  uint64_t ws_gen = 1;        // bumped whenever a workspace pointer changes
+  bool use_graphs = true;
   // per-stage event timing (lsp_profile)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;                 // created events, reused

@@ -50,7 +50,7 @@ struct NullShared {
   double gv[NC][BMAX];
   int status[NC];
   double alpha[WD];
-  double stage[2048];
+  double stage[4096];
 };
 
 template <int D, int W, int C>
@@ -308,9 +308,11 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
   const double* ps = part + (int64_t)si * nblk * NV;
   double acc = 0.0;  // thread tid < NV owns value tid
   const int total = nblk * NV;
-  constexpr int CHUNK = 2048;
+  constexpr int CHUNK = 4096;
   for (int c0 = 0; c0 < total; c0 += CHUNK) {
     const int cn = min(CHUNK, total - c0);
+    // all loads of a thread are issued before any is consumed
+#pragma unroll 16
     for (int e = tid; e < cn; e += T) sh.stage[e] = ps[c0 + e];
     __syncthreads();
     if (tid < NV) {

@@ -342,3 +342,46 @@ def test_precond_solve_maxit(torch_dev):
     ut = torch.zeros_like(ft)
     code, iters, relres = prob.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=3)
     assert code == lsp.LSP_NOT_CONVERGED and iters == 3 and relres > 1e-8
+
+
+# ---------------------------------------------------------------- graphs ----
+def test_graph_replays_match_direct_launches(torch_dev, monkeypatch):
+    """The setup and apply sequences are captured in HIP graphs and replayed
+    while their arguments are unchanged. Several replays, with eager work and
+    synchronisation in between (new potentials), must give the same bits as a
+    problem that launches directly (LSP_NO_GRAPH=1)."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    n, t, nS = 128, 2, 8
+    m = (2 * t + 1) ** 2
+    r = np.random.default_rng(21)
+    monkeypatch.setenv("LSP_NO_GRAPH", "1")
+    v0 = torch.from_numpy(r.uniform(-9e4, -2e4, n * n)).to(dev)
+    direct = lsp.Problem(2, n, v0)
+    monkeypatch.delenv("LSP_NO_GRAPH")
+    graphed = lsp.Problem(2, n, v0)
+    Pg = torch.empty(n * n * m, dtype=torch.float64, device=dev)
+    Pd = torch.empty_like(Pg)
+    ig = torch.empty(n * n, dtype=torch.int32, device=dev)
+    idd = torch.empty_like(ig)
+    u = torch.from_numpy(r.standard_normal(n * n) + 1j * r.standard_normal(n * n)).to(dev)
+    yg = torch.empty_like(u)
+    yd = torch.empty_like(u)
+    for rep in range(4):
+        vr = torch.from_numpy(r.uniform(-9e4, -2e4, n * n)).to(dev)
+        graphed.set_potential(vr)
+        direct.set_potential(vr)
+        Pg.fill_(float("nan"))
+        graphed.stencil_setup(t, nS, Pg, ig)
+        direct.stencil_setup(t, nS, Pd, idd)
+        graphed.ps_apply(u, yg)
+        direct.ps_apply(u, yd)
+        torch.cuda.synchronize()
+        assert torch.equal(Pg, Pd) and torch.equal(ig, idd), rep
+        assert torch.equal(yg, yd), rep
+        # the replayed setup still follows the row formula on its own tables
+        tab = graphed.get_tables()
+        vv = vr.cpu().numpy().reshape(n, n)
+        own = O.assemble(vv, tab["S"], tab["alpha"], tab["C"], ig.cpu().numpy().reshape(n, n),
+                         O.offsets(2, t))
+        assert np.array_equal(Pg.cpu().numpy().reshape(-1, m), own)
