@@ -16,8 +16,9 @@
 //     with T[dl] = sum_{k_d} cw[k_d][dl] r the inner sum of the thread's row;
 //     only the pairs da <= db are accumulated.
 // A wave owns 64 consecutive outer indices o = (k_1..k_{d-1}) (one per lane)
-// and 64 consecutive values of k_d, whose cw rows are staged in LDS and read
-// as wave-wide broadcasts; work units are uniform, so the load is balanced.
+// and 64 consecutive values of k_d, whose cw rows are staged in LDS (all loads
+// in flight at once) and read as wave-wide broadcasts; work units are uniform,
+// so the load is balanced.
 // Units write their partial sums, unscaled:
 // [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
 #include "setup_common.h"
@@ -42,43 +43,63 @@ __device__ __forceinline__ double green_r(int K2, double s) {
   return lsp::rcp_nr(lam + s);
 }
 
-constexpr int kTile = 64;  // outer indices per wave = values of k_d per wave
+constexpr int kTile = 64;   // outer indices per wave (one per lane)
+constexpr int kKTile = 64;  // values of k_d per wave
 
-// One wave per work unit (shift, 64 consecutive outer indices, 64 consecutive
-// values of k_d). Units below the diagonal (every k_d < k_{d-1}) write zeros.
-template <int D, int W>
-__global__ __launch_bounds__(kTile) void green_sums_kernel(const double* __restrict__ mm_part,
-                                                           int mm_blocks, int nreq,
-                                                           double* S_out, int* nS_out,
-                                                           double* vrange_out,
-                                                           const double* __restrict__ cw, int n,
-                                                           int ktiles, double* __restrict__ part) {
+// kd terms [kd0, kd0 + U) of the inner sums T. MASKED applies the triangle
+// weights: 1 above, 1/2 on and 0 below the diagonal k_d = k_{d-1}, 0 for
+// padding lanes.
+template <int W, int U, bool MASKED>
+__device__ __forceinline__ void green_terms(const double* __restrict__ cws, int kd0, int K2o,
+                                            int kk, bool valid, double s, double* tg,
+                                            double* tq) {
+  double r[U], r2[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int kd = kd0 + u;
+    const double r0 = green_r(K2o + kd * kd, s);
+    if (MASKED) {
+      const double wgt = valid ? ((kd > kk) ? 1.0 : ((kd == kk) ? 0.5 : 0.0)) : 0.0;
+      r[u] = wgt * r0;
+      r2[u] = r[u] * r0;
+    } else {
+      r[u] = r0;
+      r2[u] = r0 * r0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const double* c = cws + u * W;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      tg[j] = fma(c[j], r[u], tg[j]);
+      tq[j] = fma(c[j], r2[u], tq[j]);
+    }
+  }
+}
+
+// One wave per work unit (shift, 64 consecutive outer indices, KT consecutive
+// values of k_d). The prologue forms the shift list from the min/max partials
+// (Sec. 4.1); unit (0, 0) publishes it. Units below the diagonal (every
+// k_d < k_{d-1}) write zeros.
+template <int D, int W, int KT>
+__global__ __launch_bounds__(kTile) void green_sums_kernel(
+    const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
+    int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
+    int n, int ktiles, double* __restrict__ part) {
   using Lay = GreenLayout<D, W>;
   constexpr int NP = Lay::NP;
   constexpr int WO2 = Lay::WO2;
   constexpr int NV = Lay::NV;
   constexpr int RCH = 15;  // values reduced per round
   constexpr int SCR = (RCH * (kTile + 1) > lsp::kMaxShifts) ? RCH * (kTile + 1) : lsp::kMaxShifts;
-  __shared__ double cws[kTile * W];
+  constexpr int PER = (KT * W + kTile - 1) / kTile;  // staged table values per lane
+  __shared__ double cws[KT * W];
   __shared__ double scratch[SCR];  // shift list first, then the reduction buffer
   __shared__ int sNS, sWave[1];
   __shared__ double sRange[2], sRed[2];
-
-  // shift list (Sec. 4.1) from the min/max partials; one block publishes it
-  lsp::shift_list_block(mm_part, mm_blocks, nreq, scratch, &sNS, sRange, sWave, sRed);
-  const int nS = sNS;
   const int lane = threadIdx.x;
-  if (blockIdx.x == 0 && blockIdx.y == 0) {
-    for (int i = lane; i < nS; i += kTile) S_out[i] = scratch[i];
-    if (lane == 0) {
-      *nS_out = nS;
-      vrange_out[0] = sRange[0];
-      vrange_out[1] = sRange[1];
-    }
-  }
   const int si = blockIdx.y;
-  if (si >= nS) return;
-  const double s = scratch[si];
 
   const int H = n / 2 + 1;
   const int ot = blockIdx.x / ktiles;
@@ -101,64 +122,14 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(const double* __restr
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) K2o += ko[i] * ko[i];
   const int kk = ko[D - 2];
-  const int k_begin = q * kTile;
-  const int k_end = min(H, k_begin + kTile);
+  const int k_begin = q * KT;
+  const int k_end = min(H, k_begin + KT);
 
-  double tg[W], tq[W];
+  // every table load of the unit is issued before the shift list is formed
+  const int cnt = (k_end - k_begin) * W;
+  double stage[PER];
 #pragma unroll
-  for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
-  __syncthreads();  // every read of the shift list is done before scratch is reused
-  if (__any(valid && kk < k_end)) {
-    for (int e = lane; e < (k_end - k_begin) * W; e += kTile) cws[e] = cw[k_begin * W + e];
-    __syncthreads();
-    if (__all(valid && kk < k_begin)) {
-      // every term of the tile lies above the diagonal: weight 1
-      int kd = k_begin;
-      for (; kd + 4 <= k_end; kd += 4) {
-        double r[4], r2[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          r[u] = green_r(K2o + (kd + u) * (kd + u), s);
-          r2[u] = r[u] * r[u];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double* c = cws + (kd + u - k_begin) * W;
-#pragma unroll
-          for (int j = 0; j < W; ++j) {
-            tg[j] = fma(c[j], r[u], tg[j]);
-            tq[j] = fma(c[j], r2[u], tq[j]);
-          }
-        }
-      }
-      for (; kd < k_end; ++kd) {
-        const double r = green_r(K2o + kd * kd, s);
-        const double r2 = r * r;
-        const double* c = cws + (kd - k_begin) * W;
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          tg[j] = fma(c[j], r, tg[j]);
-          tq[j] = fma(c[j], r2, tq[j]);
-        }
-      }
-    } else {
-      // weight 1 above, 1/2 on and 0 below the diagonal; 0 for padding lanes
-      for (int kd = k_begin; kd < k_end; ++kd) {
-        const double r0 = green_r(K2o + kd * kd, s);
-        const double wgt = valid ? ((kd > kk) ? 1.0 : ((kd == kk) ? 0.5 : 0.0)) : 0.0;
-        const double r1 = wgt * r0;
-        const double r2 = r1 * r0;
-        const double* c = cws + (kd - k_begin) * W;
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-          tg[j] = fma(c[j], r1, tg[j]);
-          tq[j] = fma(c[j], r2, tq[j]);
-        }
-      }
-    }
-  }
-
-  // symmetrised accumulation of the offset pairs (da <= db)
+  for (int i = 0; i < PER; ++i) stage[i] = cw[k_begin * W + min(lane + i * kTile, cnt - 1)];
   double ck[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) ck[j] = cw[kk * W + j];
@@ -169,6 +140,50 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(const double* __restr
   } else {
     lead[0] = 1.0;
   }
+
+  lsp::shift_list_block<kTile>(mm_part, nreq, scratch, &sNS, sRange, sWave, sRed);
+  const int nS = sNS;
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int i = lane; i < nS; i += kTile) S_out[i] = scratch[i];
+    if (lane == 0) {
+      *nS_out = nS;
+      vrange_out[0] = sRange[0];
+      vrange_out[1] = sRange[1];
+    }
+  }
+  if (si >= nS) return;
+  const double s = scratch[si];
+  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
+  if (!__any(valid && kk < k_end)) {
+    // the whole tile lies below the diagonal: no contribution
+    static_assert(NV <= kTile, "one lane per partial value");
+    if (lane < NV) out[lane] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i)
+    if (lane + i * kTile < cnt) cws[lane + i * kTile] = stage[i];
+  __syncthreads();  // also orders every read of the shift list before scratch is reused
+
+  double tg[W], tq[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
+  constexpr int U = 4;
+  int kd = k_begin;
+  if (__all(valid && kk < k_begin)) {
+    // every term of the tile lies above the diagonal: weight 1
+    for (; kd + U <= k_end; kd += U)
+      green_terms<W, U, false>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
+    for (; kd < k_end; ++kd)
+      green_terms<W, 1, false>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
+  } else {
+    for (; kd + U <= k_end; kd += U)
+      green_terms<W, U, true>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
+    for (; kd < k_end; ++kd)
+      green_terms<W, 1, true>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
+  }
+
+  // symmetrised accumulation of the offset pairs (da <= db)
   double acc[NV];
 #pragma unroll
   for (int x = 0; x < WO2; ++x) {
@@ -185,10 +200,9 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(const double* __restr
   }
 
   // wave reduction through LDS in a fixed order, RCH values per round
-  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
 #pragma unroll
   for (int v0 = 0; v0 < NV; v0 += RCH) {
-    __syncthreads();
+    if (v0 > 0) __syncthreads();
 #pragma unroll
     for (int vv = 0; vv < RCH; ++vv)
       if (v0 + vv < NV) scratch[vv * (kTile + 1) + lane] = acc[v0 + vv];
@@ -213,14 +227,14 @@ hipError_t run_green(lsp_problem* p, int num_shifts, int* blocks_out) {
   int64_t O = 1;
   for (int i = 0; i < D - 1; ++i) O *= H;
   const int otiles = (int)((O + kTile - 1) / kTile);
-  const int ktiles = (H + kTile - 1) / kTile;
+  const int ktiles = (H + kKTile - 1) / kKTile;
   const int blocks = otiles * ktiles;
   const size_t need = (size_t)num_shifts * blocks * GreenLayout<D, W>::NV;
   if (need > p->ws.green_part_cap) return hipErrorOutOfMemory;
   *blocks_out = blocks;
-  hipLaunchKernelGGL((green_sums_kernel<D, W>), dim3(blocks, num_shifts), dim3(kTile), 0,
-                     p->stream, p->ws.minmax_part, lsp::minmax_blocks(p->N), num_shifts, p->ws.S,
-                     p->ws.nS, p->ws.vrange, p->cosT, p->n, ktiles, p->ws.green_part);
+  hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(blocks, num_shifts), dim3(kTile), 0,
+                     p->stream, p->ws.minmax_part, num_shifts, p->ws.S, p->ws.nS, p->ws.vrange,
+                     p->cosT, p->n, ktiles, p->ws.green_part);
   return hipGetLastError();
 }
 
@@ -229,7 +243,7 @@ size_t green_need(int n, int shifts) {
   const int H = n / 2 + 1;
   int64_t O = 1;
   for (int i = 0; i < D - 1; ++i) O *= H;
-  const int64_t blocks = ((O + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+  const int64_t blocks = ((O + kTile - 1) / kTile) * ((H + kKTile - 1) / kKTile);
   return (size_t)shifts * blocks * GreenLayout<D, W>::NV;
 }
 

@@ -420,7 +420,7 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, doub
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-    hipError_t e = lsp::launch_shift_list(p, num_shifts);
+    hipError_t e = lsp::launch_minmax(p);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     int blocks = 0;

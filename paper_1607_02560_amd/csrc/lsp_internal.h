@@ -19,7 +19,7 @@ constexpr double kPi2 = 9.869604401089358;
 // Upper bounds of the build.
 constexpr int kMaxStencil = 64;     // m = (2t+1)^d
 constexpr int kMaxShifts = 1024;    // requested |S|
-constexpr int kMinMaxBlocks = 128;  // blocks of the min/max reduction
+constexpr int kMinMaxBlocks = 256;  // blocks (= partials) of the min/max reduction
 
 struct Workspace {
   // shift list (Sec. 4.1)
@@ -102,8 +102,9 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y);
 // count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
 hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // stencil setup stages
-hipError_t launch_shift_list(lsp_problem* p, int num_shifts);
-int minmax_blocks(int64_t N);  // partials written by launch_shift_list
+// per-block (min, max) partials of v; the Green's-sum launch turns them into S
+hipError_t launch_minmax(lsp_problem* p);
+// Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace
 hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out);
 // doubles of partial sums the Green's-sum launch writes for (d, n, t, shifts)
 size_t green_partial_doubles(int d, int n, int t, int shifts);

@@ -49,7 +49,6 @@ struct NullShared {
   double vec[NC][BMAX];
   double gv[NC][BMAX];
   int status[NC];
-  double alpha[WD];
   double stage[4096];
 };
 
@@ -311,9 +310,19 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
   constexpr int CHUNK = 4096;
   for (int c0 = 0; c0 < total; c0 += CHUNK) {
     const int cn = min(CHUNK, total - c0);
-    // all loads of a thread are issued before any is consumed
-#pragma unroll 16
-    for (int e = tid; e < cn; e += T) sh.stage[e] = ps[c0 + e];
+    // every load of a thread is issued before any is consumed
+    constexpr int PER = CHUNK / T;
+    double tmp[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * T;
+      tmp[u] = (e < cn) ? ps[c0 + e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * T;
+      if (e < cn) sh.stage[e] = tmp[u];
+    }
     __syncthreads();
     if (tid < NV) {
       // entries of value tid inside this chunk: global index b*NV + tid
@@ -384,20 +393,21 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
       av = coef * sh.vec[cs][pidx];
       cv = coef * sh.gv[cs][pidx];
     }
-    sh.alpha[lane] = av;
   }
-  __syncthreads();
   if (wid != 0) return;
-  int jm = 0;
-  double am = fabs(sh.alpha[0]);
-  for (int a = 1; a < M; ++a) {
-    const double aa = fabs(sh.alpha[a]);
-    if (aa > am) {
-      am = aa;
-      jm = a;
+  // largest |alpha| over the lanes, lowest offset on ties (wave reduction)
+  double am = (lane < M) ? fabs(av) : -1.0;
+  int jm = lane;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ao = __shfl_xor(am, o);
+    const int jo = __shfl_xor(jm, o);
+    if (ao > am || (ao == am && jo < jm)) {
+      am = ao;
+      jm = jo;
     }
   }
-  const double sgn = (sh.alpha[jm] < 0.0) ? -1.0 : 1.0;
+  const double sgn = (bcast(av, jm) < 0.0) ? -1.0 : 1.0;
   if (lane < M) {
     av *= sgn;
     cv *= sgn;

@@ -125,41 +125,54 @@ __device__ __forceinline__ double snapped_centre(double vmin, double width, int 
   return (4.0 * floor(centre / kFourPi2) + 2.0) * kPi2;
 }
 
-// Shift list S from the per-block (min, max) partials of v, computed by every
-// thread of a block (nthreads = blockDim.x, a multiple of 64, <= 1024).
+// Shift list S from the kMinMaxBlocks (min, max) partials of v, computed by
+// every thread of a block of NT threads (NT a multiple of 64 dividing
+// kMinMaxBlocks). All partial loads are issued before the first use.
 // The bin centres increase with i and snap is monotone, so duplicates are
 // adjacent; they are dropped by a ballot-based stream compaction.
 // Results in LDS: sS[0..*sNS), sRange[0] = v_min, sRange[1] = v_max.
-__device__ inline void shift_list_block(const double* __restrict__ part, int nparts, int nreq,
-                                        double* sS, int* sNS, double* sRange, int* sWave,
-                                        double* sRed) {
+template <int NT>
+__device__ inline void shift_list_block(const double* __restrict__ part, int nreq, double* sS,
+                                        int* sNS, double* sRange, int* sWave, double* sRed) {
+  static_assert(NT % 64 == 0 && kMinMaxBlocks % NT == 0, "block shape");
+  constexpr int NW = NT / 64;
+  constexpr int PER = kMinMaxBlocks / NT;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
-  const int nw = blockDim.x >> 6;
-  double lo = INFINITY, hi = -INFINITY;
-  for (int b = tid; b < nparts; b += blockDim.x) {
-    lo = fmin(lo, part[2 * b]);
-    hi = fmax(hi, part[2 * b + 1]);
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  double2 x[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) x[i] = p2[tid + i * NT];
+  double lo = x[0].x, hi = x[0].y;
+#pragma unroll
+  for (int i = 1; i < PER; ++i) {
+    lo = fmin(lo, x[i].x);
+    hi = fmax(hi, x[i].y);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     lo = fmin(lo, __shfl_xor(lo, o));
     hi = fmax(hi, __shfl_xor(hi, o));
   }
-  if (lane == 0) {
-    sRed[2 * wid] = lo;
-    sRed[2 * wid + 1] = hi;
-  }
-  __syncthreads();
-  double vmin = sRed[0], vmax = sRed[1];
-  for (int w = 1; w < nw; ++w) {
-    vmin = fmin(vmin, sRed[2 * w]);
-    vmax = fmax(vmax, sRed[2 * w + 1]);
+  double vmin = lo, vmax = hi;
+  if constexpr (NW > 1) {
+    if (lane == 0) {
+      sRed[2 * wid] = lo;
+      sRed[2 * wid + 1] = hi;
+    }
+    __syncthreads();
+    vmin = sRed[0];
+    vmax = sRed[1];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      vmin = fmin(vmin, sRed[2 * w]);
+      vmax = fmax(vmax, sRed[2 * w + 1]);
+    }
   }
   const double width = (vmax - vmin) / (double)nreq;
   int base = 0;
-  for (int c0 = 0; c0 < nreq; c0 += blockDim.x) {
+  for (int c0 = 0; c0 < nreq; c0 += NT) {
     const int k = c0 + tid;
     double s = 0.0;
     bool keep = false;
@@ -169,16 +182,21 @@ __device__ inline void shift_list_block(const double* __restrict__ part, int npa
     }
     const unsigned long long bal = __ballot(keep);
     const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0) sWave[wid] = __popcll(bal);
-    __syncthreads();
-    int off = base, total = 0;
-    for (int w = 0; w < nw; ++w) {
-      if (w < wid) off += sWave[w];
-      total += sWave[w];
+    if constexpr (NW == 1) {
+      if (keep) sS[base + before] = s;
+      base += __popcll(bal);
+    } else {
+      if (lane == 0) sWave[wid] = __popcll(bal);
+      __syncthreads();
+      int off = base, total = 0;
+      for (int w = 0; w < NW; ++w) {
+        if (w < wid) off += sWave[w];
+        total += sWave[w];
+      }
+      if (keep) sS[off + before] = s;
+      base += total;
+      __syncthreads();
     }
-    if (keep) sS[off + before] = s;
-    base += total;
-    __syncthreads();
   }
   if (tid == 0) {
     *sNS = base;

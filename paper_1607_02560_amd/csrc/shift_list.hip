@@ -1,9 +1,8 @@
-// First stage of the shift list of Sec. 4.1: per-block (min, max) of the
-// potential v. The list itself (bin centres over [v_min, v_max] snapped to
-// (4m+2) pi^2, duplicates removed) is derived from these partials at the
-// start of the next kernel by lsp::shift_list_block, which every block of
-// that kernel runs, so no cross-block synchronisation or host round trip is
-// needed.
+// First half of the shift list S of Sec. 4.1: per-block (min, max) of the
+// potential v over a fixed grid of kMinMaxBlocks blocks. The Green's-sum
+// kernel reduces these partials in its prologue and forms the bin centres
+// (lsp::shift_list_block), so the list never takes a launch of its own and no
+// value goes through the host.
 #include "setup_common.h"
 
 namespace {
@@ -12,6 +11,8 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kUnroll = 8;
 
+// Block b reduces a grid-strided share of v; blocks with no element write
+// (+inf, -inf). N is a power of two >= 64, so v is read as double2.
 __global__ __launch_bounds__(kThreads) void minmax_partial_kernel(const double* __restrict__ v,
                                                                   int64_t N, double* part) {
   __shared__ double wmin[kWaves], wmax[kWaves];
@@ -19,7 +20,7 @@ __global__ __launch_bounds__(kThreads) void minmax_partial_kernel(const double* 
   const int lane = tid & 63;
   const int wid = tid >> 6;
   double lo = INFINITY, hi = -INFINITY;
-  const int64_t half = N / 2;  // N is a power of two >= 64
+  const int64_t half = N / 2;
   const double2* v2 = reinterpret_cast<const double2*>(v);
   const int64_t stride = (int64_t)gridDim.x * kThreads;
   int64_t i = (int64_t)blockIdx.x * kThreads + tid;
@@ -62,17 +63,9 @@ __global__ __launch_bounds__(kThreads) void minmax_partial_kernel(const double* 
 
 namespace lsp {
 
-int minmax_blocks(int64_t N) {
-  int64_t blocks = (N / 2 + (int64_t)kThreads * kUnroll - 1) / ((int64_t)kThreads * kUnroll);
-  if (blocks > kMinMaxBlocks) blocks = kMinMaxBlocks;
-  if (blocks < 1) blocks = 1;
-  return (int)blocks;
-}
-
-hipError_t launch_shift_list(lsp_problem* p, int num_shifts) {
-  (void)num_shifts;
-  hipLaunchKernelGGL(minmax_partial_kernel, dim3(minmax_blocks(p->N)), dim3(kThreads), 0,
-                     p->stream, p->v, p->N, p->ws.minmax_part);
+hipError_t launch_minmax(lsp_problem* p) {
+  hipLaunchKernelGGL(minmax_partial_kernel, dim3(kMinMaxBlocks), dim3(kThreads), 0, p->stream,
+                     p->v, p->N, p->ws.minmax_part);
   return hipGetLastError();
 }
 
