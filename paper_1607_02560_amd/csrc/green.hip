@@ -15,12 +15,17 @@
 //     symmetrised: g[.., da, db] = sum_kk cw[kk][da] T[db] + cw[kk][db] T[da],
 //     with T[dl] = sum_{k_d} cw[k_d][dl] r the inner sum of the thread's row;
 //     only the pairs da <= db are accumulated.
-// A wave owns 64 consecutive outer indices o = (k_1..k_{d-1}) (one per lane)
-// and 64 consecutive values of k_d, whose cw rows are staged in LDS (all loads
-// in flight at once) and read as wave-wide broadcasts; work units are uniform,
-// so the load is balanced.
-// Units write their partial sums, unscaled:
+// A work unit is 64 consecutive outer indices o = (k_1..k_{d-1}) (one per
+// lane) and 64 consecutive values of k_d, whose cw rows are staged in LDS (all
+// loads in flight at once) and read as wave-wide broadcasts. A block of four
+// waves takes one unit for four shifts, so the shift list and the staging are
+// shared; units entirely below the diagonal are never launched. Each wave
+// reduces its sums over the lanes by recursive halving and writes one
+// partial per (shift, unit), unscaled:
 // [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
+#include <algorithm>
+#include <vector>
+
 #include "setup_common.h"
 
 #pragma clang fp contract(off)
@@ -43,8 +48,11 @@ __device__ __forceinline__ double green_r(int K2, double s) {
   return lsp::rcp_nr(lam + s);
 }
 
-constexpr int kTile = 64;   // outer indices per wave (one per lane)
-constexpr int kKTile = 64;  // values of k_d per wave
+constexpr int kTile = 64;     // outer indices per unit (one per lane)
+constexpr int kKTile = 64;    // values of k_d per unit
+constexpr int kWaves = 4;     // shifts per block (one wave each)
+constexpr int kThreads = 64 * kWaves;
+constexpr size_t kResidencyLds = 40 * 1024;  // dynamic LDS per block (unused)
 
 // kd terms [kd0, kd0 + U) of the inner sums T. MASKED applies the triangle
 // weights: 1 above, 1/2 on and 0 below the diagonal k_d = k_{d-1}, 0 for
@@ -78,32 +86,75 @@ __device__ __forceinline__ void green_terms(const double* __restrict__ cws, int 
   }
 }
 
-// One wave per work unit (shift, 64 consecutive outer indices, KT consecutive
-// values of k_d). The prologue forms the shift list from the min/max partials
-// (Sec. 4.1); unit (0, 0) publishes it. Units below the diagonal (every
-// k_d < k_{d-1}) write zeros.
+// Sum of the P2 values a[] over the 64 lanes by recursive halving: at each
+// step a lane keeps one half of its vector and adds the partner's copy of
+// that half (partner = lane ^ o). After log2(P2) steps lane l holds value
+// l >> (6 - log2 P2) summed over its group of 2^(6 - log2 P2) lanes; the
+// remaining steps add across that group. The order is fixed, so the result
+// is deterministic.
+template <int P2, int O = 32>
+__device__ __forceinline__ void halving_sum(double* a, int lane) {
+  if constexpr (O >= 1) {
+    if constexpr (P2 > 1) {
+      constexpr int h = P2 / 2;
+      const bool up = (lane & O) != 0;
+#pragma unroll
+      for (int i = 0; i < h; ++i) {
+        const double send = up ? a[i] : a[h + i];
+        const double keep = up ? a[h + i] : a[i];
+        a[i] = keep + __shfl_xor(send, O);
+      }
+      halving_sum<h, O / 2>(a, lane);
+    } else {
+      a[0] += __shfl_xor(a[0], O);
+      halving_sum<1, O / 2>(a, lane);
+    }
+  }
+}
+
+constexpr int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p *= 2;
+  return p;
+}
+constexpr int log2_exact(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+// One block per (work unit, group of kWaves shifts); wave w handles shift
+// kWaves * blockIdx.y + w. A work unit is 64 consecutive outer indices
+// o = (k_1..k_{d-1}) (one per lane) and KT consecutive values of k_d; only
+// units with a term on or above the diagonal k_d >= k_{d-1} are launched
+// (their (outer tile, k tile) pairs come from `units`, built on the host).
+// The prologue forms the shift list from the min/max partials (Sec. 4.1) once
+// per block and stages the unit's cosine rows in LDS; unit 0 of shift group 0
+// publishes S, |S| and (v_min, v_max).
 template <int D, int W, int KT>
-__global__ __launch_bounds__(kTile) void green_sums_kernel(
+__global__ __launch_bounds__(kThreads) void green_sums_kernel(
     const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
     int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
-    int n, int ktiles, double* __restrict__ part) {
+    const int* __restrict__ units, int n, double* __restrict__ part) {
   using Lay = GreenLayout<D, W>;
   constexpr int NP = Lay::NP;
   constexpr int WO2 = Lay::WO2;
   constexpr int NV = Lay::NV;
-  constexpr int RCH = 15;  // values reduced per round
-  constexpr int SCR = (RCH * (kTile + 1) > lsp::kMaxShifts) ? RCH * (kTile + 1) : lsp::kMaxShifts;
-  constexpr int PER = (KT * W + kTile - 1) / kTile;  // staged table values per lane
+  static_assert(NV <= 64, "one lane per partial value");
+  constexpr int P2 = pow2_at_least(NV);
+  constexpr int PER = (KT * W + kThreads - 1) / kThreads;  // staged table values per thread
   __shared__ double cws[KT * W];
-  __shared__ double scratch[SCR];  // shift list first, then the reduction buffer
-  __shared__ int sNS, sWave[1];
-  __shared__ double sRange[2], sRed[2];
-  const int lane = threadIdx.x;
-  const int si = blockIdx.y;
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sNS, sWave[kWaves];
+  __shared__ double sRange[2], sRed[2 * kWaves];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
 
   const int H = n / 2 + 1;
-  const int ot = blockIdx.x / ktiles;
-  const int q = blockIdx.x % ktiles;
+  const int unit = units[blockIdx.x];
+  const int ot = unit >> 16;
+  const int q = unit & 0xffff;
   int O = 1;
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) O *= H;
@@ -125,11 +176,11 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(
   const int k_begin = q * KT;
   const int k_end = min(H, k_begin + KT);
 
-  // every table load of the unit is issued before the shift list is formed
+  // every table load of the block is issued before the shift list is formed
   const int cnt = (k_end - k_begin) * W;
   double stage[PER];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) stage[i] = cw[k_begin * W + min(lane + i * kTile, cnt - 1)];
+  for (int i = 0; i < PER; ++i) stage[i] = cw[k_begin * W + min(tid + i * kThreads, cnt - 1)];
   double ck[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) ck[j] = cw[kk * W + j];
@@ -141,37 +192,31 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(
     lead[0] = 1.0;
   }
 
-  lsp::shift_list_block<kTile>(mm_part, nreq, scratch, &sNS, sRange, sWave, sRed);
+  lsp::shift_list_block<kThreads>(mm_part, nreq, sS, &sNS, sRange, sWave, sRed);
   const int nS = sNS;
   if (blockIdx.x == 0 && blockIdx.y == 0) {
-    for (int i = lane; i < nS; i += kTile) S_out[i] = scratch[i];
-    if (lane == 0) {
+    for (int i = tid; i < nS; i += kThreads) S_out[i] = sS[i];
+    if (tid == 0) {
       *nS_out = nS;
       vrange_out[0] = sRange[0];
       vrange_out[1] = sRange[1];
     }
   }
-  if (si >= nS) return;
-  const double s = scratch[si];
-  double* out = part + ((int64_t)si * gridDim.x + blockIdx.x) * NV;
-  if (!__any(valid && kk < k_end)) {
-    // the whole tile lies below the diagonal: no contribution
-    static_assert(NV <= kTile, "one lane per partial value");
-    if (lane < NV) out[lane] = 0.0;
-    return;
-  }
 #pragma unroll
   for (int i = 0; i < PER; ++i)
-    if (lane + i * kTile < cnt) cws[lane + i * kTile] = stage[i];
-  __syncthreads();  // also orders every read of the shift list before scratch is reused
+    if (tid + i * kThreads < cnt) cws[tid + i * kThreads] = stage[i];
+  __syncthreads();  // the last barrier of the block: waves are independent below
 
+  const int si = blockIdx.y * kWaves + wid;
+  if (si >= nS) return;
+  const double s = sS[si];
   double tg[W], tq[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
   constexpr int U = 4;
   int kd = k_begin;
   if (__all(valid && kk < k_begin)) {
-    // every term of the tile lies above the diagonal: weight 1
+    // every term of the unit lies above the diagonal: weight 1
     for (; kd + U <= k_end; kd += U)
       green_terms<W, U, false>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
     for (; kd < k_end; ++kd)
@@ -183,8 +228,8 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(
       green_terms<W, 1, true>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
   }
 
-  // symmetrised accumulation of the offset pairs (da <= db)
-  double acc[NV];
+  // symmetrised accumulation of the offset pairs (da <= db), padded to P2
+  double a[P2];
 #pragma unroll
   for (int x = 0; x < WO2; ++x) {
     int pi = 0;
@@ -192,80 +237,88 @@ __global__ __launch_bounds__(kTile) void green_sums_kernel(
     for (int da = 0; da < W; ++da) {
 #pragma unroll
       for (int db = da; db < W; ++db) {
-        acc[x * NP + pi] = lead[x] * (ck[da] * tg[db] + ck[db] * tg[da]);
-        acc[WO2 * NP + x * NP + pi] = lead[x] * (ck[da] * tq[db] + ck[db] * tq[da]);
+        a[x * NP + pi] = lead[x] * (ck[da] * tg[db] + ck[db] * tg[da]);
+        a[WO2 * NP + x * NP + pi] = lead[x] * (ck[da] * tq[db] + ck[db] * tq[da]);
         ++pi;
       }
     }
   }
+#pragma unroll
+  for (int i = NV; i < P2; ++i) a[i] = 0.0;
+  halving_sum<P2>(a, lane);
+  constexpr int G = 6 - log2_exact(P2);  // lanes per value: 2^G
+  const int vi = lane >> G;
+  if ((lane & ((1 << G) - 1)) == 0 && vi < NV)
+    part[((int64_t)si * gridDim.x + blockIdx.x) * NV + vi] = a[0];
+}
 
-  // wave reduction through LDS in a fixed order, RCH values per round
-#pragma unroll
-  for (int v0 = 0; v0 < NV; v0 += RCH) {
-    if (v0 > 0) __syncthreads();
-#pragma unroll
-    for (int vv = 0; vv < RCH; ++vv)
-      if (v0 + vv < NV) scratch[vv * (kTile + 1) + lane] = acc[v0 + vv];
-    __syncthreads();
-    if (lane < RCH && v0 + lane < NV) {
-      const double* rr = scratch + lane * (kTile + 1);
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      for (int l = 0; l < kTile; l += 4) {
-        s0 += rr[l];
-        s1 += rr[l + 1];
-        s2 += rr[l + 2];
-        s3 += rr[l + 3];
+// Work units with at least one term on or above the diagonal, in
+// (outer tile, k tile) order, packed as (ot << 16) | q.
+template <int D>
+void build_units(int n, std::vector<int>& units) {
+  const int H = n / 2 + 1;
+  int64_t O = 1;
+  for (int i = 0; i < D - 1; ++i) O *= H;
+  const int otiles = (int)((O + kTile - 1) / kTile);
+  const int ktiles = (H + kKTile - 1) / kKTile;
+  units.clear();
+  for (int ot = 0; ot < otiles; ++ot) {
+    for (int q = 0; q < ktiles; ++q) {
+      const int k_end = std::min(H, (q + 1) * kKTile);
+      bool any = false;
+      for (int l = 0; l < kTile && !any; ++l) {
+        const int64_t o = (int64_t)ot * kTile + l;
+        if (o < O && (int)(o % H) < k_end) any = true;
       }
-      out[v0 + lane] = (s0 + s1) + (s2 + s3);
+      if (any) units.push_back((ot << 16) | q);
     }
   }
 }
 
 template <int D, int W>
-hipError_t run_green(lsp_problem* p, int num_shifts, int* blocks_out) {
-  const int H = p->n / 2 + 1;
-  int64_t O = 1;
-  for (int i = 0; i < D - 1; ++i) O *= H;
-  const int otiles = (int)((O + kTile - 1) / kTile);
-  const int ktiles = (H + kKTile - 1) / kKTile;
-  const int blocks = otiles * ktiles;
-  const size_t need = (size_t)num_shifts * blocks * GreenLayout<D, W>::NV;
-  if (need > p->ws.green_part_cap) return hipErrorOutOfMemory;
-  *blocks_out = blocks;
-  hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(blocks, num_shifts), dim3(kTile), 0,
-                     p->stream, p->ws.minmax_part, num_shifts, p->ws.S, p->ws.nS, p->ws.vrange,
-                     p->cosT, p->n, ktiles, p->ws.green_part);
+hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out) {
+  const int nunits = p->green_nunits;
+  const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
+  if (need > p->ws.green_part_cap || nunits < 1) return hipErrorInvalidValue;
+  *units_out = nunits;
+  const int groups = (num_shifts + kWaves - 1) / kWaves;
+  // The blocks are uniform and all resident at once, so the time is set by
+  // the most loaded SIMD. Reserving kResidencyLds bytes of LDS per block (on
+  // top of its ~10-12 KB of static LDS) lets at most three blocks share a
+  // CU's 160 KB, so no SIMD takes more than three waves.
+  hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(nunits, groups), dim3(kThreads),
+                     kResidencyLds, p->stream, p->ws.minmax_part, num_shifts, p->ws.S, p->ws.nS, p->ws.vrange,
+                     p->cosT, p->green_units, p->n, p->ws.green_part);
   return hipGetLastError();
-}
-
-template <int D, int W>
-size_t green_need(int n, int shifts) {
-  const int H = n / 2 + 1;
-  int64_t O = 1;
-  for (int i = 0; i < D - 1; ++i) O *= H;
-  const int64_t blocks = ((O + kTile - 1) / kTile) * ((H + kKTile - 1) / kKTile);
-  return (size_t)shifts * blocks * GreenLayout<D, W>::NV;
 }
 
 }  // namespace
 
 namespace lsp {
 
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* blocks) {
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units) {
   const int W = 2 * p->t + 1;
-  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, blocks);
-  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, blocks);
-  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, blocks);
-  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, blocks);
+  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, units);
+  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, units);
+  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, units);
+  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, units);
   return hipErrorInvalidValue;
+}
+
+void green_units(int d, int n, std::vector<int>& units) {
+  if (d == 2) build_units<2>(n, units);
+  else build_units<3>(n, units);
 }
 
 size_t green_partial_doubles(int d, int n, int t, int shifts) {
   const int W = 2 * t + 1;
-  if (d == 2 && W == 3) return green_need<2, 3>(n, shifts);
-  if (d == 2 && W == 5) return green_need<2, 5>(n, shifts);
-  if (d == 2 && W == 7) return green_need<2, 7>(n, shifts);
-  if (d == 3 && W == 3) return green_need<3, 3>(n, shifts);
+  std::vector<int> units;
+  green_units(d, n, units);
+  const size_t nu = units.size();
+  if (d == 2 && W == 3) return shifts * nu * GreenLayout<2, 3>::NV;
+  if (d == 2 && W == 5) return shifts * nu * GreenLayout<2, 5>::NV;
+  if (d == 2 && W == 7) return shifts * nu * GreenLayout<2, 7>::NV;
+  if (d == 3 && W == 3) return shifts * nu * GreenLayout<3, 3>::NV;
   return 0;
 }
 

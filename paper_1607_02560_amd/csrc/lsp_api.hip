@@ -134,6 +134,16 @@ int upload_cos_table(lsp_problem* p, int W) {
   if (hipMemcpy(p->cosT, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice) !=
       hipSuccess)
     return lsp::set_error(LSP_EHIP, "upload of the cosine table failed");
+  if (!p->green_units) {
+    std::vector<int> units;
+    lsp::green_units(p->d, p->n, units);
+    if ((rc = dalloc((void**)&p->green_units, sizeof(int) * units.size(), "green units")))
+      return rc;
+    if (hipMemcpy(p->green_units, units.data(), sizeof(int) * units.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return lsp::set_error(LSP_EHIP, "upload of the Green's-sum units failed");
+    p->green_nunits = (int)units.size();
+  }
   return LSP_OK;
 }
 
@@ -342,6 +352,7 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->z);
   dfree(p->tw);
   dfree(p->cosT);
+  dfree(p->green_units);
   dfree(p->flag);
   drop_graph(p->g_setup);
   drop_graph(p->g_apply);

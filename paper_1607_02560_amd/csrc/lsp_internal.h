@@ -54,7 +54,9 @@ struct lsp_problem {
   int device = 0;
   double* v = nullptr;        // [N] potential
   double* tw = nullptr;       // [2n] exp(-2 pi i j / n), interleaved
-  double* cosT = nullptr;     // [n] cos(2 pi j / n)
+  double* cosT = nullptr;     // [(n/2+1) * (2t+1)] folded cosine weights
+  int* green_units = nullptr; // [green_nunits] Green's-sum work units
+  int green_nunits = 0;
   double* z = nullptr;        // [2N] ps_apply partial sums
   int* flag = nullptr;        // [1] device scratch flag
   // setup state
@@ -106,6 +108,8 @@ hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hip
 hipError_t launch_minmax(lsp_problem* p);
 // Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace
 hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out);
+// work units of the Green's-sum launch for (d, n), packed (outer tile << 16) | k tile
+void green_units(int d, int n, std::vector<int>& units);
 // doubles of partial sums the Green's-sum launch writes for (d, n, t, shifts)
 size_t green_partial_doubles(int d, int n, int t, int shifts);
 // full m x m Gram matrix from the packed parity blocks (host)
