@@ -86,30 +86,65 @@ __device__ __forceinline__ void green_terms(const double* __restrict__ cws, int 
   }
 }
 
-// Sum of the P2 values a[] over the 64 lanes by recursive halving: at each
-// step a lane keeps one half of its vector and adds the partner's copy of
-// that half (partner = lane ^ o). After log2(P2) steps lane l holds value
-// l >> (6 - log2 P2) summed over its group of 2^(6 - log2 P2) lanes; the
-// remaining steps add across that group. The order is fixed, so the result
-// is deterministic.
-template <int P2, int O = 32>
-__device__ __forceinline__ void halving_sum(double* a, int lane) {
-  if constexpr (O >= 1) {
-    if constexpr (P2 > 1) {
-      constexpr int h = P2 / 2;
-      const bool up = (lane & O) != 0;
+// One step of recursive halving on lane bit BIT: of the P2 values a[], the
+// lanes with the bit clear keep the lower half and those with it set the
+// upper half, each adding the partner's copy of the half it keeps. The
+// partner agrees with the lane on every bit used by earlier steps.
+template <int P2, int BIT, int SRC>
+__device__ __forceinline__ void halving_step(double* a, int lane) {
+  constexpr int h = P2 / 2;
+  const bool up = (lane >> BIT) & 1;
 #pragma unroll
-      for (int i = 0; i < h; ++i) {
-        const double send = up ? a[i] : a[h + i];
-        const double keep = up ? a[h + i] : a[i];
-        a[i] = keep + __shfl_xor(send, O);
-      }
-      halving_sum<h, O / 2>(a, lane);
-    } else {
-      a[0] += __shfl_xor(a[0], O);
-      halving_sum<1, O / 2>(a, lane);
+  for (int i = 0; i < h; ++i) {
+    const double send = up ? a[i] : a[h + i];
+    const double keep = up ? a[h + i] : a[i];
+    double recv;
+    if constexpr (SRC == 0) recv = lsp::dpp_move<lsp::kDppRowRor8>(send);
+    else if constexpr (SRC == 1) recv = lsp::dpp_move<lsp::kDppHalfMirror>(send);
+    else if constexpr (SRC == 2) recv = lsp::dpp_move<lsp::kDppQuadXor2>(send);
+    else if constexpr (SRC == 3) recv = lsp::dpp_move<lsp::kDppQuadXor1>(send);
+    else recv = __shfl_xor(send, 1 << BIT);
+    a[i] = keep + recv;
+  }
+}
+
+// Sum of the P2 (a power of two, 2..64) values a[] over the 64 lanes by
+// recursive halving. The in-row steps (bits 3, 2, 1, 0, through DPP) halve
+// the largest vectors; the cross-row bits 4 and 5 go last, through LDS
+// permutes, when one or two values are left. The order is fixed, so the
+// result is deterministic. Returns the index of the value the lane holds
+// (the sum over all 64 lanes); lanes that agree on the returned index hold
+// the same value.
+template <int P2>
+__device__ __forceinline__ int halving_sum(double* a, int lane) {
+  static_assert(P2 >= 2 && P2 <= 64 && (P2 & (P2 - 1)) == 0, "power of two");
+  int idx = 0;
+  // bits in step order with their halvings; once one value is left the
+  // remaining bits add across lanes
+  if constexpr (P2 >= 2) halving_step<P2, 3, 0>(a, lane);
+  if constexpr (P2 >= 4) halving_step<P2 / 2, 2, 1>(a, lane);
+  if constexpr (P2 >= 8) halving_step<P2 / 4, 1, 2>(a, lane);
+  if constexpr (P2 >= 16) halving_step<P2 / 8, 0, 3>(a, lane);
+  if constexpr (P2 >= 32) halving_step<P2 / 16, 4, 4>(a, lane);
+  if constexpr (P2 >= 64) halving_step<P2 / 32, 5, 4>(a, lane);
+  // index: each step's bit selects the upper half, weights P2/2, P2/4, ...
+  {
+    constexpr int order[6] = {3, 2, 1, 0, 4, 5};
+    int w = P2 / 2;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+      if (w >= 1) idx += ((lane >> order[st]) & 1) * w;
+      w /= 2;
     }
   }
+  // bits not used for halving: plain sums across the lanes that differ in them
+  if constexpr (P2 < 2) a[0] += lsp::dpp_move<lsp::kDppRowRor8>(a[0]);
+  if constexpr (P2 < 4) a[0] += lsp::dpp_move<lsp::kDppHalfMirror>(a[0]);
+  if constexpr (P2 < 8) a[0] += lsp::dpp_move<lsp::kDppQuadXor2>(a[0]);
+  if constexpr (P2 < 16) a[0] += lsp::dpp_move<lsp::kDppQuadXor1>(a[0]);
+  if constexpr (P2 < 32) a[0] += __shfl_xor(a[0], 16);
+  if constexpr (P2 < 64) a[0] += __shfl_xor(a[0], 32);
+  return idx;
 }
 
 constexpr int pow2_at_least(int x) {
@@ -117,10 +152,13 @@ constexpr int pow2_at_least(int x) {
   while (p < x) p *= 2;
   return p;
 }
-constexpr int log2_exact(int x) {
-  int l = 0;
-  while ((1 << l) < x) ++l;
-  return l;
+
+// Wavenumbers per axis covered by the tiles: in 2D the Nyquist value
+// k = n/2 is left out of the tiling and added as single terms (see below),
+// so that every unit holds the same amount of work; in 3D all of [0, n/2].
+template <int D>
+__host__ __device__ inline int tiled_wavenumbers(int n) {
+  return D == 2 ? n / 2 : n / 2 + 1;
 }
 
 // One block per (work unit, group of kWaves shifts); wave w handles shift
@@ -131,6 +169,14 @@ constexpr int log2_exact(int x) {
 // The prologue forms the shift list from the min/max partials (Sec. 4.1) once
 // per block and stages the unit's cosine rows in LDS; unit 0 of shift group 0
 // publishes S, |S| and (v_min, v_max).
+//
+// 2D: with Ht = n/2 tiled wavenumbers, a unit is either wholly above the
+// diagonal or a square tile on it. A square tile is summed in full, which
+// gives twice the symmetrised triangle sum (the summand is symmetric in
+// (k_1, k_2)); a factor 1/2 on its pair sums undoes that. Units in the last
+// k tile add the Nyquist column k_2 = n/2 as one more term (weight 1 above
+// the diagonal, hence 2 inside a square tile before the 1/2), and the waves
+// of unit 0 add the corner (n/2, n/2), whose cosine weights are (-1)^delta.
 template <int D, int W, int KT>
 __global__ __launch_bounds__(kThreads) void green_sums_kernel(
     const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
@@ -141,6 +187,7 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
   constexpr int WO2 = Lay::WO2;
   constexpr int NV = Lay::NV;
   static_assert(NV <= 64, "one lane per partial value");
+  static_assert(D == 3 || KT == kTile, "2D diagonal units must be square tiles");
   constexpr int P2 = pow2_at_least(NV);
   constexpr int PER = (KT * W + kThreads - 1) / kThreads;  // staged table values per thread
   __shared__ double cws[KT * W];
@@ -151,13 +198,14 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
   const int lane = tid & 63;
   const int wid = tid >> 6;
 
-  const int H = n / 2 + 1;
+  const int Ht = tiled_wavenumbers<D>(n);
+  const int nyq = n / 2;
   const int unit = units[blockIdx.x];
   const int ot = unit >> 16;
   const int q = unit & 0xffff;
   int O = 1;
 #pragma unroll
-  for (int i = 0; i < D - 1; ++i) O *= H;
+  for (int i = 0; i < D - 1; ++i) O *= Ht;
   const int o = ot * kTile + lane;
   const bool valid = o < O;
   int ko[D - 1];
@@ -165,8 +213,8 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
     int rem = valid ? o : 0;
 #pragma unroll
     for (int i = D - 2; i >= 0; --i) {
-      ko[i] = rem % H;
-      rem /= H;
+      ko[i] = rem % Ht;
+      rem /= Ht;
     }
   }
   int K2o = 0;
@@ -174,16 +222,20 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
   for (int i = 0; i < D - 1; ++i) K2o += ko[i] * ko[i];
   const int kk = ko[D - 2];
   const int k_begin = q * KT;
-  const int k_end = min(H, k_begin + KT);
+  const int k_end = min(Ht, k_begin + KT);
+  const bool nyq_col = (D == 2) && (k_end == Ht);
 
   // every table load of the block is issued before the shift list is formed
   const int cnt = (k_end - k_begin) * W;
   double stage[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) stage[i] = cw[k_begin * W + min(tid + i * kThreads, cnt - 1)];
-  double ck[W];
+  double ck[W], cn[W];
 #pragma unroll
-  for (int j = 0; j < W; ++j) ck[j] = cw[kk * W + j];
+  for (int j = 0; j < W; ++j) {
+    ck[j] = cw[kk * W + j];
+    cn[j] = cw[nyq * W + j];
+  }
   double lead[WO2];
   if constexpr (D == 3) {
 #pragma unroll
@@ -215,8 +267,8 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
   for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
   constexpr int U = 4;
   int kd = k_begin;
-  if (__all(valid && kk < k_begin)) {
-    // every term of the unit lies above the diagonal: weight 1
+  if (D == 2 || __all(valid && kk < k_begin)) {
+    // weight 1 on every term
     for (; kd + U <= k_end; kd += U)
       green_terms<W, U, false>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
     for (; kd < k_end; ++kd)
@@ -226,6 +278,23 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
       green_terms<W, U, true>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
     for (; kd < k_end; ++kd)
       green_terms<W, 1, true>(cws + (kd - k_begin) * W, kd, K2o, kk, valid, s, tg, tq);
+  }
+  if constexpr (D == 2) {
+    const bool square = (q == ot);
+    if (nyq_col) {
+      const double wn = square ? 2.0 : 1.0;
+      const double r0 = green_r(K2o + nyq * nyq, s);
+      const double r1 = wn * r0;
+      const double r2 = r1 * r0;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        tg[j] = fma(cn[j], r1, tg[j]);
+        tq[j] = fma(cn[j], r2, tq[j]);
+      }
+    }
+    const double half = !valid ? 0.0 : (square ? 0.5 : 1.0);
+#pragma unroll
+    for (int j = 0; j < W; ++j) ck[j] *= half;
   }
 
   // symmetrised accumulation of the offset pairs (da <= db), padded to P2
@@ -245,30 +314,48 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
   }
 #pragma unroll
   for (int i = NV; i < P2; ++i) a[i] = 0.0;
-  halving_sum<P2>(a, lane);
-  constexpr int G = 6 - log2_exact(P2);  // lanes per value: 2^G
-  const int vi = lane >> G;
-  if ((lane & ((1 << G) - 1)) == 0 && vi < NV)
-    part[((int64_t)si * gridDim.x + blockIdx.x) * NV + vi] = a[0];
+  const int vi = halving_sum<P2>(a, lane);
+  // one writer per value: the lanes holding value vi differ only in the bits
+  // not used for halving, the highest log2(64 / P2) of the step order
+  constexpr int kUnusedMask = (P2 >= 64) ? 0 : (P2 >= 32) ? 0x20 : (P2 >= 16) ? 0x30
+                              : (P2 >= 8) ? 0x31 : (P2 >= 4) ? 0x33 : 0x37;
+  if ((lane & kUnusedMask) == 0 && vi < NV) {
+    double val = a[0];
+    if (D == 2 && blockIdx.x == 0) {
+      // corner (n/2, n/2): pair (da, db) of value vi gets cn[da] cn[db] r
+      // (r^2 for the g*g half)
+      const int pi = vi % NP;
+      int da = 0, rest = pi;
+      while (rest >= W - da) {
+        rest -= W - da;
+        ++da;
+      }
+      const int db = da + rest;
+      const double r = green_r(2 * nyq * nyq, s);
+      const double rr = (vi < NP) ? r : r * r;
+      val += (cn[da] * cn[db]) * rr;
+    }
+    part[((int64_t)si * gridDim.x + blockIdx.x) * NV + vi] = val;
+  }
 }
 
 // Work units with at least one term on or above the diagonal, in
 // (outer tile, k tile) order, packed as (ot << 16) | q.
 template <int D>
 void build_units(int n, std::vector<int>& units) {
-  const int H = n / 2 + 1;
+  const int Ht = tiled_wavenumbers<D>(n);
   int64_t O = 1;
-  for (int i = 0; i < D - 1; ++i) O *= H;
+  for (int i = 0; i < D - 1; ++i) O *= Ht;
   const int otiles = (int)((O + kTile - 1) / kTile);
-  const int ktiles = (H + kKTile - 1) / kKTile;
+  const int ktiles = (Ht + kKTile - 1) / kKTile;
   units.clear();
   for (int ot = 0; ot < otiles; ++ot) {
     for (int q = 0; q < ktiles; ++q) {
-      const int k_end = std::min(H, (q + 1) * kKTile);
+      const int k_end = std::min(Ht, (q + 1) * kKTile);
       bool any = false;
       for (int l = 0; l < kTile && !any; ++l) {
         const int64_t o = (int64_t)ot * kTile + l;
-        if (o < O && (int)(o % H) < k_end) any = true;
+        if (o < O && (int)(o % Ht) < k_end) any = true;
       }
       if (any) units.push_back((ot << 16) | q);
     }

@@ -99,6 +99,23 @@ __device__ __forceinline__ double bcast(double x, int src) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Lane exchange of a double within each 16-lane row (DPP; no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// DPP controls: rotate a 16-lane row by 8 (partner lane ^ 8), mirror each
+// 8-lane half row (partner 7 - i, which differs in bit 2), quad permutations
+// [2,3,0,1] (lane ^ 2) and [1,0,3,2] (lane ^ 1).
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppQuadXor1 = 0xB1;
+
 // Index of the shift of the sorted list S closest to vj (Sec. 4.1); the two
 // neighbours of the insertion point are compared and ties go to the lower index.
 __device__ __forceinline__ int nearest_shift(const double* S, int nS, double vj) {
@@ -150,11 +167,19 @@ __device__ inline void shift_list_block(const double* __restrict__ part, int nre
     lo = fmin(lo, x[i].x);
     hi = fmax(hi, x[i].y);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-  }
+  // wave reduction: in-row lane moves first (DPP), then across rows
+  lo = fmin(lo, dpp_move<kDppRowRor8>(lo));
+  hi = fmax(hi, dpp_move<kDppRowRor8>(hi));
+  lo = fmin(lo, dpp_move<kDppHalfMirror>(lo));
+  hi = fmax(hi, dpp_move<kDppHalfMirror>(hi));
+  lo = fmin(lo, dpp_move<kDppQuadXor2>(lo));
+  hi = fmax(hi, dpp_move<kDppQuadXor2>(hi));
+  lo = fmin(lo, dpp_move<kDppQuadXor1>(lo));
+  hi = fmax(hi, dpp_move<kDppQuadXor1>(hi));
+  lo = fmin(lo, __shfl_xor(lo, 16));
+  hi = fmax(hi, __shfl_xor(hi, 16));
+  lo = fmin(lo, __shfl_xor(lo, 32));
+  hi = fmax(hi, __shfl_xor(hi, 32));
   double vmin = lo, vmax = hi;
   if constexpr (NW > 1) {
     if (lane == 0) {
