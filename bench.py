@@ -13,6 +13,8 @@ The roofline of the dominant kernel (the per-point assembly) uses its average
 duration from per-stage HIP events that the library records on its stream.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py --copy-probe MiB   # plain device copy of a known size, for
+                                       # scaling hardware byte counters
 """
 import argparse
 import json
@@ -26,6 +28,35 @@ if ROOT not in sys.path:
 
 METRIC = "local stencils/s + ps_apply GB/s, 2D n=1024; learned vs exact at equal GMRES iters"
 HBM_PEAK_GBPS = 8000.0
+
+# HBM bytes per launch of the assembly kernel on this workload, from the
+# FETCH_SIZE and WRITE_SIZE hardware counters (rocprofv3 --pmc, one counter
+# per run), each scaled by what the same counter reads for a plain 256 MiB
+# device copy (FETCH_SIZE reads half of the copied bytes: scale 2.000;
+# WRITE_SIZE all of them: scale 1.000). The readings hold for the kernel
+# sources they were taken on (sha256 prefix of the files below); for any
+# other sources the traffic is reported as null.
+ASSEMBLE_PMC = {
+    "fetch_kib": 5286.0, "write_kib": 208896.0,
+    "fetch_scale": 262144.0 / 131084.6, "write_scale": 262144.0 / 262144.0,
+    "sources": ("paper_1607_02560_amd/csrc/assemble.hip",
+                "paper_1607_02560_amd/csrc/setup_common.h"),
+    "sources_sha256": "13788e29e14f0714",
+}
+
+
+def assemble_traffic():
+    """Counter-based HBM bytes per assembly launch, or None if the kernel
+    sources differ from those the counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ASSEMBLE_PMC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != ASSEMBLE_PMC["sources_sha256"]:
+        return None
+    return (ASSEMBLE_PMC["fetch_kib"] * ASSEMBLE_PMC["fetch_scale"]
+            + ASSEMBLE_PMC["write_kib"] * ASSEMBLE_PMC["write_scale"]) * 1024.0
 
 
 def algorithmic_bytes(N, m):
@@ -65,6 +96,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="only run 5 device-to-device copies of MiB mebibytes and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the hot path is a single-GPU build); "
@@ -77,6 +110,17 @@ def main():
     from paper_1607_02560_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        # reference for the FETCH_SIZE / WRITE_SIZE counters: each copy reads
+        # and writes exactly copy_probe MiB
+        nbytes = args.copy_probe << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+        return
     p = W.helm2d_random(args.n)
     d, n, t, N = p.d, p.n, p.t, p.N
     m = (2 * t + 1) ** d
@@ -163,7 +207,7 @@ def main():
                                                       "setup", "apply")},
         "roofline": {"kernel": "assemble_kernel (per-point P rows)", "bound": "hbm",
                      "achieved": asm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": asm_gbps / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": asm_gbps / HBM_PEAK_GBPS, "traffic": assemble_traffic(),
                      "bytes_per_launch": nb["assemble"]},
         "roofline_ps_apply": {"bound": "hbm", "achieved": apply_gbps, "peak": HBM_PEAK_GBPS,
                               "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
