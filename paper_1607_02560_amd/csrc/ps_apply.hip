@@ -16,6 +16,7 @@
 // an N2-point DFT. The scaled spectrum is transformed back by the same two
 // steps in reverse order, so the spectrum never leaves registers.
 #include "lsp_internal.h"
+#include "setup_common.h"
 
 namespace {
 
@@ -125,6 +126,311 @@ struct RegDft {
 };
 
 enum { kFirst = 0, kAccum = 1, kFinal = 2 };
+
+// ---------------------------------------------------------------------------
+// Line operator for n = 256 R3 (R3 = 1, 2, 4: n = 256, 512, 1024).
+// T = 16 R3 threads own a line; n = 16 * 16 * R3. With j = T a + t and
+// k = k1 + 16 (k2a + 16 k2b):
+//   1. thread t: 16-point DFT over a of x[T a + t], times w_n^(t k1);
+//   2. LDS transpose: thread (k1, c) = (tau / R3, tau % R3) takes the values
+//      t = R3 b + c, runs the 16-point DFT over b, times w_T^(c k2a);
+//   3. the R3-point DFT over c runs across the R3 neighbouring lanes with DPP
+//      quad permutations (radix 2), which leaves k2b = bitrev(c) in lane c;
+// every thread then holds 16 spectrum values, scales them by 4 pi^2 kk^2 / n
+// and runs the same steps backwards (conjugate twiddles), ending with
+// x[T a + t] in natural order. Two LDS transposes per line in total; 16
+// complex values per thread.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cmul(double& xr, double& xi, double wr, double wi) {
+  const double r = xr * wr - xi * wi;
+  const double i = xr * wi + xi * wr;
+  xr = r;
+  xi = i;
+}
+
+// x * conj(w)
+__device__ __forceinline__ void cmulc(double& xr, double& xi, double wr, double wi) {
+  const double r = xr * wr + xi * wi;
+  const double i = xi * wr - xr * wi;
+  xr = r;
+  xi = i;
+}
+
+// w^(m j) for j = 0..15 with w^i = tw[i] (tw[i] = exp(-2 pi i i / n)) and
+// 12 m < n: six table loads, the rest as one product each.
+__device__ __forceinline__ void twiddle16(const double2* __restrict__ tw, int m, double* wr,
+                                          double* wi) {
+  double2 lo[4], hi[4];
+  lo[0] = make_double2(1.0, 0.0);
+  hi[0] = make_double2(1.0, 0.0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    lo[r] = tw[m * r];
+    hi[r] = tw[4 * m * r];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double a = hi[q].x, b = hi[q].y;
+      if (r > 0) {
+        if (q > 0) {
+          cmul(a, b, lo[r].x, lo[r].y);
+        } else {
+          a = lo[r].x;
+          b = lo[r].y;
+        }
+      }
+      wr[4 * q + r] = a;
+      wi[4 * q + r] = b;
+    }
+  }
+}
+
+// Radix-2 step of the R3-point DFT across lanes: lane c pairs with c ^ (1 << BIT);
+// the lower lane keeps p + v, the upper p - v (one FMA with the lane's sign).
+template <int BIT>
+__device__ __forceinline__ void lane_butterfly(double& vr, double& vi, int c) {
+  constexpr int ctrl = (BIT == 0) ? lsp::kDppQuadXor1 : lsp::kDppQuadXor2;
+  const double sgn = ((c >> BIT) & 1) ? -1.0 : 1.0;
+  const double pr = lsp::dpp_move<ctrl>(vr);
+  const double pi = lsp::dpp_move<ctrl>(vi);
+  vr = fma(sgn, vr, pr);
+  vi = fma(sgn, vi, pi);
+}
+
+// Forward R3-point DFT over the lanes c (decimation in frequency); lane c ends
+// with frequency bitrev(c).
+template <int R3>
+__device__ __forceinline__ void lane_dft_fwd(double& vr, double& vi, int c) {
+  if constexpr (R3 == 2) {
+    lane_butterfly<0>(vr, vi, c);
+  } else if constexpr (R3 == 4) {
+    lane_butterfly<1>(vr, vi, c);
+    if (c == 3) {  // times exp(-i pi/2) = -i
+      const double t = vr;
+      vr = vi;
+      vi = -t;
+    }
+    lane_butterfly<0>(vr, vi, c);
+  }
+}
+
+// Inverse (conjugate) R3-point DFT: lane c holds frequency bitrev(c) and ends
+// with index c (decimation in time).
+template <int R3>
+__device__ __forceinline__ void lane_dft_inv(double& vr, double& vi, int c) {
+  if constexpr (R3 == 2) {
+    lane_butterfly<0>(vr, vi, c);
+  } else if constexpr (R3 == 4) {
+    lane_butterfly<0>(vr, vi, c);
+    if (c == 3) {  // times exp(+i pi/2) = +i
+      const double t = vr;
+      vr = -vi;
+      vi = t;
+    }
+    lane_butterfly<1>(vr, vi, c);
+  }
+}
+
+template <int R3>
+__device__ __forceinline__ int bitrev_lane(int c) {
+  if constexpr (R3 == 4) return ((c & 1) << 1) | (c >> 1);
+  return c;
+}
+
+constexpr int kFftThreads = 256;
+
+// Blocks of the strided passes: groups 2j and 2j+1 cover the two halves of
+// the same 128-byte rows, so they are placed on the same XCD (block b runs
+// on XCD b mod 8) and share its L2.
+__device__ __forceinline__ int64_t xcd_paired_group(int64_t b, int64_t nb) {
+  const int64_t full = nb & ~(int64_t)15;
+  if (b >= full) return b;
+  const int64_t x = b & 7, q = b >> 3;
+  return (((q >> 1) << 3) + x) * 2 + (q & 1);
+}
+
+// One pass of L_1 along one axis for n = 256 R3.
+//   CONTIG: the axis is the last; line L starts at L n.
+//   !CONTIG: the axis has stride st; line L = (o, i) = (L / st, L % st)
+//            starts at o n st + i; a block's LPB lines are adjacent i, so a
+//            row of the block is LPB consecutive elements.
+// Loads and stores use the "memory" thread map (line, t): for CONTIG a line's
+// T threads are consecutive lanes (consecutive addresses); for !CONTIG the
+// LPB lines of a row are consecutive lanes, so one instruction covers
+// 64 / LPB rows of LPB * 16 bytes. The spectral steps use the "line" map
+// (line = tid / T, tau = tid % T), which keeps the R3 lanes of step 3 in one
+// quad. Both maps meet in the LDS layout sh[line][k1][t].
+// MODE: kFirst out = L_1 u; kAccum out = L_1 u + acc; kFinal out = L_1 u + acc + v u.
+template <int R3, bool CONTIG, int MODE>
+__global__ __launch_bounds__(kFftThreads) void fft_line_kernel(
+    const double2* __restrict__ u, double2* __restrict__ out, const double2* __restrict__ acc,
+    const double* __restrict__ v, const double2* __restrict__ tw, int64_t nlines, int64_t st) {
+  constexpr int T = 16 * R3;
+  constexpr int n = 16 * T;
+  constexpr int LPB = kFftThreads / T;  // lines per block
+  constexpr int RS = T + 1;             // padded LDS row
+  constexpr int LS = 16 * RS + 2;       // LDS stride between lines (padded)
+  __shared__ double2 sh[LPB * LS];
+
+  const int tid = threadIdx.x;
+  const int64_t g = CONTIG ? (int64_t)blockIdx.x : xcd_paired_group(blockIdx.x, gridDim.x);
+  // memory map
+  const int ml = CONTIG ? tid / T : tid % LPB;
+  const int t = CONTIG ? tid % T : tid / LPB;
+  const int64_t Lm = g * LPB + ml;
+  const bool active = Lm < nlines;
+  int64_t base, es;
+  if constexpr (CONTIG) {
+    base = Lm * n;
+    es = 1;
+  } else {
+    const int64_t o = Lm / st, i = Lm % st;
+    base = o * n * st + i;
+    es = st;
+  }
+  double2* Sm = sh + ml * LS;
+
+  // 1. 16-point DFT over a, twiddle w_n^(t k1)
+  double xr[16], xi[16], yr[16], yi[16], wr[16], wi[16];
+  double2 zacc[16];
+  double vv[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    double2 val = make_double2(0.0, 0.0);
+    if (active) val = u[base + (int64_t)(T * a + t) * es];
+    xr[a] = val.x;
+    xi[a] = val.y;
+  }
+  if constexpr (MODE == kAccum || MODE == kFinal) {
+    // the addends are loaded up front so their latency overlaps the transform
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+      zacc[a] = active ? acc[base + (int64_t)(T * a + t) * es] : make_double2(0.0, 0.0);
+  }
+  if constexpr (MODE == kFinal) {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) vv[a] = active ? v[base + (int64_t)(T * a + t) * es] : 0.0;
+  }
+  double ur[16], ui[16];
+  if constexpr (MODE == kFinal) {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      ur[a] = xr[a];
+      ui[a] = xi[a];
+    }
+  }
+  RegDft<16, -1>::template run<1>(xr, xi, yr, yi);
+  twiddle16(tw, t, wr, wi);
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) {
+    cmul(yr[k1], yi[k1], wr[k1], wi[k1]);
+    Sm[k1 * RS + t] = make_double2(yr[k1], yi[k1]);
+  }
+  __syncthreads();
+
+  // 2. line map: thread (k1, c) runs the 16-point DFT over b of t = R3 b + c
+  const int sl = tid / T;
+  const int tau = tid % T;
+  double2* Ss = sh + sl * LS;
+  const int k1 = tau / R3;
+  const int c = tau % R3;
+#pragma unroll
+  for (int b = 0; b < 16; ++b) {
+    const double2 val = Ss[k1 * RS + R3 * b + c];
+    xr[b] = val.x;
+    xi[b] = val.y;
+  }
+  RegDft<16, -1>::template run<1>(xr, xi, yr, yi);
+  if constexpr (R3 > 1) {
+    twiddle16(tw, 16 * c, wr, wi);
+#pragma unroll
+    for (int k2a = 0; k2a < 16; ++k2a) {
+      cmul(yr[k2a], yi[k2a], wr[k2a], wi[k2a]);
+      // 3. R3-point DFT across the lanes
+      lane_dft_fwd<R3>(yr[k2a], yi[k2a], c);
+    }
+  }
+  // scale by 4 pi^2 kk^2 / n (1/n: the inverse transform is unnormalised)
+  const int k2b = bitrev_lane<R3>(c);
+#pragma unroll
+  for (int k2a = 0; k2a < 16; ++k2a) {
+    const int k = k1 + 16 * (k2a + 16 * k2b);
+    const int kk = (k < n / 2) ? k : k - n;
+    const double fac = (lsp::kFourPi2 / n) * (double)(kk * kk);
+    yr[k2a] *= fac;
+    yi[k2a] *= fac;
+  }
+  if constexpr (R3 > 1) {
+#pragma unroll
+    for (int k2a = 0; k2a < 16; ++k2a) {
+      lane_dft_inv<R3>(yr[k2a], yi[k2a], c);
+      cmulc(yr[k2a], yi[k2a], wr[k2a], wi[k2a]);
+    }
+  }
+  RegDft<16, +1>::template run<1>(yr, yi, xr, xi);
+  // each thread rewrites exactly the LDS entries it read
+#pragma unroll
+  for (int b = 0; b < 16; ++b) Ss[k1 * RS + R3 * b + c] = make_double2(xr[b], xi[b]);
+  __syncthreads();
+
+  // 4. memory map: conjugate twiddle, 16-point inverse DFT over k1
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double2 val = Sm[q * RS + t];
+    xr[q] = val.x;
+    xi[q] = val.y;
+  }
+  twiddle16(tw, t, wr, wi);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) cmulc(xr[q], xi[q], wr[q], wi[q]);
+  RegDft<16, +1>::template run<1>(xr, xi, yr, yi);
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int64_t e = base + (int64_t)(T * a + t) * es;
+    double2 r = make_double2(yr[a], yi[a]);
+    if constexpr (MODE == kAccum || MODE == kFinal) {
+      r.x += zacc[a].x;
+      r.y += zacc[a].y;
+    }
+    if constexpr (MODE == kFinal) {
+      r.x += vv[a] * ur[a];
+      r.y += vv[a] * ui[a];
+    }
+    out[e] = r;
+  }
+}
+
+template <int R3>
+hipError_t run_fft_apply(const lsp_problem* p, const double2* u, double2* y) {
+  constexpr int n = 256 * R3;
+  constexpr int LPB = kFftThreads / (16 * R3);
+  const double2* tw = reinterpret_cast<const double2*>(p->tw);
+  double2* z = reinterpret_cast<double2*>(p->z);
+  const int64_t N = p->N;
+  const int64_t nlines = N / n;
+  const int64_t blocks = (nlines + LPB - 1) / LPB;
+  for (int ax = 0; ax < p->d - 1; ++ax) {
+    int64_t st = 1;
+    for (int b = ax + 1; b < p->d; ++b) st *= n;
+    if (ax == 0) {
+      hipLaunchKernelGGL((fft_line_kernel<R3, false, kFirst>), dim3((unsigned)blocks),
+                         dim3(kFftThreads), 0, p->stream, u, z, (const double2*)nullptr, p->v,
+                         tw, nlines, st);
+    } else {
+      hipLaunchKernelGGL((fft_line_kernel<R3, false, kAccum>), dim3((unsigned)blocks),
+                         dim3(kFftThreads), 0, p->stream, u, z, (const double2*)z, p->v, tw,
+                         nlines, st);
+    }
+  }
+  hipLaunchKernelGGL((fft_line_kernel<R3, true, kFinal>), dim3((unsigned)blocks),
+                     dim3(kFftThreads), 0, p->stream, u, y, (const double2*)z, p->v, tw, nlines,
+                     (int64_t)1);
+  return hipGetLastError();
+}
+
 
 // One pass of L_1 along one axis.
 //   CONTIG: the axis is the last (unit stride); lines are rows, nlines of them.
@@ -333,9 +639,9 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y) {
     case 32: return run_ps_apply<4, 8>(p, u2, y2);
     case 64: return run_ps_apply<8, 8>(p, u2, y2);
     case 128: return run_ps_apply<8, 16>(p, u2, y2);
-    case 256: return run_ps_apply<16, 16>(p, u2, y2);
-    case 512: return run_ps_apply<16, 32>(p, u2, y2);
-    case 1024: return run_ps_apply<32, 32>(p, u2, y2);
+    case 256: return run_fft_apply<1>(p, u2, y2);
+    case 512: return run_fft_apply<2>(p, u2, y2);
+    case 1024: return run_fft_apply<4>(p, u2, y2);
     default: return hipErrorInvalidValue;
   }
 }
