@@ -164,6 +164,13 @@ def main():
     # setup alone and apply alone, K calls each
     t_setup = timed(lambda: prob.stencil_setup(t, p.num_shifts, P, idx), args.steps)
     t_apply = timed(lambda: prob.ps_apply(u, y), args.steps)
+    # the FP32-storage form: same FP64 setup, P rows rounded to float32
+    P32 = torch.empty(N * m, dtype=torch.float32, device=dev)
+    setup32 = lambda: prob.stencil_setup(t, p.num_shifts, P32, idx, precision=lsp.LSP_FP32_REFINE)
+    for _ in range(args.warmup):
+        setup32()
+    t_setup32 = timed(setup32, args.steps)
+    del P32
     # per-stage HIP events recorded by the library on its stream (direct
     # launches): the dominant kernel's average duration for the roofline
     prob.profile(True)
@@ -209,6 +216,9 @@ def main():
                      "achieved": asm_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": asm_gbps / HBM_PEAK_GBPS, "traffic": assemble_traffic(),
                      "bytes_per_launch": nb["assemble"]},
+        "form_fp32_refine": {"setup_ms": t_setup32 * 1e3, "stencils_per_s": N / t_setup32,
+                             "bytes_per_setup": N * (8 + 4 * m + 4),
+                             "hbm_frac": N * (8 + 4 * m + 4) / t_setup32 / 1e9 / HBM_PEAK_GBPS},
         "roofline_ps_apply": {"bound": "hbm", "achieved": apply_gbps, "peak": HBM_PEAK_GBPS,
                               "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
                               "bytes_per_call": nb["apply"]},

@@ -43,7 +43,12 @@ enum {
   LSP_ESTATE = -7        /* call order violated (e.g. apply before setup) */
 };
 
-enum { LSP_FP64 = 0 };
+/* Storage precision of the P rows written by lsp_stencil_setup. Every step of
+ * the setup computes in FP64 in both modes (shift list, Green's sums, Gram
+ * matrix, null vectors, assignment, P-row formula). LSP_FP32_REFINE stores
+ * each P entry rounded once to float32 (half the bytes of the dominant write);
+ * the FP64 Krylov iteration around the preconditioner refines the solution. */
+enum { LSP_FP64 = 0, LSP_FP32_REFINE = 1 };
 
 typedef struct lsp_problem lsp_problem;
 
@@ -99,15 +104,17 @@ void lsp_destroy(lsp_problem* p);
  *   t           neighbourhood radius, 1 <= t, with m = (2t+1)^d <= 64 and 2t+1 < n.
  *   num_shifts  requested |S| (1..1024); 0 selects n/16 for d = 2, n/4 for d = 3
  *               (at least 1). The effective count |S| may be smaller.
- *   precision   LSP_FP64.
- *   P_dev       output, N*m float64, row j holds the m offsets of mu_0^t in
- *               lexicographic order over [-t,t]^d (last axis fastest); the
- *               column of entry (j, a) is (j + a) mod n per axis.
+ *   precision   LSP_FP64 (P in float64) or LSP_FP32_REFINE (P in float32,
+ *               each entry the FP64 value rounded to nearest).
+ *   P_dev       output, N*m entries of the precision's type; row j holds the
+ *               m offsets of mu_0^t in lexicographic order over [-t,t]^d
+ *               (last axis fastest); the column of entry (j, a) is
+ *               (j + a) mod n per axis.
  *   idx_dev     output, N int32 shift indices (may be NULL).
  * Asynchronous: returns once the work is enqueued.
  */
 int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision,
-                      double* P_dev, int32_t* idx_dev);
+                      void* P_dev, int32_t* idx_dev);
 
 /*
  * Pseudospectral apply y = (L + diag v) u with L = F^-1 diag(4 pi^2 |k|^2) F

@@ -20,15 +20,16 @@ using lsp::Pow;
 //      shift list are staged in LDS.
 //   2. Each point gets idx_j = argmin_i |S_i - v_j| (S is sorted: the two
 //      neighbours of the insertion point are compared, ties to the lower index).
-//   3. The tile's P rows are TR contiguous spans of TW*m doubles; thread k
-//      writes doubles 2k, 2k+1 of the flattened spans with one 16-byte store,
-//      evaluating P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j) for
-//      each with one rounding per operation.
+//   3. The tile's P rows are TR contiguous spans of TW*m entries; thread k
+//      writes entries VEC k .. VEC k + VEC-1 of the flattened spans with one
+//      16-byte store (2 doubles, or 4 floats for FP32 storage), evaluating
+//      P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j) for each in
+//      FP64 with one rounding per operation (then one rounding to FP32).
 // --------------------------------------------------------------------------
-template <int D, int W, int TR, int TW>
+template <int D, int W, int TR, int TW, typename PT>
 __global__ __launch_bounds__(256) void assemble_kernel(
     const double* __restrict__ v, int n, const double* __restrict__ S,
-    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, double* __restrict__ P,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
     int32_t* __restrict__ idx_out) {
   constexpr int t = (W - 1) / 2;
   constexpr int M = Pow<D, W>::v;
@@ -75,14 +76,17 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   }
   __syncthreads();
 
-  constexpr int SPAN = TW * M;  // even: TW is even
+  // VEC entries per 16-byte store: 2 doubles or 4 floats (TW is a multiple of 4)
+  constexpr int VEC = 16 / (int)sizeof(PT);
+  constexpr int SPAN = TW * M;
   constexpr int TOTAL = TR * SPAN;
-  for (int pos = 2 * tid; pos < TOTAL; pos += 512) {
+  static_assert(SPAN % VEC == 0, "whole stores per row span");
+  for (int pos = VEC * tid; pos < TOTAL; pos += VEC * 256) {
     const int r = pos / SPAN;
     const int e = pos - r * SPAN;
-    double outv[2];
+    double outv[VEC];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < VEC; ++h) {
       const int eh = e + h;
       const int p = eh / M;
       const int a = eh - p * M;
@@ -103,7 +107,13 @@ __global__ __launch_bounds__(256) void assemble_kernel(
     }
     const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0 + r) * n + c0) * M)
                                      : (((int64_t)(r0 + r) * n + c0) * M);
-    reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(outv[0], outv[1]);
+    if constexpr (VEC == 2) {
+      reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(outv[0], outv[1]);
+    } else {
+      // FP32 storage: each entry is the FP64 value rounded once to nearest
+      reinterpret_cast<float4*>(P + rowbase)[e >> 2] =
+          make_float4((float)outv[0], (float)outv[1], (float)outv[2], (float)outv[3]);
+    }
   }
 }
 
@@ -184,12 +194,17 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
 }
 
 template <int D, int W, int TW, int TR>
-hipError_t run_assemble_tile(lsp_problem* p, double* P, int32_t* idx) {
+hipError_t run_assemble_tile(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   const int n = p->n;
   if (n % TW != 0 || n % TR != 0) return hipErrorInvalidValue;
   dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
-  hipLaunchKernelGGL((assemble_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream, p->v, n,
-                     p->ws.S, p->ws.nS, reinterpret_cast<const double2*>(p->ws.actab), P, idx);
+  const double2* act = reinterpret_cast<const double2*>(p->ws.actab);
+  if (fp32)
+    hipLaunchKernelGGL((assemble_kernel<D, W, TR, TW, float>), grid, dim3(256), 0, p->stream,
+                       p->v, n, p->ws.S, p->ws.nS, act, static_cast<float*>(P), idx);
+  else
+    hipLaunchKernelGGL((assemble_kernel<D, W, TR, TW, double>), grid, dim3(256), 0, p->stream,
+                       p->v, n, p->ws.S, p->ws.nS, act, static_cast<double*>(P), idx);
   return hipGetLastError();
 }
 
@@ -207,18 +222,18 @@ hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
 
 // assembly tiles: one row of up to 128 points (2D) or 64 points (3D)
 template <int D, int W>
-hipError_t run_assemble(lsp_problem* p, double* P, int32_t* idx) {
+hipError_t run_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   switch (p->n) {
-    case 8: return run_assemble_tile<D, W, 8, 1>(p, P, idx);
-    case 16: return run_assemble_tile<D, W, 16, 1>(p, P, idx);
-    case 32: return run_assemble_tile<D, W, 32, 1>(p, P, idx);
+    case 8: return run_assemble_tile<D, W, 8, 1>(p, P, fp32, idx);
+    case 16: return run_assemble_tile<D, W, 16, 1>(p, P, fp32, idx);
+    case 32: return run_assemble_tile<D, W, 32, 1>(p, P, fp32, idx);
     default: break;
   }
   if constexpr (D == 2) {
-    if (p->n == 64) return run_assemble_tile<D, W, 64, 1>(p, P, idx);
-    return run_assemble_tile<D, W, 128, 1>(p, P, idx);
+    if (p->n == 64) return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
+    return run_assemble_tile<D, W, 128, 1>(p, P, fp32, idx);
   } else {
-    return run_assemble_tile<D, W, 64, 1>(p, P, idx);
+    return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
   }
 }
 
@@ -248,11 +263,11 @@ hipError_t run_c_apply(const lsp_problem* p, const double* r, double* z) {
 
 namespace lsp {
 
-hipError_t launch_assemble(lsp_problem* p, double* P, int32_t* idx) {
-  LSP_DISPATCH_DW(2, 3, (run_assemble<2, 3>(p, P, idx)))
-  LSP_DISPATCH_DW(2, 5, (run_assemble<2, 5>(p, P, idx)))
-  LSP_DISPATCH_DW(2, 7, (run_assemble<2, 7>(p, P, idx)))
-  LSP_DISPATCH_DW(3, 3, (run_assemble<3, 3>(p, P, idx)))
+hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
+  LSP_DISPATCH_DW(2, 3, (run_assemble<2, 3>(p, P, fp32, idx)))
+  LSP_DISPATCH_DW(2, 5, (run_assemble<2, 5>(p, P, fp32, idx)))
+  LSP_DISPATCH_DW(2, 7, (run_assemble<2, 7>(p, P, fp32, idx)))
+  LSP_DISPATCH_DW(3, 3, (run_assemble<3, 3>(p, P, fp32, idx)))
   return hipErrorInvalidValue;
 }
 

@@ -399,11 +399,12 @@ int lsp_default_num_shifts(int d, int n) {
   return s < 1 ? 1 : s;
 }
 
-int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, double* P_dev,
+int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
                       int32_t* idx_dev) {
   if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
   if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
-  if (precision != LSP_FP64) return lsp::set_error(LSP_EINVAL, "unsupported precision");
+  if (precision != LSP_FP64 && precision != LSP_FP32_REFINE)
+    return lsp::set_error(LSP_EINVAL, "unsupported precision");
   if (t < 1) return lsp::set_error(LSP_EINVAL, "t must be >= 1");
   const int W = 2 * t + 1;
   int m = 1;
@@ -444,14 +445,14 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, doub
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
-    e = lsp::launch_assemble(p, P_dev, idx_dev);
+    e = lsp::launch_assemble(p, P_dev, precision == LSP_FP32_REFINE, idx_dev);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     lsp::stage_end(p, tk_all);
     return hipSuccess;
   };
   const uint64_t key[6] = {(uint64_t)t, (uint64_t)num_shifts, (uint64_t)(uintptr_t)P_dev,
-                           (uint64_t)(uintptr_t)idx_dev, p->ws_gen, 0};
+                           (uint64_t)(uintptr_t)idx_dev, p->ws_gen, (uint64_t)precision};
   const hipError_t e = run_graph(p, p->g_setup, key, launch);
   if (e != hipSuccess) return lsp::hip_check(e, "stencil setup launch");
   p->have_setup = true;

@@ -115,7 +115,8 @@ size_t green_partial_doubles(int d, int n, int t, int shifts);
 // full m x m Gram matrix from the packed parity blocks (host)
 int expand_gram_host(int d, int t, const double* packed, double* full);
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks);
-hipError_t launch_assemble(lsp_problem* p, double* P, int32_t* idx);
+// P: float64 rows, or float32 rows when fp32
+hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // preconditioner halves and Krylov helpers
 hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
 

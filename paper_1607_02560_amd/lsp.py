@@ -28,6 +28,7 @@ LSP_EHIP = -5
 LSP_ESOLVER = -6
 LSP_ESTATE = -7
 LSP_FP64 = 0
+LSP_FP32_REFINE = 1
 STAGES = ("shifts", "green", "null", "assemble", "setup", "apply", "c_apply")
 
 HOST_SOLVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -167,7 +168,8 @@ class Problem:
     def stencil_setup(self, t: int, num_shifts: int, P, idx=None, precision: int = LSP_FP64):
         import torch
         m = (2 * t + 1) ** self.d
-        _need(P, torch.float64, self.N * m, "P")
+        _need(P, torch.float32 if precision == LSP_FP32_REFINE else torch.float64,
+              self.N * m, "P")
         if idx is not None:
             _need(idx, torch.int32, self.N, "idx")
         _check(self.lib.lsp_stencil_setup(self._h, t, num_shifts, precision, _ptr(P),

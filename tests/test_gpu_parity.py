@@ -276,6 +276,68 @@ def test_create_rejects_nonfinite(torch_dev):
     assert ei.value.code == lsp.LSP_ENONFINITE
 
 
+# ------------------------------------------------- FP32 storage of P -----
+@pytest.mark.parametrize("d,n,t,nS", [(2, 64, 2, 4), (2, 32, 3, 3), (3, 16, 1, 4),
+                                      (2, 1024, 2, 64)])
+def test_setup_fp32_storage(torch_dev, d, n, t, nS):
+    """LSP_FP32_REFINE computes everything in FP64 and stores P in float32:
+    the shift tables and idx equal those of the FP64 setup bit for bit, and
+    every P entry is the FP64 row formula on those tables rounded once to
+    float32 (bit-exact)."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    if (d, n) == (2, 1024):
+        v = W.helm2d_random(1024).v  # the benchmark's workload
+    else:
+        v = W.random_field_v(d, n, 31 + n, -6.0 * n * n, -2.0 * n * n)
+    N = n ** d
+    m = (2 * t + 1) ** d
+    print(f"[fp32 storage] d={d} n={n} t={t} nS={nS}", flush=True)
+    prob = lsp.Problem(d, n, torch.from_numpy(np.ascontiguousarray(v).reshape(-1)).to(dev))
+    P64 = torch.empty(N * m, dtype=torch.float64, device=dev)
+    i64 = torch.empty(N, dtype=torch.int32, device=dev)
+    prob.stencil_setup(t, nS, P64, i64)
+    tab64 = prob.get_tables()
+    P32 = torch.full((N * m,), float("nan"), dtype=torch.float32, device=dev)
+    i32 = torch.full((N,), -1, dtype=torch.int32, device=dev)
+    prob.stencil_setup(t, nS, P32, i32, precision=lsp.LSP_FP32_REFINE)
+    tab32 = prob.get_tables()
+    torch.cuda.synchronize()
+    for key in ("S", "alpha", "C", "sigma_min", "g", "gamma", "M"):
+        assert np.array_equal(tab64[key], tab32[key]), key
+    assert torch.equal(i64, i32)
+    assert torch.equal(P32, P64.to(torch.float32))
+    if N <= 65536:
+        offs = O.offsets(d, t)
+        P_own = O.assemble(v, tab32["S"], tab32["alpha"], tab32["C"],
+                           i32.cpu().numpy().reshape(v.shape), offs)
+        assert np.array_equal(P32.cpu().numpy().reshape(N, m), P_own.astype(np.float32))
+    prob.close()
+
+
+def test_precond_solve_fp32_rows(torch_dev):
+    """GMRES(40) with the host LU of the float32 P rows: the FP64 Krylov
+    iteration still reaches a true residual <= 1e-8, within one iteration of
+    the count with the float64 rows."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    p = W.helm2d_gauss(32)
+    N, m = 32 * 32, 9
+    prob = lsp.Problem(2, 32, torch.from_numpy(p.v.reshape(-1)).to(dev))
+    ft = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    counts = []
+    for prec, dt in ((lsp.LSP_FP64, torch.float64), (lsp.LSP_FP32_REFINE, torch.float32)):
+        P = torch.empty(N * m, dtype=dt, device=dev)
+        prob.stencil_setup(p.t, p.num_shifts, P, precision=prec)
+        solve = lsp.host_lu_solver(P.cpu().numpy().reshape(N, m), 2, 32, p.t)
+        ut = torch.zeros_like(ft)
+        code, iters, relres = prob.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=200)
+        assert code == lsp.LSP_OK and relres <= 1e-8
+        counts.append(iters)
+    print(f"[gmres fp32 rows] iterations fp64 {counts[0]} fp32 {counts[1]}", flush=True)
+    assert abs(counts[0] - counts[1]) <= 1
+
+
 # ------------------------------------------------------------- C-apply -----
 @pytest.mark.parametrize("d,n,t,nS", [(2, 32, 1, 2), (2, 64, 2, 4), (3, 16, 1, 4), (2, 256, 2, 16)])
 def test_c_apply_matches_oracle(torch_dev, d, n, t, nS):
