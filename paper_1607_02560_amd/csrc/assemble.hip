@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   __shared__ double halo[PL * HR * HC];
   __shared__ double sS[lsp::kMaxShifts];
   __shared__ int sidx[TR * TW];
+  __shared__ int soff[M];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
   const int c0 = blockIdx.x * TW;
@@ -47,6 +48,13 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   const int mask = n - 1;
 
   for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  for (int a = tid; a < M; a += 256) {
+    if constexpr (D == 3) {
+      soff[a] = ((a / (W * W)) * HR + (a / W) % W) * HC + a % W;
+    } else {
+      soff[a] = (a / W) * HC + a % W;
+    }
+  }
   for (int e = tid; e < PL * HR * HC; e += 256) {
     const int hc = e % HC;
     const int hr = (e / HC) % HR;
@@ -76,43 +84,48 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   }
   __syncthreads();
 
-  // VEC entries per 16-byte store: 2 doubles or 4 floats (TW is a multiple of 4)
+  // VEC entries per 16-byte store: 2 doubles or 4 floats (TW is a multiple of 4).
+  // Thread k starts at entry VEC k of the row span and steps by STEP entries;
+  // its (point p, offset a) advances by (STEP / M, STEP % M) with a carry, and
+  // within a store a advances by one, so no entry needs a division. soff[a]
+  // is the halo position of offset a relative to the point's (0, .., 0) corner.
+  static_assert(TR == 1, "single-row tiles");
   constexpr int VEC = 16 / (int)sizeof(PT);
   constexpr int SPAN = TW * M;
-  constexpr int TOTAL = TR * SPAN;
+  constexpr int STEP = VEC * 256;
+  constexpr int DP = STEP / M, DA = STEP % M;
   static_assert(SPAN % VEC == 0, "whole stores per row span");
-  for (int pos = VEC * tid; pos < TOTAL; pos += VEC * 256) {
-    const int r = pos / SPAN;
-    const int e = pos - r * SPAN;
+  int p = (VEC * tid) / M;
+  int a = VEC * tid - p * M;
+  const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0) * n + c0) * M)
+                                   : (((int64_t)r0 * n + c0) * M);
+  for (int e = VEC * tid; e < SPAN; e += STEP) {
     double outv[VEC];
+    int pp = p, aa = a;
 #pragma unroll
     for (int h = 0; h < VEC; ++h) {
-      const int eh = e + h;
-      const int p = eh / M;
-      const int a = eh - p * M;
-      const int id = sidx[r * TW + p];
+      const int id = sidx[pp];
       const double s = sS[id];
-      const double2 ac = actab[id * M + a];
-      int hp = 0, hr, hc;
-      if constexpr (D == 3) {
-        hp = a / (W * W);
-        hr = r + (a / W) % W;
-        hc = p + a % W;
-      } else {
-        hr = r + a / W;
-        hc = p + a % W;
-      }
-      const double va = halo[(hp * HR + hr) * HC + hc];
+      const double2 ac = actab[id * M + aa];
+      const double va = halo[pp + soff[aa]];
       outv[h] = ac.x + ac.y * (va - s);
+      if (++aa == M) {
+        aa = 0;
+        ++pp;
+      }
     }
-    const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0 + r) * n + c0) * M)
-                                     : (((int64_t)(r0 + r) * n + c0) * M);
     if constexpr (VEC == 2) {
       reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(outv[0], outv[1]);
     } else {
       // FP32 storage: each entry is the FP64 value rounded once to nearest
       reinterpret_cast<float4*>(P + rowbase)[e >> 2] =
           make_float4((float)outv[0], (float)outv[1], (float)outv[2], (float)outv[3]);
+    }
+    p += DP;
+    a += DA;
+    if (a >= M) {
+      a -= M;
+      ++p;
     }
   }
 }
