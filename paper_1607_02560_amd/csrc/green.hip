@@ -61,6 +61,14 @@ template <int W, int U, bool MASKED>
 __device__ __forceinline__ void green_terms(const double* __restrict__ cws, int kd0, int K2o,
                                             int kk, bool valid, double s, double* tg,
                                             double* tq) {
+  // all cosine values of the U terms are read before any arithmetic, so the
+  // LDS reads overlap each other and the reciprocals
+  double c[U][W];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) c[u][j] = cws[u * W + j];
+  }
   double r[U], r2[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -77,11 +85,10 @@ __device__ __forceinline__ void green_terms(const double* __restrict__ cws, int 
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const double* c = cws + u * W;
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-      tg[j] = fma(c[j], r[u], tg[j]);
-      tq[j] = fma(c[j], r2[u], tq[j]);
+      tg[j] = fma(c[u][j], r[u], tg[j]);
+      tq[j] = fma(c[u][j], r2[u], tq[j]);
     }
   }
 }
