@@ -12,7 +12,15 @@ synchronisations. ps_apply bandwidth is algorithmic bytes / mean apply time.
 The roofline of the dominant kernel (the per-point assembly) uses its average
 duration from per-stage HIP events that the library records on its stream.
 
+A second section compares the learned-stencil setup (a BF16 surrogate network
+beside the method, with exact fallback) with the exact setup on the 3D
+Helmholtz workload n = 64, t = 1, |S| = 16: the network is trained on the GPU
+on 200,000 exact rows of other fields (seeds 1..8), both setups are timed on
+the evaluation field (seed 0), and GMRES(40) iteration counts to 1e-8 are
+compared on the same kind of field at n = 16, where the host LU of P is cheap.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-learned] [--train-steps S]
     python bench.py --copy-probe MiB   # plain device copy of a known size, for
                                        # scaling hardware byte counters
 """
@@ -66,6 +74,108 @@ def algorithmic_bytes(N, m):
     return {"assemble": N * (8 + 8 * m + 4), "setup": N * (8 + 8 * m + 4), "apply": N * 40}
 
 
+def timed(stream, fn, reps):
+    """Mean device time of fn over reps calls, two events on the stream."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def learned_vs_exact(dev, stream, reps, train_steps, threshold=1e-3):
+    """The learned-stencil setup against the exact setup (3D Helmholtz, t = 1)."""
+    import numpy as np
+    import torch
+    from paper_1607_02560_amd import lsp
+    from paper_1607_02560_amd import surrogate as SG
+    from paper_1607_02560_amd import workloads as W
+    n, t, nS, batch = 64, 1, 16, 8192
+    m = (2 * t + 1) ** 3
+    print("[bench] learned: gathering 200k exact training rows (seeds 1..8)", file=sys.stderr,
+          flush=True)
+    fields = [W.helm3d_random(n, seed=s).v for s in range(1, 9)]
+    t0 = time.perf_counter()
+    X, T = SG.gather_rows(fields, t, nS, 25000, seed=100, device=dev)
+    torch.cuda.synchronize()
+    t_gather = time.perf_counter() - t0
+    net = SG.make_mlp(3, t, seed=101, batch_rows=batch)
+    net.fit_normalisation(X, T)
+    print(f"[bench] learned: training {train_steps} Adam steps of {batch} rows", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    hist = SG.train(net, X, T, train_steps, batch, 3e-3, seed=102,
+                    report_every=max(train_steps // 4, 1), lr_final=2e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    N = n ** 3
+    # inference copy of the trained network, one batch per setup
+    inf = lsp.MLP(m + 1, SG.HIDDEN, 2 * m, N)
+    inf.set_params(net.get_params())
+    inf.set_normalisation(*net.get_normalisation())
+    ev = W.helm3d_random(n, seed=0)
+    prob = lsp.Problem(3, n, torch.from_numpy(ev.v.reshape(-1)).to(dev))
+    P = torch.empty(N * m, dtype=torch.float64, device=dev)
+    idx = torch.empty(N, dtype=torch.int32, device=dev)
+    fb = torch.empty(N, dtype=torch.int32, device=dev)
+    exact = lambda: prob.stencil_setup(t, nS, P, idx)
+    nf = [0]
+
+    def learned():
+        nf[0] = prob.stencil_setup_learned(inf, t, nS, threshold, P, fb)
+
+    for _ in range(3):
+        exact()
+        learned()
+    t_exact = timed(stream, exact, reps)
+    t_learned = timed(stream, learned, reps)
+    prob.close()
+    # GMRES(40) to 1e-8 on an n = 16 field of the same kind
+    print("[bench] learned: GMRES comparison at n=16", file=sys.stderr, flush=True)
+    ns = 16
+    small = W.helm3d_random(ns, seed=0)
+    Ns = ns ** 3
+    probs = lsp.Problem(3, ns, torch.from_numpy(small.v.reshape(-1)).to(dev))
+    ft = torch.from_numpy(small.f.reshape(-1)).to(dev)
+    Ps = torch.empty(Ns * m, dtype=torch.float64, device=dev)
+    fbs = torch.empty(Ns, dtype=torch.int32, device=dev)
+    gm = {}
+    for name in ("exact", "learned"):
+        if name == "exact":
+            probs.stencil_setup(t, small.num_shifts, Ps)
+            nfs = 0
+        else:
+            nfs = probs.stencil_setup_learned(inf, t, small.num_shifts, threshold, Ps, fbs)
+        solve = lsp.host_lu_solver(Ps.cpu().numpy().reshape(Ns, m), 3, ns, t)
+        ut = torch.zeros_like(ft)
+        code, iters, relres = probs.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=400)
+        gm[name] = {"iterations": iters, "relres": relres, "status": code, "fallback_rows": nfs}
+    probs.close()
+    net.close()
+    inf.close()
+    return {
+        "workload": f"3D Helmholtz, smooth random c in [0.8,1.2], n={n} (N={N}), t={t} "
+                    f"(3x3x3 stencils), |S|={nS}, evaluation seed 0",
+        "network": f"{m + 1}->{SG.HIDDEN}->{SG.HIDDEN}->{2 * m} SiLU, BF16 MFMA, FP32 accumulation",
+        "training": {"rows": int(X.shape[0]), "seeds": "1..8", "steps": train_steps,
+                     "batch": batch, "loss_by_step": [[int(a), float(b)] for a, b in hist],
+                     "gather_s": t_gather, "train_s": t_train,
+                     "samples_per_s": train_steps * batch / t_train},
+        "threshold_excess": threshold,
+        "exact_setup_ms": t_exact * 1e3,
+        "learned_setup_ms": t_learned * 1e3,
+        "learned_over_exact_time": t_learned / t_exact,
+        "fallback_rows": nf[0], "fallback_frac": nf[0] / N,
+        "gmres_n16": gm,
+        "gmres_iterations_equal_within_1": abs(gm["exact"]["iterations"]
+                                               - gm["learned"]["iterations"]) <= 1,
+    }
+
+
 def cpu_baseline(p):
     """The FP64 oracle timed on this host: one full setup of the same workload
     (the sample) and 10 applies. numpy's FFT runs on one thread."""
@@ -96,6 +206,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-versus-exact setup section")
+    ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run 5 device-to-device copies of MiB mebibytes and exit")
     args = ap.parse_args()
@@ -141,17 +254,6 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
 
-    def timed(fn, reps):
-        """Mean device time of fn over reps calls, two events on the stream."""
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            fn()
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) * 1e-3 / reps
-
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -162,14 +264,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # setup alone and apply alone, K calls each
-    t_setup = timed(lambda: prob.stencil_setup(t, p.num_shifts, P, idx), args.steps)
-    t_apply = timed(lambda: prob.ps_apply(u, y), args.steps)
+    t_setup = timed(stream, lambda: prob.stencil_setup(t, p.num_shifts, P, idx), args.steps)
+    t_apply = timed(stream, lambda: prob.ps_apply(u, y), args.steps)
     # the FP32-storage form: same FP64 setup, P rows rounded to float32
     P32 = torch.empty(N * m, dtype=torch.float32, device=dev)
     setup32 = lambda: prob.stencil_setup(t, p.num_shifts, P32, idx, precision=lsp.LSP_FP32_REFINE)
     for _ in range(args.warmup):
         setup32()
-    t_setup32 = timed(setup32, args.steps)
+    t_setup32 = timed(stream, setup32, args.steps)
     del P32
     # per-stage HIP events recorded by the library on its stream (direct
     # launches): the dominant kernel's average duration for the roofline
@@ -223,10 +325,13 @@ def main():
                               "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
                               "bytes_per_call": nb["apply"]},
     }
+    prob.close()
+    del P, idx
+    if not args.no_learned:
+        out["learned_vs_exact"] = learned_vs_exact(dev, stream, args.steps, args.train_steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
-    prob.close()
     print(json.dumps(out))
 
 

@@ -198,6 +198,90 @@ int lsp_stencil_size(const lsp_problem* p);
  */
 int lsp_export_pattern(int d, int n, int t, int64_t* col_host);
 
+/* ------------------------------------------------------------------------
+ * Learned stencils (a surrogate beside the method; not part of the paper).
+ * A network with two hidden SiLU layers maps the m + 1 features of a grid
+ * point (h^2 v_j and h^2 v[j + a] for a in mu_0^t, h = 1/n) to its 2m rows
+ * (the P row of Sec. 4.1 and the C row of its shift, eq. (PC), times |s_j|).
+ * Training and inference run in hand-written BF16 MFMA kernels with FP32
+ * accumulation and FP32 master weights (Adam). Inputs and targets are
+ * standardised per feature; the loss is the mean squared error of the
+ * standardised outputs.
+ * ------------------------------------------------------------------------ */
+typedef struct lsp_mlp lsp_mlp;
+
+/* Create a network with n_in inputs, n_hidden units per hidden layer (a
+ * multiple of 16) and n_out outputs, taking batches of up to batch_rows
+ * rows, on a HIP stream (NULL = default). Weights start at zero and the
+ * standardisation at (0, 1): set both before use. */
+int lsp_mlp_create(int n_in, int n_hidden, int n_out, int batch_rows, void* stream,
+                   lsp_mlp** out);
+void lsp_mlp_destroy(lsp_mlp* q);
+
+/* Number of parameters: n_hidden (n_in + n_hidden + n_out + 2) + n_out. */
+int lsp_mlp_num_params(const lsp_mlp* q);
+
+/* Host FP32 parameters in the order W1 [n_hidden][n_in], b1, W2
+ * [n_hidden][n_hidden], b2, W3 [n_out][n_hidden], b3 (row-major). Setting
+ * them also resets the Adam state. */
+int lsp_mlp_set_params(lsp_mlp* q, const float* params_host);
+int lsp_mlp_get_params(lsp_mlp* q, float* params_host);
+
+/* Standardisation, host FP32: mu_x [n_in], sd_x [n_in], mu_y [n_out],
+ * sd_y [n_out] (deviations > 0). */
+int lsp_mlp_set_normalisation(lsp_mlp* q, const float* norm_host);
+int lsp_mlp_get_normalisation(lsp_mlp* q, float* norm_host);
+
+/* Set the standardisation to the column means and deviations of X_dev
+ * [rows][n_in] and T_dev [rows][n_out] (device FP32). */
+int lsp_mlp_fit_normalisation(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows);
+
+/* Y_dev [rows][n_out] = de-standardised outputs for X_dev [rows][n_in]
+ * (device FP32), rows <= batch_rows. Asynchronous. */
+int lsp_mlp_forward(lsp_mlp* q, const float* X_dev, int rows, float* Y_dev);
+
+/* Loss and gradients of one batch without updating: grad_host (may be NULL)
+ * receives the gradients in the parameter order above, loss_host the loss.
+ * Synchronous. */
+int lsp_mlp_loss_grad(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows,
+                      float* grad_host, double* loss_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on a batch
+ * of rows <= batch_rows; loss_host (may be NULL) receives the batch loss
+ * before the step (synchronises when given). */
+int lsp_mlp_train_step(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows, float lr,
+                       double* loss_host);
+
+/* Training rows of the points points_dev [count] (device int64 flat indices)
+ * from a completed exact FP64 setup of p whose P rows are P_dev [N*m]:
+ * X_dev [count][m+1] features, T_dev [count][2m] targets (device FP32).
+ * Indices outside [0, N) give rows of NaN. Returns LSP_ESTATE without a
+ * completed exact setup. */
+int lsp_training_rows(lsp_problem* p, const double* P_dev, const int64_t* points_dev,
+                      int count, float* X_dev, float* T_dev);
+
+/* Learned setup: the shift tables of Sec. 4.1-4.2 as in lsp_stencil_setup,
+ * then the network's P and C rows for every point, each checked with the
+ * exact Gram matrices of its shift: with q = p - c (v[mu_j] - s_j),
+ * rho = sqrt(q^T M q / q^T A1 q) (M = A1 - A2, eq. (A)) is the fraction of
+ * the row of Q G that the truncation to mu drops (Sec. 3). The exact stencil
+ * itself drops rho*(s) > 0 (about 0.05 for d = 3, t = 1), so the test is on
+ * the excess: rows with rho > rho*(s_j) + threshold take the exact P and C
+ * rows (fallback_dev[j] = 1).
+ *   P_dev         output, N*m float64 (layout of lsp_stencil_setup).
+ *   fallback_dev  output, N int32 (1 = exact row used).
+ *   n_fallback_host  receives the number of fallback rows (may be NULL).
+ * The per-point C rows stay with the problem; lsp_c_apply and
+ * lsp_precond_solve use them until the next setup. The network's kernels
+ * run on the problem's stream (work pending on the network's own stream is
+ * waited for first); calls that use one network or one problem at the same
+ * time from several threads race. Errors: LSP_EINVAL (NULL pointer,
+ * threshold < 0 or NaN, a network without m + 1 inputs and 2m outputs, the
+ * sizes of lsp_stencil_setup), LSP_ENOMEM, LSP_EHIP. Synchronous. */
+int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shifts,
+                              double threshold, double* P_dev, int32_t* fallback_dev,
+                              int* n_fallback_host);
+
 #ifdef __cplusplus
 }
 #endif

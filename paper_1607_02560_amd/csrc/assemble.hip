@@ -133,7 +133,8 @@ __global__ __launch_bounds__(256) void assemble_kernel(
 // --------------------------------------------------------------------------
 // b2: z = C r, (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n] (eq. PC), complex r.
 // Same tiling as assemble_kernel; s_j is recomputed from v and S exactly as
-// the setup assigned it, so no per-point state is kept between calls.
+// the setup assigned it, so no per-point state is kept between calls. After a
+// learned setup the C rows are per point (Crows [N][m]) instead.
 // --------------------------------------------------------------------------
 template <int D, int W, int TR, int TW>
 __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict__ rvec,
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
                                                       const double* __restrict__ S,
                                                       const int* __restrict__ nS_ptr,
                                                       const double* __restrict__ Ctab,
+                                                      const double* __restrict__ Crows,
                                                       double2* __restrict__ z) {
   constexpr int t = (W - 1) / 2;
   constexpr int M = Pow<D, W>::v;
@@ -176,8 +178,13 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
     const int r = pt / TW, c = pt % TW;
     const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
                                : ((int64_t)(r0 + r) * n + c0 + c);
-    const int id = nearest_shift(sS, nS, v[g]);
-    const double* crow = Ctab + (int64_t)id * M;
+    const double* crow;
+    if (Crows) {
+      crow = Crows + g * M;  // per-point rows of a learned setup
+    } else {
+      const int id = nearest_shift(sS, nS, v[g]);
+      crow = Ctab + (int64_t)id * M;
+    }
     double zr = 0.0, zi = 0.0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -229,7 +236,7 @@ hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
   dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
   hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream,
                      reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS, p->ws.Ctab,
-                     reinterpret_cast<double2*>(z));
+                     p->learned ? p->c_rows : nullptr, reinterpret_cast<double2*>(z));
   return hipGetLastError();
 }
 

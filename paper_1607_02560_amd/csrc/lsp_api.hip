@@ -353,6 +353,8 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->tw);
   dfree(p->cosT);
   dfree(p->green_units);
+  dfree(p->c_rows);
+  dfree(p->learn_buf);
   dfree(p->flag);
   drop_graph(p->g_setup);
   drop_graph(p->g_apply);
@@ -399,12 +401,12 @@ int lsp_default_num_shifts(int d, int n) {
   return s < 1 ? 1 : s;
 }
 
-int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
-                      int32_t* idx_dev) {
-  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
-  if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
-  if (precision != LSP_FP64 && precision != LSP_FP32_REFINE)
-    return lsp::set_error(LSP_EINVAL, "unsupported precision");
+namespace {
+
+// Validation, workspaces and the cosine table shared by the exact and the
+// learned setup; num_shifts is replaced by the effective request.
+int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
+  int num_shifts = *num_shifts_io;
   if (t < 1) return lsp::set_error(LSP_EINVAL, "t must be >= 1");
   const int W = 2 * t + 1;
   int m = 1;
@@ -429,6 +431,21 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
   p->m = m;
   p->num_shifts = num_shifts;
   p->have_setup = false;
+  p->learned = false;
+  *num_shifts_io = num_shifts;
+  return LSP_OK;
+}
+
+}  // namespace
+
+int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
+                      int32_t* idx_dev) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
+  if (precision != LSP_FP64 && precision != LSP_FP32_REFINE)
+    return lsp::set_error(LSP_EINVAL, "unsupported precision");
+  int rc = prepare_setup(p, t, &num_shifts);
+  if (rc) return rc;
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
@@ -456,6 +473,88 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
   const hipError_t e = run_graph(p, p->g_setup, key, launch);
   if (e != hipSuccess) return lsp::hip_check(e, "stencil setup launch");
   p->have_setup = true;
+  return LSP_OK;
+}
+
+int lsp_training_rows(lsp_problem* p, const double* P_dev, const int64_t* points_dev,
+                      int count, float* X_dev, float* T_dev) {
+  if (!p || !P_dev || !points_dev || !X_dev || !T_dev)
+    return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (!p->have_setup || p->learned)
+    return lsp::set_error(LSP_ESTATE, "training rows need a completed exact FP64 setup");
+  if (count < 1) return lsp::set_error(LSP_EINVAL, "count must be >= 1");
+  hipError_t e = lsp::launch_features(p, points_dev, 0, count, X_dev);
+  if (e == hipSuccess) e = lsp::launch_targets(p, P_dev, points_dev, count, T_dev);
+  return lsp::hip_check(e, "training rows");
+}
+
+int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shifts,
+                              double threshold, double* P_dev, int32_t* fallback_dev,
+                              int* n_fallback_host) {
+  if (!p || !mlp || !P_dev || !fallback_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (!(threshold >= 0.0)) return lsp::set_error(LSP_EINVAL, "threshold must be >= 0");
+  int rc = prepare_setup(p, t, &num_shifts);
+  if (rc) return rc;
+  const int m = p->m;
+  if (lsp::mlp_inputs(mlp) != m + 1 || lsp::mlp_outputs(mlp) != 2 * m)
+    return lsp::set_error(LSP_EINVAL, "the surrogate needs m + 1 inputs and 2m outputs");
+  // per-point C rows and the chunk buffers of the inference
+  const size_t need = (size_t)p->N * m;
+  if (p->c_rows_cap < need) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(p->c_rows);
+    p->c_rows_cap = 0;
+    if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "learned C rows"))) return rc;
+    p->c_rows_cap = need;
+  }
+  // one buffer: rho*(s) [num_shifts], the fallback count, inputs [B][m+1] and
+  // outputs [B][2m] of one chunk (each part 256-byte aligned)
+  const int B = lsp::mlp_batch_rows(mlp);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t off_nf = up(sizeof(double) * num_shifts);
+  const size_t off_x = off_nf + 256;
+  const size_t off_y = off_x + up(sizeof(float) * (size_t)B * (m + 1));
+  const size_t bytes = off_y + up(sizeof(float) * (size_t)B * 2 * m);
+  if (p->learn_cap < bytes) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(p->learn_buf);
+    p->learn_cap = 0;
+    if ((rc = dalloc((void**)&p->learn_buf, bytes, "learned-setup buffers"))) return rc;
+    p->learn_cap = bytes;
+  }
+  double* rho_star = reinterpret_cast<double*>(p->learn_buf);
+  int* nfall = reinterpret_cast<int*>(p->learn_buf + off_nf);
+  float* X = reinterpret_cast<float*>(p->learn_buf + off_x);
+  float* Y = reinterpret_cast<float*>(p->learn_buf + off_y);
+  // the network's kernels run on the problem's stream below; work queued on
+  // the network's own stream must be finished first
+  if (lsp::mlp_stream(mlp) != p->stream) {
+    const hipError_t es = hipStreamSynchronize(lsp::mlp_stream(mlp));
+    if (es != hipSuccess) return lsp::hip_check(es, "surrogate stream");
+  }
+  hipError_t e = hipMemsetAsync(nfall, 0, sizeof(int), p->stream);
+  // exact tables (shift list, Green's sums, Gram matrices, null vectors)
+  int blocks = 0;
+  if (e == hipSuccess) e = lsp::launch_minmax(p);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts, &blocks);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks);
+  if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star);
+  // learned rows in chunks of B points, each checked against the exact tables
+  for (int64_t j0 = 0; e == hipSuccess && j0 < p->N; j0 += B) {
+    const int rows = (int)std::min<int64_t>(B, p->N - j0);
+    e = lsp::launch_features(p, nullptr, j0, rows, X);
+    if (e == hipSuccess) e = lsp::mlp_forward_raw(mlp, X, rows, Y, p->stream);
+    if (e == hipSuccess)
+      e = lsp::launch_learned_rows(p, rho_star, Y, j0, rows, threshold, P_dev, p->c_rows,
+                                   fallback_dev, nfall);
+  }
+  int nf = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nf, nfall, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "learned setup");
+  if (n_fallback_host) *n_fallback_host = nf;
+  p->have_setup = true;
+  p->learned = true;
   return LSP_OK;
 }
 

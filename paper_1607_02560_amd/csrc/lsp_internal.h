@@ -64,6 +64,13 @@ struct lsp_problem {
   int m = 0;
   int num_shifts = 0;         // requested |S| of the last setup
   bool have_setup = false;
+  // learned setup: per-point C rows [N][m] (the exact setup uses the per-shift
+  // table instead); c_apply reads them while `learned` is set
+  bool learned = false;
+  double* c_rows = nullptr;
+  size_t c_rows_cap = 0;      // doubles
+  char* learn_buf = nullptr;  // rho*(s) per shift, fallback count, network in/out chunks
+  size_t learn_cap = 0;       // bytes
   lsp::Workspace ws;
   // HIP graphs of the setup and apply launch sequences, replayed while the
   // arguments and workspaces they captured are unchanged
@@ -119,5 +126,20 @@ hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks);
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // preconditioner halves and Krylov helpers
 hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
+// surrogate (mlp.hip)
+hipError_t mlp_forward_raw(lsp_mlp* q, const float* X, int rows, float* Y, hipStream_t s);
+hipStream_t mlp_stream(const lsp_mlp* q);
+int mlp_batch_rows(const lsp_mlp* q);
+int mlp_inputs(const lsp_mlp* q);
+int mlp_outputs(const lsp_mlp* q);
+hipError_t launch_features(const lsp_problem* p, const int64_t* points, int64_t j0, int rows,
+                           float* X);
+hipError_t launch_targets(const lsp_problem* p, const double* P, const int64_t* points, int rows,
+                          float* T);
+// rho*(s) = sqrt(alpha^T M alpha / alpha^T A1 alpha) of every shift's exact stencil
+hipError_t launch_rho_star(const lsp_problem* p, double* rho_star);
+hipError_t launch_learned_rows(const lsp_problem* p, const double* rho_star, const float* Y,
+                               int64_t j0, int rows, double thr, double* P, double* Crows,
+                               int32_t* fallback, int* nfall);
 
 }  // namespace lsp

@@ -1,0 +1,836 @@
+// Learned-stencil surrogate: a 2-hidden-layer SiLU network mapping the local
+// potential patch of a grid point to its P and C rows, trained and evaluated
+// with hand-written BF16 MFMA kernels (FP32 accumulation, FP32 master weights
+// and Adam state), and the learned setup that checks every predicted row with
+// the exact Gram matrices of eq. (A) and falls back to the exact row where the
+// check fails. The surrogate is not part of the paper; its rows feed the same
+// preconditioner P^-1 C of eq. (PC).
+//
+// Network (per point): x (n_in raw features) -> standardise -> z1 = W1 x + b1,
+// a1 = silu(z1) -> z2 = W2 a1 + b2, a2 = silu(z2) -> y = W3 a2 + b3 ->
+// de-standardise. Loss: mean squared error of y against standardised targets.
+//
+// Device layouts (row-major, padded so that every GEMM dimension is a
+// multiple of 16; padded weights and biases stay zero because their
+// gradients are zero):
+//   W1 [H][Ip], b1 [H], W2 [H][H], b2 [H], W3 [Op][H], b3 [Op]
+//   activations [rows][H] (FP32 pre-activations, BF16 post-activations),
+//   inputs [rows][Ip] BF16, outputs [rows][Op] FP32.
+#include "setup_common.h"
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+
+// FP32 -> BF16 bits, round to nearest even (inputs are finite)
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (+ C[m][n] if accumulate), with
+// A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn] in BF16 and C in FP32.
+// M, N, K are multiples of 16. Four waves per block, one 16x16 tile each
+// (2 x 2 tiles per block); one v_mfma_f32_16x16x16bf16 per 16 values of k.
+// MFMA operand layout: lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
+// and D[4(l/16)+i][l%16], i = 0..3.
+__global__ __launch_bounds__(kT) void gemm_bf16_kernel(
+    const unsigned short* __restrict__ A, int64_t sam, int64_t sak,
+    const unsigned short* __restrict__ B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
+    int N, int K, const float* __restrict__ bias, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
+  const int n0 = (blockIdx.x * 2 + (wave & 1)) * 16;
+  if (m0 >= M || n0 >= N) return;  // uniform over the wave; no barrier below
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const unsigned short* ap = A + (int64_t)(m0 + r) * sam;
+  const unsigned short* bp = B + (int64_t)(n0 + r) * sbn;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a, b;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = (short)ap[(int64_t)(k0 + kq + i) * sak];
+      b[i] = (short)bp[(int64_t)(k0 + kq + i) * sbk];
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = m0 + kq + i, col = n0 + r;
+    float val = acc[i];
+    if (bias) val += bias[col];
+    float* cp = C + (int64_t)row * ldc + col;
+    if (accumulate) val += *cp;
+    *cp = val;
+  }
+}
+
+// Xb[r][c] = bf16((X[r][c] - mu[c]) / sd[c]) for r < rows, c < cols; 0 in the
+// padding (rows .. rows_pad, cols .. ld).
+__global__ void standardise_kernel(const float* __restrict__ X, int rows, int rows_pad, int cols,
+                                   int ld, const float* __restrict__ mu,
+                                   const float* __restrict__ sd, unsigned short* Xb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows_pad * ld) return;
+  const int r = (int)(e / ld), c = (int)(e % ld);
+  float v = 0.f;
+  if (r < rows && c < cols) v = (X[(int64_t)r * cols + c] - mu[c]) / sd[c];
+  Xb[e] = to_bf16(v);
+}
+
+// A = bf16(silu(Z)) elementwise
+__global__ void silu_kernel(const float* __restrict__ Z, int64_t count, unsigned short* A) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const float z = Z[e];
+  A[e] = to_bf16(z * sigmoidf_(z));
+}
+
+// dZ = dA * silu'(Z), FP32 and BF16 copies; rows >= rows_valid are zero
+__global__ void silu_back_kernel(const float* __restrict__ dA, const float* __restrict__ Z,
+                                 int64_t count, int64_t valid, float* dZ, unsigned short* dZb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  float g = 0.f;
+  if (e < valid) {
+    const float z = Z[e];
+    const float s = sigmoidf_(z);
+    g = dA[e] * (s * (1.f + z * (1.f - s)));
+  }
+  dZ[e] = g;
+  dZb[e] = to_bf16(g);
+}
+
+// R = Y - (T - mu)/sd on the valid block [rows][cols] of Y [rows_pad][ld];
+// dY = scale R (FP32 and BF16; zero in the padding); per-block sums of R^2.
+__global__ void mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                int rows, int rows_pad, int cols, int ld,
+                                const float* __restrict__ mu, const float* __restrict__ sd,
+                                float scale, float* dY, unsigned short* dYb, double* loss_part) {
+  __shared__ double red[kT];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double r2 = 0.0;
+  if (e < (int64_t)rows_pad * ld) {
+    const int r = (int)(e / ld), c = (int)(e % ld);
+    float g = 0.f;
+    if (r < rows && c < cols) {
+      const float res = Y[e] - (T[(int64_t)r * cols + c] - mu[c]) / sd[c];
+      r2 = (double)res * res;
+      g = scale * res;
+    }
+    dY[e] = g;
+    dYb[e] = to_bf16(g);
+  }
+  red[threadIdx.x] = r2;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
+}
+
+// out[c] = sum over rows of D[r][c], one block per column, fixed order
+__global__ void colsum_kernel(const float* __restrict__ D, int rows, int ld, float* out) {
+  __shared__ float red[kT];
+  const int c = blockIdx.x;
+  float s = 0.f;
+  for (int r = threadIdx.x; r < rows; r += kT) s += D[(int64_t)r * ld + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// Adam (Kingma and Ba) with bias correction on every parameter; the BF16
+// copy of each weight is refreshed from the updated FP32 value.
+__global__ void adam_kernel(float* p, const float* __restrict__ g, float* m, float* v, int count,
+                            float lr, float b1, float b2, float eps, float c1, float c2,
+                            unsigned short* pb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const float gi = g[e];
+  const float mi = b1 * m[e] + (1.f - b1) * gi;
+  const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+  m[e] = mi;
+  v[e] = vi;
+  const float mh = mi / c1, vh = vi / c2;
+  const float pn = p[e] - lr * mh / (sqrtf(vh) + eps);
+  p[e] = pn;
+  pb[e] = to_bf16(pn);
+}
+
+__global__ void to_bf16_kernel(const float* __restrict__ x, int count, unsigned short* y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) y[e] = to_bf16(x[e]);
+}
+
+// per-column mean and deviation of X [rows][cols] (FP64 sums, fixed order)
+__global__ void moments_kernel(const float* __restrict__ X, int rows, int cols, float* mu,
+                               float* sd) {
+  __shared__ double s1[kT], s2[kT];
+  const int c = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int r = threadIdx.x; r < rows; r += kT) {
+    const double x = X[(int64_t)r * cols + c];
+    a += x;
+    b += x * x;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mean = s1[0] / rows;
+    const double var = s2[0] / rows - mean * mean;
+    mu[c] = (float)mean;
+    sd[c] = (var > 0.0) ? (float)sqrt(var) : 1.0f;
+  }
+}
+
+// Y [rows][cols] = mu + sd * Ys[r][c] (de-standardise the network outputs)
+__global__ void destandardise_kernel(const float* __restrict__ Ys, int rows, int cols, int ld,
+                                     const float* __restrict__ mu, const float* __restrict__ sd,
+                                     float* Y) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e % cols);
+  Y[e] = mu[c] + sd[c] * Ys[(int64_t)r * ld + c];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------------------
+// The network object
+// ----------------------------------------------------------------------------
+struct lsp_mlp {
+  int n_in = 0, n_hidden = 0, n_out = 0;
+  int Ip = 0, Op = 0;  // padded input and output widths
+  int bmax = 0;        // rows per batch (multiple of 16)
+  hipStream_t stream = nullptr;
+  size_t nparam = 0;   // padded parameter count
+  size_t off_W1 = 0, off_b1 = 0, off_W2 = 0, off_b2 = 0, off_W3 = 0, off_b3 = 0;
+  float* param = nullptr;  // FP32 master (padded layout)
+  float* grad = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  unsigned short* pbf = nullptr;  // BF16 copy of param
+  int adam_t = 0;
+  float* norm = nullptr;  // mu_x [n_in], sd_x [n_in], mu_y [n_out], sd_y [n_out]
+  // activations for bmax rows
+  unsigned short* Xb = nullptr;
+  float* Z1 = nullptr;
+  float* Z2 = nullptr;
+  unsigned short* A1b = nullptr;
+  unsigned short* A2b = nullptr;
+  float* Y = nullptr;
+  float* dY = nullptr;
+  unsigned short* dYb = nullptr;
+  float* dA = nullptr;
+  float* dZ = nullptr;
+  unsigned short* dZb = nullptr;
+  double* loss_part = nullptr;
+  double* loss_host = nullptr;  // pinned
+};
+
+namespace {
+
+template <typename T>
+int dalloc_(T** p, size_t n) {
+  if (hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) != hipSuccess)
+    return lsp::set_error(LSP_ENOMEM, "device allocation for the surrogate failed");
+  return LSP_OK;
+}
+
+template <typename T>
+void dfree_(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+inline int round16(int x) { return (x + 15) / 16 * 16; }
+
+inline unsigned blocks_for(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak,
+                const unsigned short* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
+                int N, int K, const float* bias, bool accumulate) {
+  dim3 grid((N + 31) / 32, (M + 31) / 32);
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M,
+                     N, K, bias, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+// forward pass of rows_pad rows of raw inputs X (rows valid) on stream s;
+// leaves Z1, A1b, Z2, A2b and the standardised outputs Y [rows_pad][Op]
+hipError_t forward(lsp_mlp* q, const float* X, int rows, int rows_pad, hipStream_t s) {
+  const int H = q->n_hidden;
+  const float* mu_x = q->norm;
+  const float* sd_x = q->norm + q->n_in;
+  hipLaunchKernelGGL(standardise_kernel, dim3(blocks_for((int64_t)rows_pad * q->Ip)), dim3(kT), 0,
+                     s, X, rows, rows_pad, q->n_in, q->Ip, mu_x, sd_x, q->Xb);
+  const unsigned short* W1 = q->pbf + q->off_W1;
+  const unsigned short* W2 = q->pbf + q->off_W2;
+  const unsigned short* W3 = q->pbf + q->off_W3;
+  hipError_t e;
+  // z1 = W1 x + b1: A(b, i) = Xb[b Ip + i], B(i, h) = W1[h Ip + i]
+  if ((e = gemm(s, q->Xb, q->Ip, 1, W1, 1, q->Ip, q->Z1, H, rows_pad, H, q->Ip,
+                q->param + q->off_b1, false)))
+    return e;
+  hipLaunchKernelGGL(silu_kernel, dim3(blocks_for((int64_t)rows_pad * H)), dim3(kT), 0, s, q->Z1,
+                     (int64_t)rows_pad * H, q->A1b);
+  if ((e = gemm(s, q->A1b, H, 1, W2, 1, H, q->Z2, H, rows_pad, H, H, q->param + q->off_b2, false)))
+    return e;
+  hipLaunchKernelGGL(silu_kernel, dim3(blocks_for((int64_t)rows_pad * H)), dim3(kT), 0, s, q->Z2,
+                     (int64_t)rows_pad * H, q->A2b);
+  if ((e = gemm(s, q->A2b, H, 1, W3, 1, H, q->Y, q->Op, rows_pad, q->Op, H, q->param + q->off_b3,
+                false)))
+    return e;
+  return hipGetLastError();
+}
+
+// loss and gradients of one batch (grad buffer overwritten); loss sums to loss_part
+hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nblk_loss) {
+  const int H = q->n_hidden;
+  hipStream_t s = q->stream;
+  const float* mu_y = q->norm + 2 * q->n_in;
+  const float* sd_y = mu_y + q->n_out;
+  const float scale = 2.0f / ((float)rows * (float)q->n_out);
+  const unsigned nb = blocks_for((int64_t)rows_pad * q->Op);
+  *nblk_loss = (int)nb;
+  hipLaunchKernelGGL(mse_grad_kernel, dim3(nb), dim3(kT), 0, s, q->Y, T, rows, rows_pad, q->n_out,
+                     q->Op, mu_y, sd_y, scale, q->dY, q->dYb, q->loss_part);
+  float* g = q->grad;
+  const unsigned short* W2 = q->pbf + q->off_W2;
+  const unsigned short* W3 = q->pbf + q->off_W3;
+  hipError_t e;
+  // gW3 [Op][H] = dY^T A2: A(o, b) = dYb[b Op + o], B(b, h) = A2b[b H + h]
+  if ((e = gemm(s, q->dYb, 1, q->Op, q->A2b, H, 1, g + q->off_W3, H, q->Op, H, rows_pad, nullptr,
+                false)))
+    return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(q->Op), dim3(kT), 0, s, q->dY, rows_pad, q->Op,
+                     g + q->off_b3);
+  // dA2 = dY W3: A(b, o) = dYb[b Op + o], B(o, h) = W3[o H + h]
+  if ((e = gemm(s, q->dYb, q->Op, 1, W3, H, 1, q->dA, H, rows_pad, H, q->Op, nullptr, false)))
+    return e;
+  const int64_t cnt = (int64_t)rows_pad * H, valid = (int64_t)rows * H;
+  hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z2, cnt,
+                     valid, q->dZ, q->dZb);
+  // gW2 [H][H] = dZ2^T A1
+  if ((e = gemm(s, q->dZb, 1, H, q->A1b, H, 1, g + q->off_W2, H, H, H, rows_pad, nullptr, false)))
+    return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b2);
+  // dA1 = dZ2 W2: B(h2, h1) = W2[h2 H + h1]
+  if ((e = gemm(s, q->dZb, H, 1, W2, H, 1, q->dA, H, rows_pad, H, H, nullptr, false))) return e;
+  hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z1, cnt,
+                     valid, q->dZ, q->dZb);
+  // gW1 [H][Ip] = dZ1^T Xb
+  if ((e = gemm(s, q->dZb, 1, H, q->Xb, q->Ip, 1, g + q->off_W1, q->Ip, H, q->Ip, rows_pad,
+                nullptr, false)))
+    return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b1);
+  return hipGetLastError();
+}
+
+int check_rows(const lsp_mlp* q, int rows) {
+  if (rows < 1 || rows > q->bmax)
+    return lsp::set_error(LSP_EINVAL, "rows must be in 1.." + std::to_string(q->bmax));
+  return LSP_OK;
+}
+
+double sum_loss(lsp_mlp* q, int nblk, int rows) {
+  (void)hipMemcpyAsync(q->loss_host, q->loss_part, sizeof(double) * nblk, hipMemcpyDeviceToHost,
+                       q->stream);
+  (void)hipStreamSynchronize(q->stream);
+  double s = 0.0;
+  for (int i = 0; i < nblk; ++i) s += q->loss_host[i];
+  return s / ((double)rows * q->n_out);
+}
+
+// host FP32 parameters in the unpadded order W1, b1, W2, b2, W3, b3 <-> padded device layout
+void pad_params(const lsp_mlp* q, const float* in, std::vector<float>& out) {
+  const int I = q->n_in, H = q->n_hidden, O = q->n_out;
+  out.assign(q->nparam, 0.f);
+  size_t k = 0;
+  for (int h = 0; h < H; ++h)
+    for (int i = 0; i < I; ++i) out[q->off_W1 + (size_t)h * q->Ip + i] = in[k++];
+  for (int h = 0; h < H; ++h) out[q->off_b1 + h] = in[k++];
+  for (int h = 0; h < H; ++h)
+    for (int i = 0; i < H; ++i) out[q->off_W2 + (size_t)h * H + i] = in[k++];
+  for (int h = 0; h < H; ++h) out[q->off_b2 + h] = in[k++];
+  for (int o = 0; o < O; ++o)
+    for (int h = 0; h < H; ++h) out[q->off_W3 + (size_t)o * H + h] = in[k++];
+  for (int o = 0; o < O; ++o) out[q->off_b3 + o] = in[k++];
+}
+
+void unpad_params(const lsp_mlp* q, const std::vector<float>& in, float* out) {
+  const int I = q->n_in, H = q->n_hidden, O = q->n_out;
+  size_t k = 0;
+  for (int h = 0; h < H; ++h)
+    for (int i = 0; i < I; ++i) out[k++] = in[q->off_W1 + (size_t)h * q->Ip + i];
+  for (int h = 0; h < H; ++h) out[k++] = in[q->off_b1 + h];
+  for (int h = 0; h < H; ++h)
+    for (int i = 0; i < H; ++i) out[k++] = in[q->off_W2 + (size_t)h * H + i];
+  for (int h = 0; h < H; ++h) out[k++] = in[q->off_b2 + h];
+  for (int o = 0; o < O; ++o)
+    for (int h = 0; h < H; ++h) out[k++] = in[q->off_W3 + (size_t)o * H + h];
+  for (int o = 0; o < O; ++o) out[k++] = in[q->off_b3 + o];
+}
+
+}  // namespace
+
+namespace lsp {
+
+hipError_t mlp_forward_raw(lsp_mlp* q, const float* X, int rows, float* Y, hipStream_t s) {
+  const int rp = round16(rows);
+  hipError_t e = forward(q, X, rows, rp, s);
+  if (e != hipSuccess) return e;
+  const float* mu_y = q->norm + 2 * q->n_in;
+  hipLaunchKernelGGL(destandardise_kernel, dim3(blocks_for((int64_t)rows * q->n_out)), dim3(kT), 0,
+                     s, q->Y, rows, q->n_out, q->Op, mu_y, mu_y + q->n_out, Y);
+  return hipGetLastError();
+}
+
+hipStream_t mlp_stream(const lsp_mlp* q) { return q->stream; }
+
+int mlp_batch_rows(const lsp_mlp* q) { return q->bmax; }
+int mlp_inputs(const lsp_mlp* q) { return q->n_in; }
+int mlp_outputs(const lsp_mlp* q) { return q->n_out; }
+
+}  // namespace lsp
+
+// ----------------------------------------------------------------------------
+// C ABI
+// ----------------------------------------------------------------------------
+extern "C" {
+
+int lsp_mlp_create(int n_in, int n_hidden, int n_out, int batch_rows, void* stream,
+                   lsp_mlp** out) {
+  if (!out) return lsp::set_error(LSP_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n_in < 1 || n_hidden < 16 || n_hidden % 16 || n_out < 1 || batch_rows < 16)
+    return lsp::set_error(LSP_EINVAL, "sizes: n_in, n_out >= 1, n_hidden a multiple of 16, "
+                                      "batch_rows >= 16");
+  lsp_mlp* q = new lsp_mlp();
+  q->n_in = n_in;
+  q->n_hidden = n_hidden;
+  q->n_out = n_out;
+  q->Ip = round16(n_in);
+  q->Op = round16(n_out);
+  q->bmax = round16(batch_rows);
+  q->stream = static_cast<hipStream_t>(stream);
+  const int H = n_hidden;
+  size_t o = 0;
+  q->off_W1 = o; o += (size_t)H * q->Ip;
+  q->off_b1 = o; o += H;
+  q->off_W2 = o; o += (size_t)H * H;
+  q->off_b2 = o; o += H;
+  q->off_W3 = o; o += (size_t)q->Op * H;
+  q->off_b3 = o; o += q->Op;
+  q->nparam = o;
+  const size_t B = q->bmax;
+  int rc = LSP_OK;
+  if ((rc = dalloc_(&q->param, o)) || (rc = dalloc_(&q->grad, o)) ||
+      (rc = dalloc_(&q->adam_m, o)) || (rc = dalloc_(&q->adam_v, o)) ||
+      (rc = dalloc_(&q->pbf, o)) || (rc = dalloc_(&q->norm, 2 * (size_t)(n_in + n_out))) ||
+      (rc = dalloc_(&q->Xb, B * q->Ip)) || (rc = dalloc_(&q->Z1, B * H)) ||
+      (rc = dalloc_(&q->Z2, B * H)) || (rc = dalloc_(&q->A1b, B * H)) ||
+      (rc = dalloc_(&q->A2b, B * H)) || (rc = dalloc_(&q->Y, B * q->Op)) ||
+      (rc = dalloc_(&q->dY, B * q->Op)) || (rc = dalloc_(&q->dYb, B * q->Op)) ||
+      (rc = dalloc_(&q->dA, B * H)) || (rc = dalloc_(&q->dZ, B * H)) ||
+      (rc = dalloc_(&q->dZb, B * H)) ||
+      (rc = dalloc_(&q->loss_part, B * q->Op / kT + 1))) {
+    lsp_mlp_destroy(q);
+    return rc;
+  }
+  if (hipHostMalloc((void**)&q->loss_host, sizeof(double) * (B * q->Op / kT + 1)) != hipSuccess) {
+    lsp_mlp_destroy(q);
+    return lsp::set_error(LSP_ENOMEM, "pinned host allocation failed");
+  }
+  (void)hipMemsetAsync(q->param, 0, sizeof(float) * o, q->stream);
+  (void)hipMemsetAsync(q->adam_m, 0, sizeof(float) * o, q->stream);
+  (void)hipMemsetAsync(q->adam_v, 0, sizeof(float) * o, q->stream);
+  (void)hipMemsetAsync(q->pbf, 0, sizeof(unsigned short) * o, q->stream);
+  std::vector<float> nrm(2 * (size_t)(n_in + n_out), 0.f);
+  for (int i = 0; i < n_in; ++i) nrm[n_in + i] = 1.f;
+  for (int i = 0; i < n_out; ++i) nrm[2 * n_in + n_out + i] = 1.f;
+  if (hipMemcpy(q->norm, nrm.data(), sizeof(float) * nrm.size(), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    lsp_mlp_destroy(q);
+    return lsp::set_error(LSP_EHIP, "upload of the standardisation failed");
+  }
+  *out = q;
+  return LSP_OK;
+}
+
+void lsp_mlp_destroy(lsp_mlp* q) {
+  if (!q) return;
+  (void)hipStreamSynchronize(q->stream);
+  dfree_(q->param); dfree_(q->grad); dfree_(q->adam_m); dfree_(q->adam_v); dfree_(q->pbf);
+  dfree_(q->norm); dfree_(q->Xb); dfree_(q->Z1); dfree_(q->Z2); dfree_(q->A1b); dfree_(q->A2b);
+  dfree_(q->Y); dfree_(q->dY); dfree_(q->dYb); dfree_(q->dA); dfree_(q->dZ); dfree_(q->dZb);
+  dfree_(q->loss_part);
+  if (q->loss_host) (void)hipHostFree(q->loss_host);
+  delete q;
+}
+
+int lsp_mlp_num_params(const lsp_mlp* q) {
+  if (!q) return 0;
+  return q->n_in * q->n_hidden + q->n_hidden + q->n_hidden * q->n_hidden + q->n_hidden +
+         q->n_out * q->n_hidden + q->n_out;
+}
+
+int lsp_mlp_set_params(lsp_mlp* q, const float* params_host) {
+  if (!q || !params_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  std::vector<float> pad;
+  pad_params(q, params_host, pad);
+  if (hipMemcpy(q->param, pad.data(), sizeof(float) * pad.size(), hipMemcpyHostToDevice) !=
+      hipSuccess)
+    return lsp::set_error(LSP_EHIP, "parameter upload failed");
+  hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for((int64_t)q->nparam)), dim3(kT), 0, q->stream,
+                     q->param, (int)q->nparam, q->pbf);
+  (void)hipMemsetAsync(q->adam_m, 0, sizeof(float) * q->nparam, q->stream);
+  (void)hipMemsetAsync(q->adam_v, 0, sizeof(float) * q->nparam, q->stream);
+  q->adam_t = 0;
+  return lsp::hip_check(hipStreamSynchronize(q->stream), "parameter upload");
+}
+
+int lsp_mlp_get_params(lsp_mlp* q, float* params_host) {
+  if (!q || !params_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  std::vector<float> pad(q->nparam);
+  (void)hipStreamSynchronize(q->stream);
+  if (hipMemcpy(pad.data(), q->param, sizeof(float) * pad.size(), hipMemcpyDeviceToHost) !=
+      hipSuccess)
+    return lsp::set_error(LSP_EHIP, "parameter download failed");
+  unpad_params(q, pad, params_host);
+  return LSP_OK;
+}
+
+int lsp_mlp_set_normalisation(lsp_mlp* q, const float* norm_host) {
+  if (!q || !norm_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  const size_t n = 2 * (size_t)(q->n_in + q->n_out);
+  for (size_t i = 0; i < (size_t)q->n_in; ++i)
+    if (!(norm_host[q->n_in + i] > 0.f)) return lsp::set_error(LSP_EINVAL, "deviation <= 0");
+  for (size_t i = 0; i < (size_t)q->n_out; ++i)
+    if (!(norm_host[2 * q->n_in + q->n_out + i] > 0.f))
+      return lsp::set_error(LSP_EINVAL, "deviation <= 0");
+  if (hipMemcpy(q->norm, norm_host, sizeof(float) * n, hipMemcpyHostToDevice) != hipSuccess)
+    return lsp::set_error(LSP_EHIP, "standardisation upload failed");
+  return LSP_OK;
+}
+
+int lsp_mlp_get_normalisation(lsp_mlp* q, float* norm_host) {
+  if (!q || !norm_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  (void)hipStreamSynchronize(q->stream);
+  if (hipMemcpy(norm_host, q->norm, sizeof(float) * 2 * (q->n_in + q->n_out),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return lsp::set_error(LSP_EHIP, "standardisation download failed");
+  return LSP_OK;
+}
+
+int lsp_mlp_fit_normalisation(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows) {
+  if (!q || !X_dev || !T_dev || rows < 2) return lsp::set_error(LSP_EINVAL, "bad argument");
+  hipLaunchKernelGGL(moments_kernel, dim3(q->n_in), dim3(kT), 0, q->stream, X_dev, rows, q->n_in,
+                     q->norm, q->norm + q->n_in);
+  hipLaunchKernelGGL(moments_kernel, dim3(q->n_out), dim3(kT), 0, q->stream, T_dev, rows,
+                     q->n_out, q->norm + 2 * q->n_in, q->norm + 2 * q->n_in + q->n_out);
+  return lsp::hip_check(hipGetLastError(), "normalisation fit");
+}
+
+int lsp_mlp_forward(lsp_mlp* q, const float* X_dev, int rows, float* Y_dev) {
+  if (!q || !X_dev || !Y_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  int rc = check_rows(q, rows);
+  if (rc) return rc;
+  return lsp::hip_check(lsp::mlp_forward_raw(q, X_dev, rows, Y_dev, q->stream),
+                        "surrogate forward");
+}
+
+int lsp_mlp_loss_grad(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows,
+                      float* grad_host, double* loss_host) {
+  if (!q || !X_dev || !T_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  int rc = check_rows(q, rows);
+  if (rc) return rc;
+  const int rp = round16(rows);
+  hipError_t e = forward(q, X_dev, rows, rp, q->stream);
+  int nblk = 0;
+  if (e == hipSuccess) e = backward(q, T_dev, rows, rp, &nblk);
+  if (e != hipSuccess) return lsp::hip_check(e, "surrogate gradient");
+  const double loss = sum_loss(q, nblk, rows);
+  if (loss_host) *loss_host = loss;
+  if (grad_host) {
+    std::vector<float> pad(q->nparam);
+    if (hipMemcpy(pad.data(), q->grad, sizeof(float) * pad.size(), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+      return lsp::set_error(LSP_EHIP, "gradient download failed");
+    unpad_params(q, pad, grad_host);
+  }
+  return LSP_OK;
+}
+
+int lsp_mlp_train_step(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows, float lr,
+                       double* loss_host) {
+  if (!q || !X_dev || !T_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (!(lr > 0.f)) return lsp::set_error(LSP_EINVAL, "lr must be > 0");
+  int rc = check_rows(q, rows);
+  if (rc) return rc;
+  const int rp = round16(rows);
+  hipError_t e = forward(q, X_dev, rows, rp, q->stream);
+  int nblk = 0;
+  if (e == hipSuccess) e = backward(q, T_dev, rows, rp, &nblk);
+  if (e != hipSuccess) return lsp::hip_check(e, "surrogate training step");
+  const float b1 = 0.9f, b2 = 0.999f;
+  q->adam_t += 1;
+  const float c1 = 1.f - powf(b1, (float)q->adam_t);
+  const float c2 = 1.f - powf(b2, (float)q->adam_t);
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for((int64_t)q->nparam)), dim3(kT), 0, q->stream,
+                     q->param, q->grad, q->adam_m, q->adam_v, (int)q->nparam, lr, b1, b2, 1e-8f,
+                     c1, c2, q->pbf);
+  if ((e = hipGetLastError()) != hipSuccess) return lsp::hip_check(e, "Adam step");
+  if (loss_host) *loss_host = sum_loss(q, nblk, rows);
+  return LSP_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// Rows of a problem: features, exact targets, learned rows with fallback
+// ----------------------------------------------------------------------------
+namespace {
+
+using lsp::nearest_shift;
+using lsp::Nbhd;
+using lsp::Pow;
+
+// flat index of the neighbour a of point j (periodic)
+template <int D, int W>
+__device__ __forceinline__ int64_t neighbour(int64_t j, int n, int a) {
+  using Nb = Nbhd<D, W>;
+  int64_t g = 0, rem = j, mul = 1;
+  int c[D];
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    c[i] = (int)(rem % n);
+    rem /= n;
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) c[i] = (c[i] + Nb::comp(a, i) + n) & (n - 1);
+#pragma unroll
+  for (int i = D - 1; i >= 0; --i) {
+    g += c[i] * mul;
+    mul *= n;
+  }
+  return g;
+}
+
+// X[r] = (h^2 v_j, h^2 v[j + a] for a in mu_0^t), j = points[r] (or j0 + r)
+// (an index outside [0, N) gives a row of NaN and reads nothing)
+template <int D, int W>
+__global__ void features_kernel(const double* __restrict__ v, int n, int64_t N,
+                                const int64_t* __restrict__ points, int64_t j0, int rows,
+                                double h2, float* X) {
+  constexpr int M = Pow<D, W>::v;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t j = points ? points[r] : j0 + r;
+  float* x = X + (int64_t)r * (M + 1);
+  if (j < 0 || j >= N) {
+    for (int a = 0; a <= M; ++a) x[a] = __int_as_float(0x7fc00000);
+    return;
+  }
+  x[0] = (float)(h2 * v[j]);
+#pragma unroll
+  for (int a = 0; a < M; ++a) x[1 + a] = (float)(h2 * v[neighbour<D, W>(j, n, a)]);
+}
+
+// T[r] = (P[j, a] for a, C_{s_j}[a] |s_j| for a), j = points[r] (an index
+// outside [0, N) gives a row of NaN and reads nothing)
+template <int D, int W>
+__global__ void targets_kernel(const double* __restrict__ P, const double* __restrict__ v,
+                               int64_t N, const double* __restrict__ S,
+                               const int* __restrict__ nS_ptr, const double* __restrict__ Ctab,
+                               const int64_t* __restrict__ points, int rows, float* T) {
+  constexpr int M = Pow<D, W>::v;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t j = points[r];
+  float* t = T + (int64_t)r * 2 * M;
+  if (j < 0 || j >= N) {
+    for (int a = 0; a < 2 * M; ++a) t[a] = __int_as_float(0x7fc00000);
+    return;
+  }
+  const int id = nearest_shift(S, *nS_ptr, v[j]);
+  const double as = fabs(S[id]);
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    t[a] = (float)P[j * M + a];
+    t[M + a] = (float)(Ctab[(int64_t)id * M + a] * as);
+  }
+}
+
+// q^T A1 q and q^T M q = q^T A1 q - |G q|^2 for a stencil q on mu_0^t, with
+// G[a][b] = g[|a - b|] and A1[a][b] = gam[|a - b|] (eq. A; tables at the
+// offsets [0, 2t]^d)
+template <int D, int W>
+__device__ __forceinline__ void gram_forms(const double* __restrict__ g,
+                                           const double* __restrict__ gm, const double* q,
+                                           double& qaq, double& qmq) {
+  using Nb = Nbhd<D, W>;
+  constexpr int M = Pow<D, W>::v;
+  double a1 = 0.0, gq2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double u = 0.0, w = 0.0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) {
+      const int k = Nb::diff_index(a, b);
+      u = fma(g[k], q[b], u);
+      w = fma(gm[k], q[b], w);
+    }
+    gq2 = fma(u, u, gq2);
+    a1 = fma(q[a], w, a1);
+  }
+  qaq = a1;
+  qmq = a1 - gq2;
+}
+
+// an entry alpha + C (v - s) of an exact row, rounded exactly as the exact
+// setup's assembly rounds it (product and sum rounded separately)
+__device__ __forceinline__ double exact_entry(double alpha, double c, double v_minus_s) {
+#pragma clang fp contract(off)
+  return alpha + c * v_minus_s;
+}
+
+// rho*(s) of the exact stencil alpha_s of every shift
+template <int D, int W>
+__global__ void rho_star_kernel(const double* __restrict__ gtab, const double* __restrict__ gamtab,
+                                const double2* __restrict__ actab, const int* __restrict__ nS_ptr,
+                                double* rho_star) {
+  constexpr int M = Pow<D, W>::v;
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= *nS_ptr) return;
+  double q[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) q[a] = actab[(int64_t)id * M + a].x;
+  double qaq, qmq;
+  gram_forms<D, W>(gtab + (int64_t)id * M, gamtab + (int64_t)id * M, q, qaq, qmq);
+  rho_star[id] = sqrt(fmax(qmq, 0.0) / qaq);
+}
+
+// Learned rows of points j0 .. j0+rows-1 from the de-standardised network
+// outputs Y [rows][2m]: p = Y[:m], c = Y[m:] / |s_j|, stencil
+// q = p - c (v[mu_j] - s_j) and rho = sqrt(q^T M q / q^T A1 q) (eq. A). Rows
+// with rho > rho*(s_j) + thr, where rho*(s_j) is the same quantity for the
+// exact stencil of the shift (or with a non-finite value), take the exact row
+// alpha + C (v[mu_j] - s_j) and C; fallback[j] records which.
+template <int D, int W>
+__global__ void learned_rows_kernel(const double* __restrict__ v, int n,
+                                    const double* __restrict__ S, const int* __restrict__ nS_ptr,
+                                    const double* __restrict__ gtab,
+                                    const double* __restrict__ gamtab,
+                                    const double2* __restrict__ actab,
+                                    const double* __restrict__ rho_star,
+                                    const float* __restrict__ Y, int64_t j0, int rows, double thr,
+                                    double* P, double* Crows, int32_t* fallback, int* nfall) {
+  constexpr int M = Pow<D, W>::v;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t j = j0 + r;
+  const int id = nearest_shift(S, *nS_ptr, v[j]);
+  const double s = S[id];
+  const double inv_as = 1.0 / fabs(s);
+  double vm[M], q[M], c[M];
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    vm[a] = v[neighbour<D, W>(j, n, a)] - s;
+    c[a] = (double)Y[(int64_t)r * 2 * M + M + a] * inv_as;
+    q[a] = (double)Y[(int64_t)r * 2 * M + a] - c[a] * vm[a];
+  }
+  double qaq, qmq;
+  gram_forms<D, W>(gtab + (int64_t)id * M, gamtab + (int64_t)id * M, q, qaq, qmq);
+  const double lim = rho_star[id] + thr;
+  const bool ok = (qaq > 0.0) && isfinite(qmq) && (qmq <= lim * lim * qaq);
+  const double2* act = actab + (int64_t)id * M;
+#pragma unroll
+  for (int a = 0; a < M; ++a) {
+    double pr, cr;
+    if (ok) {
+      cr = c[a];
+      pr = (double)Y[(int64_t)r * 2 * M + a];  // the learned P row
+    } else {
+      const double2 ac = act[a];
+      cr = ac.y;
+      pr = exact_entry(ac.x, ac.y, vm[a]);
+    }
+    P[j * M + a] = pr;
+    Crows[j * M + a] = cr;
+  }
+  fallback[j] = ok ? 0 : 1;
+  if (!ok) atomicAdd(nfall, 1);
+}
+
+}  // namespace
+
+namespace lsp {
+
+#define LSP_DW_DISPATCH(FN, ...)                                              \
+  do {                                                                        \
+    const int W_ = 2 * p->t + 1;                                              \
+    if (p->d == 2 && W_ == 3) { FN<2, 3><<<grid, blk, 0, p->stream>>>(__VA_ARGS__); } \
+    else if (p->d == 2 && W_ == 5) { FN<2, 5><<<grid, blk, 0, p->stream>>>(__VA_ARGS__); } \
+    else if (p->d == 2 && W_ == 7) { FN<2, 7><<<grid, blk, 0, p->stream>>>(__VA_ARGS__); } \
+    else if (p->d == 3 && W_ == 3) { FN<3, 3><<<grid, blk, 0, p->stream>>>(__VA_ARGS__); } \
+    else return hipErrorInvalidValue;                                         \
+  } while (0)
+
+hipError_t launch_features(const lsp_problem* p, const int64_t* points, int64_t j0, int rows,
+                           float* X) {
+  const dim3 grid(blocks_for(rows, 128)), blk(128);
+  const double h2 = 1.0 / ((double)p->n * p->n);
+  LSP_DW_DISPATCH(features_kernel, p->v, p->n, p->N, points, j0, rows, h2, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_targets(const lsp_problem* p, const double* P, const int64_t* points, int rows,
+                          float* T) {
+  const dim3 grid(blocks_for(rows, 128)), blk(128);
+  LSP_DW_DISPATCH(targets_kernel, P, p->v, p->N, p->ws.S, p->ws.nS, p->ws.Ctab, points, rows,
+                  T);
+  return hipGetLastError();
+}
+
+hipError_t launch_rho_star(const lsp_problem* p, double* rho_star) {
+  const dim3 grid(blocks_for(p->num_shifts, 64)), blk(64);
+  LSP_DW_DISPATCH(rho_star_kernel, p->ws.gtab, p->ws.gamtab,
+                  reinterpret_cast<const double2*>(p->ws.actab), p->ws.nS, rho_star);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_rows(const lsp_problem* p, const double* rho_star, const float* Y,
+                               int64_t j0, int rows, double thr, double* P, double* Crows,
+                               int32_t* fallback, int* nfall) {
+  const dim3 grid(blocks_for(rows, 64)), blk(64);
+  LSP_DW_DISPATCH(learned_rows_kernel, p->v, p->n, p->ws.S, p->ws.nS, p->ws.gtab, p->ws.gamtab,
+                  reinterpret_cast<const double2*>(p->ws.actab), rho_star, Y, j0, rows, thr, P,
+                  Crows, fallback, nfall);
+  return hipGetLastError();
+}
+
+#undef LSP_DW_DISPATCH
+
+}  // namespace lsp

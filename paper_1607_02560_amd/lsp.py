@@ -76,6 +76,22 @@ def load():
         "lsp_export_pattern": (c_int, [c_int, c_int, c_int, c_void_p]),
         "lsp_profile": (c_int, [c_void_p, c_int]),
         "lsp_profile_read": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+        "lsp_mlp_create": (c_int, [c_int, c_int, c_int, c_int, c_void_p, P(c_void_p)]),
+        "lsp_mlp_destroy": (None, [c_void_p]),
+        "lsp_mlp_num_params": (c_int, [c_void_p]),
+        "lsp_mlp_set_params": (c_int, [c_void_p, c_void_p]),
+        "lsp_mlp_get_params": (c_int, [c_void_p, c_void_p]),
+        "lsp_mlp_set_normalisation": (c_int, [c_void_p, c_void_p]),
+        "lsp_mlp_get_normalisation": (c_int, [c_void_p, c_void_p]),
+        "lsp_mlp_fit_normalisation": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+        "lsp_mlp_forward": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+        "lsp_mlp_loss_grad": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p,
+                                      P(c_double)]),
+        "lsp_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.c_float,
+                                       P(c_double)]),
+        "lsp_training_rows": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
+        "lsp_stencil_setup_learned": (c_int, [c_void_p, c_void_p, c_int, c_int, c_double,
+                                              c_void_p, c_void_p, P(c_int)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib_, name)
@@ -177,6 +193,32 @@ class Problem:
                "lsp_stencil_setup")
         self.t, self.m = t, m
 
+    def training_rows(self, P, points, X, T):
+        """Features and exact targets of the given points after an exact setup."""
+        import torch
+        count = points.numel()
+        _need(P, torch.float64, self.N * self.m, "P")
+        _need(points, torch.int64, count, "points")
+        _need(X, torch.float32, count * (self.m + 1), "X")
+        _need(T, torch.float32, count * 2 * self.m, "T")
+        _check(self.lib.lsp_training_rows(self._h, _ptr(P), _ptr(points), count, _ptr(X), _ptr(T)),
+               "lsp_training_rows")
+
+
+    def stencil_setup_learned(self, mlp: "MLP", t: int, num_shifts: int, threshold: float,
+                              P, fallback) -> int:
+        """Learned setup with exact fallback; returns the number of fallback rows."""
+        import torch
+        m = (2 * t + 1) ** self.d
+        _need(P, torch.float64, self.N * m, "P")
+        _need(fallback, torch.int32, self.N, "fallback")
+        nf = ctypes.c_int()
+        _check(self.lib.lsp_stencil_setup_learned(self._h, mlp._h, t, num_shifts, threshold,
+                                                  _ptr(P), _ptr(fallback), ctypes.byref(nf)),
+               "lsp_stencil_setup_learned")
+        self.t, self.m = t, m
+        return nf.value
+
     def ps_apply(self, u, y):
         import torch
         _need(u, torch.complex128, self.N, "u")
@@ -274,3 +316,92 @@ def host_lu_solver(P_rows: np.ndarray, d: int, n: int, t: int):
     Pm = scipy.sparse.csr_matrix((P_rows.reshape(-1), cols.reshape(-1), indptr), shape=(N, N))
     lu = scipy.sparse.linalg.splu(Pm.tocsc().astype(np.complex128))
     return lu.solve
+
+
+class MLP:
+    """The learned-stencil surrogate (lsp_mlp_*): n_in -> n_hidden -> n_hidden
+    -> n_out with SiLU, BF16 MFMA kernels, FP32 master weights and Adam."""
+
+    def __init__(self, n_in: int, n_hidden: int, n_out: int, batch_rows: int = 8192,
+                 stream=None):
+        self.lib = load()
+        self.n_in, self.n_hidden, self.n_out = n_in, n_hidden, n_out
+        self.batch_rows = batch_rows
+        h = ctypes.c_void_p()
+        _check(self.lib.lsp_mlp_create(n_in, n_hidden, n_out, batch_rows,
+                                       None if stream is None else stream, ctypes.byref(h)),
+               "lsp_mlp_create")
+        self._h = h
+        self.num_params = self.lib.lsp_mlp_num_params(h)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lsp_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat: np.ndarray):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        if a.size != self.num_params:
+            raise ValueError(f"need {self.num_params} parameters, got {a.size}")
+        _check(self.lib.lsp_mlp_set_params(self._h, a.ctypes.data), "lsp_mlp_set_params")
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.num_params, dtype=np.float32)
+        _check(self.lib.lsp_mlp_get_params(self._h, a.ctypes.data), "lsp_mlp_get_params")
+        return a
+
+    def set_normalisation(self, mu_x, sd_x, mu_y, sd_y):
+        a = np.ascontiguousarray(np.concatenate([mu_x, sd_x, mu_y, sd_y]), dtype=np.float32)
+        _check(self.lib.lsp_mlp_set_normalisation(self._h, a.ctypes.data),
+               "lsp_mlp_set_normalisation")
+
+    def get_normalisation(self):
+        a = np.empty(2 * (self.n_in + self.n_out), dtype=np.float32)
+        _check(self.lib.lsp_mlp_get_normalisation(self._h, a.ctypes.data),
+               "lsp_mlp_get_normalisation")
+        i, o = self.n_in, self.n_out
+        return a[:i], a[i:2 * i], a[2 * i:2 * i + o], a[2 * i + o:]
+
+    def fit_normalisation(self, X, T):
+        import torch
+        rows = X.shape[0]
+        _need(X, torch.float32, rows * self.n_in, "X")
+        _need(T, torch.float32, rows * self.n_out, "T")
+        _check(self.lib.lsp_mlp_fit_normalisation(self._h, _ptr(X), _ptr(T), rows),
+               "lsp_mlp_fit_normalisation")
+
+    def forward(self, X, Y):
+        import torch
+        rows = X.shape[0]
+        _need(X, torch.float32, rows * self.n_in, "X")
+        _need(Y, torch.float32, rows * self.n_out, "Y")
+        _check(self.lib.lsp_mlp_forward(self._h, _ptr(X), rows, _ptr(Y)), "lsp_mlp_forward")
+
+    def loss_grad(self, X, T):
+        import torch
+        rows = X.shape[0]
+        _need(X, torch.float32, rows * self.n_in, "X")
+        _need(T, torch.float32, rows * self.n_out, "T")
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(self.lib.lsp_mlp_loss_grad(self._h, _ptr(X), _ptr(T), rows, g.ctypes.data,
+                                          ctypes.byref(loss)), "lsp_mlp_loss_grad")
+        return loss.value, g
+
+    def train_step(self, X, T, lr: float, want_loss: bool = False):
+        import torch
+        rows = X.shape[0]
+        _need(X, torch.float32, rows * self.n_in, "X")
+        _need(T, torch.float32, rows * self.n_out, "T")
+        loss = ctypes.c_double()
+        _check(self.lib.lsp_mlp_train_step(self._h, _ptr(X), _ptr(T), rows, lr,
+                                           ctypes.byref(loss) if want_loss else None),
+               "lsp_mlp_train_step")
+        return loss.value if want_loss else None
+
