@@ -200,8 +200,9 @@ int lsp_export_pattern(int d, int n, int t, int64_t* col_host);
 
 /* ------------------------------------------------------------------------
  * Learned stencils (a surrogate beside the method; not part of the paper).
- * A network with two hidden SiLU layers maps the m + 1 features of a grid
- * point (h^2 v_j and h^2 v[j + a] for a in mu_0^t, h = 1/n) to its 2m rows
+ * A network with two hidden SiLU layers maps the m + 2 features of a grid
+ * point (h^2 v_j, h^2 v[j + a] for a in mu_0^t, h = 1/n, and h^2 s_j for the
+ * shift s_j of Sec. 4.1 nearest to v_j) to its 2m rows
  * (the P row of Sec. 4.1 and the C row of its shift, eq. (PC), times |s_j|).
  * Training and inference run in hand-written BF16 MFMA kernels with FP32
  * accumulation and FP32 master weights (Adam). Inputs and targets are
@@ -254,7 +255,7 @@ int lsp_mlp_train_step(lsp_mlp* q, const float* X_dev, const float* T_dev, int r
 
 /* Training rows of the points points_dev [count] (device int64 flat indices)
  * from a completed exact FP64 setup of p whose P rows are P_dev [N*m]:
- * X_dev [count][m+1] features, T_dev [count][2m] targets (device FP32).
+ * X_dev [count][m+2] features, T_dev [count][2m] targets (device FP32).
  * Indices outside [0, N) give rows of NaN. Returns LSP_ESTATE without a
  * completed exact setup. */
 int lsp_training_rows(lsp_problem* p, const double* P_dev, const int64_t* points_dev,
@@ -270,14 +271,16 @@ int lsp_training_rows(lsp_problem* p, const double* P_dev, const int64_t* points
  * rows (fallback_dev[j] = 1).
  *   P_dev         output, N*m float64 (layout of lsp_stencil_setup).
  *   fallback_dev  output, N int32 (1 = exact row used).
- *   n_fallback_host  receives the number of fallback rows (may be NULL).
+ *   n_fallback_host  receives the number of fallback rows; with NULL the call
+ *                 returns without waiting for the GPU.
  * The per-point C rows stay with the problem; lsp_c_apply and
  * lsp_precond_solve use them until the next setup. The network's kernels
  * run on the problem's stream (work pending on the network's own stream is
  * waited for first); calls that use one network or one problem at the same
  * time from several threads race. Errors: LSP_EINVAL (NULL pointer,
- * threshold < 0 or NaN, a network without m + 1 inputs and 2m outputs, the
- * sizes of lsp_stencil_setup), LSP_ENOMEM, LSP_EHIP. Synchronous. */
+ * threshold < 0 or NaN, a network without m + 2 inputs and 2m outputs, the
+ * sizes of lsp_stencil_setup), LSP_ENOMEM, LSP_EHIP. Synchronous when
+ * n_fallback_host is given, asynchronous on the problem's stream otherwise. */
 int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shifts,
                               double threshold, double* P_dev, int32_t* fallback_dev,
                               int* n_fallback_host);

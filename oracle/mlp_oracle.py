@@ -8,8 +8,11 @@ beside the method. Its definition (inputs, network, targets, loss, fallback
 test) is written out here in plain numpy so that the GPU training and
 inference kernels can be checked against it:
 
-  features         the 1 + m inputs of grid point j: h^2 v_j and h^2 v[j + a]
-                   for the offsets a of mu_0^t (Sec. 4.2), h = 1/n
+  features         the m + 2 inputs of grid point j: h^2 v_j, h^2 v[j + a]
+                   for the offsets a of mu_0^t (Sec. 4.2), h = 1/n, and h^2 s_j
+                   for the shift s_j assigned to the point (Sec. 4.1); the
+                   exact row depends on v_j only through the patch and on the
+                   bin of v_j through s_j, which jumps between bins
   targets          the exact rows of point j: P[j, a] (Sec. 4.1) and the C row
                    of its shift (eq. PC) scaled by |s_j| (an O(1) quantity,
                    since C = G alpha and G ~ 1/|s|)
@@ -31,15 +34,17 @@ from . import lsp_oracle as O
 
 
 # ----------------------------------------------------------------- data ----
-def features(v: np.ndarray, t: int) -> np.ndarray:
-    """(N, 1 + m) inputs, rows in the grid's C order: h^2 v_j followed by
-    h^2 v[(j + a) mod n] for the offsets a of mu_0^t in lexicographic order."""
+def features(v: np.ndarray, t: int, S: np.ndarray) -> np.ndarray:
+    """(N, m + 2) inputs, rows in the grid's C order: h^2 v_j, then
+    h^2 v[(j + a) mod n] for the offsets a of mu_0^t in lexicographic order,
+    then h^2 s_j with s_j the entry of the shift list S nearest to v_j."""
     d, n = v.ndim, v.shape[0]
     h2 = 1.0 / (n * n)
     offs = O.offsets(d, t)
     cols = [h2 * v.reshape(-1)]
     for a in offs:
         cols.append(h2 * np.roll(v, tuple(-a), axis=tuple(range(d))).reshape(-1))
+    cols.append(h2 * S[O.assign_shifts(v, S).reshape(-1)])
     return np.stack(cols, axis=1)
 
 

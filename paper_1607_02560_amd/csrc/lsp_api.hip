@@ -496,8 +496,8 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   int rc = prepare_setup(p, t, &num_shifts);
   if (rc) return rc;
   const int m = p->m;
-  if (lsp::mlp_inputs(mlp) != m + 1 || lsp::mlp_outputs(mlp) != 2 * m)
-    return lsp::set_error(LSP_EINVAL, "the surrogate needs m + 1 inputs and 2m outputs");
+  if (lsp::mlp_inputs(mlp) != m + 2 || lsp::mlp_outputs(mlp) != 2 * m)
+    return lsp::set_error(LSP_EINVAL, "the surrogate needs m + 2 inputs and 2m outputs");
   // per-point C rows and the chunk buffers of the inference
   const size_t need = (size_t)p->N * m;
   if (p->c_rows_cap < need) {
@@ -507,14 +507,19 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "learned C rows"))) return rc;
     p->c_rows_cap = need;
   }
-  // one buffer: rho*(s) [num_shifts], the fallback count, inputs [B][m+1] and
-  // outputs [B][2m] of one chunk (each part 256-byte aligned)
+  // one buffer: rho*(s) [num_shifts], the fallback count, and either the
+  // packed check forms K_s [num_shifts][kd] (fused pass) or the network's
+  // inputs [B][m+2] and outputs [B][2m] of one chunk (each part 256-byte aligned)
+  const lsp::MlpView mv = lsp::mlp_view(mlp);
+  const bool fused = lsp::learned_fused_supported(p, mv);
   const int B = lsp::mlp_batch_rows(mlp);
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t off_nf = up(sizeof(double) * num_shifts);
   const size_t off_x = off_nf + 256;
-  const size_t off_y = off_x + up(sizeof(float) * (size_t)B * (m + 1));
-  const size_t bytes = off_y + up(sizeof(float) * (size_t)B * 2 * m);
+  const size_t kd = lsp::learned_kform_doubles(p->d, t);
+  const size_t off_y = off_x + (fused ? up(sizeof(double) * kd * num_shifts)
+                                      : up(sizeof(float) * (size_t)B * (m + 2)));
+  const size_t bytes = off_y + (fused ? 0 : up(sizeof(float) * (size_t)B * 2 * m));
   if (p->learn_cap < bytes) {
     (void)hipStreamSynchronize(p->stream);
     dfree(p->learn_buf);
@@ -525,6 +530,7 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   double* rho_star = reinterpret_cast<double*>(p->learn_buf);
   int* nfall = reinterpret_cast<int*>(p->learn_buf + off_nf);
   float* X = reinterpret_cast<float*>(p->learn_buf + off_x);
+  double* Kf = reinterpret_cast<double*>(p->learn_buf + off_x);
   float* Y = reinterpret_cast<float*>(p->learn_buf + off_y);
   // the network's kernels run on the problem's stream below; work queued on
   // the network's own stream must be finished first
@@ -532,25 +538,36 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     const hipError_t es = hipStreamSynchronize(lsp::mlp_stream(mlp));
     if (es != hipSuccess) return lsp::hip_check(es, "surrogate stream");
   }
-  hipError_t e = hipMemsetAsync(nfall, 0, sizeof(int), p->stream);
+  // the fused pass clears the counter itself (a kernel, not a memset node)
+  hipError_t e = fused ? hipSuccess : hipMemsetAsync(nfall, 0, sizeof(int), p->stream);
   // exact tables (shift list, Green's sums, Gram matrices, null vectors)
   int blocks = 0;
   if (e == hipSuccess) e = lsp::launch_minmax(p);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts, &blocks);
   if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks);
-  if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star);
-  // learned rows in chunks of B points, each checked against the exact tables
-  for (int64_t j0 = 0; e == hipSuccess && j0 < p->N; j0 += B) {
-    const int rows = (int)std::min<int64_t>(B, p->N - j0);
-    e = lsp::launch_features(p, nullptr, j0, rows, X);
-    if (e == hipSuccess) e = lsp::mlp_forward_raw(mlp, X, rows, Y, p->stream);
+  if (fused) {
+    // one pass: network, check against K_s and rows
     if (e == hipSuccess)
-      e = lsp::launch_learned_rows(p, rho_star, Y, j0, rows, threshold, P_dev, p->c_rows,
-                                   fallback_dev, nfall);
+      e = lsp::launch_learned_fused(p, mv, threshold, rho_star, Kf, P_dev, p->c_rows,
+                                    fallback_dev, nfall);
+  } else {
+    if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star);
+    // learned rows in chunks of B points, each checked against the exact tables
+    for (int64_t j0 = 0; e == hipSuccess && j0 < p->N; j0 += B) {
+      const int rows = (int)std::min<int64_t>(B, p->N - j0);
+      e = lsp::launch_features(p, nullptr, j0, rows, X);
+      if (e == hipSuccess) e = lsp::mlp_forward_raw(mlp, X, rows, Y, p->stream);
+      if (e == hipSuccess)
+        e = lsp::launch_learned_rows(p, rho_star, Y, j0, rows, threshold, P_dev, p->c_rows,
+                                     fallback_dev, nfall);
+    }
   }
   int nf = 0;
-  if (e == hipSuccess) e = hipMemcpyAsync(&nf, nfall, sizeof(int), hipMemcpyDeviceToHost, p->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (n_fallback_host) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&nf, nfall, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  }
   if (e != hipSuccess) return lsp::hip_check(e, "learned setup");
   if (n_fallback_host) *n_fallback_host = nf;
   p->have_setup = true;

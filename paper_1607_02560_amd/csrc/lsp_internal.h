@@ -127,6 +127,20 @@ hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // preconditioner halves and Krylov helpers
 hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
 // surrogate (mlp.hip)
+// device pointers of a network's BF16 weights (padded layout: W1 [H][round16(n_in)],
+// W2 [H][H], W3 [round16(n_out)][H]), FP32 biases and standardisation
+// (mu_x, sd_x, mu_y, sd_y)
+struct MlpView {
+  int n_in, n_hidden, n_out;
+  const unsigned short* W1;
+  const unsigned short* W2;
+  const unsigned short* W3;
+  const float* b1;
+  const float* b2;
+  const float* b3;
+  const float* norm;
+};
+MlpView mlp_view(const lsp_mlp* q);
 hipError_t mlp_forward_raw(lsp_mlp* q, const float* X, int rows, float* Y, hipStream_t s);
 hipStream_t mlp_stream(const lsp_mlp* q);
 int mlp_batch_rows(const lsp_mlp* q);
@@ -136,6 +150,12 @@ hipError_t launch_features(const lsp_problem* p, const int64_t* points, int64_t 
                            float* X);
 hipError_t launch_targets(const lsp_problem* p, const double* P, const int64_t* points, int rows,
                           float* T);
+// fused learned setup (learned.hip): network, check and rows in one pass
+bool learned_fused_supported(const lsp_problem* p, const MlpView& mv);
+size_t learned_kform_doubles(int d, int t);  // packed K doubles per shift
+hipError_t launch_learned_fused(const lsp_problem* p, const MlpView& mv, double thr,
+                                double* rho_star, double* Kf, double* P, double* Crows,
+                                int32_t* fallback, int* nfall);
 // rho*(s) = sqrt(alpha^T M alpha / alpha^T A1 alpha) of every shift's exact stencil
 hipError_t launch_rho_star(const lsp_problem* p, double* rho_star);
 hipError_t launch_learned_rows(const lsp_problem* p, const double* rho_star, const float* Y,

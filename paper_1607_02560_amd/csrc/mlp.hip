@@ -25,14 +25,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
 
-// FP32 -> BF16 bits, round to nearest even (inputs are finite)
+// FP32 -> BF16 bits, round to nearest even (v_cvt_pk_bf16_f32)
 __device__ __forceinline__ unsigned short to_bf16(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+// logistic function with the hardware reciprocal (v_rcp_f32, about 1 ulp);
+// exp(-z) = inf for very negative z gives 0
+__device__ __forceinline__ float sigmoidf_(float z) {
+  return __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
 
 // C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (+ C[m][n] if accumulate), with
 // A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn] in BF16 and C in FP32.
@@ -72,8 +74,8 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
   }
 }
 
-// Xb[r][c] = bf16((X[r][c] - mu[c]) / sd[c]) for r < rows, c < cols; 0 in the
-// padding (rows .. rows_pad, cols .. ld).
+// Xb[r][c] = bf16((X[r][c] - mu[c]) * (1 / sd[c])) for r < rows, c < cols; 0 in
+// the padding (rows .. rows_pad, cols .. ld).
 __global__ void standardise_kernel(const float* __restrict__ X, int rows, int rows_pad, int cols,
                                    int ld, const float* __restrict__ mu,
                                    const float* __restrict__ sd, unsigned short* Xb) {
@@ -81,7 +83,7 @@ __global__ void standardise_kernel(const float* __restrict__ X, int rows, int ro
   if (e >= (int64_t)rows_pad * ld) return;
   const int r = (int)(e / ld), c = (int)(e % ld);
   float v = 0.f;
-  if (r < rows && c < cols) v = (X[(int64_t)r * cols + c] - mu[c]) / sd[c];
+  if (r < rows && c < cols) v = (X[(int64_t)r * cols + c] - mu[c]) * (1.0f / sd[c]);
   Xb[e] = to_bf16(v);
 }
 
@@ -409,6 +411,13 @@ hipError_t mlp_forward_raw(lsp_mlp* q, const float* X, int rows, float* Y, hipSt
 
 hipStream_t mlp_stream(const lsp_mlp* q) { return q->stream; }
 
+MlpView mlp_view(const lsp_mlp* q) {
+  return MlpView{q->n_in,           q->n_hidden,           q->n_out,
+                 q->pbf + q->off_W1, q->pbf + q->off_W2,     q->pbf + q->off_W3,
+                 q->param + q->off_b1, q->param + q->off_b2, q->param + q->off_b3,
+                 q->norm};
+}
+
 int mlp_batch_rows(const lsp_mlp* q) { return q->bmax; }
 int mlp_inputs(const lsp_mlp* q) { return q->n_in; }
 int mlp_outputs(const lsp_mlp* q) { return q->n_out; }
@@ -638,24 +647,27 @@ __device__ __forceinline__ int64_t neighbour(int64_t j, int n, int a) {
   return g;
 }
 
-// X[r] = (h^2 v_j, h^2 v[j + a] for a in mu_0^t), j = points[r] (or j0 + r)
-// (an index outside [0, N) gives a row of NaN and reads nothing)
+// X[r] = (h^2 v_j, h^2 v[j + a] for a in mu_0^t, h^2 s_j), j = points[r] (or
+// j0 + r), s_j the shift assigned to v_j (an index outside [0, N) gives a row
+// of NaN and reads nothing)
 template <int D, int W>
 __global__ void features_kernel(const double* __restrict__ v, int n, int64_t N,
+                                const double* __restrict__ S, const int* __restrict__ nS_ptr,
                                 const int64_t* __restrict__ points, int64_t j0, int rows,
                                 double h2, float* X) {
   constexpr int M = Pow<D, W>::v;
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
   const int64_t j = points ? points[r] : j0 + r;
-  float* x = X + (int64_t)r * (M + 1);
+  float* x = X + (int64_t)r * (M + 2);
   if (j < 0 || j >= N) {
-    for (int a = 0; a <= M; ++a) x[a] = __int_as_float(0x7fc00000);
+    for (int a = 0; a < M + 2; ++a) x[a] = __int_as_float(0x7fc00000);
     return;
   }
   x[0] = (float)(h2 * v[j]);
 #pragma unroll
   for (int a = 0; a < M; ++a) x[1 + a] = (float)(h2 * v[neighbour<D, W>(j, n, a)]);
+  x[M + 1] = (float)(h2 * S[nearest_shift(S, *nS_ptr, v[j])]);
 }
 
 // T[r] = (P[j, a] for a, C_{s_j}[a] |s_j| for a), j = points[r] (an index
@@ -802,7 +814,8 @@ hipError_t launch_features(const lsp_problem* p, const int64_t* points, int64_t 
                            float* X) {
   const dim3 grid(blocks_for(rows, 128)), blk(128);
   const double h2 = 1.0 / ((double)p->n * p->n);
-  LSP_DW_DISPATCH(features_kernel, p->v, p->n, p->N, points, j0, rows, h2, X);
+  LSP_DW_DISPATCH(features_kernel, p->v, p->n, p->N, p->ws.S, p->ws.nS, points, j0, rows, h2,
+                  X);
   return hipGetLastError();
 }
 

@@ -199,25 +199,27 @@ class Problem:
         count = points.numel()
         _need(P, torch.float64, self.N * self.m, "P")
         _need(points, torch.int64, count, "points")
-        _need(X, torch.float32, count * (self.m + 1), "X")
+        _need(X, torch.float32, count * (self.m + 2), "X")
         _need(T, torch.float32, count * 2 * self.m, "T")
         _check(self.lib.lsp_training_rows(self._h, _ptr(P), _ptr(points), count, _ptr(X), _ptr(T)),
                "lsp_training_rows")
 
 
     def stencil_setup_learned(self, mlp: "MLP", t: int, num_shifts: int, threshold: float,
-                              P, fallback) -> int:
-        """Learned setup with exact fallback; returns the number of fallback rows."""
+                              P, fallback, count: bool = True):
+        """Learned setup with exact fallback; returns the number of fallback rows
+        (count=True, synchronous) or None (count=False, asynchronous)."""
         import torch
         m = (2 * t + 1) ** self.d
         _need(P, torch.float64, self.N * m, "P")
         _need(fallback, torch.int32, self.N, "fallback")
         nf = ctypes.c_int()
         _check(self.lib.lsp_stencil_setup_learned(self._h, mlp._h, t, num_shifts, threshold,
-                                                  _ptr(P), _ptr(fallback), ctypes.byref(nf)),
+                                                  _ptr(P), _ptr(fallback),
+                                                  ctypes.byref(nf) if count else None),
                "lsp_stencil_setup_learned")
         self.t, self.m = t, m
-        return nf.value
+        return nf.value if count else None
 
     def ps_apply(self, u, y):
         import torch

@@ -1,8 +1,9 @@
 """Training and use of the learned-stencil surrogate (lsp_mlp_* of the C ABI).
 
 The surrogate is not part of the paper. A network with two hidden SiLU
-layers of width 128 maps the m + 1 features of a grid point (h^2 v_j and the
-potential patch h^2 v[j + a], a in mu_0^t) to its exact P row (Sec. 4.1) and
+layers of width 128 maps the m + 2 features of a grid point (h^2 v_j, the
+potential patch h^2 v[j + a], a in mu_0^t, and h^2 s_j for the shift assigned
+to the point) to its exact P row (Sec. 4.1) and
 the C row of its shift times |s_j| (eq. PC). Training rows come from exact
 setups on fields that are not the evaluation field; the learned setup
 checks every predicted row against the exact Gram matrices of eq. (A) and
@@ -38,7 +39,7 @@ def glorot_params(n_in: int, n_hidden: int, n_out: int, seed: int) -> np.ndarray
 def gather_rows(fields, t: int, num_shifts: int, rows_per_field: int, seed: int, device):
     """Exact setups of each potential in `fields` (numpy arrays of shape
     (n,)*d) and the features / targets of `rows_per_field` random points of
-    each. Returns device tensors X [rows][m+1], T [rows][2m] (float32)."""
+    each. Returns device tensors X [rows][m+2], T [rows][2m] (float32)."""
     import torch
     r = np.random.default_rng(seed)
     xs, ts = [], []
@@ -51,7 +52,7 @@ def gather_rows(fields, t: int, num_shifts: int, rows_per_field: int, seed: int,
         prob.stencil_setup(t, num_shifts, P)
         cnt = min(rows_per_field, N)
         pts = torch.from_numpy(np.sort(r.choice(N, cnt, replace=False)).astype(np.int64)).to(device)
-        X = torch.empty((cnt, m + 1), dtype=torch.float32, device=device)
+        X = torch.empty((cnt, m + 2), dtype=torch.float32, device=device)
         T = torch.empty((cnt, 2 * m), dtype=torch.float32, device=device)
         prob.training_rows(P, pts, X, T)
         torch.cuda.synchronize(device)
@@ -88,6 +89,6 @@ def train(mlp: "lsp.MLP", X, T, steps: int, batch: int, lr: float, seed: int,
 
 def make_mlp(d: int, t: int, seed: int, batch_rows: int = 8192) -> "lsp.MLP":
     m = (2 * t + 1) ** d
-    mlp = lsp.MLP(m + 1, HIDDEN, 2 * m, batch_rows)
-    mlp.set_params(glorot_params(m + 1, HIDDEN, 2 * m, seed))
+    mlp = lsp.MLP(m + 2, HIDDEN, 2 * m, batch_rows)
+    mlp.set_params(glorot_params(m + 2, HIDDEN, 2 * m, seed))
     return mlp

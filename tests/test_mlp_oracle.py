@@ -75,15 +75,20 @@ def test_silu_known_values():
 def test_features_brute_force():
     d, n, t = 3, 5, 1
     v = np.random.default_rng(5).standard_normal((n,) * d)
-    X = MO.features(v, t)
+    S = np.array([-1.5, -0.2, 0.4, 1.1])
+    X = MO.features(v, t, S)
     offs = O.offsets(d, t)
     h2 = 1.0 / (n * n)
+    assert X.shape == (n ** d, offs.shape[0] + 2)
     for j in [0, 7, 62, 124]:
         idx = np.unravel_index(j, (n,) * d)
         assert X[j, 0] == h2 * v[idx]
         for a, off in enumerate(offs):
             nb = tuple((idx[ax] + off[ax]) % n for ax in range(d))
             assert X[j, 1 + a] == h2 * v[nb]
+        # the nearest entry of S by a scan (ties to the lower index)
+        best = min(range(len(S)), key=lambda i: (abs(S[i] - v[idx]), i))
+        assert X[j, -1] == h2 * S[best]
 
 
 def test_targets_round_trip():
