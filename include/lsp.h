@@ -285,6 +285,42 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
                               double threshold, double* P_dev, int32_t* fallback_dev,
                               int* n_fallback_host);
 
+/* ------------------------------------------------------------------------
+ * Batches (a form beside the plain method): many independent problems of
+ * uneven n set up together with one launch per setup stage over the work
+ * items of all of them, replayed as one HIP graph when the problems' stream
+ * is not the legacy default stream.
+ * ------------------------------------------------------------------------ */
+typedef struct lsp_batch lsp_batch;
+
+/* A batch over count problems created with lsp_create. They must share d,
+ * the HIP stream and the device, and have n >= 16; the batch refers to them
+ * (it does not own them) and must be destroyed before any of them. */
+int lsp_batch_create(int count, lsp_problem* const* problems, lsp_batch** out);
+void lsp_batch_destroy(lsp_batch* b);
+
+/* lsp_stencil_setup (Sec. 4.1-4.2) of every problem of the batch with a
+ * common t and precision: num_shifts[i] (NULL: the defaults), P_dev[i] (rows
+ * of problem i, layout of lsp_stencil_setup), idx_dev (NULL, or NULL
+ * entries, to skip s_j). Each problem receives exactly the tables and rows of
+ * its own lsp_stencil_setup, and its per-problem entry points (C-apply,
+ * GMRES, tables) use them afterwards. The first call for a set of sizes (and
+ * t, precision) also times the assembly tile widths that divide every n and
+ * keeps the fastest. Errors: those of lsp_stencil_setup for each problem,
+ * LSP_EINVAL for NULL rows. Asynchronous on the batch's stream after the
+ * first call for a set of arguments. */
+int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int precision,
+                            void* const* P_dev, int32_t* const* idx_dev);
+
+/* y_i = (L + diag v_i) u_i (Sec. 2) for every problem i: u_dev[i], y_dev[i]
+ * device complex128 of N_i entries, distinct. Asynchronous. */
+int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* y_dev);
+
+/* The assembly tile width the tuner chose (0 before the first setup), and
+ * optionally the four candidate widths (0 = not a candidate) and their mean
+ * times in ms (arrays of 4). */
+int lsp_batch_tile(const lsp_batch* b, int* tile_width, int* candidates, float* ms);
+
 #ifdef __cplusplus
 }
 #endif

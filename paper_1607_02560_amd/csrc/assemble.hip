@@ -27,8 +27,8 @@ using lsp::Pow;
 //      FP64 with one rounding per operation (then one rounding to FP32).
 // --------------------------------------------------------------------------
 template <int D, int W, int TR, int TW, typename PT>
-__global__ __launch_bounds__(256) void assemble_kernel(
-    const double* __restrict__ v, int n, const double* __restrict__ S,
+__device__ __forceinline__ void assemble_body(
+    int bx, int by, int bz, const double* __restrict__ v, int n, const double* __restrict__ S,
     const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
     int32_t* __restrict__ idx_out) {
   constexpr int t = (W - 1) / 2;
@@ -42,9 +42,9 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   __shared__ int soff[M];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
-  const int c0 = blockIdx.x * TW;
-  const int r0 = blockIdx.y * TR;
-  const int p0 = (D == 3) ? (int)blockIdx.z : 0;
+  const int c0 = bx * TW;
+  const int r0 = by * TR;
+  const int p0 = (D == 3) ? bz : 0;
   const int mask = n - 1;
 
   for (int i = tid; i < nS; i += 256) sS[i] = S[i];
@@ -130,8 +130,29 @@ __global__ __launch_bounds__(256) void assemble_kernel(
   }
 }
 
+template <int D, int W, int TR, int TW, typename PT>
+__global__ __launch_bounds__(256) void assemble_kernel(
+    const double* __restrict__ v, int n, const double* __restrict__ S,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
+    int32_t* __restrict__ idx_out) {
+  assemble_body<D, W, TR, TW, PT>(blockIdx.x, blockIdx.y, blockIdx.z, v, n, S, nS_ptr, actab, P,
+                                  idx_out);
+}
+
+// one launch for the problems of a batch: block b is tile (map[b].y, map[b].z,
+// map[b].w) of problem map[b].x
+template <int D, int W, int TR, int TW, typename PT>
+__global__ __launch_bounds__(256) void assemble_batched_kernel(const lsp::BatchRec* recs,
+                                                               const int4* map) {
+  const int4 it = map[blockIdx.x];
+  const lsp::BatchRec& r = recs[it.x];
+  assemble_body<D, W, TR, TW, PT>(it.y, it.z, it.w, r.v, r.n, r.S, r.nS,
+                                  reinterpret_cast<const double2*>(r.actab),
+                                  static_cast<PT*>(r.P), r.idx);
+}
+
 // --------------------------------------------------------------------------
-// b2: z = C r, (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n] (eq. PC), complex r.
+// C-apply: z = C r, (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n] (eq. PC), complex r.
 // Same tiling as assemble_kernel; s_j is recomputed from v and S exactly as
 // the setup assigned it, so no per-point state is kept between calls. After a
 // learned setup the C rows are per point (Crows [N][m]) instead.
@@ -288,6 +309,30 @@ hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   LSP_DISPATCH_DW(2, 5, (run_assemble<2, 5>(p, P, fp32, idx)))
   LSP_DISPATCH_DW(2, 7, (run_assemble<2, 7>(p, P, fp32, idx)))
   LSP_DISPATCH_DW(3, 3, (run_assemble<3, 3>(p, P, fp32, idx)))
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_assemble_batched(int d, int t, int tw, bool fp32, const BatchRec* recs,
+                                   const int4* map, int blocks, hipStream_t s) {
+  const int W = 2 * t + 1;
+#define LSP_ASM_B(D_, W_, TW_)                                                               \
+  if (d == D_ && W == W_ && tw == TW_) {                                                     \
+    if (fp32)                                                                                \
+      hipLaunchKernelGGL((assemble_batched_kernel<D_, W_, 1, TW_, float>), dim3(blocks),      \
+                         dim3(256), 0, s, recs, map);                                        \
+    else                                                                                     \
+      hipLaunchKernelGGL((assemble_batched_kernel<D_, W_, 1, TW_, double>), dim3(blocks),     \
+                         dim3(256), 0, s, recs, map);                                        \
+    return hipGetLastError();                                                                \
+  }
+#define LSP_ASM_B_TW(D_, W_) \
+  LSP_ASM_B(D_, W_, 16) LSP_ASM_B(D_, W_, 32) LSP_ASM_B(D_, W_, 64) LSP_ASM_B(D_, W_, 128)
+  LSP_ASM_B_TW(2, 3)
+  LSP_ASM_B_TW(2, 5)
+  LSP_ASM_B_TW(2, 7)
+  LSP_ASM_B_TW(3, 3)
+#undef LSP_ASM_B_TW
+#undef LSP_ASM_B
   return hipErrorInvalidValue;
 }
 

@@ -185,10 +185,11 @@ __host__ __device__ inline int tiled_wavenumbers(int n) {
 // the diagonal, hence 2 inside a square tile before the 1/2), and the waves
 // of unit 0 add the corner (n/2, n/2), whose cosine weights are (-1)^delta.
 template <int D, int W, int KT>
-__global__ __launch_bounds__(kThreads) void green_sums_kernel(
-    const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
-    int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
-    const int* __restrict__ units, int n, double* __restrict__ part) {
+__device__ __forceinline__ void green_body(
+    int bx, int by, int gx, const double* __restrict__ mm_part, int nreq,
+    double* __restrict__ S_out, int* __restrict__ nS_out, double* __restrict__ vrange_out,
+    const double* __restrict__ cw, const int* __restrict__ units, int n,
+    double* __restrict__ part) {
   using Lay = GreenLayout<D, W>;
   constexpr int NP = Lay::NP;
   constexpr int WO2 = Lay::WO2;
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
 
   const int Ht = tiled_wavenumbers<D>(n);
   const int nyq = n / 2;
-  const int unit = units[blockIdx.x];
+  const int unit = units[bx];
   const int ot = unit >> 16;
   const int q = unit & 0xffff;
   int O = 1;
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
 
   lsp::shift_list_block<kThreads>(mm_part, nreq, sS, &sNS, sRange, sWave, sRed);
   const int nS = sNS;
-  if (blockIdx.x == 0 && blockIdx.y == 0) {
+  if (bx == 0 && by == 0) {
     for (int i = tid; i < nS; i += kThreads) S_out[i] = sS[i];
     if (tid == 0) {
       *nS_out = nS;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
     if (tid + i * kThreads < cnt) cws[tid + i * kThreads] = stage[i];
   __syncthreads();  // the last barrier of the block: waves are independent below
 
-  const int si = blockIdx.y * kWaves + wid;
+  const int si = by * kWaves + wid;
   if (si >= nS) return;
   const double s = sS[si];
   double tg[W], tq[W];
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
                               : (P2 >= 8) ? 0x31 : (P2 >= 4) ? 0x33 : 0x37;
   if ((lane & kUnusedMask) == 0 && vi < NV) {
     double val = a[0];
-    if (D == 2 && blockIdx.x == 0) {
+    if (D == 2 && bx == 0) {
       // corner (n/2, n/2): pair (da, db) of value vi gets cn[da] cn[db] r
       // (r^2 for the g*g half)
       const int pi = vi % NP;
@@ -342,8 +343,28 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
       const double rr = (vi < NP) ? r : r * r;
       val += (cn[da] * cn[db]) * rr;
     }
-    part[((int64_t)si * gridDim.x + blockIdx.x) * NV + vi] = val;
+    part[((int64_t)si * gx + bx) * NV + vi] = val;
   }
+}
+
+template <int D, int W, int KT>
+__global__ __launch_bounds__(kThreads) void green_sums_kernel(
+    const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
+    int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
+    const int* __restrict__ units, int n, double* __restrict__ part) {
+  green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, mm_part, nreq, S_out, nS_out,
+                       vrange_out, cw, units, n, part);
+}
+
+// one launch for the problems of a batch: block b is unit map[b].y of shift
+// group map[b].z of problem map[b].x
+template <int D, int W, int KT>
+__global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::BatchRec* recs,
+                                                                 const int4* map) {
+  const int4 it = map[blockIdx.x];
+  const lsp::BatchRec& r = recs[it.x];
+  green_body<D, W, KT>(it.y, it.z, r.nunits, r.mm_part, r.nreq, r.S, r.nS, r.vrange, r.cw,
+                       r.units, r.n, r.part);
 }
 
 // Work units with at least one term on or above the diagonal, in
@@ -389,6 +410,25 @@ hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out) {
 }  // namespace
 
 namespace lsp {
+
+hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
+                                hipStream_t s) {
+  const int W = 2 * t + 1;
+#define LSP_GREEN_B(D_, W_)                                                                   \
+  if (d == D_ && W == W_) {                                                                   \
+    hipLaunchKernelGGL((green_batched_kernel<D_, W_, kKTile>), dim3(blocks), dim3(kThreads),  \
+                       kResidencyLds, s, recs, map);                                          \
+    return hipGetLastError();                                                                 \
+  }
+  LSP_GREEN_B(2, 3)
+  LSP_GREEN_B(2, 5)
+  LSP_GREEN_B(2, 7)
+  LSP_GREEN_B(3, 3)
+#undef LSP_GREEN_B
+  return hipErrorInvalidValue;
+}
+
+int green_shift_groups(int num_shifts) { return (num_shifts + kWaves - 1) / kWaves; }
 
 hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units) {
   const int W = 2 * p->t + 1;

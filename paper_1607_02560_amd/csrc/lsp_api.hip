@@ -401,10 +401,12 @@ int lsp_default_num_shifts(int d, int n) {
   return s < 1 ? 1 : s;
 }
 
-namespace {
+}  // extern "C"
 
-// Validation, workspaces and the cosine table shared by the exact and the
-// learned setup; num_shifts is replaced by the effective request.
+namespace lsp {
+
+// Validation, workspaces and the cosine table shared by the exact, the
+// learned and the batched setup; num_shifts is replaced by the effective request.
 int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
   int num_shifts = *num_shifts_io;
   if (t < 1) return lsp::set_error(LSP_EINVAL, "t must be >= 1");
@@ -436,7 +438,9 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
   return LSP_OK;
 }
 
-}  // namespace
+}  // namespace lsp
+
+extern "C" {
 
 int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
                       int32_t* idx_dev) {
@@ -444,7 +448,7 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
   if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
   if (precision != LSP_FP64 && precision != LSP_FP32_REFINE)
     return lsp::set_error(LSP_EINVAL, "unsupported precision");
-  int rc = prepare_setup(p, t, &num_shifts);
+  int rc = lsp::prepare_setup(p, t, &num_shifts);
   if (rc) return rc;
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
@@ -493,7 +497,7 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
                               int* n_fallback_host) {
   if (!p || !mlp || !P_dev || !fallback_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
   if (!(threshold >= 0.0)) return lsp::set_error(LSP_EINVAL, "threshold must be >= 0");
-  int rc = prepare_setup(p, t, &num_shifts);
+  int rc = lsp::prepare_setup(p, t, &num_shifts);
   if (rc) return rc;
   const int m = p->m;
   if (lsp::mlp_inputs(mlp) != m + 2 || lsp::mlp_outputs(mlp) != 2 * m)

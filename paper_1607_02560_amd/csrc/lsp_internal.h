@@ -44,6 +44,35 @@ struct Workspace {
   int cap_w = 0;                  // W^d capacity
 };
 
+// One problem of a batched launch (device memory, plain pointers into the
+// problem's own workspace): what the setup kernels of the problem take as
+// arguments in a single-problem launch.
+struct BatchRec {
+  const double* v;
+  int n;
+  int nreq;          // requested |S|
+  int64_t N;
+  double invN;
+  double* mm_part;   // min/max partials
+  double* S;
+  int* nS;
+  double* vrange;
+  const double* cw;  // folded cosine weights
+  const int* units;  // Green's-sum work units
+  int nunits;
+  double* part;      // Green's partial sums
+  double* gtab;
+  double* gamtab;
+  double* Mtab;
+  double* alpha;
+  double* Ctab;
+  double* sigma;
+  double* actab;
+  int* status;
+  void* P;           // rows (float64 or float32)
+  int32_t* idx;      // may be null
+};
+
 }  // namespace lsp
 
 struct lsp_problem {
@@ -104,6 +133,9 @@ int set_error(int code, const std::string& msg);
 int stage_begin(lsp_problem* p, int stage);
 void stage_end(lsp_problem* p, int token);
 int hip_check(hipError_t e, const char* what);
+// validation, workspaces and cosine table before a setup of radius t;
+// num_shifts (0 = default) is replaced by the effective request
+int prepare_setup(lsp_problem* p, int t, int* num_shifts);
 
 // ---- kernel launchers (asynchronous, on p->stream) ----
 // ps_apply: y = (L + diag v) u
@@ -124,6 +156,17 @@ int expand_gram_host(int d, int t, const double* packed, double* full);
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks);
 // P: float64 rows, or float32 rows when fp32
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
+// batched launches: one launch per stage over the problems of a batch; map
+// holds (problem, block coordinates) per block
+hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int blocks,
+                                 hipStream_t s);
+hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
+                                hipStream_t s);
+int green_shift_groups(int num_shifts);  // shift groups (blocks) per work unit
+hipError_t launch_null_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
+                               hipStream_t s);
+hipError_t launch_assemble_batched(int d, int t, int tw, bool fp32, const BatchRec* recs,
+                                   const int4* map, int blocks, hipStream_t s);
 // preconditioner halves and Krylov helpers
 hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
 // surrogate (mlp.hip)

@@ -283,8 +283,8 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
 }
 
 template <int D, int W>
-__global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
-    const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
+__device__ __forceinline__ void null_body(
+    int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
     double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
     double* sigma_out, double* actab, int* status) {
   using Pa = Parity<D, W>;
@@ -297,7 +297,6 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
   constexpr int NV = 2 * WO2 * NP;
   constexpr int T = 64 * NC;
   __shared__ NullShared<D, W> sh;
-  const int si = blockIdx.x;
   if (si >= *nS) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -422,6 +421,26 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
 }
 
 template <int D, int W>
+__global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
+    const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
+    double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
+    double* sigma_out, double* actab, int* status) {
+  null_body<D, W>(blockIdx.x, nS, part, nblk, invN, gtab, gamtab, Mtab, alpha_out, C_out,
+                  sigma_out, actab, status);
+}
+
+// one launch for the problems of a batch: block b solves shift map[b].y of
+// problem map[b].x
+template <int D, int W>
+__global__ __launch_bounds__(64 * (1 << D)) void null_batched_kernel(const lsp::BatchRec* recs,
+                                                                     const int4* map) {
+  const int4 it = map[blockIdx.x];
+  const lsp::BatchRec& r = recs[it.x];
+  null_body<D, W>(it.y, r.nS, r.part, r.nunits, r.invN, r.gtab, r.gamtab, r.Mtab, r.alpha,
+                  r.Ctab, r.sigma, r.actab, r.status);
+}
+
+template <int D, int W>
 hipError_t run_null(lsp_problem* p, int num_shifts, int nblk) {
   const double invN = 1.0 / (double)p->N;
   hipLaunchKernelGGL((null_vector_kernel<D, W>), dim3(num_shifts), dim3(64 * (1 << D)), 0,
@@ -434,6 +453,23 @@ hipError_t run_null(lsp_problem* p, int num_shifts, int nblk) {
 }  // namespace
 
 namespace lsp {
+
+hipError_t launch_null_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
+                               hipStream_t s) {
+  const int W = 2 * t + 1;
+#define LSP_NULL_B(D_, W_)                                                                  \
+  if (d == D_ && W == W_) {                                                                 \
+    hipLaunchKernelGGL((null_batched_kernel<D_, W_>), dim3(blocks), dim3(64 * (1 << D_)), 0, \
+                       s, recs, map);                                                       \
+    return hipGetLastError();                                                               \
+  }
+  LSP_NULL_B(2, 3)
+  LSP_NULL_B(2, 5)
+  LSP_NULL_B(2, 7)
+  LSP_NULL_B(3, 3)
+#undef LSP_NULL_B
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk) {
   const int W = 2 * p->t + 1;

@@ -93,6 +93,14 @@ def load():
         "lsp_stencil_setup_learned": (c_int, [c_void_p, c_void_p, c_int, c_int, c_double,
                                               c_void_p, c_void_p, P(c_int)]),
     }
+    sig.update({
+        "lsp_batch_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
+        "lsp_batch_destroy": (None, [c_void_p]),
+        "lsp_batch_stencil_setup": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p,
+                                            c_void_p]),
+        "lsp_batch_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "lsp_batch_tile": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib_, name)
         fn.restype = res
@@ -303,6 +311,73 @@ class Problem:
             "gamma": gam[:k * wd].reshape((k,) + (W,) * self.d).copy(),
             "M": M[:k * m * m].reshape(k, m, m).copy(),
         }
+
+
+class Batch:
+    """Problems of uneven n set up and applied together (lsp_batch_*): one launch
+    per setup stage over all of them, replayed as a HIP graph on a non-default
+    stream. The problems must outlive the batch."""
+
+    def __init__(self, problems):
+        self.lib = load()
+        self.problems = list(problems)
+        arr = (ctypes.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(self.lib.lsp_batch_create(len(self.problems), arr, ctypes.byref(h)),
+               "lsp_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.lsp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stencil_setup(self, t: int, num_shifts, P_list, idx_list=None, precision: int = LSP_FP64):
+        import torch
+        cnt = len(self.problems)
+        dt = torch.float32 if precision == LSP_FP32_REFINE else torch.float64
+        ptrs = (ctypes.c_void_p * cnt)()
+        iptrs = (ctypes.c_void_p * cnt)()
+        for i, prob in enumerate(self.problems):
+            m = (2 * t + 1) ** prob.d
+            _need(P_list[i], dt, prob.N * m, f"P[{i}]")
+            ptrs[i] = _ptr(P_list[i])
+            if idx_list is not None and idx_list[i] is not None:
+                _need(idx_list[i], torch.int32, prob.N, f"idx[{i}]")
+                iptrs[i] = _ptr(idx_list[i])
+            prob.t, prob.m = t, m
+        ns = None
+        if num_shifts is not None:
+            ns = (ctypes.c_int * cnt)(*[int(x) for x in num_shifts])
+        _check(self.lib.lsp_batch_stencil_setup(self._h, t, ns, precision, ptrs,
+                                                iptrs if idx_list is not None else None),
+               "lsp_batch_stencil_setup")
+
+    def ps_apply(self, u_list, y_list):
+        import torch
+        cnt = len(self.problems)
+        up = (ctypes.c_void_p * cnt)()
+        yp = (ctypes.c_void_p * cnt)()
+        for i, prob in enumerate(self.problems):
+            _need(u_list[i], torch.complex128, prob.N, f"u[{i}]")
+            _need(y_list[i], torch.complex128, prob.N, f"y[{i}]")
+            up[i] = _ptr(u_list[i])
+            yp[i] = _ptr(y_list[i])
+        _check(self.lib.lsp_batch_ps_apply(self._h, up, yp), "lsp_batch_ps_apply")
+
+    def tile(self):
+        """(chosen assembly tile width, candidate widths, their mean ms)."""
+        tw = ctypes.c_int(0)
+        cand = (ctypes.c_int * 4)()
+        ms = (ctypes.c_float * 4)()
+        _check(self.lib.lsp_batch_tile(self._h, ctypes.byref(tw), cand, ms), "lsp_batch_tile")
+        return tw.value, [c for c in cand if c], [float(ms[i]) for i in range(4) if cand[i]]
 
 
 def host_lu_solver(P_rows: np.ndarray, d: int, n: int, t: int):
