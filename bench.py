@@ -19,8 +19,12 @@ on 200,000 exact rows of other fields (seeds 1..8), both setups are timed on
 the evaluation field (seed 0), and GMRES(40) iteration counts to 1e-8 are
 compared on the same kind of field at n = 16, where the host LU of P is cheap.
 
+A third section times the batched form: 64 2D problems with n drawn from
+{64, 128, 256, 512}, set up (FP32 rows) and applied with one launch per stage
+for all of them, against the same 64 problems set up one by one.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-learned] [--train-steps S]
+                    [--no-learned] [--train-steps S] [--no-batched]
     python bench.py --copy-probe MiB   # plain device copy of a known size, for
                                        # scaling hardware byte counters
 """
@@ -169,6 +173,61 @@ def learned_vs_exact(dev, stream, reps, train_steps, threshold=1e-3):
     }
 
 
+def batched_section(dev, reps):
+    """The batched form on 64 problems of uneven n (2D Helmholtz, t = 2,
+    |S_p| = n_p / 16, FP32 rows): batched setup and apply (graph replays)
+    against the same 64 single-problem calls back to back."""
+    import torch
+    from paper_1607_02560_amd import lsp
+    from paper_1607_02560_amd import workloads as W
+    print("[bench] batched: 64 problems", file=sys.stderr, flush=True)
+    ps = W.batch2d(64, seed=0)
+    stream = torch.cuda.Stream(dev)
+    probs = [lsp.Problem(2, p.n, torch.from_numpy(p.v.reshape(-1)).to(dev), stream=stream)
+             for p in ps]
+    m = 25
+    Ps = [torch.empty(p.N * m, dtype=torch.float32, device=dev) for p in ps]
+    idxs = [torch.empty(p.N, dtype=torch.int32, device=dev) for p in ps]
+    us = [torch.from_numpy(p.f.reshape(-1)).to(dev) for p in ps]
+    ys = [torch.empty_like(u) for u in us]
+    nS = [p.num_shifts for p in ps]
+    torch.cuda.synchronize()
+    batch = lsp.Batch(probs)
+    bsetup = lambda: batch.stencil_setup(2, nS, Ps, idxs, precision=lsp.LSP_FP32_REFINE)
+    bapply = lambda: batch.ps_apply(us, ys)
+
+    def singles_setup():
+        for i, pr in enumerate(probs):
+            pr.stencil_setup(2, nS[i], Ps[i], idxs[i], precision=lsp.LSP_FP32_REFINE)
+
+    def singles_apply():
+        for i, pr in enumerate(probs):
+            pr.ps_apply(us[i], ys[i])
+
+    for fn in (bsetup, bapply, singles_setup, singles_apply):
+        for _ in range(3):
+            fn()
+    t_bs = timed(stream, bsetup, reps)
+    t_ba = timed(stream, bapply, reps)
+    t_ss = timed(stream, singles_setup, reps)
+    t_sa = timed(stream, singles_apply, reps)
+    tw, cand, ms = batch.tile()
+    total = sum(p.N for p in ps)
+    batch.close()
+    for pr in probs:
+        pr.close()
+    return {
+        "workload": "64 x 2D Helmholtz, n drawn from {64,128,256,512} (seed 0), own smooth "
+                    "random c in [0.8,1.2] each, t=2 (5x5 stencils), |S_p|=n_p/16, FP32 rows",
+        "sizes": {str(n): sum(1 for p in ps if p.n == n) for n in (64, 128, 256, 512)},
+        "points": total,
+        "batched_setup_ms": t_bs * 1e3, "batched_stencils_per_s": total / t_bs,
+        "single_setups_ms": t_ss * 1e3, "single_stencils_per_s": total / t_ss,
+        "batched_apply_ms": t_ba * 1e3, "single_applies_ms": t_sa * 1e3,
+        "tile_width": tw, "tile_candidates": cand, "tile_candidate_ms": ms,
+    }
+
+
 def cpu_baseline(p):
     """The FP64 oracle timed on this host: one full setup of the same workload
     (the sample) and 10 applies. numpy's FFT runs on one thread."""
@@ -202,6 +261,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-versus-exact setup section")
     ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-form section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run 5 device-to-device copies of MiB mebibytes and exit")
     args = ap.parse_args()
@@ -322,6 +383,8 @@ def main():
     del P, idx
     if not args.no_learned:
         out["learned_vs_exact"] = learned_vs_exact(dev, stream, args.steps, args.train_steps)
+    if not args.no_batched:
+        out["form_batched"] = batched_section(dev, args.steps)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(p)
