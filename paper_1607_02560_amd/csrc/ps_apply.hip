@@ -403,6 +403,291 @@ __global__ __launch_bounds__(kFftThreads) void fft_line_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Line operator with 8 values per thread, n = 64 R (R = 4, 8, 16: n = 256,
+// 512, 1024). T = 8 R threads own a line (two waves at n = 1024), so a pass
+// runs twice as many waves as the 16-value form and a SIMD holds two lines
+// in different phases (one loading or storing while the other transforms).
+// With j = T a + t, t = R b + c and k = k1 + 8 (k2a + 8 k2b):
+//   1. thread t: 8-point DFT over a, times w_n^(t k1);
+//   2. LDS transpose: thread (k1, c) takes t = R b + c, 8-point DFT over b,
+//      times w_n^(8 c k2a);
+//   3. the R-point DFT over c across R neighbouring lanes (one DPP row):
+//      radix-2 decimation in frequency, partner lane c ^ h for h = R/2 .. 1
+//      (row rotate by 8, half-row mirror then quad swap, quad swaps), the
+//      upper lane of each pair times w_{2h}^(c mod h); lane c ends with
+//      k2b = bitrev(c);
+// then the scaled spectrum goes back through the same steps (decimation in
+// time, conjugate twiddles) to natural order.
+// ---------------------------------------------------------------------------
+constexpr int kFft8Threads = 512;
+
+// w^(m j) for j = 0..7 (w^i = tw[i]): five table loads, three products.
+__device__ __forceinline__ void twiddle8(const double2* __restrict__ tw, int m, double* wr,
+                                         double* wi) {
+  double2 lo[4], hi;
+  lo[0] = make_double2(1.0, 0.0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) lo[r] = tw[m * r];
+  hi = tw[4 * m];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    wr[r] = lo[r].x;
+    wi[r] = lo[r].y;
+    double a = hi.x, b = hi.y;
+    if (r > 0) cmul(a, b, lo[r].x, lo[r].y);
+    wr[4 + r] = a;
+    wi[4 + r] = b;
+  }
+}
+
+// a double from lane c ^ h of the same 16-lane row
+template <int H>
+__device__ __forceinline__ double lane_xor(double x) {
+  if constexpr (H == 1) return lsp::dpp_move<lsp::kDppQuadXor1>(x);
+  if constexpr (H == 2) return lsp::dpp_move<lsp::kDppQuadXor2>(x);
+  if constexpr (H == 4) {
+    // mirror within 8 lanes (i -> 7 - i), then swap within quads (i -> i ^ 3)
+    return lsp::dpp_move<0x1B>(lsp::dpp_move<lsp::kDppHalfMirror>(x));
+  }
+  return lsp::dpp_move<lsp::kDppRowRor8>(x);  // H == 8
+}
+
+template <int H>
+__device__ __forceinline__ void lane_pair(double& vr, double& vi, int c) {
+  const double sgn = (c & H) ? -1.0 : 1.0;
+  const double pr = lane_xor<H>(vr);
+  const double pi = lane_xor<H>(vi);
+  vr = fma(sgn, vr, pr);
+  vi = fma(sgn, vi, pi);
+}
+
+// Per-lane twiddles of the R-point lane DFT: stage s (h = 2^s) multiplies
+// the upper lanes (c & h) by w_{2h}^(c mod h), w_m = exp(-2 pi i / m).
+template <int R>
+struct LaneTw {
+  double r[4], i[4];
+  __device__ __forceinline__ void load(const double2* __restrict__ tw, int n, int c) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int h = 1 << s;
+      r[s] = 1.0;
+      i[s] = 0.0;
+      if (h < R && (c & h)) {
+        const double2 w = tw[(c % h) * (n / (2 * h))];
+        r[s] = w.x;
+        i[s] = w.y;
+      }
+    }
+  }
+};
+
+template <int R, int S>
+__device__ __forceinline__ void lane_dif_stage(double& vr, double& vi, int c,
+                                               const LaneTw<R>& lt) {
+  lane_pair<(1 << S)>(vr, vi, c);
+  cmul(vr, vi, lt.r[S], lt.i[S]);
+}
+
+template <int R>
+__device__ __forceinline__ void lane_dft8_fwd(double& vr, double& vi, int c, const LaneTw<R>& lt) {
+  if constexpr (R >= 16) lane_dif_stage<R, 3>(vr, vi, c, lt);
+  if constexpr (R >= 8) lane_dif_stage<R, 2>(vr, vi, c, lt);
+  if constexpr (R >= 4) lane_dif_stage<R, 1>(vr, vi, c, lt);
+  if constexpr (R >= 2) lane_pair<1>(vr, vi, c);
+}
+
+template <int R, int S>
+__device__ __forceinline__ void lane_dit_stage(double& vr, double& vi, int c,
+                                               const LaneTw<R>& lt) {
+  cmulc(vr, vi, lt.r[S], lt.i[S]);
+  lane_pair<(1 << S)>(vr, vi, c);
+}
+
+template <int R>
+__device__ __forceinline__ void lane_dft8_inv(double& vr, double& vi, int c, const LaneTw<R>& lt) {
+  if constexpr (R >= 2) lane_pair<1>(vr, vi, c);
+  if constexpr (R >= 4) lane_dit_stage<R, 1>(vr, vi, c, lt);
+  if constexpr (R >= 8) lane_dit_stage<R, 2>(vr, vi, c, lt);
+  if constexpr (R >= 16) lane_dit_stage<R, 3>(vr, vi, c, lt);
+}
+
+template <int R>
+__device__ __forceinline__ int bitrev_bits(int c) {
+  int r = 0;
+#pragma unroll
+  for (int b = 1; b < R; b <<= 1) {
+    r = (r << 1) | (c & 1);
+    c >>= 1;
+  }
+  return r;
+}
+
+template <int R, bool CONTIG, int MODE>
+__global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
+    const double2* __restrict__ u, double2* __restrict__ out, const double2* __restrict__ acc,
+    const double* __restrict__ v, const double2* __restrict__ tw, int64_t nlines, int64_t st) {
+  constexpr int T = 8 * R;
+  constexpr int n = 8 * T;
+  constexpr int LPB = kFft8Threads / T;  // lines per block
+  constexpr int RS = T + 1;              // padded LDS row
+  constexpr int LS = 8 * RS + 2;         // LDS stride between lines (padded)
+  __shared__ double2 sh[LPB * LS];
+
+  const int tid = threadIdx.x;
+  const int64_t g = CONTIG ? (int64_t)blockIdx.x : xcd_paired_group(blockIdx.x, gridDim.x);
+  // memory map
+  const int ml = CONTIG ? tid / T : tid % LPB;
+  const int t = CONTIG ? tid % T : tid / LPB;
+  const int64_t Lm = g * LPB + ml;
+  const bool active = Lm < nlines;
+  int64_t base, es;
+  if constexpr (CONTIG) {
+    base = Lm * n;
+    es = 1;
+  } else {
+    const int64_t o = Lm / st, i = Lm % st;
+    base = o * n * st + i;
+    es = st;
+  }
+  double2* Sm = sh + ml * LS;
+
+  // 1. 8-point DFT over a, twiddle w_n^(t k1)
+  double xr[8], xi[8], yr[8], yi[8], wr[8], wi[8];
+  double2 zacc[8];
+  double vv[8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    double2 val = make_double2(0.0, 0.0);
+    if (active) val = u[base + (int64_t)(T * a + t) * es];
+    xr[a] = val.x;
+    xi[a] = val.y;
+  }
+  if constexpr (MODE == kAccum || MODE == kFinal) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+      zacc[a] = active ? acc[base + (int64_t)(T * a + t) * es] : make_double2(0.0, 0.0);
+  }
+  if constexpr (MODE == kFinal) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) vv[a] = active ? v[base + (int64_t)(T * a + t) * es] : 0.0;
+  }
+  double ur[8], ui[8];
+  if constexpr (MODE == kFinal) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      ur[a] = xr[a];
+      ui[a] = xi[a];
+    }
+  }
+  RegDft<8, -1>::template run<1>(xr, xi, yr, yi);
+  twiddle8(tw, t, wr, wi);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) {
+    cmul(yr[k1], yi[k1], wr[k1], wi[k1]);
+    Sm[k1 * RS + t] = make_double2(yr[k1], yi[k1]);
+  }
+  __syncthreads();
+
+  // 2. line map: thread (k1, c) runs the 8-point DFT over b of t = R b + c
+  const int sl = tid / T;
+  const int tau = tid % T;
+  double2* Ss = sh + sl * LS;
+  const int k1 = tau / R;
+  const int c = tau % R;
+  LaneTw<R> lt;
+  lt.load(tw, n, c);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const double2 val = Ss[k1 * RS + R * b + c];
+    xr[b] = val.x;
+    xi[b] = val.y;
+  }
+  RegDft<8, -1>::template run<1>(xr, xi, yr, yi);
+  twiddle8(tw, 8 * c, wr, wi);
+#pragma unroll
+  for (int k2a = 0; k2a < 8; ++k2a) {
+    cmul(yr[k2a], yi[k2a], wr[k2a], wi[k2a]);
+    // 3. R-point DFT across the lanes
+    lane_dft8_fwd<R>(yr[k2a], yi[k2a], c, lt);
+  }
+  // scale by 4 pi^2 kk^2 / n (1/n: the inverse transform is unnormalised)
+  const int k2b = bitrev_bits<R>(c);
+#pragma unroll
+  for (int k2a = 0; k2a < 8; ++k2a) {
+    const int k = k1 + 8 * (k2a + 8 * k2b);
+    const int kk = (k < n / 2) ? k : k - n;
+    const double fac = (lsp::kFourPi2 / n) * (double)(kk * kk);
+    yr[k2a] *= fac;
+    yi[k2a] *= fac;
+  }
+#pragma unroll
+  for (int k2a = 0; k2a < 8; ++k2a) {
+    lane_dft8_inv<R>(yr[k2a], yi[k2a], c, lt);
+    cmulc(yr[k2a], yi[k2a], wr[k2a], wi[k2a]);
+  }
+  RegDft<8, +1>::template run<1>(yr, yi, xr, xi);
+  // each thread rewrites exactly the LDS entries it read
+#pragma unroll
+  for (int b = 0; b < 8; ++b) Ss[k1 * RS + R * b + c] = make_double2(xr[b], xi[b]);
+  __syncthreads();
+
+  // 4. memory map: conjugate twiddle, 8-point inverse DFT over k1
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double2 val = Sm[q * RS + t];
+    xr[q] = val.x;
+    xi[q] = val.y;
+  }
+  twiddle8(tw, t, wr, wi);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cmulc(xr[q], xi[q], wr[q], wi[q]);
+  RegDft<8, +1>::template run<1>(xr, xi, yr, yi);
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int64_t e = base + (int64_t)(T * a + t) * es;
+    double2 r = make_double2(yr[a], yi[a]);
+    if constexpr (MODE == kAccum || MODE == kFinal) {
+      r.x += zacc[a].x;
+      r.y += zacc[a].y;
+    }
+    if constexpr (MODE == kFinal) {
+      r.x += vv[a] * ur[a];
+      r.y += vv[a] * ui[a];
+    }
+    out[e] = r;
+  }
+}
+
+template <int R>
+hipError_t run_fft8_apply(const lsp_problem* p, const double2* u, double2* y) {
+  constexpr int n = 64 * R;
+  constexpr int LPB = kFft8Threads / (8 * R);
+  const double2* tw = reinterpret_cast<const double2*>(p->tw);
+  double2* z = reinterpret_cast<double2*>(p->z);
+  const int64_t N = p->N;
+  const int64_t nlines = N / n;
+  const int64_t blocks = (nlines + LPB - 1) / LPB;
+  for (int ax = 0; ax < p->d - 1; ++ax) {
+    int64_t st = 1;
+    for (int b = ax + 1; b < p->d; ++b) st *= n;
+    if (ax == 0) {
+      hipLaunchKernelGGL((fft8_line_kernel<R, false, kFirst>), dim3((unsigned)blocks),
+                         dim3(kFft8Threads), 0, p->stream, u, z, (const double2*)nullptr, p->v,
+                         tw, nlines, st);
+    } else {
+      hipLaunchKernelGGL((fft8_line_kernel<R, false, kAccum>), dim3((unsigned)blocks),
+                         dim3(kFft8Threads), 0, p->stream, u, z, (const double2*)z, p->v, tw,
+                         nlines, st);
+    }
+  }
+  hipLaunchKernelGGL((fft8_line_kernel<R, true, kFinal>), dim3((unsigned)blocks),
+                     dim3(kFft8Threads), 0, p->stream, u, y, (const double2*)z, p->v, tw, nlines,
+                     (int64_t)1);
+  return hipGetLastError();
+}
+
 template <int R3>
 hipError_t run_fft_apply(const lsp_problem* p, const double2* u, double2* y) {
   constexpr int n = 256 * R3;
@@ -639,9 +924,12 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y) {
     case 32: return run_ps_apply<4, 8>(p, u2, y2);
     case 64: return run_ps_apply<8, 8>(p, u2, y2);
     case 128: return run_ps_apply<8, 16>(p, u2, y2);
+    // measured per pass at n = 1024: 12.7 + 14.9 us (8 values per thread)
+    // against 12.8 + 15.5 us (16 values); at 256 and 512 the 16-value form
+    // is 0.1-0.4 us faster
     case 256: return run_fft_apply<1>(p, u2, y2);
     case 512: return run_fft_apply<2>(p, u2, y2);
-    case 1024: return run_fft_apply<4>(p, u2, y2);
+    case 1024: return run_fft8_apply<16>(p, u2, y2);
     default: return hipErrorInvalidValue;
   }
 }
