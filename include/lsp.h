@@ -253,6 +253,18 @@ int lsp_mlp_loss_grad(lsp_mlp* q, const float* X_dev, const float* T_dev, int ro
 int lsp_mlp_train_step(lsp_mlp* q, const float* X_dev, const float* T_dev, int rows, float lr,
                        double* loss_host);
 
+/* Save the network (parameters, standardisation, Adam moments and step
+ * count) to one file: a 64-byte header (magic "LSPMLP01", version 1, n_in,
+ * n_hidden, n_out, Adam steps, parameter count, FNV-1a 64 checksum) and the
+ * FP32 payload. Synchronous. LSP_EINVAL if the file cannot be written. */
+int lsp_mlp_save(lsp_mlp* q, const char* path);
+
+/* Create a network from a file written by lsp_mlp_save, taking batches of
+ * up to batch_rows rows on a HIP stream (NULL = default); training resumes
+ * where it stopped. LSP_EINVAL for a missing, truncated or corrupted file
+ * (header or checksum mismatch). */
+int lsp_mlp_load(const char* path, int batch_rows, void* stream, lsp_mlp** out);
+
 /* Training rows of the points points_dev [count] (device int64 flat indices)
  * from a completed exact FP64 setup of p whose P rows are P_dev [N*m]:
  * X_dev [count][m+2] features, T_dev [count][2m] targets (device FP32).

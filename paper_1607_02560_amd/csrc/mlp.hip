@@ -18,6 +18,9 @@
 //   inputs [rows][Ip] BF16, outputs [rows][Op] FP32.
 #include "setup_common.h"
 
+#include <cstdio>
+#include <cstring>
+
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -612,6 +615,105 @@ int lsp_mlp_train_step(lsp_mlp* q, const float* X_dev, const float* T_dev, int r
                      c1, c2, q->pbf);
   if ((e = hipGetLastError()) != hipSuccess) return lsp::hip_check(e, "Adam step");
   if (loss_host) *loss_host = sum_loss(q, nblk, rows);
+  return LSP_OK;
+}
+
+// ---- save / load: one flat little-endian file ----
+// header (64 bytes): magic "LSPMLP01", version, n_in, n_hidden, n_out, Adam
+// step count, parameter count, FNV-1a 64 checksum of the payload; payload
+// (FP32): parameters (order of lsp_mlp_set_params), standardisation
+// (mu_x, sd_x, mu_y, sd_y), Adam first and second moments (parameter order).
+namespace {
+struct MlpFileHeader {
+  char magic[8];
+  int32_t version, n_in, n_hidden, n_out, adam_t, reserved;
+  uint64_t nparam, checksum;
+  uint64_t pad[2];
+};
+static_assert(sizeof(MlpFileHeader) == 64, "file header layout");
+
+uint64_t fnv1a(const void* data, size_t bytes, uint64_t h = 1469598103934665603ull) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < bytes; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+}  // namespace
+
+int lsp_mlp_save(lsp_mlp* q, const char* path) {
+  if (!q || !path) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  const size_t np = (size_t)lsp_mlp_num_params(q);
+  const size_t nn = 2 * (size_t)(q->n_in + q->n_out);
+  std::vector<float> payload(3 * np + nn);
+  int rc = lsp_mlp_get_params(q, payload.data());
+  if (rc) return rc;
+  if ((rc = lsp_mlp_get_normalisation(q, payload.data() + np))) return rc;
+  std::vector<float> pad(q->nparam);
+  for (int k = 0; k < 2; ++k) {
+    if (hipMemcpy(pad.data(), k == 0 ? q->adam_m : q->adam_v, sizeof(float) * q->nparam,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+      return lsp::set_error(LSP_EHIP, "Adam state download failed");
+    unpad_params(q, pad, payload.data() + np + nn + k * np);
+  }
+  MlpFileHeader h{};
+  memcpy(h.magic, "LSPMLP01", 8);
+  h.version = 1;
+  h.n_in = q->n_in;
+  h.n_hidden = q->n_hidden;
+  h.n_out = q->n_out;
+  h.adam_t = q->adam_t;
+  h.nparam = np;
+  h.checksum = fnv1a(payload.data(), sizeof(float) * payload.size());
+  FILE* f = fopen(path, "wb");
+  if (!f) return lsp::set_error(LSP_EINVAL, std::string("cannot open ") + path + " for writing");
+  const bool ok = fwrite(&h, sizeof(h), 1, f) == 1 &&
+                  fwrite(payload.data(), sizeof(float), payload.size(), f) == payload.size();
+  if (fclose(f) != 0 || !ok) return lsp::set_error(LSP_EINVAL, std::string("write failed: ") + path);
+  return LSP_OK;
+}
+
+int lsp_mlp_load(const char* path, int batch_rows, void* stream, lsp_mlp** out) {
+  if (!path || !out) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return lsp::set_error(LSP_EINVAL, std::string("cannot open ") + path);
+  MlpFileHeader h{};
+  bool ok = fread(&h, sizeof(h), 1, f) == 1 && memcmp(h.magic, "LSPMLP01", 8) == 0 &&
+            h.version == 1 && h.n_in >= 1 && h.n_out >= 1 && h.n_hidden >= 16 &&
+            h.n_hidden % 16 == 0 && h.n_in <= 4096 && h.n_out <= 4096 && h.n_hidden <= 4096 &&
+            h.adam_t >= 0;
+  const uint64_t np = ok ? (uint64_t)h.n_hidden * (h.n_in + h.n_hidden + h.n_out + 2) + h.n_out : 0;
+  ok = ok && h.nparam == np;
+  std::vector<float> payload;
+  if (ok) {
+    payload.resize(3 * np + 2 * (size_t)(h.n_in + h.n_out));
+    ok = fread(payload.data(), sizeof(float), payload.size(), f) == payload.size() &&
+         fgetc(f) == EOF && fnv1a(payload.data(), sizeof(float) * payload.size()) == h.checksum;
+  }
+  fclose(f);
+  if (!ok) return lsp::set_error(LSP_EINVAL, std::string("not a valid surrogate file: ") + path);
+  lsp_mlp* q = nullptr;
+  int rc = lsp_mlp_create(h.n_in, h.n_hidden, h.n_out, batch_rows, stream, &q);
+  if (rc) return rc;
+  const size_t nn = 2 * (size_t)(h.n_in + h.n_out);
+  if ((rc = lsp_mlp_set_params(q, payload.data())) ||
+      (rc = lsp_mlp_set_normalisation(q, payload.data() + np))) {
+    lsp_mlp_destroy(q);
+    return rc;
+  }
+  std::vector<float> pad;
+  for (int k = 0; k < 2; ++k) {
+    pad_params(q, payload.data() + np + nn + k * np, pad);
+    if (hipMemcpy(k == 0 ? q->adam_m : q->adam_v, pad.data(), sizeof(float) * q->nparam,
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      lsp_mlp_destroy(q);
+      return lsp::set_error(LSP_EHIP, "Adam state upload failed");
+    }
+  }
+  q->adam_t = h.adam_t;
+  *out = q;
   return LSP_OK;
 }
 

@@ -94,6 +94,8 @@ def load():
                                               c_void_p, c_void_p, P(c_int)]),
     }
     sig.update({
+        "lsp_mlp_save": (c_int, [c_void_p, ctypes.c_char_p]),
+        "lsp_mlp_load": (c_int, [ctypes.c_char_p, c_int, c_void_p, P(c_void_p)]),
         "lsp_batch_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
         "lsp_batch_destroy": (None, [c_void_p]),
         "lsp_batch_stencil_setup": (c_int, [c_void_p, c_int, c_void_p, c_int, c_void_p,
@@ -313,6 +315,15 @@ class Problem:
         }
 
 
+def _mlp_dims(path: str):
+    """(n_in, n_hidden, n_out) from the header of a surrogate file (after the
+    8-byte magic and the int32 version)."""
+    import struct
+    with open(path, "rb") as f:
+        head = f.read(24)
+    return struct.unpack("<3i", head[12:24])
+
+
 class Batch:
     """Problems of uneven n set up and applied together (lsp_batch_*): one launch
     per setup stage over all of them, replayed as a HIP graph on a non-default
@@ -410,6 +421,24 @@ class MLP:
                "lsp_mlp_create")
         self._h = h
         self.num_params = self.lib.lsp_mlp_num_params(h)
+
+    @classmethod
+    def load(cls, path: str, batch_rows: int = 8192, stream=None) -> "MLP":
+        """A network from a file written by save() (training state included)."""
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.lsp_mlp_load(os.fsencode(path), batch_rows, stream, ctypes.byref(h)),
+               "lsp_mlp_load")
+        obj = cls.__new__(cls)
+        obj.lib = lib
+        obj._h = h
+        obj.batch_rows = batch_rows
+        obj.num_params = lib.lsp_mlp_num_params(h)
+        obj.n_in, obj.n_hidden, obj.n_out = _mlp_dims(path)
+        return obj
+
+    def save(self, path: str):
+        _check(self.lib.lsp_mlp_save(self._h, os.fsencode(path)), "lsp_mlp_save")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -357,3 +357,82 @@ def test_learned_gmres_and_gain(torch_dev):
     prob.close()
     mlp.close()
     raw.close()
+
+
+def test_save_load_round_trip(torch_dev, tmp_path):
+    """A saved network loads with the same parameters, standardisation and
+    Adam state: forward outputs are identical and the next training step of
+    the loaded copy equals that of the original."""
+    torch, dev = torch_dev
+    from paper_1607_02560_amd import lsp
+    mlp, _ = trained_net(torch_dev, steps=50)
+    path = str(tmp_path / "net.lspmlp")
+    mlp.save(path)
+    other = lsp.MLP.load(path, batch_rows=1024)
+    assert (other.n_in, other.n_hidden, other.n_out) == (29, 128, 54)
+    assert np.array_equal(other.get_params(), mlp.get_params())
+    for a, b in zip(other.get_normalisation(), mlp.get_normalisation()):
+        assert np.array_equal(a, b)
+    r = np.random.default_rng(21)
+    X = torch.from_numpy(r.standard_normal((300, 29)).astype(np.float32) * 0.01).to(dev)
+    T = torch.from_numpy(r.standard_normal((300, 54)).astype(np.float32)).to(dev)
+    Y1 = torch.empty((300, 54), dtype=torch.float32, device=dev)
+    Y2 = torch.empty_like(Y1)
+    mlp.forward(X, Y1)
+    other.forward(X, Y2)
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+    mlp.train_step(X, T, 1e-3)
+    other.train_step(X, T, 1e-3)
+    assert np.array_equal(other.get_params(), mlp.get_params())
+    # a corrupted payload is refused
+    raw = bytearray(open(path, "rb").read())
+    raw[100] ^= 0xFF
+    bad = str(tmp_path / "bad.lspmlp")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(lsp.LSPError):
+        lsp.MLP.load(bad)
+    with pytest.raises(lsp.LSPError):
+        lsp.MLP.load(str(tmp_path / "missing.lspmlp"))
+    mlp.close()
+    other.close()
+
+
+def test_learned_setup_edge_cases(torch_dev):
+    """A network with non-finite outputs sends every row to the exact fallback;
+    the asynchronous call (no count) writes the same rows; bad arguments are
+    refused."""
+    torch, dev = torch_dev
+    from paper_1607_02560_amd import lsp
+    from paper_1607_02560_amd import surrogate as SG
+    p, prob = small_problem(torch_dev, seed=2)
+    N, m = p.N, 27
+    Pex = torch.empty(N * m, dtype=torch.float64, device=dev)
+    prob.stencil_setup(1, p.num_shifts, Pex)
+    nan_net = SG.make_mlp(3, 1, seed=1, batch_rows=256)
+    flat = nan_net.get_params()
+    flat[-54:] = np.nan  # output biases
+    nan_net.set_params(flat)
+    Pl = torch.empty(N * m, dtype=torch.float64, device=dev)
+    fb = torch.empty(N, dtype=torch.int32, device=dev)
+    nf = prob.stencil_setup_learned(nan_net, 1, p.num_shifts, 0.01, Pl, fb)
+    assert nf == N and int(fb.sum()) == N
+    assert torch.equal(Pl, Pex)
+    # asynchronous call with a trained network equals the counted one
+    mlp, _ = trained_net(torch_dev, steps=100)
+    P1 = torch.empty_like(Pl)
+    P2 = torch.full_like(Pl, float("nan"))
+    f1 = torch.empty_like(fb)
+    f2 = torch.full_like(fb, -1)
+    prob.stencil_setup_learned(mlp, 1, p.num_shifts, 0.01, P1, f1)
+    assert prob.stencil_setup_learned(mlp, 1, p.num_shifts, 0.01, P2, f2, count=False) is None
+    torch.cuda.synchronize()
+    assert torch.equal(P1, P2) and torch.equal(f1, f2)
+    with pytest.raises(lsp.LSPError):
+        prob.stencil_setup_learned(mlp, 1, p.num_shifts, -0.5, P1, f1)  # threshold < 0
+    wrong = lsp.MLP(28, 128, 54, 64)  # m + 1 inputs: not this problem's network
+    with pytest.raises(lsp.LSPError):
+        prob.stencil_setup_learned(wrong, 1, p.num_shifts, 0.01, P1, f1)
+    for q in (nan_net, mlp, wrong):
+        q.close()
+    prob.close()
