@@ -43,12 +43,14 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn] in BF16 and C in FP32.
 // M, N, K are multiples of 16. Four waves per block, one 16x16 tile each
 // (2 x 2 tiles per block); one v_mfma_f32_16x16x16bf16 per 16 values of k.
+// With gridDim.z > 1 block z sums k in [z kchunk, (z+1) kchunk) and writes
+// its raw partial tile to C + z M ldc (split_reduce_kernel adds them).
 // MFMA operand layout: lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
 // and D[4(l/16)+i][l%16], i = 0..3.
 __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     const unsigned short* __restrict__ A, int64_t sam, int64_t sak,
     const unsigned short* __restrict__ B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
-    int N, int K, const float* __restrict__ bias, int accumulate) {
+    int N, int K, const float* __restrict__ bias, int accumulate, int kchunk) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
   const int n0 = (blockIdx.x * 2 + (wave & 1)) * 16;
@@ -57,7 +59,15 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
   const unsigned short* ap = A + (int64_t)(m0 + r) * sam;
   const unsigned short* bp = B + (int64_t)(n0 + r) * sbn;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  const bool split = gridDim.z > 1;
+  if (split) {
+    C += (int64_t)blockIdx.z * M * ldc;
+    bias = nullptr;
+    accumulate = 0;
+  }
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     bf16x4 a, b;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -75,6 +85,21 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     if (accumulate) val += *cp;
     *cp = val;
   }
+}
+
+// C[m][n] = sum over z of part[z][m][n] (fixed order) (+ bias[n]) (+ C[m][n])
+__global__ void split_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
+                                    float* C, int64_t ldc, const float* __restrict__ bias,
+                                    int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)M * N) return;
+  const int m = (int)(e / N), n = (int)(e % N);
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
+  if (bias) s += bias[n];
+  float* cp = C + (int64_t)m * ldc + n;
+  if (accumulate) s += *cp;
+  *cp = s;
 }
 
 // Xb[r][c] = bf16((X[r][c] - mu[c]) * (1 / sd[c])) for r < rows, c < cols; 0 in
@@ -252,6 +277,8 @@ struct lsp_mlp {
   unsigned short* dZb = nullptr;
   double* loss_part = nullptr;
   double* loss_host = nullptr;  // pinned
+  float* gsplit = nullptr;      // k-split partial tiles of the weight gradients
+  size_t gsplit_cap = 0;
 };
 
 namespace {
@@ -273,12 +300,31 @@ inline int round16(int x) { return (x + 15) / 16 * 16; }
 
 inline unsigned blocks_for(int64_t n, int t = kT) { return (unsigned)((n + t - 1) / t); }
 
+// One GEMM; reductions long against the number of output tiles (weight
+// gradients over the batch rows) are split over k into partial tiles in
+// split_buf (split_cap floats) and summed by a second kernel in a fixed order.
 hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak,
                 const unsigned short* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
-                int N, int K, const float* bias, bool accumulate) {
+                int N, int K, const float* bias, bool accumulate, float* split_buf = nullptr,
+                size_t split_cap = 0) {
   dim3 grid((N + 31) / 32, (M + 31) / 32);
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M,
-                     N, K, bias, accumulate ? 1 : 0);
+  int splits = 1;
+  if (split_buf && K >= 1024 && (int)(grid.x * grid.y) < 128) {
+    splits = std::min(64, K / 256);
+    while (splits > 1 && (size_t)splits * M * N > split_cap) splits /= 2;
+  }
+  if (splits <= 1) {
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc,
+                       M, N, K, bias, accumulate ? 1 : 0, K);
+    return hipGetLastError();
+  }
+  const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+  splits = (K + kchunk - 1) / kchunk;
+  grid.z = splits;
+  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf,
+                     (int64_t)N, M, N, K, nullptr, 0, kchunk);
+  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)(((int64_t)M * N + kT - 1) / kT)),
+                     dim3(kT), 0, s, split_buf, splits, M, N, C, ldc, bias, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -327,7 +373,7 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
   hipError_t e;
   // gW3 [Op][H] = dY^T A2: A(o, b) = dYb[b Op + o], B(b, h) = A2b[b H + h]
   if ((e = gemm(s, q->dYb, 1, q->Op, q->A2b, H, 1, g + q->off_W3, H, q->Op, H, rows_pad, nullptr,
-                false)))
+                false, q->gsplit, q->gsplit_cap)))
     return e;
   hipLaunchKernelGGL(colsum_kernel, dim3(q->Op), dim3(kT), 0, s, q->dY, rows_pad, q->Op,
                      g + q->off_b3);
@@ -338,7 +384,8 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
   hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z2, cnt,
                      valid, q->dZ, q->dZb);
   // gW2 [H][H] = dZ2^T A1
-  if ((e = gemm(s, q->dZb, 1, H, q->A1b, H, 1, g + q->off_W2, H, H, H, rows_pad, nullptr, false)))
+  if ((e = gemm(s, q->dZb, 1, H, q->A1b, H, 1, g + q->off_W2, H, H, H, rows_pad, nullptr, false,
+                q->gsplit, q->gsplit_cap)))
     return e;
   hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b2);
   // dA1 = dZ2 W2: B(h2, h1) = W2[h2 H + h1]
@@ -347,7 +394,7 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
                      valid, q->dZ, q->dZb);
   // gW1 [H][Ip] = dZ1^T Xb
   if ((e = gemm(s, q->dZb, 1, H, q->Xb, q->Ip, 1, g + q->off_W1, q->Ip, H, q->Ip, rows_pad,
-                nullptr, false)))
+                nullptr, false, q->gsplit, q->gsplit_cap)))
     return e;
   hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b1);
   return hipGetLastError();
@@ -456,6 +503,7 @@ int lsp_mlp_create(int n_in, int n_hidden, int n_out, int batch_rows, void* stre
   q->off_W3 = o; o += (size_t)q->Op * H;
   q->off_b3 = o; o += q->Op;
   q->nparam = o;
+  q->gsplit_cap = (size_t)64 * H * std::max(H, std::max(q->Ip, q->Op));
   const size_t B = q->bmax;
   int rc = LSP_OK;
   if ((rc = dalloc_(&q->param, o)) || (rc = dalloc_(&q->grad, o)) ||
@@ -467,7 +515,8 @@ int lsp_mlp_create(int n_in, int n_hidden, int n_out, int batch_rows, void* stre
       (rc = dalloc_(&q->dY, B * q->Op)) || (rc = dalloc_(&q->dYb, B * q->Op)) ||
       (rc = dalloc_(&q->dA, B * H)) || (rc = dalloc_(&q->dZ, B * H)) ||
       (rc = dalloc_(&q->dZb, B * H)) ||
-      (rc = dalloc_(&q->loss_part, B * q->Op / kT + 1))) {
+      (rc = dalloc_(&q->loss_part, B * q->Op / kT + 1)) ||
+      (rc = dalloc_(&q->gsplit, (size_t)64 * H * std::max(H, std::max(q->Ip, q->Op))))) {
     lsp_mlp_destroy(q);
     return rc;
   }
@@ -498,6 +547,7 @@ void lsp_mlp_destroy(lsp_mlp* q) {
   dfree_(q->norm); dfree_(q->Xb); dfree_(q->Z1); dfree_(q->Z2); dfree_(q->A1b); dfree_(q->A2b);
   dfree_(q->Y); dfree_(q->dY); dfree_(q->dYb); dfree_(q->dA); dfree_(q->dZ); dfree_(q->dZb);
   dfree_(q->loss_part);
+  dfree_(q->gsplit);
   if (q->loss_host) (void)hipHostFree(q->loss_host);
   delete q;
 }
