@@ -301,7 +301,7 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
  * Batches (a form beside the plain method): many independent problems of
  * uneven n set up together with one launch per setup stage over the work
  * items of all of them, replayed as one HIP graph when the problems' stream
- * is not the legacy default stream.
+ * is not the legacy default stream (LSP_GRAPHS=0 launches directly).
  * ------------------------------------------------------------------------ */
 typedef struct lsp_batch lsp_batch;
 

@@ -3,9 +3,9 @@
 // and null vectors, per-point rows) is ONE launch over the (problem, block)
 // work items of all problems, so small problems share the GPU instead of
 // each taking a launch sequence of its own. The four launches are captured
-// once into a HIP graph and replayed while the arguments are unchanged; the
-// batched pseudospectral apply is likewise one graph over every problem's
-// apply. The tables and rows each problem receives are those of its own
+// once into a HIP graph and replayed while the arguments are unchanged, and
+// the batched pseudospectral apply is one graph over every problem's apply
+// (LSP_GRAPHS=0 launches directly). The tables and rows each problem receives are those of its own
 // single-problem setup (same kernels, same arithmetic), so every per-problem
 // entry point (C-apply, GMRES, table export) works on them afterwards.
 //
@@ -187,6 +187,9 @@ int lsp_batch_create(int count, lsp_problem* const* problems, lsp_batch** out) {
     b->stream = p->stream;
     b->probs.push_back(p);
   }
+  // graph replay on by default here: the four batched launches take 0.33-0.35 ms
+  // as a graph replay against 0.43 ms launched directly (64-problem workload)
+  b->use_graphs = lsp::graphs_enabled(true);
   *out = b;
   return LSP_OK;
 }

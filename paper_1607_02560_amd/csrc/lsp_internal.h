@@ -133,6 +133,9 @@ int set_error(int code, const std::string& msg);
 int stage_begin(lsp_problem* p, int stage);
 void stage_end(lsp_problem* p, int token);
 int hip_check(hipError_t e, const char* what);
+// HIP-graph replay of launch sequences: LSP_GRAPHS=1 turns it on, 0 off,
+// unset gives by_default (read at problem and batch creation)
+bool graphs_enabled(bool by_default);
 // validation, workspaces and cosine table before a setup of radius t;
 // num_shifts (0 = default) is replaced by the effective request
 int prepare_setup(lsp_problem* p, int t, int* num_shifts);

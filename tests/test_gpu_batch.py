@@ -84,12 +84,14 @@ SIZES_2D = [16, 32, 64, 128, 256, 64, 32, 128]
 
 @pytest.mark.parametrize("graphs", [True, False])
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batch_setup_equals_single_setups(torch_dev, graphs, precision):
+def test_batch_setup_equals_single_setups(torch_dev, graphs, precision, monkeypatch):
     torch, dev = torch_dev
-    stream = torch.cuda.Stream() if graphs else None
+    stream = torch.cuda.Stream()
+    monkeypatch.setenv("LSP_GRAPHS", "1" if graphs else "0")  # read at creation
     fields = [W.helm2d_random(n, seed=10 + i, t=2).v for i, n in enumerate(SIZES_2D)]
     nS = [max(1, n // 16) for n in SIZES_2D]
     batch, probs, Ps, idxs = run_batch(torch_dev, fields, 2, nS, precision, stream)
+    monkeypatch.delenv("LSP_GRAPHS", raising=False)
     tw, cand, ms = batch.tile()
     print(f"[batch] graphs={graphs} precision={precision} tile {tw} of {cand} ({ms} ms)",
           flush=True)
@@ -100,14 +102,16 @@ def test_batch_setup_equals_single_setups(torch_dev, graphs, precision):
         p.close()
 
 
-def test_batch_replay_with_new_potentials(torch_dev):
+def test_batch_replay_with_new_potentials(torch_dev, monkeypatch):
     """Second and third setups of the same batch (graph replays) follow new
     potentials set on the problems."""
     torch, dev = torch_dev
     stream = torch.cuda.Stream()
     sizes = [32, 64, 16]
     fields = [W.helm2d_random(n, seed=i, t=1).v for i, n in enumerate(sizes)]
+    monkeypatch.setenv("LSP_GRAPHS", "1")
     batch, probs, Ps, idxs = run_batch(torch_dev, fields, 1, None, 0, stream)
+    monkeypatch.delenv("LSP_GRAPHS")
     for rep in range(2):
         new = [W.helm2d_random(n, seed=100 + 10 * rep + i, t=1).v for i, n in enumerate(sizes)]
         for p, v in zip(probs, new):
@@ -132,14 +136,17 @@ def test_batch_3d(torch_dev):
         p.close()
 
 
-def test_batch_ps_apply(torch_dev):
+@pytest.mark.parametrize("graphs", [True, False])
+def test_batch_ps_apply(torch_dev, graphs, monkeypatch):
     torch, dev = torch_dev
     stream = torch.cuda.Stream()
     sizes = [16, 64, 256, 1024, 32]
     fields = [W.helm2d_random(n, seed=i, t=2).v for i, n in enumerate(sizes)]
     probs = make_problems(torch_dev, fields, stream)
     from paper_1607_02560_amd import lsp
+    monkeypatch.setenv("LSP_GRAPHS", "1" if graphs else "0")
     batch = lsp.Batch(probs)
+    monkeypatch.delenv("LSP_GRAPHS", raising=False)
     r = np.random.default_rng(4)
     us = [torch.from_numpy(r.standard_normal(n * n) + 1j * r.standard_normal(n * n)).to(dev)
           for n in sizes]

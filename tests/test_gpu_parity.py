@@ -408,20 +408,22 @@ def test_precond_solve_maxit(torch_dev):
 
 # ---------------------------------------------------------------- graphs ----
 def test_graph_replays_match_direct_launches(torch_dev, monkeypatch):
-    """The setup and apply sequences are captured in HIP graphs and replayed
-    while their arguments are unchanged. Several replays, with eager work and
-    synchronisation in between (new potentials), must give the same bits as a
-    problem that launches directly (LSP_NO_GRAPH=1)."""
+    """With LSP_GRAPHS=1 and a non-default stream the setup and apply
+    sequences are captured in HIP graphs and replayed while their arguments
+    are unchanged. Several replays, with eager work and synchronisation in
+    between (new potentials), must give the same bits as a problem that
+    launches directly (the default)."""
     torch, dev = torch_dev
     lsp = lsp_mod()
     n, t, nS = 128, 2, 8
     m = (2 * t + 1) ** 2
     r = np.random.default_rng(21)
-    monkeypatch.setenv("LSP_NO_GRAPH", "1")
+    stream = torch.cuda.Stream(dev)
     v0 = torch.from_numpy(r.uniform(-9e4, -2e4, n * n)).to(dev)
-    direct = lsp.Problem(2, n, v0)
-    monkeypatch.delenv("LSP_NO_GRAPH")
-    graphed = lsp.Problem(2, n, v0)
+    direct = lsp.Problem(2, n, v0, stream=stream)
+    monkeypatch.setenv("LSP_GRAPHS", "1")
+    graphed = lsp.Problem(2, n, v0, stream=stream)
+    monkeypatch.delenv("LSP_GRAPHS")
     Pg = torch.empty(n * n * m, dtype=torch.float64, device=dev)
     Pd = torch.empty_like(Pg)
     ig = torch.empty(n * n, dtype=torch.int32, device=dev)
@@ -434,6 +436,7 @@ def test_graph_replays_match_direct_launches(torch_dev, monkeypatch):
         graphed.set_potential(vr)
         direct.set_potential(vr)
         Pg.fill_(float("nan"))
+        torch.cuda.synchronize()  # torch's fill before the library's stream
         graphed.stencil_setup(t, nS, Pg, ig)
         direct.stencil_setup(t, nS, Pd, idd)
         graphed.ps_apply(u, yg)
