@@ -303,8 +303,15 @@ __device__ __forceinline__ void null_body(
   const int wid = tid >> 6;
 
   // ---- sum the partial sums of the Green's kernels (staged through LDS) ----
+  // Thread (grp, v) = (tid / NVP, tid % NVP) adds the partials of value v from
+  // work units b = grp, grp + G, ... in increasing b; then thread v adds the G
+  // group sums in group order (a fixed order, so the result is deterministic).
+  constexpr int NVP = (NV <= 32) ? 32 : 64;
+  constexpr int G = T / NVP;
+  static_assert(NV <= NVP && G >= 1, "partial-sum groups");
   const double* ps = part + (int64_t)si * nblk * NV;
-  double acc = 0.0;  // thread tid < NV owns value tid
+  const int gv = tid % NVP, grp = tid / NVP;
+  double acc = 0.0;
   const int total = nblk * NV;
   constexpr int CHUNK = 4096;
   for (int c0 = 0; c0 < total; c0 += CHUNK) {
@@ -323,16 +330,27 @@ __device__ __forceinline__ void null_body(
       if (e < cn) sh.stage[e] = tmp[u];
     }
     __syncthreads();
-    if (tid < NV) {
-      // entries of value tid inside this chunk: global index b*NV + tid
-      int e = (c0 / NV) * NV + tid;
-      if (e < c0) e += NV;
-      for (; e < c0 + cn; e += NV) acc += sh.stage[e - c0];
+    if (gv < NV) {
+      // units of this chunk holding value gv: global index b*NV + gv
+      const int b_first = c0 / NV, b_end = (c0 + cn + NV - 1) / NV;
+      int b = b_first + ((grp - b_first % G) + G) % G;
+      for (; b < b_end; b += G) {
+        const int e = b * NV + gv;
+        if (e >= c0 && e < c0 + cn) acc += sh.stage[e - c0];
+      }
     }
     __syncthreads();
   }
+  sh.stage[grp * NVP + gv] = acc;
+  __syncthreads();
+  double tot = 0.0;
+  if (tid < NV) {
+#pragma unroll
+    for (int q = 0; q < G; ++q) tot += sh.stage[q * NVP + tid];
+  }
+  __syncthreads();
   // symmetrised pair sums -> full tables, scaled by 1/N
-  if (tid < NV) sh.stage[tid] = acc;
+  if (tid < NV) sh.stage[tid] = tot;
   __syncthreads();
   for (int e = tid; e < WD; e += T) {
     const int db0 = e % W;
