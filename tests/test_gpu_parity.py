@@ -123,7 +123,7 @@ def check_setup(torch_dev, v, t, nS, full_P=True):
 
 # ------------------------------------------------------------- ps_apply ----
 @pytest.mark.parametrize("d,n", [(2, 8), (2, 16), (2, 32), (2, 64), (2, 128), (2, 256), (2, 512),
-                                 (2, 1024), (3, 8), (3, 16), (3, 32), (3, 64)])
+                                 (2, 1024), (3, 8), (3, 16), (3, 32), (3, 64), (3, 128)])
 def test_ps_apply_matches_oracle(torch_dev, d, n):
     torch, dev = torch_dev
     lsp = lsp_mod()
@@ -142,7 +142,7 @@ def test_ps_apply_matches_oracle(torch_dev, d, n):
     assert np.max(np.abs(y - y_or)) <= 1e-11 * np.max(np.abs(y_or))
 
 
-@pytest.mark.parametrize("d,n", [(2, 64), (3, 16)])
+@pytest.mark.parametrize("d,n", [(2, 64), (3, 16), (2, 1024), (3, 256)])
 def test_ps_apply_plane_waves(torch_dev, d, n):
     """Closed form: (L + v0) e_k = (4 pi^2 |k|^2 + v0) e_k."""
     torch, dev = torch_dev
@@ -195,6 +195,13 @@ def test_setup_schrod2d_wells(torch_dev):
 
 def test_setup_helm3d_random(torch_dev):
     p = W.helm3d_random(64)
+    check_setup(torch_dev, p.v, p.t, p.num_shifts)
+
+
+def test_setup_helm3d_random_n128(torch_dev):
+    """3D at n = 128 (2,097,152 points), |S| = 32: the largest 3D size the
+    oracle's FFT route finishes in seconds."""
+    p = W.helm3d_random(128)
     check_setup(torch_dev, p.v, p.t, p.num_shifts)
 
 
