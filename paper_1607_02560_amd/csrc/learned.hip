@@ -2,25 +2,29 @@
 // rows, the check of the predicted stencil against the exact Gram matrices of
 // eq. (A), and the exact row where the check fails, in one pass over the grid.
 //
-// Per block of 4 waves (persistent over chunks of 256 points, two blocks per
-// CU):
-//   * the network's BF16 weights, biases, standardisation and the shift list
-//     sit in LDS; one lane per point first finds its shift s_j (also the
-//     network's last input);
-//   * each wave evaluates 64 points as 4 groups of 16 with
+// One block of 8 waves per CU keeps the network's BF16 weights, biases,
+// standardisation, the shift list and, per shift, the tables g and g*g and
+// rho*(s) in LDS; each wave then works alone (no block barrier after the
+// loads) on chunks of 32 points:
+//   * one lane per point finds its shift s_j (also the network's last input);
+//   * the wave evaluates its 32 points as 2 groups of 16 with
 //     v_mfma_f32_16x16x16bf16 in the transposed form Z^T = W X^T, so that the
 //     accumulator layout of one layer (lane l holds rows 4(l/16)+i, column
 //     l%16) is exactly the B-operand layout of the next: activations never
 //     leave registers, and the output layer accumulates while the second
-//     hidden layer is produced;
-//   * the de-standardised outputs are written straight to the P and C rows;
-//     one lane per point reads its rows back (L2), forms q = p - c (v[mu_j] -
-//     s_j) and decides with one quadratic form q^T K_s q <= 0, K_s = M_s -
-//     (rho*(s) + threshold)^2 A1_s (eq. A), whose packed upper triangle is
-//     staged in LDS once per distinct shift of the wave and read as
-//     broadcasts; rows that fail are overwritten with the exact rows.
+//     hidden layer is produced; the check's gathers v[mu_j] are issued before
+//     the network so that it hides their latency;
+//   * the de-standardised FP32 outputs go to the wave's staging rows in LDS;
+//     lanes j and j + 32 read point j's row, form q = p - c (v[mu_j] - s_j)
+//     and split the forms of eq. (A): one accumulates q^T A1 q, the other
+//     |G q|^2 (G_ab = g[|a - b|], A1_ab = (g*g)[|a - b|]), each in the order
+//     of the unfused check; the point falls back when
+//     q^T M q > (rho*(s) + threshold)^2 q^T A1 q, M = A1 - G G;
+//   * the rows leave the staging area as contiguous (coalesced) stores of the
+//     wave's 32 x m blocks of P and C; entries of failed points are the exact
+//     rows alpha + C (v[mu_j] - s_j) and C.
 // Numerics equal the unfused path: the same BF16 roundings, FP32 bias and
-// SiLU, FP32 de-standardisation, FP64 check and rows.
+// SiLU, FP32 de-standardisation, FP64 check and rows, the same decisions.
 #include "setup_common.h"
 
 namespace {
@@ -34,10 +38,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 hbf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kH = 128;           // hidden width of the fused kernel
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;         // waves per block, one block per CU
 constexpr int kThreads = 64 * kWaves;
-constexpr int kPts = kThreads;    // points per block pass (one per lane)
+constexpr int kPW = 32;           // points per wave pass
+constexpr int kGroups = kPW / 16; // MFMA column groups per pass
 constexpr int kWStride = kH + 8;  // LDS row stride (bf16) of W2 and W3: 68 dwords
+constexpr size_t kLdsLimit = 163840;  // LDS bytes one workgroup may hold on gfx950
 
 // four FP32 values -> BF16 bits, round to nearest even (v_cvt_pk_bf16_f32),
 // the rounding of the unfused kernels
@@ -57,8 +63,12 @@ struct Fused {
   static constexpr int NI = M + 2, NO = 2 * M;
   static constexpr int IP = (NI + 15) / 16 * 16, OP = (NO + 15) / 16 * 16;
   static constexpr int W1S = IP + 8;     // LDS row stride of W1 (bf16): 12 or 20 dwords
-  static constexpr int MM = M * (M + 1) / 2;
-  static constexpr int KS = (MM + 15) / 16 * 16;  // doubles per shift of packed K
+  // staging row stride (floats): at least NO rounded up to 4, with stride / 4
+  // odd so that 16 lanes' 16-byte accesses to 16 consecutive rows hit
+  // distinct banks
+  static constexpr int SST0 = (NO + 3) / 4 * 4;
+  static constexpr int SST = ((SST0 / 4) % 2) ? SST0 : SST0 + 4;
+  static constexpr int NR = (NO + 3) / 4;  // 16-byte reads of one staged row
   static constexpr size_t oW1 = 0;
   static constexpr size_t oW2 = oW1 + 2 * (size_t)kH * W1S;
   static constexpr size_t oW3 = oW2 + 2 * (size_t)kH * kWStride;
@@ -69,84 +79,37 @@ struct Fused {
   static constexpr size_t oSX = oMX + 4 * IP;
   static constexpr size_t oMY = oSX + 4 * IP;
   static constexpr size_t oSY = oMY + 4 * OP;
-  static constexpr size_t oSV = (oSY + 4 * OP + 15) / 16 * 16;      // s_j, 64 per wave
-  static constexpr size_t oK = oSV + 8 * 64 * (size_t)kWaves;        // K_s, one per wave
-  static constexpr size_t oS = oK + 8 * (size_t)KS * kWaves;         // shift list
+  // per-wave area: s_j, 1/|s_j|, fallback flags, staged outputs
+  static constexpr size_t oWave = (oSY + 4 * OP + 15) / 16 * 16;
+  static constexpr size_t wSV = 0;
+  static constexpr size_t wINV = wSV + 8 * kPW;
+  static constexpr size_t wFLG = wINV + 8 * kPW;
+  static constexpr size_t wSID = wFLG + 4 * kPW;
+  static constexpr size_t wSTG = (wSID + 4 * kPW + 15) / 16 * 16;
+  static constexpr size_t WB = (wSTG + 4 * (size_t)kPW * SST + 15) / 16 * 16;
+  // per shift: S, the tables {(g*g)[k], g[k]} of eq. (A) and rho*(s); the
+  // tables start 16-byte aligned after the (even-padded) shift list
+  static constexpr size_t oS = oWave + WB * kWaves;
+  static constexpr size_t tab_off(int shifts) { return oS + 8 * (size_t)((shifts + 1) & ~1); }
+  static constexpr size_t rho_off(int shifts) { return tab_off(shifts) + 16 * (size_t)M * shifts; }
   // LDS bytes for a shift list of up to `shifts` entries
-  static constexpr size_t bytes(int shifts) { return oS + 8 * (size_t)shifts; }
+  static constexpr size_t bytes(int shifts) { return rho_off(shifts) + 8 * (size_t)shifts; }
   static_assert(IP <= 32 && OP <= 64, "fused kernel sizes");
+  static_assert(NR * 4 <= SST && wSTG % 16 == 0, "staging layout");
 };
+
+// makes the wave's LDS writes visible to its other lanes (LDS operations of a
+// wave complete in order; the fences keep the compiler from moving them)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // the same entry as the exact setup's assembly: product and sum rounded separately
 __device__ __forceinline__ double exact_entry(double alpha, double c, double v_minus_s) {
 #pragma clang fp contract(off)
   return alpha + c * v_minus_s;
-}
-
-// Packed K_s of every shift: for a <= b, K'[a][b] = (a == b ? 1 : 2) *
-// (M_ab - lim^2 A1_ab), lim = rho*(s) + thr, with A1_ab = gam[|a - b|],
-// M = A1 - G G (G_ab = g[|a - b|]; eq. A) and rho*(s) of the shift's exact
-// stencil alpha_s. One block of 256 threads per shift (tables staged in LDS);
-// block 0 also clears the fallback counter.
-template <int D, int W>
-__global__ __launch_bounds__(256) void kform_kernel(const double* __restrict__ gtab,
-                                                    const double* __restrict__ gamtab,
-                                                    const double2* __restrict__ actab,
-                                                    const int* __restrict__ nS_ptr, double thr,
-                                                    double* rho_star, double* Kf, int* nfall) {
-  using Nb = Nbhd<D, W>;
-  using F = Fused<D, W>;
-  constexpr int M = F::M;
-  const int si = blockIdx.x;
-  const int tid = threadIdx.x;
-  if (si == 0 && tid == 0) *nfall = 0;  // fallback count of the pass that follows
-  if (si >= *nS_ptr) return;            // uniform over the block
-  __shared__ double g[M], gm[M], al[M];
-  __shared__ int dix[M][M];             // table index of |a - b|
-  __shared__ double red[2][256];
-  if (tid < M) {
-    g[tid] = gtab[(int64_t)si * M + tid];
-    gm[tid] = gamtab[(int64_t)si * M + tid];
-    al[tid] = actab[(int64_t)si * M + tid].x;
-  }
-  for (int e = tid; e < M * M; e += 256) dix[e / M][e % M] = Nb::diff_index(e / M, e % M);
-  __syncthreads();
-  double u = 0.0, w = 0.0;
-  if (tid < M) {
-    for (int b = 0; b < M; ++b) {
-      u = fma(g[dix[tid][b]], al[b], u);
-      w = fma(gm[dix[tid][b]], al[b], w);
-    }
-    w *= al[tid];
-    u *= u;
-  }
-  red[0][tid] = u;
-  red[1][tid] = w;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (tid < o) {
-      red[0][tid] += red[0][tid + o];
-      red[1][tid] += red[1][tid + o];
-    }
-    __syncthreads();
-  }
-  const double qaq = red[1][0], qmq = qaq - red[0][0];
-  const double rs = sqrt(fmax(qmq, 0.0) / qaq);
-  if (tid == 0) rho_star[si] = rs;
-  const double lim = rs + thr, lim2 = lim * lim;
-  for (int e = tid; e < F::MM; e += 256) {
-    int r = 0, start = 0;
-    while (start + (M - r) <= e) {
-      start += M - r;
-      ++r;
-    }
-    const int c = r + (e - start);
-    double gg = 0.0;
-    for (int k = 0; k < M; ++k) gg = fma(g[dix[r][k]], g[dix[k][c]], gg);
-    const double a1 = gm[dix[r][c]];
-    const double kv = (a1 - gg) - lim2 * a1;
-    Kf[(int64_t)si * F::KS + e] = (r == c) ? kv : 2.0 * kv;
-  }
 }
 
 // flat index of (c + offset a) mod n for a runtime offset index a
@@ -198,13 +161,16 @@ struct NetPtrs {
 };
 
 template <int D, int W>
-__global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
+__global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     const double* __restrict__ v, int logn, int64_t N, double h2, const double* __restrict__ S,
-    const int* __restrict__ nS_ptr, const double2* __restrict__ actab,
-    const double* __restrict__ Kf, NetPtrs net, int nchunks, double* P, double* Crows,
-    int32_t* __restrict__ fallback, int* __restrict__ nfall) {
+    const int* __restrict__ nS_ptr, const double* __restrict__ gtab,
+    const double* __restrict__ gamtab, const double2* __restrict__ actab,
+    const double* __restrict__ rho_star, double thr, NetPtrs net, int64_t nchunks,
+    double* __restrict__ P, double* __restrict__ Crows, int32_t* __restrict__ fallback,
+    int* __restrict__ nfall) {
+  using Nb = Nbhd<D, W>;
   using F = Fused<D, W>;
-  constexpr int M = F::M, NI = F::NI, NO = F::NO, IP = F::IP, OP = F::OP;
+  constexpr int M = F::M, NI = F::NI, NO = F::NO, IP = F::IP, OP = F::OP, SST = F::SST;
   constexpr int KC1 = IP / 16, KC = kH / 16, OT = OP / 16;
   extern __shared__ __align__(16) char lds[];
   unsigned short* W1s = reinterpret_cast<unsigned short*>(lds + F::oW1);
@@ -219,8 +185,12 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
   float* sys = reinterpret_cast<float*>(lds + F::oSY);
   double* Ss = reinterpret_cast<double*>(lds + F::oS);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double* sw = reinterpret_cast<double*>(lds + F::oSV) + wave * 64;
-  double* Kw = reinterpret_cast<double*>(lds + F::oK) + wave * F::KS;
+  char* wa = lds + F::oWave + wave * F::WB;
+  double* sv = reinterpret_cast<double*>(wa + F::wSV);
+  double* iv = reinterpret_cast<double*>(wa + F::wINV);
+  int* flg = reinterpret_cast<int*>(wa + F::wFLG);
+  int* sidw = reinterpret_cast<int*>(wa + F::wSID);
+  float* stg = reinterpret_cast<float*>(wa + F::wSTG);
 
   // ---- network and shift list into LDS (once per block) ----
   for (int e = tid; e < kH * IP / 4; e += kThreads) {
@@ -252,28 +222,40 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
     sxs[e] = (e < NI) ? 1.0f / net.norm[NI + e] : 1.f;  // reciprocal deviation
   }
   const int nS = *nS_ptr;
-  for (int e = tid; e < nS; e += kThreads) Ss[e] = S[e];
-  __syncthreads();
+  double2* Tb = reinterpret_cast<double2*>(lds + F::tab_off(nS));
+  double* rs = reinterpret_cast<double*>(lds + F::rho_off(nS));
+  for (int e = tid; e < nS; e += kThreads) {
+    Ss[e] = S[e];
+    rs[e] = rho_star[e];
+  }
+  for (int e = tid; e < nS * M; e += kThreads) Tb[e] = make_double2(gamtab[e], gtab[e]);
+  __syncthreads();  // the last block-wide barrier: from here on every wave works alone
 
   const int r16 = lane & 15, qd = lane >> 4;
+  const int pl = lane & 31, half = lane >> 5;  // check: point pl, twice per wave
   int nf_local = 0;
-  for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const int64_t wbase = (int64_t)chunk * kPts + wave * 64;
-    // ---- the shift of each point (one lane per point) ----
-    const int64_t j = wbase + lane;
+  for (int64_t chunk = (int64_t)blockIdx.x * kWaves + wave; chunk < nchunks;
+       chunk += (int64_t)gridDim.x * kWaves) {
+    const int64_t wbase = chunk * kPW;
+    // ---- the shift of each point ----
+    const int64_t j = wbase + pl;
     const bool valid = j < N;
     int id = 0;
     if (valid) id = nearest_shift(Ss, nS, v[j]);
     const double s = Ss[id];
-    sw[lane] = s;
-    __syncthreads();
+    if (half == 0) {
+      sv[pl] = s;
+      iv[pl] = 1.0 / fabs(s);
+      sidw[pl] = id;
+    }
+    wave_sync();
 
-    // ---- network: 4 groups of 16 points per wave ----
+    // ---- network: 2 groups of 16 points ----
     // inputs: h^2 v_j, the patch h^2 v[j + a], h^2 s_j; every lane loads its
     // 4 KC1 values unconditionally (clamped addresses) so the loads overlap
-    bf16x4 xb[4][KC1];
+    bf16x4 xb[kGroups][KC1];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       const int64_t pt = wbase + 16 * g + r16;
       const bool pvalid = pt < N;
       const int64_t ptc = pvalid ? pt : 0;
@@ -289,7 +271,7 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
           const int64_t at = (k >= 1 && k <= M) ? neighbour_rt<D, W>(c, logn, a) : ptc;
           raw[kc][i] = v[at];
         }
-      const double sj = sw[16 * g + r16];
+      const double sj = sv[16 * g + r16];
 #pragma unroll
       for (int kc = 0; kc < KC1; ++kc) {
         f32x4 xf;
@@ -303,22 +285,29 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
         xb[g][kc] = to_bf16x4(xf);
       }
     }
-    bf16x4 a1[4][KC];
+    // the check's gathers v[mu_j] (lane pl: point j), issued here so that the
+    // network hides their latency
+    int c[D];
+    coords<D>(valid ? j : 0, logn, c);
+    double vq[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) vq[a] = v[neighbour_ct<D, W>(c, logn, a)];
+    bf16x4 a1[kGroups][KC];
 #pragma unroll
     for (int ht = 0; ht < KC; ++ht) {
-      f32x4 acc[4];
+      f32x4 acc[kGroups];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int g = 0; g < kGroups; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kc = 0; kc < KC1; ++kc) {
         const bf16x4 A =
             *reinterpret_cast<const bf16x4*>(W1s + (16 * ht + r16) * F::W1S + 16 * kc + 4 * qd);
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < kGroups; ++g)
           acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, xb[g][kc], acc[g], 0, 0, 0);
       }
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < kGroups; ++g) {
         f32x4 z;
 #pragma unroll
         for (int i = 0; i < 4; ++i) z[i] = silu(acc[g][i] + b1s[16 * ht + 4 * qd + i]);
@@ -327,27 +316,27 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
     }
     // second hidden layer tile by tile; each finished tile (16 hidden units)
     // is at once the next K chunk of the output layer
-    f32x4 acc3[4][OT];
+    f32x4 acc3[kGroups][OT];
 #pragma unroll
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < kGroups; ++g)
 #pragma unroll
       for (int ot = 0; ot < OT; ++ot) acc3[g][ot] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ht = 0; ht < KC; ++ht) {
-      f32x4 acc[4];
+      f32x4 acc[kGroups];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int g = 0; g < kGroups; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const bf16x4 A =
             *reinterpret_cast<const bf16x4*>(W2s + (16 * ht + r16) * kWStride + 16 * kc + 4 * qd);
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < kGroups; ++g)
           acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, a1[g][kc], acc[g], 0, 0, 0);
       }
-      bf16x4 a2[4];
+      bf16x4 a2[kGroups];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < kGroups; ++g) {
         f32x4 z;
 #pragma unroll
         for (int i = 0; i < 4; ++i) z[i] = silu(acc[g][i] + b2s[16 * ht + 4 * qd + i]);
@@ -358,135 +347,145 @@ __global__ __launch_bounds__(kThreads, 2) void learned_fused_kernel(
         const bf16x4 A =
             *reinterpret_cast<const bf16x4*>(W3s + (16 * ot + r16) * kWStride + 16 * ht + 4 * qd);
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+        for (int g = 0; g < kGroups; ++g)
           acc3[g][ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, a2[g], acc3[g][ot], 0, 0, 0);
       }
     }
-    // de-standardised outputs straight into the rows: P[pt][o] = y_o and
-    // C[pt][o - M] = y_o / |s_pt| (the kept rows)
+    // de-standardised outputs y_o to the staging row of their point
+    // (o < m: P entries, m <= o < 2m: C entries before the 1/|s| scaling)
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int64_t pt = wbase + 16 * g + r16;
-      if (pt < N) {
-        const double inv = 1.0 / fabs(sw[16 * g + r16]);
+    for (int g = 0; g < kGroups; ++g)
 #pragma unroll
-        for (int ot = 0; ot < OT; ++ot)
+      for (int ot = 0; ot < OT; ++ot) {
+        const int o0 = 16 * ot + 4 * qd;
+        if (o0 < NO) {
+          f32x4 y;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int o = 16 * ot + 4 * qd + i;
-            const float y = mys[o] + sys[o] * (acc3[g][ot][i] + b3s[o]);
-            if (o < M) P[pt * M + o] = (double)y;
-            else if (o < NO) Crows[pt * M + (o - M)] = (double)y * inv;
-          }
-      }
-    }
-    __syncthreads();  // the rows of the block's points are written
-
-    // ---- check, one lane per point ----
-    double vm[M], q[M];
-    if (valid) {
-      int c[D];
-      coords<D>(j, logn, c);
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        vm[a] = v[neighbour_ct<D, W>(c, logn, a)] - s;
-        q[a] = P[j * M + a] - Crows[j * M + a] * vm[a];
-      }
-    } else {
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        vm[a] = 0.0;
-        q[a] = 0.0;
-      }
-    }
-    // q^T K_s q, one pass per distinct shift of the wave: the wave copies the
-    // packed K_s into its LDS area, then the lanes of that shift read it as
-    // broadcasts
-    double form = 0.0;
-    bool todo = valid;
-    unsigned long long pending = __ballot(todo);
-    while (pending) {
-      const int sid = __builtin_amdgcn_readlane(id, __builtin_ctzll(pending));
-      const double2* Kg = reinterpret_cast<const double2*>(Kf + (int64_t)sid * F::KS);
-      double2* Kw2 = reinterpret_cast<double2*>(Kw);
-      constexpr int KV = (F::KS / 2 + 63) / 64;  // double2 per lane
-      double2 kv[KV];
-#pragma unroll
-      for (int u = 0; u < KV; ++u)
-        if (lane + 64 * u < F::KS / 2) kv[u] = Kg[lane + 64 * u];
-#pragma unroll
-      for (int u = 0; u < KV; ++u)
-        if (lane + 64 * u < F::KS / 2) Kw2[lane + 64 * u] = kv[u];
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (todo && id == sid) {
-        double f = 0.0;
-        int e = 0;
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-          double rsum = 0.0;
-#pragma unroll
-          for (int b = a; b < M; ++b) rsum = fma(Kw[e++], q[b], rsum);
-          f = fma(q[a], rsum, f);
+          for (int i = 0; i < 4; ++i)
+            y[i] = mys[o0 + i] + sys[o0 + i] * (acc3[g][ot][i] + b3s[o0 + i]);
+          *reinterpret_cast<f32x4*>(stg + (16 * g + r16) * SST + o0) = y;
         }
-        form = f;
-        todo = false;
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      pending = __ballot(todo);
-    }
-    double qq = 0.0;
+    wave_sync();
+
+    // ---- check, one lane per point (lanes pl and pl + 32 alike) ----
+    const double inv = iv[pl];
+    double q[M];
+    {
+      const float* row = stg + pl * SST;
+      f32x4 yr[F::NR];
 #pragma unroll
-    for (int a = 0; a < M; ++a) qq = fma(q[a], q[a], qq);
-    const bool ok = valid && isfinite(form) && (qq > 0.0) && (form <= 0.0);
-    if (valid && !ok) {  // the exact rows alpha + C (v[mu_j] - s_j) and C
-      const double2* act = actab + (int64_t)id * M;
+      for (int u = 0; u < F::NR; ++u) yr[u] = *reinterpret_cast<const f32x4*>(row + 4 * u);
 #pragma unroll
       for (int a = 0; a < M; ++a) {
-        const double2 ac = act[a];
-        P[j * M + a] = exact_entry(ac.x, ac.y, vm[a]);
-        Crows[j * M + a] = ac.y;
+        const double vm = vq[a] - s;
+        const double pa = (double)yr[a / 4][a % 4];
+        const double ca = (double)yr[(M + a) / 4][(M + a) % 4] * inv;
+        q[a] = pa - ca * vm;
       }
     }
-    if (valid) fallback[j] = ok ? 0 : 1;
-    nf_local += __popcll(__ballot(valid && !ok));
-    __syncthreads();  // sw and the rows are reused by the next chunk
+    // rho = sqrt(q^T M q / q^T A1 q) of eq. (A), M = A1 - G G, from the
+    // tables of the point's shift (G_ab = g[|a - b|], A1_ab = (g*g)[|a - b|]):
+    // lane pl accumulates q^T A1 q = sum_a q_a (A1 q)_a and lane pl + 32
+    // |G q|^2 = sum_a (G q)_a^2, each in the order of the unfused check, so
+    // both paths decide alike
+    double qaq, gq2;
+    {
+      const double* tab = reinterpret_cast<const double*>(Tb + id * M) + (half ? 1 : 0);
+      double tv[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) tv[k] = tab[2 * k];
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        double u = 0.0;
+#pragma unroll
+        for (int b = 0; b < M; ++b) u = fma(tv[Nb::diff_index(a, b)], q[b], u);
+        acc = fma(half ? u : q[a], u, acc);
+      }
+      const double other = __shfl_xor(acc, 32);
+      qaq = half ? other : acc;
+      gq2 = half ? acc : other;
+    }
+    const double qmq = qaq - gq2;
+    const double lim = rs[id] + thr;
+    const bool ok = valid && (qaq > 0.0) && isfinite(qmq) && (qmq <= lim * lim * qaq);
+    if (half == 0) {
+      flg[pl] = ok ? 0 : 1;
+      if (valid) fallback[j] = ok ? 0 : 1;
+    }
+    nf_local += __popcll(__ballot(half == 0 && valid && !ok));
+    wave_sync();
+
+    // ---- rows: the wave's 32 x m blocks of P and C leave as contiguous
+    // stores; entries of failed points are the exact rows alpha + C (v[mu_j] -
+    // s_j) and C ----
+    const int64_t rbase = wbase * M;
+    const int rend = (int)((N - wbase < kPW ? N - wbase : kPW) * M);  // entries of valid points
+    int ln = lane;
+    asm volatile("" : "+v"(ln));  // opaque per chunk: the index arithmetic stays in the loop
+#pragma unroll
+    for (int u = 0; u < (kPW * M + 63) / 64; ++u) {
+      const int e = ln + 64 * u;
+      if (e < rend) {
+        const int pt = e / M, a = e - pt * M;
+        const float yp = stg[pt * SST + a], yc = stg[pt * SST + M + a];
+        double pv, cv;
+        if (flg[pt] == 0) {
+          pv = (double)yp;
+          cv = (double)yc * iv[pt];
+        } else {
+          const double2 ac = actab[(int64_t)sidw[pt] * M + a];
+          int cp[D];
+          coords<D>(wbase + pt, logn, cp);
+          const double vm = v[neighbour_rt<D, W>(cp, logn, a)] - sv[pt];
+          pv = exact_entry(ac.x, ac.y, vm);
+          cv = ac.y;
+        }
+        P[rbase + e] = pv;
+        Crows[rbase + e] = cv;
+      }
+    }
+    wave_sync();  // the wave's LDS area is rewritten by its next chunk
   }
   if (lane == 0 && nf_local) atomicAdd(nfall, nf_local);
 }
 
 template <int D, int W>
 hipError_t launch_fused_dw(const lsp_problem* p, const lsp::MlpView& mv, double thr,
-                           double* rho_star, double* Kf, double* P, double* Crows,
-                           int32_t* fallback, int* nfall) {
+                           const double* rho_star, double* P, double* Crows, int32_t* fallback,
+                           int* nfall) {
   using F = Fused<D, W>;
-  hipLaunchKernelGGL((kform_kernel<D, W>), dim3(p->num_shifts), dim3(256), 0, p->stream,
-                     p->ws.gtab, p->ws.gamtab, reinterpret_cast<const double2*>(p->ws.actab),
-                     p->ws.nS, thr, rho_star, Kf, nfall);
   const size_t lds = F::bytes(p->num_shifts);
+  if (lds > kLdsLimit) return hipErrorInvalidValue;  // excluded by learned_fused_supported
   static size_t attr_bytes = 0;
+  static int per_cu = 1;
   if (attr_bytes < lds) {
-    const hipError_t e =
+    hipError_t e =
         hipFuncSetAttribute(reinterpret_cast<const void*>(&learned_fused_kernel<D, W>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    int nb = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void*>(&learned_fused_kernel<D, W>), kThreads, lds);
+    if (e != hipSuccess) return e;
+    if (nb < 1) return hipErrorInvalidConfiguration;
     attr_bytes = lds;
+    per_cu = nb;
   }
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);
   if (e != hipSuccess) return e;
-  const int64_t nchunks = (p->N + kPts - 1) / kPts;
-  const int blocks = (int)std::min<int64_t>(nchunks, 2 * (int64_t)cus);
+  const int64_t nchunks = (p->N + kPW - 1) / kPW;
+  const int64_t want = (nchunks + kWaves - 1) / kWaves;
+  const int blocks = (int)std::min<int64_t>(want, (int64_t)per_cu * cus);
   int logn = 0;
   while ((1 << logn) < p->n) ++logn;
   NetPtrs net{mv.W1, mv.W2, mv.W3, mv.b1, mv.b2, mv.b3, mv.norm};
   hipLaunchKernelGGL((learned_fused_kernel<D, W>), dim3(blocks), dim3(kThreads), lds,
                      p->stream, p->v, logn, p->N, 1.0 / ((double)p->n * p->n), p->ws.S, p->ws.nS,
-                     reinterpret_cast<const double2*>(p->ws.actab), Kf, net, (int)nchunks, P,
-                     Crows, fallback, nfall);
+                     p->ws.gtab, p->ws.gamtab, reinterpret_cast<const double2*>(p->ws.actab),
+                     rho_star, thr, net, nchunks, P, Crows, fallback, nfall);
   return hipGetLastError();
 }
 
@@ -497,27 +496,23 @@ namespace lsp {
 bool learned_fused_supported(const lsp_problem* p, const MlpView& mv) {
   const int W = 2 * p->t + 1;
   const bool shape = (p->d == 2 && (W == 3 || W == 5)) || (p->d == 3 && W == 3);
-  return shape && mv.n_hidden == kH;
-}
-
-size_t learned_kform_doubles(int d, int t) {
-  const int W = 2 * t + 1;
-  int M = 1;
-  for (int i = 0; i < d; ++i) M *= W;
-  const int MM = M * (M + 1) / 2;
-  return (size_t)(MM + 15) / 16 * 16;
+  if (!shape || mv.n_hidden != kH) return false;
+  size_t lds = 0;
+  if (p->d == 2) lds = (W == 3) ? Fused<2, 3>::bytes(p->num_shifts) : Fused<2, 5>::bytes(p->num_shifts);
+  else lds = Fused<3, 3>::bytes(p->num_shifts);
+  return lds <= kLdsLimit;
 }
 
 hipError_t launch_learned_fused(const lsp_problem* p, const MlpView& mv, double thr,
-                                double* rho_star, double* Kf, double* P, double* Crows,
+                                const double* rho_star, double* P, double* Crows,
                                 int32_t* fallback, int* nfall) {
   const int W = 2 * p->t + 1;
   if (p->d == 2 && W == 3)
-    return launch_fused_dw<2, 3>(p, mv, thr, rho_star, Kf, P, Crows, fallback, nfall);
+    return launch_fused_dw<2, 3>(p, mv, thr, rho_star, P, Crows, fallback, nfall);
   if (p->d == 2 && W == 5)
-    return launch_fused_dw<2, 5>(p, mv, thr, rho_star, Kf, P, Crows, fallback, nfall);
+    return launch_fused_dw<2, 5>(p, mv, thr, rho_star, P, Crows, fallback, nfall);
   if (p->d == 3 && W == 3)
-    return launch_fused_dw<3, 3>(p, mv, thr, rho_star, Kf, P, Crows, fallback, nfall);
+    return launch_fused_dw<3, 3>(p, mv, thr, rho_star, P, Crows, fallback, nfall);
   return hipErrorInvalidValue;
 }
 

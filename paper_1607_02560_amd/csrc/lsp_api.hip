@@ -517,18 +517,16 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "learned C rows"))) return rc;
     p->c_rows_cap = need;
   }
-  // one buffer: rho*(s) [num_shifts], the fallback count, and either the
-  // packed check forms K_s [num_shifts][kd] (fused pass) or the network's
-  // inputs [B][m+2] and outputs [B][2m] of one chunk (each part 256-byte aligned)
+  // one buffer: rho*(s) [num_shifts], the fallback count and, for the chunked
+  // path, the network's inputs [B][m+2] and outputs [B][2m] of one chunk (each
+  // part 256-byte aligned)
   const lsp::MlpView mv = lsp::mlp_view(mlp);
   const bool fused = lsp::learned_fused_supported(p, mv);
   const int B = lsp::mlp_batch_rows(mlp);
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
   const size_t off_nf = up(sizeof(double) * num_shifts);
   const size_t off_x = off_nf + 256;
-  const size_t kd = lsp::learned_kform_doubles(p->d, t);
-  const size_t off_y = off_x + (fused ? up(sizeof(double) * kd * num_shifts)
-                                      : up(sizeof(float) * (size_t)B * (m + 2)));
+  const size_t off_y = off_x + (fused ? 0 : up(sizeof(float) * (size_t)B * (m + 2)));
   const size_t bytes = off_y + (fused ? 0 : up(sizeof(float) * (size_t)B * 2 * m));
   if (p->learn_cap < bytes) {
     (void)hipStreamSynchronize(p->stream);
@@ -540,7 +538,6 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   double* rho_star = reinterpret_cast<double*>(p->learn_buf);
   int* nfall = reinterpret_cast<int*>(p->learn_buf + off_nf);
   float* X = reinterpret_cast<float*>(p->learn_buf + off_x);
-  double* Kf = reinterpret_cast<double*>(p->learn_buf + off_x);
   float* Y = reinterpret_cast<float*>(p->learn_buf + off_y);
   // the network's kernels run on the problem's stream below; work queued on
   // the network's own stream must be finished first
@@ -548,20 +545,19 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     const hipError_t es = hipStreamSynchronize(lsp::mlp_stream(mlp));
     if (es != hipSuccess) return lsp::hip_check(es, "surrogate stream");
   }
-  // the fused pass clears the counter itself (a kernel, not a memset node)
-  hipError_t e = fused ? hipSuccess : hipMemsetAsync(nfall, 0, sizeof(int), p->stream);
-  // exact tables (shift list, Green's sums, Gram matrices, null vectors)
+  // exact tables (shift list, Green's sums, Gram matrices, null vectors),
+  // then rho*(s) per shift (its kernel also clears the fallback counter)
   int blocks = 0;
-  if (e == hipSuccess) e = lsp::launch_minmax(p);
+  hipError_t e = lsp::launch_minmax(p);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts, &blocks);
   if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks);
+  if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star, nfall);
   if (fused) {
-    // one pass: network, check against K_s and rows
+    // one pass: network, check against eq. (A) and rows
     if (e == hipSuccess)
-      e = lsp::launch_learned_fused(p, mv, threshold, rho_star, Kf, P_dev, p->c_rows,
-                                    fallback_dev, nfall);
+      e = lsp::launch_learned_fused(p, mv, threshold, rho_star, P_dev, p->c_rows, fallback_dev,
+                                    nfall);
   } else {
-    if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star);
     // learned rows in chunks of B points, each checked against the exact tables
     for (int64_t j0 = 0; e == hipSuccess && j0 < p->N; j0 += B) {
       const int rows = (int)std::min<int64_t>(B, p->N - j0);

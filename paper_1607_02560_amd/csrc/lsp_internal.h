@@ -198,12 +198,12 @@ hipError_t launch_targets(const lsp_problem* p, const double* P, const int64_t* 
                           float* T);
 // fused learned setup (learned.hip): network, check and rows in one pass
 bool learned_fused_supported(const lsp_problem* p, const MlpView& mv);
-size_t learned_kform_doubles(int d, int t);  // packed K doubles per shift
 hipError_t launch_learned_fused(const lsp_problem* p, const MlpView& mv, double thr,
-                                double* rho_star, double* Kf, double* P, double* Crows,
+                                const double* rho_star, double* P, double* Crows,
                                 int32_t* fallback, int* nfall);
-// rho*(s) = sqrt(alpha^T M alpha / alpha^T A1 alpha) of every shift's exact stencil
-hipError_t launch_rho_star(const lsp_problem* p, double* rho_star);
+// rho*(s) = sqrt(alpha^T M alpha / alpha^T A1 alpha) of every shift's exact
+// stencil; also sets *nfall = 0 (a kernel store, not a memset)
+hipError_t launch_rho_star(const lsp_problem* p, double* rho_star, int* nfall);
 hipError_t launch_learned_rows(const lsp_problem* p, const double* rho_star, const float* Y,
                                int64_t j0, int rows, double thr, double* P, double* Crows,
                                int32_t* fallback, int* nfall);

@@ -220,32 +220,36 @@ def test_training_reduces_loss(torch_dev):
     mlp.close()
 
 
-# (d, n, t, hidden): the fused pass serves hidden width 128 with t = 1 (2D and
-# 3D) and t = 2 (2D); the other cases take the chunked path (network batches,
-# then a row kernel). n = 8 in 2D leaves most lanes of the fused pass idle.
-LEARNED_CASES = [(3, 16, 1, 128), (3, 16, 1, 64), (2, 32, 2, 128), (2, 32, 1, 128),
-                 (2, 8, 1, 128), (2, 32, 3, 128)]
+# (d, n, t, hidden, shifts): the fused pass serves hidden width 128 with t = 1
+# (2D and 3D) and t = 2 (2D) while its per-shift tables fit in LDS; the other
+# cases take the chunked path (network batches, then a row kernel): width 64,
+# t = 3, and 3D with 96 shifts (too many for the fused pass's LDS). n = 8 in
+# 2D leaves most lanes of the fused pass idle. shifts None: the workload's own.
+LEARNED_CASES = [(3, 16, 1, 128, None), (3, 16, 1, 64, None), (2, 32, 2, 128, None),
+                 (2, 32, 1, 128, None), (2, 8, 1, 128, None), (2, 32, 3, 128, None),
+                 (3, 16, 1, 128, 96)]
 
 
-@pytest.mark.parametrize("d,n,t,hidden", LEARNED_CASES)
-def test_learned_setup_rows_and_fallback(torch_dev, d, n, t, hidden):
+@pytest.mark.parametrize("d,n,t,hidden,shifts", LEARNED_CASES)
+def test_learned_setup_rows_and_fallback(torch_dev, d, n, t, hidden, shifts):
     """Kept rows are the network's output, fallback rows are the exact rows,
     and the decision matches the reference residual rho > rho* + threshold."""
     torch, dev = torch_dev
     from paper_1607_02560_amd import lsp
     mlp, _ = trained_net(torch_dev, steps=200, n=n, d=d, t=t, hidden=hidden)
     p = field(d, n, t, 0)
+    nS = p.num_shifts if shifts is None else shifts
     N, m = p.N, (2 * t + 1) ** d
     prob = lsp.Problem(d, n, torch.from_numpy(p.v.reshape(-1)).to(dev))
     Pex = torch.empty(N * m, dtype=torch.float64, device=dev)
-    prob.stencil_setup(t, p.num_shifts, Pex)
+    prob.stencil_setup(t, nS, Pex)
     Pl = torch.full((N * m,), float("nan"), dtype=torch.float64, device=dev)
     fb = torch.full((N,), -1, dtype=torch.int32, device=dev)
     thr = 0.01
-    nf = prob.stencil_setup_learned(mlp, t, p.num_shifts, thr, Pl, fb)
+    nf = prob.stencil_setup_learned(mlp, t, nS, thr, Pl, fb)
     fbh = fb.cpu().numpy()
     assert set(np.unique(fbh)) <= {0, 1} and int(fbh.sum()) == nf
-    print(f"[learned setup] d={d} n={n} t={t} hidden={hidden} threshold {thr}: "
+    print(f"[learned setup] d={d} n={n} t={t} hidden={hidden} shifts={nS} threshold {thr}: "
           f"{nf} of {N} rows fall back", flush=True)
     Pl_h = Pl.cpu().numpy().reshape(N, m)
     Pex_h = Pex.cpu().numpy().reshape(N, m)
