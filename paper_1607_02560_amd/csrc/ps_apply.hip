@@ -441,6 +441,33 @@ __device__ __forceinline__ void twiddle8(const double2* __restrict__ tw, int m, 
   }
 }
 
+// the four table entries twiddle8 reads for m, loaded ahead of their use
+struct Tw8Base {
+  double2 lo[3], hi;
+  __device__ __forceinline__ void load(const double2* __restrict__ tw, int m) {
+#pragma unroll
+    for (int r = 1; r < 4; ++r) lo[r - 1] = tw[m * r];
+    hi = tw[4 * m];
+  }
+  // w^(m k), k = 0..7, exactly as twiddle8 forms them
+  __device__ __forceinline__ void expand(double* wr, double* wi) const {
+    wr[0] = 1.0;
+    wi[0] = 0.0;
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+      wr[r] = lo[r - 1].x;
+      wi[r] = lo[r - 1].y;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double a = hi.x, b = hi.y;
+      if (r > 0) cmul(a, b, lo[r - 1].x, lo[r - 1].y);
+      wr[4 + r] = a;
+      wi[4 + r] = b;
+    }
+  }
+};
+
 // a double from lane c ^ h of the same 16-lane row
 template <int H>
 __device__ __forceinline__ double lane_xor(double x) {
@@ -551,6 +578,11 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
     es = st;
   }
   double2* Sm = sh + ml * LS;
+  // line map of steps 2-3: thread (k1, c) of line sl
+  const int sl = tid / T;
+  const int tau = tid % T;
+  const int k1 = tau / R;
+  const int c = tau % R;
 
   // 1. 8-point DFT over a, twiddle w_n^(t k1)
   double xr[8], xi[8], yr[8], yi[8], wr[8], wi[8];
@@ -563,6 +595,12 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
     xr[a] = val.x;
     xi[a] = val.y;
   }
+  // every twiddle of the kernel is loaded with the line, not after a barrier
+  Tw8Base tw_t, tw_c;
+  tw_t.load(tw, t);
+  tw_c.load(tw, 8 * c);
+  LaneTw<R> lt;
+  lt.load(tw, n, c);
   if constexpr (MODE == kAccum || MODE == kFinal) {
 #pragma unroll
     for (int a = 0; a < 8; ++a)
@@ -581,22 +619,16 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
     }
   }
   RegDft<8, -1>::template run<1>(xr, xi, yr, yi);
-  twiddle8(tw, t, wr, wi);
+  tw_t.expand(wr, wi);
 #pragma unroll
-  for (int k1 = 0; k1 < 8; ++k1) {
-    cmul(yr[k1], yi[k1], wr[k1], wi[k1]);
-    Sm[k1 * RS + t] = make_double2(yr[k1], yi[k1]);
+  for (int q = 0; q < 8; ++q) {
+    cmul(yr[q], yi[q], wr[q], wi[q]);
+    Sm[q * RS + t] = make_double2(yr[q], yi[q]);
   }
   __syncthreads();
 
   // 2. line map: thread (k1, c) runs the 8-point DFT over b of t = R b + c
-  const int sl = tid / T;
-  const int tau = tid % T;
   double2* Ss = sh + sl * LS;
-  const int k1 = tau / R;
-  const int c = tau % R;
-  LaneTw<R> lt;
-  lt.load(tw, n, c);
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
     const double2 val = Ss[k1 * RS + R * b + c];
@@ -604,7 +636,7 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
     xi[b] = val.y;
   }
   RegDft<8, -1>::template run<1>(xr, xi, yr, yi);
-  twiddle8(tw, 8 * c, wr, wi);
+  tw_c.expand(wr, wi);
 #pragma unroll
   for (int k2a = 0; k2a < 8; ++k2a) {
     cmul(yr[k2a], yi[k2a], wr[k2a], wi[k2a]);
@@ -639,7 +671,7 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
     xr[q] = val.x;
     xi[q] = val.y;
   }
-  twiddle8(tw, t, wr, wi);
+  tw_t.expand(wr, wi);
 #pragma unroll
   for (int q = 0; q < 8; ++q) cmulc(xr[q], xi[q], wr[q], wi[q]);
   RegDft<8, +1>::template run<1>(xr, xi, yr, yi);
