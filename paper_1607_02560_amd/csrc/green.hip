@@ -52,7 +52,7 @@ constexpr int kTile = 64;     // outer indices per unit (one per lane)
 constexpr int kKTile = 64;    // values of k_d per unit
 constexpr int kWaves = 4;     // shifts per block (one wave each)
 constexpr int kThreads = 64 * kWaves;
-constexpr size_t kResidencyLds = 40 * 1024;  // dynamic LDS per block (unused)
+constexpr size_t kResidencyLds = 40 * 1024;  // reserved, never accessed: caps residency (run_green)
 
 // kd terms [kd0, kd0 + U) of the inner sums T. MASKED applies the triangle
 // weights: 1 above, 1/2 on and 0 below the diagonal k_d = k_{d-1}, 0 for
