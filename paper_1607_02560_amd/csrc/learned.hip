@@ -3,9 +3,9 @@
 // eq. (A), and the exact row where the check fails, in one pass over the grid.
 //
 // One block of 8 waves per CU keeps the network's BF16 weights, biases,
-// standardisation, the shift list and, per shift, the tables g and g*g and
-// rho*(s) in LDS; each wave then works alone (no block barrier after the
-// loads) on chunks of 32 points:
+// standardisation, the shift list and, per shift, the upper triangles of the
+// parity blocks of A1 and M (see PForms) and rho*(s) in LDS; each wave then
+// works alone (no block barrier after the loads) on chunks of 32 points:
 //   * one lane per point finds its shift s_j (also the network's last input);
 //   * the wave evaluates its 32 points as 2 groups of 16 with
 //     v_mfma_f32_16x16x16bf16 in the transposed form Z^T = W X^T, so that the
@@ -15,22 +15,27 @@
 //     hidden layer is produced; the check's gathers v[mu_j] are issued before
 //     the network so that it hides their latency;
 //   * the de-standardised FP32 outputs go to the wave's staging rows in LDS;
-//     lanes j and j + 32 read point j's row, form q = p - c (v[mu_j] - s_j)
-//     and split the forms of eq. (A): one accumulates q^T A1 q, the other
-//     |G q|^2 (G_ab = g[|a - b|], A1_ab = (g*g)[|a - b|]), each in the order
-//     of the unfused check; the point falls back when
-//     q^T M q > (rho*(s) + threshold)^2 q^T A1 q, M = A1 - G G;
+//     lanes j and j + 32 read point j's row, form q = p - c (v[mu_j] - s_j),
+//     take its parity coordinates and split the forms of eq. (A): one
+//     accumulates q^T A1 q, the other q^T M q (M = A1 - G G), each from the
+//     block triangles of the point's shift; the point falls back when
+//     q^T M q > (rho*(s) + threshold)^2 q^T A1 q;
 //   * the rows leave the staging area as contiguous (coalesced) stores of the
 //     wave's 32 x m blocks of P and C; entries of failed points are the exact
 //     rows alpha + C (v[mu_j] - s_j) and C.
-// Numerics equal the unfused path: the same BF16 roundings, FP32 bias and
-// SiLU, FP32 de-standardisation, FP64 check and rows, the same decisions.
+// Numerics equal the unfused path (the same BF16 roundings, FP32 bias and
+// SiLU, FP32 de-standardisation, FP64 rows); its check sums the dense forms
+// instead of the parity blocks, so the two decide alike except within
+// rounding of the boundary.
+#include <utility>
+
 #include "setup_common.h"
 
 namespace {
 
 using lsp::nearest_shift;
 using lsp::Nbhd;
+using lsp::Parity;
 using lsp::Pow;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
@@ -54,6 +59,113 @@ __device__ __forceinline__ bf16x4 to_bf16x4(f32x4 x) {
 // SiLU with the logistic function of the unfused kernels (hardware reciprocal)
 __device__ __forceinline__ float silu(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+// The check's forms in the parity basis of the neighbourhood. M = A1 - G G
+// and A1 are block diagonal there (one block per parity class; the exact
+// setup stores both per shift as packed blocks), so
+//   q^T A1 q = sum_c u_c^T A1'_c u_c,   q^T M q = sum_c u_c^T M'_c u_c,
+// with u the coordinates of q in the unnormalised basis (entries +-1, the
+// orthonormal basis without its 1/sqrt2 factors: u = sums and differences of
+// reflected entries of q) and A1' = S A1_b S, M' = S M_b S, S the diagonal
+// of those factors. Only the upper triangles are kept, off-diagonal entries
+// doubled: 76 entries per form for d = 3, t = 1 instead of the m^2 = 729 of
+// the dense forms.
+template <int D, int W>
+struct PForms {
+  using Pa = Parity<D, W>;
+  using Nb = Nbhd<D, W>;
+  static constexpr int NC = Pa::NC;
+  static constexpr int M = Pow<D, W>::v;
+  __host__ __device__ static constexpr int base(int c) {  // first coordinate of class c
+    int b = 0;
+    for (int k = 0; k < c; ++k) b += Pa::size(k);
+    return b;
+  }
+  __host__ __device__ static constexpr int tri(int c) {  // first triangle entry of class c
+    int o = 0;
+    for (int k = 0; k < c; ++k) o += Pa::size(k) * (Pa::size(k) + 1) / 2;
+    return o;
+  }
+  static constexpr int TRI = tri(NC);
+  static constexpr int TRIP = TRI | 1;  // odd stride: shifts fall on different LDS banks
+  // number of axes with a nonzero 1D index in row p of class c
+  __host__ __device__ static constexpr int nz(int c, int p) {
+    int z = 0;
+    for (int i = 0; i < D; ++i) z += (Pa::coord(c, p, i) != 0) ? 1 : 0;
+    return z;
+  }
+  // class, row and column of upper-triangle entry k (rows in order, then columns)
+  __host__ __device__ static constexpr int cls(int k) {
+    int c = 0;
+    while (k >= tri(c + 1)) ++c;
+    return c;
+  }
+  __host__ __device__ static constexpr int row(int k) {
+    const int c = cls(k), B = Pa::size(c);
+    int e = k - tri(c), pr = 0;
+    while (e >= B - pr) {
+      e -= B - pr;
+      ++pr;
+    }
+    return pr;
+  }
+  __host__ __device__ static constexpr int col(int k) {
+    const int c = cls(k), B = Pa::size(c);
+    int e = k - tri(c), pr = 0;
+    while (e >= B - pr) {
+      e -= B - pr;
+      ++pr;
+    }
+    return pr + e;
+  }
+  // contribution of offset a to class c: 0 if none, else +-(row + 1)
+  __host__ __device__ static constexpr int term(int a, int c) {
+    int pidx = 0, sgn = 1;
+    for (int i = 0; i < D; ++i) {
+      const int x = Nb::comp(a, i);
+      const int j = x < 0 ? -x : x;
+      const int o = Pa::odd(c, i);
+      if (o && j == 0) return 0;
+      if (o && x < 0) sgn = -sgn;
+      pidx = pidx * Pa::count(c, i) + (j - o);
+    }
+    return sgn * (pidx + 1);
+  }
+};
+
+// u += the contribution of q[A] to class C (indices are template constants,
+// so u stays in registers)
+template <int D, int W, int A, int C>
+__device__ __forceinline__ void parity_term(const double* q, double* u) {
+  using PF = PForms<D, W>;
+  constexpr int tm = PF::term(A, C);
+  if constexpr (tm > 0) u[PF::base(C) + tm - 1] += q[A];
+  if constexpr (tm < 0) u[PF::base(C) - tm - 1] -= q[A];
+}
+template <int D, int W, int... I>
+__device__ __forceinline__ void parity_coords(const double* q, double* u,
+                                              std::integer_sequence<int, I...>) {
+  constexpr int NC = 1 << D;
+  (parity_term<D, W, I / NC, I % NC>(q, u), ...);
+}
+
+// one triangle entry K of the form u^T T u = sum_p u_p (sum_{q >= p} T'_pq u_q)
+template <int D, int W, int K>
+__device__ __forceinline__ void form_term(const double* tb, const double* u, double& r,
+                                          double& acc) {
+  using PF = PForms<D, W>;
+  constexpr int c = PF::cls(K), pr = PF::row(K), qc = PF::col(K), b0 = PF::base(c);
+  if constexpr (qc == pr) r = 0.0;
+  r = fma(tb[2 * K], u[b0 + qc], r);
+  if constexpr (qc == Parity<D, W>::size(c) - 1) acc = fma(u[b0 + pr], r, acc);
+}
+template <int D, int W, int... K>
+__device__ __forceinline__ double parity_form(const double* tb, const double* u,
+                                              std::integer_sequence<int, K...>) {
+  double r = 0.0, acc = 0.0;
+  (form_term<D, W, K>(tb, u, r, acc), ...);
+  return acc;
 }
 
 // Compile-time geometry of the fused kernel for neighbourhood mu_0^t in D dims.
@@ -87,11 +199,12 @@ struct Fused {
   static constexpr size_t wSID = wFLG + 4 * kPW;
   static constexpr size_t wSTG = (wSID + 4 * kPW + 15) / 16 * 16;
   static constexpr size_t WB = (wSTG + 4 * (size_t)kPW * SST + 15) / 16 * 16;
-  // per shift: S, the tables {(g*g)[k], g[k]} of eq. (A) and rho*(s); the
-  // tables start 16-byte aligned after the (even-padded) shift list
+  // per shift: S, the Gram triangles {A1', M'} (PForms) and rho*(s); the
+  // triangles start 16-byte aligned after the (even-padded) shift list
+  static constexpr int TRIP = PForms<D, W>::TRIP;
   static constexpr size_t oS = oWave + WB * kWaves;
   static constexpr size_t tab_off(int shifts) { return oS + 8 * (size_t)((shifts + 1) & ~1); }
-  static constexpr size_t rho_off(int shifts) { return tab_off(shifts) + 16 * (size_t)M * shifts; }
+  static constexpr size_t rho_off(int shifts) { return tab_off(shifts) + 16 * (size_t)TRIP * shifts; }
   // LDS bytes for a shift list of up to `shifts` entries
   static constexpr size_t bytes(int shifts) { return rho_off(shifts) + 8 * (size_t)shifts; }
   static_assert(IP <= 32 && OP <= 64, "fused kernel sizes");
@@ -163,12 +276,13 @@ struct NetPtrs {
 template <int D, int W>
 __global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     const double* __restrict__ v, int logn, int64_t N, double h2, const double* __restrict__ S,
-    const int* __restrict__ nS_ptr, const double* __restrict__ gtab,
-    const double* __restrict__ gamtab, const double2* __restrict__ actab,
+    const int* __restrict__ nS_ptr, const double* __restrict__ Mtab,
+    const double2* __restrict__ actab,
     const double* __restrict__ rho_star, double thr, NetPtrs net, int64_t nchunks,
     double* __restrict__ P, double* __restrict__ Crows, int32_t* __restrict__ fallback,
     int* __restrict__ nfall) {
-  using Nb = Nbhd<D, W>;
+  using Pa = Parity<D, W>;
+  using PF = PForms<D, W>;
   using F = Fused<D, W>;
   constexpr int M = F::M, NI = F::NI, NO = F::NO, IP = F::IP, OP = F::OP, SST = F::SST;
   constexpr int KC1 = IP / 16, KC = kH / 16, OT = OP / 16;
@@ -228,7 +342,29 @@ __global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 
     Ss[e] = S[e];
     rs[e] = rho_star[e];
   }
-  for (int e = tid; e < nS * M; e += kThreads) Tb[e] = make_double2(gamtab[e], gtab[e]);
+  // triangle entry k of shift si: {A1'[p][q], M'[p][q]} of its class block,
+  // scaled by the 1/sqrt2 factors of rows p and q, off-diagonals doubled
+  for (int e = tid; e < nS * PF::TRI; e += kThreads) {
+    const int si = e / PF::TRI;
+    int k = e - si * PF::TRI, c = 0;
+    while (k >= Pa::size(c) * (Pa::size(c) + 1) / 2) {
+      k -= Pa::size(c) * (Pa::size(c) + 1) / 2;
+      ++c;
+    }
+    const int B = Pa::size(c);
+    int pr = 0;
+    while (k >= B - pr) {
+      k -= B - pr;
+      ++pr;
+    }
+    const int qc = pr + k;
+    const int z = PF::nz(c, pr) + PF::nz(c, qc);
+    double f = ldexp(1.0, -(z / 2));
+    if (z & 1) f *= lsp::kInvSqrt2;
+    if (qc != pr) f *= 2.0;
+    const double* blk = Mtab + (int64_t)si * M * M + Pa::offset(c) + pr * B + qc;
+    Tb[si * PF::TRIP + (e - si * PF::TRI)] = make_double2(blk[Pa::offset(Pa::NC)] * f, blk[0] * f);
+  }
   __syncthreads();  // the last block-wide barrier: from here on every wave works alone
 
   const int r16 = lane & 15, qd = lane >> 4;
@@ -384,30 +520,21 @@ __global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 
         q[a] = pa - ca * vm;
       }
     }
-    // rho = sqrt(q^T M q / q^T A1 q) of eq. (A), M = A1 - G G, from the
-    // tables of the point's shift (G_ab = g[|a - b|], A1_ab = (g*g)[|a - b|]):
-    // lane pl accumulates q^T A1 q = sum_a q_a (A1 q)_a and lane pl + 32
-    // |G q|^2 = sum_a (G q)_a^2, each in the order of the unfused check, so
-    // both paths decide alike
-    double qaq, gq2;
+    // rho = sqrt(q^T M q / q^T A1 q) of eq. (A) in the parity basis: u are
+    // q's unnormalised parity coordinates; lane pl accumulates u^T A1' u, lane
+    // pl + 32 u^T M' u from the point's shift triangles
+    double qaq, qmq;
     {
-      const double* tab = reinterpret_cast<const double*>(Tb + id * M) + (half ? 1 : 0);
-      double tv[M];
+      double u[M];
 #pragma unroll
-      for (int k = 0; k < M; ++k) tv[k] = tab[2 * k];
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < M; ++a) {
-        double u = 0.0;
-#pragma unroll
-        for (int b = 0; b < M; ++b) u = fma(tv[Nb::diff_index(a, b)], q[b], u);
-        acc = fma(half ? u : q[a], u, acc);
-      }
+      for (int k = 0; k < M; ++k) u[k] = 0.0;
+      parity_coords<D, W>(q, u, std::make_integer_sequence<int, M * PF::NC>{});
+      const double* tb = reinterpret_cast<const double*>(Tb + id * PF::TRIP) + (half ? 1 : 0);
+      const double acc = parity_form<D, W>(tb, u, std::make_integer_sequence<int, PF::TRI>{});
       const double other = __shfl_xor(acc, 32);
       qaq = half ? other : acc;
-      gq2 = half ? acc : other;
+      qmq = half ? acc : other;
     }
-    const double qmq = qaq - gq2;
     const double lim = rs[id] + thr;
     const bool ok = valid && (qaq > 0.0) && isfinite(qmq) && (qmq <= lim * lim * qaq);
     if (half == 0) {
@@ -484,8 +611,8 @@ hipError_t launch_fused_dw(const lsp_problem* p, const lsp::MlpView& mv, double 
   NetPtrs net{mv.W1, mv.W2, mv.W3, mv.b1, mv.b2, mv.b3, mv.norm};
   hipLaunchKernelGGL((learned_fused_kernel<D, W>), dim3(blocks), dim3(kThreads), lds,
                      p->stream, p->v, logn, p->N, 1.0 / ((double)p->n * p->n), p->ws.S, p->ws.nS,
-                     p->ws.gtab, p->ws.gamtab, reinterpret_cast<const double2*>(p->ws.actab),
-                     rho_star, thr, net, nchunks, P, Crows, fallback, nfall);
+                     p->ws.Mtab, reinterpret_cast<const double2*>(p->ws.actab), rho_star, thr,
+                     net, nchunks, P, Crows, fallback, nfall);
   return hipGetLastError();
 }
 
