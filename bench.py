@@ -49,11 +49,11 @@ HBM_PEAK_GBPS = 8000.0
 # sources they were taken on (sha256 prefix of the files below); for any
 # other sources the traffic is reported as null.
 ASSEMBLE_PMC = {
-    "fetch_kib": 5292.3, "write_kib": 208896.0,
-    "fetch_scale": 262144.0 / 131084.5, "write_scale": 262144.0 / 262144.0,
+    "fetch_kib": 5285.8, "write_kib": 208896.0,
+    "fetch_scale": 262144.0 / 131085.6, "write_scale": 262144.0 / 262144.0,
     "sources": ("paper_1607_02560_amd/csrc/assemble.hip",
                 "paper_1607_02560_amd/csrc/setup_common.h"),
-    "sources_sha256": "b42acf60d3c13bc6",
+    "sources_sha256": "96ce7523714ff974",
 }
 
 
@@ -74,8 +74,11 @@ def assemble_traffic():
 def algorithmic_bytes(N, m):
     """Minimum HBM traffic per call (see the design notes):
     setup reads v (8 B/pt) and writes P (8 m B/pt) and idx (4 B/pt);
-    ps_apply reads u (16 B) and v (8 B) and writes y (16 B) per point."""
-    return {"assemble": N * (8 + 8 * m + 4), "setup": N * (8 + 8 * m + 4), "apply": N * 40}
+    ps_apply reads u (16 B) and v (8 B) and writes y (16 B) per point;
+    the C-apply reads r (16 B) and v (8 B, for the point's shift) and writes
+    z (16 B) per point."""
+    return {"assemble": N * (8 + 8 * m + 4), "setup": N * (8 + 8 * m + 4), "apply": N * 40,
+            "c_apply": N * 40}
 
 
 def timed(stream, fn, reps):
@@ -320,6 +323,13 @@ def main():
     # setup alone and apply alone, K calls each
     t_setup = timed(stream, lambda: prob.stencil_setup(t, p.num_shifts, P, idx), args.steps)
     t_apply = timed(stream, lambda: prob.ps_apply(u, y), args.steps)
+    # the C-apply z = C r of the preconditioner (once per GMRES iteration) on
+    # the tables of this setup
+    zc = torch.empty_like(u)
+    for _ in range(args.warmup):
+        prob.c_apply(u, zc)
+    t_capply = timed(stream, lambda: prob.c_apply(u, zc), args.steps)
+    del zc
     # the FP32-storage form: same FP64 setup, P rows rounded to float32
     P32 = torch.empty(N * m, dtype=torch.float32, device=dev)
     setup32 = lambda: prob.stencil_setup(t, p.num_shifts, P32, idx, precision=lsp.LSP_FP32_REFINE)
@@ -344,6 +354,7 @@ def main():
     t_asm = avg_ms("assemble") * 1e-3
     asm_gbps = nb["assemble"] / t_asm / 1e9
     apply_gbps = nb["apply"] / t_apply / 1e9
+    capply_gbps = nb["c_apply"] / t_capply / 1e9
     out = {
         "metric": METRIC,
         "value": N / t_setup,
@@ -378,6 +389,10 @@ def main():
         "roofline_ps_apply": {"bound": "hbm", "achieved": apply_gbps, "peak": HBM_PEAK_GBPS,
                               "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
                               "bytes_per_call": nb["apply"]},
+        "c_apply_ms": t_capply * 1e3,
+        "roofline_c_apply": {"bound": "hbm", "achieved": capply_gbps, "peak": HBM_PEAK_GBPS,
+                             "unit": "GB/s", "frac": capply_gbps / HBM_PEAK_GBPS,
+                             "bytes_per_call": nb["c_apply"]},
     }
     prob.close()
     del P, idx

@@ -278,21 +278,18 @@ hipError_t run_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   }
 }
 
+// C-apply tiles: 4 rows of up to 64 points, one point per thread (wider
+// tiles put several points on a thread, whose table gathers then wait in
+// sequence: 23.2 us against 17.1 us at 2D n = 1024)
 template <int D, int W>
 hipError_t run_c_apply(const lsp_problem* p, const double* r, double* z) {
-  const int cap = (D == 2) ? 256 : 64;
+  const int cap = 64;
   const int tw = p->n < cap ? p->n : cap;
   switch (tw) {
     case 8: return run_c_apply_tw<D, W, 8>(p, r, z);
     case 16: return run_c_apply_tw<D, W, 16>(p, r, z);
     case 32: return run_c_apply_tw<D, W, 32>(p, r, z);
     case 64: return run_c_apply_tw<D, W, 64>(p, r, z);
-    case 128:
-      if constexpr (D == 2) return run_c_apply_tw<D, W, 128>(p, r, z);
-      break;
-    case 256:
-      if constexpr (D == 2) return run_c_apply_tw<D, W, 256>(p, r, z);
-      break;
   }
   return hipErrorInvalidValue;
 }
