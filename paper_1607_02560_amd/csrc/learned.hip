@@ -273,8 +273,11 @@ struct NetPtrs {
   const float* norm;         // mu_x [NI], sd_x [NI], mu_y [NO], sd_y [NO]
 };
 
+// One 8-wave block per CU (its LDS allows no second), i.e. two waves per
+// SIMD: the attribute lets the compiler schedule for exactly that occupancy.
 template <int D, int W>
-__global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
+__global__ __launch_bounds__(kThreads, 1)
+__attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     const double* __restrict__ v, int logn, int64_t N, double h2, const double* __restrict__ S,
     const int* __restrict__ nS_ptr, const double* __restrict__ Mtab,
     const double2* __restrict__ actab,
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 
   int* sidw = reinterpret_cast<int*>(wa + F::wSID);
   float* stg = reinterpret_cast<float*>(wa + F::wSTG);
 
-  // ---- network and shift list into LDS (once per block) ----
+  // ---- network, shift list, Gram triangles and rho* into LDS (once per block) ----
   for (int e = tid; e < kH * IP / 4; e += kThreads) {
     const int r = e / (IP / 4), c = (e % (IP / 4)) * 4;
     *reinterpret_cast<uint2*>(W1s + r * F::W1S + c) =
@@ -345,25 +348,14 @@ __global__ __launch_bounds__(kThreads, 1) __attribute__((amdgpu_waves_per_eu(2, 
   // triangle entry k of shift si: {A1'[p][q], M'[p][q]} of its class block,
   // scaled by the 1/sqrt2 factors of rows p and q, off-diagonals doubled
   for (int e = tid; e < nS * PF::TRI; e += kThreads) {
-    const int si = e / PF::TRI;
-    int k = e - si * PF::TRI, c = 0;
-    while (k >= Pa::size(c) * (Pa::size(c) + 1) / 2) {
-      k -= Pa::size(c) * (Pa::size(c) + 1) / 2;
-      ++c;
-    }
-    const int B = Pa::size(c);
-    int pr = 0;
-    while (k >= B - pr) {
-      k -= B - pr;
-      ++pr;
-    }
-    const int qc = pr + k;
+    const int si = e / PF::TRI, k = e - si * PF::TRI;
+    const int c = PF::cls(k), pr = PF::row(k), qc = PF::col(k), B = Pa::size(c);
     const int z = PF::nz(c, pr) + PF::nz(c, qc);
     double f = ldexp(1.0, -(z / 2));
     if (z & 1) f *= lsp::kInvSqrt2;
     if (qc != pr) f *= 2.0;
     const double* blk = Mtab + (int64_t)si * M * M + Pa::offset(c) + pr * B + qc;
-    Tb[si * PF::TRIP + (e - si * PF::TRI)] = make_double2(blk[Pa::offset(Pa::NC)] * f, blk[0] * f);
+    Tb[si * PF::TRIP + k] = make_double2(blk[Pa::offset(Pa::NC)] * f, blk[0] * f);
   }
   __syncthreads();  // the last block-wide barrier: from here on every wave works alone
 
