@@ -325,7 +325,10 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
                             void* const* P_dev, int32_t* const* idx_dev);
 
 /* y_i = (L + diag v_i) u_i (Sec. 2) for every problem i: u_dev[i], y_dev[i]
- * device complex128 of N_i entries, distinct. Asynchronous. */
+ * device complex128 of N_i entries. The problems may run concurrently, so no
+ * y_dev[i] may overlap any u_dev[j] or another y_dev[j] (identical pointers
+ * are refused with LSP_EINVAL; partial overlaps are not detected).
+ * Asynchronous. */
 int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* y_dev);
 
 /* The assembly tile width the tuner chose (0 before the first setup), and

@@ -4,8 +4,9 @@
 // work items of all problems, so small problems share the GPU instead of
 // each taking a launch sequence of its own. The four launches are captured
 // once into a HIP graph and replayed while the arguments are unchanged, and
-// the batched pseudospectral apply is one graph over every problem's apply
-// (LSP_GRAPHS=0 launches directly). The tables and rows each problem receives are those of its own
+// the batched pseudospectral apply is one graph over every problem's apply,
+// the problems as parallel branches (LSP_GRAPHS=0 launches directly, one
+// problem after another). The tables and rows each problem receives are those of its own
 // single-problem setup (same kernels, same arithmetic), so every per-problem
 // entry point (C-apply, GMRES, table export) works on them afterwards.
 //
@@ -42,6 +43,13 @@ struct lsp_batch {
   hipGraphExec_t g_apply = nullptr;
   std::vector<uint64_t> apply_key;
   bool use_graphs = true;
+  // the captured apply forks onto these streams, so that independent
+  // problems become parallel branches of its graph (default priority)
+  static constexpr int kBranches = 8;
+  hipStream_t aux[kBranches] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBranches] = {};
+  bool branches = false;
 };
 
 namespace {
@@ -190,6 +198,14 @@ int lsp_batch_create(int count, lsp_problem* const* problems, lsp_batch** out) {
   // graph replay on by default here: the four batched launches take 0.33-0.35 ms
   // as a graph replay against 0.43 ms launched directly (64-problem workload)
   b->use_graphs = lsp::graphs_enabled(true);
+  if (b->use_graphs && b->stream) {
+    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; ok && k < lsp_batch::kBranches; ++k)
+      ok = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+    b->branches = ok;  // without them the captured apply stays one chain
+    if (!ok) (void)hipGetLastError();
+  }
   *out = b;
   return LSP_OK;
 }
@@ -199,6 +215,11 @@ void lsp_batch_destroy(lsp_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   drop(b->g_setup);
   drop(b->g_apply);
+  for (int k = 0; k < lsp_batch::kBranches; ++k) {
+    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->recs) (void)hipFree(b->recs);
   if (b->maps) (void)hipFree(b->maps);
   delete b;
@@ -335,12 +356,40 @@ int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* 
     key.push_back((uint64_t)(uintptr_t)y_dev[i]);
     key.push_back(b->probs[i]->ws_gen);
   }
-  const hipError_t e = run_batch_graph(b, b->g_apply, b->apply_key, key, [&]() {
-    for (int i = 0; i < count; ++i) {
-      const hipError_t le = lsp::launch_ps_apply(b->probs[i], u_dev[i], y_dev[i]);
-      if (le != hipSuccess) return le;
+  // the problems may run concurrently: an output may not be another's buffer
+  for (int i = 0; i < count; ++i)
+    for (int k = 0; k < count; ++k)
+      if (k != i && (y_dev[i] == y_dev[k] || y_dev[i] == u_dev[k]))
+        return lsp::set_error(LSP_EINVAL, "apply " + std::to_string(i) +
+                                              ": y aliases a buffer of problem " +
+                                              std::to_string(k));
+  const hipError_t e = run_batch_graph(b, b->g_apply, b->apply_key, key, [&]() -> hipError_t {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    const bool capturing = b->branches && hipStreamIsCapturing(b->stream, &st) == hipSuccess &&
+                           st == hipStreamCaptureStatusActive;
+    if (!capturing) {  // direct launches: one chain on the batch's stream
+      for (int i = 0; i < count; ++i) {
+        const hipError_t le = lsp::launch_ps_apply(b->probs[i], u_dev[i], y_dev[i]);
+        if (le != hipSuccess) return le;
+      }
+      return hipSuccess;
     }
-    return hipSuccess;
+    // fork: problem i on branch i mod kBranches (each problem has its own
+    // workspace, so the branches share nothing); join every branch, also
+    // after a failed launch, so that the capture ends cleanly
+    hipError_t fe = hipEventRecord(b->fork, b->stream);
+    for (int k = 0; fe == hipSuccess && k < lsp_batch::kBranches; ++k)
+      fe = hipStreamWaitEvent(b->aux[k], b->fork, 0);
+    hipError_t le = hipSuccess;
+    for (int i = 0; fe == hipSuccess && le == hipSuccess && i < count; ++i)
+      le = lsp::launch_ps_apply(b->probs[i], u_dev[i], y_dev[i],
+                                b->aux[i % lsp_batch::kBranches]);
+    for (int k = 0; k < lsp_batch::kBranches; ++k) {
+      hipError_t je = hipEventRecord(b->join[k], b->aux[k]);
+      if (je == hipSuccess) je = hipStreamWaitEvent(b->stream, b->join[k], 0);
+      if (fe == hipSuccess) fe = je;
+    }
+    return fe != hipSuccess ? fe : le;
   });
   return lsp::hip_check(e, "batched ps_apply launch");
 }

@@ -143,6 +143,8 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts);
 // ---- kernel launchers (asynchronous, on p->stream) ----
 // ps_apply: y = (L + diag v) u
 hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y);
+// the same on stream s (the problem's own workspace; s only orders the launches)
+hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hipStream_t s);
 // count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
 hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // stencil setup stages

@@ -693,7 +693,7 @@ __global__ __launch_bounds__(kFft8Threads) void fft8_line_kernel(
 }
 
 template <int R>
-hipError_t run_fft8_apply(const lsp_problem* p, const double2* u, double2* y) {
+hipError_t run_fft8_apply(const lsp_problem* p, const double2* u, double2* y, hipStream_t s) {
   constexpr int n = 64 * R;
   constexpr int LPB = kFft8Threads / (8 * R);
   const double2* tw = reinterpret_cast<const double2*>(p->tw);
@@ -706,22 +706,22 @@ hipError_t run_fft8_apply(const lsp_problem* p, const double2* u, double2* y) {
     for (int b = ax + 1; b < p->d; ++b) st *= n;
     if (ax == 0) {
       hipLaunchKernelGGL((fft8_line_kernel<R, false, kFirst>), dim3((unsigned)blocks),
-                         dim3(kFft8Threads), 0, p->stream, u, z, (const double2*)nullptr, p->v,
+                         dim3(kFft8Threads), 0, s, u, z, (const double2*)nullptr, p->v,
                          tw, nlines, st);
     } else {
       hipLaunchKernelGGL((fft8_line_kernel<R, false, kAccum>), dim3((unsigned)blocks),
-                         dim3(kFft8Threads), 0, p->stream, u, z, (const double2*)z, p->v, tw,
+                         dim3(kFft8Threads), 0, s, u, z, (const double2*)z, p->v, tw,
                          nlines, st);
     }
   }
   hipLaunchKernelGGL((fft8_line_kernel<R, true, kFinal>), dim3((unsigned)blocks),
-                     dim3(kFft8Threads), 0, p->stream, u, y, (const double2*)z, p->v, tw, nlines,
+                     dim3(kFft8Threads), 0, s, u, y, (const double2*)z, p->v, tw, nlines,
                      (int64_t)1);
   return hipGetLastError();
 }
 
 template <int R3>
-hipError_t run_fft_apply(const lsp_problem* p, const double2* u, double2* y) {
+hipError_t run_fft_apply(const lsp_problem* p, const double2* u, double2* y, hipStream_t s) {
   constexpr int n = 256 * R3;
   constexpr int LPB = kFftThreads / (16 * R3);
   const double2* tw = reinterpret_cast<const double2*>(p->tw);
@@ -734,16 +734,16 @@ hipError_t run_fft_apply(const lsp_problem* p, const double2* u, double2* y) {
     for (int b = ax + 1; b < p->d; ++b) st *= n;
     if (ax == 0) {
       hipLaunchKernelGGL((fft_line_kernel<R3, false, kFirst>), dim3((unsigned)blocks),
-                         dim3(kFftThreads), 0, p->stream, u, z, (const double2*)nullptr, p->v,
+                         dim3(kFftThreads), 0, s, u, z, (const double2*)nullptr, p->v,
                          tw, nlines, st);
     } else {
       hipLaunchKernelGGL((fft_line_kernel<R3, false, kAccum>), dim3((unsigned)blocks),
-                         dim3(kFftThreads), 0, p->stream, u, z, (const double2*)z, p->v, tw,
+                         dim3(kFftThreads), 0, s, u, z, (const double2*)z, p->v, tw,
                          nlines, st);
     }
   }
   hipLaunchKernelGGL((fft_line_kernel<R3, true, kFinal>), dim3((unsigned)blocks),
-                     dim3(kFftThreads), 0, p->stream, u, y, (const double2*)z, p->v, tw, nlines,
+                     dim3(kFftThreads), 0, s, u, y, (const double2*)z, p->v, tw, nlines,
                      (int64_t)1);
   return hipGetLastError();
 }
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(TPB) void line_op_kernel(const double2* u, double2*
 }
 
 template <int N1, int N2>
-hipError_t run_ps_apply(const lsp_problem* p, const double2* u, double2* y) {
+hipError_t run_ps_apply(const lsp_problem* p, const double2* u, double2* y, hipStream_t s) {
   constexpr int n = N1 * N2;
   constexpr int TPB_C = (N2 >= 128) ? N2 : 128;
   constexpr int TPB_S = (N2 >= 128) ? N2 : 128;
@@ -914,11 +914,11 @@ hipError_t run_ps_apply(const lsp_problem* p, const double2* u, double2* y) {
     const int64_t blocks = nouter * ((st + L - 1) / L);
     if (ax == 0) {
       hipLaunchKernelGGL((line_op_kernel<N1, N2, TPB_S, false, kFirst>), dim3((unsigned)blocks),
-                         dim3(TPB_S), 0, p->stream, u, z, (const double2*)nullptr, p->v, tw,
+                         dim3(TPB_S), 0, s, u, z, (const double2*)nullptr, p->v, tw,
                          nouter, st);
     } else {
       hipLaunchKernelGGL((line_op_kernel<N1, N2, TPB_S, false, kAccum>), dim3((unsigned)blocks),
-                         dim3(TPB_S), 0, p->stream, u, z, (const double2*)z, p->v, tw, nouter,
+                         dim3(TPB_S), 0, s, u, z, (const double2*)z, p->v, tw, nouter,
                          st);
     }
   }
@@ -928,7 +928,7 @@ hipError_t run_ps_apply(const lsp_problem* p, const double2* u, double2* y) {
     const int64_t nlines = N / n;
     const int64_t blocks = (nlines + L - 1) / L;
     hipLaunchKernelGGL((line_op_kernel<N1, N2, TPB_C, true, kFinal>), dim3((unsigned)blocks),
-                       dim3(TPB_C), 0, p->stream, u, y, (const double2*)z, p->v, tw, nlines,
+                       dim3(TPB_C), 0, s, u, y, (const double2*)z, p->v, tw, nlines,
                        (int64_t)1);
   }
   return hipGetLastError();
@@ -948,20 +948,24 @@ __global__ void count_nonfinite_kernel(const double* __restrict__ x, int64_t cou
 namespace lsp {
 
 hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y) {
+  return launch_ps_apply(p, u, y, p->stream);
+}
+
+hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hipStream_t s) {
   const double2* u2 = reinterpret_cast<const double2*>(u);
   double2* y2 = reinterpret_cast<double2*>(y);
   switch (p->n) {
-    case 8: return run_ps_apply<2, 4>(p, u2, y2);
-    case 16: return run_ps_apply<4, 4>(p, u2, y2);
-    case 32: return run_ps_apply<4, 8>(p, u2, y2);
-    case 64: return run_ps_apply<8, 8>(p, u2, y2);
-    case 128: return run_ps_apply<8, 16>(p, u2, y2);
+    case 8: return run_ps_apply<2, 4>(p, u2, y2, s);
+    case 16: return run_ps_apply<4, 4>(p, u2, y2, s);
+    case 32: return run_ps_apply<4, 8>(p, u2, y2, s);
+    case 64: return run_ps_apply<8, 8>(p, u2, y2, s);
+    case 128: return run_ps_apply<8, 16>(p, u2, y2, s);
     // measured per pass at n = 1024: 12.7 + 14.9 us (8 values per thread)
     // against 12.8 + 15.5 us (16 values); at 256 and 512 the 16-value form
     // is 0.1-0.4 us faster
-    case 256: return run_fft_apply<1>(p, u2, y2);
-    case 512: return run_fft_apply<2>(p, u2, y2);
-    case 1024: return run_fft8_apply<16>(p, u2, y2);
+    case 256: return run_fft_apply<1>(p, u2, y2, s);
+    case 512: return run_fft_apply<2>(p, u2, y2, s);
+    case 1024: return run_fft8_apply<16>(p, u2, y2, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -210,7 +210,21 @@ def test_batch_rejects_bad_arguments(torch_dev):
     other = make_problems(torch_dev, [W.helm2d_random(16, seed=0, t=1).v], None)
     with pytest.raises(lsp.LSPError):
         lsp.Batch([mixed[0], other[0]])
-    for p in small + mixed + other:
+    # the problems of a batched apply may run concurrently: an output may not
+    # be another problem's input or output
+    pair = make_problems(torch_dev, [W.helm2d_random(16, seed=i, t=1).v for i in (1, 2)], stream)
+    batch = lsp.Batch(pair)
+    u = [torch.zeros(256, dtype=torch.complex128, device=dev) for _ in range(2)]
+    y = [torch.zeros(256, dtype=torch.complex128, device=dev) for _ in range(2)]
+    torch.cuda.synchronize()
+    with pytest.raises(lsp.LSPError):
+        batch.ps_apply(u, [y[0], y[0]])
+    with pytest.raises(lsp.LSPError):
+        batch.ps_apply(u, [y[0], u[0]])
+    batch.ps_apply(u, y)
+    torch.cuda.synchronize()
+    batch.close()
+    for p in small + mixed + other + pair:
         p.close()
 
 
