@@ -347,9 +347,22 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
   }
   // triangle entry k of shift si: {A1'[p][q], M'[p][q]} of its class block,
   // scaled by the 1/sqrt2 factors of rows p and q, off-diagonals doubled
+  // (decoded incrementally here: the generic helpers loop over the classes
+  // once per call, which made this prologue several microseconds slower)
   for (int e = tid; e < nS * PF::TRI; e += kThreads) {
     const int si = e / PF::TRI, k = e - si * PF::TRI;
-    const int c = PF::cls(k), pr = PF::row(k), qc = PF::col(k), B = Pa::size(c);
+    int c = 0, rem = k;
+    while (rem >= Pa::size(c) * (Pa::size(c) + 1) / 2) {
+      rem -= Pa::size(c) * (Pa::size(c) + 1) / 2;
+      ++c;
+    }
+    const int B = Pa::size(c);
+    int pr = 0;
+    while (rem >= B - pr) {
+      rem -= B - pr;
+      ++pr;
+    }
+    const int qc = pr + rem;
     const int z = PF::nz(c, pr) + PF::nz(c, qc);
     double f = ldexp(1.0, -(z / 2));
     if (z & 1) f *= lsp::kInvSqrt2;
