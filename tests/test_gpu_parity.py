@@ -346,7 +346,9 @@ def test_precond_solve_fp32_rows(torch_dev):
 
 
 # ------------------------------------------------------------- C-apply -----
-@pytest.mark.parametrize("d,n,t,nS", [(2, 32, 1, 2), (2, 64, 2, 4), (3, 16, 1, 4), (2, 256, 2, 16)])
+# (2, 1024, 2, 64) is the bench workload, in the launch configuration it times
+@pytest.mark.parametrize("d,n,t,nS", [(2, 32, 1, 2), (2, 64, 2, 4), (3, 16, 1, 4), (2, 256, 2, 16),
+                                      (2, 1024, 2, 64), (3, 64, 1, 16)])
 def test_c_apply_matches_oracle(torch_dev, d, n, t, nS):
     torch, dev = torch_dev
     r = np.random.default_rng(5)
