@@ -275,6 +275,7 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
       r.alpha = p->ws.alpha;
       r.Ctab = p->ws.Ctab;
       r.sigma = p->ws.sigma;
+      r.rho = p->ws.rho;
       r.actab = p->ws.actab;
       r.status = p->ws.status;
       r.P = P_dev[i];

@@ -59,6 +59,7 @@ void free_workspace(lsp_problem* p) {
   dfree(w.alpha);
   dfree(w.Ctab);
   dfree(w.sigma);
+  dfree(w.rho);
   dfree(w.actab);
   dfree(w.status);
   w.cap_shifts = w.cap_m = w.cap_w = 0;
@@ -95,6 +96,7 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
     dfree(w.alpha);
     dfree(w.Ctab);
     dfree(w.sigma);
+    dfree(w.rho);
     dfree(w.actab);
     dfree(w.status);
     const int cs = shifts > w.cap_shifts ? shifts : w.cap_shifts;
@@ -106,6 +108,7 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
     if ((rc = dalloc((void**)&w.alpha, sizeof(double) * cs * cm, "alpha"))) return rc;
     if ((rc = dalloc((void**)&w.Ctab, sizeof(double) * cs * cm, "C"))) return rc;
     if ((rc = dalloc((void**)&w.sigma, sizeof(double) * cs, "sigma"))) return rc;
+    if ((rc = dalloc((void**)&w.rho, sizeof(double) * cs, "rho*"))) return rc;
     if ((rc = dalloc((void**)&w.actab, sizeof(double) * 2 * cs * cm, "alpha/C"))) return rc;
     if ((rc = dalloc((void**)&w.status, sizeof(int) * cs, "status"))) return rc;
     w.cap_shifts = cs;
@@ -517,14 +520,14 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "learned C rows"))) return rc;
     p->c_rows_cap = need;
   }
-  // one buffer: rho*(s) [num_shifts], the fallback count and, for the chunked
-  // path, the network's inputs [B][m+2] and outputs [B][2m] of one chunk (each
-  // part 256-byte aligned)
+  // one buffer: the fallback count and, for the chunked path, the network's
+  // inputs [B][m+2] and outputs [B][2m] of one chunk (each part 256-byte
+  // aligned)
   const lsp::MlpView mv = lsp::mlp_view(mlp);
   const bool fused = lsp::learned_fused_supported(p, mv);
   const int B = lsp::mlp_batch_rows(mlp);
   auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-  const size_t off_nf = up(sizeof(double) * num_shifts);
+  const size_t off_nf = 0;
   const size_t off_x = off_nf + 256;
   const size_t off_y = off_x + (fused ? 0 : up(sizeof(float) * (size_t)B * (m + 2)));
   const size_t bytes = off_y + (fused ? 0 : up(sizeof(float) * (size_t)B * 2 * m));
@@ -535,7 +538,7 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     if ((rc = dalloc((void**)&p->learn_buf, bytes, "learned-setup buffers"))) return rc;
     p->learn_cap = bytes;
   }
-  double* rho_star = reinterpret_cast<double*>(p->learn_buf);
+  const double* rho_star = p->ws.rho;  // written by the null-vector kernel
   int* nfall = reinterpret_cast<int*>(p->learn_buf + off_nf);
   float* X = reinterpret_cast<float*>(p->learn_buf + off_x);
   float* Y = reinterpret_cast<float*>(p->learn_buf + off_y);
@@ -545,13 +548,12 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     const hipError_t es = hipStreamSynchronize(lsp::mlp_stream(mlp));
     if (es != hipSuccess) return lsp::hip_check(es, "surrogate stream");
   }
-  // exact tables (shift list, Green's sums, Gram matrices, null vectors),
-  // then rho*(s) per shift (its kernel also clears the fallback counter)
+  // exact tables (shift list, Green's sums, Gram matrices, null vectors and
+  // rho*(s)); the null-vector kernel also clears the fallback counter
   int blocks = 0;
   hipError_t e = lsp::launch_minmax(p);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts, &blocks);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks);
-  if (e == hipSuccess) e = lsp::launch_rho_star(p, rho_star, nfall);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks, nfall);
   if (fused) {
     // one pass: network, check against eq. (A) and rows
     if (e == hipSuccess)

@@ -37,6 +37,7 @@ struct Workspace {
   double* alpha = nullptr;        // [shifts][m]
   double* Ctab = nullptr;         // [shifts][m]
   double* sigma = nullptr;        // [shifts]
+  double* rho = nullptr;          // [shifts] rho*(s) of alpha_s (eq. A; the learned check)
   double* actab = nullptr;        // [shifts][m][2] interleaved (alpha, C)
   int* status = nullptr;          // [shifts] eigen-solver status
   int cap_shifts = 0;
@@ -67,6 +68,7 @@ struct BatchRec {
   double* alpha;
   double* Ctab;
   double* sigma;
+  double* rho;
   double* actab;
   int* status;
   void* P;           // rows (float64 or float32)
@@ -158,7 +160,9 @@ void green_units(int d, int n, std::vector<int>& units);
 size_t green_partial_doubles(int d, int n, int t, int shifts);
 // full m x m Gram matrix from the packed parity blocks (host)
 int expand_gram_host(int d, int t, const double* packed, double* full);
-hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks);
+// also clears *clear_counter (a kernel store, not a memset) when it is non-null
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks,
+                               int* clear_counter = nullptr);
 // P: float64 rows, or float32 rows when fp32
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // batched launches: one launch per stage over the problems of a batch; map
@@ -203,9 +207,6 @@ bool learned_fused_supported(const lsp_problem* p, const MlpView& mv);
 hipError_t launch_learned_fused(const lsp_problem* p, const MlpView& mv, double thr,
                                 const double* rho_star, double* P, double* Crows,
                                 int32_t* fallback, int* nfall);
-// rho*(s) = sqrt(alpha^T M alpha / alpha^T A1 alpha) of every shift's exact
-// stencil; also sets *nfall = 0 (a kernel store, not a memset)
-hipError_t launch_rho_star(const lsp_problem* p, double* rho_star, int* nfall);
 hipError_t launch_learned_rows(const lsp_problem* p, const double* rho_star, const float* Y,
                                int64_t j0, int rows, double thr, double* P, double* Crows,
                                int32_t* fallback, int* nfall);

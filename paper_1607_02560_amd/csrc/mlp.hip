@@ -880,49 +880,6 @@ __device__ __forceinline__ double exact_entry(double alpha, double c, double v_m
   return alpha + c * v_minus_s;
 }
 
-// rho*(s) of the exact stencil alpha_s of every shift, one wave per shift:
-// lane a forms (G alpha)_a and (A1 alpha)_a, lane 0 then accumulates
-// |G alpha|^2 and alpha^T A1 alpha over a, all in the order of gram_forms.
-// Thread 0 of block 0 also clears the fallback counter of the pass that follows.
-template <int D, int W>
-__global__ __launch_bounds__(64) void rho_star_kernel(const double* __restrict__ gtab,
-                                                      const double* __restrict__ gamtab,
-                                                      const double2* __restrict__ actab,
-                                                      const int* __restrict__ nS_ptr,
-                                                      double* rho_star, int* nfall) {
-  using Nb = Nbhd<D, W>;
-  constexpr int M = Pow<D, W>::v;
-  static_assert(M <= 64, "one lane per row");
-  const int id = blockIdx.x, lane = threadIdx.x;
-  if (id == 0 && lane == 0) *nfall = 0;
-  if (id >= *nS_ptr) return;  // uniform over the block
-  __shared__ double al[M], gu[M], aw[M];
-  if (lane < M) al[lane] = actab[(int64_t)id * M + lane].x;
-  __syncthreads();
-  if (lane < M) {
-    const double* g = gtab + (int64_t)id * M;
-    const double* gm = gamtab + (int64_t)id * M;
-    double u = 0.0, w = 0.0;
-    for (int b = 0; b < M; ++b) {
-      const int k = Nb::diff_index(lane, b);
-      u = fma(g[k], al[b], u);
-      w = fma(gm[k], al[b], w);
-    }
-    gu[lane] = u;
-    aw[lane] = w;
-  }
-  __syncthreads();
-  if (lane == 0) {
-    double a1 = 0.0, gq2 = 0.0;
-    for (int a = 0; a < M; ++a) {
-      gq2 = fma(gu[a], gu[a], gq2);
-      a1 = fma(al[a], aw[a], a1);
-    }
-    const double qmq = a1 - gq2;
-    rho_star[id] = sqrt(fmax(qmq, 0.0) / a1);
-  }
-}
-
 // Learned rows of points j0 .. j0+rows-1 from the de-standardised network
 // outputs Y [rows][2m]: p = Y[:m], c = Y[m:] / |s_j|, stencil
 // q = p - c (v[mu_j] - s_j) and rho = sqrt(q^T M q / q^T A1 q) (eq. A). Rows
@@ -1003,13 +960,6 @@ hipError_t launch_targets(const lsp_problem* p, const double* P, const int64_t* 
   const dim3 grid(blocks_for(rows, 128)), blk(128);
   LSP_DW_DISPATCH(targets_kernel, P, p->v, p->N, p->ws.S, p->ws.nS, p->ws.Ctab, points, rows,
                   T);
-  return hipGetLastError();
-}
-
-hipError_t launch_rho_star(const lsp_problem* p, double* rho_star, int* nfall) {
-  const dim3 grid((unsigned)p->num_shifts), blk(64);
-  LSP_DW_DISPATCH(rho_star_kernel, p->ws.gtab, p->ws.gamtab,
-                  reinterpret_cast<const double2*>(p->ws.actab), p->ws.nS, rho_star, nfall);
   return hipGetLastError();
 }
 

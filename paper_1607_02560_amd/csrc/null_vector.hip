@@ -23,10 +23,13 @@
 //   4. two inverse-iteration steps whose solve is refined once against the
 //      FP64 M_b (y0 = X x, y = y0 + X (x - M y0)), removing the forward error
 //      of the explicit inverse;
-//   5. lambda_c = x^T M_b x and G_b x.
+//   5. lambda_c = x^T M_b x, x^T A1_b x and G_b x.
 // The class with the smallest lambda_c gives alpha (ties: lowest class);
 // alpha and C are mapped back to the offsets of mu_0^t, normalised to unit
-// norm with the largest-magnitude entry positive (lowest offset on ties).
+// norm with the largest-magnitude entry positive (lowest offset on ties);
+// rho*(s) = sqrt(lambda_c / x^T A1_b x) is the fraction of the row of Q G that
+// alpha's truncation drops (eq. A), which the learned setup's check compares
+// against.
 #include "setup_common.h"
 
 #pragma clang fp contract(off)
@@ -46,6 +49,7 @@ struct NullShared {
   double g[WD];
   double q[WD];
   double lam[NC];
+  double ax[NC];  // x^T A1_b x of the class's vector
   double vec[NC][BMAX];
   double gv[NC][BMAX];
   int status[NC];
@@ -272,9 +276,15 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
     mx = fma(mrow[qc], xa[qc], mx);
     gx = fma(grow[qc], xa[qc], gx);
   }
-  double lam = 0.0;
+  double ay = 0.0;
 #pragma unroll
-  for (int qc = 0; qc < B; ++qc) lam = fma(xa[qc], bcast(mx, qc), lam);
+  for (int qc = 0; qc < B; ++qc) ay = fma(arow[qc], xa[qc], ay);
+  double lam = 0.0, axx = 0.0;
+#pragma unroll
+  for (int qc = 0; qc < B; ++qc) {
+    lam = fma(xa[qc], bcast(mx, qc), lam);
+    axx = fma(xa[qc], bcast(ay, qc), axx);
+  }
   if (lane < B) {
     double xl = 0.0;
 #pragma unroll
@@ -285,6 +295,7 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   }
   if (lane == 0) {
     sh.lam[C] = ok ? lam : INFINITY;
+    sh.ax[C] = axx;
     sh.status[C] = ok ? tries : -1;
   }
 }
@@ -293,7 +304,7 @@ template <int D, int W>
 __device__ __forceinline__ void null_body(
     int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
     double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
-    double* sigma_out, double* actab, int* status) {
+    double* sigma_out, double* rho_out, double* actab, int* status, int* clear_counter) {
   using Pa = Parity<D, W>;
   using Nb = Nbhd<D, W>;
   constexpr int NC = 1 << D;
@@ -304,6 +315,7 @@ __device__ __forceinline__ void null_body(
   constexpr int NV = 2 * WO2 * NP;
   constexpr int T = 64 * NC;
   __shared__ NullShared<D, W> sh;
+  if (si == 0 && threadIdx.x == 0 && clear_counter) *clear_counter = 0;
   if (si >= *nS) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -441,6 +453,8 @@ __device__ __forceinline__ void null_body(
   }
   if (lane == 0) {
     sigma_out[si] = sqrt(fmax(lam, 0.0));
+    // rho*(s)^2 = alpha^T M alpha / alpha^T A1 alpha, alpha = Q x of the class
+    rho_out[si] = sqrt(fmax(lam, 0.0) / sh.ax[cs]);
     status[si] = sh.status[cs];
   }
 }
@@ -449,9 +463,9 @@ template <int D, int W>
 __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
     const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
     double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
-    double* sigma_out, double* actab, int* status) {
+    double* sigma_out, double* rho_out, double* actab, int* status, int* clear_counter) {
   null_body<D, W>(blockIdx.x, nS, part, nblk, invN, gtab, gamtab, Mtab, alpha_out, C_out,
-                  sigma_out, actab, status);
+                  sigma_out, rho_out, actab, status, clear_counter);
 }
 
 // one launch for the problems of a batch: block b solves shift map[b].y of
@@ -462,16 +476,16 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_batched_kernel(const lsp::
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
   null_body<D, W>(it.y, r.nS, r.part, r.nunits, r.invN, r.gtab, r.gamtab, r.Mtab, r.alpha,
-                  r.Ctab, r.sigma, r.actab, r.status);
+                  r.Ctab, r.sigma, r.rho, r.actab, r.status, nullptr);
 }
 
 template <int D, int W>
-hipError_t run_null(lsp_problem* p, int num_shifts, int nblk) {
+hipError_t run_null(lsp_problem* p, int num_shifts, int nblk, int* clear_counter) {
   const double invN = 1.0 / (double)p->N;
   hipLaunchKernelGGL((null_vector_kernel<D, W>), dim3(num_shifts), dim3(64 * (1 << D)), 0,
                      p->stream, p->ws.nS, p->ws.green_part, nblk, invN, p->ws.gtab,
                      p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab, p->ws.sigma,
-                     p->ws.actab, p->ws.status);
+                     p->ws.rho, p->ws.actab, p->ws.status, clear_counter);
   return hipGetLastError();
 }
 
@@ -496,12 +510,12 @@ hipError_t launch_null_batched(int d, int t, const BatchRec* recs, const int4* m
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk) {
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk, int* clear_counter) {
   const int W = 2 * p->t + 1;
-  if (p->d == 2 && W == 3) return run_null<2, 3>(p, num_shifts, nblk);
-  if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, nblk);
-  if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, nblk);
-  if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, nblk);
+  if (p->d == 2 && W == 3) return run_null<2, 3>(p, num_shifts, nblk, clear_counter);
+  if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, nblk, clear_counter);
+  if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, nblk, clear_counter);
+  if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, nblk, clear_counter);
   return hipErrorInvalidValue;
 }
 
