@@ -199,10 +199,16 @@ int lsp_batch_create(int count, lsp_problem* const* problems, lsp_batch** out) {
   // as a graph replay against 0.43 ms launched directly (64-problem workload)
   b->use_graphs = lsp::graphs_enabled(true);
   if (b->use_graphs && b->stream) {
-    bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+    // on the problems' device, whichever device is current
+    int cur = -1;
+    bool ok = hipGetDevice(&cur) == hipSuccess;
+    const int dev = b->probs[0]->device;
+    if (ok && cur != dev) ok = hipSetDevice(dev) == hipSuccess;
+    if (ok) ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
     for (int k = 0; ok && k < lsp_batch::kBranches; ++k)
       ok = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+    if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
     b->branches = ok;  // without them the captured apply stays one chain
     if (!ok) (void)hipGetLastError();
   }
