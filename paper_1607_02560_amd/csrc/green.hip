@@ -339,9 +339,16 @@ __device__ __forceinline__ void green_body(
         ++da;
       }
       const int db = da + rest;
+      // select with constant indices so cn[] stays in registers
+      double ca = 0.0, cb = 0.0;
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        if (j == da) ca = cn[j];
+        if (j == db) cb = cn[j];
+      }
       const double r = green_r(2 * nyq * nyq, s);
       const double rr = (vi < NP) ? r : r * r;
-      val += (cn[da] * cn[db]) * rr;
+      val += (ca * cb) * rr;
     }
     part[((int64_t)si * gx + bx) * NV + vi] = val;
   }
