@@ -21,6 +21,9 @@ Every function follows one passage of the paper:
   assign_shifts            Sec. 4.1: s_j = the shift of S closest to v_j
   assemble                 Sec. 4.1/4.2: Q, C and P rows
   stencil_setup            all of the above in the paper's order
+  global_shift, global_setup
+                           Sec. 3: the non-localized preconditioner, one
+                           shift s = mean(v) for every point
   sparse_P, sparse_C       eq. (PC) as sparse matrices
   gmres_right              Sec. 5: GMRES with restart, preconditioner P^-1 C
 
@@ -38,6 +41,10 @@ design notes of the repository):
     both P and C leaves P^-1 C unchanged, so the choice is immaterial to the solve.
   * GMRES: right preconditioning, x0 = 0, the iteration count is the total
     number of Arnoldi steps.
+  * non-localized shift (Sec. 3): the mean of v, moved only when L + s is
+    singular: x = -s / (4 pi^2) within RESONANCE_TOL * max(1, |x|) of an
+    integer >= 0 counts as singular, and s then goes to the nearest
+    (4m+2) pi^2 (the resonance-free form of Sec. 4.1, at most 2 pi^2 away).
 """
 from __future__ import annotations
 
@@ -317,6 +324,39 @@ def stencil_setup(v: np.ndarray, t: int, num_shifts: int) -> dict:
     return tab
 
 
+# --------------------------------------------------------------------------
+# Section 3: the non-localized sparsifying preconditioner
+# --------------------------------------------------------------------------
+RESONANCE_TOL = 2.0 ** -30
+
+
+def global_shift(v: np.ndarray) -> float:
+    """The one shift of the non-localized preconditioner (Sec. 3): the
+    average of v, so that q = v - s has zero mean. L + s is singular when
+    s = -4 pi^2 K for an integer K = |k|^2 >= 0; the paper then perturbs s
+    slightly. Here such an s (to RESONANCE_TOL) is replaced by the nearest
+    (4m+2) pi^2."""
+    s = float(np.mean(v, dtype=np.float64))
+    x = -s / FOUR_PI2
+    K = math.floor(x + 0.5)
+    if K >= 0 and abs(x - K) <= RESONANCE_TOL * max(1.0, abs(x)):
+        s = snap_shift(s)
+    return s
+
+
+def global_setup(v: np.ndarray, t: int) -> dict:
+    """The non-localized setup of Sec. 3 with neighbourhood radius t: the
+    tables of the single shift s = global_shift(v), every point assigned to
+    it, and P = Q + C diag(v - s) in the row layout of `assemble`."""
+    d, n = v.ndim, v.shape[0]
+    S = np.asarray([global_shift(v)], dtype=np.float64)
+    tab = shift_tables(d, n, S, t)
+    idx = np.zeros(v.shape, dtype=np.int32)
+    P = assemble(v, S, tab["alpha"], tab["C"], idx, tab["offsets"])
+    tab.update(S=S, idx=idx, P=P)
+    return tab
+
+
 def neighbour_columns(d: int, n: int, offs: np.ndarray) -> np.ndarray:
     """Column index (j + a) mod n, flattened, for each row j and offset a."""
     N = n ** d
@@ -409,11 +449,13 @@ def gmres_right(apply_A, apply_M, f: np.ndarray, rtol: float, restart: int, maxi
 
 
 def precond_solve(v: np.ndarray, f: np.ndarray, t: int, num_shifts: int,
-                  rtol: float = 1e-8, restart: int = 40, maxit: int = 400):
+                  rtol: float = 1e-8, restart: int = 40, maxit: int = 400,
+                  non_localized: bool = False):
     """Solve (L + diag v) u = f by GMRES(restart) with the preconditioner
-    P^-1 C of eq. (PC); P is factorised by a sparse LU."""
+    P^-1 C of eq. (PC); P is factorised by a sparse LU. non_localized=True
+    builds P and C by the one-shift method of Sec. 3 (num_shifts unused)."""
     d, n = v.ndim, v.shape[0]
-    setup = stencil_setup(v, t, num_shifts)
+    setup = global_setup(v, t) if non_localized else stencil_setup(v, t, num_shifts)
     P = sparse_P(setup, d, n).tocsc().astype(np.complex128)
     Cm = sparse_C(setup, d, n).astype(np.complex128)
     lu = scipy.sparse.linalg.splu(P)

@@ -78,6 +78,18 @@ def _shift_list_left_edges(v, num_shifts):
     return np.asarray(out)
 
 
+def _global_midrange(v):
+    return 0.5 * (float(np.min(v)) + float(np.max(v)))
+
+
+def _global_ignores_resonance(v):
+    return float(np.mean(v))
+
+
+def _global_always_snaps(v):
+    return O.snap_shift(float(np.mean(v)))
+
+
 MUTANTS = [
     ("symbol", _symbol_missing_4, lambda: pins.test_plane_waves_are_eigenvectors(2, 8)),
     ("ps_apply", _ps_apply_wrong_sign, lambda: pins.test_ps_apply_matches_dense(2, 8, 1)),
@@ -92,6 +104,10 @@ MUTANTS = [
     ("assign_shifts", _assign_argmax, pins.test_assign_shifts_bruteforce),
     ("assemble", _assemble_centre_only, pins.test_P_row_formula_dense),
     ("shift_list", _shift_list_left_edges, pins.test_shift_list_spreads_evenly),
+    ("global_shift", _global_midrange, lambda: pins.test_global_setup_dense_definition(2, 8, 1)),
+    ("global_shift", _global_ignores_resonance,
+     lambda: pins.test_global_shift_moves_off_resonance(5)),
+    ("global_shift", _global_always_snaps, pins.test_global_shift_keeps_non_resonant_mean),
 ]
 
 

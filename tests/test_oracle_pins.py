@@ -377,3 +377,98 @@ def test_precond_solve_helm2d_gauss_matches_dense():
     u_ref = np.linalg.solve(A, p.f.reshape(-1))
     assert np.linalg.norm(u.reshape(-1) - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
     assert iters < 60
+
+
+# ------------------------------------------- Sec. 3, non-localized method ----
+def test_global_shift_is_the_mean():
+    """Sec. 3: s is the average of v, so q = v - s has zero mean. An arithmetic
+    ramp a + b j has the closed-form mean a + b (N - 1) / 2 (exact here: every
+    partial sum is a multiple of 1/4 below 2^20)."""
+    n = 16
+    j = np.arange(n * n, dtype=np.float64).reshape(n, n)
+    v = -300.0 + 0.25 * j
+    s = O.global_shift(v)
+    assert s == -300.0 + 0.25 * (n * n - 1) / 2
+    assert np.sum(v - s) == 0.0
+
+
+@pytest.mark.parametrize("K", [0, 1, 5, 25])
+def test_global_shift_moves_off_resonance(K):
+    """A constant v = -4 pi^2 K makes L + s singular when K = |k|^2 for some
+    wavenumber (0, 1, 5 = 1 + 4, 25 = 9 + 16 on n = 16). The shift moves to a
+    value of the form (4m + 2) pi^2 at most 2 pi^2 away, where the nearest
+    eigenvalue of L + s is 2 pi^2 from zero."""
+    n = 16
+    v = np.full((n, n), -4.0 * PI2 * K)
+    lam = O.symbol(2, n)
+    assert np.min(np.abs(lam + v[0, 0])) <= 1e-12 * 4 * PI2 * max(K, 1)
+    s = O.global_shift(v)
+    assert abs(s - v[0, 0]) <= 2 * PI2 * (1 + 1e-12)
+    assert np.min(np.abs(lam + s)) == pytest.approx(2 * PI2, rel=1e-9)
+    m = (s / PI2 - 2) / 4
+    assert m == pytest.approx(round(m), abs=1e-9)
+
+
+def test_global_shift_keeps_non_resonant_mean():
+    """Away from the eigenvalues of L the mean is used as it is (Sec. 3)."""
+    v = np.full((8, 8), -4.0 * PI2 * 5.3)
+    assert O.global_shift(v) == v[0, 0]
+
+
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1)])
+def test_global_setup_dense_definition(d, n, t):
+    """Sec. 3 on a tiny grid from dense matrices: every row of Q holds the same
+    unit vector alpha, the left singular vector of the smallest singular value
+    of G[mu_j, mu_j^c] with G = (L + s)^-1 (checked against a dense SVD of that
+    block), C is Q G truncated to mu_j, and P = Q + C diag(v - s)."""
+    v = rng(21).uniform(-400, -150, (n,) * d)
+    setup = O.global_setup(v, t)
+    s = setup["S"][0]
+    assert s == pytest.approx(float(v.mean()), rel=1e-14)
+    assert np.all(setup["idx"] == 0)
+    Nn = n ** d
+    L = O.dense_laplacian(d, n)
+    G = np.linalg.inv(L + s * np.eye(Nn))
+    cols = O.neighbour_columns(d, n, setup["offsets"])
+    alpha = setup["alpha"][0]
+    assert np.linalg.norm(alpha) == pytest.approx(1.0, rel=1e-14)
+    P = O.sparse_P(setup, d, n).toarray()
+    Cm = O.sparse_C(setup, d, n).toarray()
+    vf = v.reshape(-1)
+    for j in range(0, Nn, max(1, Nn // 11)):
+        mask = np.zeros(Nn, dtype=bool)
+        mask[cols[j]] = True
+        B = G[cols[j]][:, ~mask]
+        sv = np.linalg.svd(B, compute_uv=False)
+        assert np.linalg.norm(alpha @ B) == pytest.approx(sv[-1], rel=1e-5)
+        assert setup["sigma_min"][0] == pytest.approx(sv[-1], rel=1e-5)
+        qg = (alpha @ G[cols[j]])[cols[j]]
+        assert np.allclose(Cm[j, cols[j]], qg, rtol=1e-8, atol=1e-12 * np.abs(qg).max())
+        Qj = np.zeros(Nn)
+        Qj[cols[j]] = alpha
+        assert np.allclose(P[j], Qj + Cm[j] * (vf - s), rtol=1e-13, atol=1e-15)
+
+
+def test_global_setup_is_one_shift_setup_for_constant_v():
+    """For constant v = (4m + 2) pi^2 the mean is already of the resonance-free
+    form and the shift list of Sec. 4.1 has the single entry v; the two
+    setups then coincide (up to the rounding of the mean's sum)."""
+    v = np.full((16, 16), (4 * -9 + 2) * PI2)
+    a = O.global_setup(v, 2)
+    b = O.stencil_setup(v, 2, 4)
+    assert len(b["S"]) == 1
+    assert a["S"][0] == pytest.approx(b["S"][0], rel=1e-15)
+    assert np.allclose(a["alpha"], b["alpha"], rtol=1e-8, atol=1e-12)
+    assert np.allclose(a["P"], b["P"], rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.slow
+def test_non_localized_precond_solve_converges():
+    """GMRES with the one-shift preconditioner of Sec. 3 on the n = 32
+    Helmholtz problem reaches 1e-8 and agrees with the dense solve."""
+    p = W.helm2d_gauss(32)
+    u, iters, est, true_rel, setup = O.precond_solve(p.v, p.f, p.t, p.num_shifts, rtol=1e-8,
+                                                     non_localized=True)
+    assert len(setup["S"]) == 1 and true_rel <= 1e-8 and iters < 60
+    u_ref = np.linalg.solve(O.dense_operator(p.v), p.f.reshape(-1))
+    assert np.linalg.norm(u.reshape(-1) - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
