@@ -117,6 +117,23 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision,
                       void* P_dev, int32_t* idx_dev);
 
 /*
+ * Stencil setup of the non-localized sparsifying preconditioner (Sec. 3), the
+ * method the localized one refines: one shift s for every grid point, the
+ * average of v (so that q = v - s has zero mean). When L + s is singular
+ * (x = -s / (4 pi^2) within 2^-30 max(1, |x|) of an integer K >= 0) s moves
+ * to (2 - 4K) pi^2, the value of the form (4m+2) pi^2 that lies 2 pi^2 above
+ * -4 pi^2 K. Then steps 2-4 of lsp_stencil_setup for that one
+ * shift, idx_j = 0 and P[j, a] = alpha[a] + C[a] (v[j+a] - s), i.e.
+ * P = Q + C diag(q) with Q's rows alpha. The mean is summed in a fixed order,
+ * so repeated calls give identical results.
+ *   t, precision, P_dev, idx_dev  as for lsp_stencil_setup (same layouts).
+ * lsp_get_tables, lsp_c_apply and lsp_precond_solve then use this setup.
+ * Asynchronous: returns once the work is enqueued.
+ */
+int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
+                             int32_t* idx_dev);
+
+/*
  * Pseudospectral apply y = (L + diag v) u with L = F^-1 diag(4 pi^2 |k|^2) F
  * (Sec. 2, eq. dmodel). u_dev and y_dev: N complex128, device, must not
  * overlap. Asynchronous.

@@ -43,8 +43,10 @@ design notes of the repository):
     number of Arnoldi steps.
   * non-localized shift (Sec. 3): the mean of v, moved only when L + s is
     singular: x = -s / (4 pi^2) within RESONANCE_TOL * max(1, |x|) of an
-    integer >= 0 counts as singular, and s then goes to the nearest
-    (4m+2) pi^2 (the resonance-free form of Sec. 4.1, at most 2 pi^2 away).
+    integer K >= 0 counts as singular, and s then goes to (4m+2) pi^2 with
+    m = -K (the resonance-free form of Sec. 4.1, 2 pi^2 above -4 pi^2 K; the
+    two values of that form nearest to -4 pi^2 K are equally near, and
+    choosing by K rather than by s keeps the choice stable under rounding).
 """
 from __future__ import annotations
 
@@ -334,13 +336,13 @@ def global_shift(v: np.ndarray) -> float:
     """The one shift of the non-localized preconditioner (Sec. 3): the
     average of v, so that q = v - s has zero mean. L + s is singular when
     s = -4 pi^2 K for an integer K = |k|^2 >= 0; the paper then perturbs s
-    slightly. Here such an s (to RESONANCE_TOL) is replaced by the nearest
-    (4m+2) pi^2."""
+    slightly. Here such an s (to RESONANCE_TOL) is replaced by (4m+2) pi^2
+    with m = -K, the value of that form 2 pi^2 above the singular point."""
     s = float(np.mean(v, dtype=np.float64))
     x = -s / FOUR_PI2
     K = math.floor(x + 0.5)
     if K >= 0 and abs(x - K) <= RESONANCE_TOL * max(1.0, abs(x)):
-        s = snap_shift(s)
+        s = (4 * (-K) + 2) * math.pi ** 2
     return s
 
 

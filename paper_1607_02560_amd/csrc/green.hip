@@ -168,6 +168,74 @@ __host__ __device__ inline int tiled_wavenumbers(int n) {
   return D == 2 ? n / 2 : n / 2 + 1;
 }
 
+// The one shift of the non-localized method (Sec. 3) from the min/max/sum
+// partials, computed by every thread of the block: s = mean of v, moved to
+// (2 - 4K) pi^2 (the form (4m+2) pi^2 with m = -K, 2 pi^2 above the singular
+// point) only when L + s is singular, i.e. when x = -s / (4 pi^2) lies within
+// 2^-30 max(1, |x|) of an integer K >= 0.
+// The partial sums are added in a fixed order (per thread, butterfly over
+// the lanes, waves in index order), so every thread gets the same s.
+// Results in LDS like lsp::shift_list_block: sS[0], *sNS = 1, sRange.
+template <int NT>
+__device__ inline void global_shift_block(const double* __restrict__ part, int64_t N, double* sS,
+                                          int* sNS, double* sRange, double* sRed) {
+  static_assert(NT % 64 == 0 && lsp::kMinMaxBlocks % NT == 0, "block shape");
+  constexpr int NW = NT / 64;
+  constexpr int PER = lsp::kMinMaxBlocks / NT;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  const double* ps = part + 2 * lsp::kMinMaxBlocks;
+  double2 x[PER];
+  double xs[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    x[i] = p2[tid + i * NT];
+    xs[i] = ps[tid + i * NT];
+  }
+  double lo = x[0].x, hi = x[0].y, sum = xs[0];
+#pragma unroll
+  for (int i = 1; i < PER; ++i) {
+    lo = fmin(lo, x[i].x);
+    hi = fmax(hi, x[i].y);
+    sum += xs[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    sum += __shfl_xor(sum, o);
+  }
+  if (lane == 0) {
+    sRed[3 * wid] = lo;
+    sRed[3 * wid + 1] = hi;
+    sRed[3 * wid + 2] = sum;
+  }
+  __syncthreads();
+  lo = sRed[0];
+  hi = sRed[1];
+  sum = sRed[2];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    lo = fmin(lo, sRed[3 * w]);
+    hi = fmax(hi, sRed[3 * w + 1]);
+    sum += sRed[3 * w + 2];
+  }
+  double s = sum / (double)N;
+  const double xr = -s / lsp::kFourPi2;
+  const double K = floor(xr + 0.5);
+  if (K >= 0.0 && fabs(xr - K) <= 0x1p-30 * fmax(1.0, fabs(xr)))
+    s = (2.0 - 4.0 * K) * lsp::kPi2;
+  if (tid == 0) {
+    sS[0] = s;
+    *sNS = 1;
+    sRange[0] = lo;
+    sRange[1] = hi;
+  }
+  __syncthreads();
+}
+
 // One block per (work unit, group of kWaves shifts); wave w handles shift
 // kWaves * blockIdx.y + w. A work unit is 64 consecutive outer indices
 // o = (k_1..k_{d-1}) (one per lane) and KT consecutive values of k_d; only
@@ -184,7 +252,7 @@ __host__ __device__ inline int tiled_wavenumbers(int n) {
 // k tile add the Nyquist column k_2 = n/2 as one more term (weight 1 above
 // the diagonal, hence 2 inside a square tile before the 1/2), and the waves
 // of unit 0 add the corner (n/2, n/2), whose cosine weights are (-1)^delta.
-template <int D, int W, int KT>
+template <int D, int W, int KT, bool GLOBAL>
 __device__ __forceinline__ void green_body(
     int bx, int by, int gx, const double* __restrict__ mm_part, int nreq,
     double* __restrict__ S_out, int* __restrict__ nS_out, double* __restrict__ vrange_out,
@@ -201,7 +269,7 @@ __device__ __forceinline__ void green_body(
   __shared__ double cws[KT * W];
   __shared__ double sS[lsp::kMaxShifts];
   __shared__ int sNS, sWave[kWaves];
-  __shared__ double sRange[2], sRed[2 * kWaves];
+  __shared__ double sRange[2], sRed[3 * kWaves];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
@@ -252,7 +320,14 @@ __device__ __forceinline__ void green_body(
     lead[0] = 1.0;
   }
 
-  lsp::shift_list_block<kThreads>(mm_part, nreq, sS, &sNS, sRange, sWave, sRed);
+  if constexpr (GLOBAL) {
+    int64_t N = 1;
+#pragma unroll
+    for (int i = 0; i < D; ++i) N *= n;
+    global_shift_block<kThreads>(mm_part, N, sS, &sNS, sRange, sRed);
+  } else {
+    lsp::shift_list_block<kThreads>(mm_part, nreq, sS, &sNS, sRange, sWave, sRed);
+  }
   const int nS = sNS;
   if (bx == 0 && by == 0) {
     for (int i = tid; i < nS; i += kThreads) S_out[i] = sS[i];
@@ -354,12 +429,12 @@ __device__ __forceinline__ void green_body(
   }
 }
 
-template <int D, int W, int KT>
+template <int D, int W, int KT, bool GLOBAL>
 __global__ __launch_bounds__(kThreads) void green_sums_kernel(
     const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
     int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
     const int* __restrict__ units, int n, double* __restrict__ part) {
-  green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, mm_part, nreq, S_out, nS_out,
+  green_body<D, W, KT, GLOBAL>(blockIdx.x, blockIdx.y, gridDim.x, mm_part, nreq, S_out, nS_out,
                        vrange_out, cw, units, n, part);
 }
 
@@ -370,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::Batc
                                                                  const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  green_body<D, W, KT>(it.y, it.z, r.nunits, r.mm_part, r.nreq, r.S, r.nS, r.vrange, r.cw,
+  green_body<D, W, KT, false>(it.y, it.z, r.nunits, r.mm_part, r.nreq, r.S, r.nS, r.vrange, r.cw,
                        r.units, r.n, r.part);
 }
 
@@ -398,7 +473,7 @@ void build_units(int n, std::vector<int>& units) {
 }
 
 template <int D, int W>
-hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out) {
+hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out, bool global) {
   const int nunits = p->green_nunits;
   const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
   if (need > p->ws.green_part_cap || nunits < 1) return hipErrorInvalidValue;
@@ -408,9 +483,16 @@ hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out) {
   // the most loaded SIMD. Reserving kResidencyLds bytes of LDS per block (on
   // top of its ~10-12 KB of static LDS) lets at most three blocks share a
   // CU's 160 KB, so no SIMD takes more than three waves.
-  hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(nunits, groups), dim3(kThreads),
-                     kResidencyLds, p->stream, p->ws.minmax_part, num_shifts, p->ws.S, p->ws.nS, p->ws.vrange,
-                     p->cosT, p->green_units, p->n, p->ws.green_part);
+  if (global)
+    hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile, true>), dim3(nunits, groups),
+                       dim3(kThreads), kResidencyLds, p->stream, p->ws.minmax_part, num_shifts,
+                       p->ws.S, p->ws.nS, p->ws.vrange, p->cosT, p->green_units, p->n,
+                       p->ws.green_part);
+  else
+    hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile, false>), dim3(nunits, groups),
+                       dim3(kThreads), kResidencyLds, p->stream, p->ws.minmax_part, num_shifts,
+                       p->ws.S, p->ws.nS, p->ws.vrange, p->cosT, p->green_units, p->n,
+                       p->ws.green_part);
   return hipGetLastError();
 }
 
@@ -437,12 +519,13 @@ hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* 
 
 int green_shift_groups(int num_shifts) { return (num_shifts + kWaves - 1) / kWaves; }
 
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units) {
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units, bool global) {
   const int W = 2 * p->t + 1;
-  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, units);
-  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, units);
-  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, units);
-  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, units);
+  if (global && num_shifts != 1) return hipErrorInvalidValue;
+  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, units, global);
+  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, units, global);
+  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, units, global);
+  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, units, global);
   return hipErrorInvalidValue;
 }
 

@@ -70,7 +70,7 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
   lsp::Workspace& w = p->ws;
   int rc = LSP_OK;
   if (!w.minmax_part) {
-    if ((rc = dalloc((void**)&w.minmax_part, sizeof(double) * 2 * lsp::kMinMaxBlocks, "minmax")))
+    if ((rc = dalloc((void**)&w.minmax_part, sizeof(double) * 3 * lsp::kMinMaxBlocks, "minmax")))
       return rc;
     if ((rc = dalloc((void**)&w.S, sizeof(double) * lsp::kMaxShifts, "S"))) return rc;
     if ((rc = dalloc((void**)&w.nS, sizeof(int), "nS"))) return rc;
@@ -485,6 +485,46 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
                            (uint64_t)(uintptr_t)idx_dev, p->ws_gen, (uint64_t)precision};
   const hipError_t e = run_graph(p, p->g_setup, key, launch);
   if (e != hipSuccess) return lsp::hip_check(e, "stencil setup launch");
+  p->have_setup = true;
+  return LSP_OK;
+}
+
+int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
+                             int32_t* idx_dev) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
+  if (precision != LSP_FP64 && precision != LSP_FP32_REFINE)
+    return lsp::set_error(LSP_EINVAL, "unsupported precision");
+  int num_shifts = 1;
+  int rc = lsp::prepare_setup(p, t, &num_shifts);
+  if (rc) return rc;
+  auto launch = [&]() -> hipError_t {
+    const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
+    int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
+    hipError_t e = lsp::launch_minmax(p, true);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    int blocks = 0;
+    tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
+    e = lsp::launch_green_sums(p, 1, &blocks, true);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    tk = lsp::stage_begin(p, LSP_STAGE_NULL);
+    e = lsp::launch_null_vectors(p, 1, blocks);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
+    e = lsp::launch_assemble(p, P_dev, precision == LSP_FP32_REFINE, idx_dev);
+    if (e != hipSuccess) return e;
+    lsp::stage_end(p, tk);
+    lsp::stage_end(p, tk_all);
+    return hipSuccess;
+  };
+  // the all-ones word keeps this graph apart from a localized setup's
+  const uint64_t key[6] = {(uint64_t)t, ~(uint64_t)0, (uint64_t)(uintptr_t)P_dev,
+                           (uint64_t)(uintptr_t)idx_dev, p->ws_gen, (uint64_t)precision};
+  const hipError_t e = run_graph(p, p->g_setup, key, launch);
+  if (e != hipSuccess) return lsp::hip_check(e, "non-localized setup launch");
   p->have_setup = true;
   return LSP_OK;
 }

@@ -23,7 +23,7 @@ constexpr int kMinMaxBlocks = 256;  // blocks (= partials) of the min/max reduct
 
 struct Workspace {
   // shift list (Sec. 4.1)
-  double* minmax_part = nullptr;  // [2 * kMinMaxBlocks]
+  double* minmax_part = nullptr;  // [2 * kMinMaxBlocks] (min, max), then [kMinMaxBlocks] sums
   double* S = nullptr;            // [kMaxShifts]
   int* nS = nullptr;              // effective |S|, device resident
   double* vrange = nullptr;       // [2] v_min, v_max
@@ -150,10 +150,14 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hip
 // count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
 hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // stencil setup stages
-// per-block (min, max) partials of v; the Green's-sum launch turns them into S
-hipError_t launch_minmax(lsp_problem* p);
-// Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out);
+// per-block (min, max) partials of v (with_sum: and per-block sums); the
+// Green's-sum launch turns them into S
+hipError_t launch_minmax(lsp_problem* p, bool with_sum = false);
+// Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace.
+// global: S is the one shift of the non-localized method of Sec. 3 (the mean
+// of v from the sums of launch_minmax(p, true)), not the list of Sec. 4.1
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out,
+                             bool global = false);
 // work units of the Green's-sum launch for (d, n), packed (outer tile << 16) | k tile
 void green_units(int d, int n, std::vector<int>& units);
 // doubles of partial sums the Green's-sum launch writes for (d, n, t, shifts)

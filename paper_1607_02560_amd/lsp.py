@@ -65,6 +65,7 @@ def load():
         "lsp_set_potential": (c_int, [c_void_p, c_void_p]),
         "lsp_destroy": (None, [c_void_p]),
         "lsp_stencil_setup": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
+        "lsp_stencil_setup_global": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
         "lsp_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_c_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_precond_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
@@ -201,6 +202,20 @@ class Problem:
         _check(self.lib.lsp_stencil_setup(self._h, t, num_shifts, precision, _ptr(P),
                                           _ptr(idx) if idx is not None else None),
                "lsp_stencil_setup")
+        self.t, self.m = t, m
+
+    def stencil_setup_global(self, t: int, P, idx=None, precision: int = LSP_FP64):
+        """Non-localized setup (one shift, the mean of v); same outputs as
+        stencil_setup."""
+        import torch
+        m = (2 * t + 1) ** self.d
+        _need(P, torch.float32 if precision == LSP_FP32_REFINE else torch.float64,
+              self.N * m, "P")
+        if idx is not None:
+            _need(idx, torch.int32, self.N, "idx")
+        _check(self.lib.lsp_stencil_setup_global(self._h, t, precision, _ptr(P),
+                                                 _ptr(idx) if idx is not None else None),
+               "lsp_stencil_setup_global")
         self.t, self.m = t, m
 
     def training_rows(self, P, points, X, T):

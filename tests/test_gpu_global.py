@@ -1,0 +1,138 @@
+"""Parity of the non-localized setup (Sec. 3: one shift, the mean of v) with
+the oracle, through the C ABI. Tolerances as in test_gpu_parity: the shift to
+1e-13 relative (different summation orders of the mean), idx bit-exact,
+tables at the GPU's shift to 1e-10 and the conditioning bound on alpha, P rows
+bit-exact against the row formula on the GPU's own tables."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lsp_oracle as O
+from paper_1607_02560_amd import workloads as W
+from tests.test_gpu_parity import check_setup, gpu_setup, lsp_mod, torch_dev  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+PI2 = math.pi ** 2
+
+
+@pytest.mark.parametrize("d,n,t,seed", [
+    (2, 8, 1, 0), (2, 32, 1, 1), (2, 64, 2, 2), (2, 32, 3, 3), (3, 8, 1, 4), (3, 16, 1, 5),
+    (2, 256, 2, 6)])
+def test_global_setup_random_potential(torch_dev, d, n, t, seed):
+    r = np.random.default_rng(seed)
+    h2 = 1.0 / n ** 2
+    v = r.uniform(-8.0 / h2, -1.5 / h2, (n,) * d)
+    prob, P, idx, tab = check_setup(torch_dev, v, t, 0, global_=True)
+    # every row uses the one shift: P = Q + C diag(v - s)
+    assert np.all(idx == 0)
+
+
+def test_global_setup_workloads(torch_dev):
+    for p in (W.helm2d_gauss(32), W.schrod2d_wells(256), W.helm3d_random(64)):
+        check_setup(torch_dev, p.v, p.t, 0, global_=True)
+
+
+def test_global_setup_benchmark_size(torch_dev):
+    """2D, n = 1024, t = 2: the benchmark's field with the one-shift setup."""
+    p = W.helm2d_random(1024)
+    check_setup(torch_dev, p.v, p.t, 0, global_=True)
+
+
+@pytest.mark.parametrize("K", [0, 5, 25])
+def test_global_setup_resonant_mean(torch_dev, K):
+    """A constant v = -4 pi^2 K makes L + s singular; the shift moves to
+    (2 - 4K) pi^2 on the GPU as in the oracle (same bits), and every row is
+    the same."""
+    v = np.full((32, 32), -4.0 * PI2 * K)
+    prob, P, idx, tab = check_setup(torch_dev, v, 2, 0, global_=True)
+    assert tab["S"][0] == O.global_shift(v) == (2 - 4 * K) * PI2
+    assert np.array_equal(P, np.broadcast_to(P[0], P.shape))
+
+
+def test_global_matches_one_shift_localized_for_constant_v(torch_dev):
+    """Constant v = (4m + 2) pi^2: the localized list is that single value and
+    the mean is already resonance-free, so the two setups agree (the mean's
+    rounding aside)."""
+    v = np.full((64, 64), (4 * -9 + 2) * PI2)
+    _, Pg, ig, tg = gpu_setup(torch_dev, v, 2, 0, global_=True)
+    _, Pl, il, tl = gpu_setup(torch_dev, v, 2, 4)
+    assert len(tl["S"]) == 1
+    assert tg["S"][0] == pytest.approx(tl["S"][0], rel=1e-15)
+    assert np.array_equal(ig, il)
+    assert np.allclose(Pg, Pl, rtol=1e-8, atol=1e-12)
+
+
+def test_global_then_localized_on_one_problem(torch_dev, monkeypatch):
+    """Alternating non-localized and localized setups on one problem, with
+    graphs on (LSP_GRAPHS=1, non-default stream): each output equals that of a
+    fresh problem launched directly, so the two setups never share a graph."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    n, t, nS = 64, 2, 4
+    m = (2 * t + 1) ** 2
+    v = W.helm2d_random(n, t=t).v
+    vt = torch.from_numpy(v.reshape(-1)).to(dev)
+    stream = torch.cuda.Stream(dev)
+    monkeypatch.setenv("LSP_GRAPHS", "1")
+    graphed = lsp.Problem(2, n, vt, stream=stream)
+    monkeypatch.delenv("LSP_GRAPHS")
+    direct = lsp.Problem(2, n, vt, stream=stream)
+    Pg = torch.empty(n * n * m, dtype=torch.float64, device=dev)
+    Pd = torch.empty_like(Pg)
+    for rep, mode in enumerate(["global", "local", "global", "local", "global"]):
+        Pg.fill_(float("nan"))
+        torch.cuda.synchronize()
+        if mode == "global":
+            graphed.stencil_setup_global(t, Pg)
+            direct.stencil_setup_global(t, Pd)
+        else:
+            graphed.stencil_setup(t, nS, Pg)
+            direct.stencil_setup(t, nS, Pd)
+        torch.cuda.synchronize()
+        assert torch.equal(Pg, Pd), (rep, mode)
+        tab = graphed.get_tables()
+        assert len(tab["S"]) == (1 if mode == "global" else len(O.shift_list(v, nS))), rep
+
+
+def test_global_precond_solve(torch_dev):
+    """GMRES(40) with the non-localized preconditioner: iterations within +-1
+    of the oracle's, true residual <= 1e-8, solution equal to the dense solve."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    p = W.helm2d_gauss(32)
+    prob, P, idx, tab = gpu_setup(torch_dev, p.v, p.t, 0, global_=True)
+    solve = lsp.host_lu_solver(P, 2, 32, p.t)
+    ft = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    ut = torch.zeros_like(ft)
+    code, iters, relres = prob.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=200)
+    assert code == lsp.LSP_OK
+    u_or, it_or, est_or, rel_or, _ = O.precond_solve(p.v, p.f, p.t, 0, rtol=1e-8,
+                                                     non_localized=True)
+    print(f"[gmres, non-localized] gpu iters {iters} relres {relres:.2e}; "
+          f"oracle iters {it_or} relres {rel_or:.2e}", flush=True)
+    assert abs(iters - it_or) <= 1
+    assert relres <= 1e-8 and rel_or <= 1e-8
+    u_ref = np.linalg.solve(O.dense_operator(p.v), p.f.reshape(-1))
+    assert np.linalg.norm(ut.cpu().numpy() - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+
+
+def test_global_setup_fp32_storage(torch_dev):
+    """FP32 storage of the non-localized rows: tables bit-identical to the
+    FP64 setup and P32 = float32(P64) entry by entry."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    n, t = 128, 2
+    v = W.helm2d_random(n, t=t).v
+    N, m = n * n, (2 * t + 1) ** 2
+    prob = lsp.Problem(2, n, torch.from_numpy(v.reshape(-1)).to(dev))
+    P64 = torch.empty(N * m, dtype=torch.float64, device=dev)
+    P32 = torch.full((N * m,), float("nan"), dtype=torch.float32, device=dev)
+    prob.stencil_setup_global(t, P64)
+    t64 = prob.get_tables()
+    prob.stencil_setup_global(t, P32, precision=lsp.LSP_FP32_REFINE)
+    t32 = prob.get_tables()
+    torch.cuda.synchronize()
+    for key in ("S", "alpha", "C", "sigma_min", "M"):
+        assert np.array_equal(t64[key], t32[key]), key
+    assert torch.equal(P32, P64.to(torch.float32))

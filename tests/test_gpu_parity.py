@@ -38,7 +38,7 @@ def lsp_mod():
     return lsp
 
 
-def gpu_setup(torch_dev, v, t, nS):
+def gpu_setup(torch_dev, v, t, nS, global_=False):
     torch, dev = torch_dev
     lsp = lsp_mod()
     d, n = v.ndim, v.shape[0]
@@ -48,7 +48,10 @@ def gpu_setup(torch_dev, v, t, nS):
     prob = lsp.Problem(d, n, vt)
     P = torch.full((N * m,), float("nan"), dtype=torch.float64, device=dev)
     idx = torch.full((N,), -1, dtype=torch.int32, device=dev)
-    prob.stencil_setup(t, nS, P, idx)
+    if global_:
+        prob.stencil_setup_global(t, P, idx)
+    else:
+        prob.stencil_setup(t, nS, P, idx)
     tabs = prob.get_tables()
     torch.cuda.synchronize()
     return prob, P.cpu().numpy().reshape(N, m), idx.cpu().numpy(), tabs
@@ -62,13 +65,23 @@ def oracle_window(arr, t):
     return arr[tuple(grids)]
 
 
-def check_setup(torch_dev, v, t, nS, full_P=True):
+def check_setup(torch_dev, v, t, nS, full_P=True, global_=False):
+    """global_: the non-localized setup (one shift, the mean of v); its shift
+    is checked against the oracle's to 1e-13 relative (the two sum v in
+    different orders) and the tables are then compared at the GPU's shift."""
     d, n = v.ndim, v.shape[0]
-    prob, P, idx, tab = gpu_setup(torch_dev, v, t, nS)
-    print(f"[setup parity] d={d} n={n} t={t} nS={nS}", flush=True)
-    S_or = O.shift_list(v, nS)
-    assert np.array_equal(tab["S"], S_or), (tab["S"], S_or)
-    idx_or = O.assign_shifts(v, S_or).reshape(-1)
+    print(f"[setup parity] d={d} n={n} t={t} nS={nS} global={global_}", flush=True)
+    prob, P, idx, tab = gpu_setup(torch_dev, v, t, nS, global_)
+    if global_:
+        s_or = O.global_shift(v)
+        assert len(tab["S"]) == 1, tab["S"]
+        assert abs(tab["S"][0] - s_or) <= 1e-13 * abs(s_or), (tab["S"], s_or)
+        S_or = tab["S"].copy()
+        idx_or = np.zeros(v.size, dtype=np.int32)
+    else:
+        S_or = O.shift_list(v, nS)
+        assert np.array_equal(tab["S"], S_or), (tab["S"], S_or)
+        idx_or = O.assign_shifts(v, S_or).reshape(-1)
     assert np.array_equal(idx, idx_or)
     offs = O.offsets(d, t)
     tab_or = O.shift_tables(d, n, S_or, t)

@@ -395,15 +395,15 @@ def test_global_shift_is_the_mean():
 @pytest.mark.parametrize("K", [0, 1, 5, 25])
 def test_global_shift_moves_off_resonance(K):
     """A constant v = -4 pi^2 K makes L + s singular when K = |k|^2 for some
-    wavenumber (0, 1, 5 = 1 + 4, 25 = 9 + 16 on n = 16). The shift moves to a
-    value of the form (4m + 2) pi^2 at most 2 pi^2 away, where the nearest
-    eigenvalue of L + s is 2 pi^2 from zero."""
+    wavenumber (0, 1, 5 = 1 + 4, 25 = 9 + 16 on n = 16). The shift moves to
+    the value of the form (4m + 2) pi^2 with m = -K, 2 pi^2 above, where the
+    nearest eigenvalue of L + s is 2 pi^2 from zero."""
     n = 16
     v = np.full((n, n), -4.0 * PI2 * K)
     lam = O.symbol(2, n)
     assert np.min(np.abs(lam + v[0, 0])) <= 1e-12 * 4 * PI2 * max(K, 1)
     s = O.global_shift(v)
-    assert abs(s - v[0, 0]) <= 2 * PI2 * (1 + 1e-12)
+    assert s == pytest.approx(v[0, 0] + 2 * PI2, rel=1e-14, abs=1e-12)
     assert np.min(np.abs(lam + s)) == pytest.approx(2 * PI2, rel=1e-9)
     m = (s / PI2 - 2) / 4
     assert m == pytest.approx(round(m), abs=1e-9)
