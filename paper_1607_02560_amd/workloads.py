@@ -18,6 +18,22 @@ are stand-ins with the same structure:
   helm3d_random  3D analogue of helm2d_random.
   batch2d        64 problems of uneven n drawn from {64,128,256,512}.
 
+and one stand-in for each remaining field family of Sec. 5:
+
+  helm2d_cross     2D Helmholtz, constant c = 1 background with a cross of
+                   c = 0.7: the two bands |x - 1/2| < 0.05, |y - 1/2| < 0.05.
+  helm3d_gauss     3D Helmholtz, c = 1 - 0.3 exp(-|x-x0|^2/0.02).
+  helm3d_cross     3D Helmholtz, c = 0.7 inside three cylinders of radius
+                   0.05 along the three axes through the centre, else 1.
+  schrod2d_lattice 2D Schroedinger-type, an 8 x 8 array of equal Gaussian
+                   wells at (i, j)/8 with the one at the centre missing.
+  schrod3d_wells   3D analogue of schrod2d_wells (16 random wells).
+  schrod3d_lattice 3D analogue of schrod2d_lattice (4 x 4 x 4, centre missing).
+
+For the Schroedinger family v = n^2 (v_ext - E): v_ext is a sum of wells
+-D_i exp(-|x-c_i|^2 / (2 w_i^2)), and E = 2.4 as in Sec. 5; the lattices use
+D = 10 and w = 0.02 (2D) or 0.04 (3D).
+
 Layout: C order, the last axis varies fastest; point j = (j_1,...,j_d) sits
 at x = h j. Potentials are float64, right-hand sides complex128.
 """
@@ -32,6 +48,8 @@ __all__ = [
     "Problem", "grid_coords", "periodic_sqdist", "smooth_random_c",
     "helm2d_gauss", "schrod2d_wells", "helm2d_random", "helm3d_random",
     "batch2d", "gaussian_source", "random_field_v", "make", "CONFIGS",
+    "helm2d_cross", "helm3d_gauss", "helm3d_cross", "schrod2d_lattice", "schrod3d_wells",
+    "schrod3d_lattice",
 ]
 
 
@@ -183,6 +201,102 @@ def batch2d(count: int = 64, seed: int = 0, sizes=(64, 128, 256, 512)):
             for p, n_p in enumerate(ns)]
 
 
+def _helmholtz(name: str, d: int, n: int, c: np.ndarray, t: int, num_shifts: int) -> Problem:
+    omega = 2.0 * np.pi * n / 8.0
+    v = -(omega / c) ** 2
+    f = gaussian_source(d, n, (0.5,) * d, 0.05)
+    return Problem(name, d, n, np.ascontiguousarray(v), f, t=t, num_shifts=num_shifts,
+                   omega=omega)
+
+
+def _band_distance(d: int, n: int, axis: int) -> np.ndarray:
+    """Periodic distance of the grid points from the plane x_axis = 1/2."""
+    x = np.arange(n) / n - 0.5
+    x = np.minimum(np.abs(x), 1.0 - np.abs(x))
+    shape = [1] * d
+    shape[axis] = n
+    return np.broadcast_to(x.reshape(shape), (n,) * d)
+
+
+def helm2d_cross(n: int = 128, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
+    """2D Helmholtz, constant background with a cross-shaped slow region."""
+    d = 2
+    cross = (_band_distance(d, n, 0) < 0.05) | (_band_distance(d, n, 1) < 0.05)
+    c = np.where(cross, 0.7, 1.0)
+    return _helmholtz("helm2d_cross", d, n, c, t, num_shifts or max(1, n // 16))
+
+
+def helm3d_gauss(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
+    """3D Helmholtz, constant background with a Gaussian profile at the centre."""
+    d = 3
+    c = 1.0 - 0.3 * np.exp(-periodic_sqdist(d, n, (0.5, 0.5, 0.5)) / 0.02)
+    return _helmholtz("helm3d_gauss", d, n, c, t, num_shifts or max(1, n // 4))
+
+
+def helm3d_cross(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
+    """3D Helmholtz, three slow cylinders along the axes through the centre."""
+    d = 3
+    r = [_band_distance(d, n, a) for a in range(d)]
+    cyl = ((r[1] ** 2 + r[2] ** 2 < 0.05 ** 2) | (r[0] ** 2 + r[2] ** 2 < 0.05 ** 2)
+           | (r[0] ** 2 + r[1] ** 2 < 0.05 ** 2))
+    c = np.where(cyl, 0.7, 1.0)
+    return _helmholtz("helm3d_cross", d, n, c, t, num_shifts or max(1, n // 4))
+
+
+def _wells(d: int, n: int, centres, depth, width, energy: float = 2.4) -> np.ndarray:
+    v_ext = np.zeros((n,) * d)
+    for c, D, w in zip(centres, depth, width):
+        v_ext -= D * np.exp(-periodic_sqdist(d, n, c) / (2.0 * w * w))
+    return n * n * (v_ext - energy)
+
+
+def _lattice_centres(d: int, per_axis: int):
+    """Centres k / per_axis (k = 0..per_axis-1 per axis; per_axis even, so one
+    centre is the domain's centre) without the centre one."""
+    assert per_axis % 2 == 0
+    ticks = np.arange(per_axis) / per_axis
+    grids = np.meshgrid(*([ticks] * d), indexing="ij")
+    pts = np.stack([g.reshape(-1) for g in grids], axis=1)
+    keep = np.any(np.abs(pts - 0.5) > 1e-12, axis=1)
+    assert keep.sum() == per_axis ** d - 1
+    return pts[keep]
+
+
+def _random_rhs(d: int, n: int, seed: int) -> np.ndarray:
+    rng_f = np.random.default_rng(seed)
+    return (rng_f.standard_normal((n,) * d) + 1j * rng_f.standard_normal((n,) * d)) / np.sqrt(2.0)
+
+
+def schrod2d_lattice(n: int = 128, seed: int = 0, t: int = 2, num_shifts=None) -> Problem:
+    """2D Schroedinger-type: an 8 x 8 lattice of equal wells, the centre one missing."""
+    d = 2
+    cen = _lattice_centres(d, 8)
+    v = _wells(d, n, cen, [10.0] * len(cen), [0.02] * len(cen))
+    return Problem("schrod2d_lattice", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
+                   t=t, num_shifts=num_shifts or max(1, n // 16))
+
+
+def schrod3d_wells(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
+    """3D Schroedinger-type: 16 Gaussian wells at random centres."""
+    d = 3
+    rng = np.random.default_rng(seed)
+    centres = rng.random((16, d))
+    depth = rng.uniform(5.0, 20.0, 16)
+    width = rng.uniform(0.03, 0.06, 16)
+    v = _wells(d, n, centres, depth, width)
+    return Problem("schrod3d_wells", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
+                   t=t, num_shifts=num_shifts or max(1, n // 4))
+
+
+def schrod3d_lattice(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
+    """3D Schroedinger-type: a 4 x 4 x 4 lattice of equal wells, the centre one missing."""
+    d = 3
+    cen = _lattice_centres(d, 4)
+    v = _wells(d, n, cen, [10.0] * len(cen), [0.04] * len(cen))
+    return Problem("schrod3d_lattice", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
+                   t=t, num_shifts=num_shifts or max(1, n // 4))
+
+
 def random_field_v(d: int, n: int, seed: int, lo: float, hi: float) -> np.ndarray:
     """Uniform random potential in [lo, hi] (for tests of host logic and edge cases)."""
     rng = np.random.default_rng(seed)
@@ -194,6 +308,12 @@ CONFIGS = {
     "schrod2d_wells_n256": lambda: schrod2d_wells(256),
     "helm2d_random_n1024": lambda: helm2d_random(1024),
     "helm3d_random_n64": lambda: helm3d_random(64),
+    "helm2d_cross_n128": lambda: helm2d_cross(128),
+    "helm3d_gauss_n32": lambda: helm3d_gauss(32),
+    "helm3d_cross_n32": lambda: helm3d_cross(32),
+    "schrod2d_lattice_n128": lambda: schrod2d_lattice(128),
+    "schrod3d_wells_n32": lambda: schrod3d_wells(32),
+    "schrod3d_lattice_n32": lambda: schrod3d_lattice(32),
 }
 
 

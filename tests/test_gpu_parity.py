@@ -225,6 +225,18 @@ def test_setup_helm2d_random_n1024(torch_dev):
     check_setup(torch_dev, p.v, p.t, p.num_shifts, full_P=True)
 
 
+@pytest.mark.parametrize("name", ["helm2d_cross_n128", "helm3d_gauss_n32", "helm3d_cross_n32",
+                                  "schrod2d_lattice_n128", "schrod3d_wells_n32",
+                                  "schrod3d_lattice_n32"])
+def test_setup_paper_field_families(torch_dev, name):
+    """Stand-ins for the other field families of Sec. 5 (cross profiles,
+    3D Gaussian, random wells, lattices with a vacancy): the localized and
+    the non-localized setups."""
+    p = W.make(name)
+    check_setup(torch_dev, p.v, p.t, p.num_shifts)
+    check_setup(torch_dev, p.v, p.t, 0, global_=True)
+
+
 def test_setup_constant_potential(torch_dev):
     """Translation invariance: constant v gives one shift and identical rows."""
     v = np.full((32, 32), -2.0e4)
@@ -398,6 +410,24 @@ def test_precond_solve_helm2d_gauss(torch_dev):
     u = ut.cpu().numpy()
     u_ref = np.linalg.solve(O.dense_operator(p.v), p.f.reshape(-1))
     assert np.linalg.norm(u - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+
+
+def test_precond_solve_cross_profile(torch_dev):
+    """GMRES(40) on the 2D cross-profile Helmholtz field (n = 128, t = 1):
+    iterations within +-1 of the oracle's, true residual <= 1e-8."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    p = W.helm2d_cross(128)
+    prob, P, idx, tab = gpu_setup(torch_dev, p.v, p.t, p.num_shifts)
+    solve = lsp.host_lu_solver(P, 2, p.n, p.t)
+    ft = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    ut = torch.zeros_like(ft)
+    code, iters, relres = prob.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=200)
+    assert code == lsp.LSP_OK
+    _, it_or, _, rel_or, _ = O.precond_solve(p.v, p.f, p.t, p.num_shifts, rtol=1e-8)
+    print(f"[gmres cross] gpu iters {iters} relres {relres:.2e}; oracle {it_or} {rel_or:.2e}",
+          flush=True)
+    assert abs(iters - it_or) <= 1 and relres <= 1e-8
 
 
 def test_precond_solve_callback_error(torch_dev):
