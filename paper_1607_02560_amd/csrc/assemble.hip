@@ -306,6 +306,7 @@ hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   LSP_DISPATCH_DW(2, 5, (run_assemble<2, 5>(p, P, fp32, idx)))
   LSP_DISPATCH_DW(2, 7, (run_assemble<2, 7>(p, P, fp32, idx)))
   LSP_DISPATCH_DW(3, 3, (run_assemble<3, 3>(p, P, fp32, idx)))
+  LSP_DISPATCH_DW(3, 5, (run_assemble<3, 5>(p, P, fp32, idx)))
   return hipErrorInvalidValue;
 }
 
@@ -338,6 +339,7 @@ hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z) {
   LSP_DISPATCH_DW(2, 5, (run_c_apply<2, 5>(p, r, z)))
   LSP_DISPATCH_DW(2, 7, (run_c_apply<2, 7>(p, r, z)))
   LSP_DISPATCH_DW(3, 3, (run_c_apply<3, 3>(p, r, z)))
+  LSP_DISPATCH_DW(3, 5, (run_c_apply<3, 5>(p, r, z)))
   return hipErrorInvalidValue;
 }
 

@@ -241,6 +241,8 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
   for (int i = 0; i < count; ++i) {
     if (!P_dev[i]) return lsp::set_error(LSP_EINVAL, "P_dev[" + std::to_string(i) + "] is NULL");
     nreq[i] = num_shifts ? num_shifts[i] : 0;
+    if (b->probs[i]->d == 3 && t != 1)
+      return lsp::set_error(LSP_EINVAL, "batched setups support d = 3 with t = 1");
     const int rc = lsp::prepare_setup(b->probs[i], t, &nreq[i]);
     if (rc) return rc;
   }

@@ -262,9 +262,9 @@ __device__ __forceinline__ void green_body(
   constexpr int NP = Lay::NP;
   constexpr int WO2 = Lay::WO2;
   constexpr int NV = Lay::NV;
-  static_assert(NV <= 64, "one lane per partial value");
+  static_assert(NV <= 64 || D == 3, "one lane per partial value (2D)");
   static_assert(D == 3 || KT == kTile, "2D diagonal units must be square tiles");
-  constexpr int P2 = pow2_at_least(NV);
+  constexpr int P2 = pow2_at_least(NV <= 64 ? NV : 64);
   constexpr int PER = (KT * W + kThreads - 1) / kThreads;  // staged table values per thread
   __shared__ double cws[KT * W];
   __shared__ double sS[lsp::kMaxShifts];
@@ -380,6 +380,46 @@ __device__ __forceinline__ void green_body(
     for (int j = 0; j < W; ++j) ck[j] *= half;
   }
 
+  if constexpr (NV > 64) {
+    // 3D with more than 64 values per partial (W = 5: 150): the leading
+    // offsets x go in chunks of XC, each chunk one halving sum of its
+    // 2 XC NP <= 64 values, laid out [g | g*g][x in chunk][pairs]; the lane
+    // holding local value lv writes the global value it stands for.
+    constexpr int XC = 64 / (2 * NP);
+    constexpr int NCH = (WO2 + XC - 1) / XC;
+    static_assert(XC >= 1 && D == 3, "chunked partials");
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      double a[64];
+#pragma unroll
+      for (int i = 0; i < 64; ++i) a[i] = 0.0;
+#pragma unroll
+      for (int xx = 0; xx < XC; ++xx) {
+        const int x = ch * XC + xx;
+        if (x < WO2) {
+          int pi = 0;
+#pragma unroll
+          for (int da = 0; da < W; ++da) {
+#pragma unroll
+            for (int db = da; db < W; ++db) {
+              a[xx * NP + pi] = lead[x] * (ck[da] * tg[db] + ck[db] * tg[da]);
+              a[XC * NP + xx * NP + pi] = lead[x] * (ck[da] * tq[db] + ck[db] * tq[da]);
+              ++pi;
+            }
+          }
+        }
+      }
+      const int lv = halving_sum<64>(a, lane);
+      const bool gpart = lv < XC * NP;
+      const int loc = gpart ? lv : lv - XC * NP;
+      const int x = ch * XC + loc / NP;
+      if (loc < XC * NP && x < WO2) {
+        const int vi = (gpart ? 0 : WO2 * NP) + x * NP + loc % NP;
+        part[((int64_t)si * gx + bx) * NV + vi] = a[0];
+      }
+    }
+    return;
+  } else {
   // symmetrised accumulation of the offset pairs (da <= db), padded to P2
   double a[P2];
 #pragma unroll
@@ -426,6 +466,7 @@ __device__ __forceinline__ void green_body(
       val += (ca * cb) * rr;
     }
     part[((int64_t)si * gx + bx) * NV + vi] = val;
+  }
   }
 }
 
@@ -526,6 +567,7 @@ hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units, bool gl
   if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, units, global);
   if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, units, global);
   if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, units, global);
+  if (p->d == 3 && W == 5) return run_green<3, 5>(p, num_shifts, units, global);
   return hipErrorInvalidValue;
 }
 
@@ -543,6 +585,7 @@ size_t green_partial_doubles(int d, int n, int t, int shifts) {
   if (d == 2 && W == 5) return shifts * nu * GreenLayout<2, 5>::NV;
   if (d == 2 && W == 7) return shifts * nu * GreenLayout<2, 7>::NV;
   if (d == 3 && W == 3) return shifts * nu * GreenLayout<3, 3>::NV;
+  if (d == 3 && W == 5) return shifts * nu * GreenLayout<3, 5>::NV;
   return 0;
 }
 

@@ -17,7 +17,7 @@ constexpr double kFourPi2 = 39.47841760435743;
 constexpr double kPi2 = 9.869604401089358;
 
 // Upper bounds of the build.
-constexpr int kMaxStencil = 64;     // m = (2t+1)^d
+constexpr int kMaxStencil = 125;    // m = (2t+1)^d
 constexpr int kMaxShifts = 1024;    // requested |S|
 constexpr int kMinMaxBlocks = 256;  // blocks (= partials) of the min/max reduction
 

@@ -300,6 +300,78 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   }
 }
 
+// alpha and C on mu_0^t for m > 64 offsets (3D, t = 2): wave 0, lane l
+// holds offsets l + 64 h. Same mapping, sign rule (largest |alpha| positive,
+// lowest offset on ties) and outputs as the m <= 64 path.
+template <int D, int W>
+__device__ void map_back_wide(NullShared<D, W>& sh, int cs, int wid, int lane, int si,
+                              double* alpha_out, double* C_out, double* actab) {
+  using Pa = Parity<D, W>;
+  using Nb = Nbhd<D, W>;
+  constexpr int M = Pow<D, W>::v;
+  constexpr int H = (M + 63) / 64;
+  if (wid != 0) return;
+  double av[H], cv[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    av[h] = 0.0;
+    cv[h] = 0.0;
+    const int a = lane + 64 * h;
+    if (a < M) {
+      double coef = 1.0;
+      int pidx = 0;
+      for (int i = 0; i < D; ++i) {
+        const int xi = Nb::comp(a, i);
+        const int ji = xi < 0 ? -xi : xi;
+        const int odd = Pa::odd(cs, i);
+        if (odd && ji == 0) coef = 0.0;
+        if (ji != 0) coef *= (odd && xi < 0) ? -lsp::kInvSqrt2 : lsp::kInvSqrt2;
+        pidx = pidx * Pa::count(cs, i) + (ji - odd < 0 ? 0 : ji - odd);
+      }
+      if (coef != 0.0) {
+        av[h] = coef * sh.vec[cs][pidx];
+        cv[h] = coef * sh.gv[cs][pidx];
+      }
+    }
+  }
+  // largest |alpha| over all offsets, lowest offset on ties
+  double am = -1.0;
+  int jm = M;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int a = lane + 64 * h;
+    if (a < M && fabs(av[h]) > am) {  // h increases with a: ties keep the lower
+      am = fabs(av[h]);
+      jm = a;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ao = __shfl_xor(am, o);
+    const int jo = __shfl_xor(jm, o);
+    if (ao > am || (ao == am && jo < jm)) {
+      am = ao;
+      jm = jo;
+    }
+  }
+  // alpha at offset jm, from the lane that holds it
+  double at = 0.0;
+#pragma unroll
+  for (int h = 0; h < H; ++h)
+    if (jm / 64 == h) at = av[h];
+  const double sgn = (bcast(at, jm % 64) < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int a = lane + 64 * h;
+    if (a < M) {
+      alpha_out[(int64_t)si * M + a] = av[h] * sgn;
+      C_out[(int64_t)si * M + a] = cv[h] * sgn;
+      reinterpret_cast<double2*>(actab)[(int64_t)si * M + a] =
+          make_double2(av[h] * sgn, cv[h] * sgn);
+    }
+  }
+}
+
 template <int D, int W>
 __device__ __forceinline__ void null_body(
     int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
@@ -325,9 +397,9 @@ __device__ __forceinline__ void null_body(
   // Thread (grp, v) = (tid / NVP, tid % NVP) adds the partials of value v from
   // work units b = grp, grp + G, ... in increasing b; then thread v adds the G
   // group sums in group order (a fixed order, so the result is deterministic).
-  constexpr int NVP = (NV <= 32) ? 32 : 64;
+  constexpr int NVP = (NV <= 32) ? 32 : (NV <= 64) ? 64 : 256;
   constexpr int G = T / NVP;
-  static_assert(NV <= NVP && G >= 1, "partial-sum groups");
+  static_assert(NV <= NVP && G >= 1 && T % NVP == 0, "partial-sum groups");
   const double* ps = part + (int64_t)si * nblk * NV;
   const int gv = tid % NVP, grp = tid / NVP;
   double acc = 0.0;
@@ -412,6 +484,9 @@ __device__ __forceinline__ void null_body(
   for (int c = 1; c < NC; ++c)
     if (sh.lam[c] < sh.lam[cs]) cs = c;
   const double lam = sh.lam[cs];
+  if constexpr (M > 64) {
+    map_back_wide<D, W>(sh, cs, wid, lane, si, alpha_out, C_out, actab);
+  } else {
   double av = 0.0, cv = 0.0;
   if (wid == 0 && lane < M) {
     // offset a = lane: block row and coefficient of a in class cs
@@ -451,6 +526,8 @@ __device__ __forceinline__ void null_body(
     C_out[(int64_t)si * M + lane] = cv;
     reinterpret_cast<double2*>(actab)[(int64_t)si * M + lane] = make_double2(av, cv);
   }
+  }
+  if (wid != 0) return;
   if (lane == 0) {
     sigma_out[si] = sqrt(fmax(lam, 0.0));
     // rho*(s)^2 = alpha^T M alpha / alpha^T A1 alpha, alpha = Q x of the class
@@ -516,6 +593,7 @@ hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk, int* cl
   if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, nblk, clear_counter);
   if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, nblk, clear_counter);
   if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, nblk, clear_counter);
+  if (p->d == 3 && W == 5) return run_null<3, 5>(p, num_shifts, nblk, clear_counter);
   return hipErrorInvalidValue;
 }
 
@@ -560,6 +638,7 @@ int expand_gram_host(int d, int t, const double* packed, double* full) {
     else if (d == 2 && W == 5) parity_basis_host<2, 5>(c, Q.data());
     else if (d == 2 && W == 7) parity_basis_host<2, 7>(c, Q.data());
     else if (d == 3 && W == 3) parity_basis_host<3, 3>(c, Q.data());
+    else if (d == 3 && W == 5) parity_basis_host<3, 5>(c, Q.data());
     else return -1;
     const double* Mc = packed + off;
     for (int a = 0; a < M; ++a)

@@ -127,8 +127,11 @@ def check_setup(torch_dev, v, t, nS, full_P=True, global_=False):
         vnb = np.stack([np.roll(v, tuple(-offs[a]), axis=tuple(range(d))).reshape(-1)
                         for a in range(offs.shape[0])], axis=1)
         dist = np.abs(vnb - S_or[idx_or][:, None])
-        bound = da_tab[idx_or] + dc_tab[idx_or] * dist + 8 * EPS * (np.abs(P_or) + np.abs(
-            tab_or["C"][idx_or]) * dist)
+        # |P - P_or| <= |d alpha| + |d C| |v - s| in exact arithmetic; each side
+        # also carries the rounding of its own evaluation alpha + C (v - s)
+        rnd = (np.abs(P_or) + np.abs(P) + (np.abs(tab_or["C"][idx_or])
+                                            + np.abs(tab["C"][idx_or])) * dist)
+        bound = da_tab[idx_or] + dc_tab[idx_or] * dist + 8 * EPS * rnd
         assert np.all(np.abs(P - tab_or_P) <= bound)
     print(f"   |S|={len(S_or)} max alpha diff {worst.get('alpha', 0):.2e}", flush=True)
     return prob, P, idx, tab
@@ -287,7 +290,7 @@ def test_setup_rejects_bad_arguments(torch_dev):
     prob = lsp.Problem(2, 16, torch.full((256,), -100.0, dtype=torch.float64, device=dev))
     P = torch.empty(256 * 81, dtype=torch.float64, device=dev)
     with pytest.raises(lsp.LSPError):
-        prob.stencil_setup(4, 2, P)          # (2t+1)^2 = 81 > 64
+        prob.stencil_setup(4, 2, P)          # 2D supports t <= 3
     P9 = torch.empty(256 * 9, dtype=torch.float64, device=dev)
     with pytest.raises(lsp.LSPError):
         prob.stencil_setup(1, 2, P9, precision=7)   # unknown precision mode
@@ -310,7 +313,7 @@ def test_create_rejects_nonfinite(torch_dev):
 
 # ------------------------------------------------- FP32 storage of P -----
 @pytest.mark.parametrize("d,n,t,nS", [(2, 64, 2, 4), (2, 32, 3, 3), (3, 16, 1, 4),
-                                      (2, 1024, 2, 64)])
+                                      (2, 1024, 2, 64), (3, 16, 2, 4)])
 def test_setup_fp32_storage(torch_dev, d, n, t, nS):
     """LSP_FP32_REFINE computes everything in FP64 and stores P in float32:
     the shift tables and idx equal those of the FP64 setup bit for bit, and
@@ -373,7 +376,8 @@ def test_precond_solve_fp32_rows(torch_dev):
 # ------------------------------------------------------------- C-apply -----
 # (2, 1024, 2, 64) is the bench workload, in the launch configuration it times
 @pytest.mark.parametrize("d,n,t,nS", [(2, 32, 1, 2), (2, 64, 2, 4), (3, 16, 1, 4), (2, 256, 2, 16),
-                                      (2, 1024, 2, 64), (3, 64, 1, 16)])
+                                      (2, 1024, 2, 64), (3, 64, 1, 16), (3, 16, 2, 4),
+                                      (3, 64, 2, 16)])
 def test_c_apply_matches_oracle(torch_dev, d, n, t, nS):
     torch, dev = torch_dev
     r = np.random.default_rng(5)

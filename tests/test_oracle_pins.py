@@ -182,7 +182,7 @@ def test_default_shift_counts_match_tables():
 
 # ------------------------------------------------------- eq. (A), Sec. 4.2 --
 @pytest.mark.parametrize("d,n,t,m_shift", [(2, 16, 1, -20), (2, 16, 2, -30), (3, 8, 1, -9),
-                                           (1, 32, 2, -15)])
+                                           (1, 32, 2, -15), (3, 8, 2, -9)])
 def test_gram_identity(d, n, t, m_shift):
     """B B^T = A1 - A2 with B = G_s[mu_0, mu_0^c] built explicitly (eq. A)."""
     s = (4 * m_shift + 2) * PI2
@@ -202,7 +202,8 @@ def test_offsets_order():
     assert O.offsets(3, 2).shape == (125, 3)
 
 
-@pytest.mark.parametrize("d,n,t,m_shift", [(2, 16, 1, -20), (2, 16, 2, -30), (3, 8, 1, -9)])
+@pytest.mark.parametrize("d,n,t,m_shift", [(2, 16, 1, -20), (2, 16, 2, -30), (3, 8, 1, -9),
+                                           (3, 8, 2, -9)])
 def test_null_vector_is_the_optimal_stencil(d, n, t, m_shift):
     """alpha from the eigen route is the minimiser of ||alpha^T B||_2 (Sec. 3):
     it agrees with the last left singular vector of B (the definition route)
@@ -243,7 +244,7 @@ def _dense_setup(v, t, num_shifts):
     return setup, L, Q, cols
 
 
-@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1)])
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1), (3, 6, 2)])
 def test_C_is_truncated_QG_and_residual_is_sigma(d, n, t):
     """C[j, mu_j] = (Q G_{s_j})[j, mu_j] and ||(Q G_{s_j})[j, mu_j^c]|| = sigma_min
     (Sec. 3 truncation, Sec. 4.1 local shifts), dense on a tiny grid."""
@@ -415,7 +416,7 @@ def test_global_shift_keeps_non_resonant_mean():
     assert O.global_shift(v) == v[0, 0]
 
 
-@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1)])
+@pytest.mark.parametrize("d,n,t", [(2, 8, 1), (2, 12, 2), (3, 6, 1), (3, 6, 2)])
 def test_global_setup_dense_definition(d, n, t):
     """Sec. 3 on a tiny grid from dense matrices: every row of Q holds the same
     unit vector alpha, the left singular vector of the smallest singular value
