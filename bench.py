@@ -285,6 +285,35 @@ def non_localized_section(dev, t_setup_g, N):
             "gmres": gm}
 
 
+def section_3d_t2(dev, reps):
+    """Setup with 5x5x5 stencils (t = 2) on the 3D Helmholtz field, n = 64."""
+    import torch
+    from paper_1607_02560_amd import lsp
+    from paper_1607_02560_amd import workloads as W
+    q = W.helm3d_random(64, t=2)
+    m = (2 * q.t + 1) ** 3
+    pr = lsp.Problem(3, q.n, torch.from_numpy(q.v.reshape(-1)).to(dev))
+    Pq = torch.empty(q.N * m, dtype=torch.float64, device=dev)
+    iq = torch.empty(q.N, dtype=torch.int32, device=dev)
+    fn = lambda: pr.stencil_setup(q.t, q.num_shifts, Pq, iq)
+    for _ in range(3):
+        fn()
+    stream = torch.cuda.current_stream(dev)
+    ts = timed(stream, fn, reps)
+    pr.profile(True)
+    for _ in range(reps):
+        fn()
+    prof = pr.profile_read()
+    pr.profile(False)
+    pr.close()
+    stage = {k: prof[k][0] / max(prof[k][1], 1) for k in ("shifts", "green", "null", "assemble")}
+    nbytes = q.N * (8 + 8 * m + 4)
+    return {"workload": f"3D Helmholtz, smooth random c in [0.8,1.2], n={q.n} (N={q.N}), "
+                        f"t={q.t} (5x5x5 stencils), |S|={q.num_shifts}",
+            "setup_ms": ts * 1e3, "stencils_per_s": q.N / ts, "stage_ms_profiled": stage,
+            "assemble_hbm_frac": nbytes / (stage["assemble"] * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -297,6 +326,8 @@ def main():
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-form section")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the non-localized and 3D t = 2 sections")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run 5 device-to-device copies of MiB mebibytes and exit")
     args = ap.parse_args()
@@ -370,10 +401,11 @@ def main():
     del P32
     # the non-localized setup of Sec. 3 (one shift, the mean of v) on the
     # same field and buffers
-    setup_g = lambda: prob.stencil_setup_global(t, P, idx)
-    for _ in range(args.warmup):
-        setup_g()
-    t_setup_g = timed(stream, setup_g, args.steps)
+    if not args.no_extras:
+        setup_g = lambda: prob.stencil_setup_global(t, P, idx)
+        for _ in range(args.warmup):
+            setup_g()
+        t_setup_g = timed(stream, setup_g, args.steps)
     # per-stage HIP events recorded by the library on its stream (direct
     # launches): the dominant kernel's average duration for the roofline
     prob.profile(True)
@@ -426,14 +458,17 @@ def main():
         "roofline_ps_apply": {"bound": "hbm", "achieved": apply_gbps, "peak": HBM_PEAK_GBPS,
                               "unit": "GB/s", "frac": apply_gbps / HBM_PEAK_GBPS,
                               "bytes_per_call": nb["apply"]},
-        "non_localized": non_localized_section(dev, t_setup_g, N),
         "c_apply_ms": t_capply * 1e3,
         "roofline_c_apply": {"bound": "hbm", "achieved": capply_gbps, "peak": HBM_PEAK_GBPS,
                              "unit": "GB/s", "frac": capply_gbps / HBM_PEAK_GBPS,
                              "bytes_per_call": nb["c_apply"]},
     }
+    if not args.no_extras:
+        out["non_localized"] = non_localized_section(dev, t_setup_g, N)
     prob.close()
     del P, idx
+    if not args.no_extras:
+        out["form_3d_t2"] = section_3d_t2(dev, args.steps)
     if not args.no_learned:
         out["learned_vs_exact"] = learned_vs_exact(dev, stream, args.steps, args.train_steps)
     if not args.no_batched:

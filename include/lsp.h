@@ -101,7 +101,9 @@ void lsp_destroy(lsp_problem* p);
  *   5. per grid point j: idx_j = index in S of the shift closest to v_j
  *      (ties to the lower index) and the P row
  *      P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j+a] - s_j), a in mu_0^t.
- *   t           neighbourhood radius, 1 <= t, with m = (2t+1)^d <= 64 and 2t+1 < n.
+ *   t           neighbourhood radius: t = 1, 2, 3 for d = 2 and t = 1, 2 for d = 3
+ *               (m = (2t+1)^d up to 49 and 125), with 2t+1 < n and N >= 2m.
+ *               The learned and batched setups take d = 3 only with t = 1.
  *   num_shifts  requested |S| (1..1024); 0 selects n/16 for d = 2, n/4 for d = 3
  *               (at least 1). The effective count |S| may be smaller.
  *   precision   LSP_FP64 (P in float64) or LSP_FP32_REFINE (P in float32,
