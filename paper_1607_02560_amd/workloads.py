@@ -25,14 +25,18 @@ and one stand-in for each remaining field family of Sec. 5:
   helm3d_gauss     3D Helmholtz, c = 1 - 0.3 exp(-|x-x0|^2/0.02).
   helm3d_cross     3D Helmholtz, c = 0.7 inside three cylinders of radius
                    0.05 along the three axes through the centre, else 1.
-  schrod2d_lattice 2D Schroedinger-type, an 8 x 8 array of equal Gaussian
-                   wells at (i, j)/8 with the one at the centre missing.
-  schrod3d_wells   3D analogue of schrod2d_wells (16 random wells).
+  schrod2d_lattice 2D Schroedinger, an 8 x 8 array of equal Gaussians at
+                   (i, j)/8 with the one at the centre missing.
+  schrod3d_wells   3D Schroedinger, 16 Gaussians at random centres.
   schrod3d_lattice 3D analogue of schrod2d_lattice (4 x 4 x 4, centre missing).
 
-For the Schroedinger family v = n^2 (v_ext - E): v_ext is a sum of wells
--D_i exp(-|x-c_i|^2 / (2 w_i^2)), and E = 2.4 as in Sec. 5; the lattices use
-D = 10 and w = 0.02 (2D) or 0.04 (3D).
+The Schroedinger stand-ins follow Sec. 5's scaling v = (v_ext(x/h) - E)/h^2
+with E = 2.4: v_ext >= 0 is a sum of Gaussian bumps A_i exp(-|y - y_i|^2 /
+(2 s_i^2)) in grid units y = x/h, so -h^2 v <= E and every oscillation spans
+at least 2 pi / sqrt(2.4) > 4 grid points. The lattices use A = 4, s = 2 grid
+points (1.5 in 3D); the random bumps A ~ U[2, 6], s ~ U[1.5, 3].
+(schrod2d_wells above is the deliberately harder deep-well case, outside that
+scaling.)
 
 Layout: C order, the last axis varies fastest; point j = (j_1,...,j_d) sits
 at x = h j. Potentials are float64, right-hand sides complex128.
@@ -243,10 +247,13 @@ def helm3d_cross(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Pro
     return _helmholtz("helm3d_cross", d, n, c, t, num_shifts or max(1, n // 4))
 
 
-def _wells(d: int, n: int, centres, depth, width, energy: float = 2.4) -> np.ndarray:
+def _bumps(d: int, n: int, centres, height, width_grid, energy: float = 2.4) -> np.ndarray:
+    """v = n^2 (v_ext - energy), v_ext a sum of Gaussian bumps whose widths
+    are given in grid points (Sec. 5: v_ext is a function of x/h)."""
     v_ext = np.zeros((n,) * d)
-    for c, D, w in zip(centres, depth, width):
-        v_ext -= D * np.exp(-periodic_sqdist(d, n, c) / (2.0 * w * w))
+    for c, A, s in zip(centres, height, width_grid):
+        w = s / n
+        v_ext += A * np.exp(-periodic_sqdist(d, n, c) / (2.0 * w * w))
     return n * n * (v_ext - energy)
 
 
@@ -268,31 +275,31 @@ def _random_rhs(d: int, n: int, seed: int) -> np.ndarray:
 
 
 def schrod2d_lattice(n: int = 128, seed: int = 0, t: int = 2, num_shifts=None) -> Problem:
-    """2D Schroedinger-type: an 8 x 8 lattice of equal wells, the centre one missing."""
+    """2D Schroedinger: an 8 x 8 lattice of equal bumps, the centre one missing."""
     d = 2
     cen = _lattice_centres(d, 8)
-    v = _wells(d, n, cen, [10.0] * len(cen), [0.02] * len(cen))
+    v = _bumps(d, n, cen, [4.0] * len(cen), [2.0] * len(cen))
     return Problem("schrod2d_lattice", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
                    t=t, num_shifts=num_shifts or max(1, n // 16))
 
 
 def schrod3d_wells(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
-    """3D Schroedinger-type: 16 Gaussian wells at random centres."""
+    """3D Schroedinger: 16 Gaussian bumps at random centres."""
     d = 3
     rng = np.random.default_rng(seed)
     centres = rng.random((16, d))
-    depth = rng.uniform(5.0, 20.0, 16)
-    width = rng.uniform(0.03, 0.06, 16)
-    v = _wells(d, n, centres, depth, width)
+    height = rng.uniform(2.0, 6.0, 16)
+    width = rng.uniform(1.5, 3.0, 16)
+    v = _bumps(d, n, centres, height, width)
     return Problem("schrod3d_wells", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
                    t=t, num_shifts=num_shifts or max(1, n // 4))
 
 
 def schrod3d_lattice(n: int = 32, seed: int = 0, t: int = 1, num_shifts=None) -> Problem:
-    """3D Schroedinger-type: a 4 x 4 x 4 lattice of equal wells, the centre one missing."""
+    """3D Schroedinger: a 4 x 4 x 4 lattice of equal bumps, the centre one missing."""
     d = 3
     cen = _lattice_centres(d, 4)
-    v = _wells(d, n, cen, [10.0] * len(cen), [0.04] * len(cen))
+    v = _bumps(d, n, cen, [4.0] * len(cen), [1.5] * len(cen))
     return Problem("schrod3d_lattice", d, n, np.ascontiguousarray(v), _random_rhs(d, n, seed + 1),
                    t=t, num_shifts=num_shifts or max(1, n // 4))
 

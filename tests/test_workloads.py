@@ -44,21 +44,27 @@ def test_helm3d_gauss_is_slowest_at_the_centre():
 def test_lattice_has_a_vacancy_at_the_centre(d, n, per_axis):
     p = W.schrod2d_lattice(n) if d == 2 else W.schrod3d_lattice(n)
     background = -2.4 * n * n
-    well = n * n * (-10.0 - 2.4)
+    bump = n * n * (4.0 - 2.4)
     step = n // per_axis
     centre = (n // 2,) * d
-    # the vacancy sits at the background value; every other lattice site is a well
-    assert p.v[centre] == pytest.approx(background, rel=1e-6)
+    # the vacancy sits at the background value; every other lattice site is a bump
+    assert p.v[centre] == pytest.approx(background, rel=1e-4)
     for idx in np.ndindex(*([per_axis] * d)):
         site = tuple(i * step for i in idx)
         if site != centre:
-            assert p.v[site] == pytest.approx(well, rel=1e-3)
+            assert p.v[site] == pytest.approx(bump, rel=1e-3)
 
 
-def test_schrod3d_wells_range_and_energy():
-    p = W.schrod3d_wells(32)
-    n2 = 32 * 32
-    assert p.v.max() <= -2.4 * n2 + 1e-9 and p.v.min() >= -(20.0 * 16 + 2.4) * n2
+@pytest.mark.parametrize("name", ["schrod2d_lattice_n128", "schrod3d_wells_n32",
+                                  "schrod3d_lattice_n32"])
+def test_schrodinger_scaling_resolves_every_oscillation(name):
+    """Sec. 5's scaling: v >= -E/h^2 with E = 2.4, so the local wavenumber
+    sqrt(-v) never exceeds sqrt(2.4)/h and an oscillation spans > 4 points."""
+    p = W.make(name)
+    n2 = p.n * p.n
+    assert p.v.min() >= -2.4 * n2 * (1 + 1e-12)
+    points_per_oscillation = 2 * math.pi / math.sqrt(-p.v.min() / n2)
+    assert points_per_oscillation > 4.0
 
 
 @pytest.mark.parametrize("name", sorted(W.CONFIGS))
