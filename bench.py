@@ -257,32 +257,32 @@ def cpu_baseline(p):
 def non_localized_section(dev, t_setup_g, N):
     """The one-shift method of Sec. 3 beside the localized one: its setup
     time on the benchmark's field, and GMRES(40) iteration counts of both
-    preconditioners on a smaller field (host LU of P)."""
+    preconditioners on two smaller fields of Sec. 5's families (host LU of P)."""
     import torch
     from paper_1607_02560_amd import lsp
     from paper_1607_02560_amd import workloads as W
-    q = W.helm2d_gauss(128)
-    Nq, mq = q.N, (2 * q.t + 1) ** q.d
-    pr = lsp.Problem(q.d, q.n, torch.from_numpy(q.v.reshape(-1)).to(dev))
-    ft = torch.from_numpy(q.f.reshape(-1)).to(dev)
-    Pq = torch.empty(Nq * mq, dtype=torch.float64, device=dev)
-    gm = {}
-    for name in ("localized", "non_localized"):
-        if name == "localized":
-            pr.stencil_setup(q.t, q.num_shifts, Pq)
-        else:
-            pr.stencil_setup_global(q.t, Pq)
-        S = pr.get_tables()["S"]
-        solve = lsp.host_lu_solver(Pq.cpu().numpy().reshape(Nq, mq), q.d, q.n, q.t)
-        ut = torch.zeros_like(ft)
-        code, iters, relres = pr.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=400)
-        gm[name] = {"iterations": iters, "relres": relres, "status": code,
-                    "shifts": [float(x) for x in S]}
-    pr.close()
-    return {"setup_ms": t_setup_g * 1e3, "stencils_per_s": N / t_setup_g,
-            "gmres_workload": f"2D Helmholtz, Gaussian c, n={q.n}, t={q.t}, |S|={q.num_shifts} "
-                              f"(localized)",
-            "gmres": gm}
+    out = {"setup_ms": t_setup_g * 1e3, "stencils_per_s": N / t_setup_g, "gmres": {}}
+    for q in (W.helm2d_gauss(128), W.helm2d_cross(256)):
+        Nq, mq = q.N, (2 * q.t + 1) ** q.d
+        pr = lsp.Problem(q.d, q.n, torch.from_numpy(q.v.reshape(-1)).to(dev))
+        ft = torch.from_numpy(q.f.reshape(-1)).to(dev)
+        Pq = torch.empty(Nq * mq, dtype=torch.float64, device=dev)
+        gm = {"workload": f"{q.name}, n={q.n}, t={q.t}, |S|={q.num_shifts} (localized)"}
+        for name in ("localized", "non_localized"):
+            if name == "localized":
+                pr.stencil_setup(q.t, q.num_shifts, Pq)
+            else:
+                pr.stencil_setup_global(q.t, Pq)
+            S = pr.get_tables()["S"]
+            solve = lsp.host_lu_solver(Pq.cpu().numpy().reshape(Nq, mq), q.d, q.n, q.t)
+            ut = torch.zeros_like(ft)
+            code, iters, relres = pr.precond_solve(ft, ut, solve, rtol=1e-8, restart=40,
+                                                   maxit=400)
+            gm[name] = {"iterations": iters, "relres": relres, "status": code,
+                        "shifts": len(S)}
+        pr.close()
+        out["gmres"][f"{q.name}_n{q.n}"] = gm
+    return out
 
 
 def section_3d_t2(dev, reps):
