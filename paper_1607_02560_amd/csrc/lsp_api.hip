@@ -427,7 +427,8 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
                                           " exceeds " + std::to_string(lsp::kMaxStencil));
   if (W >= p->n) return lsp::set_error(LSP_EINVAL, "2t+1 must be smaller than n");
   if (p->N < 2 * (int64_t)m) return lsp::set_error(LSP_EINVAL, "N must be at least 2m");
-  if (p->d == 3 && W != 3 && W != 5) return lsp::set_error(LSP_EINVAL, "d = 3 supports t = 1, 2");
+  if (p->d == 3 && W != 3 && W != 5)
+    return lsp::set_error(LSP_EINVAL, "d = 3 supports t = 1, 2");
   if (p->d == 2 && W > 7) return lsp::set_error(LSP_EINVAL, "d = 2 supports t = 1, 2, 3");
   if (num_shifts == 0) num_shifts = lsp_default_num_shifts(p->d, p->n);
   if (num_shifts < 1) return lsp::set_error(LSP_EINVAL, "num_shifts must be >= 0");
@@ -547,7 +548,8 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
                               int* n_fallback_host) {
   if (!p || !mlp || !P_dev || !fallback_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
   if (!(threshold >= 0.0)) return lsp::set_error(LSP_EINVAL, "threshold must be >= 0");
-  if (p->d == 3 && t != 1) return lsp::set_error(LSP_EINVAL, "the learned setup supports d = 3 with t = 1");
+  if (p->d == 3 && t != 1)
+    return lsp::set_error(LSP_EINVAL, "the learned setup supports d = 3 with t = 1");
   int rc = lsp::prepare_setup(p, t, &num_shifts);
   if (rc) return rc;
   const int m = p->m;
