@@ -24,6 +24,8 @@ Every function follows one passage of the paper:
   global_shift, global_setup
                            Sec. 3: the non-localized preconditioner, one
                            shift s = mean(v) for every point
+  nd_tmap, nd_setup        Sec. 4.2 and Fig. 3: the per-point radius t_j that
+                           nested dissection with leaf box b allows
   sparse_P, sparse_C       eq. (PC) as sparse matrices
   gmres_right              Sec. 5: GMRES with restart, preconditioner P^-1 C
 
@@ -41,6 +43,11 @@ design notes of the repository):
     both P and C leaves P^-1 C unchanged, so the choice is immaterial to the solve.
   * GMRES: right preconditioning, x0 = 0, the iteration count is the total
     number of Arnoldi steps.
+  * per-point radius (Sec. 4.2, Fig. 3): separators are the grid planes
+    j_i = 0 mod b; a vertex (all coordinates on separators) takes t = b, any
+    other point the smallest distance from its off-separator coordinates to a
+    separator plane; then t_j = min(that, t_max). This reproduces every value
+    of Fig. 3.
   * non-localized shift (Sec. 3): the mean of v, moved only when L + s is
     singular: x = -s / (4 pi^2) within RESONANCE_TOL * max(1, |x|) of an
     integer K >= 0 counts as singular, and s then goes to (4m+2) pi^2 with
@@ -359,6 +366,53 @@ def global_setup(v: np.ndarray, t: int) -> dict:
     return tab
 
 
+# --------------------------------------------------------------------------
+# Section 4.2, Fig. 3: the radius each point may use under nested dissection
+# --------------------------------------------------------------------------
+def nd_tmap(d: int, n: int, b: int, tmax: int) -> np.ndarray:
+    """t_j of Sec. 4.2: the largest radius that keeps the sparsity nested
+    dissection with leaf box b needs (Fig. 3), capped at tmax. Separators are
+    the planes j_i = 0 mod b. A vertex (every coordinate on a separator) may
+    reach t = b; any other point reaches up to the nearest separator plane
+    across its coordinates off the separators."""
+    if n % b != 0 or b < 2:
+        raise ValueError("the leaf box b must divide n")
+    coords = np.stack(np.unravel_index(np.arange(n ** d), (n,) * d), axis=-1)
+    r = coords % b
+    dist = np.minimum(r, b - r)
+    off = r != 0
+    reach = np.where(off, dist, n).min(axis=1)
+    t = np.where(off.any(axis=1), reach, b)
+    return np.minimum(t, tmax).reshape((n,) * d)
+
+
+def nd_setup(v: np.ndarray, b: int, tmax: int, num_shifts: int) -> dict:
+    """Stencils with the per-point radius t_j = nd_tmap (Sec. 4.2): the tables
+    of every radius t <= tmax for each shift, and rows j of P and C from the
+    tables of (s_j, t_j). Rows use the layout of radius tmax (offsets
+    mu_0^tmax); entries outside mu_0^{t_j} are zero."""
+    d, n = v.ndim, v.shape[0]
+    S = shift_list(v, num_shifts)
+    idx = assign_shifts(v, S)
+    flat_idx = idx.reshape(-1)
+    tm = nd_tmap(d, n, b, tmax).reshape(-1)
+    offs = offsets(d, tmax)
+    where = {tuple(o): k for k, o in enumerate(offs)}
+    P = np.zeros((v.size, offs.shape[0]))
+    Crows = np.zeros_like(P)
+    tables = {}
+    for t in range(1, tmax + 1):
+        tab = shift_tables(d, n, S, t)
+        tables[t] = tab
+        pos = np.array([where[tuple(o)] for o in tab["offsets"]])
+        sel = np.nonzero(tm == t)[0]
+        Pt = assemble(v, S, tab["alpha"], tab["C"], idx, tab["offsets"])
+        P[np.ix_(sel, pos)] = Pt[sel]
+        Crows[np.ix_(sel, pos)] = tab["C"][flat_idx[sel]]
+    return {"S": S, "idx": idx, "tmap": tm.reshape(v.shape), "P": P, "Crows": Crows,
+            "offsets": offs, "tables": tables}
+
+
 def neighbour_columns(d: int, n: int, offs: np.ndarray) -> np.ndarray:
     """Column index (j + a) mod n, flattened, for each row j and offset a."""
     N = n ** d
@@ -452,14 +506,21 @@ def gmres_right(apply_A, apply_M, f: np.ndarray, rtol: float, restart: int, maxi
 
 def precond_solve(v: np.ndarray, f: np.ndarray, t: int, num_shifts: int,
                   rtol: float = 1e-8, restart: int = 40, maxit: int = 400,
-                  non_localized: bool = False):
+                  non_localized: bool = False, nd_leaf: int = 0):
     """Solve (L + diag v) u = f by GMRES(restart) with the preconditioner
     P^-1 C of eq. (PC); P is factorised by a sparse LU. non_localized=True
-    builds P and C by the one-shift method of Sec. 3 (num_shifts unused)."""
+    builds P and C by the one-shift method of Sec. 3 (num_shifts unused);
+    nd_leaf = b > 0 uses the per-point radius of Sec. 4.2 with leaf box b and
+    t as its cap."""
     d, n = v.ndim, v.shape[0]
-    setup = global_setup(v, t) if non_localized else stencil_setup(v, t, num_shifts)
-    P = sparse_P(setup, d, n).tocsc().astype(np.complex128)
-    Cm = sparse_C(setup, d, n).astype(np.complex128)
+    if nd_leaf:
+        setup = nd_setup(v, nd_leaf, t, num_shifts)
+        P = sparse_rows(setup["P"], d, n, setup["offsets"]).tocsc().astype(np.complex128)
+        Cm = sparse_rows(setup["Crows"], d, n, setup["offsets"]).astype(np.complex128)
+    else:
+        setup = global_setup(v, t) if non_localized else stencil_setup(v, t, num_shifts)
+        P = sparse_P(setup, d, n).tocsc().astype(np.complex128)
+        Cm = sparse_C(setup, d, n).astype(np.complex128)
     lu = scipy.sparse.linalg.splu(P)
 
     def apply_A(x):

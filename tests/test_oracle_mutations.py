@@ -90,6 +90,21 @@ def _global_always_snaps(v):
     return O.snap_shift(float(np.mean(v)))
 
 
+def _tmap_vertex_one(d, n, b, tmax):
+    t = _orig["nd_tmap"](d, n, b, tmax)
+    coords = np.stack(np.unravel_index(np.arange(n ** d), (n,) * d), axis=-1)
+    vert = np.all(coords % b == 0, axis=1).reshape(t.shape)
+    return np.where(vert, 1, t)
+
+
+def _tmap_edge_full(d, n, b, tmax):
+    coords = np.stack(np.unravel_index(np.arange(n ** d), (n,) * d), axis=-1)
+    r = coords % b
+    dist = np.minimum(r, b - r)
+    t = np.where(np.all(r == 0, axis=1), b, dist.max(axis=1))
+    return np.minimum(t, tmax).reshape((n,) * d)
+
+
 MUTANTS = [
     ("symbol", _symbol_missing_4, lambda: pins.test_plane_waves_are_eigenvectors(2, 8)),
     ("ps_apply", _ps_apply_wrong_sign, lambda: pins.test_ps_apply_matches_dense(2, 8, 1)),
@@ -108,6 +123,8 @@ MUTANTS = [
     ("global_shift", _global_ignores_resonance,
      lambda: pins.test_global_shift_moves_off_resonance(5)),
     ("global_shift", _global_always_snaps, pins.test_global_shift_keeps_non_resonant_mean),
+    ("nd_tmap", _tmap_vertex_one, pins.test_nd_tmap_matches_fig3),
+    ("nd_tmap", _tmap_edge_full, pins.test_nd_tmap_matches_fig3),
 ]
 
 

@@ -5,6 +5,7 @@ closed forms, brute-force dense linear algebra on tiny grids, identities the
 paper states (eq. A, the convolution identity, translation invariance) and
 the worked example of Fig. 2. CPU only.
 """
+import itertools
 import json
 import math
 import os
@@ -473,3 +474,70 @@ def test_non_localized_precond_solve_converges():
     assert len(setup["S"]) == 1 and true_rel <= 1e-8 and iters < 60
     u_ref = np.linalg.solve(O.dense_operator(p.v), p.f.reshape(-1))
     assert np.linalg.norm(u.reshape(-1) - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+
+
+# ---------------------------------------------- Sec. 4.2, per-point radius ----
+def test_nd_tmap_matches_fig3():
+    """The worked example of Fig. 3: 16 x 16 grid, leaf box 4, the radius of
+    every point as the figure prints it (tests/golden/fig3_tmap_n16_b4.txt)."""
+    T = np.loadtxt(os.path.join(GOLDEN, "fig3_tmap_n16_b4.txt"), dtype=int)
+    M = O.nd_tmap(2, 16, 4, 16)
+    assert np.array_equal(M, T) and np.array_equal(M.T, T)
+
+
+@pytest.mark.parametrize("d,n,b", [(2, 16, 4), (2, 24, 8), (3, 12, 4)])
+def test_nd_tmap_box_points_stay_in_their_box(d, n, b):
+    """Fig. 3's requirement, by brute force: the neighbourhood of radius t_j of
+    a box point (no coordinate on a separator plane) meets no point outside its
+    closed box (the box and its bounding separators), and radius t_j + 1 would.
+    Vertices reach t = b (they are eliminated last)."""
+    tm = O.nd_tmap(d, n, b, n).reshape(-1)
+    coords = np.stack(np.unravel_index(np.arange(n ** d), (n,) * d), axis=-1)
+    for j in range(0, n ** d, 3):
+        c = coords[j]
+        r = c % b
+        if np.all(r == 0):
+            assert tm[j] == b
+            continue
+        if np.any(r == 0):
+            continue  # edge and face points: checked against Fig. 3 above
+        lo = c - r  # corner of the closed box [lo, lo + b] along every axis
+
+        def inside(t):
+            for off in itertools.product(range(-t, t + 1), repeat=d):
+                q = c + np.array(off)
+                if np.any(q < lo) or np.any(q > lo + b):
+                    return False
+            return True
+
+        assert inside(int(tm[j])) and not inside(int(tm[j]) + 1), (c, tm[j])
+
+
+def test_nd_setup_rows():
+    """Per-point rows (Sec. 4.2): a row with t_j = t equals the uniform-t row of
+    the same shift on mu_0^t and is zero outside it; with the cap 1 the setup is
+    the uniform t = 1 setup."""
+    v = rng(31).uniform(-3000, -1000, (16, 16))
+    nd = O.nd_setup(v, 8, 2, 4)
+    offs = nd["offsets"]
+    tm = nd["tmap"].reshape(-1)
+    assert set(np.unique(tm)) == {1, 2}
+    for t in (1, 2):
+        uni = O.stencil_setup(v, t, 4)
+        inner = np.all(np.abs(offs) <= t, axis=1)
+        sel = tm == t
+        assert np.array_equal(nd["P"][np.ix_(sel, inner)], uni["P"][sel])
+        assert np.all(nd["P"][np.ix_(sel, ~inner)] == 0.0)
+        Cu = uni["C"][uni["idx"].reshape(-1)]
+        assert np.array_equal(nd["Crows"][np.ix_(sel, inner)], Cu[sel])
+    one = O.nd_setup(v, 8, 1, 4)
+    assert np.array_equal(one["P"], O.stencil_setup(v, 1, 4)["P"])
+
+
+@pytest.mark.slow
+def test_nd_precond_solve_converges():
+    """GMRES with the per-point radius (leaf box 8, t <= 2) on the cross
+    profile at n = 64 reaches a true residual of 1e-8 within 40 iterations."""
+    p = W.helm2d_cross(64)
+    _, itn, _, rn, _ = O.precond_solve(p.v, p.f, 2, p.num_shifts, rtol=1e-8, nd_leaf=8)
+    assert rn <= 1e-8 and itn <= 40
