@@ -136,6 +136,28 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
                              int32_t* idx_dev);
 
 /*
+ * Stencil setup with the per-point radius of Sec. 4.2 (Fig. 3): point j uses
+ * radius t_j, the largest that keeps the sparsity nested dissection with
+ * leaf box `leaf` needs, capped at 2. Separators are the grid planes
+ * j_i = 0 mod leaf; a vertex (every coordinate on a separator) may reach
+ * t = leaf, any other point reaches up to the nearest separator plane across
+ * its coordinates off the separators. The shift list, s_j and the tables of
+ * radius 1 and 2 are those of lsp_stencil_setup with t = 1 and t = 2.
+ *   leaf        leaf box size b >= 2, dividing n (Sec. 5 uses 8).
+ *   num_shifts  as for lsp_stencil_setup.
+ *   P_dev       output, N*5^d float64 in the layout of radius 2 (the offsets
+ *               of mu_0^2, lexicographic, last axis fastest); a row with
+ *               t_j = 1 holds its radius-1 stencil on mu_0^1 and zeros on the
+ *               other offsets.
+ *   idx_dev     output, N int32 shift indices (may be NULL).
+ * Needs 2t+1 = 5 < n. lsp_c_apply and lsp_precond_solve then use the rows
+ * C[j, mu_j^{t_j}] of this setup; lsp_get_tables returns the radius-2 tables.
+ * Launches directly (no graph). Asynchronous.
+ */
+int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev,
+                         int32_t* idx_dev);
+
+/*
  * Pseudospectral apply y = (L + diag v) u with L = F^-1 diag(4 pi^2 |k|^2) F
  * (Sec. 2, eq. dmodel). u_dev and y_dev: N complex128, device, must not
  * overlap. Asynchronous.

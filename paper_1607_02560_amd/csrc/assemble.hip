@@ -257,7 +257,8 @@ hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
   dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
   hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream,
                      reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS, p->ws.Ctab,
-                     p->learned ? p->c_rows : nullptr, reinterpret_cast<double2*>(z));
+                     (p->learned || p->per_point_C) ? p->c_rows : nullptr,
+                     reinterpret_cast<double2*>(z));
   return hipGetLastError();
 }
 

@@ -363,6 +363,7 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->cosT);
   dfree(p->green_units);
   dfree(p->c_rows);
+  dfree(p->nd_act1);
   dfree(p->learn_buf);
   dfree(p->flag);
   drop_graph(p->g_setup);
@@ -445,6 +446,7 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
   p->num_shifts = num_shifts;
   p->have_setup = false;
   p->learned = false;
+  p->per_point_C = false;
   *num_shifts_io = num_shifts;
   return LSP_OK;
 }
@@ -527,6 +529,54 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
                            (uint64_t)(uintptr_t)idx_dev, p->ws_gen, (uint64_t)precision};
   const hipError_t e = run_graph(p, p->g_setup, key, launch);
   if (e != hipSuccess) return lsp::hip_check(e, "non-localized setup launch");
+  p->have_setup = true;
+  return LSP_OK;
+}
+
+int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev,
+                         int32_t* idx_dev) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
+  if (leaf < 2 || p->n % leaf != 0)
+    return lsp::set_error(LSP_EINVAL, "the leaf box must be >= 2 and divide n");
+  // radius-1 tables first (shift list, Green's sums, null vectors), kept aside
+  int ns1 = num_shifts;
+  int rc = lsp::prepare_setup(p, 1, &ns1);
+  if (rc) return rc;
+  const int m1 = p->m;
+  hipError_t e = lsp::launch_minmax(p);
+  int blocks = 0;
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns1, &blocks);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns1, blocks);
+  if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup (radius 1)");
+  const size_t need1 = (size_t)ns1 * m1;
+  if (p->nd_act1_cap < need1) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(p->nd_act1);
+    p->nd_act1_cap = 0;
+    if ((rc = dalloc((void**)&p->nd_act1, sizeof(double2) * need1, "radius-1 tables"))) return rc;
+    p->nd_act1_cap = need1;
+  }
+  if (hipMemcpyAsync(p->nd_act1, p->ws.actab, sizeof(double2) * need1, hipMemcpyDeviceToDevice,
+                     p->stream) != hipSuccess)
+    return lsp::set_error(LSP_EHIP, "copy of the radius-1 tables failed");
+  // then the radius-2 tables in the workspace, and the rows
+  int ns2 = num_shifts;
+  if ((rc = lsp::prepare_setup(p, 2, &ns2))) return rc;
+  const size_t need = (size_t)p->N * p->m;
+  if (p->c_rows_cap < need) {
+    (void)hipStreamSynchronize(p->stream);
+    dfree(p->c_rows);
+    p->c_rows_cap = 0;
+    if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "per-point C rows"))) return rc;
+    p->c_rows_cap = need;
+  }
+  e = lsp::launch_minmax(p);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns2, &blocks);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns2, blocks);
+  if (e == hipSuccess) e = lsp::launch_assemble_nd(p, p->nd_act1, leaf, P_dev, idx_dev);
+  if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup");
+  p->per_point_C = true;
   p->have_setup = true;
   return LSP_OK;
 }

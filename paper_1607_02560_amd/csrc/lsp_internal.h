@@ -98,8 +98,12 @@ struct lsp_problem {
   // learned setup: per-point C rows [N][m] (the exact setup uses the per-shift
   // table instead); c_apply reads them while `learned` is set
   bool learned = false;
+  // setup with per-point radius (Sec. 4.2): C rows are per point too
+  bool per_point_C = false;
   double* c_rows = nullptr;
   size_t c_rows_cap = 0;      // doubles
+  double2* nd_act1 = nullptr; // (alpha, C) of radius 1 per shift, for that setup
+  size_t nd_act1_cap = 0;     // entries
   char* learn_buf = nullptr;  // rho*(s) per shift, fallback count, network in/out chunks
   size_t learn_cap = 0;       // bytes
   lsp::Workspace ws;
@@ -153,6 +157,11 @@ hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hip
 // per-block (min, max) partials of v (with_sum: and per-block sums); the
 // Green's-sum launch turns them into S
 hipError_t launch_minmax(lsp_problem* p, bool with_sum = false);
+// rows of per-point radius (Sec. 4.2, leaf box `leaf`, radius <= 2) from the
+// radius-1 tables act1 and the radius-2 tables of the workspace; writes P,
+// idx and the per-point C rows (p->c_rows, [N][5^d])
+hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
+                              int32_t* idx);
 // Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace.
 // global: S is the one shift of the non-localized method of Sec. 3 (the mean
 // of v from the sums of launch_minmax(p, true)), not the list of Sec. 4.1

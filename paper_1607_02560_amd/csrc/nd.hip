@@ -1,0 +1,110 @@
+// Rows of per-point radius (Sec. 4.2, Fig. 3): point j uses the stencil of
+// radius t_j, the largest radius that keeps the sparsity nested dissection with
+// leaf box b needs, capped at 2 (the radii Sec. 5 computes). The separators are
+// the grid planes j_i = 0 mod b; a vertex (every coordinate on a separator)
+// may reach t = b, any other point reaches up to the nearest separator plane
+// across its coordinates off the separators.
+//
+// Rows keep the layout of radius 2 (the 5^d offsets of mu_0^2, lexicographic,
+// last axis fastest); a row with t_j = 1 holds the radius-1 stencil on the
+// offsets of mu_0^1 and zeros elsewhere. Entry a of row j is
+//   alpha^{t_j}_{s_j}[a] + C^{t_j}_{s_j}[a] (v[j + a] - s_j),
+// evaluated exactly as the uniform-radius assembly does, and the row of C is
+// written beside it for the C-apply.
+#include "setup_common.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+using lsp::nearest_shift;
+using lsp::Pow;
+
+template <int D>
+__device__ __forceinline__ int nd_radius(const int* c, int b, int tmax) {
+  int reach = b;
+  bool off = false;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int r = c[i] % b;
+    if (r != 0) {
+      off = true;
+      reach = min(reach, min(r, b - r));
+    }
+  }
+  return min(off ? reach : b, tmax);
+}
+
+// one thread per point; act1/act2 are the (alpha, C) tables of radius 1 and 2
+template <int D>
+__global__ __launch_bounds__(256) void assemble_nd_kernel(
+    const double* __restrict__ v, int n, int64_t N, const double* __restrict__ S,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ act1,
+    const double2* __restrict__ act2, int b, double* __restrict__ P,
+    double* __restrict__ Crows, int32_t* __restrict__ idx_out) {
+  constexpr int W2 = 5;
+  constexpr int M2 = Pow<D, 5>::v;
+  constexpr int M1 = Pow<D, 3>::v;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  int c[D];
+  {
+    int64_t rem = j;
+#pragma unroll
+    for (int i = D - 1; i >= 0; --i) {
+      c[i] = (int)(rem % n);
+      rem /= n;
+    }
+  }
+  const int id = nearest_shift(S, *nS_ptr, v[j]);
+  const double s = S[id];
+  if (idx_out) idx_out[j] = id;
+  const int t = nd_radius<D>(c, b, 2);
+  const int mask = n - 1;
+  for (int a = 0; a < M2; ++a) {
+    int o[D];
+    int rem = a;
+#pragma unroll
+    for (int i = D - 1; i >= 0; --i) {
+      o[i] = rem % W2 - 2;
+      rem /= W2;
+    }
+    bool inner = true;
+    int a1 = 0;
+    int64_t g = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      inner = inner && o[i] >= -1 && o[i] <= 1;
+      a1 = a1 * 3 + o[i] + 1;
+      g = g * n + ((c[i] + o[i]) & mask);
+    }
+    double pv = 0.0, cv = 0.0;
+    if (t >= 2 || inner) {
+      const double2 ac = (t >= 2) ? act2[(int64_t)id * M2 + a] : act1[(int64_t)id * M1 + a1];
+      pv = ac.x + ac.y * (v[g] - s);
+      cv = ac.y;
+    }
+    P[j * M2 + a] = pv;
+    Crows[j * M2 + a] = cv;
+  }
+}
+
+}  // namespace
+
+namespace lsp {
+
+hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
+                              int32_t* idx) {
+  const int64_t N = p->N;
+  const dim3 grid((unsigned)((N + 255) / 256)), blk(256);
+  const double2* act2 = reinterpret_cast<const double2*>(p->ws.actab);
+  if (p->d == 2)
+    hipLaunchKernelGGL(assemble_nd_kernel<2>, grid, blk, 0, p->stream, p->v, p->n, N, p->ws.S,
+                       p->ws.nS, act1, act2, leaf, P, p->c_rows, idx);
+  else
+    hipLaunchKernelGGL(assemble_nd_kernel<3>, grid, blk, 0, p->stream, p->v, p->n, N, p->ws.S,
+                       p->ws.nS, act1, act2, leaf, P, p->c_rows, idx);
+  return hipGetLastError();
+}
+
+}  // namespace lsp

@@ -66,6 +66,7 @@ def load():
         "lsp_destroy": (None, [c_void_p]),
         "lsp_stencil_setup": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p]),
         "lsp_stencil_setup_global": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
+        "lsp_stencil_setup_nd": (c_int, [c_void_p, c_int, c_int, c_void_p, c_void_p]),
         "lsp_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_c_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_precond_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
@@ -217,6 +218,19 @@ class Problem:
                                                  _ptr(idx) if idx is not None else None),
                "lsp_stencil_setup_global")
         self.t, self.m = t, m
+
+    def stencil_setup_nd(self, leaf: int, num_shifts: int, P, idx=None):
+        """Setup with the per-point radius of Sec. 4.2 (leaf box `leaf`,
+        radius <= 2); P holds N rows of 5^d entries (radius-2 layout)."""
+        import torch
+        m = 5 ** self.d
+        _need(P, torch.float64, self.N * m, "P")
+        if idx is not None:
+            _need(idx, torch.int32, self.N, "idx")
+        _check(self.lib.lsp_stencil_setup_nd(self._h, leaf, num_shifts, _ptr(P),
+                                             _ptr(idx) if idx is not None else None),
+               "lsp_stencil_setup_nd")
+        self.t, self.m = 2, m
 
     def training_rows(self, P, points, X, T):
         """Features and exact targets of the given points after an exact setup."""
