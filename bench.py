@@ -465,6 +465,13 @@ def main():
     }
     if not args.no_extras:
         out["non_localized"] = non_localized_section(dev, t_setup_g, N)
+        # the per-point radius of Sec. 4.2 (leaf box 8, t <= 2) on the same field
+        setup_nd = lambda: prob.stencil_setup_nd(8, p.num_shifts, P, idx)
+        for _ in range(args.warmup):
+            setup_nd()
+        t_nd = timed(stream, setup_nd, args.steps)
+        out["form_nd_radius"] = {"leaf": 8, "t_max": 2, "setup_ms": t_nd * 1e3,
+                                 "stencils_per_s": N / t_nd}
     prob.close()
     del P, idx
     if not args.no_extras:
