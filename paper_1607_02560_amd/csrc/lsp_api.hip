@@ -130,7 +130,6 @@ int upload_cos_table(lsp_problem* p, int W) {
       cw[(size_t)k * W + dl] = wk * cos(2.0 * M_PI * (double)j / (double)p->n);
     }
   }
-  dfree(p->cosT);
   ++p->ws_gen;
   int rc = dalloc((void**)&p->cosT, sizeof(double) * cw.size(), "cos table");
   if (rc) return rc;
@@ -360,7 +359,8 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->v);
   dfree(p->z);
   dfree(p->tw);
-  dfree(p->cosT);
+  for (double*& c : p->cos_by_t) dfree(c);
+  p->cosT = nullptr;
   dfree(p->green_units);
   dfree(p->c_rows);
   dfree(p->nd_act1);
@@ -437,10 +437,14 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
     return lsp::set_error(LSP_EINVAL, "num_shifts exceeds " + std::to_string(lsp::kMaxShifts));
   int rc = ensure_workspace(p, num_shifts, t, m, m);
   if (rc) return rc;
-  if (p->t != t || !p->cosT) {
+  // one cosine table per t, uploaded once: switching t (the per-point-radius
+  // setup does so twice per call) only repoints cosT
+  if (!p->cos_by_t[t]) {
     (void)hipStreamSynchronize(p->stream);
     if ((rc = upload_cos_table(p, W))) return rc;
+    p->cos_by_t[t] = p->cosT;
   }
+  p->cosT = p->cos_by_t[t];
   p->t = t;
   p->m = m;
   p->num_shifts = num_shifts;

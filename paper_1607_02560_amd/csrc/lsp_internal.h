@@ -85,7 +85,8 @@ struct lsp_problem {
   int device = 0;
   double* v = nullptr;        // [N] potential
   double* tw = nullptr;       // [2n] exp(-2 pi i j / n), interleaved
-  double* cosT = nullptr;     // [(n/2+1) * (2t+1)] folded cosine weights
+  double* cosT = nullptr;     // [(n/2+1) * (2t+1)] folded cosine weights of the current t
+  double* cos_by_t[4] = {nullptr, nullptr, nullptr, nullptr};  // tables kept per t = 1..3
   int* green_units = nullptr; // [green_nunits] Green's-sum work units
   int green_nunits = 0;
   double* z = nullptr;        // [2N] ps_apply partial sums

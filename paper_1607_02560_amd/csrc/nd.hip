@@ -35,7 +35,9 @@ __device__ __forceinline__ int nd_radius(const int* c, int b, int tmax) {
   return min(off ? reach : b, tmax);
 }
 
-// one thread per point; act1/act2 are the (alpha, C) tables of radius 1 and 2
+// one thread per entry (j, a) of the radius-2 layout, so that consecutive
+// threads store consecutive doubles; act1/act2 are the (alpha, C) tables of
+// radius 1 and 2
 template <int D>
 __global__ __launch_bounds__(256) void assemble_nd_kernel(
     const double* __restrict__ v, int n, int64_t N, const double* __restrict__ S,
@@ -45,8 +47,15 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
   constexpr int W2 = 5;
   constexpr int M2 = Pow<D, 5>::v;
   constexpr int M1 = Pow<D, 3>::v;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= N) return;
+  // the shift list in LDS for the nearest-shift searches of the block
+  __shared__ double sS[lsp::kMaxShifts];
+  const int nS = *nS_ptr;
+  for (int i = threadIdx.x; i < nS; i += 256) sS[i] = S[i];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= N * M2) return;
+  const int64_t j = e / M2;
+  const int a = (int)(e - j * M2);
   int c[D];
   {
     int64_t rem = j;
@@ -56,37 +65,37 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
       rem /= n;
     }
   }
-  const int id = nearest_shift(S, *nS_ptr, v[j]);
-  const double s = S[id];
-  if (idx_out) idx_out[j] = id;
+  const int id = nearest_shift(sS, nS, v[j]);
+  const double s = sS[id];
+  if (idx_out && a == 0) idx_out[j] = id;
   const int t = nd_radius<D>(c, b, 2);
   const int mask = n - 1;
-  for (int a = 0; a < M2; ++a) {
-    int o[D];
+  int o[D];
+  {
     int rem = a;
 #pragma unroll
     for (int i = D - 1; i >= 0; --i) {
       o[i] = rem % W2 - 2;
       rem /= W2;
     }
-    bool inner = true;
-    int a1 = 0;
-    int64_t g = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      inner = inner && o[i] >= -1 && o[i] <= 1;
-      a1 = a1 * 3 + o[i] + 1;
-      g = g * n + ((c[i] + o[i]) & mask);
-    }
-    double pv = 0.0, cv = 0.0;
-    if (t >= 2 || inner) {
-      const double2 ac = (t >= 2) ? act2[(int64_t)id * M2 + a] : act1[(int64_t)id * M1 + a1];
-      pv = ac.x + ac.y * (v[g] - s);
-      cv = ac.y;
-    }
-    P[j * M2 + a] = pv;
-    Crows[j * M2 + a] = cv;
   }
+  bool inner = true;
+  int a1 = 0;
+  int64_t g = 0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    inner = inner && o[i] >= -1 && o[i] <= 1;
+    a1 = a1 * 3 + o[i] + 1;
+    g = g * n + ((c[i] + o[i]) & mask);
+  }
+  double pv = 0.0, cv = 0.0;
+  if (t >= 2 || inner) {
+    const double2 ac = (t >= 2) ? act2[(int64_t)id * M2 + a] : act1[(int64_t)id * M1 + a1];
+    pv = ac.x + ac.y * (v[g] - s);
+    cv = ac.y;
+  }
+  P[e] = pv;
+  Crows[e] = cv;
 }
 
 }  // namespace
@@ -96,7 +105,8 @@ namespace lsp {
 hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
                               int32_t* idx) {
   const int64_t N = p->N;
-  const dim3 grid((unsigned)((N + 255) / 256)), blk(256);
+  const int64_t entries = N * (p->d == 2 ? 25 : 125);
+  const dim3 grid((unsigned)((entries + 255) / 256)), blk(256);
   const double2* act2 = reinterpret_cast<const double2*>(p->ws.actab);
   if (p->d == 2)
     hipLaunchKernelGGL(assemble_nd_kernel<2>, grid, blk, 0, p->stream, p->v, p->n, N, p->ws.S,
