@@ -47,15 +47,40 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
   constexpr int W2 = 5;
   constexpr int M2 = Pow<D, 5>::v;
   constexpr int M1 = Pow<D, 3>::v;
-  // the shift list in LDS for the nearest-shift searches of the block
+  // the shift list in LDS; then, once per point of the block's entry range
+  // (at most 256 / M2 + 2 points), its shift, s_j and radius
+  constexpr int PTS = 256 / M2 + 2;
   __shared__ double sS[lsp::kMaxShifts];
+  __shared__ double sSj[PTS];
+  __shared__ int sId[PTS], sT[PTS];
   const int nS = *nS_ptr;
   for (int i = threadIdx.x; i < nS; i += 256) sS[i] = S[i];
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * 256;
+  const int64_t j0 = e0 / M2;
+  if (threadIdx.x < PTS) {
+    const int64_t jp = j0 + threadIdx.x;
+    if (jp < N) {
+      int cp[D];
+      int64_t rem = jp;
+#pragma unroll
+      for (int i = D - 1; i >= 0; --i) {
+        cp[i] = (int)(rem % n);
+        rem /= n;
+      }
+      const int id = nearest_shift(sS, nS, v[jp]);
+      sId[threadIdx.x] = id;
+      sSj[threadIdx.x] = sS[id];
+      sT[threadIdx.x] = nd_radius<D>(cp, b, 2);
+      if (idx_out) idx_out[jp] = id;
+    }
+  }
+  __syncthreads();
+  const int64_t e = e0 + threadIdx.x;
   if (e >= N * M2) return;
   const int64_t j = e / M2;
   const int a = (int)(e - j * M2);
+  const int lp = (int)(j - j0);
   int c[D];
   {
     int64_t rem = j;
@@ -65,10 +90,9 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
       rem /= n;
     }
   }
-  const int id = nearest_shift(sS, nS, v[j]);
-  const double s = sS[id];
-  if (idx_out && a == 0) idx_out[j] = id;
-  const int t = nd_radius<D>(c, b, 2);
+  const int id = sId[lp];
+  const double s = sSj[lp];
+  const int t = sT[lp];
   const int mask = n - 1;
   int o[D];
   {
