@@ -231,9 +231,36 @@ def batched_section(dev, reps):
     }
 
 
+def _oracle_tables_worker(args):
+    """One process of the all-cores oracle timing: the oracle's per-shift
+    tables (Green's kernels by FFT, Gram matrix, null vector) for a slice of
+    the shift list."""
+    d, n, S, t = args
+    from oracle import lsp_oracle as O
+    tab = O.shift_tables(d, n, S, t)
+    return tab["alpha"], tab["C"]
+
+
+def _oracle_apply_worker(args):
+    """One process of the all-cores oracle timing: `reps` oracle applies."""
+    v, f, reps = args
+    from oracle import lsp_oracle as O
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        O.ps_apply(v, f)
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(p):
     """The FP64 oracle timed on this host: one full setup of the same workload
-    (the sample) and 10 applies. numpy's FFT runs on one thread."""
+    (the sample) and 10 applies, on one core (numpy's FFT is single-threaded)
+    and on all cores. On all cores the oracle's functions run unchanged in
+    one process per core: the per-shift tables (independent per shift) are
+    split over the processes and the shift list, assignment and rows run in
+    the parent; for the apply every process runs the oracle's apply, and the
+    rate is the applies all processes complete per second."""
+    import multiprocessing as mp
+
     import numpy as np
     from oracle import lsp_oracle as O
     t0 = time.perf_counter()
@@ -244,7 +271,7 @@ def cpu_baseline(p):
     for _ in range(reps):
         O.ps_apply(p.v, p.f)
     t_apply = (time.perf_counter() - t0) / reps
-    return {
+    out = {
         "value": p.N / t_setup, "unit": "stencils/s", "cores": 1, "kind": "oracle",
         "sample": f"one full setup of the same workload (N={p.N}, |S|={p.num_shifts}) "
                   f"and {reps} applies; numpy FFT single-threaded",
@@ -252,6 +279,37 @@ def cpu_baseline(p):
         "ps_apply_GBps": 40.0 * p.N / t_apply / 1e9,
         "host_cpus": os.cpu_count(),
     }
+    # all cores: at most 16 processes (the host share of one GPU on the
+    # benchmark machines), spawned (not forked: the parent holds the GPU)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_tables_worker, [(p.d, 8, np.asarray([-1e3]), 1)] * workers)  # warm-up
+        t0 = time.perf_counter()
+        S = O.shift_list(p.v, p.num_shifts)
+        parts = pool.map(_oracle_tables_worker,
+                         [(p.d, p.n, S[i::workers], p.t) for i in range(workers)
+                          if len(S[i::workers])])
+        m = (2 * p.t + 1) ** p.d
+        alpha = np.zeros((len(S), m))
+        C = np.zeros((len(S), m))
+        for i, (a, c) in enumerate(parts):
+            alpha[i::workers] = a
+            C[i::workers] = c
+        idx = O.assign_shifts(p.v, S)
+        O.assemble(p.v, S, alpha, C, idx, O.offsets(p.d, p.t))
+        t_setup_all = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pool.map(_oracle_apply_worker, [(p.v, p.f, reps)] * workers)
+        t_apply_all = (time.perf_counter() - t0) / (reps * workers)
+    out["all_cores"] = {
+        "cores": workers, "value": p.N / t_setup_all, "unit": "stencils/s",
+        "setup_s": t_setup_all, "ps_apply_s_per_apply": t_apply_all,
+        "ps_apply_GBps": 40.0 * p.N / t_apply_all / 1e9,
+        "sample": f"the same setup with the per-shift tables split over {workers} processes; "
+                  f"{reps} applies in each of {workers} processes",
+    }
+    return out
 
 
 def non_localized_section(dev, t_setup_g, N):

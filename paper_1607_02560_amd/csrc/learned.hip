@@ -27,6 +27,8 @@
 // SiLU, FP32 de-standardisation, FP64 rows); its check sums the dense forms
 // instead of the parity blocks, so the two decide alike except within
 // rounding of the boundary.
+#include <map>
+#include <mutex>
 #include <utility>
 
 #include "setup_common.h"
@@ -590,20 +592,34 @@ hipError_t launch_fused_dw(const lsp_problem* p, const lsp::MlpView& mv, double 
   using F = Fused<D, W>;
   const size_t lds = F::bytes(p->num_shifts);
   if (lds > kLdsLimit) return hipErrorInvalidValue;  // excluded by learned_fused_supported
-  static size_t attr_bytes = 0;
-  static int per_cu = 1;
-  if (attr_bytes < lds) {
-    hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&learned_fused_kernel<D, W>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    int nb = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void*>(&learned_fused_kernel<D, W>), kThreads, lds);
-    if (e != hipSuccess) return e;
-    if (nb < 1) return hipErrorInvalidConfiguration;
-    attr_bytes = lds;
-    per_cu = nb;
+  // The kernel's dynamic-LDS attribute and its occupancy are properties of
+  // the function on one device, shared by every problem object that launches
+  // it there: keep them per device and update them under a lock, so problems
+  // used from different threads do not race on them.
+  struct Attr {
+    size_t bytes = 0;
+    int per_cu = 1;
+  };
+  static std::mutex mu;
+  static std::map<int, Attr> attrs;
+  int per_cu = 1;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    Attr& at = attrs[p->device];
+    if (at.bytes < lds) {
+      hipError_t e =
+          hipFuncSetAttribute(reinterpret_cast<const void*>(&learned_fused_kernel<D, W>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      int nb = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&learned_fused_kernel<D, W>), kThreads, lds);
+      if (e != hipSuccess) return e;
+      if (nb < 1) return hipErrorInvalidConfiguration;
+      at.bytes = lds;
+      at.per_cu = nb;
+    }
+    per_cu = at.per_cu;
   }
   int cus = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device);

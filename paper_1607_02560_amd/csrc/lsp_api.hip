@@ -162,6 +162,26 @@ int check_finite_device(lsp_problem* p, const double* x, int64_t count, const ch
   return LSP_OK;
 }
 
+// Eigen-solver status of the last setup's shifts: LSP_ERESONANT when the
+// Gram block of some shift could not be factorised (its null vector, and so
+// its rows, are not valid). Synchronises the stream.
+int check_setup_status(lsp_problem* p) {
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "synchronise");
+  int ns = 0;
+  e = hipMemcpy(&ns, p->ws.nS, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return lsp::hip_check(e, "read |S|");
+  if (ns <= 0) return LSP_OK;
+  std::vector<int> st(ns);
+  e = hipMemcpy(st.data(), p->ws.status, sizeof(int) * ns, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return lsp::hip_check(e, "status copy");
+  for (int i = 0; i < ns; ++i)
+    if (st[i] < 0)
+      return lsp::set_error(LSP_ERESONANT, "Gram matrix of shift " + std::to_string(i) +
+                                               " could not be factorised");
+  return LSP_OK;
+}
+
 void drop_graph(lsp_problem::GraphCache& gc) {
   if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
   gc.exec = nullptr;
@@ -675,7 +695,11 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
   }
   if (e != hipSuccess) return lsp::hip_check(e, "learned setup");
-  if (n_fallback_host) *n_fallback_host = nf;
+  if (n_fallback_host) {
+    // synchronous call: report a shift whose Gram block failed
+    if ((rc = check_setup_status(p))) return rc;
+    *n_fallback_host = nf;
+  }
   p->have_setup = true;
   p->learned = true;
   return LSP_OK;
@@ -750,16 +774,7 @@ int lsp_get_tables(lsp_problem* p, int capacity, int* nS, double* S_host, double
         return lsp::set_error(LSP_EINVAL, "unsupported stencil for the Gram expansion");
   }
   // eigen-solver status: report a failed elimination
-  std::vector<int> st(ns > 0 ? ns : 1);
-  if (ns > 0) {
-    e = hipMemcpy(st.data(), p->ws.status, sizeof(int) * ns, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return lsp::hip_check(e, "status copy");
-    for (int i = 0; i < ns; ++i)
-      if (st[i] < 0)
-        return lsp::set_error(LSP_ERESONANT, "Gram matrix of shift " + std::to_string(i) +
-                                                 " could not be factorised");
-  }
-  return LSP_OK;
+  return check_setup_status(p);
 }
 
 int lsp_export_pattern(int d, int n, int t, int64_t* col_host) {
@@ -813,7 +828,9 @@ int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev, double
   if (!p->have_setup) return lsp::set_error(LSP_ESTATE, "precond_solve needs a completed setup");
   const int64_t N = p->N;
   const int64_t N2 = 2 * N;
-  int rc = check_finite_device(p, f_dev, N2, "f");
+  int rc = check_setup_status(p);
+  if (rc) return rc;
+  rc = check_finite_device(p, f_dev, N2, "f");
   if (rc) return rc;
   // workspace: V (restart+1), Z (restart), w, tmp; coefficient buffer
   const size_t need = (size_t)N2 * (2 * (size_t)restart + 3) + 2 * (size_t)(restart + 2);

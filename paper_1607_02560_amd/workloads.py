@@ -10,7 +10,8 @@ names "a Gaussian profile", "random Gaussians", ...). The recipes below
 are stand-ins with the same structure:
 
   helm2d_gauss   2D Helmholtz, c = 1 - 0.3 exp(-|x-x0|^2/0.02),
-                 omega for 8 points per wavelength at c = 1, 3x3 stencil.
+                 omega for 8 points per wavelength at c = 1, 3x3 stencil,
+                 |S| = 2 at n <= 32 and n/16 above.
   schrod2d_wells 2D Schroedinger-type, 16 Gaussian wells of depth
                  U[5,20] n^2 and width U[0.02,0.05], minus E = 0.5 max depth.
   helm2d_random  2D Helmholtz, c a smooth random field in [0.8,1.2]
@@ -146,15 +147,18 @@ def smooth_random_c(d: int, n: int, seed: int, lo=0.8, hi=1.2, kmax=8.0) -> np.n
     return lo + (hi - lo) * (psi - pmin) / (pmax - pmin)
 
 
-def helm2d_gauss(n: int = 32, seed: int = 0) -> Problem:
-    """2D Helmholtz, Gaussian-profile velocity, 3x3 stencils, |S| = 2."""
+def helm2d_gauss(n: int = 32, seed: int = 0, num_shifts=None) -> Problem:
+    """2D Helmholtz, Gaussian-profile velocity, 3x3 stencils; |S| = 2 at
+    n <= 32 (the small configuration) and n/16 above, the ratio of Sec. 5."""
     d = 2
     c = 1.0 - 0.3 * np.exp(-periodic_sqdist(d, n, (0.5, 0.5)) / 0.02)
     omega = 2.0 * np.pi * n / 8.0
     v = -(omega / c) ** 2
     f = gaussian_source(d, n, (0.3, 0.3), 0.05)
+    if num_shifts is None:
+        num_shifts = 2 if n <= 32 else n // 16
     return Problem("helm2d_gauss", d, n, np.ascontiguousarray(v), f, t=1,
-                   num_shifts=2, omega=omega)
+                   num_shifts=num_shifts, omega=omega)
 
 
 def schrod2d_wells(n: int = 256, seed: int = 0, wells: int = 16) -> Problem:
