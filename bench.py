@@ -17,7 +17,9 @@ beside the method, with exact fallback) with the exact setup on the 3D
 Helmholtz workload n = 64, t = 1, |S| = 16: the network is trained on the GPU
 on 200,000 exact rows of other fields (seeds 1..8), both setups are timed on
 the evaluation field (seed 0), and GMRES(40) iteration counts to 1e-8 are
-compared on the same kind of field at n = 16, where the host LU of P is cheap.
+compared on the same kind of field at n = 16, where the host LU of P is cheap,
+with a network trained the same way on n = 16 fields (its fallback fraction is
+reported beside the counts).
 
 A third section times the batched form: 64 2D problems with n drawn from
 {64, 128, 256, 512}, set up (FP32 rows) and applied with one launch per stage
@@ -135,28 +137,39 @@ def learned_vs_exact(dev, stream, reps, train_steps, threshold=1e-3):
     t_learned = timed(stream, learned, reps)
     nf = [prob.stencil_setup_learned(net, t, nS, threshold, P, fb)]
     prob.close()
-    # GMRES(40) to 1e-8 on an n = 16 field of the same kind
+    net.close()
+    # GMRES(40) to 1e-8 on an n = 16 field of the same kind (seed 0), where the
+    # host LU of P is cheap, with a network trained the same way on n = 16
+    # fields (seeds 1..8, every point): the comparison runs with the network's
+    # rows, and the fallback fraction says how many
     print("[bench] learned: GMRES comparison at n=16", file=sys.stderr, flush=True)
     ns = 16
+    Xs, Ts = SG.gather_rows([W.helm3d_random(ns, seed=s).v for s in range(1, 9)], t, 0, ns ** 3,
+                            seed=103, device=dev)
+    net16 = SG.make_mlp(3, t, seed=104, batch_rows=4096)
+    net16.fit_normalisation(Xs, Ts)
+    SG.train(net16, Xs, Ts, 2000, 4096, 3e-3, seed=105, lr_final=3e-4)
     small = W.helm3d_random(ns, seed=0)
     Ns = ns ** 3
     probs = lsp.Problem(3, ns, torch.from_numpy(small.v.reshape(-1)).to(dev))
     ft = torch.from_numpy(small.f.reshape(-1)).to(dev)
     Ps = torch.empty(Ns * m, dtype=torch.float64, device=dev)
     fbs = torch.empty(Ns, dtype=torch.int32, device=dev)
-    gm = {}
+    gm = {"network": f"trained on {int(Xs.shape[0])} exact rows of n={ns} fields (seeds 1..8), "
+                     f"2000 Adam steps of 4096 rows", "threshold_excess": threshold}
     for name in ("exact", "learned"):
         if name == "exact":
             probs.stencil_setup(t, small.num_shifts, Ps)
             nfs = 0
         else:
-            nfs = probs.stencil_setup_learned(net, t, small.num_shifts, threshold, Ps, fbs)
+            nfs = probs.stencil_setup_learned(net16, t, small.num_shifts, threshold, Ps, fbs)
         solve = lsp.host_lu_solver(Ps.cpu().numpy().reshape(Ns, m), 3, ns, t)
         ut = torch.zeros_like(ft)
         code, iters, relres = probs.precond_solve(ft, ut, solve, rtol=1e-8, restart=40, maxit=400)
-        gm[name] = {"iterations": iters, "relres": relres, "status": code, "fallback_rows": nfs}
+        gm[name] = {"iterations": iters, "relres": relres, "status": code, "fallback_rows": nfs,
+                    "fallback_frac": nfs / Ns}
     probs.close()
-    net.close()
+    net16.close()
     return {
         "workload": f"3D Helmholtz, smooth random c in [0.8,1.2], n={n} (N={N}), t={t} "
                     f"(3x3x3 stencils), |S|={nS}, evaluation seed 0",

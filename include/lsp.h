@@ -315,13 +315,16 @@ int lsp_training_rows(lsp_problem* p, const double* P_dev, const int64_t* points
                       int count, float* X_dev, float* T_dev);
 
 /* Learned setup: the shift tables of Sec. 4.1-4.2 as in lsp_stencil_setup,
- * then the network's P and C rows for every point, each checked with the
- * exact Gram matrices of its shift: with q = p - c (v[mu_j] - s_j),
+ * then, for every point, the network's outputs p (P row) and c (C row),
+ * which propose the stencil q = p - c (v[mu_j] - s_j) (the row of Q). The
+ * stencil is checked with the exact Gram matrices of the point's shift:
  * rho = sqrt(q^T M q / q^T A1 q) (M = A1 - A2, eq. (A)) is the fraction of
  * the row of Q G that the truncation to mu drops (Sec. 3). The exact stencil
  * itself drops rho*(s) > 0 (about 0.05 for d = 3, t = 1), so the test is on
- * the excess: rows with rho > rho*(s_j) + threshold take the exact P and C
- * rows (fallback_dev[j] = 1).
+ * the excess. A kept point takes the rows its stencil defines,
+ * C[j, mu_j] = (Q G)[j, mu_j] = G_mu,mu q and P = q + C (v[mu_j] - s_j)
+ * (Sec. 4.1, eq. (PC)); a point with rho > rho*(s_j) + threshold (or a
+ * non-finite output) takes the exact P and C rows (fallback_dev[j] = 1).
  *   P_dev         output, N*m float64 (layout of lsp_stencil_setup).
  *   fallback_dev  output, N int32 (1 = exact row used).
  *   n_fallback_host  receives the number of fallback rows; with NULL the call

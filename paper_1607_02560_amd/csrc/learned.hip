@@ -1,11 +1,12 @@
-// Fused learned setup: for every grid point, the surrogate network's P and C
-// rows, the check of the predicted stencil against the exact Gram matrices of
-// eq. (A), and the exact row where the check fails, in one pass over the grid.
+// Fused learned setup: for every grid point, the surrogate network's proposed
+// stencil, its check against the exact Gram matrices of eq. (A), and the rows
+// of P and C it defines (or the exact rows where the check fails), in one
+// pass over the grid.
 //
 // One block of 8 waves per CU keeps the network's BF16 weights, biases,
 // standardisation, the shift list and, per shift, the upper triangles of the
-// parity blocks of A1 and M (see PForms) and rho*(s) in LDS; each wave then
-// works alone (no block barrier after the loads) on chunks of 32 points:
+// parity blocks of A1, M and G (see PForms) and rho*(s) in LDS; each wave
+// then works alone (no block barrier after the loads) on chunks of 32 points:
 //   * one lane per point finds its shift s_j (also the network's last input);
 //   * the wave evaluates its 32 points as 2 groups of 16 with
 //     v_mfma_f32_16x16x16bf16 in the transposed form Z^T = W X^T, so that the
@@ -15,18 +16,20 @@
 //     hidden layer is produced; the check's gathers v[mu_j] are issued before
 //     the network so that it hides their latency;
 //   * the de-standardised FP32 outputs go to the wave's staging rows in LDS;
-//     lanes j and j + 32 read point j's row, form q = p - c (v[mu_j] - s_j),
-//     take its parity coordinates and split the forms of eq. (A): one
-//     accumulates q^T A1 q, the other q^T M q (M = A1 - G G), each from the
-//     block triangles of the point's shift; the point falls back when
-//     q^T M q > (rho*(s) + threshold)^2 q^T A1 q;
-//   * the rows leave the staging area as contiguous (coalesced) stores of the
-//     wave's 32 x m blocks of P and C; entries of failed points are the exact
-//     rows alpha + C (v[mu_j] - s_j) and C.
-// Numerics equal the unfused path (the same BF16 roundings, FP32 bias and
-// SiLU, FP32 de-standardisation, FP64 rows); its check sums the dense forms
-// instead of the parity blocks, so the two decide alike except within
-// rounding of the boundary.
+//     lanes j and j + 32 read point j's row, form the stencil
+//     q = p - c (v[mu_j] - s_j), take its parity coordinates and split the
+//     forms of eq. (A): one accumulates q^T A1 q, the other q^T M q
+//     (M = A1 - G G), each from the block triangles of the point's shift; the
+//     point falls back when q^T M q > (rho*(s) + threshold)^2 q^T A1 q;
+//   * a kept point's rows are the ones its stencil defines, C = G_mu,mu q
+//     (from the G blocks) and P = q + C (v[mu_j] - s_j); a failed point's are
+//     the exact rows alpha + C (v[mu_j] - s_j) and C of its shift;
+//   * the FP64 rows go through the staging area and leave as contiguous
+//     (coalesced) stores of the wave's 32 x m blocks of C and P.
+// The network's numerics equal the unfused path's (the same BF16 roundings,
+// FP32 bias and SiLU, FP32 de-standardisation); the unfused check sums the
+// dense forms instead of the parity blocks, so the two decide alike except
+// within rounding of the boundary, and their rows agree to rounding.
 #include <map>
 #include <mutex>
 #include <utility>
@@ -170,6 +173,49 @@ __device__ __forceinline__ double parity_form(const double* tb, const double* u,
   return acc;
 }
 
+// C = G_mu,mu q in the same basis: G_mu,mu = sum_c U_c G'_c U_c^T with U_c the
+// +-1 map of parity_coords and G'_c = S G_b S (full symmetric block, upper
+// triangle stored, entries not doubled), so C = sum_c U_c (G'_c u_c). Class
+// by class: y_c = G'_c u_c from the triangle, then its entries are scattered
+// back to the offsets (the transpose of parity_coords).
+template <int D, int W, int K>
+__device__ __forceinline__ void gvec_term(const double* gt, const double* u, double* y) {
+  using PF = PForms<D, W>;
+  constexpr int c = PF::cls(K), pr = PF::row(K), qc = PF::col(K), b0 = PF::base(c);
+  const double gv = gt[K];
+  y[b0 + pr] = fma(gv, u[b0 + qc], y[b0 + pr]);
+  if constexpr (qc != pr) y[b0 + qc] = fma(gv, u[b0 + pr], y[b0 + qc]);
+}
+template <int D, int W, int A, int C>
+__device__ __forceinline__ void unparity_term(const double* y, double* out) {
+  using PF = PForms<D, W>;
+  constexpr int tm = PF::term(A, C);
+  if constexpr (tm > 0) out[A] += y[PF::base(C) + tm - 1];
+  if constexpr (tm < 0) out[A] -= y[PF::base(C) - tm - 1];
+}
+template <int D, int W, int C, int... K>
+__device__ __forceinline__ void gvec_class(const double* gt, const double* u, double* y,
+                                           std::integer_sequence<int, K...>) {
+  (gvec_term<D, W, PForms<D, W>::tri(C) + K>(gt, u, y), ...);
+}
+template <int D, int W, int C, int... A>
+__device__ __forceinline__ void unparity_class(const double* y, double* out,
+                                               std::integer_sequence<int, A...>) {
+  (unparity_term<D, W, A, C>(y, out), ...);
+}
+template <int D, int W, int... C>
+__device__ __forceinline__ void g_times(const double* gt, const double* u, double* out,
+                                        std::integer_sequence<int, C...>) {
+  using PF = PForms<D, W>;
+  constexpr int M = PF::M;
+  double y[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) y[k] = 0.0;
+  ((gvec_class<D, W, C>(gt, u, y, std::make_integer_sequence<int, PF::tri(C + 1) - PF::tri(C)>{}),
+    unparity_class<D, W, C>(y, out, std::make_integer_sequence<int, M>{})),
+   ...);
+}
+
 // Compile-time geometry of the fused kernel for neighbourhood mu_0^t in D dims.
 template <int D, int W>
 struct Fused {
@@ -193,24 +239,26 @@ struct Fused {
   static constexpr size_t oSX = oMX + 4 * IP;
   static constexpr size_t oMY = oSX + 4 * IP;
   static constexpr size_t oSY = oMY + 4 * OP;
-  // per-wave area: s_j, 1/|s_j|, fallback flags, staged outputs
+  // per-wave area: s_j, 1/|s_j|, staged outputs (FP32 network outputs, then
+  // the FP64 rows)
   static constexpr size_t oWave = (oSY + 4 * OP + 15) / 16 * 16;
   static constexpr size_t wSV = 0;
   static constexpr size_t wINV = wSV + 8 * kPW;
-  static constexpr size_t wFLG = wINV + 8 * kPW;
-  static constexpr size_t wSID = wFLG + 4 * kPW;
-  static constexpr size_t wSTG = (wSID + 4 * kPW + 15) / 16 * 16;
+  static constexpr size_t wSTG = (wINV + 8 * kPW + 15) / 16 * 16;
   static constexpr size_t WB = (wSTG + 4 * (size_t)kPW * SST + 15) / 16 * 16;
-  // per shift: S, the Gram triangles {A1', M'} (PForms) and rho*(s); the
-  // triangles start 16-byte aligned after the (even-padded) shift list
+  // per shift: S, the Gram triangles {A1', M'} (PForms), the triangle of G'
+  // and rho*(s); the triangles start 16-byte aligned after the (even-padded)
+  // shift list
   static constexpr int TRIP = PForms<D, W>::TRIP;
   static constexpr size_t oS = oWave + WB * kWaves;
   static constexpr size_t tab_off(int shifts) { return oS + 8 * (size_t)((shifts + 1) & ~1); }
-  static constexpr size_t rho_off(int shifts) { return tab_off(shifts) + 16 * (size_t)TRIP * shifts; }
+  static constexpr size_t gt_off(int shifts) { return tab_off(shifts) + 16 * (size_t)TRIP * shifts; }
+  static constexpr size_t rho_off(int shifts) { return gt_off(shifts) + 8 * (size_t)TRIP * shifts; }
   // LDS bytes for a shift list of up to `shifts` entries
   static constexpr size_t bytes(int shifts) { return rho_off(shifts) + 8 * (size_t)shifts; }
   static_assert(IP <= 32 && OP <= 64, "fused kernel sizes");
   static_assert(NR * 4 <= SST && wSTG % 16 == 0, "staging layout");
+  static_assert(2 * kPW * M <= kPW * SST, "FP64 rows of a pass fit the staging area");
 };
 
 // makes the wave's LDS writes visible to its other lanes (LDS operations of a
@@ -307,8 +355,6 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
   char* wa = lds + F::oWave + wave * F::WB;
   double* sv = reinterpret_cast<double*>(wa + F::wSV);
   double* iv = reinterpret_cast<double*>(wa + F::wINV);
-  int* flg = reinterpret_cast<int*>(wa + F::wFLG);
-  int* sidw = reinterpret_cast<int*>(wa + F::wSID);
   float* stg = reinterpret_cast<float*>(wa + F::wSTG);
 
   // ---- network, shift list, Gram triangles and rho* into LDS (once per block) ----
@@ -342,6 +388,7 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
   }
   const int nS = *nS_ptr;
   double2* Tb = reinterpret_cast<double2*>(lds + F::tab_off(nS));
+  double* Gt = reinterpret_cast<double*>(lds + F::gt_off(nS));
   double* rs = reinterpret_cast<double*>(lds + F::rho_off(nS));
   for (int e = tid; e < nS; e += kThreads) {
     Ss[e] = S[e];
@@ -368,8 +415,9 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     const int z = PF::nz(c, pr) + PF::nz(c, qc);
     double f = ldexp(1.0, -(z / 2));
     if (z & 1) f *= lsp::kInvSqrt2;
-    if (qc != pr) f *= 2.0;
     const double* blk = Mtab + (int64_t)si * M * M + Pa::offset(c) + pr * B + qc;
+    Gt[si * PF::TRIP + k] = blk[2 * Pa::offset(Pa::NC)] * f;  // G' (not doubled)
+    if (qc != pr) f *= 2.0;
     Tb[si * PF::TRIP + k] = make_double2(blk[Pa::offset(Pa::NC)] * f, blk[0] * f);
   }
   __syncthreads();  // the last block-wide barrier: from here on every wave works alone
@@ -389,7 +437,6 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     if (half == 0) {
       sv[pl] = s;
       iv[pl] = 1.0 / fabs(s);
-      sidw[pl] = id;
     }
     wave_sync();
 
@@ -530,12 +577,12 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     // rho = sqrt(q^T M q / q^T A1 q) of eq. (A) in the parity basis: u are
     // q's unnormalised parity coordinates; lane pl accumulates u^T A1' u, lane
     // pl + 32 u^T M' u from the point's shift triangles
+    double u[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) u[k] = 0.0;
+    parity_coords<D, W>(q, u, std::make_integer_sequence<int, M * PF::NC>{});
     double qaq, qmq;
     {
-      double u[M];
-#pragma unroll
-      for (int k = 0; k < M; ++k) u[k] = 0.0;
-      parity_coords<D, W>(q, u, std::make_integer_sequence<int, M * PF::NC>{});
       const double* tb = reinterpret_cast<const double*>(Tb + id * PF::TRIP) + (half ? 1 : 0);
       const double acc = parity_form<D, W>(tb, u, std::make_integer_sequence<int, PF::TRI>{});
       const double other = __shfl_xor(acc, 32);
@@ -544,41 +591,63 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     }
     const double lim = rs[id] + thr;
     const bool ok = valid && (qaq > 0.0) && isfinite(qmq) && (qmq <= lim * lim * qaq);
-    if (half == 0) {
-      flg[pl] = ok ? 0 : 1;
-      if (valid) fallback[j] = ok ? 0 : 1;
-    }
+    if (half == 0 && valid) fallback[j] = ok ? 0 : 1;
     nf_local += __popcll(__ballot(half == 0 && valid && !ok));
-    wave_sync();
 
-    // ---- rows: the wave's 32 x m blocks of P and C leave as contiguous
-    // stores; entries of failed points are the exact rows alpha + C (v[mu_j] -
-    // s_j) and C ----
+    // ---- the point's rows. The network only proposes the stencil q (the
+    // row of Q); a kept point takes the rows that stencil defines:
+    // C = (Q G)[j, mu_j] = G_mu,mu q and P = q + C (v[mu_j] - s_j) (Sec. 4.1,
+    // eq. PC), so its row of C A - P differs from zero only by the truncated
+    // part that rho measures. A failed point takes its shift's exact rows
+    // alpha + C (v[mu_j] - s_j) and C. ----
+    double cr[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) cr[a] = 0.0;
+    g_times<D, W>(Gt + id * PF::TRIP, u, cr, std::make_integer_sequence<int, PF::NC>{});
+    if (!ok) {
+#pragma unroll
+      for (int a = 0; a < M; ++a) {
+        const double2 ac = actab[(int64_t)id * M + a];
+        q[a] = ac.x;
+        cr[a] = ac.y;
+      }
+    }
+    // both halves hold the same rows; each stages half of every row (FP64)
+    // in the wave's staging area, whose FP32 outputs every lane has read, and
+    // the wave's 32 x m block then leaves as contiguous stores
+    double* stgd = reinterpret_cast<double*>(stg);
+    constexpr int HM = (M + 1) / 2;
     const int64_t rbase = wbase * M;
     const int rend = (int)((N - wbase < kPW ? N - wbase : kPW) * M);  // entries of valid points
-    int ln = lane;
-    asm volatile("" : "+v"(ln));  // opaque per chunk: the index arithmetic stays in the loop
+    wave_sync();
 #pragma unroll
-    for (int u = 0; u < (kPW * M + 63) / 64; ++u) {
-      const int e = ln + 64 * u;
-      if (e < rend) {
-        const int pt = e / M, a = e - pt * M;
-        const float yp = stg[pt * SST + a], yc = stg[pt * SST + M + a];
-        double pv, cv;
-        if (flg[pt] == 0) {
-          pv = (double)yp;
-          cv = (double)yc * iv[pt];
-        } else {
-          const double2 ac = actab[(int64_t)sidw[pt] * M + a];
-          int cp[D];
-          coords<D>(wbase + pt, logn, cp);
-          const double vm = v[neighbour_rt<D, W>(cp, logn, a)] - sv[pt];
-          pv = exact_entry(ac.x, ac.y, vm);
-          cv = ac.y;
-        }
-        P[rbase + e] = pv;
-        Crows[rbase + e] = cv;
-      }
+    for (int i = 0; i < HM; ++i) {
+      const double hi = (HM + i < M) ? cr[(HM + i < M) ? HM + i : 0] : 0.0;
+      if (half == 0) stgd[pl * M + i] = cr[i];
+      else if (HM + i < M) stgd[pl * M + HM + i] = hi;
+    }
+    wave_sync();
+#pragma unroll
+    for (int w = 0; w < (kPW * M + 63) / 64; ++w) {
+      const int e = lane + 64 * w;
+      if (e < rend) Crows[rbase + e] = stgd[e];
+    }
+    // P entries with the rounding of the exact assembly (product and sum
+    // rounded separately)
+#pragma unroll
+    for (int a = 0; a < M; ++a) q[a] = exact_entry(q[a], cr[a], vq[a] - s);
+    wave_sync();
+#pragma unroll
+    for (int i = 0; i < HM; ++i) {
+      const double hi = (HM + i < M) ? q[(HM + i < M) ? HM + i : 0] : 0.0;
+      if (half == 0) stgd[pl * M + i] = q[i];
+      else if (HM + i < M) stgd[pl * M + HM + i] = hi;
+    }
+    wave_sync();
+#pragma unroll
+    for (int w = 0; w < (kPW * M + 63) / 64; ++w) {
+      const int e = lane + 64 * w;
+      if (e < rend) P[rbase + e] = stgd[e];
     }
     wave_sync();  // the wave's LDS area is rewritten by its next chunk
   }

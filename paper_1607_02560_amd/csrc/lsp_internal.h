@@ -33,7 +33,7 @@ struct Workspace {
   // per-shift tables
   double* gtab = nullptr;         // [shifts][W^d]   W = 2t+1, offsets [0,2t]^d
   double* gamtab = nullptr;       // [shifts][W^d]
-  double* Mtab = nullptr;         // [shifts][m*m]: packed parity blocks of M, then of A1
+  double* Mtab = nullptr;         // [shifts][m*m]: packed parity blocks of M, then of A1, then of G
   double* alpha = nullptr;        // [shifts][m]
   double* Ctab = nullptr;         // [shifts][m]
   double* sigma = nullptr;        // [shifts]

@@ -847,13 +847,13 @@ __global__ void targets_kernel(const double* __restrict__ P, const double* __res
   }
 }
 
-// q^T A1 q and q^T M q = q^T A1 q - |G q|^2 for a stencil q on mu_0^t, with
-// G[a][b] = g[|a - b|] and A1[a][b] = gam[|a - b|] (eq. A; tables at the
+// q^T A1 q, q^T M q = q^T A1 q - |G q|^2 and G q for a stencil q on mu_0^t,
+// with G[a][b] = g[|a - b|] and A1[a][b] = gam[|a - b|] (eq. A; tables at the
 // offsets [0, 2t]^d)
 template <int D, int W>
 __device__ __forceinline__ void gram_forms(const double* __restrict__ g,
                                            const double* __restrict__ gm, const double* q,
-                                           double& qaq, double& qmq) {
+                                           double& qaq, double& qmq, double* gq) {
   using Nb = Nbhd<D, W>;
   constexpr int M = Pow<D, W>::v;
   double a1 = 0.0, gq2 = 0.0;
@@ -866,6 +866,7 @@ __device__ __forceinline__ void gram_forms(const double* __restrict__ g,
       u = fma(g[k], q[b], u);
       w = fma(gm[k], q[b], w);
     }
+    gq[a] = u;
     gq2 = fma(u, u, gq2);
     a1 = fma(q[a], w, a1);
   }
@@ -882,9 +883,11 @@ __device__ __forceinline__ double exact_entry(double alpha, double c, double v_m
 
 // Learned rows of points j0 .. j0+rows-1 from the de-standardised network
 // outputs Y [rows][2m]: p = Y[:m], c = Y[m:] / |s_j|, stencil
-// q = p - c (v[mu_j] - s_j) and rho = sqrt(q^T M q / q^T A1 q) (eq. A). Rows
-// with rho > rho*(s_j) + thr, where rho*(s_j) is the same quantity for the
-// exact stencil of the shift (or with a non-finite value), take the exact row
+// q = p - c (v[mu_j] - s_j) and rho = sqrt(q^T M q / q^T A1 q) (eq. A). A
+// kept point takes the rows its stencil defines, C = (Q G)[j, mu_j] =
+// G_mu,mu q and P = q + C (v[mu_j] - s_j) (Sec. 4.1, eq. PC). Rows with
+// rho > rho*(s_j) + thr, where rho*(s_j) is the same quantity for the exact
+// stencil of the shift (or with a non-finite value), take the exact row
 // alpha + C (v[mu_j] - s_j) and C; fallback[j] records which.
 template <int D, int W>
 __global__ void learned_rows_kernel(const double* __restrict__ v, int n,
@@ -909,8 +912,8 @@ __global__ void learned_rows_kernel(const double* __restrict__ v, int n,
     c[a] = (double)Y[(int64_t)r * 2 * M + M + a] * inv_as;
     q[a] = (double)Y[(int64_t)r * 2 * M + a] - c[a] * vm[a];
   }
-  double qaq, qmq;
-  gram_forms<D, W>(gtab + (int64_t)id * M, gamtab + (int64_t)id * M, q, qaq, qmq);
+  double qaq, qmq, gq[M];
+  gram_forms<D, W>(gtab + (int64_t)id * M, gamtab + (int64_t)id * M, q, qaq, qmq, gq);
   const double lim = rho_star[id] + thr;
   const bool ok = (qaq > 0.0) && isfinite(qmq) && (qmq <= lim * lim * qaq);
   const double2* act = actab + (int64_t)id * M;
@@ -918,8 +921,8 @@ __global__ void learned_rows_kernel(const double* __restrict__ v, int n,
   for (int a = 0; a < M; ++a) {
     double pr, cr;
     if (ok) {
-      cr = c[a];
-      pr = (double)Y[(int64_t)r * 2 * M + a];  // the learned P row
+      cr = gq[a];
+      pr = exact_entry(q[a], gq[a], vm[a]);
     } else {
       const double2 ac = act[a];
       cr = ac.y;

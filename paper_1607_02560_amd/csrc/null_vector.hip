@@ -61,8 +61,8 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   using Pa = Parity<D, W>;
   constexpr int B = Pa::size(C);
   constexpr int NS = 1 << D;  // per-axis term choices of a block entry
-  static_assert(2 * Pa::offset(Pa::NC) <= Pow<D, W>::v * Pow<D, W>::v,
-                "the M and A1 blocks of a shift share its m*m slot");
+  static_assert(3 * Pa::offset(Pa::NC) <= Pow<D, W>::v * Pow<D, W>::v,
+                "the M, A1 and G blocks of a shift share its m*m slot");
   const int p = (lane < B) ? lane : 0;
 
   // per-axis 1D indices of row p
@@ -137,13 +137,16 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
 #pragma unroll
   for (int qc = 0; qc < B; ++qc) mrow[qc] = arow[qc] - mrow[qc];
   if (lane < B) {
-    // the shift's M blocks, then (after all of them) its A1 blocks
+    // the shift's M blocks, then (after all of them) its A1 blocks, then its
+    // G blocks (the learned setup forms C = G q from them)
     double* mo = Mtab_si + Pa::offset(C) + lane * B;
     double* ao = Mtab_si + Pa::offset(Pa::NC) + Pa::offset(C) + lane * B;
+    double* go = Mtab_si + 2 * Pa::offset(Pa::NC) + Pa::offset(C) + lane * B;
 #pragma unroll
     for (int qc = 0; qc < B; ++qc) {
       mo[qc] = mrow[qc];
       ao[qc] = arow[qc];
+      go[qc] = grow[qc];
     }
   }
 
