@@ -117,9 +117,15 @@ void build_maps(const lsp_batch* b, const std::vector<int>& nreq, int tw,
   for (int i = 0; i < (int)b->probs.size(); ++i) {
     const lsp_problem* p = b->probs[i];
     for (int bx = 0; bx < lsp::kMinMaxBlocks; ++bx) mm.push_back(make_int4(i, bx, 0, 0));
-    const int groups = lsp::green_shift_groups(nreq[i]);
-    for (int by = 0; by < groups; ++by)
-      for (int bx = 0; bx < p->green_nunits; ++bx) green.push_back(make_int4(i, bx, by, 0));
+    if (b->d == 2) {
+      // the balanced Green's launch of the problem: its waves in blocks of 4
+      const int blocks = lsp::green2d_waves(p->n, nreq[i]) / 4;
+      for (int bx = 0; bx < blocks; ++bx) green.push_back(make_int4(i, bx, 0, 0));
+    } else {
+      const int groups = lsp::green_shift_groups(nreq[i]);
+      for (int by = 0; by < groups; ++by)
+        for (int bx = 0; bx < p->green_nunits; ++bx) green.push_back(make_int4(i, bx, by, 0));
+    }
     for (int si = 0; si < nreq[i]; ++si) null.push_back(make_int4(i, si, 0, 0));
     const int planes = (b->d == 3) ? p->n : 1;
     for (int bz = 0; bz < planes; ++bz)
@@ -270,12 +276,15 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
       r.N = p->N;
       r.invN = 1.0 / (double)p->N;
       r.mm_part = p->ws.minmax_part;
+      r.ticket = p->ws.ticket;
       r.S = p->ws.S;
       r.nS = p->ws.nS;
       r.vrange = p->ws.vrange;
       r.cw = p->cosT;
       r.units = p->green_units;
       r.nunits = p->green_nunits;
+      r.gwaves = (p->d == 2) ? lsp::green2d_waves(p->n, nreq[i]) : 0;
+      r.sps = (p->d == 2) ? lsp::green2d_sps(p->n) : 0;
       r.part = p->ws.green_part;
       r.gtab = p->ws.gtab;
       r.gamtab = p->ws.gamtab;

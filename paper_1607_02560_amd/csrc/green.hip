@@ -168,82 +168,13 @@ __host__ __device__ inline int tiled_wavenumbers(int n) {
   return D == 2 ? n / 2 : n / 2 + 1;
 }
 
-// The one shift of the non-localized method (Sec. 3) from the min/max/sum
-// partials, computed by every thread of the block: s = mean of v, moved to
-// (2 - 4K) pi^2 (the form (4m+2) pi^2 with m = -K, 2 pi^2 above the singular
-// point) only when L + s is singular, i.e. when x = -s / (4 pi^2) lies within
-// 2^-30 max(1, |x|) of an integer K >= 0.
-// The partial sums are added in a fixed order (per thread, butterfly over
-// the lanes, waves in index order), so every thread gets the same s.
-// Results in LDS like lsp::shift_list_block: sS[0], *sNS = 1, sRange.
-template <int NT>
-__device__ inline void global_shift_block(const double* __restrict__ part, int64_t N, double* sS,
-                                          int* sNS, double* sRange, double* sRed) {
-  static_assert(NT % 64 == 0 && lsp::kMinMaxBlocks % NT == 0, "block shape");
-  constexpr int NW = NT / 64;
-  constexpr int PER = lsp::kMinMaxBlocks / NT;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
-  const double2* p2 = reinterpret_cast<const double2*>(part);
-  const double* ps = part + 2 * lsp::kMinMaxBlocks;
-  double2 x[PER];
-  double xs[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    x[i] = p2[tid + i * NT];
-    xs[i] = ps[tid + i * NT];
-  }
-  double lo = x[0].x, hi = x[0].y, sum = xs[0];
-#pragma unroll
-  for (int i = 1; i < PER; ++i) {
-    lo = fmin(lo, x[i].x);
-    hi = fmax(hi, x[i].y);
-    sum += xs[i];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, o));
-    hi = fmax(hi, __shfl_xor(hi, o));
-    sum += __shfl_xor(sum, o);
-  }
-  if (lane == 0) {
-    sRed[3 * wid] = lo;
-    sRed[3 * wid + 1] = hi;
-    sRed[3 * wid + 2] = sum;
-  }
-  __syncthreads();
-  lo = sRed[0];
-  hi = sRed[1];
-  sum = sRed[2];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) {
-    lo = fmin(lo, sRed[3 * w]);
-    hi = fmax(hi, sRed[3 * w + 1]);
-    sum += sRed[3 * w + 2];
-  }
-  double s = sum / (double)N;
-  const double xr = -s / lsp::kFourPi2;
-  const double K = floor(xr + 0.5);
-  if (K >= 0.0 && fabs(xr - K) <= 0x1p-30 * fmax(1.0, fabs(xr)))
-    s = (2.0 - 4.0 * K) * lsp::kPi2;
-  if (tid == 0) {
-    sS[0] = s;
-    *sNS = 1;
-    sRange[0] = lo;
-    sRange[1] = hi;
-  }
-  __syncthreads();
-}
-
 // One block per (work unit, group of kWaves shifts); wave w handles shift
 // kWaves * blockIdx.y + w. A work unit is 64 consecutive outer indices
 // o = (k_1..k_{d-1}) (one per lane) and KT consecutive values of k_d; only
 // units with a term on or above the diagonal k_d >= k_{d-1} are launched
 // (their (outer tile, k tile) pairs come from `units`, built on the host).
-// The prologue forms the shift list from the min/max partials (Sec. 4.1) once
-// per block and stages the unit's cosine rows in LDS; unit 0 of shift group 0
-// publishes S, |S| and (v_min, v_max).
+// The prologue stages the unit's cosine rows in LDS; the shift list comes
+// from the min/max launch before this one.
 //
 // 2D: with Ht = n/2 tiled wavenumbers, a unit is either wholly above the
 // diagonal or a square tile on it. A square tile is summed in full, which
@@ -252,10 +183,9 @@ __device__ inline void global_shift_block(const double* __restrict__ part, int64
 // k tile add the Nyquist column k_2 = n/2 as one more term (weight 1 above
 // the diagonal, hence 2 inside a square tile before the 1/2), and the waves
 // of unit 0 add the corner (n/2, n/2), whose cosine weights are (-1)^delta.
-template <int D, int W, int KT, bool GLOBAL>
+template <int D, int W, int KT>
 __device__ __forceinline__ void green_body(
-    int bx, int by, int gx, const double* __restrict__ mm_part, int nreq,
-    double* __restrict__ S_out, int* __restrict__ nS_out, double* __restrict__ vrange_out,
+    int bx, int by, int gx, const double* __restrict__ S, const int* __restrict__ nS_ptr,
     const double* __restrict__ cw, const int* __restrict__ units, int n,
     double* __restrict__ part) {
   using Lay = GreenLayout<D, W>;
@@ -267,9 +197,6 @@ __device__ __forceinline__ void green_body(
   constexpr int P2 = pow2_at_least(NV <= 64 ? NV : 64);
   constexpr int PER = (KT * W + kThreads - 1) / kThreads;  // staged table values per thread
   __shared__ double cws[KT * W];
-  __shared__ double sS[lsp::kMaxShifts];
-  __shared__ int sNS, sWave[kWaves];
-  __shared__ double sRange[2], sRed[3 * kWaves];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
@@ -301,7 +228,7 @@ __device__ __forceinline__ void green_body(
   const int k_end = min(Ht, k_begin + KT);
   const bool nyq_col = (D == 2) && (k_end == Ht);
 
-  // every table load of the block is issued before the shift list is formed
+  // every table load of the block is issued before any is used
   const int cnt = (k_end - k_begin) * W;
   double stage[PER];
 #pragma unroll
@@ -320,23 +247,7 @@ __device__ __forceinline__ void green_body(
     lead[0] = 1.0;
   }
 
-  if constexpr (GLOBAL) {
-    int64_t N = 1;
-#pragma unroll
-    for (int i = 0; i < D; ++i) N *= n;
-    global_shift_block<kThreads>(mm_part, N, sS, &sNS, sRange, sRed);
-  } else {
-    lsp::shift_list_block<kThreads>(mm_part, nreq, sS, &sNS, sRange, sWave, sRed);
-  }
-  const int nS = sNS;
-  if (bx == 0 && by == 0) {
-    for (int i = tid; i < nS; i += kThreads) S_out[i] = sS[i];
-    if (tid == 0) {
-      *nS_out = nS;
-      vrange_out[0] = sRange[0];
-      vrange_out[1] = sRange[1];
-    }
-  }
+  const int nS = *nS_ptr;
 #pragma unroll
   for (int i = 0; i < PER; ++i)
     if (tid + i * kThreads < cnt) cws[tid + i * kThreads] = stage[i];
@@ -344,7 +255,7 @@ __device__ __forceinline__ void green_body(
 
   const int si = by * kWaves + wid;
   if (si >= nS) return;
-  const double s = sS[si];
+  const double s = S[si];
   double tg[W], tq[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
@@ -470,13 +381,11 @@ __device__ __forceinline__ void green_body(
   }
 }
 
-template <int D, int W, int KT, bool GLOBAL>
+template <int D, int W, int KT>
 __global__ __launch_bounds__(kThreads) void green_sums_kernel(
-    const double* __restrict__ mm_part, int nreq, double* __restrict__ S_out,
-    int* __restrict__ nS_out, double* __restrict__ vrange_out, const double* __restrict__ cw,
+    const double* __restrict__ S, const int* __restrict__ nS_ptr, const double* __restrict__ cw,
     const int* __restrict__ units, int n, double* __restrict__ part) {
-  green_body<D, W, KT, GLOBAL>(blockIdx.x, blockIdx.y, gridDim.x, mm_part, nreq, S_out, nS_out,
-                       vrange_out, cw, units, n, part);
+  green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, S, nS_ptr, cw, units, n, part);
 }
 
 // one launch for the problems of a batch: block b is unit map[b].y of shift
@@ -486,8 +395,155 @@ __global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::Batc
                                                                  const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  green_body<D, W, KT, false>(it.y, it.z, r.nunits, r.mm_part, r.nreq, r.S, r.nS, r.vrange, r.cw,
-                       r.units, r.n, r.part);
+  green_body<D, W, KT>(it.y, it.z, r.nunits, r.S, r.nS, r.cw, r.units, r.n, r.part);
+}
+
+// --------------------------------------------------------------------------
+// 2D with balanced waves. With Ht = n/2 tiled wavenumbers per axis, KT =
+// min(64, Ht) and T = Ht / KT tiles, the work is the upper triangle of
+// NU = T (T + 1) / 2 tile pairs (ot <= q, row-major) per shift; one "step" is
+// one value of k_2 for the KT values k_1 = 64 ot + lane of a tile pair, so
+// every shift holds SPS = NU KT steps and the whole launch nS SPS. The launch
+// has a fixed number of waves NWV (a function of n, t and the requested |S|
+// only, so a batched launch partitions a problem exactly as its own launch
+// does); wave w takes the R = ceil(nS SPS / NWV) consecutive steps from w R.
+// Along its range a lane accumulates the inner sums T[dl] of its k_1 over the
+// steps of a tile pair and, at the pair's end, folds them into its pair sums
+// (weight 1/2 on a square tile pair, the summand being symmetric in (k_1,
+// k_2)); where its range leaves a shift (or ends) the wave reduces the pair
+// sums over its lanes and writes them as the partial of (wave w, shift s), at
+// slot w + s. Slots of one shift are consecutive in w, and slot w + s is
+// unique, since each step along the ranges advances w or s. The cosine
+// values of a step are wave-uniform (scalar loads). The Nyquist column
+// k_2 = n/2 is one extra term of the piece that ends a pair in the last k
+// tile, and the corner (n/2, n/2) is added by the wave that holds a shift's
+// first step.
+// --------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __restrict__ S,
+                                             const int* __restrict__ nS_ptr,
+                                             const double* __restrict__ cw, int n,
+                                             double* __restrict__ part) {
+  using Lay = GreenLayout<2, W>;
+  constexpr int NP = Lay::NP;
+  constexpr int NV = Lay::NV;
+  constexpr int P2 = pow2_at_least(NV);
+  constexpr int U = 4;
+  const int lane = threadIdx.x & 63;
+  const int Ht = n / 2;
+  const int KT = Ht < kTile ? Ht : kTile;
+  const int T = Ht / KT;
+  const int NU = T * (T + 1) / 2;
+  const int SPS = NU * KT;
+  const int nS = *nS_ptr;
+  const int total = nS * SPS;
+  const int R = (total + nwv - 1) / nwv;
+  int g = wave * R;
+  const int gend = min(g + R, total);
+  if (g >= gend) return;
+  const int nyq = n / 2;
+  double cn[W];
+#pragma unroll
+  for (int j = 0; j < W; ++j) cn[j] = cw[nyq * W + j];
+  while (g < gend) {
+    const int si = g / SPS;
+    const int send = min(gend, (si + 1) * SPS);
+    const double s = S[si];
+    double a[P2];
+#pragma unroll
+    for (int i = 0; i < P2; ++i) a[i] = 0.0;
+    const bool corner = (g == si * SPS);
+    while (g < send) {
+      const int rem = g - si * SPS;
+      const int u = rem / KT;
+      const int kk = rem - u * KT;
+      int ot = 0, base = 0;
+      while (u >= base + (T - ot)) {
+        base += T - ot;
+        ++ot;
+      }
+      const int q = ot + (u - base);
+      const int gstop = min(send, g - kk + KT);
+      const bool valid = lane < KT;
+      const int k1 = ot * KT + (valid ? lane : 0);
+      const int K2o = k1 * k1;
+      double tg[W], tq[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
+      int kd = q * KT + kk;
+      const int kd_end = kd + (gstop - g);
+      for (; kd + U <= kd_end; kd += U)
+        green_terms<W, U, false>(cw + kd * W, kd, K2o, 0, true, s, tg, tq);
+      for (; kd < kd_end; ++kd) green_terms<W, 1, false>(cw + kd * W, kd, K2o, 0, true, s, tg, tq);
+      const bool square = (q == ot);
+      if (q == T - 1 && gstop - g + kk == KT) {
+        // the Nyquist column k_2 = n/2: weight 1 above the diagonal, hence 2
+        // inside a square tile pair before its 1/2
+        const double r0 = green_r(K2o + nyq * nyq, s);
+        const double r1 = (square ? 2.0 : 1.0) * r0;
+        const double r2 = r1 * r0;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+          tg[j] = fma(cn[j], r1, tg[j]);
+          tq[j] = fma(cn[j], r2, tq[j]);
+        }
+      }
+      const double half = !valid ? 0.0 : (square ? 0.5 : 1.0);
+      double ck[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) ck[j] = cw[k1 * W + j] * half;
+      int pi = 0;
+#pragma unroll
+      for (int da = 0; da < W; ++da) {
+#pragma unroll
+        for (int db = da; db < W; ++db) {
+          a[pi] = fma(ck[da], tg[db], fma(ck[db], tg[da], a[pi]));
+          a[NP + pi] = fma(ck[da], tq[db], fma(ck[db], tq[da], a[NP + pi]));
+          ++pi;
+        }
+      }
+      g = gstop;
+    }
+    if (corner && lane == 0) {
+      // the corner (n/2, n/2) once per shift: pair (da, db) gets cn[da] cn[db] r
+      // (r^2 for the g*g half)
+      const double r = green_r(2 * nyq * nyq, s);
+      int pi = 0;
+#pragma unroll
+      for (int da = 0; da < W; ++da) {
+#pragma unroll
+        for (int db = da; db < W; ++db) {
+          a[pi] += (cn[da] * cn[db]) * r;
+          a[NP + pi] += (cn[da] * cn[db]) * (r * r);
+          ++pi;
+        }
+      }
+    }
+    const int vi = halving_sum<P2>(a, lane);
+    constexpr int kUnusedMask = (P2 >= 64) ? 0 : (P2 >= 32) ? 0x20 : (P2 >= 16) ? 0x30
+                                : (P2 >= 8) ? 0x31 : (P2 >= 4) ? 0x33 : 0x37;
+    if ((lane & kUnusedMask) == 0 && vi < NV)
+      part[((int64_t)wave + si) * NV + vi] = a[0];
+  }
+}
+
+template <int W>
+__global__ __launch_bounds__(kThreads) void green2d_kernel(
+    int nwv, const double* __restrict__ S, const int* __restrict__ nS_ptr,
+    const double* __restrict__ cw, int n, double* __restrict__ part) {
+  const int wave = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  green2d_body<W>(wave, nwv, S, nS_ptr, cw, n, part);
+}
+
+// one launch for the problems of a batch: block b holds waves 4 map[b].y ..
+// 4 map[b].y + 3 of problem map[b].x
+template <int W>
+__global__ __launch_bounds__(kThreads) void green2d_batched_kernel(const lsp::BatchRec* recs,
+                                                                   const int4* map) {
+  const int4 it = map[blockIdx.x];
+  const lsp::BatchRec& r = recs[it.x];
+  const int wave = it.y * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  green2d_body<W>(wave, r.gwaves, r.S, r.nS, r.cw, r.n, r.part);
 }
 
 // Work units with at least one term on or above the diagonal, in
@@ -514,26 +570,26 @@ void build_units(int n, std::vector<int>& units) {
 }
 
 template <int D, int W>
-hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out, bool global) {
-  const int nunits = p->green_nunits;
-  const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
-  if (need > p->ws.green_part_cap || nunits < 1) return hipErrorInvalidValue;
-  *units_out = nunits;
-  const int groups = (num_shifts + kWaves - 1) / kWaves;
-  // The blocks are uniform and all resident at once, so the time is set by
-  // the most loaded SIMD. Reserving kResidencyLds bytes of LDS per block (on
-  // top of its ~10-12 KB of static LDS) lets at most three blocks share a
-  // CU's 160 KB, so no SIMD takes more than three waves.
-  if (global)
-    hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile, true>), dim3(nunits, groups),
-                       dim3(kThreads), kResidencyLds, p->stream, p->ws.minmax_part, num_shifts,
-                       p->ws.S, p->ws.nS, p->ws.vrange, p->cosT, p->green_units, p->n,
-                       p->ws.green_part);
-  else
-    hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile, false>), dim3(nunits, groups),
-                       dim3(kThreads), kResidencyLds, p->stream, p->ws.minmax_part, num_shifts,
-                       p->ws.S, p->ws.nS, p->ws.vrange, p->cosT, p->green_units, p->n,
-                       p->ws.green_part);
+hipError_t run_green(const lsp_problem* p, int num_shifts) {
+  if constexpr (D == 2) {
+    const int nwv = lsp::green2d_waves(p->n, num_shifts);
+    const size_t need = (size_t)(nwv + num_shifts) * GreenLayout<2, W>::NV;
+    if (need > p->ws.green_part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads), 0, p->stream,
+                       nwv, p->ws.S, p->ws.nS, p->cosT, p->n, p->ws.green_part);
+  } else {
+    const int nunits = p->green_nunits;
+    const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
+    if (need > p->ws.green_part_cap || nunits < 1) return hipErrorInvalidValue;
+    const int groups = (num_shifts + kWaves - 1) / kWaves;
+    // The blocks are uniform and all resident at once, so the time is set by
+    // the most loaded SIMD. Reserving kResidencyLds bytes of LDS per block (on
+    // top of its ~10-12 KB of static LDS) lets at most three blocks share a
+    // CU's 160 KB, so no SIMD takes more than three waves.
+    hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(nunits, groups), dim3(kThreads),
+                       kResidencyLds, p->stream, p->ws.S, p->ws.nS, p->cosT, p->green_units,
+                       p->n, p->ws.green_part);
+  }
   return hipGetLastError();
 }
 
@@ -541,33 +597,56 @@ hipError_t run_green(lsp_problem* p, int num_shifts, int* units_out, bool global
 
 namespace lsp {
 
+int green2d_waves(int n, int num_shifts) {
+  const int Ht = n / 2;
+  const int KT = Ht < kTile ? Ht : kTile;
+  const int T = Ht / KT;
+  const int64_t steps = (int64_t)num_shifts * (T * (T + 1) / 2) * KT;
+  // at least 32 steps per wave (the per-piece reduction stays a small part
+  // of a wave's work), at most 2048 waves (two per SIMD of a 256-CU part),
+  // a whole number of 4-wave blocks
+  int64_t w = (steps + 31) / 32;
+  w = std::max<int64_t>(kWaves, std::min<int64_t>(2048, w));
+  return (int)((w + kWaves - 1) / kWaves * kWaves);
+}
+
+int green2d_sps(int n) {
+  const int Ht = n / 2;
+  const int KT = Ht < kTile ? Ht : kTile;
+  const int T = Ht / KT;
+  return (T * (T + 1) / 2) * KT;
+}
+
 hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
                                 hipStream_t s) {
   const int W = 2 * t + 1;
-#define LSP_GREEN_B(D_, W_)                                                                   \
-  if (d == D_ && W == W_) {                                                                   \
-    hipLaunchKernelGGL((green_batched_kernel<D_, W_, kKTile>), dim3(blocks), dim3(kThreads),  \
-                       kResidencyLds, s, recs, map);                                          \
-    return hipGetLastError();                                                                 \
+#define LSP_GREEN2_B(W_)                                                                  \
+  if (d == 2 && W == W_) {                                                                \
+    hipLaunchKernelGGL((green2d_batched_kernel<W_>), dim3(blocks), dim3(kThreads), 0, s,  \
+                       recs, map);                                                        \
+    return hipGetLastError();                                                             \
   }
-  LSP_GREEN_B(2, 3)
-  LSP_GREEN_B(2, 5)
-  LSP_GREEN_B(2, 7)
-  LSP_GREEN_B(3, 3)
-#undef LSP_GREEN_B
+  LSP_GREEN2_B(3)
+  LSP_GREEN2_B(5)
+  LSP_GREEN2_B(7)
+#undef LSP_GREEN2_B
+  if (d == 3 && W == 3) {
+    hipLaunchKernelGGL((green_batched_kernel<3, 3, kKTile>), dim3(blocks), dim3(kThreads),
+                       kResidencyLds, s, recs, map);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
 int green_shift_groups(int num_shifts) { return (num_shifts + kWaves - 1) / kWaves; }
 
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* units, bool global) {
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts) {
   const int W = 2 * p->t + 1;
-  if (global && num_shifts != 1) return hipErrorInvalidValue;
-  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, units, global);
-  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, units, global);
-  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, units, global);
-  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, units, global);
-  if (p->d == 3 && W == 5) return run_green<3, 5>(p, num_shifts, units, global);
+  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts);
+  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts);
+  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts);
+  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts);
+  if (p->d == 3 && W == 5) return run_green<3, 5>(p, num_shifts);
   return hipErrorInvalidValue;
 }
 
@@ -578,14 +657,18 @@ void green_units(int d, int n, std::vector<int>& units) {
 
 size_t green_partial_doubles(int d, int n, int t, int shifts) {
   const int W = 2 * t + 1;
+  if (d == 2) {
+    const size_t slots = (size_t)green2d_waves(n, shifts) + shifts;
+    if (W == 3) return slots * GreenLayout<2, 3>::NV;
+    if (W == 5) return slots * GreenLayout<2, 5>::NV;
+    if (W == 7) return slots * GreenLayout<2, 7>::NV;
+    return 0;
+  }
   std::vector<int> units;
   green_units(d, n, units);
   const size_t nu = units.size();
-  if (d == 2 && W == 3) return shifts * nu * GreenLayout<2, 3>::NV;
-  if (d == 2 && W == 5) return shifts * nu * GreenLayout<2, 5>::NV;
-  if (d == 2 && W == 7) return shifts * nu * GreenLayout<2, 7>::NV;
-  if (d == 3 && W == 3) return shifts * nu * GreenLayout<3, 3>::NV;
-  if (d == 3 && W == 5) return shifts * nu * GreenLayout<3, 5>::NV;
+  if (W == 3) return shifts * nu * GreenLayout<3, 3>::NV;
+  if (W == 5) return shifts * nu * GreenLayout<3, 5>::NV;
   return 0;
 }
 

@@ -49,6 +49,7 @@ int dalloc(void** ptr, size_t bytes, const char* what) {
 void free_workspace(lsp_problem* p) {
   lsp::Workspace& w = p->ws;
   dfree(w.minmax_part);
+  dfree(w.ticket);
   dfree(w.S);
   dfree(w.nS);
   dfree(w.vrange);
@@ -72,6 +73,9 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
   if (!w.minmax_part) {
     if ((rc = dalloc((void**)&w.minmax_part, sizeof(double) * 3 * lsp::kMinMaxBlocks, "minmax")))
       return rc;
+    if ((rc = dalloc((void**)&w.ticket, sizeof(unsigned), "ticket"))) return rc;
+    if (hipMemsetAsync(w.ticket, 0, sizeof(unsigned), p->stream) != hipSuccess)
+      return lsp::set_error(LSP_EHIP, "hipMemsetAsync(ticket) failed");
     if ((rc = dalloc((void**)&w.S, sizeof(double) * lsp::kMaxShifts, "S"))) return rc;
     if ((rc = dalloc((void**)&w.nS, sizeof(int), "nS"))) return rc;
     if ((rc = dalloc((void**)&w.vrange, sizeof(double) * 2, "vrange"))) return rc;
@@ -119,24 +123,16 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
 }
 
 // cw[k][delta] = w(k) cos(2 pi k delta / n), k in [0, n/2], delta in [0, W):
-// the folded cosine weights of the Green's sums (w = 1 at k = 0, n/2; else 2).
+// the folded cosine weights of the Green's sums (w = 1 at k = 0, n/2; else 2),
+// computed on the device; in 3D also the Green's-sum work units.
 int upload_cos_table(lsp_problem* p, int W) {
   const int H = p->n / 2 + 1;
-  std::vector<double> cw((size_t)H * W);
-  for (int k = 0; k < H; ++k) {
-    const double wk = (k == 0 || k == p->n / 2) ? 1.0 : 2.0;
-    for (int dl = 0; dl < W; ++dl) {
-      const long j = ((long)k * dl) % p->n;
-      cw[(size_t)k * W + dl] = wk * cos(2.0 * M_PI * (double)j / (double)p->n);
-    }
-  }
   ++p->ws_gen;
-  int rc = dalloc((void**)&p->cosT, sizeof(double) * cw.size(), "cos table");
+  int rc = dalloc((void**)&p->cosT, sizeof(double) * (size_t)H * W, "cos table");
   if (rc) return rc;
-  if (hipMemcpy(p->cosT, cw.data(), sizeof(double) * cw.size(), hipMemcpyHostToDevice) !=
-      hipSuccess)
-    return lsp::set_error(LSP_EHIP, "upload of the cosine table failed");
-  if (!p->green_units) {
+  hipError_t e = lsp::launch_cos_table(p->n, W, p->cosT, p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "cosine table");
+  if (p->d == 3 && !p->green_units) {
     std::vector<int> units;
     lsp::green_units(p->d, p->n, units);
     if ((rc = dalloc((void**)&p->green_units, sizeof(int) * units.size(), "green units")))
@@ -490,16 +486,15 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-    hipError_t e = lsp::launch_minmax(p);
+    hipError_t e = lsp::launch_minmax(p, num_shifts);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
-    int blocks = 0;
     tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
-    e = lsp::launch_green_sums(p, num_shifts, &blocks);
+    e = lsp::launch_green_sums(p, num_shifts);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_NULL);
-    e = lsp::launch_null_vectors(p, num_shifts, blocks);
+    e = lsp::launch_null_vectors(p, num_shifts);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
@@ -529,16 +524,15 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-    hipError_t e = lsp::launch_minmax(p, true);
+    hipError_t e = lsp::launch_minmax(p, 1, true);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
-    int blocks = 0;
     tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
-    e = lsp::launch_green_sums(p, 1, &blocks, true);
+    e = lsp::launch_green_sums(p, 1);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_NULL);
-    e = lsp::launch_null_vectors(p, 1, blocks);
+    e = lsp::launch_null_vectors(p, 1);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
@@ -568,10 +562,9 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
   int rc = lsp::prepare_setup(p, 1, &ns1);
   if (rc) return rc;
   const int m1 = p->m;
-  hipError_t e = lsp::launch_minmax(p);
-  int blocks = 0;
-  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns1, &blocks);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns1, blocks);
+  hipError_t e = lsp::launch_minmax(p, ns1);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns1);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns1);
   if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup (radius 1)");
   const size_t need1 = (size_t)ns1 * m1;
   if (p->nd_act1_cap < need1) {
@@ -595,9 +588,9 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
     if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "per-point C rows"))) return rc;
     p->c_rows_cap = need;
   }
-  e = lsp::launch_minmax(p);
-  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns2, &blocks);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns2, blocks);
+  e = lsp::launch_minmax(p, ns2);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns2);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns2);
   if (e == hipSuccess) e = lsp::launch_assemble_nd(p, p->nd_act1, leaf, P_dev, idx_dev);
   if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup");
   p->per_point_C = true;
@@ -668,10 +661,9 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   }
   // exact tables (shift list, Green's sums, Gram matrices, null vectors and
   // rho*(s)); the null-vector kernel also clears the fallback counter
-  int blocks = 0;
-  hipError_t e = lsp::launch_minmax(p);
-  if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts, &blocks);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, blocks, nfall);
+  hipError_t e = lsp::launch_minmax(p, num_shifts);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts);
+  if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, nfall);
   if (fused) {
     // one pass: network, check against eq. (A) and rows
     if (e == hipSuccess)

@@ -24,6 +24,7 @@ constexpr int kMinMaxBlocks = 256;  // blocks (= partials) of the min/max reduct
 struct Workspace {
   // shift list (Sec. 4.1)
   double* minmax_part = nullptr;  // [2 * kMinMaxBlocks] (min, max), then [kMinMaxBlocks] sums
+  unsigned* ticket = nullptr;     // min/max blocks' ticket counter (a multiple of kMinMaxBlocks between launches)
   double* S = nullptr;            // [kMaxShifts]
   int* nS = nullptr;              // effective |S|, device resident
   double* vrange = nullptr;       // [2] v_min, v_max
@@ -55,12 +56,15 @@ struct BatchRec {
   int64_t N;
   double invN;
   double* mm_part;   // min/max partials
+  unsigned* ticket;  // their ticket counter
   double* S;
   int* nS;
   double* vrange;
   const double* cw;  // folded cosine weights
-  const int* units;  // Green's-sum work units
+  const int* units;  // Green's-sum work units (3D)
   int nunits;
+  int gwaves;        // waves of the balanced 2D Green's launch (green2d_waves)
+  int sps;           // its steps per shift (green2d_sps), 0 in 3D
   double* part;      // Green's partial sums
   double* gtab;
   double* gamtab;
@@ -155,28 +159,34 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hip
 // count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
 hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // stencil setup stages
-// per-block (min, max) partials of v (with_sum: and per-block sums); the
-// Green's-sum launch turns them into S
-hipError_t launch_minmax(lsp_problem* p, bool with_sum = false);
+// shift list S (Sec. 4.1; global: the one shift of the non-localized method
+// of Sec. 3) into ws.S, ws.nS and ws.vrange from one launch over v (min/max
+// partials, the last block forms the list); with cw non-null the same launch
+// also writes the folded cosine table of (cos_n, cos_w)
+hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
+                             bool global, hipStream_t s, int cos_n, int cos_w, double* cw);
+hipError_t launch_minmax(lsp_problem* p, int nreq, bool global = false);
+// folded cosine table cw[k][dl] = w(k) cos(2 pi k dl / n), k in [0, n/2], dl in [0, W)
+hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s);
 // rows of per-point radius (Sec. 4.2, leaf box `leaf`, radius <= 2) from the
 // radius-1 tables act1 and the radius-2 tables of the workspace; writes P,
 // idx and the per-point C rows (p->c_rows, [N][5^d])
 hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
                               int32_t* idx);
-// Green's sums; also publishes S, |S| and (v_min, v_max) to the workspace.
-// global: S is the one shift of the non-localized method of Sec. 3 (the mean
-// of v from the sums of launch_minmax(p, true)), not the list of Sec. 4.1
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts, int* chunks_out,
-                             bool global = false);
-// work units of the Green's-sum launch for (d, n), packed (outer tile << 16) | k tile
+// Green's sums of the shifts in the workspace (num_shifts = requested |S|)
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts);
+// waves of the balanced 2D Green's launch for (n, requested |S|) and its steps
+// per shift; a function of the arguments only, shared by single and batched launches
+int green2d_waves(int n, int num_shifts);
+int green2d_sps(int n);
+// work units of the 3D Green's-sum launch for (d, n), packed (outer tile << 16) | k tile
 void green_units(int d, int n, std::vector<int>& units);
 // doubles of partial sums the Green's-sum launch writes for (d, n, t, shifts)
 size_t green_partial_doubles(int d, int n, int t, int shifts);
 // full m x m Gram matrix from the packed parity blocks (host)
 int expand_gram_host(int d, int t, const double* packed, double* full);
 // also clears *clear_counter (a kernel store, not a memset) when it is non-null
-hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int chunks,
-                               int* clear_counter = nullptr);
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int* clear_counter = nullptr);
 // P: float64 rows, or float32 rows when fp32
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // batched launches: one launch per stage over the problems of a batch; map

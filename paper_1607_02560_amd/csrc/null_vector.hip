@@ -375,11 +375,30 @@ __device__ void map_back_wide(NullShared<D, W>& sh, int cs, int wid, int lane, i
   }
 }
 
+// Partials of shift si: nblk per shift in shift order (3D), or, for the
+// balanced 2D launch of NWV waves over SPS steps per shift (sps > 0), the
+// pieces (w, si) of the waves w whose ranges meet the shift, at slots w + si.
+__device__ __forceinline__ void partial_range(int si, int nS, int nblk, int sps, int nwv,
+                                              int* first, int* count) {
+  if (sps > 0) {
+    const int64_t total = (int64_t)nS * sps;
+    const int64_t R = (total + nwv - 1) / nwv;
+    const int w0 = (int)(((int64_t)si * sps) / R);
+    const int w1 = (int)(((int64_t)(si + 1) * sps - 1) / R);
+    *first = w0 + si;
+    *count = w1 - w0 + 1;
+  } else {
+    *first = si * nblk;
+    *count = nblk;
+  }
+}
+
 template <int D, int W>
 __device__ __forceinline__ void null_body(
-    int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
-    double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
-    double* sigma_out, double* rho_out, double* actab, int* status, int* clear_counter) {
+    int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, int sps,
+    int nwv, double invN, double* gtab, double* gamtab, double* Mtab, double* alpha_out,
+    double* C_out, double* sigma_out, double* rho_out, double* actab, int* status,
+    int* clear_counter) {
   using Pa = Parity<D, W>;
   using Nb = Nbhd<D, W>;
   constexpr int NC = 1 << D;
@@ -391,7 +410,8 @@ __device__ __forceinline__ void null_body(
   constexpr int T = 64 * NC;
   __shared__ NullShared<D, W> sh;
   if (si == 0 && threadIdx.x == 0 && clear_counter) *clear_counter = 0;
-  if (si >= *nS) return;
+  const int nSv = *nS;
+  if (si >= nSv) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wid = tid >> 6;
@@ -403,10 +423,12 @@ __device__ __forceinline__ void null_body(
   constexpr int NVP = (NV <= 32) ? 32 : (NV <= 64) ? 64 : 256;
   constexpr int G = T / NVP;
   static_assert(NV <= NVP && G >= 1 && T % NVP == 0, "partial-sum groups");
-  const double* ps = part + (int64_t)si * nblk * NV;
+  int pfirst = 0, pcount = 0;
+  partial_range(si, nSv, nblk, sps, nwv, &pfirst, &pcount);
+  const double* ps = part + (int64_t)pfirst * NV;
   const int gv = tid % NVP, grp = tid / NVP;
   double acc = 0.0;
-  const int total = nblk * NV;
+  const int total = pcount * NV;
   constexpr int CHUNK = 4096;
   for (int c0 = 0; c0 < total; c0 += CHUNK) {
     const int cn = min(CHUNK, total - c0);
@@ -541,11 +563,11 @@ __device__ __forceinline__ void null_body(
 
 template <int D, int W>
 __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
-    const int* __restrict__ nS, const double* __restrict__ part, int nblk, double invN,
-    double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
+    const int* __restrict__ nS, const double* __restrict__ part, int nblk, int sps, int nwv,
+    double invN, double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
     double* sigma_out, double* rho_out, double* actab, int* status, int* clear_counter) {
-  null_body<D, W>(blockIdx.x, nS, part, nblk, invN, gtab, gamtab, Mtab, alpha_out, C_out,
-                  sigma_out, rho_out, actab, status, clear_counter);
+  null_body<D, W>(blockIdx.x, nS, part, nblk, sps, nwv, invN, gtab, gamtab, Mtab, alpha_out,
+                  C_out, sigma_out, rho_out, actab, status, clear_counter);
 }
 
 // one launch for the problems of a batch: block b solves shift map[b].y of
@@ -555,16 +577,18 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_batched_kernel(const lsp::
                                                                      const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  null_body<D, W>(it.y, r.nS, r.part, r.nunits, r.invN, r.gtab, r.gamtab, r.Mtab, r.alpha,
-                  r.Ctab, r.sigma, r.rho, r.actab, r.status, nullptr);
+  null_body<D, W>(it.y, r.nS, r.part, r.nunits, r.sps, r.gwaves, r.invN, r.gtab, r.gamtab,
+                  r.Mtab, r.alpha, r.Ctab, r.sigma, r.rho, r.actab, r.status, nullptr);
 }
 
 template <int D, int W>
-hipError_t run_null(lsp_problem* p, int num_shifts, int nblk, int* clear_counter) {
+hipError_t run_null(const lsp_problem* p, int num_shifts, int* clear_counter) {
   const double invN = 1.0 / (double)p->N;
+  const int sps = (D == 2) ? lsp::green2d_sps(p->n) : 0;
+  const int nwv = (D == 2) ? lsp::green2d_waves(p->n, num_shifts) : 0;
   hipLaunchKernelGGL((null_vector_kernel<D, W>), dim3(num_shifts), dim3(64 * (1 << D)), 0,
-                     p->stream, p->ws.nS, p->ws.green_part, nblk, invN, p->ws.gtab,
-                     p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab, p->ws.sigma,
+                     p->stream, p->ws.nS, p->ws.green_part, p->green_nunits, sps, nwv, invN,
+                     p->ws.gtab, p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab, p->ws.sigma,
                      p->ws.rho, p->ws.actab, p->ws.status, clear_counter);
   return hipGetLastError();
 }
@@ -590,13 +614,13 @@ hipError_t launch_null_batched(int d, int t, const BatchRec* recs, const int4* m
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int nblk, int* clear_counter) {
+hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int* clear_counter) {
   const int W = 2 * p->t + 1;
-  if (p->d == 2 && W == 3) return run_null<2, 3>(p, num_shifts, nblk, clear_counter);
-  if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, nblk, clear_counter);
-  if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, nblk, clear_counter);
-  if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, nblk, clear_counter);
-  if (p->d == 3 && W == 5) return run_null<3, 5>(p, num_shifts, nblk, clear_counter);
+  if (p->d == 2 && W == 3) return run_null<2, 3>(p, num_shifts, clear_counter);
+  if (p->d == 2 && W == 5) return run_null<2, 5>(p, num_shifts, clear_counter);
+  if (p->d == 2 && W == 7) return run_null<2, 7>(p, num_shifts, clear_counter);
+  if (p->d == 3 && W == 3) return run_null<3, 3>(p, num_shifts, clear_counter);
+  if (p->d == 3 && W == 5) return run_null<3, 5>(p, num_shifts, clear_counter);
   return hipErrorInvalidValue;
 }
 

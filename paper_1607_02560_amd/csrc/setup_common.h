@@ -231,4 +231,72 @@ __device__ inline void shift_list_block(const double* __restrict__ part, int nre
   __syncthreads();
 }
 
+// The one shift of the non-localized method (Sec. 3) from the min/max/sum
+// partials, computed by every thread of the block: s = mean of v, moved to
+// (2 - 4K) pi^2 (the form (4m+2) pi^2 with m = -K, 2 pi^2 above the singular
+// point) only when L + s is singular, i.e. when x = -s / (4 pi^2) lies within
+// 2^-30 max(1, |x|) of an integer K >= 0.
+// The partial sums are added in a fixed order (per thread, butterfly over
+// the lanes, waves in index order), so every thread gets the same s.
+// Results in LDS like lsp::shift_list_block: sS[0], *sNS = 1, sRange.
+template <int NT>
+__device__ inline void global_shift_block(const double* __restrict__ part, int64_t N, double* sS,
+                                          int* sNS, double* sRange, double* sRed) {
+  static_assert(NT % 64 == 0 && kMinMaxBlocks % NT == 0, "block shape");
+  constexpr int NW = NT / 64;
+  constexpr int PER = kMinMaxBlocks / NT;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wid = tid >> 6;
+  const double2* p2 = reinterpret_cast<const double2*>(part);
+  const double* ps = part + 2 * kMinMaxBlocks;
+  double2 x[PER];
+  double xs[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    x[i] = p2[tid + i * NT];
+    xs[i] = ps[tid + i * NT];
+  }
+  double lo = x[0].x, hi = x[0].y, sum = xs[0];
+#pragma unroll
+  for (int i = 1; i < PER; ++i) {
+    lo = fmin(lo, x[i].x);
+    hi = fmax(hi, x[i].y);
+    sum += xs[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o));
+    hi = fmax(hi, __shfl_xor(hi, o));
+    sum += __shfl_xor(sum, o);
+  }
+  if (lane == 0) {
+    sRed[3 * wid] = lo;
+    sRed[3 * wid + 1] = hi;
+    sRed[3 * wid + 2] = sum;
+  }
+  __syncthreads();
+  lo = sRed[0];
+  hi = sRed[1];
+  sum = sRed[2];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) {
+    lo = fmin(lo, sRed[3 * w]);
+    hi = fmax(hi, sRed[3 * w + 1]);
+    sum += sRed[3 * w + 2];
+  }
+  double s = sum / (double)N;
+  const double xr = -s / kFourPi2;
+  const double K = floor(xr + 0.5);
+  if (K >= 0.0 && fabs(xr - K) <= 0x1p-30 * fmax(1.0, fabs(xr)))
+    s = (2.0 - 4.0 * K) * kPi2;
+  if (tid == 0) {
+    sS[0] = s;
+    *sNS = 1;
+    sRange[0] = lo;
+    sRange[1] = hi;
+  }
+  __syncthreads();
+}
+
 }  // namespace lsp

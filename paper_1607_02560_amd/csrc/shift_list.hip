@@ -1,9 +1,15 @@
-// First half of the shift list S of Sec. 4.1: per-block (min, max) of the
-// potential v over a fixed grid of kMinMaxBlocks blocks (and, for the one
-// shift of the non-localized method of Sec. 3, per-block sums of v). The Green's-sum
-// kernel reduces these partials in its prologue and forms the bin centres
-// (lsp::shift_list_block), so the list never takes a launch of its own and no
-// value goes through the host.
+// The shift list S of Sec. 4.1 (and the one shift of the non-localized
+// method of Sec. 3), in one launch: a fixed grid of kMinMaxBlocks blocks writes
+// per-block (min, max) partials of the potential v (and, for the one shift,
+// per-block sums); the block that finishes last (a ticket counter that is
+// never reset: 256 tickets per launch, so it stays a multiple of 256 between
+// launches) reduces the partials, forms the bin centres, snaps them and
+// removes duplicates, and publishes S, |S| and (v_min, v_max). No value goes
+// through the host.
+//
+// The same launch can also write the folded cosine weights of the Green's
+// sums, cw[k][dl] = w(k) cos(2 pi k dl / n) for k in [0, n/2], dl in [0, W)
+// (w = 1 at k = 0 and k = n/2, else 2), one entry per thread of the grid.
 #include "setup_common.h"
 
 namespace {
@@ -66,20 +72,85 @@ __device__ __forceinline__ void minmax_body(int bx, int gx, const double* __rest
       hi = fmax(hi, wmax[w]);
       if constexpr (SUM) sum += wsum[w];
     }
-    part[2 * bx] = lo;
-    part[2 * bx + 1] = hi;
-    if constexpr (SUM) part[2 * lsp::kMinMaxBlocks + bx] = sum;
+    // device-scope atomic swaps: they take effect where the ticket's atomic
+    // does, so the last block's atomic reads see them without writing back
+    // this XCD's L2 (which a fence would); s_waitcnt below makes them
+    // complete before the ticket is drawn
+    using u64 = unsigned long long;
+    u64* pu = reinterpret_cast<u64*>(part);
+    (void)atomicExch(pu + 2 * bx, (u64)__double_as_longlong(lo));
+    (void)atomicExch(pu + 2 * bx + 1, (u64)__double_as_longlong(hi));
+    if constexpr (SUM)
+      (void)atomicExch(pu + 2 * lsp::kMinMaxBlocks + bx, (u64)__double_as_longlong(sum));
   }
 }
 
-__global__ __launch_bounds__(kThreads) void minmax_partial_kernel(const double* __restrict__ v,
-                                                                  int64_t N, double* part) {
-  minmax_body<false>(blockIdx.x, gridDim.x, v, N, part);
+// Block bx of kMinMaxBlocks: its partials, then a ticket; the block that draws
+// the last ticket of the launch forms the shift list from all partials.
+// GLOBAL: the one shift of the non-localized method (the mean of v), else the
+// nreq bin centres of Sec. 4.1.
+template <bool GLOBAL>
+__device__ __forceinline__ void minmax_shift_body(int bx, const double* __restrict__ v, int64_t N,
+                                                  double* part, unsigned* ticket, int nreq,
+                                                  double* S_out, int* nS_out,
+                                                  double* vrange_out) {
+  minmax_body<GLOBAL>(bx, lsp::kMinMaxBlocks, v, N, part);
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_s_waitcnt(0);  // the partials' swaps have completed
+    const unsigned tk = atomicAdd(ticket, 1u);
+    last = ((tk + 1u) % (unsigned)lsp::kMinMaxBlocks) == 0u;
+  }
+  __syncthreads();
+  if (!last) return;
+  // every block's partials, read with device-scope atomics (see minmax_body)
+  __shared__ double sPart[3 * lsp::kMinMaxBlocks];
+  {
+    using u64 = unsigned long long;
+    u64* pu = reinterpret_cast<u64*>(part);
+    constexpr int cnt = (GLOBAL ? 3 : 2) * lsp::kMinMaxBlocks;
+    for (int e = threadIdx.x; e < cnt; e += kThreads)
+      sPart[e] = __longlong_as_double((long long)atomicAdd(pu + e, 0ull));
+  }
+  __syncthreads();
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sNS, sWave[kWaves];
+  __shared__ double sRange[2], sRed[3 * kWaves];
+  if constexpr (GLOBAL)
+    lsp::global_shift_block<kThreads>(sPart, N, sS, &sNS, sRange, sRed);
+  else
+    lsp::shift_list_block<kThreads>(sPart, nreq, sS, &sNS, sRange, sWave, sRed);
+  const int nS = sNS;
+  for (int i = threadIdx.x; i < nS; i += kThreads) S_out[i] = sS[i];
+  if (threadIdx.x == 0) {
+    *nS_out = nS;
+    vrange_out[0] = sRange[0];
+    vrange_out[1] = sRange[1];
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void minmax_sum_partial_kernel(
-    const double* __restrict__ v, int64_t N, double* part) {
-  minmax_body<true>(blockIdx.x, gridDim.x, v, N, part);
+// cw entry e of the folded cosine table of (n, W): e = k W + dl
+__device__ __forceinline__ void cos_entry(int n, int W, int e, double* cw) {
+  const int k = e / W, dl = e - k * W;
+  const double wk = (k == 0 || k == n / 2) ? 1.0 : 2.0;
+  const int j = (int)(((int64_t)k * dl) % n);
+  cw[e] = wk * cospi(2.0 * (double)j / (double)n);
+}
+
+template <bool GLOBAL>
+__global__ __launch_bounds__(kThreads) void minmax_shift_kernel(
+    const double* __restrict__ v, int64_t N, double* part, unsigned* ticket, int nreq,
+    double* S_out, int* nS_out, double* vrange_out, int cos_n, int cos_w, double* cw) {
+  if (cw) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e < (cos_n / 2 + 1) * cos_w) cos_entry(cos_n, cos_w, e, cw);
+  }
+  minmax_shift_body<GLOBAL>(blockIdx.x, v, N, part, ticket, nreq, S_out, nS_out, vrange_out);
+}
+
+__global__ __launch_bounds__(kThreads) void cos_table_kernel(int n, int W, double* cw) {
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e < (n / 2 + 1) * W) cos_entry(n, W, e, cw);
 }
 
 // one launch for the problems of a batch: block b works for problem map[b].x
@@ -88,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void minmax_batched_kernel(const lsp::Bat
                                                                   const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  minmax_body<false>(it.y, lsp::kMinMaxBlocks, r.v, r.N, r.mm_part);
+  minmax_shift_body<false>(it.y, r.v, r.N, r.mm_part, r.ticket, r.nreq, r.S, r.nS, r.vrange);
 }
 
 }  // namespace
@@ -101,13 +172,27 @@ hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int bloc
   return hipGetLastError();
 }
 
-hipError_t launch_minmax(lsp_problem* p, bool with_sum) {
-  if (with_sum)
-    hipLaunchKernelGGL(minmax_sum_partial_kernel, dim3(kMinMaxBlocks), dim3(kThreads), 0,
-                       p->stream, p->v, p->N, p->ws.minmax_part);
+hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
+                             bool global, hipStream_t s, int cos_n, int cos_w, double* cw) {
+  if (cw && (cos_n / 2 + 1) * cos_w > kMinMaxBlocks * kThreads) return hipErrorInvalidValue;
+  if (global)
+    hipLaunchKernelGGL(minmax_shift_kernel<true>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v,
+                       N, ws.minmax_part, ws.ticket, 1, ws.S, ws.nS, ws.vrange, cos_n, cos_w, cw);
   else
-    hipLaunchKernelGGL(minmax_partial_kernel, dim3(kMinMaxBlocks), dim3(kThreads), 0, p->stream,
-                       p->v, p->N, p->ws.minmax_part);
+    hipLaunchKernelGGL(minmax_shift_kernel<false>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v,
+                       N, ws.minmax_part, ws.ticket, nreq, ws.S, ws.nS, ws.vrange, cos_n, cos_w,
+                       cw);
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax(lsp_problem* p, int nreq, bool global) {
+  return launch_shift_list(p->v, p->N, p->ws, nreq, global, p->stream, 0, 0, nullptr);
+}
+
+hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s) {
+  const int cnt = (n / 2 + 1) * W;
+  hipLaunchKernelGGL(cos_table_kernel, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                     s, n, W, cw);
   return hipGetLastError();
 }
 
