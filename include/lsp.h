@@ -25,6 +25,7 @@
 #ifndef LSP_H
 #define LSP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -238,6 +239,33 @@ int lsp_stencil_size(const lsp_problem* p);
  * CSR row pointer is j*m.
  */
 int lsp_export_pattern(int d, int n, int t, int64_t* col_host);
+
+/*
+ * Stencil setup that allocates nothing, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc. The same setup as lsp_stencil_setup (same kernels, bit-identical
+ * P rows and shift indices) for a 2D problem, without a problem object:
+ *   d, n        d must be 2; n a power of two in [8, 1024].
+ *   v_dev       N float64 potential samples (device), read in place: not
+ *               copied and not checked (it must be finite).
+ *   t, num_shifts, precision, P_dev, idx_dev  as for lsp_stencil_setup
+ *               (t = 1, 2, 3).
+ *   stream      hipStream_t for the launches (NULL = default stream).
+ * Every intermediate (shift-list partials, cosine table, Green's partial
+ * sums, per-shift tables) lives in one fixed device array of the library,
+ * lsp_static_scratch_bytes() bytes per GPU, held until the process ends; a
+ * setup needing more (large |S| with t = 3 at n = 1024) returns LSP_EINVAL
+ * before any launch. Calls no hipMalloc, hipFree or allocating routine on
+ * success. All calls on one GPU share its array, which keeps the last call's
+ * contents: calls that overlap on one GPU (different streams or threads)
+ * race. The per-shift tables are not exported; lsp_c_apply and
+ * lsp_precond_solve need a problem object. Asynchronous.
+ */
+int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_shifts,
+                             int precision, void* P_dev, int32_t* idx_dev, void* stream);
+
+/* Bytes of the fixed device array of lsp_stencil_setup_static (per GPU). */
+size_t lsp_static_scratch_bytes(void);
 
 /* ------------------------------------------------------------------------
  * Learned stencils (a surrogate beside the method; not part of the paper).

@@ -96,6 +96,9 @@ def load():
                                               c_void_p, c_void_p, P(c_int)]),
     }
     sig.update({
+        "lsp_stencil_setup_static": (c_int, [c_int, c_int, c_void_p, c_int, c_int, c_int,
+                                             c_void_p, c_void_p, c_void_p]),
+        "lsp_static_scratch_bytes": (ctypes.c_size_t, []),
         "lsp_mlp_save": (c_int, [c_void_p, ctypes.c_char_p]),
         "lsp_mlp_load": (c_int, [ctypes.c_char_p, c_int, c_void_p, P(c_void_p)]),
         "lsp_batch_create": (c_int, [c_int, c_void_p, P(c_void_p)]),
@@ -418,6 +421,33 @@ class Batch:
         ms = (ctypes.c_float * 4)()
         _check(self.lib.lsp_batch_tile(self._h, ctypes.byref(tw), cand, ms), "lsp_batch_tile")
         return tw.value, [c for c in cand if c], [float(ms[i]) for i in range(4) if cand[i]]
+
+
+def stencil_setup_static(d: int, n: int, v, t: int, num_shifts: int, P, idx=None,
+                         precision: int = LSP_FP64, stream=None):
+    """lsp_stencil_setup_static: the setup of Problem.stencil_setup for a 2D
+    potential v (device float64, N entries, read in place), allocating
+    nothing: every intermediate lives in the library's fixed device array.
+    Calls that overlap on one GPU race."""
+    import torch
+    lib = load()
+    N = n ** d
+    m = (2 * t + 1) ** d
+    _need(v, torch.float64, N, "v")
+    _need(P, torch.float32 if precision == LSP_FP32_REFINE else torch.float64, N * m, "P")
+    if idx is not None:
+        _need(idx, torch.int32, N, "idx")
+    if stream is None:
+        stream = torch.cuda.current_stream(v.device)
+    _check(lib.lsp_stencil_setup_static(d, n, _ptr(v), t, num_shifts, precision, _ptr(P),
+                                        _ptr(idx) if idx is not None else None,
+                                        ctypes.c_void_p(stream.cuda_stream)),
+           "lsp_stencil_setup_static")
+
+
+def static_scratch_bytes() -> int:
+    """Size of the fixed device array of lsp_stencil_setup_static (per GPU)."""
+    return int(load().lsp_static_scratch_bytes())
 
 
 def host_lu_solver(P_rows: np.ndarray, d: int, n: int, t: int):

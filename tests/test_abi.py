@@ -93,3 +93,19 @@ def test_export_pattern_rejects(lib):
     buf = np.zeros(10, dtype=np.int64)
     assert lib.lsp_export_pattern(2, 4, 2, buf.ctypes.data) == lsp.LSP_EINVAL
     assert lib.lsp_export_pattern(2, 8, 1, None) == lsp.LSP_EINVAL
+
+
+def test_static_setup_host_validation(lib):
+    """The allocation-free setup refuses, on the host and before any launch,
+    a dimension other than 2, bad sizes and a setup larger than its fixed
+    device array."""
+    P = ctypes.c_void_p(16)
+    v = ctypes.c_void_p(16)
+    assert lib.lsp_static_scratch_bytes() >= (1 << 20)
+    assert lib.lsp_stencil_setup_static(3, 16, v, 1, 4, 0, P, None, None) == lsp.LSP_EINVAL
+    assert lib.lsp_stencil_setup_static(2, 100, v, 1, 4, 0, P, None, None) == lsp.LSP_EINVAL
+    assert lib.lsp_stencil_setup_static(2, 16, None, 1, 4, 0, P, None, None) == lsp.LSP_EINVAL
+    assert lib.lsp_stencil_setup_static(2, 16, v, 4, 4, 0, P, None, None) == lsp.LSP_EINVAL
+    code = lib.lsp_stencil_setup_static(2, 1024, v, 3, 1024, 0, P, None, None)
+    assert code == lsp.LSP_EINVAL
+    assert b"static scratch" in lib.lsp_last_error()
