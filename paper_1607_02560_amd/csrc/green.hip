@@ -24,6 +24,7 @@
 // partial per (shift, unit), unscaled:
 // [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "setup_common.h"
@@ -404,33 +405,79 @@ __global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::Batc
 // NU = T (T + 1) / 2 tile pairs (ot <= q, row-major) per shift; one "step" is
 // one value of k_2 for the KT values k_1 = 64 ot + lane of a tile pair, so
 // every shift holds SPS = NU KT steps and the whole launch nS SPS. The launch
-// has a fixed number of waves NWV (a function of n, t and the requested |S|
+// has a fixed number of waves NWV (a function of n and the requested |S|
 // only, so a batched launch partitions a problem exactly as its own launch
 // does); wave w takes the R = ceil(nS SPS / NWV) consecutive steps from w R.
 // Along its range a lane accumulates the inner sums T[dl] of its k_1 over the
-// steps of a tile pair and, at the pair's end, folds them into its pair sums
-// (weight 1/2 on a square tile pair, the summand being symmetric in (k_1,
-// k_2)); where its range leaves a shift (or ends) the wave reduces the pair
-// sums over its lanes and writes them as the partial of (wave w, shift s), at
-// slot w + s. Slots of one shift are consecutive in w, and slot w + s is
-// unique, since each step along the ranges advances w or s. The cosine
-// values of a step are wave-uniform (scalar loads). The Nyquist column
-// k_2 = n/2 is one extra term of the piece that ends a pair in the last k
-// tile, and the corner (n/2, n/2) is added by the wave that holds a shift's
-// first step.
+// steps of one row of tile pairs (all pairs of one ot share the lane's k_1;
+// the diagonal pair ot = q is summed over its full square with halved
+// cosine weights, the summand being symmetric in (k_1, k_2)) and, where the
+// row ends, folds them into its pair sums. Where its range leaves a shift (or
+// ends) the wave sums the pair sums over its lanes (through LDS, in a fixed
+// order) and writes them as the partial of (wave w, shift s), at slot w + s.
+// Slots of one shift are consecutive in w, and slot w + s is unique, since
+// each step along the ranges advances w or s. The cosine values and k_2^2 of
+// a step are wave-uniform (scalar loads). The Nyquist column k_2 = n/2 is one
+// extra term of the piece that ends a row's last pair, and the corner
+// (n/2, n/2) is added by the wave that holds a shift's first step.
 // --------------------------------------------------------------------------
+
+// One term r = 1/(lambda_k + s), lambda_k = 4 pi^2 |k|^2 with |k|^2 exact as a
+// double: the roundings of green_r.
+__device__ __forceinline__ double green_rd(double K2, double s) {
+  const double lam = lsp::kFourPi2 * K2;
+  return lsp::rcp_cubic(lam + s);
+}
+
+// steps kd0 .. kd0 + U - 1 of a lane's inner sums (weights cws, k^2 ksq)
+template <int W, int U>
+__device__ __forceinline__ void green2d_terms(const double* __restrict__ cws,
+                                              const double* __restrict__ ksq, double K2o,
+                                              double s, double* tg, double* tq) {
+  double c[U][W], r[U], r2[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) c[u][j] = cws[u * W + j];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    r[u] = green_rd(K2o + ksq[u], s);
+    r2[u] = r[u] * r[u];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      tg[j] = fma(c[u][j], r[u], tg[j]);
+      tq[j] = fma(c[u][j], r2[u], tq[j]);
+    }
+  }
+}
+
+template <int W>
+struct Green2d {
+  static constexpr int NP = GreenLayout<2, W>::NP;
+  static constexpr int NV = GreenLayout<2, W>::NV;
+  static constexpr int P2 = pow2_at_least(NV);
+  static constexpr int RS = NV + 1;                 // LDS row of one lane (doubles, odd)
+  static constexpr size_t kWaveLds = sizeof(double) * 64 * RS;
+  static constexpr size_t kBlockLds = kWaveLds * kWaves;
+};
+
 template <int W>
 __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __restrict__ S,
                                              const int* __restrict__ nS_ptr,
                                              const double* __restrict__ cw, int n,
-                                             double* __restrict__ part) {
-  using Lay = GreenLayout<2, W>;
-  constexpr int NP = Lay::NP;
-  constexpr int NV = Lay::NV;
-  constexpr int P2 = pow2_at_least(NV);
+                                             double* __restrict__ part, double* red) {
+  using G = Green2d<W>;
+  constexpr int NP = G::NP, NV = G::NV, P2 = G::P2, RS = G::RS;
   constexpr int U = 4;
   const int lane = threadIdx.x & 63;
   const int Ht = n / 2;
+  const int H = Ht + 1;
+  const double* cwh = cw + H * W;   // halved weights (diagonal tile pairs)
+  const double* ksq = cw + 2 * H * W;
   const int KT = Ht < kTile ? Ht : kTile;
   const int T = Ht / KT;
   const int NU = T * (T + 1) / 2;
@@ -445,6 +492,7 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
   double cn[W];
 #pragma unroll
   for (int j = 0; j < W; ++j) cn[j] = cw[nyq * W + j];
+  const bool valid = lane < KT;
   while (g < gend) {
     const int si = g / SPS;
     const int send = min(gend, (si + 1) * SPS);
@@ -454,44 +502,48 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
     for (int i = 0; i < P2; ++i) a[i] = 0.0;
     const bool corner = (g == si * SPS);
     while (g < send) {
+      // the row of tile pairs (ot, q >= ot) holding step g
       const int rem = g - si * SPS;
       const int u = rem / KT;
-      const int kk = rem - u * KT;
       int ot = 0, base = 0;
       while (u >= base + (T - ot)) {
         base += T - ot;
         ++ot;
       }
-      const int q = ot + (u - base);
-      const int gstop = min(send, g - kk + KT);
-      const bool valid = lane < KT;
+      const int rstop = min(send, si * SPS + (base + T - ot) * KT);
       const int k1 = ot * KT + (valid ? lane : 0);
-      const int K2o = k1 * k1;
+      const double K2o = (double)(k1 * k1);
       double tg[W], tq[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
-      int kd = q * KT + kk;
-      const int kd_end = kd + (gstop - g);
-      for (; kd + U <= kd_end; kd += U)
-        green_terms<W, U, false>(cw + kd * W, kd, K2o, 0, true, s, tg, tq);
-      for (; kd < kd_end; ++kd) green_terms<W, 1, false>(cw + kd * W, kd, K2o, 0, true, s, tg, tq);
-      const bool square = (q == ot);
-      if (q == T - 1 && gstop - g + kk == KT) {
-        // the Nyquist column k_2 = n/2: weight 1 above the diagonal, hence 2
-        // inside a square tile pair before its 1/2
-        const double r0 = green_r(K2o + nyq * nyq, s);
-        const double r1 = (square ? 2.0 : 1.0) * r0;
-        const double r2 = r1 * r0;
+      while (g < rstop) {
+        const int rr = g - si * SPS;
+        const int uu = rr / KT;
+        const int kk = rr - uu * KT;
+        const int q = ot + (uu - base);
+        const int ustop = min(rstop, g - kk + KT);
+        const double* tab = (q == ot) ? cwh : cw;
+        int kd = q * KT + kk;
+        const int kd_end = kd + (ustop - g);
+        for (; kd + U <= kd_end; kd += U)
+          green2d_terms<W, U>(tab + kd * W, ksq + kd, K2o, s, tg, tq);
+        for (; kd < kd_end; ++kd) green2d_terms<W, 1>(tab + kd * W, ksq + kd, K2o, s, tg, tq);
+        if (q == T - 1 && ustop - g + kk == KT) {
+          // the Nyquist column k_2 = n/2, weight 1 (a diagonal pair's full
+          // square counts it twice, then halves)
+          const double r0 = green_rd(K2o + (double)(nyq * nyq), s);
+          const double r2 = r0 * r0;
 #pragma unroll
-        for (int j = 0; j < W; ++j) {
-          tg[j] = fma(cn[j], r1, tg[j]);
-          tq[j] = fma(cn[j], r2, tq[j]);
+          for (int j = 0; j < W; ++j) {
+            tg[j] = fma(cn[j], r0, tg[j]);
+            tq[j] = fma(cn[j], r2, tq[j]);
+          }
         }
+        g = ustop;
       }
-      const double half = !valid ? 0.0 : (square ? 0.5 : 1.0);
       double ck[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) ck[j] = cw[k1 * W + j] * half;
+      for (int j = 0; j < W; ++j) ck[j] = valid ? cw[k1 * W + j] : 0.0;
       int pi = 0;
 #pragma unroll
       for (int da = 0; da < W; ++da) {
@@ -502,12 +554,11 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
           ++pi;
         }
       }
-      g = gstop;
     }
     if (corner && lane == 0) {
       // the corner (n/2, n/2) once per shift: pair (da, db) gets cn[da] cn[db] r
       // (r^2 for the g*g half)
-      const double r = green_r(2 * nyq * nyq, s);
+      const double r = green_rd((double)(2 * nyq * nyq), s);
       int pi = 0;
 #pragma unroll
       for (int da = 0; da < W; ++da) {
@@ -519,11 +570,27 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
         }
       }
     }
-    const int vi = halving_sum<P2>(a, lane);
-    constexpr int kUnusedMask = (P2 >= 64) ? 0 : (P2 >= 32) ? 0x20 : (P2 >= 16) ? 0x30
-                                : (P2 >= 8) ? 0x31 : (P2 >= 4) ? 0x33 : 0x37;
-    if ((lane & kUnusedMask) == 0 && vi < NV)
-      part[((int64_t)wave + si) * NV + vi] = a[0];
+    // sum over the lanes: lane l writes its P2 values to row l of the
+    // wave's LDS area; lane l then adds value l % P2 over the rows of its
+    // group (64 / P2 groups of P2 rows), and the groups meet by lane moves
+    double* row = red + lane * RS;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) row[i] = a[i];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int col = lane % P2;
+    const int grp = lane / P2;
+    const int colr = col < NV ? col : 0;  // lanes past the last value read a valid one
+    double sum = 0.0;
+#pragma unroll
+    for (int i = 0; i < P2; ++i) sum += red[(grp * P2 + i) * RS + colr];
+    if constexpr (P2 <= 32) sum += __shfl_xor(sum, 32);
+    if constexpr (P2 <= 16) sum += __shfl_xor(sum, 16);
+    if (grp == 0 && col < NV) part[((int64_t)wave + si) * NV + col] = sum;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");  // the area is rewritten next
   }
 }
 
@@ -531,8 +598,10 @@ template <int W>
 __global__ __launch_bounds__(kThreads) void green2d_kernel(
     int nwv, const double* __restrict__ S, const int* __restrict__ nS_ptr,
     const double* __restrict__ cw, int n, double* __restrict__ part) {
-  const int wave = blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  green2d_body<W>(wave, nwv, S, nS_ptr, cw, n, part);
+  extern __shared__ double green_red[];
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = blockIdx.x * kWaves + wid;
+  green2d_body<W>(wave, nwv, S, nS_ptr, cw, n, part, green_red + wid * 64 * Green2d<W>::RS);
 }
 
 // one launch for the problems of a batch: block b holds waves 4 map[b].y ..
@@ -540,10 +609,13 @@ __global__ __launch_bounds__(kThreads) void green2d_kernel(
 template <int W>
 __global__ __launch_bounds__(kThreads) void green2d_batched_kernel(const lsp::BatchRec* recs,
                                                                    const int4* map) {
+  extern __shared__ double green_red[];
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  const int wave = it.y * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  green2d_body<W>(wave, r.gwaves, r.S, r.nS, r.cw, r.n, r.part);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wave = it.y * kWaves + wid;
+  green2d_body<W>(wave, r.gwaves, r.S, r.nS, r.cw, r.n, r.part,
+                  green_red + wid * 64 * Green2d<W>::RS);
 }
 
 // Work units with at least one term on or above the diagonal, in
@@ -569,14 +641,32 @@ void build_units(int n, std::vector<int>& units) {
   }
 }
 
+// the dynamic LDS of the 2D kernels may exceed the default per-block limit
+// (t = 3): raise it once per function
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [&]() {
+    err = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  });
+  return err;
+}
+
 template <int D, int W>
 hipError_t run_green(const lsp_problem* p, int num_shifts) {
   if constexpr (D == 2) {
+    if (hipError_t e = allow_lds(&green2d_kernel<W>, Green2d<W>::kBlockLds); e != hipSuccess)
+      return e;
     const int nwv = lsp::green2d_waves(p->n, num_shifts);
     const size_t need = (size_t)(nwv + num_shifts) * GreenLayout<2, W>::NV;
     if (need > p->ws.green_part_cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads), 0, p->stream,
-                       nwv, p->ws.S, p->ws.nS, p->cosT, p->n, p->ws.green_part);
+    // the per-wave LDS areas of the lane sums also cap the residency at two
+    // blocks (two waves per SIMD) per CU for t <= 2
+    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads),
+                       Green2d<W>::kBlockLds, p->stream, nwv, p->ws.S, p->ws.nS, p->cosT, p->n,
+                       p->ws.green_part);
   } else {
     const int nunits = p->green_nunits;
     const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
@@ -622,8 +712,11 @@ hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* 
   const int W = 2 * t + 1;
 #define LSP_GREEN2_B(W_)                                                                  \
   if (d == 2 && W == W_) {                                                                \
-    hipLaunchKernelGGL((green2d_batched_kernel<W_>), dim3(blocks), dim3(kThreads), 0, s,  \
-                       recs, map);                                                        \
+    if (hipError_t e = allow_lds(&green2d_batched_kernel<W_>, Green2d<W_>::kBlockLds);    \
+        e != hipSuccess)                                                                  \
+      return e;                                                                           \
+    hipLaunchKernelGGL((green2d_batched_kernel<W_>), dim3(blocks), dim3(kThreads),        \
+                       Green2d<W_>::kBlockLds, s, recs, map);                             \
     return hipGetLastError();                                                             \
   }
   LSP_GREEN2_B(3)

@@ -126,9 +126,9 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
 // the folded cosine weights of the Green's sums (w = 1 at k = 0, n/2; else 2),
 // computed on the device; in 3D also the Green's-sum work units.
 int upload_cos_table(lsp_problem* p, int W) {
-  const int H = p->n / 2 + 1;
   ++p->ws_gen;
-  int rc = dalloc((void**)&p->cosT, sizeof(double) * (size_t)H * W, "cos table");
+  int rc = dalloc((void**)&p->cosT, sizeof(double) * (size_t)lsp::cos_table_doubles(p->n, W),
+                  "cos table");
   if (rc) return rc;
   hipError_t e = lsp::launch_cos_table(p->n, W, p->cosT, p->stream);
   if (e != hipSuccess) return lsp::hip_check(e, "cosine table");

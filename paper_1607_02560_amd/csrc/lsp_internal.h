@@ -89,7 +89,7 @@ struct lsp_problem {
   int device = 0;
   double* v = nullptr;        // [N] potential
   double* tw = nullptr;       // [2n] exp(-2 pi i j / n), interleaved
-  double* cosT = nullptr;     // [(n/2+1) * (2t+1)] folded cosine weights of the current t
+  double* cosT = nullptr;     // [cos_table_doubles(n, 2t+1)] folded cosine weights of the current t
   double* cos_by_t[4] = {nullptr, nullptr, nullptr, nullptr};  // tables kept per t = 1..3
   int* green_units = nullptr; // [green_nunits] Green's-sum work units
   int green_nunits = 0;
@@ -166,8 +166,10 @@ hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hip
 hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
                              bool global, hipStream_t s, int cos_n, int cos_w, double* cw);
 hipError_t launch_minmax(lsp_problem* p, int nreq, bool global = false);
-// folded cosine table cw[k][dl] = w(k) cos(2 pi k dl / n), k in [0, n/2], dl in [0, W)
+// folded cosine table cw[k][dl] = w(k) cos(2 pi k dl / n), k in [0, n/2], dl in [0, W),
+// followed by the same values halved and by k^2 (as doubles) for k in [0, n/2]
 hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s);
+__host__ __device__ inline int cos_table_doubles(int n, int W) { return (n / 2 + 1) * (2 * W + 1); }
 // rows of per-point radius (Sec. 4.2, leaf box `leaf`, radius <= 2) from the
 // radius-1 tables act1 and the radius-2 tables of the workspace; writes P,
 // idx and the per-point C rows (p->c_rows, [N][5^d])

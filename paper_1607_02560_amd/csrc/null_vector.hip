@@ -215,9 +215,15 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   for (int it = 0; it < 100; ++it) {
 #pragma unroll
     for (int rep = 0; rep < 4; ++rep) {
-      double y = 0.0;
+      // three interleaved partial sums: a third of the FMA chain's latency
+      double y0 = 0.0, y1 = 0.0, y2 = 0.0;
 #pragma unroll
-      for (int qc = 0; qc < B; ++qc) y = fma(xrow[qc], xa[qc], y);
+      for (int qc = 0; qc < B; qc += 3) {
+        y0 = fma(xrow[qc], xa[qc], y0);
+        if (qc + 1 < B) y1 = fma(xrow[qc + 1], xa[qc + 1], y1);
+        if (qc + 2 < B) y2 = fma(xrow[qc + 2], xa[qc + 2], y2);
+      }
+      double y = (y0 + y1) + y2;
       y *= xscale;
 #pragma unroll
       for (int qc = 0; qc < B; ++qc) xa[qc] = bcast(y, qc);

@@ -129,12 +129,23 @@ __device__ __forceinline__ void minmax_shift_body(int bx, const double* __restri
   }
 }
 
-// cw entry e of the folded cosine table of (n, W): e = k W + dl
+// entry e of the cosine tables of (n, W), H = n/2 + 1 rows (lsp::cos_table_doubles):
+// cw[k W + dl] for e < H W, then the same values halved (the weights of a
+// diagonal tile pair of the 2D Green's sums), then k^2 as doubles
 __device__ __forceinline__ void cos_entry(int n, int W, int e, double* cw) {
-  const int k = e / W, dl = e - k * W;
+  const int H = n / 2 + 1;
+  if (e >= 2 * H * W) {
+    const int k = e - 2 * H * W;
+    cw[e] = (double)(k * k);
+    return;
+  }
+  const bool halved = e >= H * W;
+  const int eh = halved ? e - H * W : e;
+  const int k = eh / W, dl = eh - k * W;
   const double wk = (k == 0 || k == n / 2) ? 1.0 : 2.0;
   const int j = (int)(((int64_t)k * dl) % n);
-  cw[e] = wk * cospi(2.0 * (double)j / (double)n);
+  const double c = wk * cospi(2.0 * (double)j / (double)n);
+  cw[e] = halved ? 0.5 * c : c;
 }
 
 template <bool GLOBAL>
@@ -143,14 +154,14 @@ __global__ __launch_bounds__(kThreads) void minmax_shift_kernel(
     double* S_out, int* nS_out, double* vrange_out, int cos_n, int cos_w, double* cw) {
   if (cw) {
     const int e = blockIdx.x * kThreads + threadIdx.x;
-    if (e < (cos_n / 2 + 1) * cos_w) cos_entry(cos_n, cos_w, e, cw);
+    if (e < lsp::cos_table_doubles(cos_n, cos_w)) cos_entry(cos_n, cos_w, e, cw);
   }
   minmax_shift_body<GLOBAL>(blockIdx.x, v, N, part, ticket, nreq, S_out, nS_out, vrange_out);
 }
 
 __global__ __launch_bounds__(kThreads) void cos_table_kernel(int n, int W, double* cw) {
   const int e = blockIdx.x * kThreads + threadIdx.x;
-  if (e < (n / 2 + 1) * W) cos_entry(n, W, e, cw);
+  if (e < lsp::cos_table_doubles(n, W)) cos_entry(n, W, e, cw);
 }
 
 // one launch for the problems of a batch: block b works for problem map[b].x
@@ -174,7 +185,7 @@ hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int bloc
 
 hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
                              bool global, hipStream_t s, int cos_n, int cos_w, double* cw) {
-  if (cw && (cos_n / 2 + 1) * cos_w > kMinMaxBlocks * kThreads) return hipErrorInvalidValue;
+  if (cw && cos_table_doubles(cos_n, cos_w) > kMinMaxBlocks * kThreads) return hipErrorInvalidValue;
   if (global)
     hipLaunchKernelGGL(minmax_shift_kernel<true>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v,
                        N, ws.minmax_part, ws.ticket, 1, ws.S, ws.nS, ws.vrange, cos_n, cos_w, cw);
@@ -190,7 +201,7 @@ hipError_t launch_minmax(lsp_problem* p, int nreq, bool global) {
 }
 
 hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s) {
-  const int cnt = (n / 2 + 1) * W;
+  const int cnt = cos_table_doubles(n, W);
   hipLaunchKernelGGL(cos_table_kernel, dim3((cnt + kThreads - 1) / kThreads), dim3(kThreads), 0,
                      s, n, W, cw);
   return hipGetLastError();

@@ -60,7 +60,7 @@ Carve carve(int n, int t, int shifts) {
   c.S = take(sizeof(double) * lsp::kMaxShifts);
   c.nS = take(sizeof(int));
   c.vrange = take(sizeof(double) * 2);
-  c.cw = take(sizeof(double) * (size_t)(n / 2 + 1) * W);
+  c.cw = take(sizeof(double) * (size_t)lsp::cos_table_doubles(n, W));
   c.part = take(sizeof(double) * lsp::green_partial_doubles(2, n, t, shifts));
   c.gtab = take(sizeof(double) * (size_t)shifts * m);
   c.gamtab = take(sizeof(double) * (size_t)shifts * m);
