@@ -188,6 +188,75 @@ int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev,
                       int* iters, double* relres);
 
 /*
+ * Nested-dissection factors of P (Sec. 3, Fig. 1) for the device P-solve of
+ * eq. (PC): a multifrontal LU of P computed on the host (the factorisation is
+ * a host step; the solve with its factors runs every Krylov iteration, the
+ * T_NDapp term of Table 1). Fronts k = 0..nfronts-1 are in elimination order;
+ * front k eliminates the grid points F_k (a box interior or a separator
+ * piece, f[k] >= 1 of them) and couples to the later points U_k (u[k] >= 0).
+ * Every array is host memory (int64 or float64), read only during
+ * lsp_psolve_upload and not kept:
+ *   f, u            [nfronts] sizes of F_k and U_k
+ *   off_F, off_U    [nfronts+1] prefix sums of f and u (off_F[nfronts] = N,
+ *                   off_U[nfronts] = nidx_U)
+ *   idx_F           [N] the F_k concatenated (flat grid indices)
+ *   idx_Fp          [N] the same with each front's row pivoting applied
+ *                   (the row of P that pivot row i of front k came from)
+ *   idx_U           [nidx_U] the U_k concatenated
+ *   off_blk         [4*nfronts] offsets into data of front k's dense
+ *                   row-major blocks: L_FF^-1 (f x f, inverse of the unit
+ *                   lower factor), L_UF (u x f), U_FF^-1 (f x f), U_FU (f x u)
+ *   data            [ndata] the dense blocks
+ *   upd_ptr         [N+1], upd_pos [nidx_U]: for grid point i, the entries
+ *                   upd_pos[upd_ptr[i] .. upd_ptr[i+1]) are the positions in
+ *                   the concatenated U lists that name i, in front order
+ *   lev_ptr         [nlevels+1], lev_fronts [nfronts]: fronts grouped into
+ *                   levels of mutually independent fronts (one merge step of
+ *                   the boxes each); lev_fronts must list 0..nfronts-1 in
+ *                   order, so each level is a consecutive range of fronts
+ */
+typedef struct lsp_nd_factors {
+  int64_t nfronts, nlevels, nidx_U, ndata;
+  const int64_t *f, *u, *off_F, *off_U, *idx_F, *idx_Fp, *idx_U, *off_blk;
+  const double* data;
+  const int64_t *upd_ptr, *upd_pos, *lev_ptr, *lev_fronts;
+} lsp_nd_factors;
+
+/*
+ * Copy the factors to the device (replacing any earlier upload) and
+ * precompute the per-level product lists. Every offset, size and index is
+ * checked on the host first (LSP_EINVAL: nothing uploaded, an earlier upload
+ * stays in place); LSP_ENOMEM or LSP_EHIP if a device allocation or copy
+ * fails (then no factors are left). The device copy is owned by the problem and freed
+ * by the next upload or lsp_destroy. Synchronous.
+ */
+int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac);
+
+/*
+ * z = P^-1 r with the uploaded factors: level by level, a forward pass
+ * (gather of the right-hand side and of the updates earlier fronts sent,
+ * then y_F = L_FF^-1 r_F and the updates L_UF y_F) and a backward pass
+ * (x_F = U_FF^-1 (y_F - U_FU x_U)). Every sum runs in a fixed order, so
+ * the result is deterministic. r_dev, z_dev: N complex128 device arrays,
+ * must not overlap. LSP_ESTATE without an upload. Asynchronous.
+ */
+int lsp_psolve_apply(lsp_problem* p, const double* r_dev, double* z_dev);
+
+/*
+ * lsp_precond_solve with every step on the device: GMRES(restart) with the
+ * right preconditioner P^-1 C (eq. PC), C from the last setup and P^-1 from
+ * lsp_psolve_upload. One Arnoldi step (C-apply, P-solve, pseudospectral
+ * apply, classical Gram-Schmidt twice with fixed-order two-stage reductions,
+ * Givens rotation of the new Hessenberg column) is a sequence of device
+ * launches, replayed from a HIP graph captured once per column k unless
+ * LSP_GRAPHS=0; the host reads one residual estimate per step to decide
+ * whether to stop. Arguments, x0 = 0, the stopping rule and the outputs are
+ * those of lsp_precond_solve. Synchronous.
+ */
+int lsp_precond_solve_device(lsp_problem* p, const double* f_dev, double* u_dev, double rtol,
+                             int restart, int maxit, int* iters, double* relres);
+
+/*
  * Host copies of the per-shift tables of the last setup. Synchronises.
  * Any pointer may be NULL. Sizes: S_host[nS], alpha_host[nS*m], C_host[nS*m],
  * sigma_host[nS], g_host[nS*(2t+1)^d], gam_host[nS*(2t+1)^d] (g_s and
@@ -211,7 +280,8 @@ int lsp_default_num_shifts(int d, int n);
  * list), LSP_STAGE_GREEN (shift list and Green's kernel sums), LSP_STAGE_NULL (Gram matrix and null vector),
  * LSP_STAGE_ASSEMBLE (per-point rows), LSP_STAGE_SETUP (the whole
  * lsp_stencil_setup), LSP_STAGE_APPLY (lsp_ps_apply), LSP_STAGE_CAPPLY
- * (lsp_c_apply).
+ * (lsp_c_apply), LSP_STAGE_PSOLVE (lsp_psolve_apply), LSP_STAGE_ARNOLDI (one
+ * Arnoldi step of lsp_precond_solve_device, graph replay included).
  * lsp_profile(p, 1) starts recording and clears the totals; lsp_profile(p, 0)
  * stops. lsp_profile_read synchronises the stream and writes, for each stage
  * s < nstages, the summed milliseconds ms_host[s] and the number of timed
@@ -225,7 +295,9 @@ enum {
   LSP_STAGE_SETUP = 4,
   LSP_STAGE_APPLY = 5,
   LSP_STAGE_CAPPLY = 6,
-  LSP_NUM_STAGES = 7
+  LSP_STAGE_PSOLVE = 7,
+  LSP_STAGE_ARNOLDI = 8,
+  LSP_NUM_STAGES = 9
 };
 int lsp_profile(lsp_problem* p, int enable);
 int lsp_profile_read(lsp_problem* p, int nstages, double* ms_host, int* count_host);

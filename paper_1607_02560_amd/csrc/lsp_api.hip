@@ -13,16 +13,6 @@
 
 #include "lsp_internal.h"
 
-namespace lsp {
-hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
-                            double* part, hipStream_t s);
-hipError_t launch_multi_axpy(const double* V, int64_t ldv, int nv, const double* coef,
-                             double sign, double* w, int64_t N, hipStream_t s);
-hipError_t launch_scale(const double* x, double a, double* y, int64_t N, hipStream_t s);
-hipError_t launch_sub(const double* b, const double* x, double* y, int64_t N, hipStream_t s);
-int dot_blocks(int64_t N);
-}  // namespace lsp
-
 namespace {
 thread_local std::string g_last_error;
 
@@ -228,6 +218,15 @@ hipError_t run_graph(lsp_problem* p, lsp_problem::GraphCache& gc, const uint64_t
 
 namespace lsp {
 
+void free_device_gmres(lsp_problem* p) {
+  for (lsp_problem::GraphCache& gc : p->g_arnoldi) drop_graph(gc);
+  p->g_arnoldi.clear();
+  dfree(p->dk);
+  p->dk_doubles = 0;
+  if (p->dk_host) (void)hipHostFree(p->dk_host);
+  p->dk_host = nullptr;
+}
+
 bool graphs_enabled(bool by_default) {
   const char* g = getenv("LSP_GRAPHS");
   if (!g || !g[0]) return by_default;
@@ -325,6 +324,7 @@ int lsp_create(int d, int n, const double* v_dev, void* stream, lsp_problem** ou
   for (int i = 0; i < d; ++i) p->N *= n;
   p->stream = reinterpret_cast<hipStream_t>(stream);
   p->use_graphs = lsp::graphs_enabled(false);
+  p->krylov_graphs = lsp::graphs_enabled(true);
   (void)hipGetDevice(&p->device);
   int rc = LSP_OK;
   if ((rc = dalloc((void**)&p->v, sizeof(double) * p->N, "potential")) ||
@@ -389,6 +389,8 @@ void lsp_destroy(lsp_problem* p) {
   dfree(p->kry);
   dfree(p->red);
   if (p->red_host) (void)hipHostFree(p->red_host);
+  lsp::free_psolve(p);
+  lsp::free_device_gmres(p);
   free_workspace(p);
   delete p;
 }
@@ -977,6 +979,182 @@ int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev, double
   if ((rc = dots(w, 1, w, &r2))) return rc;
   if (iters) *iters = it;
   if (relres) *relres = sqrt(r2.real()) / fnorm;
+#undef LSP_HIP
+  return (est <= rtol) ? LSP_OK : LSP_NOT_CONVERGED;
+}
+
+int lsp_precond_solve_device(lsp_problem* p, const double* f_dev, double* u_dev, double rtol,
+                             int restart, int maxit, int* iters, double* relres) {
+  if (!p || !f_dev || !u_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (f_dev == u_dev) return lsp::set_error(LSP_EINVAL, "f and u must not alias");
+  if (!(rtol > 0.0) || restart < 1 || restart > 1000 || maxit < 1)
+    return lsp::set_error(LSP_EINVAL, "invalid rtol, restart or maxit");
+  if (!p->have_setup) return lsp::set_error(LSP_ESTATE, "precond_solve needs a completed setup");
+  if (!p->nd.ready) return lsp::set_error(LSP_ESTATE, "no P factors uploaded (lsp_psolve_upload)");
+  const int64_t N = p->N;
+  const int64_t N2 = 2 * N;
+  int rc = check_setup_status(p);
+  if (rc) return rc;
+  rc = check_finite_device(p, f_dev, N2, "f");
+  if (rc) return rc;
+  const int nblk = lsp::dot_blocks(N);
+  const size_t R = (size_t)restart;
+  const size_t need = (size_t)N2 * (2 * R + 3) + 2 * (R + 1) * nblk + 2 * (R + 1) * 2 +
+                      2 * R * R + 2 * R * 2 + 2 * (R + 1) + 2 * R + lsp::kScCount;
+  hipStream_t s = p->stream;
+  if (need > p->dk_doubles) {
+    (void)hipStreamSynchronize(s);
+    lsp::free_device_gmres(p);
+    if ((rc = dalloc((void**)&p->dk, sizeof(double) * need, "device GMRES workspace"))) return rc;
+    p->dk_doubles = need;
+  }
+  if (!p->dk_host &&
+      hipHostMalloc((void**)&p->dk_host, sizeof(double) * lsp::kScCount, hipHostMallocDefault) !=
+          hipSuccess) {
+    p->dk_host = nullptr;
+    return lsp::set_error(LSP_ENOMEM, "pinned host allocation failed");
+  }
+  double* V = p->dk;
+  double* Z = V + (size_t)N2 * (R + 1);
+  double* w = Z + (size_t)N2 * R;
+  double* tmp = w + N2;
+  double* part = tmp + N2;
+  double* hA = part + 2 * (R + 1) * nblk;
+  double* hB = hA + 2 * (R + 1);
+  double* H = hB + 2 * (R + 1);
+  double* cs = H + 2 * R * R;
+  double* sn = cs + 2 * R;
+  double* g = sn + 2 * R;
+  double* y = g + 2 * (R + 1);
+  double* sc = y + 2 * R;
+  double* sc_h = p->dk_host;
+
+#define LSP_HIP(call, what)                                \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return lsp::hip_check(e_, what); \
+  } while (0)
+
+  // the scalars of the last step, read back on the host
+  auto read_scalars = [&]() -> int {
+    LSP_HIP(hipMemcpyAsync(sc_h, sc, sizeof(double) * lsp::kScCount, hipMemcpyDeviceToHost, s),
+            "scalar readback");
+    LSP_HIP(hipStreamSynchronize(s), "scalar sync");
+    return LSP_OK;
+  };
+  // one Arnoldi step at column k: z_k = P^-1 C v_k, w = A z_k, two passes of
+  // classical Gram-Schmidt against v_0..v_k, the Givens update of column k
+  // and v_{k+1} = w / ||w||
+  auto step = [&](int k) -> hipError_t {
+    double* vk = V + (size_t)N2 * k;
+    double* zk = Z + (size_t)N2 * k;
+    hipError_t e = lsp::launch_c_apply(p, vk, tmp);
+    if (e == hipSuccess) e = lsp::launch_psolve(p, tmp, zk, s);
+    if (e == hipSuccess) e = lsp::launch_ps_apply(p, zk, w, s);
+    if (e == hipSuccess) e = lsp::launch_multi_dot(V, N, k + 1, w, N, part, s);
+    if (e == hipSuccess) e = lsp::launch_reduce_parts(part, nblk, k + 1, hA, s);
+    if (e == hipSuccess) e = lsp::launch_multi_axpy(V, N, k + 1, hA, -1.0, w, N, s);
+    if (e == hipSuccess) e = lsp::launch_multi_dot(V, N, k + 1, w, N, part, s);
+    if (e == hipSuccess) e = lsp::launch_reduce_parts(part, nblk, k + 1, hB, s);
+    if (e == hipSuccess) e = lsp::launch_multi_axpy(V, N, k + 1, hB, -1.0, w, N, s);
+    if (e == hipSuccess) e = lsp::launch_multi_dot(w, N, 1, w, N, part, s);
+    if (e == hipSuccess)
+      e = lsp::launch_givens(part, nblk, hA, hB, H, cs, sn, g, sc, k, restart, s);
+    if (e == hipSuccess) e = lsp::launch_scale_dev(w, sc + lsp::kScInv, V + (size_t)N2 * (k + 1), N, s);
+    return e;
+  };
+  // the step through a graph captured once per column (kept while the
+  // workspaces, the setup's radius and kind and the factors are unchanged)
+  const bool graphs = p->krylov_graphs && s != nullptr;
+  if ((int)p->g_arnoldi.size() < restart) p->g_arnoldi.resize(restart);
+  auto run_step = [&](int k) -> hipError_t {
+    if (!graphs) return step(k);
+    lsp_problem::GraphCache& gc = p->g_arnoldi[k];
+    const uint64_t key[6] = {(uint64_t)(uintptr_t)p->dk, p->ws_gen,
+                             (uint64_t)restart | ((uint64_t)k << 20),
+                             (uint64_t)p->t | ((uint64_t)p->learned << 8) |
+                                 ((uint64_t)p->per_point_C << 9),
+                             (uint64_t)(uintptr_t)p->c_rows, (uint64_t)(uintptr_t)p->nd.data};
+    bool same = gc.valid;
+    for (int i = 0; i < 6 && same; ++i) same = (gc.key[i] == key[i]);
+    if (!same) {
+      if (gc.exec) (void)hipGraphExecDestroy(gc.exec);
+      gc.exec = nullptr;
+      gc.valid = false;
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return e;
+      const hipError_t le = step(k);
+      hipGraph_t graph = nullptr;
+      e = hipStreamEndCapture(s, &graph);
+      if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : e;
+      }
+      e = hipGraphInstantiate(&gc.exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) {
+        gc.exec = nullptr;
+        return e;
+      }
+      for (int i = 0; i < 6; ++i) gc.key[i] = key[i];
+      gc.valid = true;
+    }
+    return hipGraphLaunch(gc.exec, s);
+  };
+
+  // ||f||
+  LSP_HIP(lsp::launch_multi_dot(f_dev, N, 1, f_dev, N, part, s), "dot");
+  LSP_HIP(lsp::launch_krylov_norm(part, nblk, 0, restart, sc, g, s), "norm");
+  LSP_HIP(hipMemsetAsync(u_dev, 0, sizeof(double) * N2, s), "zero u");
+  if ((rc = read_scalars())) return rc;
+  const double fnorm = sc_h[lsp::kScFnorm];
+  if (fnorm == 0.0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return LSP_OK;
+  }
+  int it = 0;
+  double est = 1.0;
+  bool first = true;
+  while (it < maxit) {
+    // r = f - A u, beta = ||r||, v_0 = r / beta
+    if (first) {
+      LSP_HIP(hipMemcpyAsync(tmp, f_dev, sizeof(double) * N2, hipMemcpyDeviceToDevice, s), "copy f");
+    } else {
+      LSP_HIP(lsp::launch_ps_apply(p, u_dev, w, s), "apply");
+      LSP_HIP(lsp::launch_sub(f_dev, w, tmp, N, s), "residual");
+    }
+    first = false;
+    LSP_HIP(lsp::launch_multi_dot(tmp, N, 1, tmp, N, part, s), "dot");
+    LSP_HIP(lsp::launch_krylov_norm(part, nblk, 1, restart, sc, g, s), "cycle start");
+    LSP_HIP(lsp::launch_scale_dev(tmp, sc + lsp::kScInv, V, N, s), "normalise");
+    if ((rc = read_scalars())) return rc;
+    est = sc_h[lsp::kScEst];
+    if (est <= rtol) break;
+    int k_used = 0;
+    for (int k = 0; k < restart; ++k) {
+      const int tk = lsp::stage_begin(p, LSP_STAGE_ARNOLDI);
+      LSP_HIP(run_step(k), "Arnoldi step");
+      lsp::stage_end(p, tk);
+      if ((rc = read_scalars())) return rc;
+      ++it;
+      k_used = k + 1;
+      est = sc_h[lsp::kScEst];
+      if (est <= rtol || it >= maxit || sc_h[lsp::kScBreak] != 0.0) break;
+    }
+    // u += Z y with y = H^-1 g
+    LSP_HIP(lsp::launch_trisolve(H, g, k_used, restart, y, s), "triangular solve");
+    LSP_HIP(lsp::launch_multi_axpy(Z, N, k_used, y, 1.0, u_dev, N, s), "update");
+    if (est <= rtol) break;
+  }
+  // true residual
+  LSP_HIP(lsp::launch_ps_apply(p, u_dev, tmp, s), "apply");
+  LSP_HIP(lsp::launch_sub(f_dev, tmp, w, N, s), "residual");
+  LSP_HIP(lsp::launch_multi_dot(w, N, 1, w, N, part, s), "dot");
+  LSP_HIP(lsp::launch_krylov_norm(part, nblk, 1, restart, sc, g, s), "residual norm");
+  if ((rc = read_scalars())) return rc;
+  if (iters) *iters = it;
+  if (relres) *relres = sc_h[lsp::kScBeta] / fnorm;
 #undef LSP_HIP
   return (est <= rtol) ? LSP_OK : LSP_NOT_CONVERGED;
 }

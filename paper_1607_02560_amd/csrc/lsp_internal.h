@@ -79,6 +79,25 @@ struct BatchRec {
   int32_t* idx;      // may be null
 };
 
+// Device P-solve: nested-dissection factors of P uploaded by
+// lsp_psolve_upload (front sizes, offsets, index lists, dense blocks), the
+// product tasks of each level and the solve's buffers.
+struct NDSolve {
+  struct Level {
+    int64_t row0 = 0, row1 = 0;   // rows of the level's fronts in the F lists
+    int64_t f_task0 = 0, u_task0 = 0;
+    int nf_tasks = 0, nu_tasks = 0;
+  };
+  int64_t *f = nullptr, *u = nullptr, *off_F = nullptr, *off_U = nullptr;
+  int64_t *idx_F = nullptr, *idx_Fp = nullptr, *idx_U = nullptr, *off_blk = nullptr;
+  int64_t *upd_ptr = nullptr, *upd_pos = nullptr;
+  double* data = nullptr;
+  int2* tasks = nullptr;           // (front, first row) of 32-row products
+  double2 *R = nullptr, *Yc = nullptr, *T = nullptr, *W = nullptr;
+  std::vector<Level> levels;
+  bool ready = false;
+};
+
 }  // namespace lsp
 
 struct lsp_problem {
@@ -122,6 +141,7 @@ struct lsp_problem {
   GraphCache g_setup, g_apply;
   uint64_t ws_gen = 1;        // bumped whenever a workspace pointer changes
   bool use_graphs = true;
+  bool krylov_graphs = true;   // capture the Arnoldi step of the device GMRES
   // per-stage event timing (lsp_profile)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;                 // created events, reused
@@ -134,6 +154,12 @@ struct lsp_problem {
   size_t kry_doubles = 0;
   double* red = nullptr;      // reduction partials
   double* red_host = nullptr; // pinned host mirror
+  // device P-solve and device GMRES
+  lsp::NDSolve nd;
+  double* dk = nullptr;       // device GMRES: basis, Hessenberg state, partials
+  size_t dk_doubles = 0;
+  double* dk_host = nullptr;  // pinned: residual estimate and flags of the last step
+  std::vector<GraphCache> g_arnoldi;  // one captured Arnoldi step per column k
 };
 
 namespace lsp {
@@ -204,6 +230,36 @@ hipError_t launch_assemble_batched(int d, int t, int tw, bool fp32, const BatchR
                                    const int4* map, int blocks, hipStream_t s);
 // preconditioner halves and Krylov helpers
 hipError_t launch_c_apply(const lsp_problem* p, const double* r, double* z);
+// ---- GMRES (krylov.hip); vectors complex128 ----
+// part[i * dot_blocks(N) + b] = block b's share of <V_i, w>, i < nv
+hipError_t launch_multi_dot(const double* V, int64_t ldv, int nv, const double* w, int64_t N,
+                            double* part, hipStream_t s);
+// w += sign * sum_i coef[i] V_i (coef: nv complex, device)
+hipError_t launch_multi_axpy(const double* V, int64_t ldv, int nv, const double* coef,
+                             double sign, double* w, int64_t N, hipStream_t s);
+hipError_t launch_scale(const double* x, double a, double* y, int64_t N, hipStream_t s);
+hipError_t launch_sub(const double* b, const double* x, double* y, int64_t N, hipStream_t s);
+int dot_blocks(int64_t N);  // <= 256
+// out[i] = sum_b part[i * nblk + b] for i < nv, in a fixed order
+hipError_t launch_reduce_parts(const double* part, int nblk, int nv, double* out, hipStream_t s);
+// slots of the device GMRES scalars
+enum { kScFnorm = 0, kScEst = 1, kScInv = 2, kScBreak = 3, kScBeta = 4, kScCount = 8 };
+// ||x|| from the partials of <x, x>: mode 0 stores ||f||; mode 1 starts a
+// restart cycle (beta, g = beta e_1, estimate, scale 1/beta)
+hipError_t launch_krylov_norm(const double* part, int nblk, int mode, int restart, double* sc,
+                              double* g, hipStream_t s);
+// Hessenberg column k from the two Gram-Schmidt passes and ||w||, rotated
+hipError_t launch_givens(const double* part, int nblk, const double* hA, const double* hB,
+                         double* H, double* cs, double* sn, double* g, double* sc, int k,
+                         int restart, hipStream_t s);
+hipError_t launch_trisolve(const double* H, const double* g, int k_used, int restart, double* y,
+                           hipStream_t s);
+hipError_t launch_scale_dev(const double* x, const double* a, double* y, int64_t N,
+                            hipStream_t s);
+// device P-solve z = P^-1 r from the uploaded factors (r, z: N complex)
+hipError_t launch_psolve(const lsp_problem* p, const double* r, double* z, hipStream_t s);
+void free_psolve(lsp_problem* p);
+void free_device_gmres(lsp_problem* p);
 // surrogate (mlp.hip)
 // device pointers of a network's BF16 weights (padded layout: W1 [H][round16(n_in)],
 // W2 [H][H], W3 [round16(n_out)][H]), FP32 biases and standardisation

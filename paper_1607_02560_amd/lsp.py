@@ -29,12 +29,21 @@ LSP_ESOLVER = -6
 LSP_ESTATE = -7
 LSP_FP64 = 0
 LSP_FP32_REFINE = 1
-STAGES = ("shifts", "green", "null", "assemble", "setup", "apply", "c_apply")
+STAGES = ("shifts", "green", "null", "assemble", "setup", "apply", "c_apply", "psolve",
+          "arnoldi")
 
 HOST_SOLVE_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double), ctypes.c_int64)
 
 _lib = None
+
+
+class NDFactors(ctypes.Structure):
+    """struct lsp_nd_factors: host arrays of the nested-dissection factors."""
+    _fields_ = [(k, ctypes.c_int64) for k in ("nfronts", "nlevels", "nidx_U", "ndata")] + \
+        [(k, ctypes.c_void_p) for k in ("f", "u", "off_F", "off_U", "idx_F", "idx_Fp", "idx_U",
+                                        "off_blk", "data", "upd_ptr", "upd_pos", "lev_ptr",
+                                        "lev_fronts")]
 
 
 class LSPError(RuntimeError):
@@ -107,6 +116,10 @@ def load():
                                             c_void_p]),
         "lsp_batch_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_batch_tile": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p]),
+        "lsp_psolve_upload": (c_int, [c_void_p, P(NDFactors)]),
+        "lsp_psolve_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
+        "lsp_precond_solve_device": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int,
+                                             c_int, P(c_int), P(c_double)]),
     })
     for name, (res, args) in sig.items():
         fn = getattr(lib_, name)
@@ -302,6 +315,40 @@ class Problem:
         if code == LSP_ESOLVER and errors:
             raise LSPError(code, "lsp_precond_solve") from errors[0]
         _check(code, "lsp_precond_solve")
+        return code, iters.value, relres.value
+
+    def psolve_upload(self, factors):
+        """Copy nested-dissection factors of P to the device: an nd.NDFactor
+        or the dict of its export()."""
+        ex = factors.export() if hasattr(factors, "export") else factors
+        keep = {}
+        for k in ("f", "u", "off_F", "off_U", "idx_F", "idx_Fp", "idx_U", "off_blk", "upd_ptr",
+                  "upd_pos", "lev_ptr", "lev_fronts"):
+            keep[k] = np.ascontiguousarray(ex[k], dtype=np.int64)
+        keep["data"] = np.ascontiguousarray(ex["data"], dtype=np.float64)
+        st = NDFactors(nfronts=keep["f"].size, nlevels=keep["lev_ptr"].size - 1,
+                       nidx_U=keep["idx_U"].size, ndata=keep["data"].size,
+                       **{k: v.ctypes.data for k, v in keep.items()})
+        _check(self.lib.lsp_psolve_upload(self._h, ctypes.byref(st)), "lsp_psolve_upload")
+
+    def psolve_apply(self, r, z):
+        """z = P^-1 r on the device with the uploaded factors."""
+        import torch
+        _need(r, torch.complex128, self.N, "r")
+        _need(z, torch.complex128, self.N, "z")
+        _check(self.lib.lsp_psolve_apply(self._h, _ptr(r), _ptr(z)), "lsp_psolve_apply")
+
+    def precond_solve_device(self, f, u, rtol=1e-8, restart=40, maxit=400):
+        """GMRES(restart) with P^-1 C, every step on the device (P^-1 from
+        psolve_upload). Returns (status, iterations, relres)."""
+        import torch
+        _need(f, torch.complex128, self.N, "f")
+        _need(u, torch.complex128, self.N, "u")
+        iters = ctypes.c_int(0)
+        relres = ctypes.c_double(0.0)
+        code = self.lib.lsp_precond_solve_device(self._h, _ptr(f), _ptr(u), rtol, restart, maxit,
+                                                 ctypes.byref(iters), ctypes.byref(relres))
+        _check(code, "lsp_precond_solve_device")
         return code, iters.value, relres.value
 
     def profile(self, enable: bool):
