@@ -21,6 +21,11 @@ compared on the same kind of field at n = 16, where the host LU of P is cheap,
 with a network trained the same way on n = 16 fields (its fallback fraction is
 reported beside the counts).
 
+A Krylov section runs GMRES(40) with every step on the device (the P-solve
+with nested-dissection factors of P computed on the host) on the 2D
+cross-profile field at n = 256, and times one Arnoldi step, graph-replayed
+and launched directly, and the P-solve alone.
+
 A third section times the batched form: 64 2D problems with n drawn from
 {64, 128, 256, 512}, set up (FP32 rows) and applied with one launch per stage
 for all of them, against the same 64 problems set up one by one.
@@ -356,6 +361,102 @@ def non_localized_section(dev, t_setup_g, N):
     return out
 
 
+def krylov_section(dev, reps):
+    """GMRES(40) with every step on the device (eq. (PC), Sec. 5), on the 2D
+    cross-profile Helmholtz field at n = 256: P rows of the uniform t = 1
+    setup and of the per-point radius (leaf box 8, t <= 2), factorised on the
+    host by nested dissection (Sec. 3, Fig. 1) and solved on the device. One
+    Arnoldi step (C-apply, P-solve, ps_apply, two Gram-Schmidt passes,
+    Givens) is timed with HIP events around each step, replayed from its
+    captured graph and launched directly; the P-solve alone is timed too."""
+    import numpy as np
+    import scipy.sparse
+    import torch
+    from paper_1607_02560_amd import lsp, nd
+    from paper_1607_02560_amd import workloads as W
+    q = W.helm2d_cross(256)
+    out = {"workload": f"{q.name}, n={q.n} (N={q.N}), |S|={q.num_shifts}, rtol 1e-8, "
+                       "restart 40", "cases": {}}
+    stream = torch.cuda.Stream(dev)
+    ft = torch.from_numpy(q.f.reshape(-1)).to(dev)
+    for label, t, leaf in (("t1", 1, None), ("nd_radius_leaf8", 2, 8)):
+        m = (2 * t + 1) ** 2
+        res = {}
+        for graphs in ("1", "0"):
+            old = os.environ.get("LSP_GRAPHS")
+            os.environ["LSP_GRAPHS"] = graphs
+            try:
+                pr = lsp.Problem(2, q.n, torch.from_numpy(q.v.reshape(-1)).to(dev),
+                                 stream=stream)
+            finally:
+                if old is None:
+                    os.environ.pop("LSP_GRAPHS", None)
+                else:
+                    os.environ["LSP_GRAPHS"] = old
+            Pq = torch.empty(q.N * m, dtype=torch.float64, device=dev)
+            if leaf:
+                pr.stencil_setup_nd(leaf, q.num_shifts, Pq)
+            else:
+                pr.stencil_setup(t, q.num_shifts, Pq)
+            torch.cuda.synchronize()
+            rows = Pq.cpu().numpy().reshape(q.N, m)
+            cols = lsp.export_pattern(2, q.n, t)
+            S = scipy.sparse.csr_matrix((rows.reshape(-1), cols.reshape(-1),
+                                         np.arange(0, q.N * m + 1, m)), shape=(q.N, q.N))
+            t0 = time.perf_counter()
+            F = nd.factor(S, 2, q.n, leaf or 8)
+            t_factor = time.perf_counter() - t0
+            ex = F.export()
+            t0 = time.perf_counter()
+            pr.psolve_upload(ex)
+            t_upload = time.perf_counter() - t0
+            ut = torch.zeros_like(ft)
+            pr.precond_solve_device(ft, ut, rtol=1e-8, restart=40, maxit=400)  # capture
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, iters, relres = pr.precond_solve_device(ft, ut, rtol=1e-8, restart=40,
+                                                          maxit=400)
+            t_solve = time.perf_counter() - t0
+            pr.profile(True)
+            pr.precond_solve_device(ft, ut, rtol=1e-8, restart=40, maxit=400)
+            rt = torch.from_numpy(q.f.reshape(-1)).to(dev)
+            zt = torch.empty_like(rt)
+            for _ in range(reps):
+                pr.psolve_apply(rt, zt)
+            prof = pr.profile_read()
+            pr.profile(False)
+            step_ms = prof["arnoldi"][0] / max(prof["arnoldi"][1], 1)
+            ps_ms = prof["psolve"][0] / max(prof["psolve"][1], 1)
+            entry = {"iterations": iters, "relres": relres, "status": code,
+                     "solve_ms": t_solve * 1e3, "arnoldi_step_ms": step_ms}
+            if graphs == "1":
+                # algorithmic bytes of one P-solve: every dense block read
+                # once, r read, z written, the index lists and the update
+                # slots read (solve buffers are reread per level: not counted)
+                nb = 8 * ex["data"].size + 32 * q.N + 8 * (3 * q.N + 2 * ex["idx_U"].size)
+                entry.update({
+                    "host_factor_s": t_factor, "upload_s": t_upload,
+                    "levels": int(ex["lev_ptr"].size - 1), "fronts": int(ex["f"].size),
+                    "factor_MB": ex["data"].nbytes / 1e6,
+                    "psolve_ms": ps_ms,
+                    "roofline_psolve": {"bound": "hbm", "achieved": nb / (ps_ms * 1e-3) / 1e9,
+                                        "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                        "frac": nb / (ps_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                        "bytes_per_call": int(nb)}})
+                # the host loop with the host solve of the same factors
+                uh = torch.zeros_like(ft)
+                t0 = time.perf_counter()
+                _, it_h, _ = pr.precond_solve(ft, uh, F.solve, rtol=1e-8, restart=40, maxit=400)
+                entry["host_loop"] = {"iterations": it_h,
+                                      "solve_ms": (time.perf_counter() - t0) * 1e3}
+                res["graph"] = entry
+            else:
+                res["direct"] = entry
+            pr.close()
+        out["cases"][label] = res
+    return out
+
+
 def section_3d_t2(dev, reps):
     """Setup with 5x5x5 stencils (t = 2) on the 3D Helmholtz field, n = 64."""
     import torch
@@ -547,6 +648,9 @@ def main():
     del P, idx
     if not args.no_extras:
         out["form_3d_t2"] = section_3d_t2(dev, args.steps)
+        print("[bench] device GMRES with the nested-dissection P-solve", file=sys.stderr,
+              flush=True)
+        out["krylov_device"] = krylov_section(dev, args.steps)
     if not args.no_learned:
         out["learned_vs_exact"] = learned_vs_exact(dev, stream, args.steps, args.train_steps)
     if not args.no_batched:

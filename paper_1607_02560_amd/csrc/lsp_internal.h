@@ -85,14 +85,20 @@ struct BatchRec {
 struct NDSolve {
   struct Level {
     int64_t row0 = 0, row1 = 0;   // rows of the level's fronts in the F lists
-    int64_t f_task0 = 0, u_task0 = 0;
-    int nf_tasks = 0, nu_tasks = 0;
+    int64_t front0 = 0;           // its fronts: front0 .. front0 + nfronts - 1
+    int nfronts = 0;
+    bool fused = false;           // one block per front, else split products
+    int64_t fmax = 0, umax = 0;   // largest f and u of the level
+    int lanes_f = 8, lanes_u = 8; // lanes per row for f and u columns
+    // split products: row tasks of f x f, u x f and f x u blocks
+    int64_t ff_task0 = 0, uf_task0 = 0, fu_task0 = 0;
+    int ff_tasks = 0, uf_tasks = 0, fu_tasks = 0;
   };
   int64_t *f = nullptr, *u = nullptr, *off_F = nullptr, *off_U = nullptr;
   int64_t *idx_F = nullptr, *idx_Fp = nullptr, *idx_U = nullptr, *off_blk = nullptr;
-  int64_t *upd_ptr = nullptr, *upd_pos = nullptr;
+  int64_t *upd_ptr = nullptr, *slot = nullptr;  // updates of a point: slots upd_ptr[i]..upd_ptr[i+1]
   double* data = nullptr;
-  int2* tasks = nullptr;           // (front, first row) of 32-row products
+  int2* tasks = nullptr;           // (front, first row) of the split products
   double2 *R = nullptr, *Yc = nullptr, *T = nullptr, *W = nullptr;
   std::vector<Level> levels;
   bool ready = false;

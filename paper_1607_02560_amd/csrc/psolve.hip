@@ -9,15 +9,23 @@
 //   forward  (levels in order):   y_F = L^-1 Pi r_F,   r_U -= L_UF y_F
 //   backward (levels reversed):   x_F = U^-1 (y_F - U_FU x_U)
 // Fronts of one level (one merge step of the boxes) do not depend on each
-// other, so a level is three launches forward (gather, two products) and two
-// backward. The updates r_U -= L_UF y_F are not scattered: each front stores
+// other, so each pass takes one level per launch (or per few launches). The
+// updates r_U -= L_UF y_F are not scattered: each front stores
 // its products L_UF y_F in the slots of its U list, and a point gathers the
 // slots that name it, in front order, when its own front is reached; every
 // sum is in a fixed order, so the solve is deterministic.
 //
-// Row products: a block of 256 threads computes 32 rows of one front, 8 lanes
-// per row striding over the columns (complex right-hand side, real factors),
-// then a butterfly over the 8 lanes.
+// Levels with many small fronts run one block per front: forward, the block
+// gathers r_F into LDS, forms y_F there (and stores it), then the updates
+// L_UF y_F; backward, it gathers x_U into LDS, forms y_F - U_FU x_U there,
+// then x_F. Levels with few large fronts split each product over blocks of
+// rows, one launch per product (the first gathers r_F itself).
+//
+// Row products: LANES lanes share a row (8 to 64, by the row length), each
+// striding over the columns with four independent loads in flight (the last
+// up to three chunks as predicated loads issued together), then a butterfly
+// over the LANES lanes. Real factors, complex vectors.
+#include <algorithm>
 #include <vector>
 
 #include "lsp_internal.h"
@@ -25,10 +33,9 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kLanesPerRow = 8;
-constexpr int kRowsPerTask = kThreads / kLanesPerRow;  // 32
-
-enum { kFwdL = 0, kFwdLUF = 1, kBwdUFU = 2, kBwdU = 3 };
+constexpr int kFusedMinFronts = 64;   // a level runs fused with at least this many fronts
+constexpr int kFusedMaxFU = 2048;     // and f + u <= this (LDS: (f + u) complex entries)
+constexpr int kSplitGatherMax = 4096; // split levels gather inside the first product up to this f
 
 struct Fac {
   const int64_t* f;
@@ -36,76 +43,286 @@ struct Fac {
   const int64_t* off_F;
   const int64_t* off_U;
   const int64_t* idx_F;
+  const int64_t* idx_Fp;
   const int64_t* idx_U;
   const int64_t* off_blk;
   const double* data;
+  const int64_t* upd_ptr;
+  const int64_t* slot;  // U-list position -> its update slot (slots grouped by point)
 };
 
-// R[row] = r[idx_Fp[row]] - sum of the update slots naming that point, for
-// the rows [r0, r1) of one level (its fronts are consecutive)
-__global__ __launch_bounds__(kThreads) void nd_gather_kernel(
-    const double2* __restrict__ r, const int64_t* __restrict__ idx_Fp,
-    const int64_t* __restrict__ upd_ptr, const int64_t* __restrict__ upd_pos,
-    const double2* __restrict__ Wslots, int64_t r0, int64_t r1, double2* __restrict__ R) {
-  const int64_t row = r0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (row >= r1) return;
-  const int64_t pt = idx_Fp[row];
+// lanes per row for rows of c columns
+int lanes_for(int64_t c) { return c >= 192 ? 64 : c >= 96 ? 32 : c >= 40 ? 16 : 8; }
+
+// r_eff = r[pt] - the updates sent to pt, which sit in the consecutive slots
+// upd_ptr[pt] .. upd_ptr[pt+1] in front order
+__device__ inline double2 gather_point(const Fac& fc, const double2* __restrict__ r,
+                                       const double2* __restrict__ Wslots, int64_t pt) {
   double2 v = r[pt];
-  for (int64_t q = upd_ptr[pt]; q < upd_ptr[pt + 1]; ++q) {
-    const double2 w = Wslots[upd_pos[q]];
+  int64_t q = fc.upd_ptr[pt];
+  const int64_t qe = fc.upd_ptr[pt + 1];
+  for (; q + 3 < qe; q += 4) {  // four loads in flight, subtracted in order
+    const double2 w0 = Wslots[q], w1 = Wslots[q + 1], w2 = Wslots[q + 2], w3 = Wslots[q + 3];
+    v.x = (((v.x - w0.x) - w1.x) - w2.x) - w3.x;
+    v.y = (((v.y - w0.y) - w1.y) - w2.y) - w3.y;
+  }
+  for (; q < qe; ++q) {
+    const double2 w = Wslots[q];
     v.x -= w.x;
     v.y -= w.y;
   }
-  R[row] = v;
+  return v;
 }
 
-// One task = 32 rows of one front's product (see MODE):
+// sum_j mrow[j] x(j) over this lane's columns j = sub, sub + LANES, ...,
+// reduced over the LANES lanes of the row (every lane gets the sum)
+template <int LANES, typename X>
+__device__ inline double2 row_dot(const double* __restrict__ mrow, int64_t cols, int sub,
+                                  bool active, X x) {
+  double ar0 = 0.0, ai0 = 0.0, ar1 = 0.0, ai1 = 0.0;
+  if (active) {
+    int64_t j = sub;
+    for (; j + 3 * LANES < cols; j += 4 * LANES) {
+      const double m0 = mrow[j], m1 = mrow[j + LANES], m2 = mrow[j + 2 * LANES],
+                   m3 = mrow[j + 3 * LANES];
+      const double2 x0 = x(j), x1 = x(j + LANES), x2 = x(j + 2 * LANES), x3 = x(j + 3 * LANES);
+      ar0 = fma(m0, x0.x, ar0);
+      ai0 = fma(m0, x0.y, ai0);
+      ar1 = fma(m1, x1.x, ar1);
+      ai1 = fma(m1, x1.y, ai1);
+      ar0 = fma(m2, x2.x, ar0);
+      ai0 = fma(m2, x2.y, ai0);
+      ar1 = fma(m3, x3.x, ar1);
+      ai1 = fma(m3, x3.y, ai1);
+    }
+    // the last (up to three) chunks: predicated loads issued together
+    const bool t0 = j < cols, t1 = j + LANES < cols, t2 = j + 2 * LANES < cols;
+    const double m0 = t0 ? mrow[j] : 0.0, m1 = t1 ? mrow[j + LANES] : 0.0,
+                 m2 = t2 ? mrow[j + 2 * LANES] : 0.0;
+    const double2 z = make_double2(0.0, 0.0);
+    const double2 x0 = t0 ? x(j) : z, x1 = t1 ? x(j + LANES) : z, x2 = t2 ? x(j + 2 * LANES) : z;
+    if (t0) {
+      ar0 = fma(m0, x0.x, ar0);
+      ai0 = fma(m0, x0.y, ai0);
+    }
+    if (t1) {
+      ar1 = fma(m1, x1.x, ar1);
+      ai1 = fma(m1, x1.y, ai1);
+    }
+    if (t2) {
+      ar0 = fma(m2, x2.x, ar0);
+      ai0 = fma(m2, x2.y, ai0);
+    }
+  }
+  double ar = ar0 + ar1, ai = ai0 + ai1;
+#pragma unroll
+  for (int o = 1; o < LANES; o <<= 1) {
+    ar += __shfl_xor(ar, o);
+    ai += __shfl_xor(ai, o);
+  }
+  return make_double2(ar, ai);
+}
+
+// forward, one block per front of the level
+template <int LANES>
+__global__ __launch_bounds__(kThreads) void nd_fwd_fused_kernel(Fac fc, int64_t front0,
+                                                                const double2* __restrict__ r,
+                                                                double2* __restrict__ Yc,
+                                                                double2* __restrict__ Wslots) {
+  extern __shared__ double2 lds[];
+  const int64_t k = front0 + blockIdx.x;
+  const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
+  double2* R = lds;
+  double2* Y = lds + f;
+  for (int64_t i = threadIdx.x; i < f; i += kThreads)
+    R[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
+  __syncthreads();
+  constexpr int G = kThreads / LANES;
+  const int g = threadIdx.x / LANES, sub = threadIdx.x % LANES;
+  const double* Linv = fc.data + fc.off_blk[4 * k];
+  for (int64_t i0 = 0; i0 < f; i0 += G) {
+    const int64_t i = i0 + g;
+    const double2 y = row_dot<LANES>(Linv + i * f, f, sub, i < f, [&](int64_t j) { return R[j]; });
+    if (sub == 0 && i < f) {
+      Y[i] = y;
+      Yc[oF + i] = y;
+    }
+  }
+  __syncthreads();
+  const double* LUF = fc.data + fc.off_blk[4 * k + 1];
+  for (int64_t i0 = 0; i0 < u; i0 += G) {
+    const int64_t i = i0 + g;
+    const double2 w = row_dot<LANES>(LUF + i * f, f, sub, i < u, [&](int64_t j) { return Y[j]; });
+    if (sub == 0 && i < u) Wslots[fc.slot[oU + i]] = w;
+  }
+}
+
+// backward, one block per front: LU lanes for the rows of U_FU (u columns),
+// LF for those of U_FF^-1 (f columns)
+template <int LU, int LF>
+__global__ __launch_bounds__(kThreads) void nd_bwd_fused_kernel(Fac fc, int64_t front0,
+                                                                const double2* __restrict__ Yc,
+                                                                double2* __restrict__ X) {
+  extern __shared__ double2 lds[];
+  const int64_t k = front0 + blockIdx.x;
+  const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
+  double2* XU = lds;
+  double2* T = lds + u;
+  for (int64_t j = threadIdx.x; j < u; j += kThreads) XU[j] = X[fc.idx_U[oU + j]];
+  __syncthreads();
+  {
+    constexpr int G = kThreads / LU;
+    const int g = threadIdx.x / LU, sub = threadIdx.x % LU;
+    const double* UFU = fc.data + fc.off_blk[4 * k + 3];
+    for (int64_t i0 = 0; i0 < f; i0 += G) {
+      const int64_t i = i0 + g;
+      const double2 h = row_dot<LU>(UFU + i * u, u, sub, i < f, [&](int64_t j) { return XU[j]; });
+      if (sub == 0 && i < f) {
+        const double2 y = Yc[oF + i];
+        T[i] = make_double2(y.x - h.x, y.y - h.y);
+      }
+    }
+  }
+  __syncthreads();
+  constexpr int G = kThreads / LF;
+  const int g = threadIdx.x / LF, sub = threadIdx.x % LF;
+  const double* Uinv = fc.data + fc.off_blk[4 * k + 2];
+  for (int64_t i0 = 0; i0 < f; i0 += G) {
+    const int64_t i = i0 + g;
+    const double2 x = row_dot<LF>(Uinv + i * f, f, sub, i < f, [&](int64_t j) { return T[j]; });
+    if (sub == 0 && i < f) X[fc.idx_F[oF + i]] = x;
+  }
+}
+
+// split levels: R[row] = r_eff of the point of F-list row `row`, rows [r0, r1)
+__global__ __launch_bounds__(kThreads) void nd_gather_kernel(Fac fc, const double2* __restrict__ r,
+                                                             const double2* __restrict__ Wslots,
+                                                             int64_t r0, int64_t r1,
+                                                             double2* __restrict__ R) {
+  const int64_t row = r0 + (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (row >= r1) return;
+  R[row] = gather_point(fc, r, Wslots, fc.idx_Fp[row]);
+}
+
+// split levels, first forward product with the gather folded in: each block
+// of a front gathers r_F of the whole front into LDS, then forms its rows of
+// y_F = L_FF^-1 r_F (f <= kSplitGatherMax)
+template <int LANES>
+__global__ __launch_bounds__(kThreads) void nd_fwd_split_kernel(Fac fc,
+                                                                const int2* __restrict__ tasks,
+                                                                const double2* __restrict__ r,
+                                                                const double2* __restrict__ Wslots,
+                                                                double2* __restrict__ Yc) {
+  extern __shared__ double2 lds[];
+  const int2 tk = tasks[blockIdx.x];
+  const int64_t k = tk.x;
+  const int64_t f = fc.f[k], oF = fc.off_F[k];
+  for (int64_t i = threadIdx.x; i < f; i += kThreads)
+    lds[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
+  __syncthreads();
+  const int sub = threadIdx.x % LANES;
+  const int64_t i = tk.y + threadIdx.x / LANES;
+  const double* Linv = fc.data + fc.off_blk[4 * k];
+  const double2 y = row_dot<LANES>(Linv + i * f, f, sub, i < f, [&](int64_t j) { return lds[j]; });
+  if (sub == 0 && i < f) Yc[oF + i] = y;
+}
+
+enum { kFwdL = 0, kFwdLUF = 1, kBwdUFU = 2, kBwdU = 3 };
+
+// split levels: one task = kThreads / LANES rows of one front's product
 //   kFwdL    Yc[oF + i] = sum_j Linv[i][j] R[oF + j]            i < f
 //   kFwdLUF  W[oU + i]  = sum_j LUF[i][j] Yc[oF + j]            i < u
 //   kBwdUFU  T[oF + i]  = Yc[oF + i] - sum_j UFU[i][j] X[U[j]]  i < f
 //   kBwdU    X[F[i]]    = sum_j Uinv[i][j] T[oF + j]            i < f
-template <int MODE>
+template <int MODE, int LANES>
 __global__ __launch_bounds__(kThreads) void nd_product_kernel(Fac fc, const int2* __restrict__ tasks,
                                                               const double2* __restrict__ in,
                                                               const double2* __restrict__ Yc,
                                                               double2* __restrict__ out) {
   const int2 tk = tasks[blockIdx.x];
-  const int k = tk.x;
-  const int64_t fk = fc.f[k], uk = fc.u[k];
-  const int64_t oF = fc.off_F[k], oU = fc.off_U[k];
+  const int64_t k = tk.x;
+  const int64_t fk = fc.f[k], uk = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
   const int64_t rows = (MODE == kFwdLUF) ? uk : fk;
-  const int64_t cols = (MODE == kFwdLUF) ? fk : (MODE == kBwdUFU ? uk : fk);
+  const int64_t cols = (MODE == kBwdUFU) ? uk : fk;
   const int blk = (MODE == kFwdL) ? 0 : (MODE == kFwdLUF) ? 1 : (MODE == kBwdU) ? 2 : 3;
   const double* mat = fc.data + fc.off_blk[4 * k + blk];
-  const int sub = threadIdx.x % kLanesPerRow;
-  const int64_t i = tk.y + threadIdx.x / kLanesPerRow;
-  double ar = 0.0, ai = 0.0;
-  if (i < rows) {
-    const double* mrow = mat + i * cols;
-    for (int64_t j = sub; j < cols; j += kLanesPerRow) {
-      const double m = mrow[j];
-      double2 x;
-      if constexpr (MODE == kBwdUFU) x = in[fc.idx_U[oU + j]];
-      else x = in[oF + j];
-      ar = fma(m, x.x, ar);
-      ai = fma(m, x.y, ai);
-    }
+  const int sub = threadIdx.x % LANES;
+  const int64_t i = tk.y + threadIdx.x / LANES;
+  const bool act = i < rows;
+  double2 acc;
+  if constexpr (MODE == kBwdUFU) {
+    const int64_t* U = fc.idx_U + oU;
+    acc = row_dot<LANES>(mat + i * cols, cols, sub, act, [&](int64_t j) { return in[U[j]]; });
+  } else {
+    acc = row_dot<LANES>(mat + i * cols, cols, sub, act, [&](int64_t j) { return in[oF + j]; });
   }
-#pragma unroll
-  for (int o = 1; o < kLanesPerRow; o <<= 1) {
-    ar += __shfl_xor(ar, o);
-    ai += __shfl_xor(ai, o);
-  }
-  if (sub != 0 || i >= rows) return;
+  if (sub != 0 || !act) return;
   if constexpr (MODE == kFwdL) {
-    out[oF + i] = make_double2(ar, ai);
+    out[oF + i] = acc;
   } else if constexpr (MODE == kFwdLUF) {
-    out[oU + i] = make_double2(ar, ai);
+    out[fc.slot[oU + i]] = acc;
   } else if constexpr (MODE == kBwdUFU) {
     const double2 y = Yc[oF + i];
-    out[oF + i] = make_double2(y.x - ar, y.y - ai);
+    out[oF + i] = make_double2(y.x - acc.x, y.y - acc.y);
   } else {
-    out[fc.idx_F[oF + i]] = make_double2(ar, ai);
+    out[fc.idx_F[oF + i]] = acc;
+  }
+}
+
+template <int MODE>
+void launch_product(int lanes, int ntasks, hipStream_t st, const Fac& fc, const int2* tasks,
+                    const double2* in, const double2* Yc, double2* out) {
+  const dim3 grid(ntasks), block(kThreads);
+  switch (lanes) {
+    case 8: hipLaunchKernelGGL((nd_product_kernel<MODE, 8>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
+    case 16: hipLaunchKernelGGL((nd_product_kernel<MODE, 16>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
+    case 32: hipLaunchKernelGGL((nd_product_kernel<MODE, 32>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
+    default: hipLaunchKernelGGL((nd_product_kernel<MODE, 64>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
+  }
+}
+
+void launch_fwd_split(int lanes, int ntasks, size_t lds, hipStream_t st, const Fac& fc,
+                      const int2* tasks, const double2* r, const double2* W, double2* Yc) {
+  const dim3 grid(ntasks), block(kThreads);
+  switch (lanes) {
+    case 8: hipLaunchKernelGGL(nd_fwd_split_kernel<8>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
+    case 16: hipLaunchKernelGGL(nd_fwd_split_kernel<16>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
+    case 32: hipLaunchKernelGGL(nd_fwd_split_kernel<32>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
+    default: hipLaunchKernelGGL(nd_fwd_split_kernel<64>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
+  }
+}
+
+void launch_fwd_fused(int lanes, int nfronts, size_t lds, hipStream_t st, const Fac& fc,
+                      int64_t front0, const double2* r, double2* Yc, double2* W) {
+  const dim3 grid(nfronts), block(kThreads);
+  switch (lanes) {
+    case 8: hipLaunchKernelGGL(nd_fwd_fused_kernel<8>, grid, block, lds, st, fc, front0, r, Yc, W); break;
+    case 16: hipLaunchKernelGGL(nd_fwd_fused_kernel<16>, grid, block, lds, st, fc, front0, r, Yc, W); break;
+    case 32: hipLaunchKernelGGL(nd_fwd_fused_kernel<32>, grid, block, lds, st, fc, front0, r, Yc, W); break;
+    default: hipLaunchKernelGGL(nd_fwd_fused_kernel<64>, grid, block, lds, st, fc, front0, r, Yc, W); break;
+  }
+}
+
+template <int LU>
+void launch_bwd_fused_lf(int lf, const dim3& grid, size_t lds, hipStream_t st, const Fac& fc,
+                         int64_t front0, const double2* Yc, double2* X) {
+  const dim3 block(kThreads);
+  switch (lf) {
+    case 8: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 8>), grid, block, lds, st, fc, front0, Yc, X); break;
+    case 16: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 16>), grid, block, lds, st, fc, front0, Yc, X); break;
+    case 32: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 32>), grid, block, lds, st, fc, front0, Yc, X); break;
+    default: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 64>), grid, block, lds, st, fc, front0, Yc, X); break;
+  }
+}
+
+void launch_bwd_fused(int lu, int lf, int nfronts, size_t lds, hipStream_t st, const Fac& fc,
+                      int64_t front0, const double2* Yc, double2* X) {
+  const dim3 grid(nfronts);
+  switch (lu) {
+    case 8: launch_bwd_fused_lf<8>(lf, grid, lds, st, fc, front0, Yc, X); break;
+    case 16: launch_bwd_fused_lf<16>(lf, grid, lds, st, fc, front0, Yc, X); break;
+    case 32: launch_bwd_fused_lf<32>(lf, grid, lds, st, fc, front0, Yc, X); break;
+    default: launch_bwd_fused_lf<64>(lf, grid, lds, st, fc, front0, Yc, X); break;
   }
 }
 
@@ -130,7 +347,7 @@ void free_psolve(lsp_problem* p) {
   NDSolve& s = p->nd;
   for (void* ptr : {(void*)s.f, (void*)s.u, (void*)s.off_F, (void*)s.off_U, (void*)s.idx_F,
                     (void*)s.idx_Fp, (void*)s.idx_U, (void*)s.off_blk, (void*)s.data,
-                    (void*)s.upd_ptr, (void*)s.upd_pos, (void*)s.tasks, (void*)s.R,
+                    (void*)s.upd_ptr, (void*)s.slot, (void*)s.tasks, (void*)s.R,
                     (void*)s.Yc, (void*)s.T, (void*)s.W})
     if (ptr) (void)hipFree(ptr);
   s = NDSolve();
@@ -138,28 +355,41 @@ void free_psolve(lsp_problem* p) {
 
 hipError_t launch_psolve(const lsp_problem* p, const double* r_dev, double* z_dev, hipStream_t st) {
   const NDSolve& s = p->nd;
-  const Fac fc{s.f, s.u, s.off_F, s.off_U, s.idx_F, s.idx_U, s.off_blk, s.data};
+  const Fac fc{s.f,    s.u,    s.off_F,   s.off_U, s.idx_F, s.idx_Fp,
+               s.idx_U, s.off_blk, s.data, s.upd_ptr, s.slot};
   const double2* r = reinterpret_cast<const double2*>(r_dev);
   double2* X = reinterpret_cast<double2*>(z_dev);
   const int L = (int)s.levels.size();
   for (int l = 0; l < L; ++l) {
     const NDSolve::Level& lv = s.levels[l];
-    const int64_t nrow = lv.row1 - lv.row0;
-    hipLaunchKernelGGL(nd_gather_kernel, dim3((unsigned)((nrow + kThreads - 1) / kThreads)),
-                       dim3(kThreads), 0, st, r, s.idx_Fp, s.upd_ptr, s.upd_pos, s.W, lv.row0,
-                       lv.row1, s.R);
-    hipLaunchKernelGGL(nd_product_kernel<kFwdL>, dim3(lv.nf_tasks), dim3(kThreads), 0, st, fc,
-                       s.tasks + lv.f_task0, s.R, s.Yc, s.Yc);
-    if (lv.nu_tasks)
-      hipLaunchKernelGGL(nd_product_kernel<kFwdLUF>, dim3(lv.nu_tasks), dim3(kThreads), 0, st,
-                         fc, s.tasks + lv.u_task0, s.Yc, s.Yc, s.W);
+    if (lv.fused) {
+      launch_fwd_fused(lv.lanes_f, lv.nfronts, sizeof(double2) * 2 * lv.fmax, st, fc, lv.front0,
+                       r, s.Yc, s.W);
+      continue;
+    }
+    if (lv.fmax <= kSplitGatherMax) {
+      launch_fwd_split(lv.lanes_f, lv.ff_tasks, sizeof(double2) * lv.fmax, st, fc,
+                       s.tasks + lv.ff_task0, r, s.W, s.Yc);
+    } else {
+      const int64_t nrow = lv.row1 - lv.row0;
+      hipLaunchKernelGGL(nd_gather_kernel, dim3((unsigned)((nrow + kThreads - 1) / kThreads)),
+                         dim3(kThreads), 0, st, fc, r, s.W, lv.row0, lv.row1, s.R);
+      launch_product<kFwdL>(lv.lanes_f, lv.ff_tasks, st, fc, s.tasks + lv.ff_task0, s.R, s.Yc,
+                            s.Yc);
+    }
+    if (lv.uf_tasks)
+      launch_product<kFwdLUF>(lv.lanes_f, lv.uf_tasks, st, fc, s.tasks + lv.uf_task0, s.Yc, s.Yc,
+                              s.W);
   }
   for (int l = L - 1; l >= 0; --l) {
     const NDSolve::Level& lv = s.levels[l];
-    hipLaunchKernelGGL(nd_product_kernel<kBwdUFU>, dim3(lv.nf_tasks), dim3(kThreads), 0, st, fc,
-                       s.tasks + lv.f_task0, X, s.Yc, s.T);
-    hipLaunchKernelGGL(nd_product_kernel<kBwdU>, dim3(lv.nf_tasks), dim3(kThreads), 0, st, fc,
-                       s.tasks + lv.f_task0, s.T, s.Yc, X);
+    if (lv.fused) {
+      launch_bwd_fused(lv.lanes_u, lv.lanes_f, lv.nfronts,
+                       sizeof(double2) * (lv.fmax + lv.umax), st, fc, lv.front0, s.Yc, X);
+      continue;
+    }
+    launch_product<kBwdUFU>(lv.lanes_u, lv.fu_tasks, st, fc, s.tasks + lv.fu_task0, X, s.Yc, s.T);
+    launch_product<kBwdU>(lv.lanes_f, lv.ff_tasks, st, fc, s.tasks + lv.ff_task0, s.T, s.Yc, X);
   }
   return hipGetLastError();
 }
@@ -171,7 +401,7 @@ extern "C" {
 int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
   if (!p || !fac) return lsp::set_error(LSP_EINVAL, "NULL argument");
   const int64_t N = p->N, nf = fac->nfronts, nl = fac->nlevels, nU = fac->nidx_U;
-  if (nf < 1 || nl < 1 || nl > nf || nU < 0 || fac->ndata < 0)
+  if (nf < 1 || nf > INT32_MAX || nl < 1 || nl > nf || nU < 0 || fac->ndata < 0)
     return lsp::set_error(LSP_EINVAL, "invalid front, level or size counts");
   if (!fac->f || !fac->u || !fac->off_F || !fac->off_U || !fac->idx_F || !fac->idx_Fp ||
       (nU && (!fac->idx_U || !fac->upd_pos)) || !fac->off_blk || (fac->ndata && !fac->data) ||
@@ -202,7 +432,20 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
   for (int64_t i = 0; i < nU; ++i)
     if (fac->idx_U[i] < 0 || fac->idx_U[i] >= N || fac->upd_pos[i] < 0 || fac->upd_pos[i] >= nU)
       return lsp::set_error(LSP_EINVAL, "update list entry out of range");
-  // levels: consecutive fronts, and the tasks of their products
+  // the forward pass writes the update of U-list position q into slot[q], so
+  // that a point's updates are consecutive; upd_pos must be a permutation
+  std::vector<int64_t> slot((size_t)nU, -1);
+  for (int64_t q = 0; q < nU; ++q) {
+    int64_t& sl = slot[(size_t)fac->upd_pos[q]];
+    if (sl >= 0) return lsp::set_error(LSP_EINVAL, "upd_pos names a U-list position twice");
+    sl = q;
+  }
+  for (int64_t pt = 0; pt < N; ++pt)
+    for (int64_t q = fac->upd_ptr[pt]; q < fac->upd_ptr[pt + 1]; ++q)
+      if (fac->idx_U[fac->upd_pos[q]] != pt)
+        return lsp::set_error(LSP_EINVAL, "upd_pos lists a U-list position of another point");
+  // levels: consecutive fronts; fused (one block per front) or split, and
+  // the row tasks of the split products
   std::vector<lsp::NDSolve::Level> levels;
   std::vector<int2> tasks;
   for (int64_t l = 0; l < nl; ++l) {
@@ -213,14 +456,33 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
     lsp::NDSolve::Level lv;
     lv.row0 = fac->off_F[a];
     lv.row1 = fac->off_F[b];
-    lv.f_task0 = (int64_t)tasks.size();
-    for (int64_t k = a; k < b; ++k)
-      for (int64_t r0 = 0; r0 < fac->f[k]; r0 += kRowsPerTask) tasks.push_back(make_int2((int)k, (int)r0));
-    lv.nf_tasks = (int)(tasks.size() - lv.f_task0);
-    lv.u_task0 = (int64_t)tasks.size();
-    for (int64_t k = a; k < b; ++k)
-      for (int64_t r0 = 0; r0 < fac->u[k]; r0 += kRowsPerTask) tasks.push_back(make_int2((int)k, (int)r0));
-    lv.nu_tasks = (int)(tasks.size() - lv.u_task0);
+    lv.front0 = a;
+    lv.nfronts = (int)(b - a);
+    for (int64_t k = a; k < b; ++k) {
+      lv.fmax = std::max(lv.fmax, fac->f[k]);
+      lv.umax = std::max(lv.umax, fac->u[k]);
+    }
+    lv.lanes_f = lanes_for(lv.fmax);
+    lv.lanes_u = lanes_for(lv.umax);
+    lv.fused = lv.nfronts >= kFusedMinFronts && lv.fmax + lv.umax <= kFusedMaxFU;
+    if (!lv.fused) {
+      auto add = [&](int lanes, bool u_rows) {
+        const int per = kThreads / lanes;
+        for (int64_t k = a; k < b; ++k) {
+          const int64_t rows = u_rows ? fac->u[k] : fac->f[k];
+          for (int64_t r0 = 0; r0 < rows; r0 += per) tasks.push_back(make_int2((int)k, (int)r0));
+        }
+      };
+      lv.ff_task0 = (int64_t)tasks.size();
+      add(lv.lanes_f, false);
+      lv.ff_tasks = (int)(tasks.size() - lv.ff_task0);
+      lv.uf_task0 = (int64_t)tasks.size();
+      add(lv.lanes_f, true);
+      lv.uf_tasks = (int)(tasks.size() - lv.uf_task0);
+      lv.fu_task0 = (int64_t)tasks.size();
+      add(lv.lanes_u, false);
+      lv.fu_tasks = (int)(tasks.size() - lv.fu_task0);
+    }
     levels.push_back(lv);
   }
   (void)hipStreamSynchronize(p->stream);
@@ -236,7 +498,7 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
       (rc = up(&s.off_blk, fac->off_blk, 4 * nf, "block offsets")) ||
       (rc = up(&s.data, fac->data, fac->ndata, "dense blocks")) ||
       (rc = up(&s.upd_ptr, fac->upd_ptr, N + 1, "update pointers")) ||
-      (rc = up(&s.upd_pos, fac->upd_pos, nU, "update positions")) ||
+      (rc = up(&s.slot, slot.data(), nU, "update slots of the U lists")) ||
       (rc = up(&s.tasks, tasks.data(), tasks.size(), "tasks")) ||
       (rc = up<double2>(&s.R, nullptr, N, "solve buffer")) ||
       (rc = up<double2>(&s.Yc, nullptr, N, "solve buffer")) ||
