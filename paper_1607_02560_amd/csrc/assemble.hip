@@ -20,9 +20,10 @@ using lsp::Pow;
 //      shift list are staged in LDS.
 //   2. Each point gets idx_j = argmin_i |S_i - v_j| (S is sorted: the two
 //      neighbours of the insertion point are compared, ties to the lower index).
-//   3. The tile's P rows are TR contiguous spans of TW*m entries; thread k
-//      writes entries VEC k .. VEC k + VEC-1 of the flattened spans with one
-//      16-byte store (2 doubles, or 4 floats for FP32 storage), evaluating
+//   3. The tile's P rows are TR contiguous spans of TW*m entries, written in
+//      steps of a whole number of points; thread k writes entries
+//      VEC k .. VEC k + VEC-1 of each step with one 16-byte store (2 doubles,
+//      or 4 floats for FP32 storage), evaluating
 //      P[j, a] = alpha_{s_j}[a] + C_{s_j}[a] (v[j + a] - s_j) for each in
 //      FP64 with one rounding per operation (then one rounding to FP32).
 // --------------------------------------------------------------------------
@@ -38,7 +39,8 @@ __device__ __forceinline__ void assemble_body(
   constexpr int HC = TW + 2 * t;
   __shared__ double halo[PL * HR * HC];
   __shared__ double sS[lsp::kMaxShifts];
-  __shared__ int sidx[TR * TW];
+  __shared__ int spM[TR * TW];     // per point: M times its shift index
+  __shared__ double spS[TR * TW];  // per point: its shift s_j
   __shared__ int soff[M];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
@@ -75,7 +77,8 @@ __device__ __forceinline__ void assemble_body(
   for (int pt = tid; pt < TR * TW; pt += 256) {
     const int r = pt / TW, c = pt % TW;
     const int best = nearest_shift(sS, nS, halo[((PL / 2) * HR + r + t) * HC + c + t]);
-    sidx[pt] = best;
+    spM[pt] = best * M;
+    spS[pt] = sS[best];
     if (idx_out) {
       const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
                                  : ((int64_t)(r0 + r) * n + c0 + c);
@@ -85,34 +88,43 @@ __device__ __forceinline__ void assemble_body(
   __syncthreads();
 
   // VEC entries per 16-byte store: 2 doubles or 4 floats (TW is a multiple of 4).
-  // Thread k starts at entry VEC k of the row span and steps by STEP entries;
-  // its (point p, offset a) advances by (STEP / M, STEP % M) with a carry, and
-  // within a store a advances by one, so no entry needs a division. soff[a]
-  // is the halo position of offset a relative to the point's (0, .., 0) corner.
+  // The TR = 1 row span of TW * M entries is written in steps of STEP entries
+  // by the first TACT = 256 - 256 % M threads, so that a step is a whole
+  // number DP of points: thread k's store always covers the same VEC offsets
+  // (entries VEC k .. VEC k + VEC - 1 of a step, possibly reaching into the
+  // next point), and their offsets, halo positions and point increments are
+  // worked out once. Per entry the loop then reads the point's shift (row
+  // base and value, both in LDS), one alpha/C pair and one halo value.
   static_assert(TR == 1, "single-row tiles");
   constexpr int VEC = 16 / (int)sizeof(PT);
   constexpr int SPAN = TW * M;
-  constexpr int STEP = VEC * 256;
-  constexpr int DP = STEP / M, DA = STEP % M;
-  static_assert(SPAN % VEC == 0, "whole stores per row span");
-  int p = (VEC * tid) / M;
-  int a = VEC * tid - p * M;
+  constexpr int TACT = 256 - 256 % M;
+  constexpr int STEP = VEC * TACT;
+  constexpr int DP = STEP / M;
+  static_assert(SPAN % VEC == 0 && STEP % M == 0, "whole stores, whole points per step");
+  if (tid >= TACT) return;
+  const int e0 = VEC * tid;
+  const int pt0 = e0 / M;
+  int aoff[VEC], hoff[VEC], pinc[VEC];
+#pragma unroll
+  for (int h = 0; h < VEC; ++h) {
+    const int e = e0 + h;
+    pinc[h] = e / M - pt0;
+    aoff[h] = e % M;
+    hoff[h] = soff[aoff[h]] + pinc[h];  // halo index = point + hoff
+  }
   const int64_t rowbase = (D == 3) ? ((((int64_t)p0 * n + r0) * n + c0) * M)
                                    : (((int64_t)r0 * n + c0) * M);
-  for (int e = VEC * tid; e < SPAN; e += STEP) {
+  int pp = pt0;
+  for (int e = e0; e < SPAN; e += STEP, pp += DP) {
     double outv[VEC];
-    int pp = p, aa = a;
 #pragma unroll
     for (int h = 0; h < VEC; ++h) {
-      const int id = sidx[pp];
-      const double s = sS[id];
-      const double2 ac = actab[id * M + aa];
-      const double va = halo[pp + soff[aa]];
+      const int q = pp + pinc[h];
+      const double s = spS[q];
+      const double2 ac = actab[spM[q] + aoff[h]];
+      const double va = halo[pp + hoff[h]];
       outv[h] = ac.x + ac.y * (va - s);
-      if (++aa == M) {
-        aa = 0;
-        ++pp;
-      }
     }
     if constexpr (VEC == 2) {
       reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(outv[0], outv[1]);
@@ -120,12 +132,6 @@ __device__ __forceinline__ void assemble_body(
       // FP32 storage: each entry is the FP64 value rounded once to nearest
       reinterpret_cast<float4*>(P + rowbase)[e >> 2] =
           make_float4((float)outv[0], (float)outv[1], (float)outv[2], (float)outv[3]);
-    }
-    p += DP;
-    a += DA;
-    if (a >= M) {
-      a -= M;
-      ++p;
     }
   }
 }
