@@ -142,8 +142,10 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
  * leaf box `leaf` needs, capped at 2. Separators are the grid planes
  * j_i = 0 mod leaf; a vertex (every coordinate on a separator) may reach
  * t = leaf, any other point reaches up to the nearest separator plane across
- * its coordinates off the separators. The shift list, s_j and the tables of
- * radius 1 and 2 are those of lsp_stencil_setup with t = 1 and t = 2.
+ * its coordinates off the separators. The shift list, s_j and the radius-2
+ * tables are those of lsp_stencil_setup with t = 2; the radius-1 tables come
+ * from the same Green's sums (their values at offsets [0,2]^d), so they equal
+ * those of lsp_stencil_setup with t = 1 up to the order of summation.
  *   leaf        leaf box size b >= 2, dividing n (Sec. 5 uses 8).
  *   num_shifts  as for lsp_stencil_setup.
  *   P_dev       output, N*5^d float64 in the layout of radius 2 (the offsets
@@ -152,7 +154,9 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
  *               other offsets.
  *   idx_dev     output, N int32 shift indices (may be NULL).
  * Needs 2t+1 = 5 < n. lsp_c_apply and lsp_precond_solve then use the rows
- * C[j, mu_j^{t_j}] of this setup; lsp_get_tables returns the radius-2 tables.
+ * C[j, mu_j^{t_j}] of this setup (read from the tables of each point's
+ * radius); lsp_get_tables returns the radius-2 tables, lsp_get_tables_nd1
+ * the radius-1 tables.
  * Launches directly (no graph). Asynchronous.
  */
 int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev,
@@ -268,6 +272,18 @@ int lsp_precond_solve_device(lsp_problem* p, const double* f_dev, double* u_dev,
 int lsp_get_tables(lsp_problem* p, int capacity, int* nS, double* S_host,
                    double* alpha_host, double* C_host, double* sigma_host,
                    double* g_host, double* gam_host, double* M_host);
+
+/*
+ * Host copies of the radius-1 tables of the last per-point-radius setup
+ * (lsp_stencil_setup_nd; the radius-2 tables are those of lsp_get_tables):
+ * alpha_host[nS*3^d], C_host[nS*3^d] (offsets of mu_0^1), sigma_host[nS],
+ * g_host[nS*3^d], gam_host[nS*3^d] (g_s and g_s * g_s at offsets [0,2]^d,
+ * lexicographic). Any pointer may be NULL. LSP_ESTATE if the last setup was
+ * not a per-point-radius setup; LSP_EINVAL if capacity < |S| (stored in
+ * *nS in every case). Synchronises.
+ */
+int lsp_get_tables_nd1(lsp_problem* p, int capacity, int* nS, double* alpha_host,
+                       double* C_host, double* sigma_host, double* g_host, double* gam_host);
 
 /* Default shift-list size used when lsp_stencil_setup gets num_shifts = 0:
  * n/16 for d = 2 and n/4 for d = 3, at least 1 (the ratios of Tables 2-9,

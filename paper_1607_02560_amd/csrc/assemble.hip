@@ -161,7 +161,9 @@ __global__ __launch_bounds__(256) void assemble_batched_kernel(const lsp::BatchR
 // C-apply: z = C r, (C r)_j = sum_a C_{s_j}[a] r[(j + a) mod n] (eq. PC), complex r.
 // Same tiling as assemble_kernel; s_j is recomputed from v and S exactly as
 // the setup assigned it, so no per-point state is kept between calls. After a
-// learned setup the C rows are per point (Crows [N][m]) instead.
+// learned setup the C rows are per point (Crows [N][m]) instead; after a
+// per-point-radius setup (leaf > 0) a point of radius 1 takes its row from
+// the radius-1 table C1 (zero outside mu_0^1).
 // --------------------------------------------------------------------------
 template <int D, int W, int TR, int TW>
 __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict__ rvec,
@@ -170,6 +172,7 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
                                                       const int* __restrict__ nS_ptr,
                                                       const double* __restrict__ Ctab,
                                                       const double* __restrict__ Crows,
+                                                      const double* __restrict__ C1, int leaf,
                                                       double2* __restrict__ z) {
   constexpr int t = (W - 1) / 2;
   constexpr int M = Pow<D, W>::v;
@@ -206,11 +209,26 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
     const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
                                : ((int64_t)(r0 + r) * n + c0 + c);
     const double* crow;
+    const double* crow1 = nullptr;  // radius-1 row of a per-point-radius setup
     if (Crows) {
       crow = Crows + g * M;  // per-point rows of a learned setup
     } else {
       const int id = nearest_shift(sS, nS, v[g]);
       crow = Ctab + (int64_t)id * M;
+      if constexpr (W == 5) {
+        if (leaf > 0) {
+          int cp[D];
+          if constexpr (D == 3) {
+            cp[0] = p0;
+            cp[1] = r0 + r;
+            cp[2] = c0 + c;
+          } else {
+            cp[0] = r0 + r;
+            cp[1] = c0 + c;
+          }
+          if (lsp::nd_radius<D>(cp, leaf, 2) < 2) crow1 = C1 + (int64_t)id * Pow<D, 3>::v;
+        }
+      }
     }
     double zr = 0.0, zi = 0.0;
 #pragma unroll
@@ -232,7 +250,20 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
         hc = c + t + da[1];
       }
       const double2 x = halo[(hp * HR + hr) * HC + hc];
-      const double ca = crow[a];
+      double ca;
+      if (crow1) {
+        // radius 1: the offsets of mu_0^1 from its table, zero elsewhere
+        bool in = true;
+        int a1 = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          in = in && da[k] >= -1 && da[k] <= 1;
+          a1 = a1 * 3 + da[k] + 1;
+        }
+        ca = in ? crow1[a1] : 0.0;
+      } else {
+        ca = crow[a];
+      }
       zr = fma(ca, x.x, zr);
       zi = fma(ca, x.y, zi);
     }
@@ -263,7 +294,7 @@ hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
   dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
   hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream,
                      reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS, p->ws.Ctab,
-                     (p->learned || p->per_point_C) ? p->c_rows : nullptr,
+                     p->learned ? p->c_rows : nullptr, p->nd1.C, p->learned ? 0 : p->nd_leaf,
                      reinterpret_cast<double2*>(z));
   return hipGetLastError();
 }

@@ -165,6 +165,15 @@ int check_setup_status(lsp_problem* p) {
     if (st[i] < 0)
       return lsp::set_error(LSP_ERESONANT, "Gram matrix of shift " + std::to_string(i) +
                                                " could not be factorised");
+  if (p->nd_leaf > 0 && p->nd1.status && ns <= p->nd1_shifts) {
+    // the radius-1 tables of a per-point-radius setup
+    e = hipMemcpy(st.data(), p->nd1.status, sizeof(int) * ns, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lsp::hip_check(e, "status copy");
+    for (int i = 0; i < ns; ++i)
+      if (st[i] < 0)
+        return lsp::set_error(LSP_ERESONANT, "radius-1 Gram matrix of shift " +
+                                                 std::to_string(i) + " could not be factorised");
+  }
   return LSP_OK;
 }
 
@@ -379,7 +388,7 @@ void lsp_destroy(lsp_problem* p) {
   p->cosT = nullptr;
   dfree(p->green_units);
   dfree(p->c_rows);
-  dfree(p->nd_act1);
+  dfree(p->nd_t1);
   dfree(p->learn_buf);
   dfree(p->flag);
   drop_graph(p->g_setup);
@@ -468,7 +477,7 @@ int prepare_setup(lsp_problem* p, int t, int* num_shifts_io) {
   p->num_shifts = num_shifts;
   p->have_setup = false;
   p->learned = false;
-  p->per_point_C = false;
+  p->nd_leaf = 0;
   *num_shifts_io = num_shifts;
   return LSP_OK;
 }
@@ -559,43 +568,52 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
   if (!P_dev) return lsp::set_error(LSP_EINVAL, "P_dev is NULL");
   if (leaf < 2 || p->n % leaf != 0)
     return lsp::set_error(LSP_EINVAL, "the leaf box must be >= 2 and divide n");
-  // radius-1 tables first (shift list, Green's sums, null vectors), kept aside
-  int ns1 = num_shifts;
-  int rc = lsp::prepare_setup(p, 1, &ns1);
+  // one shift list and one radius-2 Green's pass; the radius-2 tables go to
+  // the workspace and the radius-1 tables (their Green's values are the
+  // radius-2 pass's at offsets [0, 2]^d) to the problem's radius-1 area
+  int ns = num_shifts;
+  int rc = lsp::prepare_setup(p, 2, &ns);
   if (rc) return rc;
-  const int m1 = p->m;
-  hipError_t e = lsp::launch_minmax(p, ns1);
-  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns1);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns1);
-  if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup (radius 1)");
-  const size_t need1 = (size_t)ns1 * m1;
-  if (p->nd_act1_cap < need1) {
+  const int d = p->d;
+  const size_t m1 = (d == 2) ? 9 : 27;
+  const size_t per = sizeof(double) * (2 * m1 + m1 * m1 + 2 * m1 + 2) + sizeof(double2) * m1 +
+                     sizeof(int);
+  const size_t bytes = per * (size_t)ns + 16 * 256;
+  if (p->nd_t1_bytes < bytes) {
     (void)hipStreamSynchronize(p->stream);
-    dfree(p->nd_act1);
-    p->nd_act1_cap = 0;
-    if ((rc = dalloc((void**)&p->nd_act1, sizeof(double2) * need1, "radius-1 tables"))) return rc;
-    p->nd_act1_cap = need1;
+    dfree(p->nd_t1);
+    p->nd_t1_bytes = 0;
+    p->nd1 = lsp::NdTables1{};
+    if ((rc = dalloc((void**)&p->nd_t1, bytes, "radius-1 tables"))) return rc;
+    p->nd_t1_bytes = bytes;
+    ++p->ws_gen;
   }
-  if (hipMemcpyAsync(p->nd_act1, p->ws.actab, sizeof(double2) * need1, hipMemcpyDeviceToDevice,
-                     p->stream) != hipSuccess)
-    return lsp::set_error(LSP_EHIP, "copy of the radius-1 tables failed");
-  // then the radius-2 tables in the workspace, and the rows
-  int ns2 = num_shifts;
-  if ((rc = lsp::prepare_setup(p, 2, &ns2))) return rc;
-  const size_t need = (size_t)p->N * p->m;
-  if (p->c_rows_cap < need) {
-    (void)hipStreamSynchronize(p->stream);
-    dfree(p->c_rows);
-    p->c_rows_cap = 0;
-    if ((rc = dalloc((void**)&p->c_rows, sizeof(double) * need, "per-point C rows"))) return rc;
-    p->c_rows_cap = need;
+  {
+    size_t off = 0;
+    auto take = [&](size_t b) {
+      char* at = p->nd_t1 + off;
+      off = (off + b + 255) / 256 * 256;
+      return at;
+    };
+    const size_t S = (size_t)ns;
+    lsp::NdTables1& t1 = p->nd1;
+    t1.gtab = reinterpret_cast<double*>(take(sizeof(double) * S * m1));
+    t1.gamtab = reinterpret_cast<double*>(take(sizeof(double) * S * m1));
+    t1.Mtab = reinterpret_cast<double*>(take(sizeof(double) * S * m1 * m1));
+    t1.alpha = reinterpret_cast<double*>(take(sizeof(double) * S * m1));
+    t1.C = reinterpret_cast<double*>(take(sizeof(double) * S * m1));
+    t1.sigma = reinterpret_cast<double*>(take(sizeof(double) * S));
+    t1.rho = reinterpret_cast<double*>(take(sizeof(double) * S));
+    t1.actab = reinterpret_cast<double2*>(take(sizeof(double2) * S * m1));
+    t1.status = reinterpret_cast<int*>(take(sizeof(int) * S));
+    p->nd1_shifts = ns;
   }
-  e = lsp::launch_minmax(p, ns2);
-  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns2);
-  if (e == hipSuccess) e = lsp::launch_null_vectors(p, ns2);
-  if (e == hipSuccess) e = lsp::launch_assemble_nd(p, p->nd_act1, leaf, P_dev, idx_dev);
+  hipError_t e = lsp::launch_minmax(p, ns);
+  if (e == hipSuccess) e = lsp::launch_green_sums(p, ns);
+  if (e == hipSuccess) e = lsp::launch_null_nd(p, ns, p->nd1);
+  if (e == hipSuccess) e = lsp::launch_assemble_nd(p, p->nd1.actab, leaf, P_dev, idx_dev);
   if (e != hipSuccess) return lsp::hip_check(e, "per-point-radius setup");
-  p->per_point_C = true;
+  p->nd_leaf = leaf;
   p->have_setup = true;
   return LSP_OK;
 }
@@ -721,6 +739,39 @@ int lsp_c_apply(lsp_problem* p, const double* r_dev, double* z_dev) {
   const int rc = lsp::hip_check(lsp::launch_c_apply(p, r_dev, z_dev), "c_apply launch");
   lsp::stage_end(p, tk);
   return rc;
+}
+
+int lsp_get_tables_nd1(lsp_problem* p, int capacity, int* nS, double* alpha_host,
+                       double* C_host, double* sigma_host, double* g_host, double* gam_host) {
+  if (!p) return lsp::set_error(LSP_EINVAL, "problem is NULL");
+  if (!p->have_setup || p->nd_leaf <= 0 || !p->nd1.status)
+    return lsp::set_error(LSP_ESTATE, "the last setup was not a per-point-radius setup");
+  hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return lsp::hip_check(e, "synchronise");
+  int ns = 0;
+  e = hipMemcpy(&ns, p->ws.nS, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return lsp::hip_check(e, "read |S|");
+  if (nS) *nS = ns;
+  if (capacity < ns) return lsp::set_error(LSP_EINVAL, "capacity smaller than |S|");
+  const size_t m1 = (p->d == 2) ? 9 : 27;
+  const lsp::NdTables1& t1 = p->nd1;
+  struct Copy {
+    void* dst;
+    const void* src;
+    size_t bytes;
+  } copies[] = {
+      {alpha_host, t1.alpha, sizeof(double) * ns * m1},
+      {C_host, t1.C, sizeof(double) * ns * m1},
+      {sigma_host, t1.sigma, sizeof(double) * ns},
+      {g_host, t1.gtab, sizeof(double) * ns * m1},
+      {gam_host, t1.gamtab, sizeof(double) * ns * m1},
+  };
+  for (const Copy& c : copies) {
+    if (!c.dst || c.bytes == 0) continue;
+    e = hipMemcpy(c.dst, c.src, c.bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return lsp::hip_check(e, "table copy");
+  }
+  return check_setup_status(p);
 }
 
 int lsp_get_tables(lsp_problem* p, int capacity, int* nS, double* S_host, double* alpha_host,
@@ -1073,8 +1124,9 @@ int lsp_precond_solve_device(lsp_problem* p, const double* f_dev, double* u_dev,
     const uint64_t key[6] = {(uint64_t)(uintptr_t)p->dk, p->ws_gen,
                              (uint64_t)restart | ((uint64_t)k << 20),
                              (uint64_t)p->t | ((uint64_t)p->learned << 8) |
-                                 ((uint64_t)p->per_point_C << 9),
-                             (uint64_t)(uintptr_t)p->c_rows, (uint64_t)(uintptr_t)p->nd.data};
+                                 ((uint64_t)p->nd_leaf << 9),
+                             (uint64_t)(uintptr_t)p->c_rows ^ (uint64_t)(uintptr_t)p->nd1.C,
+                             (uint64_t)(uintptr_t)p->nd.data};
     bool same = gc.valid;
     for (int i = 0; i < 6 && same; ++i) same = (gc.key[i] == key[i]);
     if (!same) {

@@ -79,6 +79,14 @@ struct BatchRec {
   int32_t* idx;      // may be null
 };
 
+// per-point-radius setup: radius-1 tables (nS shifts, m1 = 3^d) formed from
+// the radius-2 Green's pass
+struct NdTables1 {
+  double *gtab, *gamtab, *Mtab, *alpha, *C, *sigma, *rho;
+  double2* actab;
+  int* status;
+};
+
 // Device P-solve: nested-dissection factors of P uploaded by
 // lsp_psolve_upload (front sizes, offsets, index lists, dense blocks), the
 // product tasks of each level and the solve's buffers.
@@ -129,11 +137,14 @@ struct lsp_problem {
   // table instead); c_apply reads them while `learned` is set
   bool learned = false;
   // setup with per-point radius (Sec. 4.2): C rows are per point too
-  bool per_point_C = false;
+  int nd_leaf = 0;            // leaf box of a per-point-radius setup (0: none)
   double* c_rows = nullptr;
   size_t c_rows_cap = 0;      // doubles
-  double2* nd_act1 = nullptr; // (alpha, C) of radius 1 per shift, for that setup
-  size_t nd_act1_cap = 0;     // entries
+  // radius-1 tables of that setup (one allocation, nd_t1_bytes, carved into nd1)
+  char* nd_t1 = nullptr;
+  size_t nd_t1_bytes = 0;
+  lsp::NdTables1 nd1{};
+  int nd1_shifts = 0;
   char* learn_buf = nullptr;  // rho*(s) per shift, fallback count, network in/out chunks
   size_t learn_cap = 0;       // bytes
   lsp::Workspace ws;
@@ -221,6 +232,9 @@ size_t green_partial_doubles(int d, int n, int t, int shifts);
 int expand_gram_host(int d, int t, const double* packed, double* full);
 // also clears *clear_counter (a kernel store, not a memset) when it is non-null
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int* clear_counter = nullptr);
+// one launch: the radius-2 tables into the workspace and the radius-1 tables
+// into t1, both from the radius-2 Green's partial sums (p->t must be 2)
+hipError_t launch_null_nd(lsp_problem* p, int num_shifts, const NdTables1& t1);
 // P: float64 rows, or float32 rows when fp32
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // batched launches: one launch per stage over the problems of a batch; map

@@ -9,117 +9,154 @@
 // last axis fastest); a row with t_j = 1 holds the radius-1 stencil on the
 // offsets of mu_0^1 and zeros elsewhere. Entry a of row j is
 //   alpha^{t_j}_{s_j}[a] + C^{t_j}_{s_j}[a] (v[j + a] - s_j),
-// evaluated exactly as the uniform-radius assembly does, and the row of C is
-// written beside it for the C-apply.
+// evaluated exactly as the uniform-radius assembly does.
 #include "setup_common.h"
 
 #pragma clang fp contract(off)
 
 namespace {
 
+using lsp::nd_radius;
 using lsp::nearest_shift;
 using lsp::Pow;
 
-template <int D>
-__device__ __forceinline__ int nd_radius(const int* c, int b, int tmax) {
-  int reach = b;
-  bool off = false;
-#pragma unroll
-  for (int i = 0; i < D; ++i) {
-    const int r = c[i] % b;
-    if (r != 0) {
-      off = true;
-      reach = min(reach, min(r, b - r));
-    }
-  }
-  return min(off ? reach : b, tmax);
-}
-
-// one thread per entry (j, a) of the radius-2 layout, so that consecutive
-// threads store consecutive doubles; act1/act2 are the (alpha, C) tables of
-// radius 1 and 2
-template <int D>
+// A block owns TW consecutive points of one grid row (as the uniform
+// assembly tiles): the potential on the row segment plus a halo of 2 in
+// every direction, the shift list and per point its shift and radius are
+// staged in LDS. The tile's rows form one span of TW * 5^d entries, written
+// in steps of a whole number of points by the first TACT = 256 - 256 % M2
+// threads; each thread's VEC = 2 entries per step keep their offsets, so
+// the offset-dependent parts (radius-1 position, inner flag, halo position,
+// point increment) are worked out once. P is written with 16-byte stores;
+// the C-apply reads C from the tables of the point's radius (no C rows are
+// stored).
+template <int D, int TW>
 __global__ __launch_bounds__(256) void assemble_nd_kernel(
-    const double* __restrict__ v, int n, int64_t N, const double* __restrict__ S,
+    const double* __restrict__ v, int n, int lg, const double* __restrict__ S,
     const int* __restrict__ nS_ptr, const double2* __restrict__ act1,
     const double2* __restrict__ act2, int b, double* __restrict__ P,
-    double* __restrict__ Crows, int32_t* __restrict__ idx_out) {
+    int32_t* __restrict__ idx_out) {
   constexpr int W2 = 5;
+  constexpr int t = 2;
   constexpr int M2 = Pow<D, 5>::v;
   constexpr int M1 = Pow<D, 3>::v;
-  // the shift list in LDS; then, once per point of the block's entry range
-  // (at most 256 / M2 + 2 points), its shift, s_j and radius
-  constexpr int PTS = 256 / M2 + 2;
+  constexpr int PL = (D == 3) ? W2 : 1;
+  constexpr int HR = 1 + 2 * t;
+  constexpr int HC = TW + 2 * t;
+  __shared__ double halo[PL * HR * HC];
   __shared__ double sS[lsp::kMaxShifts];
-  __shared__ double sSj[PTS];
-  __shared__ int sId[PTS], sT[PTS];
+  __shared__ double spS[TW];   // per point: s_j
+  __shared__ int spA[TW];      // per point: the row base of its table (M2 id or M1 id)
+  __shared__ int spT[TW];      // per point: t_j
+  const int tid = threadIdx.x;
   const int nS = *nS_ptr;
-  for (int i = threadIdx.x; i < nS; i += 256) sS[i] = S[i];
-  __syncthreads();
-  const int64_t e0 = (int64_t)blockIdx.x * 256;
-  const int64_t j0 = e0 / M2;
-  if (threadIdx.x < PTS) {
-    const int64_t jp = j0 + threadIdx.x;
-    if (jp < N) {
-      int cp[D];
-      int64_t rem = jp;
-#pragma unroll
-      for (int i = D - 1; i >= 0; --i) {
-        cp[i] = (int)(rem % n);
-        rem /= n;
-      }
-      const int id = nearest_shift(sS, nS, v[jp]);
-      sId[threadIdx.x] = id;
-      sSj[threadIdx.x] = sS[id];
-      sT[threadIdx.x] = nd_radius<D>(cp, b, 2);
-      if (idx_out) idx_out[jp] = id;
-    }
-  }
-  __syncthreads();
-  const int64_t e = e0 + threadIdx.x;
-  if (e >= N * M2) return;
-  const int64_t j = e / M2;
-  const int a = (int)(e - j * M2);
-  const int lp = (int)(j - j0);
-  int c[D];
-  {
-    int64_t rem = j;
-#pragma unroll
-    for (int i = D - 1; i >= 0; --i) {
-      c[i] = (int)(rem % n);
-      rem /= n;
-    }
-  }
-  const int id = sId[lp];
-  const double s = sSj[lp];
-  const int t = sT[lp];
+  const int c0 = blockIdx.x * TW;
+  const int r0 = blockIdx.y;
+  const int p0 = (D == 3) ? (int)blockIdx.z : 0;
   const int mask = n - 1;
-  int o[D];
-  {
-    int rem = a;
+  for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  for (int e = tid; e < PL * HR * HC; e += 256) {
+    const int hc = e % HC;
+    const int hr = (e / HC) % HR;
+    const int hp = e / (HC * HR);
+    const int gc = (c0 - t + hc) & mask;
+    const int gr = (r0 - t + hr) & mask;
+    int64_t g;
+    if constexpr (D == 3) {
+      const int gp = (p0 - t + hp) & mask;
+      g = ((((int64_t)gp << lg) + gr) << lg) + gc;
+    } else {
+      g = ((int64_t)gr << lg) + gc;
+    }
+    halo[e] = v[g];
+  }
+  __syncthreads();
+  const int64_t pbase = (D == 3) ? ((((int64_t)p0 << lg) + r0) << lg) + c0
+                                 : ((int64_t)r0 << lg) + c0;
+  for (int pt = tid; pt < TW; pt += 256) {
+    const int id = nearest_shift(sS, nS, halo[((PL / 2) * HR + t) * HC + pt + t]);
+    int cp[D];
+    if constexpr (D == 3) {
+      cp[0] = p0;
+      cp[1] = r0;
+      cp[2] = c0 + pt;
+    } else {
+      cp[0] = r0;
+      cp[1] = c0 + pt;
+    }
+    const int tj = nd_radius<D>(cp, b, 2);
+    spS[pt] = sS[id];
+    spT[pt] = tj;
+    spA[pt] = (tj >= 2) ? id * M2 : id * M1;
+    if (idx_out) idx_out[pbase + pt] = id;
+  }
+  __syncthreads();
+
+  constexpr int VEC = 2;
+  constexpr int SPAN = TW * M2;
+  constexpr int TACT = 256 - 256 % M2;
+  constexpr int STEP = VEC * TACT;
+  constexpr int DP = STEP / M2;
+  static_assert(SPAN % VEC == 0 && STEP % M2 == 0, "whole stores, whole points per step");
+  if (tid >= TACT) return;
+  const int e0 = VEC * tid;
+  const int pt0 = e0 / M2;
+  int a2[VEC], a1[VEC], hoff[VEC], pinc[VEC];
+  bool inner[VEC];
+#pragma unroll
+  for (int h = 0; h < VEC; ++h) {
+    const int e = e0 + h;
+    pinc[h] = e / M2 - pt0;
+    const int a = e % M2;
+    a2[h] = a;
+    // offsets of a (last axis fastest), its radius-1 index and halo position
+    int rem = a, i1 = 0, mul = 1, ho = 0, hm = 1;
+    bool in = true;
 #pragma unroll
     for (int i = D - 1; i >= 0; --i) {
-      o[i] = rem % W2 - 2;
+      const int o = rem % W2;  // o - 2 in [-2, 2]
       rem /= W2;
+      in = in && o >= 1 && o <= 3;
+      i1 += (o - 1) * mul;
+      mul *= 3;
+      ho += o * hm;
+      hm *= (i == D - 1) ? HC : HR;
     }
+    inner[h] = in;
+    a1[h] = in ? i1 : 0;
+    hoff[h] = ho + pinc[h];  // halo index = point + hoff
   }
-  bool inner = true;
-  int a1 = 0;
-  int64_t g = 0;
+  const int64_t rowbase = pbase * M2;
+  int pp = pt0;
+  for (int e = e0; e < SPAN; e += STEP, pp += DP) {
+    double pv[VEC];
 #pragma unroll
-  for (int i = 0; i < D; ++i) {
-    inner = inner && o[i] >= -1 && o[i] <= 1;
-    a1 = a1 * 3 + o[i] + 1;
-    g = g * n + ((c[i] + o[i]) & mask);
+    for (int h = 0; h < VEC; ++h) {
+      const int q = pp + pinc[h];
+      const int tj = spT[q];
+      pv[h] = 0.0;
+      if (tj >= 2 || inner[h]) {
+        const double2 ac = (tj >= 2) ? act2[spA[q] + a2[h]] : act1[spA[q] + a1[h]];
+        const double va = halo[pp + hoff[h]];
+        pv[h] = ac.x + ac.y * (va - spS[q]);
+      }
+    }
+    reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(pv[0], pv[1]);
   }
-  double pv = 0.0, cv = 0.0;
-  if (t >= 2 || inner) {
-    const double2 ac = (t >= 2) ? act2[(int64_t)id * M2 + a] : act1[(int64_t)id * M1 + a1];
-    pv = ac.x + ac.y * (v[g] - s);
-    cv = ac.y;
-  }
-  P[e] = pv;
-  Crows[e] = cv;
+}
+
+template <int D, int TW>
+hipError_t run_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
+                           int32_t* idx) {
+  const int n = p->n;
+  if (n % TW != 0) return hipErrorInvalidValue;
+  int lg = 0;
+  while ((1 << lg) < n) ++lg;
+  const dim3 grid(n / TW, n, (D == 3) ? n : 1), blk(256);
+  const double2* act2 = reinterpret_cast<const double2*>(p->ws.actab);
+  hipLaunchKernelGGL((assemble_nd_kernel<D, TW>), grid, blk, 0, p->stream, p->v, n, lg, p->ws.S,
+                     p->ws.nS, act1, act2, leaf, P, idx);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -128,17 +165,22 @@ namespace lsp {
 
 hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
                               int32_t* idx) {
-  const int64_t N = p->N;
-  const int64_t entries = N * (p->d == 2 ? 25 : 125);
-  const dim3 grid((unsigned)((entries + 255) / 256)), blk(256);
-  const double2* act2 = reinterpret_cast<const double2*>(p->ws.actab);
-  if (p->d == 2)
-    hipLaunchKernelGGL(assemble_nd_kernel<2>, grid, blk, 0, p->stream, p->v, p->n, N, p->ws.S,
-                       p->ws.nS, act1, act2, leaf, P, p->c_rows, idx);
-  else
-    hipLaunchKernelGGL(assemble_nd_kernel<3>, grid, blk, 0, p->stream, p->v, p->n, N, p->ws.S,
-                       p->ws.nS, act1, act2, leaf, P, p->c_rows, idx);
-  return hipGetLastError();
+  const int n = p->n;
+  if (p->d == 2) {
+    switch (n) {
+      case 8: return run_assemble_nd<2, 8>(p, act1, leaf, P, idx);
+      case 16: return run_assemble_nd<2, 16>(p, act1, leaf, P, idx);
+      case 32: return run_assemble_nd<2, 32>(p, act1, leaf, P, idx);
+      case 64: return run_assemble_nd<2, 64>(p, act1, leaf, P, idx);
+      default: return run_assemble_nd<2, 128>(p, act1, leaf, P, idx);
+    }
+  }
+  switch (n) {
+    case 8: return run_assemble_nd<3, 8>(p, act1, leaf, P, idx);
+    case 16: return run_assemble_nd<3, 16>(p, act1, leaf, P, idx);
+    case 32: return run_assemble_nd<3, 32>(p, act1, leaf, P, idx);
+    default: return run_assemble_nd<3, 64>(p, act1, leaf, P, idx);
+  }
 }
 
 }  // namespace lsp

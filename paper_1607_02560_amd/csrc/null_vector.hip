@@ -399,22 +399,27 @@ __device__ __forceinline__ void partial_range(int si, int nS, int nblk, int sps,
   }
 }
 
-template <int D, int W>
+// WP: the window 2 WP - 1 of the Green's partial sums read (WP >= W); the
+// sums of a wider window hold every offset of [0, W - 1]^d, so the radius-1
+// tables can be formed from the radius-2 pass.
+template <int D, int W, int WP = W>
 __device__ __forceinline__ void null_body(
-    int si, const int* __restrict__ nS, const double* __restrict__ part, int nblk, int sps,
-    int nwv, double invN, double* gtab, double* gamtab, double* Mtab, double* alpha_out,
-    double* C_out, double* sigma_out, double* rho_out, double* actab, int* status,
-    int* clear_counter) {
+    NullShared<D, W>& sh, int si, const int* __restrict__ nS, const double* __restrict__ part,
+    int nblk, int sps, int nwv, double invN, double* gtab, double* gamtab, double* Mtab,
+    double* alpha_out, double* C_out, double* sigma_out, double* rho_out, double* actab,
+    int* status, int* clear_counter) {
   using Pa = Parity<D, W>;
   using Nb = Nbhd<D, W>;
+  static_assert(WP >= W, "the partial sums must cover the window");
   constexpr int NC = 1 << D;
   constexpr int WD = Pow<D, W>::v;
   constexpr int M = WD;
-  constexpr int NP = W * (W + 1) / 2;
-  constexpr int WO2 = Pow<D - 2, W>::v;
+  // layout of the partial sums (window WP): pairs da <= db, per leading
+  // offset in 3D, g then g * g
+  constexpr int NP = WP * (WP + 1) / 2;
+  constexpr int WO2 = Pow<D - 2, WP>::v;
   constexpr int NV = 2 * WO2 * NP;
   constexpr int T = 64 * NC;
-  __shared__ NullShared<D, W> sh;
   if (si == 0 && threadIdx.x == 0 && clear_counter) *clear_counter = 0;
   const int nSv = *nS;
   if (si >= nSv) return;
@@ -479,7 +484,7 @@ __device__ __forceinline__ void null_body(
     const int da0 = (e / W) % W;
     const int x = (D == 3) ? e / (W * W) : 0;
     const int da = min(da0, db0), db = max(da0, db0);
-    const int pi = da * W - (da * (da - 1)) / 2 + (db - da);
+    const int pi = da * WP - (da * (da - 1)) / 2 + (db - da);
     const double gval = sh.stage[x * NP + pi] * invN;
     const double qval = sh.stage[WO2 * NP + x * NP + pi] * invN;
     sh.g[e] = gval;
@@ -572,7 +577,8 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_vector_kernel(
     const int* __restrict__ nS, const double* __restrict__ part, int nblk, int sps, int nwv,
     double invN, double* gtab, double* gamtab, double* Mtab, double* alpha_out, double* C_out,
     double* sigma_out, double* rho_out, double* actab, int* status, int* clear_counter) {
-  null_body<D, W>(blockIdx.x, nS, part, nblk, sps, nwv, invN, gtab, gamtab, Mtab, alpha_out,
+  __shared__ NullShared<D, W> sh;
+  null_body<D, W>(sh, blockIdx.x, nS, part, nblk, sps, nwv, invN, gtab, gamtab, Mtab, alpha_out,
                   C_out, sigma_out, rho_out, actab, status, clear_counter);
 }
 
@@ -583,8 +589,35 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_batched_kernel(const lsp::
                                                                      const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  null_body<D, W>(it.y, r.nS, r.part, r.nunits, r.sps, r.gwaves, r.invN, r.gtab, r.gamtab,
+  __shared__ NullShared<D, W> sh;
+  null_body<D, W>(sh, it.y, r.nS, r.part, r.nunits, r.sps, r.gwaves, r.invN, r.gtab, r.gamtab,
                   r.Mtab, r.alpha, r.Ctab, r.sigma, r.rho, r.actab, r.status, nullptr);
+}
+
+// Both radii of the per-point-radius setup from one radius-2 Green's pass:
+// blocks 0 .. nreq-1 solve radius 2 into the problem's tables, blocks
+// nreq .. 2 nreq - 1 radius 1 into the tables of t1. The two parts share one
+// LDS area.
+struct NullOut {
+  double *gtab, *gamtab, *Mtab, *alpha, *C, *sigma, *rho, *actab;
+  int* status;
+};
+
+template <int D>
+__global__ __launch_bounds__(64 * (1 << D)) void null_nd_kernel(
+    const int* __restrict__ nS, const double* __restrict__ part, int nblk, int sps, int nwv,
+    double invN, int nreq, NullOut t2, NullOut t1) {
+  constexpr size_t B5 = sizeof(NullShared<D, 5>), B3 = sizeof(NullShared<D, 3>);
+  __shared__ __align__(16) unsigned char raw[B5 > B3 ? B5 : B3];
+  if ((int)blockIdx.x < nreq) {
+    null_body<D, 5>(*reinterpret_cast<NullShared<D, 5>*>(raw), blockIdx.x, nS, part, nblk, sps,
+                    nwv, invN, t2.gtab, t2.gamtab, t2.Mtab, t2.alpha, t2.C, t2.sigma, t2.rho,
+                    t2.actab, t2.status, nullptr);
+  } else {
+    null_body<D, 3, 5>(*reinterpret_cast<NullShared<D, 3>*>(raw), blockIdx.x - nreq, nS, part,
+                       nblk, sps, nwv, invN, t1.gtab, t1.gamtab, t1.Mtab, t1.alpha, t1.C,
+                       t1.sigma, t1.rho, t1.actab, t1.status, nullptr);
+  }
 }
 
 template <int D, int W>
@@ -618,6 +651,25 @@ hipError_t launch_null_batched(int d, int t, const BatchRec* recs, const int4* m
   LSP_NULL_B(3, 3)
 #undef LSP_NULL_B
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_null_nd(lsp_problem* p, int num_shifts, const NdTables1& t1) {
+  if (p->t != 2 || (p->d != 2 && p->d != 3)) return hipErrorInvalidValue;
+  const double invN = 1.0 / (double)p->N;
+  const int sps = (p->d == 2) ? lsp::green2d_sps(p->n) : 0;
+  const int nwv = (p->d == 2) ? lsp::green2d_waves(p->n, num_shifts) : 0;
+  const NullOut o2{p->ws.gtab, p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab,
+                   p->ws.sigma, p->ws.rho, p->ws.actab, p->ws.status};
+  const NullOut o1{t1.gtab, t1.gamtab, t1.Mtab, t1.alpha, t1.C,
+                   t1.sigma, t1.rho, reinterpret_cast<double*>(t1.actab), t1.status};
+  const dim3 grid(2 * num_shifts), block(64 * (1 << p->d));
+  if (p->d == 2)
+    hipLaunchKernelGGL(null_nd_kernel<2>, grid, block, 0, p->stream, p->ws.nS, p->ws.green_part,
+                       p->green_nunits, sps, nwv, invN, num_shifts, o2, o1);
+  else
+    hipLaunchKernelGGL(null_nd_kernel<3>, grid, block, 0, p->stream, p->ws.nS, p->ws.green_part,
+                       p->green_nunits, sps, nwv, invN, num_shifts, o2, o1);
+  return hipGetLastError();
 }
 
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int* clear_counter) {

@@ -6,6 +6,26 @@
 
 namespace lsp {
 
+// Radius t_j of point c (coordinates per axis) in the per-point-radius setup
+// with leaf box b (Sec. 4.2, Fig. 3): the separators are the grid planes
+// c_i = 0 mod b; a vertex (every coordinate on a separator) may reach b, any
+// other point reaches up to the nearest separator plane across its
+// coordinates off the separators; capped at tmax.
+template <int D>
+__device__ __forceinline__ int nd_radius(const int* c, int b, int tmax) {
+  int reach = b;
+  bool off = false;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const int r = c[i] % b;
+    if (r != 0) {
+      off = true;
+      reach = min(reach, min(r, b - r));
+    }
+  }
+  return min(off ? reach : b, tmax);
+}
+
 template <int D, int W>
 struct Pow {
   static constexpr int v = W * Pow<D - 1, W>::v;

@@ -116,6 +116,8 @@ def load():
                                             c_void_p]),
         "lsp_batch_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_batch_tile": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p]),
+        "lsp_get_tables_nd1": (c_int, [c_void_p, c_int, P(c_int), c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_void_p]),
         "lsp_psolve_upload": (c_int, [c_void_p, P(NDFactors)]),
         "lsp_psolve_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_precond_solve_device": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int,
@@ -362,6 +364,27 @@ class Problem:
         _check(self.lib.lsp_profile_read(self._h, len(STAGES), ms.ctypes.data, cnt.ctypes.data),
                "lsp_profile_read")
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
+
+    def get_tables_nd1(self, capacity: int = 1024) -> dict:
+        """Host copies of the radius-1 tables of the last per-point-radius setup."""
+        m1 = 3 ** self.d
+        alpha = np.zeros(capacity * m1)
+        C = np.zeros(capacity * m1)
+        sigma = np.zeros(capacity)
+        g = np.zeros(capacity * m1)
+        gam = np.zeros(capacity * m1)
+        nS = ctypes.c_int(0)
+        _check(self.lib.lsp_get_tables_nd1(self._h, capacity, ctypes.byref(nS), alpha.ctypes.data,
+                                           C.ctypes.data, sigma.ctypes.data, g.ctypes.data,
+                                           gam.ctypes.data), "lsp_get_tables_nd1")
+        k = nS.value
+        return {
+            "alpha": alpha[:k * m1].reshape(k, m1).copy(),
+            "C": C[:k * m1].reshape(k, m1).copy(),
+            "sigma_min": sigma[:k].copy(),
+            "g": g[:k * m1].reshape((k,) + (3,) * self.d).copy(),
+            "gamma": gam[:k * m1].reshape((k,) + (3,) * self.d).copy(),
+        }
 
     def get_tables(self, capacity: int = 1024) -> dict:
         """Host copies of the per-shift tables of the last setup."""

@@ -1,8 +1,12 @@
 """The per-point radius of Sec. 4.2 (lsp_stencil_setup_nd) through the C ABI:
-every row equals, bit for bit, the row of the uniform-radius setup of its own
-radius (radius-1 rows padded with zeros), the radius map matches the oracle's
-(pinned to Fig. 3), the rows match the oracle's nd_setup to 1e-8, the C-apply
-uses the per-point C rows, and GMRES counts are within one of the oracle's."""
+radius-2 rows equal, bit for bit, the rows of the uniform radius-2 setup;
+radius-1 rows (padded with zeros) equal, bit for bit, the row formula on the
+setup's own radius-1 tables, which are formed from the radius-2 Green's pass
+(the same sums at offsets [0, 2]^d, added in another order) and agree with
+the uniform radius-1 setup's tables to rounding; the radius map matches the
+oracle's (pinned to Fig. 3), the rows match the oracle's nd_setup to 1e-8,
+the C-apply uses the per-point C rows, and GMRES counts are within one of the
+oracle's."""
 import numpy as np
 import pytest
 
@@ -26,7 +30,7 @@ def run_nd(torch_dev, v, leaf, nS):
     return prob, P.cpu().numpy().reshape(N, M), idx.cpu().numpy()
 
 
-def uniform(torch_dev, v, t, nS):
+def uniform(torch_dev, v, t, nS, tables=False):
     torch, dev = torch_dev
     lsp = lsp_mod()
     d, n = v.ndim, v.shape[0]
@@ -36,8 +40,20 @@ def uniform(torch_dev, v, t, nS):
     prob.stencil_setup(t, nS, P)
     torch.cuda.synchronize()
     out = P.cpu().numpy().reshape(N, m)
+    tab = prob.get_tables() if tables else None
     prob.close()
-    return out
+    return (out, tab) if tables else out
+
+
+def rows_from_tables(v, S, idx, alpha, C, t):
+    """P[j, a] = alpha[a] + C[a] (v[j + a] - s_j) on the host, one rounding per
+    operation in the kernels' order (Sec. 4.1)."""
+    d = v.ndim
+    offs = O.offsets(d, t)
+    N = v.size
+    vj = np.stack([np.roll(v, tuple(-o), axis=tuple(range(d))).reshape(-1) for o in offs], axis=1)
+    s = S[idx][:, None]
+    return alpha[idx] + C[idx] * (vj - s)
 
 
 @pytest.mark.parametrize("d,n,leaf,nS,seed", [(2, 64, 8, 4, 0), (2, 32, 4, 3, 1),
@@ -50,13 +66,23 @@ def test_nd_rows_are_the_uniform_rows_of_their_radius(torch_dev, d, n, leaf, nS,
     tm = O.nd_tmap(d, n, leaf, 2).reshape(-1)
     offs = O.offsets(d, 2)
     inner = np.all(np.abs(offs) <= 1, axis=1)
-    P1 = uniform(torch_dev, v, 1, nS)
+    P1, tab1 = uniform(torch_dev, v, 1, nS, tables=True)
     P2 = uniform(torch_dev, v, 2, nS)
     two, one = tm == 2, tm == 1
     assert two.any() and one.any()
     assert np.array_equal(P[two], P2[two])
-    assert np.array_equal(P[np.ix_(one, inner)], P1[one])
+    # radius 1: the row formula on this setup's radius-1 tables, bit for bit
+    t1 = prob.get_tables_nd1()
+    S = prob.get_tables()["S"]
+    R1 = rows_from_tables(v, S, idx, t1["alpha"], t1["C"], 1)
+    assert np.array_equal(P[np.ix_(one, inner)], R1[one])
     assert np.all(P[np.ix_(one, ~inner)] == 0.0)
+    # ... and those tables are the uniform radius-1 tables up to the order of
+    # the Green's sums (well-separated 2D/3D null vectors: a plain bound)
+    for key, tol in (("g", 1e-13), ("gamma", 1e-13), ("alpha", 1e-10), ("C", 1e-10)):
+        a, b = t1[key].reshape(len(S), -1), tab1[key].reshape(len(S), -1)
+        assert np.linalg.norm(a - b) <= tol * np.linalg.norm(b), key
+    assert np.linalg.norm(P[np.ix_(one, inner)] - P1[one]) <= 1e-10 * np.linalg.norm(P1[one])
     assert np.array_equal(idx, O.assign_shifts(v, O.shift_list(v, nS)).reshape(-1))
     if d == 2:
         # (the uniform setups carry the conditioning-aware comparison with the
@@ -68,16 +94,12 @@ def test_nd_rows_are_the_uniform_rows_of_their_radius(torch_dev, d, n, leaf, nS,
 
 def test_nd_c_apply_uses_per_point_rows(torch_dev):
     """z = C r with C[j, mu_j^{t_j}] = C^{t_j}_{s_j}: against the sparse rows
-    built from the GPU's own tables (radius 2 from this setup, radius 1 from a
-    uniform t = 1 setup, which computes the same tables), to 1e-13."""
+    built from the setup's own tables of both radii, to 1e-13."""
     torch, dev = torch_dev
     lsp = lsp_mod()
     p = W.helm2d_cross(64)
-    prob1 = lsp.Problem(2, p.n, torch.from_numpy(p.v.reshape(-1)).to(dev))
-    prob1.stencil_setup(1, p.num_shifts, torch.empty(p.N * 9, dtype=torch.float64, device=dev))
-    C1 = prob1.get_tables()["C"]
-    prob1.close()
     prob, P, idx = run_nd(torch_dev, p.v, 8, p.num_shifts)
+    C1 = prob.get_tables_nd1()["C"]
     C2 = prob.get_tables()["C"]
     tm = O.nd_tmap(2, p.n, 8, 2).reshape(-1)
     offs = O.offsets(2, 2)
