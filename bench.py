@@ -320,6 +320,10 @@ def cpu_baseline(p):
         t0 = time.perf_counter()
         pool.map(_oracle_apply_worker, [(p.v, p.f, reps)] * workers)
         t_apply_all = (time.perf_counter() - t0) / (reps * workers)
+        # let the workers exit by themselves before the pool is torn down, so
+        # that no process outlives the benchmark
+        pool.close()
+        pool.join()
     out["all_cores"] = {
         "cores": workers, "value": p.N / t_setup_all, "unit": "stencils/s",
         "setup_s": t_setup_all, "ps_apply_s_per_apply": t_apply_all,

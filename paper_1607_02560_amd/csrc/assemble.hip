@@ -231,28 +231,36 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
       }
     }
     double zr = 0.0, zi = 0.0;
+    // the row sum for a coefficient rule coef(a, da); two instances below,
+    // so that the uniform loop keeps its loads free of branches
+    auto row_sum = [&](auto coef) {
 #pragma unroll
-    for (int a = 0; a < M; ++a) {
-      int da[D];
-      int rem = a;
+      for (int a = 0; a < M; ++a) {
+        int da[D];
+        int rem = a;
 #pragma unroll
-      for (int k = D - 1; k >= 0; --k) {
-        da[k] = rem % W - t;
-        rem /= W;
+        for (int k = D - 1; k >= 0; --k) {
+          da[k] = rem % W - t;
+          rem /= W;
+        }
+        int hp = 0, hr, hc;
+        if constexpr (D == 3) {
+          hp = t + da[0];
+          hr = r + t + da[1];
+          hc = c + t + da[2];
+        } else {
+          hr = r + t + da[0];
+          hc = c + t + da[1];
+        }
+        const double2 x = halo[(hp * HR + hr) * HC + hc];
+        const double ca = coef(a, da);
+        zr = fma(ca, x.x, zr);
+        zi = fma(ca, x.y, zi);
       }
-      int hp = 0, hr, hc;
-      if constexpr (D == 3) {
-        hp = t + da[0];
-        hr = r + t + da[1];
-        hc = c + t + da[2];
-      } else {
-        hr = r + t + da[0];
-        hc = c + t + da[1];
-      }
-      const double2 x = halo[(hp * HR + hr) * HC + hc];
-      double ca;
-      if (crow1) {
-        // radius 1: the offsets of mu_0^1 from its table, zero elsewhere
+    };
+    if (crow1) {
+      // radius 1: the offsets of mu_0^1 from its table, zero elsewhere
+      row_sum([&](int, const int* da) {
         bool in = true;
         int a1 = 0;
 #pragma unroll
@@ -260,12 +268,10 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
           in = in && da[k] >= -1 && da[k] <= 1;
           a1 = a1 * 3 + da[k] + 1;
         }
-        ca = in ? crow1[a1] : 0.0;
-      } else {
-        ca = crow[a];
-      }
-      zr = fma(ca, x.x, zr);
-      zi = fma(ca, x.y, zi);
+        return in ? crow1[a1] : 0.0;
+      });
+    } else {
+      row_sum([&](int a, const int*) { return crow[a]; });
     }
     z[g] = make_double2(zr, zi);
   }
