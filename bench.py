@@ -31,7 +31,8 @@ A third section times the batched form: 64 2D problems with n drawn from
 for all of them, against the same 64 problems set up one by one.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--no-learned] [--train-steps S] [--no-batched]
+                    [--no-learned] [--train-steps S] [--no-batched] [--no-extras]
+    python bench.py --krylov-only      # the device-GMRES section alone
     python bench.py --copy-probe MiB   # plain device copy of a known size, for
                                        # scaling hardware byte counters
 """
@@ -56,11 +57,11 @@ HBM_PEAK_GBPS = 8000.0
 # sources they were taken on (sha256 prefix of the files below); for any
 # other sources the traffic is reported as null.
 ASSEMBLE_PMC = {
-    "fetch_kib": 5289.4, "write_kib": 208896.0,
-    "fetch_scale": 262144.0 / 131085.5, "write_scale": 262144.0 / 262144.0,
+    "fetch_kib": 5289.6, "write_kib": 208929.9,
+    "fetch_scale": 262144.0 / 131092.8, "write_scale": 262144.0 / 262144.0,
     "sources": ("paper_1607_02560_amd/csrc/assemble.hip",
                 "paper_1607_02560_amd/csrc/setup_common.h"),
-    "sources_sha256": "b186060596711419",
+    "sources_sha256": "ea756f97b0d7ff58",
 }
 
 
@@ -504,6 +505,8 @@ def main():
                     help="skip the batched-form section")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the non-localized and 3D t = 2 sections")
+    ap.add_argument("--krylov-only", action="store_true",
+                    help="only run the device-GMRES section (for profiling its kernels)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="only run 5 device-to-device copies of MiB mebibytes and exit")
     args = ap.parse_args()
@@ -528,6 +531,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+        return
+    if args.krylov_only:
+        print(json.dumps({"krylov_device": krylov_section(dev, args.steps)}))
         return
     p = W.helm2d_random(args.n)
     d, n, t, N = p.d, p.n, p.t, p.N
