@@ -48,6 +48,7 @@ if ROOT not in sys.path:
 
 METRIC = "local stencils/s + ps_apply GB/s, 2D n=1024; learned vs exact at equal GMRES iters"
 HBM_PEAK_GBPS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA
 
 # HBM bytes per launch of the assembly kernel on this workload, from the
 # FETCH_SIZE and WRITE_SIZE hardware counters (rocprofv3 --pmc, one counter
@@ -141,6 +142,13 @@ def learned_vs_exact(dev, stream, reps, train_steps, threshold=1e-3):
         learned()
     t_exact = timed(stream, exact, reps)
     t_learned = timed(stream, learned, reps)
+    # the network-and-rows kernel alone (per-stage HIP events of the library)
+    prob.profile(True)
+    for _ in range(reps):
+        learned()
+    prof = prob.profile_read()
+    prob.profile(False)
+    t_rows = prof["assemble"][0] / max(prof["assemble"][1], 1) * 1e-3
     nf = [prob.stencil_setup_learned(net, t, nS, threshold, P, fb)]
     prob.close()
     net.close()
@@ -176,9 +184,22 @@ def learned_vs_exact(dev, stream, reps, train_steps, threshold=1e-3):
                     "fallback_frac": nfs / Ns}
     probs.close()
     net16.close()
+    # MFMA work: BF16 products of the network (unpadded sizes), against the
+    # dense BF16 peak of the part
+    n_in, n_h, n_out = m + 2, SG.HIDDEN, 2 * m
+    fwd = 2 * (n_in * n_h + n_h * n_h + n_h * n_out)            # flop per row, forward
+    train = fwd + fwd + 2 * (n_h * n_h + n_out * n_h)           # + weight and input gradients
+    sps = train_steps * batch / t_train
     return {
         "workload": f"3D Helmholtz, smooth random c in [0.8,1.2], n={n} (N={N}), t={t} "
                     f"(3x3x3 stencils), |S|={nS}, evaluation seed 0",
+        "mfma": {"peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "flop_per_row_forward": fwd, "flop_per_row_train": train,
+                 "train_achieved": sps * train / 1e12,
+                 "train_frac": sps * train / 1e12 / BF16_PEAK_TFLOPS,
+                 "learned_rows_kernel_ms": t_rows * 1e3,
+                 "learned_rows_achieved": N * fwd / t_rows / 1e12,
+                 "learned_rows_frac": N * fwd / t_rows / 1e12 / BF16_PEAK_TFLOPS},
         "network": f"{m + 2}->{SG.HIDDEN}->{SG.HIDDEN}->{2 * m} SiLU, BF16 MFMA, FP32 accumulation",
         "training": {"rows": int(X.shape[0]), "seeds": "1..8", "steps": train_steps,
                      "batch": batch, "loss_by_step": [[int(a), float(b)] for a, b in hist],

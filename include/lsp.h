@@ -294,8 +294,9 @@ int lsp_default_num_shifts(int d, int n);
  * Per-stage timing with HIP events on the problem's stream (for measurement;
  * off by default). Stages: LSP_STAGE_SHIFTS (min/max of v for the shift
  * list), LSP_STAGE_GREEN (shift list and Green's kernel sums), LSP_STAGE_NULL (Gram matrix and null vector),
- * LSP_STAGE_ASSEMBLE (per-point rows), LSP_STAGE_SETUP (the whole
- * lsp_stencil_setup), LSP_STAGE_APPLY (lsp_ps_apply), LSP_STAGE_CAPPLY
+ * LSP_STAGE_ASSEMBLE (per-point rows; for lsp_stencil_setup_learned the
+ * network, check and rows), LSP_STAGE_SETUP (the whole lsp_stencil_setup or
+ * lsp_stencil_setup_learned), LSP_STAGE_APPLY (lsp_ps_apply), LSP_STAGE_CAPPLY
  * (lsp_c_apply), LSP_STAGE_PSOLVE (lsp_psolve_apply), LSP_STAGE_ARNOLDI (one
  * Arnoldi step of lsp_precond_solve_device, graph replay included).
  * lsp_profile(p, 1) starts recording and clears the totals; lsp_profile(p, 0)

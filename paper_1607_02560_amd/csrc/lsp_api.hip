@@ -681,9 +681,18 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   }
   // exact tables (shift list, Green's sums, Gram matrices, null vectors and
   // rho*(s)); the null-vector kernel also clears the fallback counter
+  const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
+  int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
   hipError_t e = lsp::launch_minmax(p, num_shifts);
+  lsp::stage_end(p, tk);
+  tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts);
+  lsp::stage_end(p, tk);
+  tk = lsp::stage_begin(p, LSP_STAGE_NULL);
   if (e == hipSuccess) e = lsp::launch_null_vectors(p, num_shifts, nfall);
+  lsp::stage_end(p, tk);
+  // the learned rows take the place of the assembly in the stage timing
+  tk = lsp::stage_begin(p, LSP_STAGE_ASSEMBLE);
   if (fused) {
     // one pass: network, check against eq. (A) and rows
     if (e == hipSuccess)
@@ -700,6 +709,8 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
                                      fallback_dev, nfall);
     }
   }
+  lsp::stage_end(p, tk);
+  lsp::stage_end(p, tk_all);
   int nf = 0;
   if (n_fallback_host) {
     if (e == hipSuccess)

@@ -42,7 +42,8 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (+ C[m][n] if accumulate), with
 // A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn] in BF16 and C in FP32.
 // M, N, K are multiples of 16. Four waves per block, one 16x16 tile each
-// (2 x 2 tiles per block); one v_mfma_f32_16x16x16bf16 per 16 values of k.
+// (2 x 2 tiles per block); one v_mfma_f32_16x16x16bf16 per 16 values of k,
+// operands of four k-steps loaded together.
 // With gridDim.z > 1 block z sums k in [z kchunk, (z+1) kchunk) and writes
 // its raw partial tile to C + z M ldc (split_reduce_kernel adds them).
 // MFMA operand layout: lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
@@ -67,7 +68,24 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     bias = nullptr;
     accumulate = 0;
   }
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  // four k-steps of operands are loaded before their four MFMAs (one memory
+  // round trip per 64 values of k); the MFMAs run in k order either way
+  int k0 = kb;
+  for (; k0 + 64 <= ke; k0 += 64) {
+    bf16x4 a[4], b[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[g][i] = (short)ap[(int64_t)(k0 + 16 * g + kq + i) * sak];
+        b[g][i] = (short)bp[(int64_t)(k0 + 16 * g + kq + i) * sbk];
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b[g], acc, 0, 0, 0);
+  }
+  for (; k0 < ke; k0 += 16) {
     bf16x4 a, b;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -95,7 +113,15 @@ __global__ void split_reduce_kernel(const float* __restrict__ part, int splits, 
   if (e >= (int64_t)M * N) return;
   const int m = (int)(e / N), n = (int)(e % N);
   float s = 0.f;
-  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * M * N + e];
+  int z = 0;
+  for (; z + 8 <= splits; z += 8) {  // eight loads in flight, added in order
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(z + u) * M * N + e];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u];
+  }
+  for (; z < splits; ++z) s += part[(int64_t)z * M * N + e];
   if (bias) s += bias[n];
   float* cp = C + (int64_t)m * ldc + n;
   if (accumulate) s += *cp;
@@ -167,19 +193,48 @@ __global__ void mse_grad_kernel(const float* __restrict__ Y, const float* __rest
   if (threadIdx.x == 0) loss_part[blockIdx.x] = red[0];
 }
 
-// out[c] = sum over rows of D[r][c], one block per column, fixed order
-__global__ void colsum_kernel(const float* __restrict__ D, int rows, int ld, float* out) {
+// Column sums out[c] = sum over rows of D[r][c] in two fixed-order stages.
+// Stage 1: block (cb, rb) sums columns 64 cb .. 64 cb + 63 over the rows of
+// row block rb (kColRows rows): thread (g, c) takes rows g, g + 4, ... with
+// eight loads in flight (a wave reads 64 consecutive columns of one row), and
+// the four row groups meet in LDS; part[rb][c] holds the block's sums.
+constexpr int kColRows = 128;
+
+__global__ __launch_bounds__(kT) void colsum_partial_kernel(const float* __restrict__ D, int rows,
+                                                            int ld, int ncol, float* part) {
   __shared__ float red[kT];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * kColRows;
+  const int r1 = min(rows, r0 + kColRows);
   float s = 0.f;
-  for (int r = threadIdx.x; r < rows; r += kT) s += D[(int64_t)r * ld + c];
+  if (c < ncol) {
+    int r = r0 + g;
+    for (; r + 28 < r1; r += 32) {
+      float x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = D[(int64_t)(r + 4 * u) * ld + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += x[u];
+    }
+    for (; r < r1; r += 4) s += D[(int64_t)r * ld + c];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int o = kT / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[c] = red[0];
+  if (g == 0 && c < ncol)
+    part[(int64_t)blockIdx.y * ncol + c] =
+        ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) +
+        red[threadIdx.x + 192];
+}
+
+// Stage 2: out[c] = sum over row blocks of part[rb][c], in row-block order
+__global__ void colsum_final_kernel(const float* __restrict__ part, int nrb, int ncol,
+                                    float* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  float s = 0.f;
+  for (int rb = 0; rb < nrb; ++rb) s += part[(int64_t)rb * ncol + c];
+  out[c] = s;
 }
 
 // Adam (Kingma and Ba) with bias correction on every parameter; the BF16
@@ -279,6 +334,7 @@ struct lsp_mlp {
   double* loss_host = nullptr;  // pinned
   float* gsplit = nullptr;      // k-split partial tiles of the weight gradients
   size_t gsplit_cap = 0;
+  float* colpart = nullptr;     // column-sum partials of the bias gradients
 };
 
 namespace {
@@ -325,6 +381,18 @@ hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak
                      (int64_t)N, M, N, K, nullptr, 0, kchunk);
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)(((int64_t)M * N + kT - 1) / kT)),
                      dim3(kT), 0, s, split_buf, splits, M, N, C, ldc, bias, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+// out[c] = column sums of D [rows][ld] (ncol columns), two launches; part
+// holds ceil(rows / kColRows) * ncol floats
+hipError_t colsum(hipStream_t s, const float* D, int rows, int ld, int ncol, float* part,
+                  float* out) {
+  const int nrb = (rows + kColRows - 1) / kColRows;
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((unsigned)((ncol + 63) / 64), (unsigned)nrb),
+                     dim3(kT), 0, s, D, rows, ld, ncol, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3(blocks_for(ncol)), dim3(kT), 0, s, part, nrb,
+                     ncol, out);
   return hipGetLastError();
 }
 
@@ -375,8 +443,7 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
   if ((e = gemm(s, q->dYb, 1, q->Op, q->A2b, H, 1, g + q->off_W3, H, q->Op, H, rows_pad, nullptr,
                 false, q->gsplit, q->gsplit_cap)))
     return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(q->Op), dim3(kT), 0, s, q->dY, rows_pad, q->Op,
-                     g + q->off_b3);
+  if ((e = colsum(s, q->dY, rows_pad, q->Op, q->Op, q->colpart, g + q->off_b3))) return e;
   // dA2 = dY W3: A(b, o) = dYb[b Op + o], B(o, h) = W3[o H + h]
   if ((e = gemm(s, q->dYb, q->Op, 1, W3, H, 1, q->dA, H, rows_pad, H, q->Op, nullptr, false)))
     return e;
@@ -387,7 +454,7 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
   if ((e = gemm(s, q->dZb, 1, H, q->A1b, H, 1, g + q->off_W2, H, H, H, rows_pad, nullptr, false,
                 q->gsplit, q->gsplit_cap)))
     return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b2);
+  if ((e = colsum(s, q->dZ, rows_pad, H, H, q->colpart, g + q->off_b2))) return e;
   // dA1 = dZ2 W2: B(h2, h1) = W2[h2 H + h1]
   if ((e = gemm(s, q->dZb, H, 1, W2, H, 1, q->dA, H, rows_pad, H, H, nullptr, false))) return e;
   hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z1, cnt,
@@ -396,7 +463,7 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
   if ((e = gemm(s, q->dZb, 1, H, q->Xb, q->Ip, 1, g + q->off_W1, q->Ip, H, q->Ip, rows_pad,
                 nullptr, false, q->gsplit, q->gsplit_cap)))
     return e;
-  hipLaunchKernelGGL(colsum_kernel, dim3(H), dim3(kT), 0, s, q->dZ, rows_pad, H, g + q->off_b1);
+  if ((e = colsum(s, q->dZ, rows_pad, H, H, q->colpart, g + q->off_b1))) return e;
   return hipGetLastError();
 }
 
@@ -516,7 +583,9 @@ int lsp_mlp_create(int n_in, int n_hidden, int n_out, int batch_rows, void* stre
       (rc = dalloc_(&q->dA, B * H)) || (rc = dalloc_(&q->dZ, B * H)) ||
       (rc = dalloc_(&q->dZb, B * H)) ||
       (rc = dalloc_(&q->loss_part, B * q->Op / kT + 1)) ||
-      (rc = dalloc_(&q->gsplit, (size_t)64 * H * std::max(H, std::max(q->Ip, q->Op))))) {
+      (rc = dalloc_(&q->gsplit, (size_t)64 * H * std::max(H, std::max(q->Ip, q->Op)))) ||
+      (rc = dalloc_(&q->colpart,
+                    (B + kColRows - 1) / kColRows * (size_t)std::max(H, q->Op)))) {
     lsp_mlp_destroy(q);
     return rc;
   }
@@ -548,6 +617,7 @@ void lsp_mlp_destroy(lsp_mlp* q) {
   dfree_(q->Y); dfree_(q->dY); dfree_(q->dYb); dfree_(q->dA); dfree_(q->dZ); dfree_(q->dZb);
   dfree_(q->loss_part);
   dfree_(q->gsplit);
+  dfree_(q->colpart);
   if (q->loss_host) (void)hipHostFree(q->loss_host);
   delete q;
 }

@@ -65,19 +65,22 @@ def gather_rows(fields, t: int, num_shifts: int, rows_per_field: int, seed: int,
 
 def train(mlp: "lsp.MLP", X, T, steps: int, batch: int, lr: float, seed: int,
           report_every: int = 0, lr_final: float | None = None):
-    """Adam on random batches of the rows (indices drawn on the host, the
-    batch gathered on the device). The learning rate decays geometrically to
-    lr_final when given. Returns the list of (step, loss) reported."""
+    """Adam on random batches of the rows (indices drawn on the device from a
+    seeded generator, the batch gathered on the device, so a step makes no
+    host-to-device copy). The learning rate decays geometrically to lr_final
+    when given. Returns the list of (step, loss) reported."""
     import torch
-    r = np.random.default_rng(seed)
     rows = X.shape[0]
     dev = X.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
     Xb = torch.empty((batch, X.shape[1]), dtype=torch.float32, device=dev)
     Tb = torch.empty((batch, T.shape[1]), dtype=torch.float32, device=dev)
+    idx = torch.empty(batch, dtype=torch.int64, device=dev)
     hist = []
     decay = 1.0 if lr_final is None else (lr_final / lr) ** (1.0 / max(steps - 1, 1))
     for it in range(steps):
-        idx = torch.from_numpy(r.integers(0, rows, batch).astype(np.int64)).to(dev)
+        torch.randint(0, rows, (batch,), generator=gen, device=dev, out=idx)
         torch.index_select(X, 0, idx, out=Xb)
         torch.index_select(T, 0, idx, out=Tb)
         want = report_every > 0 and (it % report_every == 0 or it == steps - 1)
