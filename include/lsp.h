@@ -209,7 +209,8 @@ int lsp_precond_solve(lsp_problem* p, const double* f_dev, double* u_dev,
  *   idx_U           [nidx_U] the U_k concatenated
  *   off_blk         [4*nfronts] offsets into data of front k's dense
  *                   row-major blocks: L_FF^-1 (f x f, inverse of the unit
- *                   lower factor), L_UF (u x f), U_FF^-1 (f x f), U_FU (f x u)
+ *                   lower factor), L_UF L_FF^-1 (u x f), U_FF^-1 (f x f),
+ *                   U_FF^-1 U_FU (f x u)
  *   data            [ndata] the dense blocks
  *   upd_ptr         [N+1], upd_pos [nidx_U]: for grid point i, the entries
  *                   upd_pos[upd_ptr[i] .. upd_ptr[i+1]) are the positions in
@@ -239,9 +240,9 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac);
 /*
  * z = P^-1 r with the uploaded factors: level by level, a forward pass
  * (gather of the right-hand side and of the updates earlier fronts sent,
- * then y_F = L_FF^-1 r_F and the updates L_UF y_F) and a backward pass
- * (x_F = U_FF^-1 (y_F - U_FU x_U)). Every sum runs in a fixed order, so
- * the result is deterministic. r_dev, z_dev: N complex128 device arrays,
+ * then y_F = L_FF^-1 r_F and the updates (L_UF L_FF^-1) r_F) and a backward
+ * pass (x_F = U_FF^-1 y_F - (U_FF^-1 U_FU) x_U), one launch per level and
+ * pass. Every sum runs in a fixed order, so the result is deterministic. r_dev, z_dev: N complex128 device arrays,
  * must not overlap. LSP_ESTATE without an upload. Asynchronous.
  */
 int lsp_psolve_apply(lsp_problem* p, const double* r_dev, double* z_dev);

@@ -96,18 +96,19 @@ struct NDSolve {
     int64_t front0 = 0;           // its fronts: front0 .. front0 + nfronts - 1
     int nfronts = 0;
     bool fused = false;           // one block per front, else split products
+    bool staged = false;          // split: each block gathers r_F into LDS (else a gather launch)
     int64_t fmax = 0, umax = 0;   // largest f and u of the level
-    int lanes_f = 8, lanes_u = 8; // lanes per row for f and u columns
-    // split products: row tasks of f x f, u x f and f x u blocks
-    int64_t ff_task0 = 0, uf_task0 = 0, fu_task0 = 0;
-    int ff_tasks = 0, uf_tasks = 0, fu_tasks = 0;
+    int lanes_f = 8, lanes_b = 8; // lanes per row: forward (f columns), backward (f and u)
+    // split levels: row tasks of the forward (f + u rows) and backward (f rows)
+    int64_t fwd_task0 = 0, bwd_task0 = 0;
+    int fwd_tasks = 0, bwd_tasks = 0;
   };
   int64_t *f = nullptr, *u = nullptr, *off_F = nullptr, *off_U = nullptr;
   int64_t *idx_F = nullptr, *idx_Fp = nullptr, *idx_U = nullptr, *off_blk = nullptr;
   int64_t *upd_ptr = nullptr, *slot = nullptr;  // updates of a point: slots upd_ptr[i]..upd_ptr[i+1]
   double* data = nullptr;
   int2* tasks = nullptr;           // (front, first row) of the split products
-  double2 *R = nullptr, *Yc = nullptr, *T = nullptr, *W = nullptr;
+  double2 *R = nullptr, *Yc = nullptr, *W = nullptr;
   std::vector<Level> levels;
   bool ready = false;
 };

@@ -3,23 +3,25 @@
 // factorisation itself is the plain host step, see nd.py).
 //
 // The factors come per front (the points eliminated together: a box interior
-// or a separator piece): its F and U index lists, the inverses of its
-// triangular blocks L^-1 and U^-1 and its off-diagonal blocks L_UF and U_FU,
-// all dense and row-major. With Pi the row permutation of F,
-//   forward  (levels in order):   y_F = L^-1 Pi r_F,   r_U -= L_UF y_F
-//   backward (levels reversed):   x_F = U^-1 (y_F - U_FU x_U)
-// Fronts of one level (one merge step of the boxes) do not depend on each
-// other, so each pass takes one level per launch (or per few launches). The
-// updates r_U -= L_UF y_F are not scattered: each front stores
-// its products L_UF y_F in the slots of its U list, and a point gathers the
-// slots that name it, in front order, when its own front is reached; every
-// sum is in a fixed order, so the solve is deterministic.
+// or a separator piece): its F and U index lists and four dense row-major
+// blocks, L_FF^-1, L_UF L_FF^-1, U_FF^-1 and U_FF^-1 U_FU (formed on the
+// host). With Pi the row permutation of F and r_F the front's right-hand side
+// after the updates of earlier fronts,
+//   forward  (levels in order):   y_F = L_FF^-1 Pi r_F,
+//                                 updates (L_UF L_FF^-1) Pi r_F for the U points
+//   backward (levels reversed):   x_F = U_FF^-1 y_F - (U_FF^-1 U_FU) x_U
+// so each pass is a set of independent row products per level: one launch
+// per level and pass. Fronts of one level (one merge step of the boxes) do
+// not depend on each other. The updates are not scattered: each front stores
+// them in the slots of its U list, numbered so that the updates a point
+// receives are consecutive (in front order), and a point gathers them when
+// its own front is reached; every sum is in a fixed order, so the solve is
+// deterministic.
 //
-// Levels with many small fronts run one block per front: forward, the block
-// gathers r_F into LDS, forms y_F there (and stores it), then the updates
-// L_UF y_F; backward, it gathers x_U into LDS, forms y_F - U_FU x_U there,
-// then x_F. Levels with few large fronts split each product over blocks of
-// rows, one launch per product (the first gathers r_F itself).
+// Levels with many small fronts run one block per front (the block gathers
+// r_F, or y_F and x_U, into LDS first); levels with few large fronts split
+// the rows over blocks, each block gathering the front's r_F into LDS itself
+// (backward, the blocks read y_F and x_U directly).
 //
 // Row products: LANES lanes share a row (8 to 64, by the row length), each
 // striding over the columns with four independent loads in flight (the last
@@ -36,6 +38,8 @@ constexpr int kThreads = 256;
 constexpr int kFusedMinFronts = 64;   // a level runs fused with at least this many fronts
 constexpr int kFusedMaxFU = 2048;     // and f + u <= this (LDS: (f + u) complex entries)
 constexpr int kSplitGatherMax = 4096; // split levels gather inside the first product up to this f
+constexpr int kStagedMaxTasks = 4;    // ... and while a front spans at most this many blocks
+                                      // (each block gathers the whole r_F again)
 
 struct Fac {
   const int64_t* f;
@@ -51,8 +55,11 @@ struct Fac {
   const int64_t* slot;  // U-list position -> its update slot (slots grouped by point)
 };
 
-// lanes per row for rows of c columns
+// lanes per row for rows of c columns: split products (few rows per block)
+// and one-block-per-front products (many rows per block, so fewer lanes per
+// row keep more rows in flight)
 int lanes_for(int64_t c) { return c >= 192 ? 64 : c >= 96 ? 32 : c >= 40 ? 16 : 8; }
+int lanes_for_fused(int64_t c) { return c >= 384 ? 64 : c >= 192 ? 32 : c >= 80 ? 16 : 8; }
 
 // r_eff = r[pt] - the updates sent to pt, which sit in the consecutive slots
 // upd_ptr[pt] .. upd_ptr[pt+1] in front order
@@ -123,7 +130,8 @@ __device__ inline double2 row_dot(const double* __restrict__ mrow, int64_t cols,
   return make_double2(ar, ai);
 }
 
-// forward, one block per front of the level
+// forward, one block per front of the level: rows i < f give y_F (stored in
+// Yc), rows f <= i < f + u the updates (stored in their slots)
 template <int LANES>
 __global__ __launch_bounds__(kThreads) void nd_fwd_fused_kernel(Fac fc, int64_t front0,
                                                                 const double2* __restrict__ r,
@@ -132,69 +140,54 @@ __global__ __launch_bounds__(kThreads) void nd_fwd_fused_kernel(Fac fc, int64_t 
   extern __shared__ double2 lds[];
   const int64_t k = front0 + blockIdx.x;
   const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
-  double2* R = lds;
-  double2* Y = lds + f;
   for (int64_t i = threadIdx.x; i < f; i += kThreads)
-    R[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
+    lds[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
   __syncthreads();
   constexpr int G = kThreads / LANES;
   const int g = threadIdx.x / LANES, sub = threadIdx.x % LANES;
   const double* Linv = fc.data + fc.off_blk[4 * k];
-  for (int64_t i0 = 0; i0 < f; i0 += G) {
+  const double* LUFL = fc.data + fc.off_blk[4 * k + 1];
+  for (int64_t i0 = 0; i0 < f + u; i0 += G) {
     const int64_t i = i0 + g;
-    const double2 y = row_dot<LANES>(Linv + i * f, f, sub, i < f, [&](int64_t j) { return R[j]; });
-    if (sub == 0 && i < f) {
-      Y[i] = y;
-      Yc[oF + i] = y;
+    const double* row = (i < f) ? Linv + i * f : LUFL + (i - f) * f;
+    const double2 y =
+        row_dot<LANES>(row, f, sub, i < f + u, [&](int64_t j) { return lds[j]; });
+    if (sub == 0 && i < f + u) {
+      if (i < f) Yc[oF + i] = y;
+      else Wslots[fc.slot[oU + i - f]] = y;
     }
-  }
-  __syncthreads();
-  const double* LUF = fc.data + fc.off_blk[4 * k + 1];
-  for (int64_t i0 = 0; i0 < u; i0 += G) {
-    const int64_t i = i0 + g;
-    const double2 w = row_dot<LANES>(LUF + i * f, f, sub, i < u, [&](int64_t j) { return Y[j]; });
-    if (sub == 0 && i < u) Wslots[fc.slot[oU + i]] = w;
   }
 }
 
-// backward, one block per front: LU lanes for the rows of U_FU (u columns),
-// LF for those of U_FF^-1 (f columns)
-template <int LU, int LF>
+// backward, one block per front: x_F = U_FF^-1 y_F - (U_FF^-1 U_FU) x_U with
+// y_F and x_U gathered into LDS
+template <int LANES>
 __global__ __launch_bounds__(kThreads) void nd_bwd_fused_kernel(Fac fc, int64_t front0,
                                                                 const double2* __restrict__ Yc,
                                                                 double2* __restrict__ X) {
   extern __shared__ double2 lds[];
   const int64_t k = front0 + blockIdx.x;
   const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
-  double2* XU = lds;
-  double2* T = lds + u;
+  double2* YF = lds;
+  double2* XU = lds + f;
+  for (int64_t j = threadIdx.x; j < f; j += kThreads) YF[j] = Yc[oF + j];
   for (int64_t j = threadIdx.x; j < u; j += kThreads) XU[j] = X[fc.idx_U[oU + j]];
   __syncthreads();
-  {
-    constexpr int G = kThreads / LU;
-    const int g = threadIdx.x / LU, sub = threadIdx.x % LU;
-    const double* UFU = fc.data + fc.off_blk[4 * k + 3];
-    for (int64_t i0 = 0; i0 < f; i0 += G) {
-      const int64_t i = i0 + g;
-      const double2 h = row_dot<LU>(UFU + i * u, u, sub, i < f, [&](int64_t j) { return XU[j]; });
-      if (sub == 0 && i < f) {
-        const double2 y = Yc[oF + i];
-        T[i] = make_double2(y.x - h.x, y.y - h.y);
-      }
-    }
-  }
-  __syncthreads();
-  constexpr int G = kThreads / LF;
-  const int g = threadIdx.x / LF, sub = threadIdx.x % LF;
+  constexpr int G = kThreads / LANES;
+  const int g = threadIdx.x / LANES, sub = threadIdx.x % LANES;
   const double* Uinv = fc.data + fc.off_blk[4 * k + 2];
+  const double* UU = fc.data + fc.off_blk[4 * k + 3];
   for (int64_t i0 = 0; i0 < f; i0 += G) {
     const int64_t i = i0 + g;
-    const double2 x = row_dot<LF>(Uinv + i * f, f, sub, i < f, [&](int64_t j) { return T[j]; });
-    if (sub == 0 && i < f) X[fc.idx_F[oF + i]] = x;
+    const bool act = i < f;
+    const double2 a = row_dot<LANES>(Uinv + i * f, f, sub, act, [&](int64_t j) { return YF[j]; });
+    const double2 b = row_dot<LANES>(UU + i * u, u, sub, act, [&](int64_t j) { return XU[j]; });
+    if (sub == 0 && act) X[fc.idx_F[oF + i]] = make_double2(a.x - b.x, a.y - b.y);
   }
 }
 
-// split levels: R[row] = r_eff of the point of F-list row `row`, rows [r0, r1)
+// split levels, gather: R[row] = r_eff of the point of F-list row `row`,
+// rows [r0, r1) (only for fronts too large to stage r_F in LDS)
 __global__ __launch_bounds__(kThreads) void nd_gather_kernel(Fac fc, const double2* __restrict__ r,
                                                              const double2* __restrict__ Wslots,
                                                              int64_t r0, int64_t r1,
@@ -204,127 +197,111 @@ __global__ __launch_bounds__(kThreads) void nd_gather_kernel(Fac fc, const doubl
   R[row] = gather_point(fc, r, Wslots, fc.idx_Fp[row]);
 }
 
-// split levels, first forward product with the gather folded in: each block
-// of a front gathers r_F of the whole front into LDS, then forms its rows of
-// y_F = L_FF^-1 r_F (f <= kSplitGatherMax)
-template <int LANES>
+// split levels, forward: one task = kThreads / LANES rows (of the f + u rows
+// of a front) of y_F and the updates. STAGED: each block gathers the front's
+// r_F into LDS; otherwise r_F is read from R (filled by nd_gather_kernel).
+template <int LANES, bool STAGED>
 __global__ __launch_bounds__(kThreads) void nd_fwd_split_kernel(Fac fc,
                                                                 const int2* __restrict__ tasks,
                                                                 const double2* __restrict__ r,
-                                                                const double2* __restrict__ Wslots,
-                                                                double2* __restrict__ Yc) {
+                                                                const double2* __restrict__ R,
+                                                                double2* __restrict__ Yc,
+                                                                double2* __restrict__ Wslots) {
   extern __shared__ double2 lds[];
   const int2 tk = tasks[blockIdx.x];
   const int64_t k = tk.x;
-  const int64_t f = fc.f[k], oF = fc.off_F[k];
-  for (int64_t i = threadIdx.x; i < f; i += kThreads)
-    lds[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
-  __syncthreads();
+  const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
+  if constexpr (STAGED) {
+    for (int64_t i = threadIdx.x; i < f; i += kThreads)
+      lds[i] = gather_point(fc, r, Wslots, fc.idx_Fp[oF + i]);
+    __syncthreads();
+  }
   const int sub = threadIdx.x % LANES;
   const int64_t i = tk.y + threadIdx.x / LANES;
-  const double* Linv = fc.data + fc.off_blk[4 * k];
-  const double2 y = row_dot<LANES>(Linv + i * f, f, sub, i < f, [&](int64_t j) { return lds[j]; });
-  if (sub == 0 && i < f) Yc[oF + i] = y;
-}
-
-enum { kFwdL = 0, kFwdLUF = 1, kBwdUFU = 2, kBwdU = 3 };
-
-// split levels: one task = kThreads / LANES rows of one front's product
-//   kFwdL    Yc[oF + i] = sum_j Linv[i][j] R[oF + j]            i < f
-//   kFwdLUF  W[oU + i]  = sum_j LUF[i][j] Yc[oF + j]            i < u
-//   kBwdUFU  T[oF + i]  = Yc[oF + i] - sum_j UFU[i][j] X[U[j]]  i < f
-//   kBwdU    X[F[i]]    = sum_j Uinv[i][j] T[oF + j]            i < f
-template <int MODE, int LANES>
-__global__ __launch_bounds__(kThreads) void nd_product_kernel(Fac fc, const int2* __restrict__ tasks,
-                                                              const double2* __restrict__ in,
-                                                              const double2* __restrict__ Yc,
-                                                              double2* __restrict__ out) {
-  const int2 tk = tasks[blockIdx.x];
-  const int64_t k = tk.x;
-  const int64_t fk = fc.f[k], uk = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
-  const int64_t rows = (MODE == kFwdLUF) ? uk : fk;
-  const int64_t cols = (MODE == kBwdUFU) ? uk : fk;
-  const int blk = (MODE == kFwdL) ? 0 : (MODE == kFwdLUF) ? 1 : (MODE == kBwdU) ? 2 : 3;
-  const double* mat = fc.data + fc.off_blk[4 * k + blk];
-  const int sub = threadIdx.x % LANES;
-  const int64_t i = tk.y + threadIdx.x / LANES;
-  const bool act = i < rows;
-  double2 acc;
-  if constexpr (MODE == kBwdUFU) {
-    const int64_t* U = fc.idx_U + oU;
-    acc = row_dot<LANES>(mat + i * cols, cols, sub, act, [&](int64_t j) { return in[U[j]]; });
+  const bool act = i < f + u;
+  const double* row = (i < f) ? fc.data + fc.off_blk[4 * k] + i * f
+                              : fc.data + fc.off_blk[4 * k + 1] + (i - f) * f;
+  double2 y;
+  if constexpr (STAGED) {
+    y = row_dot<LANES>(row, f, sub, act, [&](int64_t j) { return lds[j]; });
   } else {
-    acc = row_dot<LANES>(mat + i * cols, cols, sub, act, [&](int64_t j) { return in[oF + j]; });
+    y = row_dot<LANES>(row, f, sub, act, [&](int64_t j) { return R[oF + j]; });
   }
   if (sub != 0 || !act) return;
-  if constexpr (MODE == kFwdL) {
-    out[oF + i] = acc;
-  } else if constexpr (MODE == kFwdLUF) {
-    out[fc.slot[oU + i]] = acc;
-  } else if constexpr (MODE == kBwdUFU) {
-    const double2 y = Yc[oF + i];
-    out[oF + i] = make_double2(y.x - acc.x, y.y - acc.y);
-  } else {
-    out[fc.idx_F[oF + i]] = acc;
-  }
+  if (i < f) Yc[oF + i] = y;
+  else Wslots[fc.slot[oU + i - f]] = y;
 }
 
-template <int MODE>
-void launch_product(int lanes, int ntasks, hipStream_t st, const Fac& fc, const int2* tasks,
-                    const double2* in, const double2* Yc, double2* out) {
-  const dim3 grid(ntasks), block(kThreads);
-  switch (lanes) {
-    case 8: hipLaunchKernelGGL((nd_product_kernel<MODE, 8>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
-    case 16: hipLaunchKernelGGL((nd_product_kernel<MODE, 16>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
-    case 32: hipLaunchKernelGGL((nd_product_kernel<MODE, 32>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
-    default: hipLaunchKernelGGL((nd_product_kernel<MODE, 64>), grid, block, 0, st, fc, tasks, in, Yc, out); break;
-  }
+// split levels, backward: one task = kThreads / LANES rows of x_F
+template <int LANES>
+__global__ __launch_bounds__(kThreads) void nd_bwd_split_kernel(Fac fc,
+                                                                const int2* __restrict__ tasks,
+                                                                const double2* __restrict__ Yc,
+                                                                double2* __restrict__ X) {
+  const int2 tk = tasks[blockIdx.x];
+  const int64_t k = tk.x;
+  const int64_t f = fc.f[k], u = fc.u[k], oF = fc.off_F[k], oU = fc.off_U[k];
+  const int sub = threadIdx.x % LANES;
+  const int64_t i = tk.y + threadIdx.x / LANES;
+  const bool act = i < f;
+  const double* Uinv = fc.data + fc.off_blk[4 * k + 2];
+  const double* UU = fc.data + fc.off_blk[4 * k + 3];
+  const int64_t* U = fc.idx_U + oU;
+  const double2 a = row_dot<LANES>(Uinv + i * f, f, sub, act, [&](int64_t j) { return Yc[oF + j]; });
+  const double2 b = row_dot<LANES>(UU + i * u, u, sub, act, [&](int64_t j) { return X[U[j]]; });
+  if (sub == 0 && act) X[fc.idx_F[oF + i]] = make_double2(a.x - b.x, a.y - b.y);
 }
 
-void launch_fwd_split(int lanes, int ntasks, size_t lds, hipStream_t st, const Fac& fc,
-                      const int2* tasks, const double2* r, const double2* W, double2* Yc) {
-  const dim3 grid(ntasks), block(kThreads);
-  switch (lanes) {
-    case 8: hipLaunchKernelGGL(nd_fwd_split_kernel<8>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
-    case 16: hipLaunchKernelGGL(nd_fwd_split_kernel<16>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
-    case 32: hipLaunchKernelGGL(nd_fwd_split_kernel<32>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
-    default: hipLaunchKernelGGL(nd_fwd_split_kernel<64>, grid, block, lds, st, fc, tasks, r, W, Yc); break;
+#define LSP_LANES_SWITCH(lanes, CALL8, CALL16, CALL32, CALL64) \
+  switch (lanes) {                                             \
+    case 8: CALL8; break;                                      \
+    case 16: CALL16; break;                                    \
+    case 32: CALL32; break;                                    \
+    default: CALL64; break;                                    \
   }
-}
 
 void launch_fwd_fused(int lanes, int nfronts, size_t lds, hipStream_t st, const Fac& fc,
                       int64_t front0, const double2* r, double2* Yc, double2* W) {
   const dim3 grid(nfronts), block(kThreads);
-  switch (lanes) {
-    case 8: hipLaunchKernelGGL(nd_fwd_fused_kernel<8>, grid, block, lds, st, fc, front0, r, Yc, W); break;
-    case 16: hipLaunchKernelGGL(nd_fwd_fused_kernel<16>, grid, block, lds, st, fc, front0, r, Yc, W); break;
-    case 32: hipLaunchKernelGGL(nd_fwd_fused_kernel<32>, grid, block, lds, st, fc, front0, r, Yc, W); break;
-    default: hipLaunchKernelGGL(nd_fwd_fused_kernel<64>, grid, block, lds, st, fc, front0, r, Yc, W); break;
-  }
+  LSP_LANES_SWITCH(lanes,
+      hipLaunchKernelGGL(nd_fwd_fused_kernel<8>, grid, block, lds, st, fc, front0, r, Yc, W),
+      hipLaunchKernelGGL(nd_fwd_fused_kernel<16>, grid, block, lds, st, fc, front0, r, Yc, W),
+      hipLaunchKernelGGL(nd_fwd_fused_kernel<32>, grid, block, lds, st, fc, front0, r, Yc, W),
+      hipLaunchKernelGGL(nd_fwd_fused_kernel<64>, grid, block, lds, st, fc, front0, r, Yc, W))
 }
 
-template <int LU>
-void launch_bwd_fused_lf(int lf, const dim3& grid, size_t lds, hipStream_t st, const Fac& fc,
-                         int64_t front0, const double2* Yc, double2* X) {
-  const dim3 block(kThreads);
-  switch (lf) {
-    case 8: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 8>), grid, block, lds, st, fc, front0, Yc, X); break;
-    case 16: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 16>), grid, block, lds, st, fc, front0, Yc, X); break;
-    case 32: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 32>), grid, block, lds, st, fc, front0, Yc, X); break;
-    default: hipLaunchKernelGGL((nd_bwd_fused_kernel<LU, 64>), grid, block, lds, st, fc, front0, Yc, X); break;
-  }
-}
-
-void launch_bwd_fused(int lu, int lf, int nfronts, size_t lds, hipStream_t st, const Fac& fc,
+void launch_bwd_fused(int lanes, int nfronts, size_t lds, hipStream_t st, const Fac& fc,
                       int64_t front0, const double2* Yc, double2* X) {
-  const dim3 grid(nfronts);
-  switch (lu) {
-    case 8: launch_bwd_fused_lf<8>(lf, grid, lds, st, fc, front0, Yc, X); break;
-    case 16: launch_bwd_fused_lf<16>(lf, grid, lds, st, fc, front0, Yc, X); break;
-    case 32: launch_bwd_fused_lf<32>(lf, grid, lds, st, fc, front0, Yc, X); break;
-    default: launch_bwd_fused_lf<64>(lf, grid, lds, st, fc, front0, Yc, X); break;
-  }
+  const dim3 grid(nfronts), block(kThreads);
+  LSP_LANES_SWITCH(lanes,
+      hipLaunchKernelGGL(nd_bwd_fused_kernel<8>, grid, block, lds, st, fc, front0, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_fused_kernel<16>, grid, block, lds, st, fc, front0, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_fused_kernel<32>, grid, block, lds, st, fc, front0, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_fused_kernel<64>, grid, block, lds, st, fc, front0, Yc, X))
 }
+
+template <bool STAGED>
+void launch_fwd_split(int lanes, int ntasks, size_t lds, hipStream_t st, const Fac& fc,
+                      const int2* tasks, const double2* r, const double2* R, double2* Yc,
+                      double2* W) {
+  const dim3 grid(ntasks), block(kThreads);
+  LSP_LANES_SWITCH(lanes,
+      hipLaunchKernelGGL((nd_fwd_split_kernel<8, STAGED>), grid, block, lds, st, fc, tasks, r, R, Yc, W),
+      hipLaunchKernelGGL((nd_fwd_split_kernel<16, STAGED>), grid, block, lds, st, fc, tasks, r, R, Yc, W),
+      hipLaunchKernelGGL((nd_fwd_split_kernel<32, STAGED>), grid, block, lds, st, fc, tasks, r, R, Yc, W),
+      hipLaunchKernelGGL((nd_fwd_split_kernel<64, STAGED>), grid, block, lds, st, fc, tasks, r, R, Yc, W))
+}
+
+void launch_bwd_split(int lanes, int ntasks, hipStream_t st, const Fac& fc, const int2* tasks,
+                      const double2* Yc, double2* X) {
+  const dim3 grid(ntasks), block(kThreads);
+  LSP_LANES_SWITCH(lanes,
+      hipLaunchKernelGGL(nd_bwd_split_kernel<8>, grid, block, 0, st, fc, tasks, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_split_kernel<16>, grid, block, 0, st, fc, tasks, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_split_kernel<32>, grid, block, 0, st, fc, tasks, Yc, X),
+      hipLaunchKernelGGL(nd_bwd_split_kernel<64>, grid, block, 0, st, fc, tasks, Yc, X))
+}
+#undef LSP_LANES_SWITCH
 
 // device copy of count host entries (src NULL: allocation only)
 template <typename T>
@@ -348,7 +325,7 @@ void free_psolve(lsp_problem* p) {
   for (void* ptr : {(void*)s.f, (void*)s.u, (void*)s.off_F, (void*)s.off_U, (void*)s.idx_F,
                     (void*)s.idx_Fp, (void*)s.idx_U, (void*)s.off_blk, (void*)s.data,
                     (void*)s.upd_ptr, (void*)s.slot, (void*)s.tasks, (void*)s.R,
-                    (void*)s.Yc, (void*)s.T, (void*)s.W})
+                    (void*)s.Yc, (void*)s.W})
     if (ptr) (void)hipFree(ptr);
   s = NDSolve();
 }
@@ -363,33 +340,26 @@ hipError_t launch_psolve(const lsp_problem* p, const double* r_dev, double* z_de
   for (int l = 0; l < L; ++l) {
     const NDSolve::Level& lv = s.levels[l];
     if (lv.fused) {
-      launch_fwd_fused(lv.lanes_f, lv.nfronts, sizeof(double2) * 2 * lv.fmax, st, fc, lv.front0,
-                       r, s.Yc, s.W);
-      continue;
-    }
-    if (lv.fmax <= kSplitGatherMax) {
-      launch_fwd_split(lv.lanes_f, lv.ff_tasks, sizeof(double2) * lv.fmax, st, fc,
-                       s.tasks + lv.ff_task0, r, s.W, s.Yc);
+      launch_fwd_fused(lv.lanes_f, lv.nfronts, sizeof(double2) * lv.fmax, st, fc, lv.front0, r,
+                       s.Yc, s.W);
+    } else if (lv.staged) {
+      launch_fwd_split<true>(lv.lanes_f, lv.fwd_tasks, sizeof(double2) * lv.fmax, st, fc,
+                             s.tasks + lv.fwd_task0, r, s.R, s.Yc, s.W);
     } else {
       const int64_t nrow = lv.row1 - lv.row0;
       hipLaunchKernelGGL(nd_gather_kernel, dim3((unsigned)((nrow + kThreads - 1) / kThreads)),
                          dim3(kThreads), 0, st, fc, r, s.W, lv.row0, lv.row1, s.R);
-      launch_product<kFwdL>(lv.lanes_f, lv.ff_tasks, st, fc, s.tasks + lv.ff_task0, s.R, s.Yc,
-                            s.Yc);
+      launch_fwd_split<false>(lv.lanes_f, lv.fwd_tasks, 0, st, fc, s.tasks + lv.fwd_task0, r,
+                              s.R, s.Yc, s.W);
     }
-    if (lv.uf_tasks)
-      launch_product<kFwdLUF>(lv.lanes_f, lv.uf_tasks, st, fc, s.tasks + lv.uf_task0, s.Yc, s.Yc,
-                              s.W);
   }
   for (int l = L - 1; l >= 0; --l) {
     const NDSolve::Level& lv = s.levels[l];
-    if (lv.fused) {
-      launch_bwd_fused(lv.lanes_u, lv.lanes_f, lv.nfronts,
-                       sizeof(double2) * (lv.fmax + lv.umax), st, fc, lv.front0, s.Yc, X);
-      continue;
-    }
-    launch_product<kBwdUFU>(lv.lanes_u, lv.fu_tasks, st, fc, s.tasks + lv.fu_task0, X, s.Yc, s.T);
-    launch_product<kBwdU>(lv.lanes_f, lv.ff_tasks, st, fc, s.tasks + lv.ff_task0, s.T, s.Yc, X);
+    if (lv.fused)
+      launch_bwd_fused(lv.lanes_b, lv.nfronts, sizeof(double2) * (lv.fmax + lv.umax), st, fc,
+                       lv.front0, s.Yc, X);
+    else
+      launch_bwd_split(lv.lanes_b, lv.bwd_tasks, st, fc, s.tasks + lv.bwd_task0, s.Yc, X);
   }
   return hipGetLastError();
 }
@@ -462,26 +432,27 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
       lv.fmax = std::max(lv.fmax, fac->f[k]);
       lv.umax = std::max(lv.umax, fac->u[k]);
     }
-    lv.lanes_f = lanes_for(lv.fmax);
-    lv.lanes_u = lanes_for(lv.umax);
     lv.fused = lv.nfronts >= kFusedMinFronts && lv.fmax + lv.umax <= kFusedMaxFU;
+    lv.lanes_f = lv.fused ? lanes_for_fused(lv.fmax) : lanes_for(lv.fmax);
+    lv.lanes_b = lv.fused ? lanes_for_fused(std::max(lv.fmax, lv.umax))
+                          : lanes_for(std::max(lv.fmax, lv.umax));
+    lv.staged = lv.fmax <= kSplitGatherMax &&
+                (lv.fmax + lv.umax + kThreads / lv.lanes_f - 1) / (kThreads / lv.lanes_f) <=
+                    kStagedMaxTasks;
     if (!lv.fused) {
-      auto add = [&](int lanes, bool u_rows) {
+      auto add = [&](int lanes, bool with_u) {
         const int per = kThreads / lanes;
         for (int64_t k = a; k < b; ++k) {
-          const int64_t rows = u_rows ? fac->u[k] : fac->f[k];
+          const int64_t rows = fac->f[k] + (with_u ? fac->u[k] : 0);
           for (int64_t r0 = 0; r0 < rows; r0 += per) tasks.push_back(make_int2((int)k, (int)r0));
         }
       };
-      lv.ff_task0 = (int64_t)tasks.size();
-      add(lv.lanes_f, false);
-      lv.ff_tasks = (int)(tasks.size() - lv.ff_task0);
-      lv.uf_task0 = (int64_t)tasks.size();
+      lv.fwd_task0 = (int64_t)tasks.size();
       add(lv.lanes_f, true);
-      lv.uf_tasks = (int)(tasks.size() - lv.uf_task0);
-      lv.fu_task0 = (int64_t)tasks.size();
-      add(lv.lanes_u, false);
-      lv.fu_tasks = (int)(tasks.size() - lv.fu_task0);
+      lv.fwd_tasks = (int)(tasks.size() - lv.fwd_task0);
+      lv.bwd_task0 = (int64_t)tasks.size();
+      add(lv.lanes_b, false);
+      lv.bwd_tasks = (int)(tasks.size() - lv.bwd_task0);
     }
     levels.push_back(lv);
   }
@@ -502,7 +473,6 @@ int lsp_psolve_upload(lsp_problem* p, const lsp_nd_factors* fac) {
       (rc = up(&s.tasks, tasks.data(), tasks.size(), "tasks")) ||
       (rc = up<double2>(&s.R, nullptr, N, "solve buffer")) ||
       (rc = up<double2>(&s.Yc, nullptr, N, "solve buffer")) ||
-      (rc = up<double2>(&s.T, nullptr, N, "solve buffer")) ||
       (rc = up<double2>(&s.W, nullptr, nU, "update slots"))) {
     lsp::free_psolve(p);
     return rc;

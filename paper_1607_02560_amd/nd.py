@@ -153,9 +153,13 @@ class NDFactor:
 
     def export(self):
         """Plain arrays of the factors for the device solve: per front its
-        sizes and offsets, the index lists, the inverses of its triangular
-        blocks and its off-diagonal blocks, the front levels, and, per grid
-        point, the positions of the updates other fronts send to it."""
+        sizes and offsets, the index lists, four dense blocks, the front
+        levels, and, per grid point, the positions of the updates other fronts
+        send to it. The blocks are L_FF^-1, L_UF L_FF^-1, U_FF^-1 and
+        U_FF^-1 U_FU, so that with r_F the front's gathered right-hand side
+        both forward products (y_F = L_FF^-1 r_F and the updates
+        L_UF y_F = (L_UF L_FF^-1) r_F) read r_F only, and the backward step
+        x_F = U_FF^-1 y_F - (U_FF^-1 U_FU) x_U is one product per row."""
         nf = len(self.fronts)
         f_sz = np.array([f.F.size for f in self.fronts], dtype=np.int64)
         u_sz = np.array([f.U.size for f in self.fronts], dtype=np.int64)
@@ -166,14 +170,14 @@ class NDFactor:
         idx_U = (np.concatenate([f.U for f in self.fronts]) if u_sz.sum() else
                  np.zeros(0)).astype(np.int64)
         blocks = []
-        off_blk = np.zeros((nf, 4), dtype=np.int64)   # Linv, LUF, Uinv, UFU
+        off_blk = np.zeros((nf, 4), dtype=np.int64)   # Linv, LUF Linv, Uinv, Uinv UFU
         cur = 0
         for k in range(nf):
             f = int(f_sz[k])
             Linv = scipy.linalg.solve_triangular(self.L[k], np.eye(f), lower=True,
                                                  unit_diagonal=True)
             Uinv = scipy.linalg.solve_triangular(self.Ublk[k], np.eye(f), lower=False)
-            for j, blk in enumerate((Linv, self.LUF[k], Uinv, self.UFU[k])):
+            for j, blk in enumerate((Linv, self.LUF[k] @ Linv, Uinv, Uinv @ self.UFU[k])):
                 off_blk[k, j] = cur
                 blocks.append(np.ascontiguousarray(blk, dtype=np.float64).reshape(-1))
                 cur += blk.size

@@ -85,10 +85,10 @@ def test_nd_ordering_structure():
 
 def replay_device_algorithm(ex, r):
     """The device solve written out on the host from the exported arrays
-    (level by level: gather with the updates sent to each point, triangular
-    inverses as dense products, updates stored per U position; then the
-    backward pass), to check the export independently of the factor's own
-    solve."""
+    (level by level: gather with the updates sent to each point, y_F and the
+    updates as products with L_FF^-1 and L_UF L_FF^-1, updates stored per U
+    position; then the backward pass x_F = U_FF^-1 y_F - (U_FF^-1 U_FU) x_U),
+    to check the export independently of the factor's own solve."""
     N = ex["upd_ptr"].size - 1
     Y = np.zeros(N, dtype=r.dtype)
     X = np.zeros(N, dtype=r.dtype)
@@ -106,19 +106,19 @@ def replay_device_algorithm(ex, r):
             Linv = ex["data"][ob[k, 0]:ob[k, 0] + f * f].reshape(f, f)
             Y[F] = Linv @ reff
             if u:
-                LUF = ex["data"][ob[k, 1]:ob[k, 1] + u * f].reshape(u, f)
-                Wbuf[ex["off_U"][k]:ex["off_U"][k] + u] = LUF @ Y[F]
+                LUFL = ex["data"][ob[k, 1]:ob[k, 1] + u * f].reshape(u, f)
+                Wbuf[ex["off_U"][k]:ex["off_U"][k] + u] = LUFL @ reff
     for lv in range(nlev - 1, -1, -1):
         for k in ex["lev_fronts"][ex["lev_ptr"][lv]:ex["lev_ptr"][lv + 1]]:
             f, u = ex["f"][k], ex["u"][k]
             F = ex["idx_F"][ex["off_F"][k]:ex["off_F"][k] + f]
             U = ex["idx_U"][ex["off_U"][k]:ex["off_U"][k] + u]
-            t = Y[F].copy()
-            if u:
-                UFU = ex["data"][ob[k, 3]:ob[k, 3] + f * u].reshape(f, u)
-                t -= UFU @ X[U]
             Uinv = ex["data"][ob[k, 2]:ob[k, 2] + f * f].reshape(f, f)
-            X[F] = Uinv @ t
+            x = Uinv @ Y[F]
+            if u:
+                UU = ex["data"][ob[k, 3]:ob[k, 3] + f * u].reshape(f, u)
+                x -= UU @ X[U]
+            X[F] = x
     return X
 
 
