@@ -145,6 +145,94 @@ __global__ __launch_bounds__(256) void assemble_kernel(
                                   idx_out);
 }
 
+// 2D assembly with the shift tables in LDS. The (alpha, C) gathers of the
+// kernel above go through L1 (16 B per entry, spread over the points' shift
+// rows), which bounds it above its store floor in the FP32 form. Here a
+// block owns TR rows of TW points and first copies the nS x M table into LDS
+// (kActLds pairs at most), so the per-entry gathers read LDS; the copy is
+// amortised over the TR rows. Same stores, same arithmetic, same rows.
+constexpr int kActLds = 2048;  // (alpha, C) pairs staged in LDS: 32 KB
+
+template <int W, int TR, int TW, typename PT>
+__global__ __launch_bounds__(256) void assemble_lds_kernel(
+    const double* __restrict__ v, int n, const double* __restrict__ S,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
+    int32_t* __restrict__ idx_out) {
+  constexpr int t = (W - 1) / 2;
+  constexpr int M = W * W;
+  constexpr int HR = TR + 2 * t;
+  constexpr int HC = TW + 2 * t;
+  __shared__ double halo[HR * HC];
+  __shared__ double sS[kActLds / M];  // nS <= kActLds / M on this path
+  __shared__ double2 sAct[kActLds];
+  __shared__ int spM[TR * TW];
+  __shared__ double spS[TR * TW];
+  __shared__ int soff[M];
+  const int tid = threadIdx.x;
+  const int nS = *nS_ptr;
+  const int c0 = blockIdx.x * TW;
+  const int r0 = blockIdx.y * TR;
+  const int mask = n - 1;
+  for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  for (int i = tid; i < nS * M; i += 256) sAct[i] = actab[i];
+  for (int a = tid; a < M; a += 256) soff[a] = (a / W) * HC + a % W;
+  for (int e = tid; e < HR * HC; e += 256) {
+    const int hc = e % HC, hr = e / HC;
+    halo[e] = v[(int64_t)((r0 - t + hr) & mask) * n + ((c0 - t + hc) & mask)];
+  }
+  __syncthreads();
+  for (int pt = tid; pt < TR * TW; pt += 256) {
+    const int r = pt / TW, c = pt % TW;
+    const int best = nearest_shift(sS, nS, halo[(r + t) * HC + c + t]);
+    spM[pt] = best * M;
+    spS[pt] = sS[best];
+    if (idx_out) idx_out[(int64_t)(r0 + r) * n + c0 + c] = best;
+  }
+  __syncthreads();
+  // whole-point store steps as in assemble_body, once per row of the tile
+  constexpr int VEC = 16 / (int)sizeof(PT);
+  constexpr int SPAN = TW * M;
+  constexpr int TACT = 256 - 256 % M;
+  constexpr int STEP = VEC * TACT;
+  constexpr int DP = STEP / M;
+  static_assert(SPAN % VEC == 0 && STEP % M == 0, "whole stores, whole points per step");
+  if (tid >= TACT) return;
+  const int e0 = VEC * tid;
+  const int pt0 = e0 / M;
+  int aoff[VEC], hoff[VEC], pinc[VEC];
+#pragma unroll
+  for (int h = 0; h < VEC; ++h) {
+    const int e = e0 + h;
+    pinc[h] = e / M - pt0;
+    aoff[h] = e % M;
+    hoff[h] = soff[aoff[h]] + pinc[h];
+  }
+#pragma unroll 1
+  for (int rr = 0; rr < TR; ++rr) {
+    PT* Prow = P + ((int64_t)(r0 + rr) * n + c0) * M;
+    const int qb = rr * TW;       // the row's first point in the tile
+    const int hb = rr * HC;       // its halo row
+    int pp = pt0;
+    for (int e = e0; e < SPAN; e += STEP, pp += DP) {
+      double outv[VEC];
+#pragma unroll
+      for (int h = 0; h < VEC; ++h) {
+        const int q = qb + pp + pinc[h];
+        const double s = spS[q];
+        const double2 ac = sAct[spM[q] + aoff[h]];
+        const double va = halo[hb + pp + hoff[h]];
+        outv[h] = ac.x + ac.y * (va - s);
+      }
+      if constexpr (VEC == 2) {
+        reinterpret_cast<double2*>(Prow)[e >> 1] = make_double2(outv[0], outv[1]);
+      } else {
+        reinterpret_cast<float4*>(Prow)[e >> 2] =
+            make_float4((float)outv[0], (float)outv[1], (float)outv[2], (float)outv[3]);
+      }
+    }
+  }
+}
+
 // one launch for the problems of a batch: block b is tile (map[b].y, map[b].z,
 // map[b].w) of problem map[b].x
 template <int D, int W, int TR, int TW, typename PT>
@@ -277,6 +365,20 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
   }
 }
 
+template <int W, int TR, int TW>
+hipError_t run_assemble_lds(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
+  const int n = p->n;
+  dim3 grid(n / TW, n / TR);
+  const double2* act = reinterpret_cast<const double2*>(p->ws.actab);
+  if (fp32)
+    hipLaunchKernelGGL((assemble_lds_kernel<W, TR, TW, float>), grid, dim3(256), 0, p->stream,
+                       p->v, n, p->ws.S, p->ws.nS, act, static_cast<float*>(P), idx);
+  else
+    hipLaunchKernelGGL((assemble_lds_kernel<W, TR, TW, double>), grid, dim3(256), 0, p->stream,
+                       p->v, n, p->ws.S, p->ws.nS, act, static_cast<double*>(P), idx);
+  return hipGetLastError();
+}
+
 template <int D, int W, int TW, int TR>
 hipError_t run_assemble_tile(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   const int n = p->n;
@@ -316,6 +418,10 @@ hipError_t run_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   }
   if constexpr (D == 2) {
     if (p->n == 64) return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
+    // FP32 rows: the tables fit in LDS (the requested |S| bounds the
+    // effective one) and the grid of 4-row tiles still fills the chip
+    if (fp32 && p->n >= 512 && p->num_shifts * W * W <= kActLds)
+      return run_assemble_lds<W, 4, 128>(p, P, fp32, idx);
     return run_assemble_tile<D, W, 128, 1>(p, P, fp32, idx);
   } else {
     return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
