@@ -666,6 +666,12 @@ def main():
                              "unit": "GB/s", "frac": capply_gbps / HBM_PEAK_GBPS,
                              "bytes_per_call": nb["c_apply"]},
     }
+    # the launch-shape tuner on the same problem (after the measurements
+    # above, which use the built-in shapes)
+    out["autotune"] = {"choices_and_ms": prob.autotune(t, p.num_shifts, P, u, y, reps=5),
+                       "note": "fastest candidate per shape; the headline uses the built-in "
+                               "shapes"}
+    prob.set_tuning()
     if not args.no_extras:
         out["non_localized"] = non_localized_section(dev, t_setup_g, N)
         # the per-point radius of Sec. 4.2 (leaf box 8, t <= 2) on the same field

@@ -320,6 +320,40 @@ enum {
 int lsp_profile(lsp_problem* p, int enable);
 int lsp_profile_read(lsp_problem* p, int nstages, double* ms_host, int* count_host);
 
+/*
+ * Launch-shape tuning (not in the paper). Three shapes of this problem's
+ * kernels can be chosen per problem; 0 selects the built-in default:
+ *   LSP_TUNE_GREEN_WAVES    2D: the most waves of the Green's-sum launch
+ *                           (512, 1024, 1536 or 2048);
+ *   LSP_TUNE_ASSEMBLY_TILE  2D, n >= 128: the assembly's tile, 32, 64 or 128
+ *                           points of one row, or 1 for 4 x 128 tiles with
+ *                           the shift tables staged in LDS;
+ *   LSP_TUNE_APPLY_FORM     n = 256, 512, 1024: the apply's line transform
+ *                           with 8 or 16 values per thread.
+ * The assembly tile does not change any result; the Green's wave count and
+ * the apply form change the order of summation (results agree to rounding).
+ * lsp_autotune runs the setup (t, num_shifts, precision, P_dev as for
+ * lsp_stencil_setup) and the apply (u_dev to y_dev, N complex128 each) with
+ * every candidate of each shape in turn, reps timed calls each (HIP events on
+ * the problem's stream), keeps the fastest, and writes the choices to
+ * choice_host[LSP_TUNE_COUNT] and the chosen mean times (ms: setup, setup,
+ * apply) to ms_host[LSP_TUNE_COUNT] (either may be NULL). The setup's outputs
+ * then hold the last candidate's results. Synchronous.
+ * lsp_set_tuning sets the choices directly (LSP_EINVAL for a value outside
+ * the lists above); lsp_get_tuning reads them.
+ */
+enum {
+  LSP_TUNE_GREEN_WAVES = 0,
+  LSP_TUNE_ASSEMBLY_TILE = 1,
+  LSP_TUNE_APPLY_FORM = 2,
+  LSP_TUNE_COUNT = 3
+};
+int lsp_autotune(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
+                 const double* u_dev, double* y_dev, int reps, int* choice_host,
+                 double* ms_host);
+int lsp_set_tuning(lsp_problem* p, const int* choice_host);
+int lsp_get_tuning(const lsp_problem* p, int* choice_host);
+
 /* Number of stencil entries m = (2t+1)^d of the last setup (0 before setup). */
 int lsp_stencil_size(const lsp_problem* p);
 

@@ -418,10 +418,17 @@ hipError_t run_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
   }
   if constexpr (D == 2) {
     if (p->n == 64) return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
+    // a tuned shape (lsp_autotune): 1-row tiles of 32, 64 or 128 points, or
+    // (code 1) the LDS-table kernel
+    const int tuned = p->tune[LSP_TUNE_ASSEMBLY_TILE];
+    const bool lds_ok = p->num_shifts * W * W <= kActLds;
+    if (tuned == 32) return run_assemble_tile<D, W, 32, 1>(p, P, fp32, idx);
+    if (tuned == 64) return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
+    if (tuned == 128) return run_assemble_tile<D, W, 128, 1>(p, P, fp32, idx);
+    if (tuned == 1 && lds_ok) return run_assemble_lds<W, 4, 128>(p, P, fp32, idx);
     // FP32 rows: the tables fit in LDS (the requested |S| bounds the
     // effective one) and the grid of 4-row tiles still fills the chip
-    if (fp32 && p->n >= 512 && p->num_shifts * W * W <= kActLds)
-      return run_assemble_lds<W, 4, 128>(p, P, fp32, idx);
+    if (fp32 && p->n >= 512 && lds_ok) return run_assemble_lds<W, 4, 128>(p, P, fp32, idx);
     return run_assemble_tile<D, W, 128, 1>(p, P, fp32, idx);
   } else {
     return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);

@@ -659,7 +659,7 @@ hipError_t run_green(const lsp_problem* p, int num_shifts) {
   if constexpr (D == 2) {
     if (hipError_t e = allow_lds(&green2d_kernel<W>, Green2d<W>::kBlockLds); e != hipSuccess)
       return e;
-    const int nwv = lsp::green2d_waves(p->n, num_shifts);
+    const int nwv = lsp::green2d_waves(p->n, num_shifts, p->tune[LSP_TUNE_GREEN_WAVES]);
     const size_t need = (size_t)(nwv + num_shifts) * GreenLayout<2, W>::NV;
     if (need > p->ws.green_part_cap) return hipErrorInvalidValue;
     // the per-wave LDS areas of the lane sums also cap the residency at two
@@ -687,7 +687,7 @@ hipError_t run_green(const lsp_problem* p, int num_shifts) {
 
 namespace lsp {
 
-int green2d_waves(int n, int num_shifts) {
+int green2d_waves(int n, int num_shifts, int max_waves) {
   const int Ht = n / 2;
   const int KT = Ht < kTile ? Ht : kTile;
   const int T = Ht / KT;
@@ -696,7 +696,8 @@ int green2d_waves(int n, int num_shifts) {
   // of a wave's work), at most 2048 waves (two per SIMD of a 256-CU part),
   // a whole number of 4-wave blocks
   int64_t w = (steps + 31) / 32;
-  w = std::max<int64_t>(kWaves, std::min<int64_t>(2048, w));
+  const int64_t cap = (max_waves > 0 && max_waves <= 2048) ? max_waves : 2048;
+  w = std::max<int64_t>(kWaves, std::min<int64_t>(cap, w));
   return (int)((w + kWaves - 1) / kWaves * kWaves);
 }
 

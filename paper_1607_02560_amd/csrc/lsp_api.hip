@@ -404,6 +404,105 @@ void lsp_destroy(lsp_problem* p) {
   delete p;
 }
 
+namespace {
+// the candidates of each tuned shape (0: the default)
+bool tune_value_ok(int knob, int v) {
+  switch (knob) {
+    case LSP_TUNE_GREEN_WAVES: return v == 0 || v == 512 || v == 1024 || v == 1536 || v == 2048;
+    case LSP_TUNE_ASSEMBLY_TILE: return v == 0 || v == 1 || v == 32 || v == 64 || v == 128;
+    case LSP_TUNE_APPLY_FORM: return v == 0 || v == 8 || v == 16;
+    default: return false;
+  }
+}
+}  // namespace
+
+int lsp_set_tuning(lsp_problem* p, const int* choice_host) {
+  if (!p || !choice_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  for (int k = 0; k < LSP_TUNE_COUNT; ++k)
+    if (!tune_value_ok(k, choice_host[k]))
+      return lsp::set_error(LSP_EINVAL, "tuning value " + std::to_string(choice_host[k]) +
+                                            " is not a candidate of shape " + std::to_string(k));
+  (void)hipStreamSynchronize(p->stream);
+  for (int k = 0; k < LSP_TUNE_COUNT; ++k) p->tune[k] = choice_host[k];
+  ++p->ws_gen;  // cached graphs hold the old shapes
+  return LSP_OK;
+}
+
+int lsp_get_tuning(const lsp_problem* p, int* choice_host) {
+  if (!p || !choice_host) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  for (int k = 0; k < LSP_TUNE_COUNT; ++k) choice_host[k] = p->tune[k];
+  return LSP_OK;
+}
+
+int lsp_autotune(lsp_problem* p, int t, int num_shifts, int precision, void* P_dev,
+                 const double* u_dev, double* y_dev, int reps, int* choice_host,
+                 double* ms_host) {
+  if (!p || !P_dev || !u_dev || !y_dev) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  if (reps < 1 || reps > 1000) return lsp::set_error(LSP_EINVAL, "reps must be in 1..1000");
+  hipStream_t s = p->stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return lsp::set_error(LSP_EHIP, "event creation failed");
+  }
+  // mean time of reps calls of one candidate (after one untimed call)
+  auto time_it = [&](bool setup, double* ms) -> int {
+    auto call = [&]() -> int {
+      return setup ? lsp_stencil_setup(p, t, num_shifts, precision, P_dev, nullptr)
+                   : lsp_ps_apply(p, u_dev, y_dev);
+    };
+    int rc = call();
+    if (rc < 0) return rc;
+    if (hipEventRecord(e0, s) != hipSuccess) return lsp::set_error(LSP_EHIP, "event record");
+    for (int i = 0; i < reps; ++i)
+      if ((rc = call()) < 0) return rc;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return lsp::set_error(LSP_EHIP, "event wait");
+    float f = 0.f;
+    if (hipEventElapsedTime(&f, e0, e1) != hipSuccess) return lsp::set_error(LSP_EHIP, "event time");
+    *ms = (double)f / reps;
+    return LSP_OK;
+  };
+  const int n = p->n;
+  std::vector<int> cand[LSP_TUNE_COUNT];
+  if (p->d == 2) cand[LSP_TUNE_GREEN_WAVES] = {512, 1024, 1536, 2048};
+  if (p->d == 2 && n >= 128) cand[LSP_TUNE_ASSEMBLY_TILE] = {32, 64, 128, 1};
+  if (n == 256 || n == 512 || n == 1024) cand[LSP_TUNE_APPLY_FORM] = {8, 16};
+  int rc = LSP_OK;
+  double best_ms[LSP_TUNE_COUNT] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < LSP_TUNE_COUNT && rc == LSP_OK; ++k) {
+    const bool setup = (k != LSP_TUNE_APPLY_FORM);
+    if (cand[k].empty()) {
+      p->tune[k] = 0;
+      rc = time_it(setup, &best_ms[k]);
+      continue;
+    }
+    int best = 0;
+    double bms = 0.0;
+    for (int v : cand[k]) {
+      p->tune[k] = v;
+      ++p->ws_gen;
+      double ms = 0.0;
+      if ((rc = time_it(setup, &ms)) != LSP_OK) break;
+      if (best == 0 || ms < bms) {
+        best = v;
+        bms = ms;
+      }
+    }
+    p->tune[k] = best;
+    ++p->ws_gen;
+    best_ms[k] = bms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != LSP_OK) return rc;
+  for (int k = 0; k < LSP_TUNE_COUNT; ++k) {
+    if (choice_host) choice_host[k] = p->tune[k];
+    if (ms_host) ms_host[k] = best_ms[k];
+  }
+  return LSP_OK;
+}
+
 int lsp_stencil_size(const lsp_problem* p) { return (p && p->have_setup) ? p->m : 0; }
 
 int lsp_profile(lsp_problem* p, int enable) {

@@ -160,6 +160,8 @@ struct lsp_problem {
   uint64_t ws_gen = 1;        // bumped whenever a workspace pointer changes
   bool use_graphs = true;
   bool krylov_graphs = true;   // capture the Arnoldi step of the device GMRES
+  // launch shapes chosen by lsp_autotune / lsp_set_tuning (0: the default)
+  int tune[LSP_TUNE_COUNT] = {0, 0, 0};
   // per-stage event timing (lsp_profile)
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;                 // created events, reused
@@ -223,7 +225,9 @@ hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, dou
 hipError_t launch_green_sums(lsp_problem* p, int num_shifts);
 // waves of the balanced 2D Green's launch for (n, requested |S|) and its steps
 // per shift; a function of the arguments only, shared by single and batched launches
-int green2d_waves(int n, int num_shifts);
+// waves of the balanced 2D Green's launch; max_waves (a multiple of 4,
+// <= 2048) caps the count, 0 = the default cap of 2048
+int green2d_waves(int n, int num_shifts, int max_waves = 0);
 int green2d_sps(int n);
 // work units of the 3D Green's-sum launch for (d, n), packed (outer tile << 16) | k tile
 void green_units(int d, int n, std::vector<int>& units);

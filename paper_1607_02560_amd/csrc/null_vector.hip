@@ -624,7 +624,7 @@ template <int D, int W>
 hipError_t run_null(const lsp_problem* p, int num_shifts, int* clear_counter) {
   const double invN = 1.0 / (double)p->N;
   const int sps = (D == 2) ? lsp::green2d_sps(p->n) : 0;
-  const int nwv = (D == 2) ? lsp::green2d_waves(p->n, num_shifts) : 0;
+  const int nwv = (D == 2) ? lsp::green2d_waves(p->n, num_shifts, p->tune[LSP_TUNE_GREEN_WAVES]) : 0;
   hipLaunchKernelGGL((null_vector_kernel<D, W>), dim3(num_shifts), dim3(64 * (1 << D)), 0,
                      p->stream, p->ws.nS, p->ws.green_part, p->green_nunits, sps, nwv, invN,
                      p->ws.gtab, p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab, p->ws.sigma,
@@ -657,7 +657,7 @@ hipError_t launch_null_nd(lsp_problem* p, int num_shifts, const NdTables1& t1) {
   if (p->t != 2 || (p->d != 2 && p->d != 3)) return hipErrorInvalidValue;
   const double invN = 1.0 / (double)p->N;
   const int sps = (p->d == 2) ? lsp::green2d_sps(p->n) : 0;
-  const int nwv = (p->d == 2) ? lsp::green2d_waves(p->n, num_shifts) : 0;
+  const int nwv = (p->d == 2) ? lsp::green2d_waves(p->n, num_shifts, p->tune[LSP_TUNE_GREEN_WAVES]) : 0;
   const NullOut o2{p->ws.gtab, p->ws.gamtab, p->ws.Mtab, p->ws.alpha, p->ws.Ctab,
                    p->ws.sigma, p->ws.rho, p->ws.actab, p->ws.status};
   const NullOut o1{t1.gtab, t1.gamtab, t1.Mtab, t1.alpha, t1.C,

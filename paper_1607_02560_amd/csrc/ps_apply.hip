@@ -963,9 +963,15 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hip
     // measured per pass at n = 1024: 12.7 + 14.9 us (8 values per thread)
     // against 12.8 + 15.5 us (16 values); at 256 and 512 the 16-value form
     // is 0.1-0.4 us faster
-    case 256: return run_fft_apply<1>(p, u2, y2, s);
-    case 512: return run_fft_apply<2>(p, u2, y2, s);
-    case 1024: return run_fft8_apply<16>(p, u2, y2, s);
+    case 256:
+      return p->tune[LSP_TUNE_APPLY_FORM] == 8 ? run_fft8_apply<4>(p, u2, y2, s)
+                                               : run_fft_apply<1>(p, u2, y2, s);
+    case 512:
+      return p->tune[LSP_TUNE_APPLY_FORM] == 8 ? run_fft8_apply<8>(p, u2, y2, s)
+                                               : run_fft_apply<2>(p, u2, y2, s);
+    case 1024:
+      return p->tune[LSP_TUNE_APPLY_FORM] == 16 ? run_fft_apply<4>(p, u2, y2, s)
+                                                : run_fft8_apply<16>(p, u2, y2, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -118,6 +118,10 @@ def load():
         "lsp_batch_tile": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p]),
         "lsp_get_tables_nd1": (c_int, [c_void_p, c_int, P(c_int), c_void_p, c_void_p,
                                        c_void_p, c_void_p, c_void_p]),
+        "lsp_autotune": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                 c_int, c_void_p, c_void_p]),
+        "lsp_set_tuning": (c_int, [c_void_p, c_void_p]),
+        "lsp_get_tuning": (c_int, [c_void_p, c_void_p]),
         "lsp_psolve_upload": (c_int, [c_void_p, P(NDFactors)]),
         "lsp_psolve_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_precond_solve_device": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_int,
@@ -318,6 +322,36 @@ class Problem:
             raise LSPError(code, "lsp_precond_solve") from errors[0]
         _check(code, "lsp_precond_solve")
         return code, iters.value, relres.value
+
+    TUNE_KEYS = ("green_waves", "assembly_tile", "apply_form")
+
+    def autotune(self, t: int, num_shifts: int, P, u, y, precision: int = LSP_FP64,
+                 reps: int = 10) -> dict:
+        """Time every candidate launch shape on this problem and keep the
+        fastest; returns {shape: (choice, mean ms)}. P receives setup rows,
+        y the apply's output."""
+        import torch
+        m = (2 * t + 1) ** self.d
+        dt = torch.float32 if precision == LSP_FP32_REFINE else torch.float64
+        _need(P, dt, self.N * m, "P")
+        _need(u, torch.complex128, self.N, "u")
+        _need(y, torch.complex128, self.N, "y")
+        ch = np.zeros(3, dtype=np.int32)
+        ms = np.zeros(3)
+        _check(self.lib.lsp_autotune(self._h, t, num_shifts, precision, _ptr(P), _ptr(u),
+                                     _ptr(y), reps, ch.ctypes.data, ms.ctypes.data),
+               "lsp_autotune")
+        self.t, self.m = t, m
+        return {k: (int(c), float(v)) for k, c, v in zip(self.TUNE_KEYS, ch, ms)}
+
+    def set_tuning(self, green_waves: int = 0, assembly_tile: int = 0, apply_form: int = 0):
+        ch = np.array([green_waves, assembly_tile, apply_form], dtype=np.int32)
+        _check(self.lib.lsp_set_tuning(self._h, ch.ctypes.data), "lsp_set_tuning")
+
+    def get_tuning(self) -> dict:
+        ch = np.zeros(3, dtype=np.int32)
+        _check(self.lib.lsp_get_tuning(self._h, ch.ctypes.data), "lsp_get_tuning")
+        return dict(zip(self.TUNE_KEYS, (int(c) for c in ch)))
 
     def psolve_upload(self, factors):
         """Copy nested-dissection factors of P to the device: an nd.NDFactor
