@@ -42,3 +42,47 @@ def test_single_precision_sums_lose_alpha():
         assert max(e64) < 1e-8, e64
         assert max(e32) > 0.1, e32
         assert np.median(e32) > 1e-2, e32
+
+
+def refined_errors(n, nshift=4, steps=2):
+    """alpha from FP32 Green's sums, then `steps` FP64 inverse-iteration steps
+    (a <- M^-1 a, normalised) against the Gram matrix from the FP32 sums and
+    against the one from FP64 sums."""
+    p = W.helm2d_random(n, t=2)
+    S = O.shift_list(p.v, max(1, n // 16))
+    offs = O.offsets(2, 2)
+    lam = O.symbol(2, n)
+    out = []
+    for s in S[:nshift]:
+        g, gam = O.green_kernels(2, n, s)
+        M64 = O.gram(g, gam, offs)[3]
+        a64 = O.null_vector(M64)[0]
+        r = (1.0 / (lam.astype(np.float32) + np.float32(s))).astype(np.float32)
+        gq = np.real(sf.ifftn(r.astype(np.complex64))).astype(np.float64)
+        gg = np.real(sf.ifftn((r * r).astype(np.complex64))).astype(np.float64)
+        M32 = O.gram(gq, gg, offs)[3]
+        a32 = O.null_vector(M32)[0]
+        res = {}
+        for name, M in (("against_fp32_gram", M32), ("against_fp64_gram", M64)):
+            a = a32.copy()
+            for _ in range(steps):
+                a = np.linalg.solve(M, a)
+                a /= np.linalg.norm(a)
+            res[name] = np.linalg.norm(np.sign(a @ a64) * a - a64)
+        out.append(res)
+    return out
+
+
+def test_fp64_refinement_needs_the_fp64_gram_matrix():
+    """The precision form 'FP32 contraction, then an FP64 refinement of alpha'
+    only helps if the refinement runs against the FP64 Gram matrix, which
+    needs the FP64 Green's sums, the whole cost of the FP64 route. Refined
+    against the FP32 Gram matrix, alpha stays as wrong as before."""
+    for steps, bound in ((2, 1e-2), (8, 1e-7)):
+        errs = refined_errors(128, steps=steps)
+        e32 = [e["against_fp32_gram"] for e in errs]
+        e64 = [e["against_fp64_gram"] for e in errs]
+        # measured: FP64 Gram 1.6e-4..5e-3 after 2 steps, 3e-10..1.4e-8 after 8;
+        # FP32 Gram 0.1..1.2 after any number of steps
+        assert max(e64) < bound, (steps, e64)
+        assert np.median(e32) > 1e-2, (steps, e32)
