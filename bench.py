@@ -58,8 +58,8 @@ BF16_PEAK_TFLOPS = 2500.0  # dense BF16 MFMA
 # sources they were taken on (sha256 prefix of the files below); for any
 # other sources the traffic is reported as null.
 ASSEMBLE_PMC = {
-    "fetch_kib": 5292.6, "write_kib": 205854.1,
-    "fetch_scale": 262144.0 / 131093.9, "write_scale": 262144.0 / 262144.0,
+    "fetch_kib": 5289.6, "write_kib": 208927.6,
+    "fetch_scale": 262144.0 / 131088.6, "write_scale": 262144.0 / 262144.0,
     "sources": ("paper_1607_02560_amd/csrc/assemble.hip",
                 "paper_1607_02560_amd/csrc/setup_common.h"),
     "sources_sha256": "997073233fc08094",
@@ -666,13 +666,13 @@ def main():
                              "unit": "GB/s", "frac": capply_gbps / HBM_PEAK_GBPS,
                              "bytes_per_call": nb["c_apply"]},
     }
-    # the launch-shape tuner on the same problem (after the measurements
-    # above, which use the built-in shapes)
-    out["autotune"] = {"choices_and_ms": prob.autotune(t, p.num_shifts, P, u, y, reps=5),
-                       "note": "fastest candidate per shape; the headline uses the built-in "
-                               "shapes"}
-    prob.set_tuning()
     if not args.no_extras:
+        # the launch-shape tuner on the same problem (after the measurements
+        # above, which use the built-in shapes)
+        out["autotune"] = {"choices_and_ms": prob.autotune(t, p.num_shifts, P, u, y, reps=5),
+                           "note": "fastest candidate per shape; the headline uses the "
+                                   "built-in shapes"}
+        prob.set_tuning()
         out["non_localized"] = non_localized_section(dev, t_setup_g, N)
         # the per-point radius of Sec. 4.2 (leaf box 8, t <= 2) on the same field
         setup_nd = lambda: prob.stencil_setup_nd(8, p.num_shifts, P, idx)
