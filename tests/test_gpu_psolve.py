@@ -46,8 +46,9 @@ def sparse_rows(rows, d, n, t):
     return P
 
 
-def setup(torch_dev, p, t, nd_leaf=None, stream=None):
-    """Problem, its P rows (host) and the nested-dissection factors of P."""
+def setup(torch_dev, p, t, nd_leaf=None, stream=None, leaf=None):
+    """Problem, its P rows (host) and the nested-dissection factors of P
+    (leaf box `leaf`, else the per-point radius's leaf box, else 8)."""
     torch, dev = torch_dev
     lsp = lsp_mod()
     d, n = p.d, p.n
@@ -62,7 +63,7 @@ def setup(torch_dev, p, t, nd_leaf=None, stream=None):
     torch.cuda.synchronize()
     rows = P.cpu().numpy().reshape(p.N, m)
     S = sparse_rows(rows, d, n, t)
-    F = nd.factor(S, d, n, nd_leaf or 8)
+    F = nd.factor(S, d, n, leaf or nd_leaf or 8)
     prob.psolve_upload(F)
     return prob, S, F
 
@@ -100,6 +101,55 @@ def test_device_psolve(torch_dev, name, t, leaf):
     prob.psolve_apply(rt, z2)
     torch.cuda.synchronize()
     assert np.array_equal(z2.cpu().numpy(), z)
+    prob.close()
+
+
+@pytest.mark.parametrize("leaf,t", [(4, 1), (8, 2)])
+def test_device_psolve_3d(torch_dev, leaf, t):
+    """3D (n = 16, three merge axes, separator planes): uniform t = 1 rows with
+    leaf box 4, and the per-point radius with leaf box 8; the device solve
+    against scipy's direct solve and the host solve of the same factors, and
+    device GMRES against the oracle's count."""
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    p = W.helm3d_random(16)
+    print(f"[psolve 3d] n=16 leaf={leaf} t={t}", flush=True)
+    if t == 2:
+        prob, S, F = setup(torch_dev, p, 2, nd_leaf=leaf)
+    else:
+        prob, S, F = setup(torch_dev, p, 1, leaf=leaf)
+    x = rand_c(p.N, 7)
+    zt = torch.empty(p.N, dtype=torch.complex128, device=dev)
+    prob.psolve_apply(torch.from_numpy(x).to(dev), zt)
+    torch.cuda.synchronize()
+    z = zt.cpu().numpy()
+    ref = scipy.sparse.linalg.spsolve(S.tocsc().astype(np.complex128), x)
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+    host = F.solve(x)
+    assert np.linalg.norm(z - host) <= 1e-12 * np.linalg.norm(host)
+    ft = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    ut = torch.zeros_like(ft)
+    code, iters, relres = prob.precond_solve_device(ft, ut, rtol=1e-8, restart=40, maxit=200)
+    assert code == lsp.LSP_OK and relres <= 1e-8
+    if t == 2:
+        _, it_or, _, _, _ = O.precond_solve(p.v, p.f, 2, p.num_shifts, rtol=1e-8, nd_leaf=leaf)
+    else:
+        _, it_or, _, _, _ = O.precond_solve(p.v, p.f, 1, p.num_shifts, rtol=1e-8)
+    print(f"  device gmres {iters} (oracle {it_or}), relres {relres:.2e}", flush=True)
+    assert abs(iters - it_or) <= 1
+    prob.close()
+
+
+def test_device_gmres_rejects_nonfinite_rhs(torch_dev):
+    torch, dev = torch_dev
+    lsp = lsp_mod()
+    p = W.helm2d_gauss(32)
+    prob, S, F = setup(torch_dev, p, 1)
+    ft = torch.from_numpy(p.f.reshape(-1)).to(dev)
+    ft[17] = complex(float("nan"), 0.0)
+    with pytest.raises(lsp.LSPError) as ei:
+        prob.precond_solve_device(ft, torch.zeros_like(ft))
+    assert ei.value.code == lsp.LSP_ENONFINITE
     prob.close()
 
 
