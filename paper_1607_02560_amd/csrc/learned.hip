@@ -8,13 +8,15 @@
 // parity blocks of A1, M and G (see PForms) and rho*(s) in LDS; each wave
 // then works alone (no block barrier after the loads) on chunks of 32 points:
 //   * one lane per point finds its shift s_j (also the network's last input);
-//   * the wave evaluates its 32 points as 2 groups of 16 with
-//     v_mfma_f32_16x16x16bf16 in the transposed form Z^T = W X^T, so that the
-//     accumulator layout of one layer (lane l holds rows 4(l/16)+i, column
-//     l%16) is exactly the B-operand layout of the next: activations never
-//     leave registers, and the output layer accumulates while the second
-//     hidden layer is produced; the check's gathers v[mu_j] are issued before
-//     the network so that it hides their latency;
+//   * the wave evaluates its 32 points as 2 groups of 16 in the transposed
+//     form Z^T = W X^T, so that the accumulator layout of one layer (lane l
+//     holds rows 4(l/16)+i, column l%16) is the B-operand layout of the next:
+//     two such 16-row tiles side by side are one 32-wide k operand of
+//     v_mfma_f32_16x16x32_bf16 (lane group q holds k = 4q .. 4q+3 of each);
+//     activations never leave registers, and the output layer accumulates
+//     while the second hidden layer is produced tile pair by tile pair; the
+//     check's gathers v[mu_j] are issued before the network so that it hides
+//     their latency;
 //   * the de-standardised FP32 outputs go to the wave's staging rows in LDS;
 //     lanes j and j + 32 read point j's row, form the stencil
 //     q = p - c (v[mu_j] - s_j), take its parity coordinates and split the
@@ -44,7 +46,22 @@ using lsp::Parity;
 using lsp::Pow;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// the operand of one v_mfma_f32_16x16x32_bf16 from two 16-wide k tiles: lane
+// group q holds k = 4q .. 4q+3 of the first and of the second tile (the
+// placement the network GEMM kernel uses, so both sum in the same order)
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+  s16x8 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = lo[i];
+    v[4 + i] = hi[i];
+  }
+  return __builtin_bit_cast(bf16x8, v);
+}
 typedef __bf16 hbf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kH = 128;           // hidden width of the fused kernel
@@ -489,12 +506,21 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
 #pragma unroll
       for (int g = 0; g < kGroups; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kc = 0; kc < KC1; ++kc) {
-        const bf16x4 A =
-            *reinterpret_cast<const bf16x4*>(W1s + (16 * ht + r16) * F::W1S + 16 * kc + 4 * qd);
+      for (int kc = 0; kc + 1 < KC1; kc += 2) {
+        const unsigned short* wr = W1s + (16 * ht + r16) * F::W1S + 16 * kc + 4 * qd;
+        const bf16x8 A = cat8(*reinterpret_cast<const bf16x4*>(wr),
+                              *reinterpret_cast<const bf16x4*>(wr + 16));
 #pragma unroll
         for (int g = 0; g < kGroups; ++g)
-          acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, xb[g][kc], acc[g], 0, 0, 0);
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, cat8(xb[g][kc], xb[g][kc + 1]),
+                                                           acc[g], 0, 0, 0);
+      }
+      if constexpr (KC1 % 2 == 1) {
+        const bf16x4 A = *reinterpret_cast<const bf16x4*>(W1s + (16 * ht + r16) * F::W1S +
+                                                          16 * (KC1 - 1) + 4 * qd);
+#pragma unroll
+        for (int g = 0; g < kGroups; ++g)
+          acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, xb[g][KC1 - 1], acc[g], 0, 0, 0);
       }
 #pragma unroll
       for (int g = 0; g < kGroups; ++g) {
@@ -511,34 +537,45 @@ __attribute__((amdgpu_waves_per_eu(2, 2))) void learned_fused_kernel(
     for (int g = 0; g < kGroups; ++g)
 #pragma unroll
       for (int ot = 0; ot < OT; ++ot) acc3[g][ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+    static_assert(KC % 2 == 0, "hidden width: whole pairs of 16-wide tiles");
+    // second-layer tiles in pairs: tile ht of z2 = W2 a1, SiLU, and the pair
+    // (ht, ht+1) is the next 32-wide K block of the output layer
 #pragma unroll
-    for (int ht = 0; ht < KC; ++ht) {
-      f32x4 acc[kGroups];
+    for (int hp = 0; hp < KC; hp += 2) {
+      bf16x4 a2[2][kGroups];
 #pragma unroll
-      for (int g = 0; g < kGroups; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int h2i = 0; h2i < 2; ++h2i) {
+        const int ht = hp + h2i;
+        f32x4 acc[kGroups];
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        const bf16x4 A =
-            *reinterpret_cast<const bf16x4*>(W2s + (16 * ht + r16) * kWStride + 16 * kc + 4 * qd);
+        for (int g = 0; g < kGroups; ++g) acc[g] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int g = 0; g < kGroups; ++g)
-          acc[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, a1[g][kc], acc[g], 0, 0, 0);
-      }
-      bf16x4 a2[kGroups];
+        for (int kc = 0; kc < KC; kc += 2) {
+          const unsigned short* wr = W2s + (16 * ht + r16) * kWStride + 16 * kc + 4 * qd;
+          const bf16x8 A = cat8(*reinterpret_cast<const bf16x4*>(wr),
+                                *reinterpret_cast<const bf16x4*>(wr + 16));
 #pragma unroll
-      for (int g = 0; g < kGroups; ++g) {
-        f32x4 z;
+          for (int g = 0; g < kGroups; ++g)
+            acc[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, cat8(a1[g][kc], a1[g][kc + 1]),
+                                                             acc[g], 0, 0, 0);
+        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) z[i] = silu(acc[g][i] + b2s[16 * ht + 4 * qd + i]);
-        a2[g] = to_bf16x4(z);
+        for (int g = 0; g < kGroups; ++g) {
+          f32x4 z;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) z[i] = silu(acc[g][i] + b2s[16 * ht + 4 * qd + i]);
+          a2[h2i][g] = to_bf16x4(z);
+        }
       }
 #pragma unroll
       for (int ot = 0; ot < OT; ++ot) {
-        const bf16x4 A =
-            *reinterpret_cast<const bf16x4*>(W3s + (16 * ot + r16) * kWStride + 16 * ht + 4 * qd);
+        const unsigned short* wr = W3s + (16 * ot + r16) * kWStride + 16 * hp + 4 * qd;
+        const bf16x8 A = cat8(*reinterpret_cast<const bf16x4*>(wr),
+                              *reinterpret_cast<const bf16x4*>(wr + 16));
 #pragma unroll
         for (int g = 0; g < kGroups; ++g)
-          acc3[g][ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, a2[g], acc3[g][ot], 0, 0, 0);
+          acc3[g][ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, cat8(a2[0][g], a2[1][g]),
+                                                               acc3[g][ot], 0, 0, 0);
       }
     }
     // de-standardised outputs y_o to the staging row of their point

@@ -24,6 +24,8 @@
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 256;
@@ -42,8 +44,12 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (+ C[m][n] if accumulate), with
 // A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn] in BF16 and C in FP32.
 // M, N, K are multiples of 16. Four waves per block, one 16x16 tile each
-// (2 x 2 tiles per block); one v_mfma_f32_16x16x16bf16 per 16 values of k,
-// operands of four k-steps loaded together.
+// (2 x 2 tiles per block). k runs in blocks of 32 from the start of the
+// block's range, one v_mfma_f32_16x16x32_bf16 each, with lane group q
+// holding k = 4q .. 4q+3 and 16 + 4q .. 16 + 4q + 3 of the block (the
+// placement the fused learned kernel uses for its tile pairs, so both sum in
+// the same order); a last odd 16 of k takes one v_mfma_f32_16x16x16bf16.
+// Operands of two k-blocks are loaded together.
 // With gridDim.z > 1 block z sums k in [z kchunk, (z+1) kchunk) and writes
 // its raw partial tile to C + z M ldc (split_reduce_kernel adds them).
 // MFMA operand layout: lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
@@ -68,24 +74,30 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     bias = nullptr;
     accumulate = 0;
   }
-  // four k-steps of operands are loaded before their four MFMAs (one memory
+  // two 32-blocks of operands are loaded before their two MFMAs (one memory
   // round trip per 64 values of k); the MFMAs run in k order either way
+  auto load8 = [&](const unsigned short* p, int64_t stride, int kbase) {
+    s16x8 v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      v[i] = (short)p[(int64_t)(kbase + kq + i) * stride];
+      v[4 + i] = (short)p[(int64_t)(kbase + 16 + kq + i) * stride];
+    }
+    return __builtin_bit_cast(bf16x8, v);
+  };
   int k0 = kb;
   for (; k0 + 64 <= ke; k0 += 64) {
-    bf16x4 a[4], b[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[g][i] = (short)ap[(int64_t)(k0 + 16 * g + kq + i) * sak];
-        b[g][i] = (short)bp[(int64_t)(k0 + 16 * g + kq + i) * sbk];
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[g], b[g], acc, 0, 0, 0);
+    const bf16x8 a0 = load8(ap, sak, k0), b0 = load8(bp, sbk, k0);
+    const bf16x8 a1 = load8(ap, sak, k0 + 32), b1 = load8(bp, sbk, k0 + 32);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
   }
-  for (; k0 < ke; k0 += 16) {
+  if (k0 + 32 <= ke) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(ap, sak, k0), load8(bp, sbk, k0), acc,
+                                                  0, 0, 0);
+    k0 += 32;
+  }
+  if (k0 < ke) {  // the last 16 values of k
     bf16x4 a, b;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -374,7 +386,8 @@ hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak
                        M, N, K, bias, accumulate ? 1 : 0, K);
     return hipGetLastError();
   }
-  const int kchunk = ((K + splits - 1) / splits + 15) / 16 * 16;
+  // whole 32-blocks per split (the k placement starts at each split's start)
+  const int kchunk = ((K + splits - 1) / splits + 31) / 32 * 32;
   splits = (K + kchunk - 1) / kchunk;
   grid.z = splits;
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf,
