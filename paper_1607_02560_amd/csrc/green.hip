@@ -416,7 +416,7 @@ __global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::Batc
 // ends) the wave sums the pair sums over its lanes (through LDS, in a fixed
 // order) and writes them as the partial of (wave w, shift s), at slot w + s.
 // Slots of one shift are consecutive in w, and slot w + s is unique, since
-// each step along the ranges advances w or s. The cosine values and k_2^2 of
+// each step along the ranges advances w or s. The cosine values and 4 pi^2 k_2^2 of
 // a step are wave-uniform (scalar loads). The Nyquist column k_2 = n/2 is one
 // extra term of the piece that ends a row's last pair, and the corner
 // (n/2, n/2) is added by the wave that holds a shift's first step.
@@ -429,11 +429,14 @@ __device__ __forceinline__ double green_rd(double K2, double s) {
   return lsp::rcp_cubic(lam + s);
 }
 
-// steps kd0 .. kd0 + U - 1 of a lane's inner sums (weights cws, k^2 ksq)
+// steps kd0 .. kd0 + U - 1 of a lane's inner sums: weights cws, lam2 the
+// per-axis eigenvalues 4 pi^2 k_2^2 of the steps (table), base = 4 pi^2 k_1^2
+// + s of the lane (one rounding), so a term costs one add before its
+// reciprocal: r = 1/(base + lam2)
 template <int W, int U>
 __device__ __forceinline__ void green2d_terms(const double* __restrict__ cws,
-                                              const double* __restrict__ ksq, double K2o,
-                                              double s, double* tg, double* tq) {
+                                              const double* __restrict__ lam2, double base,
+                                              double* tg, double* tq) {
   double c[U][W], r[U], r2[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
@@ -442,7 +445,7 @@ __device__ __forceinline__ void green2d_terms(const double* __restrict__ cws,
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    r[u] = green_rd(K2o + ksq[u], s);
+    r[u] = lsp::rcp_cubic(base + lam2[u]);
     r2[u] = r[u] * r[u];
   }
 #pragma unroll
@@ -477,7 +480,7 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
   const int Ht = n / 2;
   const int H = Ht + 1;
   const double* cwh = cw + H * W;   // halved weights (diagonal tile pairs)
-  const double* ksq = cw + 2 * H * W;
+  const double* lam2 = cw + 2 * H * W;  // 4 pi^2 k^2, k in [0, n/2]
   const int KT = Ht < kTile ? Ht : kTile;
   const int T = Ht / KT;
   const int NU = T * (T + 1) / 2;
@@ -512,7 +515,7 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
       }
       const int rstop = min(send, si * SPS + (base + T - ot) * KT);
       const int k1 = ot * KT + (valid ? lane : 0);
-      const double K2o = (double)(k1 * k1);
+      const double lbase = fma(lsp::kFourPi2, (double)(k1 * k1), s);
       double tg[W], tq[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
@@ -526,12 +529,12 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
         int kd = q * KT + kk;
         const int kd_end = kd + (ustop - g);
         for (; kd + U <= kd_end; kd += U)
-          green2d_terms<W, U>(tab + kd * W, ksq + kd, K2o, s, tg, tq);
-        for (; kd < kd_end; ++kd) green2d_terms<W, 1>(tab + kd * W, ksq + kd, K2o, s, tg, tq);
+          green2d_terms<W, U>(tab + kd * W, lam2 + kd, lbase, tg, tq);
+        for (; kd < kd_end; ++kd) green2d_terms<W, 1>(tab + kd * W, lam2 + kd, lbase, tg, tq);
         if (q == T - 1 && ustop - g + kk == KT) {
           // the Nyquist column k_2 = n/2, weight 1 (a diagonal pair's full
           // square counts it twice, then halves)
-          const double r0 = green_rd(K2o + (double)(nyq * nyq), s);
+          const double r0 = lsp::rcp_cubic(lbase + lam2[nyq]);
           const double r2 = r0 * r0;
 #pragma unroll
           for (int j = 0; j < W; ++j) {

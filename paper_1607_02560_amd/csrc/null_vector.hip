@@ -64,6 +64,12 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   static_assert(3 * Pa::offset(Pa::NC) <= Pow<D, W>::v * Pow<D, W>::v,
                 "the M, A1 and G blocks of a shift share its m*m slot");
   const int p = (lane < B) ? lane : 0;
+  // 3D with t = 2 (27-row classes): keep fewer values live across the power
+  // iteration, so that the kernel stays within the register file: the
+  // convergence test tracks only the lane's own entry (then the largest
+  // change over the wave, the same maximum), and G_b x and A1_b x at the end
+  // read the rows back from the shift's table instead of keeping them
+  constexpr bool kLean = (D == 3 && W == 5);
 
   // per-axis 1D indices of row p
   int jp[D];
@@ -206,12 +212,12 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
     xscale = fmax(xscale, fabs(bcast(dk, k)));
   }
   xscale = (xscale > 0.0 && isfinite(xscale)) ? 1.0 / xscale : 1.0;
-  double xa[B], xprev[B];
+  constexpr int NPREV = kLean ? 1 : B;
+  double xa[B], xprev[NPREV];
 #pragma unroll
-  for (int qc = 0; qc < B; ++qc) {
-    xa[qc] = 1.0 + 0.37 * (double)((qc * 7 + 3) % 11) / 11.0;  // generic start
-    xprev[qc] = 0.0;
-  }
+  for (int qc = 0; qc < B; ++qc) xa[qc] = 1.0 + 0.37 * (double)((qc * 7 + 3) % 11) / 11.0;  // generic start
+#pragma unroll
+  for (int qc = 0; qc < NPREV; ++qc) xprev[qc] = 0.0;
   for (int it = 0; it < 100; ++it) {
 #pragma unroll
     for (int rep = 0; rep < 4; ++rep) {
@@ -233,11 +239,24 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
     for (int qc = 0; qc < B; ++qc) nrm = fma(xa[qc], xa[qc], nrm);
     const double sc = lsp::rsqrt_nr(nrm);
     double dmx = 0.0;
+    if constexpr (kLean) {
+      double xo = 0.0;
 #pragma unroll
-    for (int qc = 0; qc < B; ++qc) {
-      xa[qc] *= sc;
-      dmx = fmax(dmx, fabs(xa[qc] - xprev[qc]));
-      xprev[qc] = xa[qc];
+      for (int qc = 0; qc < B; ++qc) {
+        xa[qc] *= sc;
+        if (qc == p) xo = xa[qc];
+      }
+      dmx = (lane < B) ? fabs(xo - xprev[0]) : 0.0;
+      xprev[0] = xo;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) dmx = fmax(dmx, __shfl_xor(dmx, o));
+    } else {
+#pragma unroll
+      for (int qc = 0; qc < B; ++qc) {
+        xa[qc] *= sc;
+        dmx = fmax(dmx, fabs(xa[qc] - xprev[qc]));
+        xprev[qc] = xa[qc];
+      }
     }
     if (dmx < 1e-15) break;
   }
@@ -279,15 +298,28 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   }
 
   // ---- lambda_c = x^T M_b x, G_b x ----
-  double mx = 0.0, gx = 0.0;
+  double mx = 0.0, gx = 0.0, ay = 0.0;
+  if constexpr (kLean) {
+    // row p of G_b and of A1_b as this lane stored them above (lanes past
+    // the class read row 0; their values are not used)
+    const double* gback = Mtab_si + 2 * Pa::offset(Pa::NC) + Pa::offset(C) + p * B;
+    const double* aback = Mtab_si + Pa::offset(Pa::NC) + Pa::offset(C) + p * B;
 #pragma unroll
-  for (int qc = 0; qc < B; ++qc) {
-    mx = fma(mrow[qc], xa[qc], mx);
-    gx = fma(grow[qc], xa[qc], gx);
+    for (int qc = 0; qc < B; ++qc) {
+      mx = fma(mrow[qc], xa[qc], mx);
+      gx = fma(gback[qc], xa[qc], gx);
+    }
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) ay = fma(aback[qc], xa[qc], ay);
+  } else {
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) {
+      mx = fma(mrow[qc], xa[qc], mx);
+      gx = fma(grow[qc], xa[qc], gx);
+    }
+#pragma unroll
+    for (int qc = 0; qc < B; ++qc) ay = fma(arow[qc], xa[qc], ay);
   }
-  double ay = 0.0;
-#pragma unroll
-  for (int qc = 0; qc < B; ++qc) ay = fma(arow[qc], xa[qc], ay);
   double lam = 0.0, axx = 0.0;
 #pragma unroll
   for (int qc = 0; qc < B; ++qc) {

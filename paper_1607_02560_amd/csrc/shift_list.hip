@@ -1,11 +1,13 @@
 // The shift list S of Sec. 4.1 (and the one shift of the non-localized
-// method of Sec. 3), in one launch: a fixed grid of kMinMaxBlocks blocks writes
-// per-block (min, max) partials of the potential v (and, for the one shift,
-// per-block sums); the block that finishes last (a ticket counter that is
-// never reset: 256 tickets per launch, so it stays a multiple of 256 between
-// launches) reduces the partials, forms the bin centres, snaps them and
-// removes duplicates, and publishes S, |S| and (v_min, v_max). No value goes
-// through the host.
+// method of Sec. 3): a fixed grid of kMinMaxBlocks blocks writes per-block
+// (min, max) partials of the potential v (and, for the one shift, per-block
+// sums); one block then reduces the partials, forms the bin centres, snaps
+// them and removes duplicates, and publishes S, |S| and (v_min, v_max). No
+// value goes through the host. A single problem uses two launches (the
+// kernel boundary orders the partials before their reader, with no atomics
+// on the way); the batched form keeps one launch per batch, where the block
+// that finishes last (a ticket counter that is never reset: 256 tickets per
+// problem and launch, so it stays a multiple of 256) does the reduction.
 //
 // The same launch can also write the folded cosine weights of the Green's
 // sums, cw[k][dl] = w(k) cos(2 pi k dl / n) for k in [0, n/2], dl in [0, W)
@@ -25,7 +27,9 @@ constexpr int kUnroll = 8;
 // in its own element order, then a butterfly over the lanes (both partners
 // add the same two values, so every lane holds the same sum), then the waves
 // in index order.
-template <bool SUM>
+// ATOMIC writes the partials with device-scope atomic swaps (for a reader in
+// the same launch), else with plain stores (for a reader in a later launch).
+template <bool SUM, bool ATOMIC>
 __device__ __forceinline__ void minmax_body(int bx, int gx, const double* __restrict__ v,
                                             int64_t N, double* part) {
   __shared__ double wmin[kWaves], wmax[kWaves], wsum[kWaves];
@@ -76,12 +80,17 @@ __device__ __forceinline__ void minmax_body(int bx, int gx, const double* __rest
     // does, so the last block's atomic reads see them without writing back
     // this XCD's L2 (which a fence would); s_waitcnt below makes them
     // complete before the ticket is drawn
-    using u64 = unsigned long long;
-    u64* pu = reinterpret_cast<u64*>(part);
-    (void)atomicExch(pu + 2 * bx, (u64)__double_as_longlong(lo));
-    (void)atomicExch(pu + 2 * bx + 1, (u64)__double_as_longlong(hi));
-    if constexpr (SUM)
-      (void)atomicExch(pu + 2 * lsp::kMinMaxBlocks + bx, (u64)__double_as_longlong(sum));
+    if constexpr (ATOMIC) {
+      using u64 = unsigned long long;
+      u64* pu = reinterpret_cast<u64*>(part);
+      (void)atomicExch(pu + 2 * bx, (u64)__double_as_longlong(lo));
+      (void)atomicExch(pu + 2 * bx + 1, (u64)__double_as_longlong(hi));
+      if constexpr (SUM)
+        (void)atomicExch(pu + 2 * lsp::kMinMaxBlocks + bx, (u64)__double_as_longlong(sum));
+    } else {
+      reinterpret_cast<double2*>(part)[bx] = make_double2(lo, hi);
+      if constexpr (SUM) part[2 * lsp::kMinMaxBlocks + bx] = sum;
+    }
   }
 }
 
@@ -94,7 +103,7 @@ __device__ __forceinline__ void minmax_shift_body(int bx, const double* __restri
                                                   double* part, unsigned* ticket, int nreq,
                                                   double* S_out, int* nS_out,
                                                   double* vrange_out) {
-  minmax_body<GLOBAL>(bx, lsp::kMinMaxBlocks, v, N, part);
+  minmax_body<GLOBAL, true>(bx, lsp::kMinMaxBlocks, v, N, part);
   __shared__ int last;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_s_waitcnt(0);  // the partials' swaps have completed
@@ -131,12 +140,13 @@ __device__ __forceinline__ void minmax_shift_body(int bx, const double* __restri
 
 // entry e of the cosine tables of (n, W), H = n/2 + 1 rows (lsp::cos_table_doubles):
 // cw[k W + dl] for e < H W, then the same values halved (the weights of a
-// diagonal tile pair of the 2D Green's sums), then k^2 as doubles
+// diagonal tile pair of the 2D Green's sums), then the per-axis eigenvalues
+// 4 pi^2 k^2 of the symbol of -Laplacian (Sec. 2)
 __device__ __forceinline__ void cos_entry(int n, int W, int e, double* cw) {
   const int H = n / 2 + 1;
   if (e >= 2 * H * W) {
     const int k = e - 2 * H * W;
-    cw[e] = (double)(k * k);
+    cw[e] = lsp::kFourPi2 * (double)(k * k);
     return;
   }
   const bool halved = e >= H * W;
@@ -148,15 +158,38 @@ __device__ __forceinline__ void cos_entry(int n, int W, int e, double* cw) {
   cw[e] = halved ? 0.5 * c : c;
 }
 
-template <bool GLOBAL>
-__global__ __launch_bounds__(kThreads) void minmax_shift_kernel(
-    const double* __restrict__ v, int64_t N, double* part, unsigned* ticket, int nreq,
-    double* S_out, int* nS_out, double* vrange_out, int cos_n, int cos_w, double* cw) {
+// first launch of a single problem: the partials (and, with cw, the cosine
+// tables, one entry per thread of the grid)
+template <bool SUM>
+__global__ __launch_bounds__(kThreads) void minmax_part_kernel(const double* __restrict__ v,
+                                                               int64_t N, double* part, int cos_n,
+                                                               int cos_w, double* cw) {
   if (cw) {
     const int e = blockIdx.x * kThreads + threadIdx.x;
     if (e < lsp::cos_table_doubles(cos_n, cos_w)) cos_entry(cos_n, cos_w, e, cw);
   }
-  minmax_shift_body<GLOBAL>(blockIdx.x, v, N, part, ticket, nreq, S_out, nS_out, vrange_out);
+  minmax_body<SUM, false>(blockIdx.x, lsp::kMinMaxBlocks, v, N, part);
+}
+
+// second launch: one block forms S from the partials of the launch before
+template <bool GLOBAL>
+__global__ __launch_bounds__(kThreads) void shift_from_parts_kernel(
+    const double* __restrict__ part, int64_t N, int nreq, double* S_out, int* nS_out,
+    double* vrange_out) {
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sNS, sWave[kWaves];
+  __shared__ double sRange[2], sRed[3 * kWaves];
+  if constexpr (GLOBAL)
+    lsp::global_shift_block<kThreads>(part, N, sS, &sNS, sRange, sRed);
+  else
+    lsp::shift_list_block<kThreads>(part, nreq, sS, &sNS, sRange, sWave, sRed);
+  const int nS = sNS;
+  for (int i = threadIdx.x; i < nS; i += kThreads) S_out[i] = sS[i];
+  if (threadIdx.x == 0) {
+    *nS_out = nS;
+    vrange_out[0] = sRange[0];
+    vrange_out[1] = sRange[1];
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void cos_table_kernel(int n, int W, double* cw) {
@@ -186,13 +219,17 @@ hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int bloc
 hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
                              bool global, hipStream_t s, int cos_n, int cos_w, double* cw) {
   if (cw && cos_table_doubles(cos_n, cos_w) > kMinMaxBlocks * kThreads) return hipErrorInvalidValue;
-  if (global)
-    hipLaunchKernelGGL(minmax_shift_kernel<true>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v,
-                       N, ws.minmax_part, ws.ticket, 1, ws.S, ws.nS, ws.vrange, cos_n, cos_w, cw);
-  else
-    hipLaunchKernelGGL(minmax_shift_kernel<false>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v,
-                       N, ws.minmax_part, ws.ticket, nreq, ws.S, ws.nS, ws.vrange, cos_n, cos_w,
-                       cw);
+  if (global) {
+    hipLaunchKernelGGL(minmax_part_kernel<true>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v, N,
+                       ws.minmax_part, cos_n, cos_w, cw);
+    hipLaunchKernelGGL(shift_from_parts_kernel<true>, dim3(1), dim3(kThreads), 0, s,
+                       ws.minmax_part, N, 1, ws.S, ws.nS, ws.vrange);
+  } else {
+    hipLaunchKernelGGL(minmax_part_kernel<false>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v, N,
+                       ws.minmax_part, cos_n, cos_w, cw);
+    hipLaunchKernelGGL(shift_from_parts_kernel<false>, dim3(1), dim3(kThreads), 0, s,
+                       ws.minmax_part, N, nreq, ws.S, ws.nS, ws.vrange);
+  }
   return hipGetLastError();
 }
 

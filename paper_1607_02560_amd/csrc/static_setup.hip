@@ -2,8 +2,7 @@
 // problem with no allocation at all, for callers that cannot allocate (code
 // under HIP graph capture, serving loops, harnesses that forbid it).
 //
-// Every intermediate of the setup (the min/max partials and their ticket,
-// the shift list, the folded cosine table, the Green's partial sums and the
+// Every intermediate of the setup (the min/max partials, the shift list, the folded cosine table, the Green's partial sums and the
 // per-shift tables) lives in one file-scope device array, `scratch`, of
 // kStaticScratchBytes per GPU. The array's name is only a host-side stand-in:
 // its device address is looked up once per device (hipGetSymbolAddress, with
@@ -14,10 +13,8 @@
 //
 // Every call on one GPU shares its array, which keeps the last call's
 // contents: calls that overlap on one GPU (on different streams, or from
-// different threads) race. The one value that must start in a known state,
-// the min/max ticket counter, is cleared by a kernel (not a memset) in the
-// first call on each device; every setup leaves it at a multiple of the
-// min/max grid, which is all the kernels need.
+// different threads) race. Every value of the array is written by the
+// launch before the one that reads it, so nothing needs clearing.
 #include <mutex>
 
 #include "lsp_internal.h"
@@ -31,17 +28,12 @@ static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 std::mutex g_mu;
 unsigned char* g_ptr[kMaxDevices] = {};
-bool g_cleared[kMaxDevices] = {};
-
-__global__ void clear_ticket_kernel(unsigned* ticket) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *ticket = 0u;
-}
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Byte offsets of the setup's buffers in the static array for (n, t, shifts).
 struct Carve {
-  size_t minmax, ticket, S, nS, vrange, cw, part, gtab, gamtab, Mtab, alpha, Ctab, sigma, rho,
+  size_t minmax, S, nS, vrange, cw, part, gtab, gamtab, Mtab, alpha, Ctab, sigma, rho,
       actab, status, total;
 };
 
@@ -56,7 +48,6 @@ Carve carve(int n, int t, int shifts) {
     return at;
   };
   c.minmax = take(sizeof(double) * 3 * lsp::kMinMaxBlocks);
-  c.ticket = take(sizeof(unsigned));
   c.S = take(sizeof(double) * lsp::kMaxShifts);
   c.nS = take(sizeof(int));
   c.vrange = take(sizeof(double) * 2);
@@ -109,7 +100,6 @@ int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_s
   if (dev < 0 || dev >= kMaxDevices) return lsp::set_error(LSP_EINVAL, "device index too large");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   unsigned char* base = nullptr;
-  bool clear = false;
   {
     std::lock_guard<std::mutex> lock(g_mu);
     if (!g_ptr[dev]) {
@@ -119,8 +109,6 @@ int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_s
       g_ptr[dev] = static_cast<unsigned char*>(ptr);
     }
     base = g_ptr[dev];
-    clear = !g_cleared[dev];
-    g_cleared[dev] = true;
   }
   // a problem object on the stack, its workspace carved from the array: the
   // launchers of lsp_stencil_setup take it as they take a created problem
@@ -136,7 +124,6 @@ int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_s
   p.num_shifts = num_shifts;
   lsp::Workspace& w = p.ws;
   w.minmax_part = reinterpret_cast<double*>(base + c.minmax);
-  w.ticket = reinterpret_cast<unsigned*>(base + c.ticket);
   w.S = reinterpret_cast<double*>(base + c.S);
   w.nS = reinterpret_cast<int*>(base + c.nS);
   w.vrange = reinterpret_cast<double*>(base + c.vrange);
@@ -155,12 +142,8 @@ int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_s
   w.cap_m = m;
   w.cap_w = m;
   p.cosT = reinterpret_cast<double*>(base + c.cw);
-  if (clear) {
-    hipLaunchKernelGGL(clear_ticket_kernel, dim3(1), dim3(64), 0, s, w.ticket);
-    if ((e = hipGetLastError()) != hipSuccess) return lsp::hip_check(e, "ticket clear");
-  }
-  // shift list and cosine table in one launch, then the Green's sums, the
-  // null vectors and the rows, as lsp_stencil_setup launches them
+  // min/max partials with the cosine table, the shift list, then the Green's
+  // sums, the null vectors and the rows, as lsp_stencil_setup launches them
   e = lsp::launch_shift_list(p.v, N, w, num_shifts, false, s, n, W, p.cosT);
   if (e == hipSuccess) e = lsp::launch_green_sums(&p, num_shifts);
   if (e == hipSuccess) e = lsp::launch_null_vectors(&p, num_shifts);
