@@ -324,7 +324,7 @@ int lsp_profile_read(lsp_problem* p, int nstages, double* ms_host, int* count_ho
  * Launch-shape tuning (not in the paper). Three shapes of this problem's
  * kernels can be chosen per problem; 0 selects the built-in default:
  *   LSP_TUNE_GREEN_WAVES    2D: the most waves of the Green's-sum launch
- *                           (512, 1024, 1536 or 2048);
+ *                           (512, 1024, 1536, 2048 or 3072);
  *   LSP_TUNE_ASSEMBLY_TILE  2D, n >= 128: the assembly's tile, 32, 64 or 128
  *                           points of one row, or 1 for 4 x 128 tiles with
  *                           the shift tables staged in LDS;

@@ -24,7 +24,6 @@
 // partial per (shift, unit), unscaled:
 // [g | g*g][leading offsets W^(d-2)][pairs W(W+1)/2].
 #include <algorithm>
-#include <mutex>
 #include <vector>
 
 #include "setup_common.h"
@@ -382,11 +381,47 @@ __device__ __forceinline__ void green_body(
   }
 }
 
+// Shift list of a single problem, formed by every block of its Green's-sum
+// launch from the min/max partials of the launch before (the same list in
+// every block: the same partials through the same fixed-order code); block 0
+// also publishes S, |S| and (v_min, v_max) for the launches after. GLOBAL:
+// the one shift of the non-localized method.
+struct ShiftShared {
+  double S[lsp::kMaxShifts];
+  double range[2];
+  double red[3 * kWaves];
+  int nS;
+  int wave[kWaves];
+};
+
+__device__ __forceinline__ void shift_prologue(ShiftShared& sh, const double* __restrict__ mm_part,
+                                               int64_t N, int nreq, int global,
+                                               double* __restrict__ S_out,
+                                               int* __restrict__ nS_out,
+                                               double* __restrict__ vrange_out) {
+  if (global)
+    lsp::global_shift_block<kThreads>(mm_part, N, sh.S, &sh.nS, sh.range, sh.red);
+  else
+    lsp::shift_list_block<kThreads>(mm_part, nreq, sh.S, &sh.nS, sh.range, sh.wave, sh.red);
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int i = threadIdx.x; i < sh.nS; i += kThreads) S_out[i] = sh.S[i];
+    if (threadIdx.x == 0) {
+      *nS_out = sh.nS;
+      vrange_out[0] = sh.range[0];
+      vrange_out[1] = sh.range[1];
+    }
+  }
+}
+
 template <int D, int W, int KT>
 __global__ __launch_bounds__(kThreads) void green_sums_kernel(
-    const double* __restrict__ S, const int* __restrict__ nS_ptr, const double* __restrict__ cw,
-    const int* __restrict__ units, int n, double* __restrict__ part) {
-  green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, S, nS_ptr, cw, units, n, part);
+    const double* __restrict__ mm_part, int64_t N, int nreq, int global,
+    const double* __restrict__ cw, const int* __restrict__ units, int n,
+    double* __restrict__ part, double* __restrict__ S_out, int* __restrict__ nS_out,
+    double* __restrict__ vrange_out) {
+  __shared__ ShiftShared sh;
+  shift_prologue(sh, mm_part, N, nreq, global, S_out, nS_out, vrange_out);
+  green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, sh.S, &sh.nS, cw, units, n, part);
 }
 
 // one launch for the problems of a batch: block b is unit map[b].y of shift
@@ -463,18 +498,15 @@ struct Green2d {
   static constexpr int NP = GreenLayout<2, W>::NP;
   static constexpr int NV = GreenLayout<2, W>::NV;
   static constexpr int P2 = pow2_at_least(NV);
-  static constexpr int RS = NV + 1;                 // LDS row of one lane (doubles, odd)
-  static constexpr size_t kWaveLds = sizeof(double) * 64 * RS;
-  static constexpr size_t kBlockLds = kWaveLds * kWaves;
 };
 
 template <int W>
 __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __restrict__ S,
                                              const int* __restrict__ nS_ptr,
                                              const double* __restrict__ cw, int n,
-                                             double* __restrict__ part, double* red) {
+                                             double* __restrict__ part) {
   using G = Green2d<W>;
-  constexpr int NP = G::NP, NV = G::NV, P2 = G::P2, RS = G::RS;
+  constexpr int NP = G::NP, NV = G::NV, P2 = G::P2;
   constexpr int U = 4;
   const int lane = threadIdx.x & 63;
   const int Ht = n / 2;
@@ -573,38 +605,26 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
         }
       }
     }
-    // sum over the lanes: lane l writes its P2 values to row l of the
-    // wave's LDS area; lane l then adds value l % P2 over the rows of its
-    // group (64 / P2 groups of P2 rows), and the groups meet by lane moves
-    double* row = red + lane * RS;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) row[i] = a[i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int col = lane % P2;
-    const int grp = lane / P2;
-    const int colr = col < NV ? col : 0;  // lanes past the last value read a valid one
-    double sum = 0.0;
-#pragma unroll
-    for (int i = 0; i < P2; ++i) sum += red[(grp * P2 + i) * RS + colr];
-    if constexpr (P2 <= 32) sum += __shfl_xor(sum, 32);
-    if constexpr (P2 <= 16) sum += __shfl_xor(sum, 16);
-    if (grp == 0 && col < NV) part[((int64_t)wave + si) * NV + col] = sum;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");  // the area is rewritten next
+    // sum over the lanes by recursive halving (a fixed order); one writer
+    // per value: the lanes holding value vi differ only in the bits the
+    // halving did not use
+    const int vi = halving_sum<P2>(a, lane);
+    constexpr int kUnusedMask = (P2 >= 64) ? 0 : (P2 >= 32) ? 0x20 : (P2 >= 16) ? 0x30
+                                : (P2 >= 8) ? 0x31 : (P2 >= 4) ? 0x33 : 0x37;
+    if ((lane & kUnusedMask) == 0 && vi < NV) part[((int64_t)wave + si) * NV + vi] = a[0];
   }
 }
 
 template <int W>
 __global__ __launch_bounds__(kThreads) void green2d_kernel(
-    int nwv, const double* __restrict__ S, const int* __restrict__ nS_ptr,
-    const double* __restrict__ cw, int n, double* __restrict__ part) {
-  extern __shared__ double green_red[];
+    int nwv, const double* __restrict__ mm_part, int64_t N, int nreq, int global,
+    const double* __restrict__ cw, int n, double* __restrict__ part, double* __restrict__ S_out,
+    int* __restrict__ nS_out, double* __restrict__ vrange_out) {
+  __shared__ ShiftShared sh;
+  shift_prologue(sh, mm_part, N, nreq, global, S_out, nS_out, vrange_out);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWaves + wid;
-  green2d_body<W>(wave, nwv, S, nS_ptr, cw, n, part, green_red + wid * 64 * Green2d<W>::RS);
+  green2d_body<W>(wave, nwv, sh.S, &sh.nS, cw, n, part);
 }
 
 // one launch for the problems of a batch: block b holds waves 4 map[b].y ..
@@ -612,13 +632,11 @@ __global__ __launch_bounds__(kThreads) void green2d_kernel(
 template <int W>
 __global__ __launch_bounds__(kThreads) void green2d_batched_kernel(const lsp::BatchRec* recs,
                                                                    const int4* map) {
-  extern __shared__ double green_red[];
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = it.y * kWaves + wid;
-  green2d_body<W>(wave, r.gwaves, r.S, r.nS, r.cw, r.n, r.part,
-                  green_red + wid * 64 * Green2d<W>::RS);
+  green2d_body<W>(wave, r.gwaves, r.S, r.nS, r.cw, r.n, r.part);
 }
 
 // Work units with at least one term on or above the diagonal, in
@@ -644,32 +662,15 @@ void build_units(int n, std::vector<int>& units) {
   }
 }
 
-// the dynamic LDS of the 2D kernels may exceed the default per-block limit
-// (t = 3): raise it once per function
-template <typename K>
-hipError_t allow_lds(K kernel, size_t bytes) {
-  static std::once_flag once;
-  static hipError_t err = hipSuccess;
-  std::call_once(once, [&]() {
-    err = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  });
-  return err;
-}
-
 template <int D, int W>
-hipError_t run_green(const lsp_problem* p, int num_shifts) {
+hipError_t run_green(const lsp_problem* p, int num_shifts, bool global) {
   if constexpr (D == 2) {
-    if (hipError_t e = allow_lds(&green2d_kernel<W>, Green2d<W>::kBlockLds); e != hipSuccess)
-      return e;
     const int nwv = lsp::green2d_waves(p->n, num_shifts, p->tune[LSP_TUNE_GREEN_WAVES]);
     const size_t need = (size_t)(nwv + num_shifts) * GreenLayout<2, W>::NV;
     if (need > p->ws.green_part_cap) return hipErrorInvalidValue;
-    // the per-wave LDS areas of the lane sums also cap the residency at two
-    // blocks (two waves per SIMD) per CU for t <= 2
-    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads),
-                       Green2d<W>::kBlockLds, p->stream, nwv, p->ws.S, p->ws.nS, p->cosT, p->n,
-                       p->ws.green_part);
+    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads), 0,
+                       p->stream, nwv, p->ws.minmax_part, p->N, num_shifts, (int)global,
+                       p->cosT, p->n, p->ws.green_part, p->ws.S, p->ws.nS, p->ws.vrange);
   } else {
     const int nunits = p->green_nunits;
     const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;
@@ -680,8 +681,9 @@ hipError_t run_green(const lsp_problem* p, int num_shifts) {
     // top of its ~10-12 KB of static LDS) lets at most three blocks share a
     // CU's 160 KB, so no SIMD takes more than three waves.
     hipLaunchKernelGGL((green_sums_kernel<D, W, kKTile>), dim3(nunits, groups), dim3(kThreads),
-                       kResidencyLds, p->stream, p->ws.S, p->ws.nS, p->cosT, p->green_units,
-                       p->n, p->ws.green_part);
+                       kResidencyLds, p->stream, p->ws.minmax_part, p->N, num_shifts,
+                       (int)global, p->cosT, p->green_units, p->n, p->ws.green_part, p->ws.S,
+                       p->ws.nS, p->ws.vrange);
   }
   return hipGetLastError();
 }
@@ -696,10 +698,10 @@ int green2d_waves(int n, int num_shifts, int max_waves) {
   const int T = Ht / KT;
   const int64_t steps = (int64_t)num_shifts * (T * (T + 1) / 2) * KT;
   // at least 32 steps per wave (the per-piece reduction stays a small part
-  // of a wave's work), at most 2048 waves (two per SIMD of a 256-CU part),
-  // a whole number of 4-wave blocks
+  // of a wave's work), by default at most 2048 waves (two per SIMD of a
+  // 256-CU part; up to 3072 on request), a whole number of 4-wave blocks
   int64_t w = (steps + 31) / 32;
-  const int64_t cap = (max_waves > 0 && max_waves <= 2048) ? max_waves : 2048;
+  const int64_t cap = (max_waves > 0 && max_waves <= 3072) ? max_waves : 2048;
   w = std::max<int64_t>(kWaves, std::min<int64_t>(cap, w));
   return (int)((w + kWaves - 1) / kWaves * kWaves);
 }
@@ -716,11 +718,8 @@ hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* 
   const int W = 2 * t + 1;
 #define LSP_GREEN2_B(W_)                                                                  \
   if (d == 2 && W == W_) {                                                                \
-    if (hipError_t e = allow_lds(&green2d_batched_kernel<W_>, Green2d<W_>::kBlockLds);    \
-        e != hipSuccess)                                                                  \
-      return e;                                                                           \
-    hipLaunchKernelGGL((green2d_batched_kernel<W_>), dim3(blocks), dim3(kThreads),        \
-                       Green2d<W_>::kBlockLds, s, recs, map);                             \
+    hipLaunchKernelGGL((green2d_batched_kernel<W_>), dim3(blocks), dim3(kThreads), 0, s,  \
+                       recs, map);                                                        \
     return hipGetLastError();                                                             \
   }
   LSP_GREEN2_B(3)
@@ -737,13 +736,13 @@ hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* 
 
 int green_shift_groups(int num_shifts) { return (num_shifts + kWaves - 1) / kWaves; }
 
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts) {
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, bool global) {
   const int W = 2 * p->t + 1;
-  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts);
-  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts);
-  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts);
-  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts);
-  if (p->d == 3 && W == 5) return run_green<3, 5>(p, num_shifts);
+  if (p->d == 2 && W == 3) return run_green<2, 3>(p, num_shifts, global);
+  if (p->d == 2 && W == 5) return run_green<2, 5>(p, num_shifts, global);
+  if (p->d == 2 && W == 7) return run_green<2, 7>(p, num_shifts, global);
+  if (p->d == 3 && W == 3) return run_green<3, 3>(p, num_shifts, global);
+  if (p->d == 3 && W == 5) return run_green<3, 5>(p, num_shifts, global);
   return hipErrorInvalidValue;
 }
 
@@ -755,7 +754,8 @@ void green_units(int d, int n, std::vector<int>& units) {
 size_t green_partial_doubles(int d, int n, int t, int shifts) {
   const int W = 2 * t + 1;
   if (d == 2) {
-    const size_t slots = (size_t)green2d_waves(n, shifts) + shifts;
+    // room for the largest wave count a tuning may ask for
+    const size_t slots = (size_t)green2d_waves(n, shifts, 3072) + shifts;
     if (W == 3) return slots * GreenLayout<2, 3>::NV;
     if (W == 5) return slots * GreenLayout<2, 5>::NV;
     if (W == 7) return slots * GreenLayout<2, 7>::NV;

@@ -408,7 +408,8 @@ namespace {
 // the candidates of each tuned shape (0: the default)
 bool tune_value_ok(int knob, int v) {
   switch (knob) {
-    case LSP_TUNE_GREEN_WAVES: return v == 0 || v == 512 || v == 1024 || v == 1536 || v == 2048;
+    case LSP_TUNE_GREEN_WAVES:
+      return v == 0 || v == 512 || v == 1024 || v == 1536 || v == 2048 || v == 3072;
     case LSP_TUNE_ASSEMBLY_TILE: return v == 0 || v == 1 || v == 32 || v == 64 || v == 128;
     case LSP_TUNE_APPLY_FORM: return v == 0 || v == 8 || v == 16;
     default: return false;
@@ -465,7 +466,7 @@ int lsp_autotune(lsp_problem* p, int t, int num_shifts, int precision, void* P_d
   };
   const int n = p->n;
   std::vector<int> cand[LSP_TUNE_COUNT];
-  if (p->d == 2) cand[LSP_TUNE_GREEN_WAVES] = {512, 1024, 1536, 2048};
+  if (p->d == 2) cand[LSP_TUNE_GREEN_WAVES] = {512, 1024, 1536, 2048, 3072};
   if (p->d == 2 && n >= 128) cand[LSP_TUNE_ASSEMBLY_TILE] = {32, 64, 128, 1};
   if (n == 256 || n == 512 || n == 1024) cand[LSP_TUNE_APPLY_FORM] = {8, 16};
   int rc = LSP_OK;
@@ -596,7 +597,7 @@ int lsp_stencil_setup(lsp_problem* p, int t, int num_shifts, int precision, void
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-    hipError_t e = lsp::launch_minmax(p, num_shifts);
+    hipError_t e = lsp::launch_minmax(p);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
@@ -634,11 +635,11 @@ int lsp_stencil_setup_global(lsp_problem* p, int t, int precision, void* P_dev,
   auto launch = [&]() -> hipError_t {
     const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
     int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-    hipError_t e = lsp::launch_minmax(p, 1, true);
+    hipError_t e = lsp::launch_minmax(p, true);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
-    e = lsp::launch_green_sums(p, 1);
+    e = lsp::launch_green_sums(p, 1, true);
     if (e != hipSuccess) return e;
     lsp::stage_end(p, tk);
     tk = lsp::stage_begin(p, LSP_STAGE_NULL);
@@ -707,7 +708,7 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
     t1.status = reinterpret_cast<int*>(take(sizeof(int) * S));
     p->nd1_shifts = ns;
   }
-  hipError_t e = lsp::launch_minmax(p, ns);
+  hipError_t e = lsp::launch_minmax(p);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, ns);
   if (e == hipSuccess) e = lsp::launch_null_nd(p, ns, p->nd1);
   if (e == hipSuccess) e = lsp::launch_assemble_nd(p, p->nd1.actab, leaf, P_dev, idx_dev);
@@ -782,7 +783,7 @@ int lsp_stencil_setup_learned(lsp_problem* p, lsp_mlp* mlp, int t, int num_shift
   // rho*(s)); the null-vector kernel also clears the fallback counter
   const int tk_all = lsp::stage_begin(p, LSP_STAGE_SETUP);
   int tk = lsp::stage_begin(p, LSP_STAGE_SHIFTS);
-  hipError_t e = lsp::launch_minmax(p, num_shifts);
+  hipError_t e = lsp::launch_minmax(p);
   lsp::stage_end(p, tk);
   tk = lsp::stage_begin(p, LSP_STAGE_GREEN);
   if (e == hipSuccess) e = lsp::launch_green_sums(p, num_shifts);

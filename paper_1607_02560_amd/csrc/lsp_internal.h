@@ -205,13 +205,14 @@ hipError_t launch_ps_apply(const lsp_problem* p, const double* u, double* y, hip
 // count of non-finite entries of x[0..count) written to *flag (flag zeroed first)
 hipError_t launch_count_nonfinite(const double* x, int64_t count, int* flag, hipStream_t s);
 // stencil setup stages
-// shift list S (Sec. 4.1; global: the one shift of the non-localized method
-// of Sec. 3) into ws.S, ws.nS and ws.vrange from one launch over v (min/max
-// partials, the last block forms the list); with cw non-null the same launch
-// also writes the folded cosine table of (cos_n, cos_w)
-hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
-                             bool global, hipStream_t s, int cos_n, int cos_w, double* cw);
-hipError_t launch_minmax(lsp_problem* p, int nreq, bool global = false);
+// min/max partials of v for the shift list S (Sec. 4.1; global: also the
+// per-block sums for the one shift of the non-localized method of Sec. 3)
+// into ws.minmax_part; the Green's-sum launch that follows forms S from them.
+// With cw non-null the same launch also writes the folded cosine table of
+// (cos_n, cos_w).
+hipError_t launch_minmax_parts(const double* v, int64_t N, const Workspace& ws, bool global,
+                               hipStream_t s, int cos_n, int cos_w, double* cw);
+hipError_t launch_minmax(lsp_problem* p, bool global = false);
 // folded cosine table cw[k][dl] = w(k) cos(2 pi k dl / n), k in [0, n/2], dl in [0, W),
 // followed by the same values halved and by k^2 (as doubles) for k in [0, n/2]
 hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s);
@@ -221,8 +222,11 @@ __host__ __device__ inline int cos_table_doubles(int n, int W) { return (n / 2 +
 // idx and the per-point C rows (p->c_rows, [N][5^d])
 hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
                               int32_t* idx);
-// Green's sums of the shifts in the workspace (num_shifts = requested |S|)
-hipError_t launch_green_sums(lsp_problem* p, int num_shifts);
+// Green's sums (num_shifts = requested |S|); every block of the launch forms
+// the shift list from the min/max partials that launch_minmax left in the
+// workspace and block 0 publishes it (ws.S, ws.nS, ws.vrange). global: the
+// one shift of the non-localized method.
+hipError_t launch_green_sums(lsp_problem* p, int num_shifts, bool global = false);
 // waves of the balanced 2D Green's launch for (n, requested |S|) and its steps
 // per shift; a function of the arguments only, shared by single and batched launches
 // waves of the balanced 2D Green's launch; max_waves (a multiple of 4,

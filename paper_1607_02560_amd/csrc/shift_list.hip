@@ -1,13 +1,14 @@
 // The shift list S of Sec. 4.1 (and the one shift of the non-localized
 // method of Sec. 3): a fixed grid of kMinMaxBlocks blocks writes per-block
 // (min, max) partials of the potential v (and, for the one shift, per-block
-// sums); one block then reduces the partials, forms the bin centres, snaps
-// them and removes duplicates, and publishes S, |S| and (v_min, v_max). No
-// value goes through the host. A single problem uses two launches (the
-// kernel boundary orders the partials before their reader, with no atomics
-// on the way); the batched form keeps one launch per batch, where the block
-// that finishes last (a ticket counter that is never reset: 256 tickets per
-// problem and launch, so it stays a multiple of 256) does the reduction.
+// sums); a block then reduces the partials, forms the bin centres, snaps
+// them and removes duplicates (lsp::shift_list_block). No value goes through
+// the host. For a single problem every block of the Green's-sum launch that
+// follows forms the list itself from the partials (the kernel boundary orders
+// them; no atomics), and its block 0 publishes S, |S| and (v_min, v_max).
+// The batched form keeps one launch per batch here, where the block that
+// finishes last (a ticket counter that is never reset: 256 tickets per
+// problem and launch, so it stays a multiple of 256) forms the list.
 //
 // The same launch can also write the folded cosine weights of the Green's
 // sums, cw[k][dl] = w(k) cos(2 pi k dl / n) for k in [0, n/2], dl in [0, W)
@@ -158,8 +159,8 @@ __device__ __forceinline__ void cos_entry(int n, int W, int e, double* cw) {
   cw[e] = halved ? 0.5 * c : c;
 }
 
-// first launch of a single problem: the partials (and, with cw, the cosine
-// tables, one entry per thread of the grid)
+// the partials of a single problem (and, with cw, the cosine tables, one
+// entry per thread of the grid)
 template <bool SUM>
 __global__ __launch_bounds__(kThreads) void minmax_part_kernel(const double* __restrict__ v,
                                                                int64_t N, double* part, int cos_n,
@@ -169,27 +170,6 @@ __global__ __launch_bounds__(kThreads) void minmax_part_kernel(const double* __r
     if (e < lsp::cos_table_doubles(cos_n, cos_w)) cos_entry(cos_n, cos_w, e, cw);
   }
   minmax_body<SUM, false>(blockIdx.x, lsp::kMinMaxBlocks, v, N, part);
-}
-
-// second launch: one block forms S from the partials of the launch before
-template <bool GLOBAL>
-__global__ __launch_bounds__(kThreads) void shift_from_parts_kernel(
-    const double* __restrict__ part, int64_t N, int nreq, double* S_out, int* nS_out,
-    double* vrange_out) {
-  __shared__ double sS[lsp::kMaxShifts];
-  __shared__ int sNS, sWave[kWaves];
-  __shared__ double sRange[2], sRed[3 * kWaves];
-  if constexpr (GLOBAL)
-    lsp::global_shift_block<kThreads>(part, N, sS, &sNS, sRange, sRed);
-  else
-    lsp::shift_list_block<kThreads>(part, nreq, sS, &sNS, sRange, sWave, sRed);
-  const int nS = sNS;
-  for (int i = threadIdx.x; i < nS; i += kThreads) S_out[i] = sS[i];
-  if (threadIdx.x == 0) {
-    *nS_out = nS;
-    vrange_out[0] = sRange[0];
-    vrange_out[1] = sRange[1];
-  }
 }
 
 __global__ __launch_bounds__(kThreads) void cos_table_kernel(int n, int W, double* cw) {
@@ -216,25 +196,20 @@ hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int bloc
   return hipGetLastError();
 }
 
-hipError_t launch_shift_list(const double* v, int64_t N, const Workspace& ws, int nreq,
-                             bool global, hipStream_t s, int cos_n, int cos_w, double* cw) {
+hipError_t launch_minmax_parts(const double* v, int64_t N, const Workspace& ws, bool global,
+                               hipStream_t s, int cos_n, int cos_w, double* cw) {
   if (cw && cos_table_doubles(cos_n, cos_w) > kMinMaxBlocks * kThreads) return hipErrorInvalidValue;
-  if (global) {
+  if (global)
     hipLaunchKernelGGL(minmax_part_kernel<true>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v, N,
                        ws.minmax_part, cos_n, cos_w, cw);
-    hipLaunchKernelGGL(shift_from_parts_kernel<true>, dim3(1), dim3(kThreads), 0, s,
-                       ws.minmax_part, N, 1, ws.S, ws.nS, ws.vrange);
-  } else {
+  else
     hipLaunchKernelGGL(minmax_part_kernel<false>, dim3(kMinMaxBlocks), dim3(kThreads), 0, s, v, N,
                        ws.minmax_part, cos_n, cos_w, cw);
-    hipLaunchKernelGGL(shift_from_parts_kernel<false>, dim3(1), dim3(kThreads), 0, s,
-                       ws.minmax_part, N, nreq, ws.S, ws.nS, ws.vrange);
-  }
   return hipGetLastError();
 }
 
-hipError_t launch_minmax(lsp_problem* p, int nreq, bool global) {
-  return launch_shift_list(p->v, p->N, p->ws, nreq, global, p->stream, 0, 0, nullptr);
+hipError_t launch_minmax(lsp_problem* p, bool global) {
+  return launch_minmax_parts(p->v, p->N, p->ws, global, p->stream, 0, 0, nullptr);
 }
 
 hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s) {

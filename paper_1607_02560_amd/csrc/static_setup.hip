@@ -142,9 +142,10 @@ int lsp_stencil_setup_static(int d, int n, const double* v_dev, int t, int num_s
   w.cap_m = m;
   w.cap_w = m;
   p.cosT = reinterpret_cast<double*>(base + c.cw);
-  // min/max partials with the cosine table, the shift list, then the Green's
-  // sums, the null vectors and the rows, as lsp_stencil_setup launches them
-  e = lsp::launch_shift_list(p.v, N, w, num_shifts, false, s, n, W, p.cosT);
+  // min/max partials with the cosine table, then the Green's sums (which form
+  // the shift list), the null vectors and the rows, as lsp_stencil_setup
+  // launches them
+  e = lsp::launch_minmax_parts(p.v, N, w, false, s, n, W, p.cosT);
   if (e == hipSuccess) e = lsp::launch_green_sums(&p, num_shifts);
   if (e == hipSuccess) e = lsp::launch_null_vectors(&p, num_shifts);
   if (e == hipSuccess) e = lsp::launch_assemble(&p, P_dev, precision == LSP_FP32_REFINE, idx_dev);

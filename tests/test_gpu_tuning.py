@@ -77,7 +77,7 @@ def test_every_shape_computes_the_same(torch_dev, n):
         assert np.array_equal(P132, P032), tile
     bound = row_bound(tab0)
     print(f"  row bound {bound:.2e}", flush=True)
-    for waves in (512, 1024, 1536, 2048):
+    for waves in (512, 1024, 1536, 2048, 3072):
         prob.set_tuning(green_waves=waves)
         P1, i1, tab1 = run(torch_dev, prob, p, t, P, idx)
         assert np.array_equal(i1, i0)
@@ -91,7 +91,7 @@ def test_every_shape_computes_the_same(torch_dev, n):
     prob.set_tuning()
     ch = prob.autotune(t, p.num_shifts, P, u, y, reps=3)
     print(f"  autotune: {ch}", flush=True)
-    assert ch["green_waves"][0] in (512, 1024, 1536, 2048)
+    assert ch["green_waves"][0] in (512, 1024, 1536, 2048, 3072)
     assert ch["assembly_tile"][0] in (32, 64, 128, 1)
     assert ch["apply_form"][0] in (8, 16)
     assert prob.get_tuning() == {k: v[0] for k, v in ch.items()}
