@@ -8,6 +8,7 @@
 
 namespace {
 
+using lsp::kBatchLdsTile;
 using lsp::nearest_shift;
 using lsp::Pow;
 
@@ -151,11 +152,11 @@ __global__ __launch_bounds__(256) void assemble_kernel(
 // block owns TR rows of TW points and first copies the nS x M table into LDS
 // (kActLds pairs at most), so the per-entry gathers read LDS; the copy is
 // amortised over the TR rows. Same stores, same arithmetic, same rows.
-constexpr int kActLds = 2048;  // (alpha, C) pairs staged in LDS: 32 KB
+using lsp::kActLds;
 
-template <int W, int TR, int TW, typename PT>
-__global__ __launch_bounds__(256) void assemble_lds_kernel(
-    const double* __restrict__ v, int n, const double* __restrict__ S,
+template <int W, int TR, int TW, typename PT, int ACT = kActLds>
+__device__ __forceinline__ void assemble_lds_body(
+    int bx, int by, const double* __restrict__ v, int n, const double* __restrict__ S,
     const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
     int32_t* __restrict__ idx_out) {
   constexpr int t = (W - 1) / 2;
@@ -163,15 +164,15 @@ __global__ __launch_bounds__(256) void assemble_lds_kernel(
   constexpr int HR = TR + 2 * t;
   constexpr int HC = TW + 2 * t;
   __shared__ double halo[HR * HC];
-  __shared__ double sS[kActLds / M];  // nS <= kActLds / M on this path
-  __shared__ double2 sAct[kActLds];
+  __shared__ double sS[ACT / M];  // nS <= ACT / M on this path
+  __shared__ double2 sAct[ACT];
   __shared__ int spM[TR * TW];
   __shared__ double spS[TR * TW];
   __shared__ int soff[M];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
-  const int c0 = blockIdx.x * TW;
-  const int r0 = blockIdx.y * TR;
+  const int c0 = bx * TW;
+  const int r0 = by * TR;
   const int mask = n - 1;
   for (int i = tid; i < nS; i += 256) sS[i] = S[i];
   for (int i = tid; i < nS * M; i += 256) sAct[i] = actab[i];
@@ -233,6 +234,26 @@ __global__ __launch_bounds__(256) void assemble_lds_kernel(
   }
 }
 
+template <int W, int TR, int TW, typename PT>
+__global__ __launch_bounds__(256) void assemble_lds_kernel(
+    const double* __restrict__ v, int n, const double* __restrict__ S,
+    const int* __restrict__ nS_ptr, const double2* __restrict__ actab, PT* __restrict__ P,
+    int32_t* __restrict__ idx_out) {
+  assemble_lds_body<W, TR, TW, PT>(blockIdx.x, blockIdx.y, v, n, S, nS_ptr, actab, P, idx_out);
+}
+
+// the same for the problems of a batch: block b is tile (map[b].y, map[b].z)
+// of problem map[b].x
+template <int W, int TR, int TW, typename PT>
+__global__ __launch_bounds__(256) void assemble_lds_batched_kernel(const lsp::BatchRec* recs,
+                                                                   const int4* map) {
+  const int4 it = map[blockIdx.x];
+  const lsp::BatchRec& r = recs[it.x];
+  assemble_lds_body<W, TR, TW, PT, lsp::kBatchActLds>(it.y, it.z, r.v, r.n, r.S, r.nS,
+                                                      reinterpret_cast<const double2*>(r.actab),
+                                                      static_cast<PT*>(r.P), r.idx);
+}
+
 // one launch for the problems of a batch: block b is tile (map[b].y, map[b].z,
 // map[b].w) of problem map[b].x
 template <int D, int W, int TR, int TW, typename PT>
@@ -253,7 +274,14 @@ __global__ __launch_bounds__(256) void assemble_batched_kernel(const lsp::BatchR
 // per-point-radius setup (leaf > 0) a point of radius 1 takes its row from
 // the radius-1 table C1 (zero outside mu_0^1).
 // --------------------------------------------------------------------------
-template <int D, int W, int TR, int TW>
+// LC: the shift table C (nS x m <= kCApplyLds values, nS <= kCApplyShifts)
+// is copied into LDS with the halo, so that a point's row is read from LDS
+// and the only global round trip before the sums is the one of the halo
+// (the point's v is loaded with it).
+constexpr int kCApplyShifts = 128;
+constexpr int kCApplyLds = 2048;
+
+template <int D, int W, int TR, int TW, bool LC>
 __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict__ rvec,
                                                       const double* __restrict__ v, int n,
                                                       const double* __restrict__ S,
@@ -267,15 +295,26 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
   constexpr int PL = (D == 3) ? W : 1;
   constexpr int HR = TR + 2 * t;
   constexpr int HC = TW + 2 * t;
+  static_assert(TR * TW <= 256, "one point per thread");
   __shared__ double2 halo[PL * HR * HC];
-  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ double sS[LC ? kCApplyShifts : lsp::kMaxShifts];
+  __shared__ double sC[LC ? kCApplyLds : 1];
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
   const int c0 = blockIdx.x * TW;
   const int r0 = blockIdx.y * TR;
   const int p0 = (D == 3) ? (int)blockIdx.z : 0;
   const int mask = n - 1;
+  // this thread's point (if any) and its potential, loaded with the halo
+  const bool has_pt = tid < TR * TW;
+  const int pr = tid / TW, pc = tid % TW;
+  const int64_t gpt = (D == 3) ? (((int64_t)p0 * n + r0 + pr) * n + c0 + pc)
+                               : ((int64_t)(r0 + pr) * n + c0 + pc);
+  const double vpt = has_pt ? v[gpt] : 0.0;
   for (int i = tid; i < nS; i += 256) sS[i] = S[i];
+  if constexpr (LC) {
+    for (int i = tid; i < nS * M; i += 256) sC[i] = Ctab[i];
+  }
   for (int e = tid; e < PL * HR * HC; e += 256) {
     const int hc = e % HC;
     const int hr = (e / HC) % HR;
@@ -292,18 +331,18 @@ __global__ __launch_bounds__(256) void c_apply_kernel(const double2* __restrict_
     halo[e] = rvec[g];
   }
   __syncthreads();
-  for (int pt = tid; pt < TR * TW; pt += 256) {
-    const int r = pt / TW, c = pt % TW;
-    const int64_t g = (D == 3) ? (((int64_t)p0 * n + r0 + r) * n + c0 + c)
-                               : ((int64_t)(r0 + r) * n + c0 + c);
+  if (has_pt) {
+    const int r = pr, c = pc;
+    const int64_t g = gpt;
     const double* crow;
     const double* crow1 = nullptr;  // radius-1 row of a per-point-radius setup
-    if (Crows) {
+    if (!LC && Crows) {
       crow = Crows + g * M;  // per-point rows of a learned setup
     } else {
-      const int id = nearest_shift(sS, nS, v[g]);
-      crow = Ctab + (int64_t)id * M;
-      if constexpr (W == 5) {
+      const int id = nearest_shift(sS, nS, vpt);
+      if constexpr (LC) crow = sC + id * M;
+      else crow = Ctab + (int64_t)id * M;
+      if constexpr (W == 5 && !LC) {
         if (leaf > 0) {
           int cp[D];
           if constexpr (D == 3) {
@@ -397,13 +436,27 @@ hipError_t run_assemble_tile(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
 template <int D, int W, int TW>
 hipError_t run_c_apply_tw(const lsp_problem* p, const double* r, double* z) {
   constexpr int TR = 4;
+  constexpr int M = Pow<D, W>::v;
   const int n = p->n;
   if (n % TW != 0 || n % TR != 0) return hipErrorInvalidValue;
   dim3 grid(n / TW, n / TR, (D == 3) ? n : 1);
-  hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW>), grid, dim3(256), 0, p->stream,
-                     reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS, p->ws.Ctab,
-                     p->learned ? p->c_rows : nullptr, p->nd1.C, p->learned ? 0 : p->nd_leaf,
-                     reinterpret_cast<double2*>(z));
+  // the LDS table form for the shift tables of a uniform-radius exact setup
+  // (the requested |S| bounds the one the setup kept), used in 3D with t = 1:
+  // 6.5 -> 5.8 us at n = 64; in 2D (n = 1024, t = 2: 16.6 -> 18.3 us) the
+  // copy of the table into every block of 256 points costs more than the
+  // gathers it saves, and in 3D with t = 2 (17.1 us either way) its LDS halves
+  // the residency
+  const bool lc = D == 3 && W == 3 && !p->learned && p->nd_leaf == 0 &&
+                  p->num_shifts <= kCApplyShifts && p->num_shifts * M <= kCApplyLds;
+  if (lc)
+    hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW, true>), grid, dim3(256), 0, p->stream,
+                       reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS,
+                       p->ws.Ctab, nullptr, nullptr, 0, reinterpret_cast<double2*>(z));
+  else
+    hipLaunchKernelGGL((c_apply_kernel<D, W, TR, TW, false>), grid, dim3(256), 0, p->stream,
+                       reinterpret_cast<const double2*>(r), p->v, n, p->ws.S, p->ws.nS,
+                       p->ws.Ctab, p->learned ? p->c_rows : nullptr, p->nd1.C,
+                       p->learned ? 0 : p->nd_leaf, reinterpret_cast<double2*>(z));
   return hipGetLastError();
 }
 
@@ -470,6 +523,21 @@ hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
 hipError_t launch_assemble_batched(int d, int t, int tw, bool fp32, const BatchRec* recs,
                                    const int4* map, int blocks, hipStream_t s) {
   const int W = 2 * t + 1;
+  // tw = kBatchLdsTile: 4 x 64 tiles with the shift tables in LDS (2D)
+#define LSP_ASM_LDS_B(W_)                                                                    \
+  if (d == 2 && W == W_ && tw == kBatchLdsTile) {                                            \
+    if (fp32)                                                                                \
+      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 4, 64, float>), dim3(blocks),      \
+                         dim3(256), 0, s, recs, map);                                        \
+    else                                                                                     \
+      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 4, 64, double>), dim3(blocks),     \
+                         dim3(256), 0, s, recs, map);                                        \
+    return hipGetLastError();                                                                \
+  }
+  LSP_ASM_LDS_B(3)
+  LSP_ASM_LDS_B(5)
+  LSP_ASM_LDS_B(7)
+#undef LSP_ASM_LDS_B
 #define LSP_ASM_B(D_, W_, TW_)                                                               \
   if (d == D_ && W == W_ && tw == TW_) {                                                     \
     if (fp32)                                                                                \

@@ -11,8 +11,10 @@
 // entry point (C-apply, GMRES, table export) works on them afterwards.
 //
 // The assembly tile width is chosen per batch by timing the candidate widths
-// that divide every n of the batch (the first setup of a batch, and again
-// whenever its sizes change).
+// that divide every n of the batch, and in 2D the LDS-table form (4 x 64
+// tiles, the shift tables copied into LDS; "width" 1) where every problem's
+// tables fit (the first setup of a batch, and again whenever its sizes or
+// shift counts change).
 #include "lsp_internal.h"
 
 #include <algorithm>
@@ -127,6 +129,12 @@ void build_maps(const lsp_batch* b, const std::vector<int>& nreq, int tw,
         for (int bx = 0; bx < p->green_nunits; ++bx) green.push_back(make_int4(i, bx, by, 0));
     }
     for (int si = 0; si < nreq[i]; ++si) null.push_back(make_int4(i, si, 0, 0));
+    if (tw == lsp::kBatchLdsTile) {
+      // 2D tiles of 4 rows x 64 points (the LDS-table form)
+      for (int by = 0; by < p->n / 4; ++by)
+        for (int bx = 0; bx < p->n / 64; ++bx) asmb.push_back(make_int4(i, bx, by, 0));
+      continue;
+    }
     const int planes = (b->d == 3) ? p->n : 1;
     for (int bz = 0; bz < planes; ++bz)
       for (int by = 0; by < p->n; ++by)
@@ -263,6 +271,7 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
     key.push_back(p->ws_gen);
     key.push_back((uint64_t)nreq[i]);
     sizes.push_back(p->n);
+    sizes.push_back(nreq[i]);
   }
   int rc = LSP_OK;
   if (key != b->rec_key) {
@@ -311,12 +320,26 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
     // tune the assembly tile width: one full setup, then each candidate width
     // that divides every n (the rows it writes are the same for every width)
     int ncand = 0;
+    int cand[5] = {0, 0, 0, 0, 0};
     for (int w : kTileWidths) {
       bool ok = true;
       for (const lsp_problem* p : b->probs) ok = ok && (p->n % w == 0);
-      if (ok) b->tw_candidates[ncand++] = w;
+      if (ok) cand[ncand++] = w;
     }
-    for (int c = ncand; c < 4; ++c) b->tw_candidates[c] = 0;
+    // the LDS-table form (2D, 4 x 64 tiles) where every problem's shift
+    // tables fit; with four widths as well, the smallest width gives way
+    bool lds = b->d == 2;
+    const int64_t m = (int64_t)(2 * t + 1) * (2 * t + 1);
+    for (int i = 0; i < count; ++i)
+      lds = lds && b->probs[i]->n % 64 == 0 && (int64_t)nreq[i] * m <= lsp::kBatchActLds;
+    if (lds) {
+      if (ncand == 4) {
+        for (int c = 0; c < 3; ++c) cand[c] = cand[c + 1];
+        ncand = 3;
+      }
+      cand[ncand++] = lsp::kBatchLdsTile;
+    }
+    for (int c = 0; c < 4; ++c) b->tw_candidates[c] = cand[c];
     if (ncand == 0) return lsp::set_error(LSP_EINVAL, "no assembly tile width divides every n");
     if ((rc = upload_maps(b, nreq, b->tw_candidates[ncand - 1]))) return rc;
     e = launch_stages(b, t, fp32, b->tw_candidates[ncand - 1]);
