@@ -6,7 +6,9 @@ per-point P rows) followed by one pseudospectral apply (L + diag v) u, on the
 stencils), |S| = 64, FP64. Inputs are resident on the GPU before timing.
 
 Prints one JSON line. value = local stencils per second, N / (mean device
-time of one setup over K setups, two events on the stream). ms_per_step is
+time of one setup over max(K, 100) setups after W of their own, two events on
+the stream: a steady-state rate; the same count times the apply, the C-apply
+and the other setup forms of this workload). ms_per_step is
 the wall time of the K timed steps (setup + apply) between device
 synchronisations. ps_apply bandwidth is algorithmic bytes / mean apply time.
 The roofline of the dominant kernel (the per-point assembly) uses its average
@@ -585,25 +587,26 @@ def main():
         step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    # setup alone and apply alone, K calls each (after W setups of their own:
-    # the step loop above interleaves the apply)
+    # setup alone and apply alone, max(K, 100) calls each (after W setups of
+    # their own: the step loop above interleaves the apply)
+    reps = max(args.steps, 100)
     for _ in range(args.warmup):
         prob.stencil_setup(t, p.num_shifts, P, idx)
-    t_setup = timed(stream, lambda: prob.stencil_setup(t, p.num_shifts, P, idx), args.steps)
-    t_apply = timed(stream, lambda: prob.ps_apply(u, y), args.steps)
+    t_setup = timed(stream, lambda: prob.stencil_setup(t, p.num_shifts, P, idx), reps)
+    t_apply = timed(stream, lambda: prob.ps_apply(u, y), reps)
     # the C-apply z = C r of the preconditioner (once per GMRES iteration) on
     # the tables of this setup
     zc = torch.empty_like(u)
     for _ in range(args.warmup):
         prob.c_apply(u, zc)
-    t_capply = timed(stream, lambda: prob.c_apply(u, zc), args.steps)
+    t_capply = timed(stream, lambda: prob.c_apply(u, zc), reps)
     del zc
     # the FP32-storage form: same FP64 setup, P rows rounded to float32
     P32 = torch.empty(N * m, dtype=torch.float32, device=dev)
     setup32 = lambda: prob.stencil_setup(t, p.num_shifts, P32, idx, precision=lsp.LSP_FP32_REFINE)
     for _ in range(args.warmup):
         setup32()
-    t_setup32 = timed(stream, setup32, args.steps)
+    t_setup32 = timed(stream, setup32, reps)
     del P32
     # the non-localized setup of Sec. 3 (one shift, the mean of v) on the
     # same field and buffers
@@ -611,7 +614,7 @@ def main():
         setup_g = lambda: prob.stencil_setup_global(t, P, idx)
         for _ in range(args.warmup):
             setup_g()
-        t_setup_g = timed(stream, setup_g, args.steps)
+        t_setup_g = timed(stream, setup_g, reps)
     # per-stage HIP events recorded by the library on its stream (direct
     # launches): the dominant kernel's average duration for the roofline
     prob.profile(True)
@@ -681,7 +684,7 @@ def main():
         setup_nd = lambda: prob.stencil_setup_nd(8, p.num_shifts, P, idx)
         for _ in range(args.warmup):
             setup_nd()
-        t_nd = timed(stream, setup_nd, args.steps)
+        t_nd = timed(stream, setup_nd, reps)
         out["form_nd_radius"] = {"leaf": 8, "t_max": 2, "setup_ms": t_nd * 1e3,
                                  "stencils_per_s": N / t_nd}
     prob.close()

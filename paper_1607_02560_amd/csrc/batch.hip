@@ -169,7 +169,8 @@ int upload_maps(lsp_batch* b, const std::vector<int>& nreq, int tw) {
 }
 
 hipError_t launch_stages(const lsp_batch* b, int t, bool fp32, int tw) {
-  hipError_t e = lsp::launch_minmax_batched(b->recs, b->maps + b->off_mm, b->n_mm, b->stream);
+  hipError_t e = lsp::launch_minmax_batched(b->recs, b->maps + b->off_mm, b->n_mm,
+                                            (int)b->probs.size(), b->stream);
   if (e == hipSuccess)
     e = lsp::launch_green_batched(b->d, t, b->recs, b->maps + b->off_green, b->n_green,
                                   b->stream);
@@ -285,7 +286,6 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
       r.N = p->N;
       r.invN = 1.0 / (double)p->N;
       r.mm_part = p->ws.minmax_part;
-      r.ticket = p->ws.ticket;
       r.S = p->ws.S;
       r.nS = p->ws.nS;
       r.vrange = p->ws.vrange;

@@ -383,9 +383,10 @@ __device__ __forceinline__ void green_body(
 
 // Shift list of a single problem, formed by every block of its Green's-sum
 // launch from the min/max partials of the launch before (the same list in
-// every block: the same partials through the same fixed-order code); block 0
-// also publishes S, |S| and (v_min, v_max) for the launches after. GLOBAL:
-// the one shift of the non-localized method.
+// every block: the same partials through the same fixed-order code); block
+// (0, 0) (publish) also writes S, |S| and (v_min, v_max) for the launches
+// after. global: the one shift of the non-localized method. (The batched
+// launches read the list that the batched shift-list launch formed.)
 struct ShiftShared {
   double S[lsp::kMaxShifts];
   double range[2];
@@ -395,7 +396,7 @@ struct ShiftShared {
 };
 
 __device__ __forceinline__ void shift_prologue(ShiftShared& sh, const double* __restrict__ mm_part,
-                                               int64_t N, int nreq, int global,
+                                               int64_t N, int nreq, int global, bool publish,
                                                double* __restrict__ S_out,
                                                int* __restrict__ nS_out,
                                                double* __restrict__ vrange_out) {
@@ -403,7 +404,7 @@ __device__ __forceinline__ void shift_prologue(ShiftShared& sh, const double* __
     lsp::global_shift_block<kThreads>(mm_part, N, sh.S, &sh.nS, sh.range, sh.red);
   else
     lsp::shift_list_block<kThreads>(mm_part, nreq, sh.S, &sh.nS, sh.range, sh.wave, sh.red);
-  if (blockIdx.x == 0 && blockIdx.y == 0) {
+  if (publish) {
     for (int i = threadIdx.x; i < sh.nS; i += kThreads) S_out[i] = sh.S[i];
     if (threadIdx.x == 0) {
       *nS_out = sh.nS;
@@ -420,7 +421,8 @@ __global__ __launch_bounds__(kThreads) void green_sums_kernel(
     double* __restrict__ part, double* __restrict__ S_out, int* __restrict__ nS_out,
     double* __restrict__ vrange_out) {
   __shared__ ShiftShared sh;
-  shift_prologue(sh, mm_part, N, nreq, global, S_out, nS_out, vrange_out);
+  shift_prologue(sh, mm_part, N, nreq, global, blockIdx.x == 0 && blockIdx.y == 0, S_out, nS_out,
+                 vrange_out);
   green_body<D, W, KT>(blockIdx.x, blockIdx.y, gridDim.x, sh.S, &sh.nS, cw, units, n, part);
 }
 
@@ -621,7 +623,8 @@ __global__ __launch_bounds__(kThreads) void green2d_kernel(
     const double* __restrict__ cw, int n, double* __restrict__ part, double* __restrict__ S_out,
     int* __restrict__ nS_out, double* __restrict__ vrange_out) {
   __shared__ ShiftShared sh;
-  shift_prologue(sh, mm_part, N, nreq, global, S_out, nS_out, vrange_out);
+  shift_prologue(sh, mm_part, N, nreq, global, blockIdx.x == 0 && blockIdx.y == 0, S_out, nS_out,
+                 vrange_out);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wave = blockIdx.x * kWaves + wid;
   green2d_body<W>(wave, nwv, sh.S, &sh.nS, cw, n, part);

@@ -39,7 +39,6 @@ int dalloc(void** ptr, size_t bytes, const char* what) {
 void free_workspace(lsp_problem* p) {
   lsp::Workspace& w = p->ws;
   dfree(w.minmax_part);
-  dfree(w.ticket);
   dfree(w.S);
   dfree(w.nS);
   dfree(w.vrange);
@@ -63,9 +62,6 @@ int ensure_workspace(lsp_problem* p, int shifts, int t, int m, int wd) {
   if (!w.minmax_part) {
     if ((rc = dalloc((void**)&w.minmax_part, sizeof(double) * 3 * lsp::kMinMaxBlocks, "minmax")))
       return rc;
-    if ((rc = dalloc((void**)&w.ticket, sizeof(unsigned), "ticket"))) return rc;
-    if (hipMemsetAsync(w.ticket, 0, sizeof(unsigned), p->stream) != hipSuccess)
-      return lsp::set_error(LSP_EHIP, "hipMemsetAsync(ticket) failed");
     if ((rc = dalloc((void**)&w.S, sizeof(double) * lsp::kMaxShifts, "S"))) return rc;
     if ((rc = dalloc((void**)&w.nS, sizeof(int), "nS"))) return rc;
     if ((rc = dalloc((void**)&w.vrange, sizeof(double) * 2, "vrange"))) return rc;

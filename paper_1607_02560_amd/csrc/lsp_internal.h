@@ -28,7 +28,6 @@ constexpr int kBatchActLds = 1024;  // its table capacity in pairs (16 KB: more 
 struct Workspace {
   // shift list (Sec. 4.1)
   double* minmax_part = nullptr;  // [2 * kMinMaxBlocks] (min, max), then [kMinMaxBlocks] sums
-  unsigned* ticket = nullptr;     // min/max blocks' ticket counter (a multiple of kMinMaxBlocks between launches)
   double* S = nullptr;            // [kMaxShifts]
   int* nS = nullptr;              // effective |S|, device resident
   double* vrange = nullptr;       // [2] v_min, v_max
@@ -60,7 +59,6 @@ struct BatchRec {
   int64_t N;
   double invN;
   double* mm_part;   // min/max partials
-  unsigned* ticket;  // their ticket counter
   double* S;
   int* nS;
   double* vrange;
@@ -252,7 +250,10 @@ hipError_t launch_null_nd(lsp_problem* p, int num_shifts, const NdTables1& t1);
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);
 // batched launches: one launch per stage over the problems of a batch; map
 // holds (problem, block coordinates) per block
-hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int blocks,
+// min/max partials of every problem of a batch (map: (problem, block) of
+// each problem's kMinMaxBlocks blocks), then each problem's shift list
+// (count problems, one block each)
+hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int blocks, int count,
                                  hipStream_t s);
 hipError_t launch_green_batched(int d, int t, const BatchRec* recs, const int4* map, int blocks,
                                 hipStream_t s);

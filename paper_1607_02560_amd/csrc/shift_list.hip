@@ -1,14 +1,12 @@
 // The shift list S of Sec. 4.1 (and the one shift of the non-localized
-// method of Sec. 3): a fixed grid of kMinMaxBlocks blocks writes per-block
-// (min, max) partials of the potential v (and, for the one shift, per-block
-// sums); a block then reduces the partials, forms the bin centres, snaps
-// them and removes duplicates (lsp::shift_list_block). No value goes through
-// the host. For a single problem every block of the Green's-sum launch that
-// follows forms the list itself from the partials (the kernel boundary orders
-// them; no atomics), and its block 0 publishes S, |S| and (v_min, v_max).
-// The batched form keeps one launch per batch here, where the block that
-// finishes last (a ticket counter that is never reset: 256 tickets per
-// problem and launch, so it stays a multiple of 256) forms the list.
+// method of Sec. 3): a grid of blocks writes per-block (min, max) partials of
+// the potential v (and, for the one shift, per-block sums) with plain
+// stores; then the partials are reduced, the bin centres formed, snapped and
+// deduplicated (lsp::shift_list_block; the kernel boundary orders the
+// partials, no atomics). Every problem takes kMinMaxBlocks blocks. For a
+// single problem every block of its Green's-sum launch forms the list (block
+// 0 publishes S, |S| and (v_min, v_max)); a batch forms each problem's list
+// in a one-block-per-problem launch. No value goes through the host.
 //
 // The same launch can also write the folded cosine weights of the Green's
 // sums, cw[k][dl] = w(k) cos(2 pi k dl / n) for k in [0, n/2], dl in [0, W)
@@ -28,9 +26,7 @@ constexpr int kUnroll = 8;
 // in its own element order, then a butterfly over the lanes (both partners
 // add the same two values, so every lane holds the same sum), then the waves
 // in index order.
-// ATOMIC writes the partials with device-scope atomic swaps (for a reader in
-// the same launch), else with plain stores (for a reader in a later launch).
-template <bool SUM, bool ATOMIC>
+template <bool SUM>
 __device__ __forceinline__ void minmax_body(int bx, int gx, const double* __restrict__ v,
                                             int64_t N, double* part) {
   __shared__ double wmin[kWaves], wmax[kWaves], wsum[kWaves];
@@ -77,65 +73,8 @@ __device__ __forceinline__ void minmax_body(int bx, int gx, const double* __rest
       hi = fmax(hi, wmax[w]);
       if constexpr (SUM) sum += wsum[w];
     }
-    // device-scope atomic swaps: they take effect where the ticket's atomic
-    // does, so the last block's atomic reads see them without writing back
-    // this XCD's L2 (which a fence would); s_waitcnt below makes them
-    // complete before the ticket is drawn
-    if constexpr (ATOMIC) {
-      using u64 = unsigned long long;
-      u64* pu = reinterpret_cast<u64*>(part);
-      (void)atomicExch(pu + 2 * bx, (u64)__double_as_longlong(lo));
-      (void)atomicExch(pu + 2 * bx + 1, (u64)__double_as_longlong(hi));
-      if constexpr (SUM)
-        (void)atomicExch(pu + 2 * lsp::kMinMaxBlocks + bx, (u64)__double_as_longlong(sum));
-    } else {
-      reinterpret_cast<double2*>(part)[bx] = make_double2(lo, hi);
-      if constexpr (SUM) part[2 * lsp::kMinMaxBlocks + bx] = sum;
-    }
-  }
-}
-
-// Block bx of kMinMaxBlocks: its partials, then a ticket; the block that draws
-// the last ticket of the launch forms the shift list from all partials.
-// GLOBAL: the one shift of the non-localized method (the mean of v), else the
-// nreq bin centres of Sec. 4.1.
-template <bool GLOBAL>
-__device__ __forceinline__ void minmax_shift_body(int bx, const double* __restrict__ v, int64_t N,
-                                                  double* part, unsigned* ticket, int nreq,
-                                                  double* S_out, int* nS_out,
-                                                  double* vrange_out) {
-  minmax_body<GLOBAL, true>(bx, lsp::kMinMaxBlocks, v, N, part);
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __builtin_amdgcn_s_waitcnt(0);  // the partials' swaps have completed
-    const unsigned tk = atomicAdd(ticket, 1u);
-    last = ((tk + 1u) % (unsigned)lsp::kMinMaxBlocks) == 0u;
-  }
-  __syncthreads();
-  if (!last) return;
-  // every block's partials, read with device-scope atomics (see minmax_body)
-  __shared__ double sPart[3 * lsp::kMinMaxBlocks];
-  {
-    using u64 = unsigned long long;
-    u64* pu = reinterpret_cast<u64*>(part);
-    constexpr int cnt = (GLOBAL ? 3 : 2) * lsp::kMinMaxBlocks;
-    for (int e = threadIdx.x; e < cnt; e += kThreads)
-      sPart[e] = __longlong_as_double((long long)atomicAdd(pu + e, 0ull));
-  }
-  __syncthreads();
-  __shared__ double sS[lsp::kMaxShifts];
-  __shared__ int sNS, sWave[kWaves];
-  __shared__ double sRange[2], sRed[3 * kWaves];
-  if constexpr (GLOBAL)
-    lsp::global_shift_block<kThreads>(sPart, N, sS, &sNS, sRange, sRed);
-  else
-    lsp::shift_list_block<kThreads>(sPart, nreq, sS, &sNS, sRange, sWave, sRed);
-  const int nS = sNS;
-  for (int i = threadIdx.x; i < nS; i += kThreads) S_out[i] = sS[i];
-  if (threadIdx.x == 0) {
-    *nS_out = nS;
-    vrange_out[0] = sRange[0];
-    vrange_out[1] = sRange[1];
+    reinterpret_cast<double2*>(part)[bx] = make_double2(lo, hi);
+    if constexpr (SUM) part[2 * lsp::kMinMaxBlocks + bx] = sum;
   }
 }
 
@@ -169,7 +108,7 @@ __global__ __launch_bounds__(kThreads) void minmax_part_kernel(const double* __r
     const int e = blockIdx.x * kThreads + threadIdx.x;
     if (e < lsp::cos_table_doubles(cos_n, cos_w)) cos_entry(cos_n, cos_w, e, cw);
   }
-  minmax_body<SUM, false>(blockIdx.x, lsp::kMinMaxBlocks, v, N, part);
+  minmax_body<SUM>(blockIdx.x, lsp::kMinMaxBlocks, v, N, part);
 }
 
 __global__ __launch_bounds__(kThreads) void cos_table_kernel(int n, int W, double* cw) {
@@ -183,18 +122,35 @@ __global__ __launch_bounds__(kThreads) void minmax_batched_kernel(const lsp::Bat
                                                                   const int4* map) {
   const int4 it = map[blockIdx.x];
   const lsp::BatchRec& r = recs[it.x];
-  minmax_shift_body<false>(it.y, r.v, r.N, r.mm_part, r.ticket, r.nreq, r.S, r.nS, r.vrange);
+  minmax_body<false>(it.y, lsp::kMinMaxBlocks, r.v, r.N, r.mm_part);
+}
+
+// block b forms the shift list of problem b of a batch from its partials
+__global__ __launch_bounds__(kThreads) void shift_list_batched_kernel(const lsp::BatchRec* recs) {
+  const lsp::BatchRec& r = recs[blockIdx.x];
+  __shared__ double sS[lsp::kMaxShifts];
+  __shared__ int sNS, sWave[kWaves];
+  __shared__ double sRange[2], sRed[3 * kWaves];
+  lsp::shift_list_block<kThreads>(r.mm_part, r.nreq, sS, &sNS, sRange, sWave, sRed);
+  for (int i = threadIdx.x; i < sNS; i += kThreads) r.S[i] = sS[i];
+  if (threadIdx.x == 0) {
+    *r.nS = sNS;
+    r.vrange[0] = sRange[0];
+    r.vrange[1] = sRange[1];
+  }
 }
 
 }  // namespace
 
 namespace lsp {
 
-hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int blocks,
+hipError_t launch_minmax_batched(const BatchRec* recs, const int4* map, int blocks, int count,
                                  hipStream_t s) {
   hipLaunchKernelGGL(minmax_batched_kernel, dim3(blocks), dim3(kThreads), 0, s, recs, map);
+  hipLaunchKernelGGL(shift_list_batched_kernel, dim3(count), dim3(kThreads), 0, s, recs);
   return hipGetLastError();
 }
+
 
 hipError_t launch_minmax_parts(const double* v, int64_t N, const Workspace& ws, bool global,
                                hipStream_t s, int cos_n, int cos_w, double* cw) {
