@@ -535,6 +535,14 @@ int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* 
  * gives way to it when four widths divide every n). */
 int lsp_batch_tile(const lsp_batch* b, int* tile_width, int* candidates, float* ms);
 
+/* Fix the assembly tile width of the following setups of the batch instead of
+ * tuning it: 16, 32, 64 or 128 (must divide every n), or 1 (the LDS-table
+ * form: 2D, every n a multiple of 64, |S| m <= 1024 for every problem); 0
+ * returns to the tuner. Every width gives the same rows. LSP_EINVAL for
+ * another value here, or at the next lsp_batch_stencil_setup if the width
+ * does not fit that batch (nothing is launched then). */
+int lsp_batch_set_tile(lsp_batch* b, int tile_width);
+
 #ifdef __cplusplus
 }
 #endif

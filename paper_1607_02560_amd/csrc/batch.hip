@@ -37,6 +37,8 @@ struct lsp_batch {
   // it was tuned on
   int tw = 0;
   std::vector<int> tuned_key;
+  int forced_tw = 0;       // lsp_batch_set_tile: 0 = tune, else this width
+  bool tw_forced = false;  // the current tw came from forced_tw
   int tw_candidates[4] = {0, 0, 0, 0};
   float tw_ms[4] = {0, 0, 0, 0};
   // graphs
@@ -316,7 +318,34 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
     drop(b->g_setup);
   }
   hipError_t e = hipSuccess;
-  if (b->tw == 0 || sizes != b->tuned_key) {
+  const int64_t m_rows = (int64_t)(2 * t + 1) * (2 * t + 1);
+  // the LDS-table form (2D, 4 x 64 tiles) where every problem's shift tables fit
+  bool lds_ok = b->d == 2;
+  for (int i = 0; i < count; ++i)
+    lds_ok = lds_ok && b->probs[i]->n % 64 == 0 && (int64_t)nreq[i] * m_rows <= lsp::kBatchActLds;
+  if (b->forced_tw) {
+    // a width set by the caller: checked against this batch, no tuning
+    const int w = b->forced_tw;
+    bool ok = (w == lsp::kBatchLdsTile) ? lds_ok : true;
+    if (w != lsp::kBatchLdsTile)
+      for (const lsp_problem* p : b->probs) ok = ok && (p->n % w == 0);
+    if (!ok)
+      return lsp::set_error(LSP_EINVAL, "the assembly tile width set for this batch does not "
+                                        "fit its sizes or shift tables");
+    if (!b->tw_forced || b->tw != w || sizes != b->tuned_key || b->n_asm == 0 ||
+        b->setup_key.empty() || key != b->setup_key) {
+      b->tw = w;
+      b->tw_forced = true;
+      b->tuned_key = sizes;
+      for (int c = 0; c < 4; ++c) {
+        b->tw_candidates[c] = (c == 0) ? w : 0;
+        b->tw_ms[c] = 0.f;
+      }
+      if ((rc = upload_maps(b, nreq, w))) return rc;
+      drop(b->g_setup);
+    }
+  } else if (b->tw == 0 || b->tw_forced || sizes != b->tuned_key) {
+    b->tw_forced = false;
     // tune the assembly tile width: one full setup, then each candidate width
     // that divides every n (the rows it writes are the same for every width)
     int ncand = 0;
@@ -326,13 +355,9 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
       for (const lsp_problem* p : b->probs) ok = ok && (p->n % w == 0);
       if (ok) cand[ncand++] = w;
     }
-    // the LDS-table form (2D, 4 x 64 tiles) where every problem's shift
-    // tables fit; with four widths as well, the smallest width gives way
-    bool lds = b->d == 2;
-    const int64_t m = (int64_t)(2 * t + 1) * (2 * t + 1);
-    for (int i = 0; i < count; ++i)
-      lds = lds && b->probs[i]->n % 64 == 0 && (int64_t)nreq[i] * m <= lsp::kBatchActLds;
-    if (lds) {
+    // the LDS-table form where it fits; with four widths as well, the
+    // smallest width gives way
+    if (lds_ok) {
       if (ncand == 4) {
         for (int c = 0; c < 3; ++c) cand[c] = cand[c + 1];
         ncand = 3;
@@ -433,6 +458,15 @@ int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* 
     return fe != hipSuccess ? fe : le;
   });
   return lsp::hip_check(e, "batched ps_apply launch");
+}
+
+int lsp_batch_set_tile(lsp_batch* b, int tile_width) {
+  if (!b) return lsp::set_error(LSP_EINVAL, "NULL argument");
+  bool known = tile_width == 0 || tile_width == lsp::kBatchLdsTile;
+  for (int w : kTileWidths) known = known || tile_width == w;
+  if (!known) return lsp::set_error(LSP_EINVAL, "tile width must be 0, 1, 16, 32, 64 or 128");
+  b->forced_tw = tile_width;
+  return LSP_OK;
 }
 
 int lsp_batch_tile(const lsp_batch* b, int* tile_width, int* candidates, float* ms) {

@@ -116,6 +116,7 @@ def load():
                                             c_void_p]),
         "lsp_batch_ps_apply": (c_int, [c_void_p, c_void_p, c_void_p]),
         "lsp_batch_tile": (c_int, [c_void_p, P(c_int), c_void_p, c_void_p]),
+        "lsp_batch_set_tile": (c_int, [c_void_p, c_int]),
         "lsp_get_tables_nd1": (c_int, [c_void_p, c_int, P(c_int), c_void_p, c_void_p,
                                        c_void_p, c_void_p, c_void_p]),
         "lsp_autotune": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p,
@@ -517,6 +518,11 @@ class Batch:
             up[i] = _ptr(u_list[i])
             yp[i] = _ptr(y_list[i])
         _check(self.lib.lsp_batch_ps_apply(self._h, up, yp), "lsp_batch_ps_apply")
+
+    def set_tile(self, tile_width: int = 0):
+        """lsp_batch_set_tile: fix the assembly tile width (16, 32, 64, 128,
+        or 1 for the LDS-table form) of the following setups; 0 = tune."""
+        _check(self.lib.lsp_batch_set_tile(self._h, int(tile_width)), "lsp_batch_set_tile")
 
     def tile(self):
         """(chosen assembly tile width, candidate widths, their mean ms)."""

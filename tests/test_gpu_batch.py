@@ -243,3 +243,52 @@ def test_batch_c5_workload(torch_dev):
     batch.close()
     for p in probs:
         p.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_every_tile_width(torch_dev, precision):
+    """Every assembly tile width the tuner may pick (set with
+    lsp_batch_set_tile, including the LDS-table form 1) gives each problem
+    its single setup's rows bit for bit; widths that do not fit the batch are
+    refused before anything is launched."""
+    torch, dev = torch_dev
+    from paper_1607_02560_amd import lsp
+    stream = torch.cuda.Stream()
+    sizes = [64, 128, 64, 256]
+    fields = [W.helm2d_random(n, seed=30 + i, t=2).v for i, n in enumerate(sizes)]
+    nS = [max(1, n // 16) for n in sizes]
+    probs = make_problems(torch_dev, fields, stream)
+    batch = lsp.Batch(probs)
+    Ps, idxs = [], []
+    for p in probs:
+        Ps.append(torch.empty(p.N * 25, dtype=torch.float32 if precision else torch.float64,
+                              device=dev))
+        idxs.append(torch.empty(p.N, dtype=torch.int32, device=dev))
+    singles = [single_setup(torch_dev, v, 2, nS[i], precision, stream)
+               for i, v in enumerate(fields)]
+    for tw in (1, 16, 32, 64, 0):
+        batch.set_tile(tw)
+        for P in Ps:
+            P.fill_(float("nan"))
+        for ix in idxs:
+            ix.fill_(-1)
+        torch.cuda.synchronize()
+        batch.stencil_setup(2, nS, Ps, idxs, precision=precision)
+        torch.cuda.synchronize()
+        got_tw = batch.tile()[0]
+        print(f"[batch tile] requested {tw}, used {got_tw}", flush=True)
+        if tw:
+            assert got_tw == tw
+        for i in range(len(sizes)):
+            assert np.array_equal(Ps[i].cpu().numpy(), singles[i][0]), (tw, i)
+            assert np.array_equal(idxs[i].cpu().numpy(), singles[i][1]), (tw, i)
+    with pytest.raises(lsp.LSPError) as ei:
+        batch.set_tile(48)
+    assert ei.value.code == lsp.LSP_EINVAL
+    batch.set_tile(128)  # does not divide n = 64: refused at the setup
+    with pytest.raises(lsp.LSPError) as ei:
+        batch.stencil_setup(2, nS, Ps, idxs, precision=precision)
+    assert ei.value.code == lsp.LSP_EINVAL
+    batch.close()
+    for p in probs:
+        p.close()
