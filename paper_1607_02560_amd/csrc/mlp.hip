@@ -16,6 +16,8 @@
 //   W1 [H][Ip], b1 [H], W2 [H][H], b2 [H], W3 [Op][H], b3 [Op]
 //   activations [rows][H] (FP32 pre-activations, BF16 post-activations),
 //   inputs [rows][Ip] BF16, outputs [rows][Op] FP32.
+#include <type_traits>
+
 #include "setup_common.h"
 
 #include <cstdio>
@@ -54,6 +56,10 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // its raw partial tile to C + z M ldc (split_reduce_kernel adds them).
 // MFMA operand layout: lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16]
 // and D[4(l/16)+i][l%16], i = 0..3.
+// AK1 / BK1: the operand is contiguous in k (sak = 1 / sbk = 1, rows 8-byte
+// aligned), so the four k values a lane needs per 16 come in one 8-byte load
+// instead of four 2-byte loads (the same values, the same sums).
+template <bool AK1, bool BK1>
 __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     const unsigned short* __restrict__ A, int64_t sam, int64_t sak,
     const unsigned short* __restrict__ B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
@@ -76,35 +82,48 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
   }
   // two 32-blocks of operands are loaded before their two MFMAs (one memory
   // round trip per 64 values of k); the MFMAs run in k order either way
-  auto load8 = [&](const unsigned short* p, int64_t stride, int kbase) {
-    s16x8 v;
+  auto load8 = [&](const unsigned short* p, int64_t stride, int kbase, auto unit) {
+    if constexpr (decltype(unit)::value) {
+      const uint2 lo = *reinterpret_cast<const uint2*>(p + kbase + kq);
+      const uint2 hi = *reinterpret_cast<const uint2*>(p + kbase + 16 + kq);
+      return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+    } else {
+      s16x8 v;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      v[i] = (short)p[(int64_t)(kbase + kq + i) * stride];
-      v[4 + i] = (short)p[(int64_t)(kbase + 16 + kq + i) * stride];
+      for (int i = 0; i < 4; ++i) {
+        v[i] = (short)p[(int64_t)(kbase + kq + i) * stride];
+        v[4 + i] = (short)p[(int64_t)(kbase + 16 + kq + i) * stride];
+      }
+      return __builtin_bit_cast(bf16x8, v);
     }
-    return __builtin_bit_cast(bf16x8, v);
   };
+  auto load4 = [&](const unsigned short* p, int64_t stride, int kbase, auto unit) {
+    if constexpr (decltype(unit)::value) {
+      return __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2*>(p + kbase + kq));
+    } else {
+      bf16x4 v;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v[i] = (short)p[(int64_t)(kbase + kq + i) * stride];
+      return v;
+    }
+  };
+  const std::integral_constant<bool, AK1> ua{};
+  const std::integral_constant<bool, BK1> ub{};
   int k0 = kb;
   for (; k0 + 64 <= ke; k0 += 64) {
-    const bf16x8 a0 = load8(ap, sak, k0), b0 = load8(bp, sbk, k0);
-    const bf16x8 a1 = load8(ap, sak, k0 + 32), b1 = load8(bp, sbk, k0 + 32);
+    const bf16x8 a0 = load8(ap, sak, k0, ua), b0 = load8(bp, sbk, k0, ub);
+    const bf16x8 a1 = load8(ap, sak, k0 + 32, ua), b1 = load8(bp, sbk, k0 + 32, ub);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
   }
   if (k0 + 32 <= ke) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(ap, sak, k0), load8(bp, sbk, k0), acc,
-                                                  0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(load8(ap, sak, k0, ua), load8(bp, sbk, k0, ub),
+                                                  acc, 0, 0, 0);
     k0 += 32;
   }
   if (k0 < ke) {  // the last 16 values of k
-    bf16x4 a, b;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a[i] = (short)ap[(int64_t)(k0 + kq + i) * sak];
-      b[i] = (short)bp[(int64_t)(k0 + kq + i) * sbk];
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(load4(ap, sak, k0, ua), load4(bp, sbk, k0, ub),
+                                                    acc, 0, 0, 0);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -240,12 +259,21 @@ __global__ __launch_bounds__(kT) void colsum_partial_kernel(const float* __restr
 }
 
 // Stage 2: out[c] = sum over row blocks of part[rb][c], in row-block order
+// (eight loads in flight, added in order)
 __global__ void colsum_final_kernel(const float* __restrict__ part, int nrb, int ncol,
                                     float* out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   float s = 0.f;
-  for (int rb = 0; rb < nrb; ++rb) s += part[(int64_t)rb * ncol + c];
+  int rb = 0;
+  for (; rb + 8 <= nrb; rb += 8) {
+    float x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = part[(int64_t)(rb + u) * ncol + c];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += x[u];
+  }
+  for (; rb < nrb; ++rb) s += part[(int64_t)rb * ncol + c];
   out[c] = s;
 }
 
@@ -376,22 +404,27 @@ hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak
                 int N, int K, const float* bias, bool accumulate, float* split_buf = nullptr,
                 size_t split_cap = 0) {
   dim3 grid((N + 31) / 32, (M + 31) / 32);
+  // operands contiguous in k with 8-byte aligned rows take the vector loads
+  const bool ak1 = sak == 1 && sam % 4 == 0 && ((uintptr_t)A & 7) == 0;
+  const bool bk1 = sbk == 1 && sbn % 4 == 0 && ((uintptr_t)B & 7) == 0;
+  auto kern = ak1 ? (bk1 ? gemm_bf16_kernel<true, true> : gemm_bf16_kernel<true, false>)
+                  : (bk1 ? gemm_bf16_kernel<false, true> : gemm_bf16_kernel<false, false>);
   int splits = 1;
   if (split_buf && K >= 1024 && (int)(grid.x * grid.y) < 128) {
     splits = std::min(64, K / 256);
     while (splits > 1 && (size_t)splits * M * N > split_cap) splits /= 2;
   }
   if (splits <= 1) {
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc,
-                       M, N, K, bias, accumulate ? 1 : 0, K);
+    hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K,
+                       bias, accumulate ? 1 : 0, K);
     return hipGetLastError();
   }
   // whole 32-blocks per split (the k placement starts at each split's start)
   const int kchunk = ((K + splits - 1) / splits + 31) / 32 * 32;
   splits = (K + kchunk - 1) / kchunk;
   grid.z = splits;
-  hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf,
-                     (int64_t)N, M, N, K, nullptr, 0, kchunk);
+  hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf, (int64_t)N,
+                     M, N, K, nullptr, 0, kchunk);
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)(((int64_t)M * N + kT - 1) / kT)),
                      dim3(kT), 0, s, split_buf, splits, M, N, C, ldc, bias, accumulate ? 1 : 0);
   return hipGetLastError();
