@@ -59,11 +59,19 @@ __device__ __forceinline__ float sigmoidf_(float z) {
 // AK1 / BK1: the operand is contiguous in k (sak = 1 / sbk = 1, rows 8-byte
 // aligned), so the four k values a lane needs per 16 come in one 8-byte load
 // instead of four 2-byte loads (the same values, the same sums).
-template <bool AK1, bool BK1>
+// EPI (no k split): the elementwise step that follows the product, fused
+// into its store, with the operations of the separate kernels it replaces:
+//   kEpiSilu      C as usual, and Ab = bf16(silu(C)) (same ld);
+//   kEpiSiluBack  the product is dA; C = dZ = dA silu'(Z) (Z the same
+//                 shape, rows >= valid_rows zero) and Ab = bf16(dZ).
+enum { kEpiNone = 0, kEpiSilu = 1, kEpiSiluBack = 2 };
+
+template <bool AK1, bool BK1, int EPI>
 __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     const unsigned short* __restrict__ A, int64_t sam, int64_t sak,
     const unsigned short* __restrict__ B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
-    int N, int K, const float* __restrict__ bias, int accumulate, int kchunk) {
+    int N, int K, const float* __restrict__ bias, int accumulate, int kchunk,
+    unsigned short* __restrict__ Ab, const float* __restrict__ Zin, int valid_rows) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = (blockIdx.y * 2 + (wave >> 1)) * 16;
   const int n0 = (blockIdx.x * 2 + (wave & 1)) * 16;
@@ -130,9 +138,22 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
     const int row = m0 + kq + i, col = n0 + r;
     float val = acc[i];
     if (bias) val += bias[col];
-    float* cp = C + (int64_t)row * ldc + col;
+    const int64_t at = (int64_t)row * ldc + col;
+    float* cp = C + at;
     if (accumulate) val += *cp;
-    *cp = val;
+    if constexpr (EPI == kEpiSiluBack) {
+      float gz = 0.f;
+      if (row < valid_rows) {
+        const float z = Zin[at];
+        const float sg = sigmoidf_(z);
+        gz = val * (sg * (1.f + z * (1.f - sg)));
+      }
+      *cp = gz;
+      Ab[at] = to_bf16(gz);
+    } else {
+      *cp = val;
+      if constexpr (EPI == kEpiSilu) Ab[at] = to_bf16(val * sigmoidf_(val));
+    }
   }
 }
 
@@ -170,29 +191,6 @@ __global__ void standardise_kernel(const float* __restrict__ X, int rows, int ro
   float v = 0.f;
   if (r < rows && c < cols) v = (X[(int64_t)r * cols + c] - mu[c]) * (1.0f / sd[c]);
   Xb[e] = to_bf16(v);
-}
-
-// A = bf16(silu(Z)) elementwise
-__global__ void silu_kernel(const float* __restrict__ Z, int64_t count, unsigned short* A) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  const float z = Z[e];
-  A[e] = to_bf16(z * sigmoidf_(z));
-}
-
-// dZ = dA * silu'(Z), FP32 and BF16 copies; rows >= rows_valid are zero
-__global__ void silu_back_kernel(const float* __restrict__ dA, const float* __restrict__ Z,
-                                 int64_t count, int64_t valid, float* dZ, unsigned short* dZb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= count) return;
-  float g = 0.f;
-  if (e < valid) {
-    const float z = Z[e];
-    const float s = sigmoidf_(z);
-    g = dA[e] * (s * (1.f + z * (1.f - s)));
-  }
-  dZ[e] = g;
-  dZb[e] = to_bf16(g);
 }
 
 // R = Y - (T - mu)/sd on the valid block [rows][cols] of Y [rows_pad][ld];
@@ -399,24 +397,43 @@ inline unsigned blocks_for(int64_t n, int t = kT) { return (unsigned)((n + t - 1
 // One GEMM; reductions long against the number of output tiles (weight
 // gradients over the batch rows) are split over k into partial tiles in
 // split_buf (split_cap floats) and summed by a second kernel in a fixed order.
+using GemmKernel = void (*)(const unsigned short*, int64_t, int64_t, const unsigned short*,
+                           int64_t, int64_t, float*, int64_t, int, int, int, const float*, int, int,
+                           unsigned short*, const float*, int);
+
+template <int EPI>
+GemmKernel gemm_kernel_for(bool ak1, bool bk1) {
+  return ak1 ? (bk1 ? gemm_bf16_kernel<true, true, EPI> : gemm_bf16_kernel<true, false, EPI>)
+             : (bk1 ? gemm_bf16_kernel<false, true, EPI> : gemm_bf16_kernel<false, false, EPI>);
+}
+
+// epi: the elementwise step fused into the store (gemm_bf16_kernel), with its
+// BF16 output Ab, and for kEpiSiluBack the pre-activations Zin and the valid
+// rows; an epilogue is only taken without a k split, bias or accumulation
+// of kEpiSiluBack
 hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak,
                 const unsigned short* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, int M,
                 int N, int K, const float* bias, bool accumulate, float* split_buf = nullptr,
-                size_t split_cap = 0) {
+                size_t split_cap = 0, int epi = kEpiNone, unsigned short* Ab = nullptr,
+                const float* Zin = nullptr, int valid_rows = 0) {
   dim3 grid((N + 31) / 32, (M + 31) / 32);
   // operands contiguous in k with 8-byte aligned rows take the vector loads
   const bool ak1 = sak == 1 && sam % 4 == 0 && ((uintptr_t)A & 7) == 0;
   const bool bk1 = sbk == 1 && sbn % 4 == 0 && ((uintptr_t)B & 7) == 0;
-  auto kern = ak1 ? (bk1 ? gemm_bf16_kernel<true, true> : gemm_bf16_kernel<true, false>)
-                  : (bk1 ? gemm_bf16_kernel<false, true> : gemm_bf16_kernel<false, false>);
   int splits = 1;
   if (split_buf && K >= 1024 && (int)(grid.x * grid.y) < 128) {
     splits = std::min(64, K / 256);
     while (splits > 1 && (size_t)splits * M * N > split_cap) splits /= 2;
   }
+  if (epi != kEpiNone &&
+      (splits > 1 || !Ab || (epi == kEpiSiluBack && (!Zin || bias || accumulate))))
+    return hipErrorInvalidValue;
+  const GemmKernel kern = epi == kEpiSilu       ? gemm_kernel_for<kEpiSilu>(ak1, bk1)
+                          : epi == kEpiSiluBack ? gemm_kernel_for<kEpiSiluBack>(ak1, bk1)
+                                                : gemm_kernel_for<kEpiNone>(ak1, bk1);
   if (splits <= 1) {
     hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K,
-                       bias, accumulate ? 1 : 0, K);
+                       bias, accumulate ? 1 : 0, K, Ab, Zin, valid_rows);
     return hipGetLastError();
   }
   // whole 32-blocks per split (the k placement starts at each split's start)
@@ -424,7 +441,7 @@ hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak
   splits = (K + kchunk - 1) / kchunk;
   grid.z = splits;
   hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf, (int64_t)N,
-                     M, N, K, nullptr, 0, kchunk);
+                     M, N, K, nullptr, 0, kchunk, nullptr, nullptr, 0);
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)(((int64_t)M * N + kT - 1) / kT)),
                      dim3(kT), 0, s, split_buf, splits, M, N, C, ldc, bias, accumulate ? 1 : 0);
   return hipGetLastError();
@@ -456,14 +473,12 @@ hipError_t forward(lsp_mlp* q, const float* X, int rows, int rows_pad, hipStream
   hipError_t e;
   // z1 = W1 x + b1: A(b, i) = Xb[b Ip + i], B(i, h) = W1[h Ip + i]
   if ((e = gemm(s, q->Xb, q->Ip, 1, W1, 1, q->Ip, q->Z1, H, rows_pad, H, q->Ip,
-                q->param + q->off_b1, false)))
+                q->param + q->off_b1, false, nullptr, 0, kEpiSilu, q->A1b)))
     return e;
-  hipLaunchKernelGGL(silu_kernel, dim3(blocks_for((int64_t)rows_pad * H)), dim3(kT), 0, s, q->Z1,
-                     (int64_t)rows_pad * H, q->A1b);
-  if ((e = gemm(s, q->A1b, H, 1, W2, 1, H, q->Z2, H, rows_pad, H, H, q->param + q->off_b2, false)))
+  // (a1 = bf16(silu(z1)) in the same launch)
+  if ((e = gemm(s, q->A1b, H, 1, W2, 1, H, q->Z2, H, rows_pad, H, H, q->param + q->off_b2, false,
+                nullptr, 0, kEpiSilu, q->A2b)))
     return e;
-  hipLaunchKernelGGL(silu_kernel, dim3(blocks_for((int64_t)rows_pad * H)), dim3(kT), 0, s, q->Z2,
-                     (int64_t)rows_pad * H, q->A2b);
   if ((e = gemm(s, q->A2b, H, 1, W3, 1, H, q->Y, q->Op, rows_pad, q->Op, H, q->param + q->off_b3,
                 false)))
     return e;
@@ -490,26 +505,27 @@ hipError_t backward(lsp_mlp* q, const float* T, int rows, int rows_pad, int* nbl
                 false, q->gsplit, q->gsplit_cap)))
     return e;
   if ((e = colsum(s, q->dY, rows_pad, q->Op, q->Op, q->colpart, g + q->off_b3))) return e;
-  // dA2 = dY W3: A(b, o) = dYb[b Op + o], B(o, h) = W3[o H + h]
-  if ((e = gemm(s, q->dYb, q->Op, 1, W3, H, 1, q->dA, H, rows_pad, H, q->Op, nullptr, false)))
+  // dA2 = dY W3: A(b, o) = dYb[b Op + o], B(o, h) = W3[o H + h]; the same
+  // launch stores dZ2 = dA2 silu'(Z2) (FP32 in dZ, BF16 in dZb)
+  if ((e = gemm(s, q->dYb, q->Op, 1, W3, H, 1, q->dZ, H, rows_pad, H, q->Op, nullptr, false,
+                nullptr, 0, kEpiSiluBack, q->dZb, q->Z2, rows)))
     return e;
-  const int64_t cnt = (int64_t)rows_pad * H, valid = (int64_t)rows * H;
-  hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z2, cnt,
-                     valid, q->dZ, q->dZb);
   // gW2 [H][H] = dZ2^T A1
   if ((e = gemm(s, q->dZb, 1, H, q->A1b, H, 1, g + q->off_W2, H, H, H, rows_pad, nullptr, false,
                 q->gsplit, q->gsplit_cap)))
     return e;
   if ((e = colsum(s, q->dZ, rows_pad, H, H, q->colpart, g + q->off_b2))) return e;
-  // dA1 = dZ2 W2: B(h2, h1) = W2[h2 H + h1]
-  if ((e = gemm(s, q->dZb, H, 1, W2, H, 1, q->dA, H, rows_pad, H, H, nullptr, false))) return e;
-  hipLaunchKernelGGL(silu_back_kernel, dim3(blocks_for(cnt)), dim3(kT), 0, s, q->dA, q->Z1, cnt,
-                     valid, q->dZ, q->dZb);
+  // dA1 = dZ2 W2: B(h2, h1) = W2[h2 H + h1]; the same launch stores
+  // dZ1 = dA1 silu'(Z1), FP32 in dA and BF16 in A1b (a1 is not read again;
+  // dZb is this product's operand)
+  if ((e = gemm(s, q->dZb, H, 1, W2, H, 1, q->dA, H, rows_pad, H, H, nullptr, false, nullptr, 0,
+                kEpiSiluBack, q->A1b, q->Z1, rows)))
+    return e;
   // gW1 [H][Ip] = dZ1^T Xb
-  if ((e = gemm(s, q->dZb, 1, H, q->Xb, q->Ip, 1, g + q->off_W1, q->Ip, H, q->Ip, rows_pad,
+  if ((e = gemm(s, q->A1b, 1, H, q->Xb, q->Ip, 1, g + q->off_W1, q->Ip, H, q->Ip, rows_pad,
                 nullptr, false, q->gsplit, q->gsplit_cap)))
     return e;
-  if ((e = colsum(s, q->dZ, rows_pad, H, H, q->colpart, g + q->off_b1))) return e;
+  if ((e = colsum(s, q->dA, rows_pad, H, H, q->colpart, g + q->off_b1))) return e;
   return hipGetLastError();
 }
 
