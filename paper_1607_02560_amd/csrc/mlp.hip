@@ -157,6 +157,66 @@ __global__ __launch_bounds__(kT) void gemm_bf16_kernel(
   }
 }
 
+// The same product for operands that are strided in k and contiguous in m
+// and n (sam = 1, sbn = 1: the weight gradients, which reduce over the batch
+// rows): per 32 values of k the block copies its 32 x 32 tiles of A and B
+// into LDS with 16-byte loads (8 values of m or n for one k per thread) and
+// stores them transposed, so that every lane reads its MFMA operands as two
+// 8-byte LDS reads; k beyond the block's range is read as zero, so a last 16
+// of k takes the 32-wide product too. Rows or columns past M or N load zeros
+// and are not stored. Output as gemm_bf16_kernel (split in k: raw partials).
+constexpr int kLdsK = 32 + 8;  // LDS row of one m (or n): 32 values of k, padded
+
+__global__ __launch_bounds__(kT) void gemm_bf16_kt_kernel(
+    const unsigned short* __restrict__ A, int64_t sak, const unsigned short* __restrict__ B,
+    int64_t sbk, float* C, int64_t ldc, int M, int N, int K, int kchunk) {
+  __shared__ __align__(16) unsigned short sA[32 * kLdsK];
+  __shared__ __align__(16) unsigned short sB[32 * kLdsK];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int mb = blockIdx.y * 32, nb = blockIdx.x * 32;
+  const int r = lane & 15, kq = (lane >> 4) * 4;
+  const int mw = (wave >> 1) * 16, nw = (wave & 1) * 16;  // the wave's tile in the block
+  const int kb = blockIdx.z * kchunk;
+  const int ke = min(K, kb + kchunk);
+  if (gridDim.z > 1) C += (int64_t)blockIdx.z * M * ldc;
+  // copy roles: threads 0..127 take A, 128..255 take B; one k and 8 of m (n)
+  const bool isA = tid < 128;
+  const int t = tid & 127;
+  const int kk = t >> 2, seg = (t & 3) * 8;
+  const int lim = isA ? M - mb : N - nb;
+  const unsigned short* src = isA ? A + mb + seg : B + nb + seg;
+  const int64_t sk = isA ? sak : sbk;
+  unsigned short* dst = (isA ? sA : sB) + seg * kLdsK + kk;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (k0 + kk < ke && seg < lim) v = *reinterpret_cast<const uint4*>(src + (int64_t)(k0 + kk) * sk);
+    const unsigned int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dst[(2 * j) * kLdsK] = (unsigned short)(w[j] & 0xffffu);
+      dst[(2 * j + 1) * kLdsK] = (unsigned short)(w[j] >> 16);
+    }
+    __syncthreads();
+    const unsigned short* pa = sA + (mw + r) * kLdsK + kq;
+    const unsigned short* pb = sB + (nw + r) * kLdsK + kq;
+    const uint2 a0 = *reinterpret_cast<const uint2*>(pa), a1 = *reinterpret_cast<const uint2*>(pa + 16);
+    const uint2 b0 = *reinterpret_cast<const uint2*>(pb), b1 = *reinterpret_cast<const uint2*>(pb + 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        __builtin_bit_cast(bf16x8, make_uint4(a0.x, a0.y, a1.x, a1.y)),
+        __builtin_bit_cast(bf16x8, make_uint4(b0.x, b0.y, b1.x, b1.y)), acc, 0, 0, 0);
+    __syncthreads();
+  }
+  const int col = nb + nw + r;
+  if (col >= N) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = mb + mw + kq + i;
+    if (row < M) C[(int64_t)row * ldc + col] = acc[i];
+  }
+}
+
 // C[m][n] = sum over z of part[z][m][n] (fixed order) (+ bias[n]) (+ C[m][n])
 __global__ void split_reduce_kernel(const float* __restrict__ part, int splits, int M, int N,
                                     float* C, int64_t ldc, const float* __restrict__ bias,
@@ -428,20 +488,33 @@ hipError_t gemm(hipStream_t s, const unsigned short* A, int64_t sam, int64_t sak
   if (epi != kEpiNone &&
       (splits > 1 || !Ab || (epi == kEpiSiluBack && (!Zin || bias || accumulate))))
     return hipErrorInvalidValue;
+  // both operands strided in k, contiguous in m and n, 16-byte aligned rows:
+  // the LDS-transposing kernel (no bias, no accumulation, no epilogue)
+  const bool kt = !ak1 && !bk1 && sam == 1 && sbn == 1 && sak % 8 == 0 && sbk % 8 == 0 &&
+                  ((uintptr_t)A & 15) == 0 && ((uintptr_t)B & 15) == 0 && !bias && !accumulate &&
+                  epi == kEpiNone;
   const GemmKernel kern = epi == kEpiSilu       ? gemm_kernel_for<kEpiSilu>(ak1, bk1)
                           : epi == kEpiSiluBack ? gemm_kernel_for<kEpiSiluBack>(ak1, bk1)
                                                 : gemm_kernel_for<kEpiNone>(ak1, bk1);
   if (splits <= 1) {
-    hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K,
-                       bias, accumulate ? 1 : 0, K, Ab, Zin, valid_rows);
+    if (kt)
+      hipLaunchKernelGGL(gemm_bf16_kt_kernel, grid, dim3(kT), 0, s, A, sak, B, sbk, C, ldc, M, N,
+                         K, K);
+    else
+      hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K,
+                         bias, accumulate ? 1 : 0, K, Ab, Zin, valid_rows);
     return hipGetLastError();
   }
   // whole 32-blocks per split (the k placement starts at each split's start)
   const int kchunk = ((K + splits - 1) / splits + 31) / 32 * 32;
   splits = (K + kchunk - 1) / kchunk;
   grid.z = splits;
-  hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf, (int64_t)N,
-                     M, N, K, nullptr, 0, kchunk, nullptr, nullptr, 0);
+  if (kt)
+    hipLaunchKernelGGL(gemm_bf16_kt_kernel, grid, dim3(kT), 0, s, A, sak, B, sbk, split_buf,
+                       (int64_t)N, M, N, K, kchunk);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(kT), 0, s, A, sam, sak, B, sbk, sbn, split_buf,
+                       (int64_t)N, M, N, K, nullptr, 0, kchunk, nullptr, nullptr, 0);
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)(((int64_t)M * N + kT - 1) / kT)),
                      dim3(kT), 0, s, split_buf, splits, M, N, C, ldc, bias, accumulate ? 1 : 0);
   return hipGetLastError();
