@@ -450,8 +450,9 @@ __global__ __launch_bounds__(kThreads) void green_batched_kernel(const lsp::Batc
 // the diagonal pair ot = q is summed over its full square with halved
 // cosine weights, the summand being symmetric in (k_1, k_2)) and, where the
 // row ends, folds them into its pair sums. Where its range leaves a shift (or
-// ends) the wave sums the pair sums over its lanes (through LDS, in a fixed
-// order) and writes them as the partial of (wave w, shift s), at slot w + s.
+// ends) the wave sums the pair sums over its lanes (recursive halving with
+// DPP lane moves, a fixed order) and writes them as the partial of (wave w,
+// shift s), at slot w + s.
 // Slots of one shift are consecutive in w, and slot w + s is unique, since
 // each step along the ranges advances w or s. The cosine values and 4 pi^2 k_2^2 of
 // a step are wave-uniform (scalar loads). The Nyquist column k_2 = n/2 is one
@@ -550,6 +551,11 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
       const int rstop = min(send, si * SPS + (base + T - ot) * KT);
       const int k1 = ot * KT + (valid ? lane : 0);
       const double lbase = fma(lsp::kFourPi2, (double)(k1 * k1), s);
+      // the lane's cosine row for the fold, loaded before the row's terms so
+      // that its latency overlaps them
+      double ck[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) ck[j] = valid ? cw[k1 * W + j] : 0.0;
       double tg[W], tq[W];
 #pragma unroll
       for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
@@ -578,9 +584,6 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
         }
         g = ustop;
       }
-      double ck[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j) ck[j] = valid ? cw[k1 * W + j] : 0.0;
       int pi = 0;
 #pragma unroll
       for (int da = 0; da < W; ++da) {
@@ -665,15 +668,27 @@ void build_units(int n, std::vector<int>& units) {
   }
 }
 
+// LDS reserved (never accessed) per 2D block so that the blocks spread evenly
+// over the CUs. The blocks are uniform and all resident at once, so the time
+// is set by the most loaded SIMD. Their VGPRs let three blocks share a CU;
+// where two per CU are wanted (CUs < blocks <= 2 CUs), a total of 64 KB of
+// LDS per block (of a CU's 160 KB) lets no CU take a third.
+size_t green2d_residency_lds(int blocks, int cus) {
+  if (cus <= 0 || blocks <= cus || blocks > 2 * cus) return 0;
+  return 64 * 1024 - sizeof(ShiftShared);
+}
+
 template <int D, int W>
 hipError_t run_green(const lsp_problem* p, int num_shifts, bool global) {
   if constexpr (D == 2) {
     const int nwv = lsp::green2d_waves(p->n, num_shifts, p->tune[LSP_TUNE_GREEN_WAVES]);
     const size_t need = (size_t)(nwv + num_shifts) * GreenLayout<2, W>::NV;
     if (need > p->ws.green_part_cap) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((green2d_kernel<W>), dim3(nwv / kWaves), dim3(kThreads), 0,
-                       p->stream, nwv, p->ws.minmax_part, p->N, num_shifts, (int)global,
-                       p->cosT, p->n, p->ws.green_part, p->ws.S, p->ws.nS, p->ws.vrange);
+    const int blocks = nwv / kWaves;
+    hipLaunchKernelGGL((green2d_kernel<W>), dim3(blocks), dim3(kThreads),
+                       green2d_residency_lds(blocks, p->cus), p->stream, nwv, p->ws.minmax_part,
+                       p->N, num_shifts, (int)global, p->cosT, p->n, p->ws.green_part, p->ws.S,
+                       p->ws.nS, p->ws.vrange);
   } else {
     const int nunits = p->green_nunits;
     const size_t need = (size_t)num_shifts * nunits * GreenLayout<D, W>::NV;

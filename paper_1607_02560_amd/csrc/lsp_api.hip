@@ -331,6 +331,8 @@ int lsp_create(int d, int n, const double* v_dev, void* stream, lsp_problem** ou
   p->use_graphs = lsp::graphs_enabled(false);
   p->krylov_graphs = lsp::graphs_enabled(true);
   (void)hipGetDevice(&p->device);
+  if (hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess)
+    p->cus = 0;
   int rc = LSP_OK;
   if ((rc = dalloc((void**)&p->v, sizeof(double) * p->N, "potential")) ||
       (rc = dalloc((void**)&p->z, sizeof(double) * 2 * p->N, "apply scratch")) ||

@@ -123,6 +123,7 @@ struct lsp_problem {
   int64_t N = 0;
   hipStream_t stream = nullptr;
   int device = 0;
+  int cus = 0;                // compute units of the device
   double* v = nullptr;        // [N] potential
   double* tw = nullptr;       // [2n] exp(-2 pi i j / n), interleaved
   double* cosT = nullptr;     // [cos_table_doubles(n, 2t+1)] folded cosine weights of the current t
