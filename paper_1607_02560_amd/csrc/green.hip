@@ -531,8 +531,12 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
 #pragma unroll
   for (int j = 0; j < W; ++j) cn[j] = cw[nyq * W + j];
   const bool valid = lane < KT;
-  while (g < gend) {
-    const int si = g / SPS;
+  // KT is a power of two (n is): the step's pair and position within it by
+  // shifts; the shift index advances with g (each range after the first
+  // starts at a shift boundary)
+  const int kts = __builtin_ctz(KT);
+  int si = g / SPS;
+  for (; g < gend; ++si) {
     const int send = min(gend, (si + 1) * SPS);
     const double s = S[si];
     double a[P2];
@@ -542,7 +546,7 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
     while (g < send) {
       // the row of tile pairs (ot, q >= ot) holding step g
       const int rem = g - si * SPS;
-      const int u = rem / KT;
+      const int u = rem >> kts;
       int ot = 0, base = 0;
       while (u >= base + (T - ot)) {
         base += T - ot;
@@ -561,8 +565,8 @@ __device__ __forceinline__ void green2d_body(int wave, int nwv, const double* __
       for (int j = 0; j < W; ++j) tg[j] = tq[j] = 0.0;
       while (g < rstop) {
         const int rr = g - si * SPS;
-        const int uu = rr / KT;
-        const int kk = rr - uu * KT;
+        const int uu = rr >> kts;
+        const int kk = rr & (KT - 1);
         const int q = ot + (uu - base);
         const int ustop = min(rstop, g - kk + KT);
         const double* tab = (q == ot) ? cwh : cw;
