@@ -135,10 +135,49 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
   double mrow[B];
 #pragma unroll
   for (int qc = 0; qc < B; ++qc) mrow[qc] = 0.0;
+  if constexpr (kLean) {
+    // 3D with t = 2: row r of G_b comes from LDS, one broadcast read per
+    // entry (all lanes read the same address), in place of a lane-r
+    // broadcast through a scalar register per entry: the same operands in
+    // the same order. The class's block of the partial-sum staging area
+    // (free while the classes run) holds it. Columns go in chunks of KC
+    // with a rolled loop over r inside (the lane's own G[p][r] read back
+    // from LDS too): fully unrolled, the B*B reads are hoisted and spill.
+    static_assert(Pa::offset(Pa::NC) <= (int)(sizeof(sh.stage) / sizeof(double)),
+                  "the G blocks fit the staging area");
+    double* gb = sh.stage + Pa::offset(C);
+    if (lane < B) {
+      // the A1 and G blocks go out here (below for the other shapes), so
+      // that G's row need not stay live across the product
+      double* ao = Mtab_si + Pa::offset(Pa::NC) + Pa::offset(C) + lane * B;
+      double* go = Mtab_si + 2 * Pa::offset(Pa::NC) + Pa::offset(C) + lane * B;
 #pragma unroll
-  for (int r = 0; r < B; ++r) {
+      for (int qc = 0; qc < B; ++qc) {
+        gb[lane * B + qc] = grow[qc];
+        ao[qc] = arow[qc];
+        go[qc] = grow[qc];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr int KC = 9;
 #pragma unroll
-    for (int qc = 0; qc < B; ++qc) mrow[qc] = fma(grow[r], bcast(grow[qc], r), mrow[qc]);
+    for (int c0 = 0; c0 < B; c0 += KC) {
+#pragma unroll 1
+      for (int r = 0; r < B; ++r) {
+        const double gpr = gb[p * B + r];
+#pragma unroll
+        for (int qc = c0; qc < ((c0 + KC < B) ? c0 + KC : B); ++qc)
+          mrow[qc] = fma(gpr, gb[r * B + qc], mrow[qc]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+#pragma unroll
+      for (int qc = 0; qc < B; ++qc) mrow[qc] = fma(grow[r], bcast(grow[qc], r), mrow[qc]);
+    }
   }
 #pragma unroll
   for (int qc = 0; qc < B; ++qc) mrow[qc] = arow[qc] - mrow[qc];
@@ -151,8 +190,10 @@ __device__ void solve_class(NullShared<D, W>& sh, int lane, int si, double* Mtab
 #pragma unroll
     for (int qc = 0; qc < B; ++qc) {
       mo[qc] = mrow[qc];
-      ao[qc] = arow[qc];
-      go[qc] = grow[qc];
+      if constexpr (!kLean) {
+        ao[qc] = arow[qc];
+        go[qc] = grow[qc];
+      }
     }
   }
 
