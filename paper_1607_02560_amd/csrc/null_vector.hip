@@ -575,12 +575,16 @@ __device__ __forceinline__ void null_body(
     case 2: solve_class<D, W, 2>(sh, lane, si, Mtab_si); break;
     case 3: solve_class<D, W, 3>(sh, lane, si, Mtab_si); break;
     default:
+      // waves w and w + 4 share a SIMD. Class sizes by index are 27, 18,
+      // 18, 12, 18, 12, 12, 8 for t = 2 (8, 4, 4, 2, 4, 2, 2, 1 for t = 1):
+      // waves 4-7 take classes 7-4, so the largest class shares its SIMD
+      // with the smallest instead of an 18-row one
       if constexpr (D == 3) {
         switch (wid) {
-          case 4: solve_class<D, W, 4>(sh, lane, si, Mtab_si); break;
-          case 5: solve_class<D, W, 5>(sh, lane, si, Mtab_si); break;
-          case 6: solve_class<D, W, 6>(sh, lane, si, Mtab_si); break;
-          case 7: solve_class<D, W, 7>(sh, lane, si, Mtab_si); break;
+          case 4: solve_class<D, W, 7>(sh, lane, si, Mtab_si); break;
+          case 5: solve_class<D, W, 6>(sh, lane, si, Mtab_si); break;
+          case 6: solve_class<D, W, 5>(sh, lane, si, Mtab_si); break;
+          case 7: solve_class<D, W, 4>(sh, lane, si, Mtab_si); break;
         }
       }
       break;
