@@ -348,6 +348,17 @@ def cpu_baseline(p):
         # that no process outlives the benchmark
         pool.close()
         pool.join()
+    # the spawn context also started multiprocessing's resource-tracker
+    # process, which otherwise lives until this interpreter exits: release the
+    # pool's semaphores first (collecting the pool unregisters them), then stop
+    # the tracker and wait for it
+    import gc
+    from multiprocessing import resource_tracker
+    del pool
+    gc.collect()
+    tracker = getattr(resource_tracker, "_resource_tracker", None)
+    if tracker is not None and hasattr(tracker, "_stop"):
+        tracker._stop()
     out["all_cores"] = {
         "cores": workers, "value": p.N / t_setup_all, "unit": "stencils/s",
         "setup_s": t_setup_all, "ps_apply_s_per_apply": t_apply_all,
