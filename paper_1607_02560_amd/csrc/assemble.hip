@@ -89,16 +89,17 @@ __device__ __forceinline__ void assemble_body(
   __syncthreads();
 
   // VEC entries per 16-byte store: 2 doubles or 4 floats (TW is a multiple of 4).
-  // The TR = 1 row span of TW * M entries is written in steps of STEP entries
+  // The span of TR * TW * M entries (TR > 1 only with TW = n, so that the
+  // tile's rows follow each other in P) is written in steps of STEP entries
   // by the first TACT = 256 - 256 % M threads, so that a step is a whole
   // number DP of points: thread k's store always covers the same VEC offsets
   // (entries VEC k .. VEC k + VEC - 1 of a step, possibly reaching into the
   // next point), and their offsets, halo positions and point increments are
   // worked out once. Per entry the loop then reads the point's shift (row
   // base and value, both in LDS), one alpha/C pair and one halo value.
-  static_assert(TR == 1, "single-row tiles");
+  static_assert(TR == 1 || D == 3, "multi-row tiles: 3D rows of n points");
   constexpr int VEC = 16 / (int)sizeof(PT);
-  constexpr int SPAN = TW * M;
+  constexpr int SPAN = TR * TW * M;
   constexpr int TACT = 256 - 256 % M;
   constexpr int STEP = VEC * TACT;
   constexpr int DP = STEP / M;
@@ -124,7 +125,9 @@ __device__ __forceinline__ void assemble_body(
       const int q = pp + pinc[h];
       const double s = spS[q];
       const double2 ac = actab[spM[q] + aoff[h]];
-      const double va = halo[pp + hoff[h]];
+      // point q sits in halo row q / TW (TW is a power of two), whose start
+      // is 2t further on per row than in a single-row tile
+      const double va = halo[pp + hoff[h] + (TR > 1 ? (q / TW) * (2 * t) : 0)];
       outv[h] = ac.x + ac.y * (va - s);
     }
     if constexpr (VEC == 2) {
@@ -484,6 +487,9 @@ hipError_t run_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
     if (fp32 && p->n >= 512 && lds_ok) return run_assemble_lds<W, 4, 128>(p, P, fp32, idx);
     return run_assemble_tile<D, W, 128, 1>(p, P, fp32, idx);
   } else {
+    // t = 1 at n = 64: tiles of two whole rows (128 points; 3D n = 64 setup
+    // 35.7 -> 34.5 us; with t = 2 the same time either way)
+    if (W == 3 && p->n == 64) return run_assemble_tile<D, W, 64, 2>(p, P, fp32, idx);
     return run_assemble_tile<D, W, 64, 1>(p, P, fp32, idx);
   }
 }
