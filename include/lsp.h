@@ -529,7 +529,7 @@ int lsp_batch_ps_apply(lsp_batch* b, const double* const* u_dev, double* const* 
 
 /* The assembly tile width the tuner chose (0 before the first setup), and
  * optionally the four candidate widths (0 = not a candidate) and their mean
- * times in ms (arrays of 4). Width 1 is the 2D form with tiles of 4 rows x 64
+ * times in ms (arrays of 4). Width 1 is the 2D form with tiles of 8 rows x 64
  * points and the shift tables copied into LDS (a candidate when every n is a
  * multiple of 64 and |S| m <= 1024 for every problem; the smallest width
  * gives way to it when four widths divide every n). */

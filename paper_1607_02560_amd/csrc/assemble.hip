@@ -529,14 +529,14 @@ hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx) {
 hipError_t launch_assemble_batched(int d, int t, int tw, bool fp32, const BatchRec* recs,
                                    const int4* map, int blocks, hipStream_t s) {
   const int W = 2 * t + 1;
-  // tw = kBatchLdsTile: 4 x 64 tiles with the shift tables in LDS (2D)
+  // tw = kBatchLdsTile: 8 x 64 tiles with the shift tables in LDS (2D)
 #define LSP_ASM_LDS_B(W_)                                                                    \
   if (d == 2 && W == W_ && tw == kBatchLdsTile) {                                            \
     if (fp32)                                                                                \
-      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 4, 64, float>), dim3(blocks),      \
+      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 8, 64, float>), dim3(blocks),      \
                          dim3(256), 0, s, recs, map);                                        \
     else                                                                                     \
-      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 4, 64, double>), dim3(blocks),     \
+      hipLaunchKernelGGL((assemble_lds_batched_kernel<W_, 8, 64, double>), dim3(blocks),     \
                          dim3(256), 0, s, recs, map);                                        \
     return hipGetLastError();                                                                \
   }

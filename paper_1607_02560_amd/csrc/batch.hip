@@ -11,7 +11,7 @@
 // entry point (C-apply, GMRES, table export) works on them afterwards.
 //
 // The assembly tile width is chosen per batch by timing the candidate widths
-// that divide every n of the batch, and in 2D the LDS-table form (4 x 64
+// that divide every n of the batch, and in 2D the LDS-table form (8 x 64
 // tiles, the shift tables copied into LDS; "width" 1) where every problem's
 // tables fit (the first setup of a batch, and again whenever its sizes or
 // shift counts change).
@@ -132,8 +132,8 @@ void build_maps(const lsp_batch* b, const std::vector<int>& nreq, int tw,
     }
     for (int si = 0; si < nreq[i]; ++si) null.push_back(make_int4(i, si, 0, 0));
     if (tw == lsp::kBatchLdsTile) {
-      // 2D tiles of 4 rows x 64 points (the LDS-table form)
-      for (int by = 0; by < p->n / 4; ++by)
+      // 2D tiles of 8 rows x 64 points (the LDS-table form)
+      for (int by = 0; by < p->n / 8; ++by)
         for (int bx = 0; bx < p->n / 64; ++bx) asmb.push_back(make_int4(i, bx, by, 0));
       continue;
     }
@@ -319,7 +319,7 @@ int lsp_batch_stencil_setup(lsp_batch* b, int t, const int* num_shifts, int prec
   }
   hipError_t e = hipSuccess;
   const int64_t m_rows = (int64_t)(2 * t + 1) * (2 * t + 1);
-  // the LDS-table form (2D, 4 x 64 tiles) where every problem's shift tables fit
+  // the LDS-table form (2D, 8 x 64 tiles) where every problem's shift tables fit
   bool lds_ok = b->d == 2;
   for (int i = 0; i < count; ++i)
     lds_ok = lds_ok && b->probs[i]->n % 64 == 0 && (int64_t)nreq[i] * m_rows <= lsp::kBatchActLds;

@@ -22,7 +22,7 @@ constexpr int kMaxShifts = 1024;    // requested |S|
 constexpr int kMinMaxBlocks = 256;  // blocks (= partials) of the min/max reduction
 constexpr int kActLds = 2048;       // (alpha, C) pairs the LDS-table assembly stages (32 KB)
 constexpr int kBatchLdsTile = 1;    // batched assembly "tile width" of the LDS-table form
-                                    // (4 rows x 64 points, 2D, nS m <= kBatchActLds)
+                                    // (8 rows x 64 points, 2D, nS m <= kBatchActLds)
 constexpr int kBatchActLds = 1024;  // its table capacity in pairs (16 KB: more blocks per CU)
 
 struct Workspace {
