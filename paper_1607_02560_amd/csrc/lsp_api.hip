@@ -674,7 +674,8 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
   if (rc) return rc;
   const int d = p->d;
   const size_t m1 = (d == 2) ? 9 : 27;
-  const size_t per = sizeof(double) * (2 * m1 + m1 * m1 + 2 * m1 + 2) + sizeof(double2) * m1 +
+  const size_t m2 = (d == 2) ? 25 : 125;  // the (alpha, C) pairs in the radius-2 layout
+  const size_t per = sizeof(double) * (2 * m1 + m1 * m1 + 2 * m1 + 2) + sizeof(double2) * m2 +
                      sizeof(int);
   const size_t bytes = per * (size_t)ns + 16 * 256;
   if (p->nd_t1_bytes < bytes) {
@@ -702,7 +703,7 @@ int lsp_stencil_setup_nd(lsp_problem* p, int leaf, int num_shifts, double* P_dev
     t1.C = reinterpret_cast<double*>(take(sizeof(double) * S * m1));
     t1.sigma = reinterpret_cast<double*>(take(sizeof(double) * S));
     t1.rho = reinterpret_cast<double*>(take(sizeof(double) * S));
-    t1.actab = reinterpret_cast<double2*>(take(sizeof(double2) * S * m1));
+    t1.actab = reinterpret_cast<double2*>(take(sizeof(double2) * S * m2));
     t1.status = reinterpret_cast<int*>(take(sizeof(int) * S));
     p->nd1_shifts = ns;
   }

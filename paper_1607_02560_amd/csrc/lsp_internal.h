@@ -85,7 +85,7 @@ struct BatchRec {
 // the radius-2 Green's pass
 struct NdTables1 {
   double *gtab, *gamtab, *Mtab, *alpha, *C, *sigma, *rho;
-  double2* actab;
+  double2* actab;  // [nS][5^d] (alpha, C) pairs in the radius-2 layout, (0, 0) outside mu_0^1
   int* status;
 };
 
@@ -221,8 +221,8 @@ hipError_t launch_minmax(lsp_problem* p, bool global = false);
 hipError_t launch_cos_table(int n, int W, double* cw, hipStream_t s);
 __host__ __device__ inline int cos_table_doubles(int n, int W) { return (n / 2 + 1) * (2 * W + 1); }
 // rows of per-point radius (Sec. 4.2, leaf box `leaf`, radius <= 2) from the
-// radius-1 tables act1 and the radius-2 tables of the workspace; writes P,
-// idx and the per-point C rows (p->c_rows, [N][5^d])
+// radius-1 (alpha, C) pairs act1 (in the radius-2 layout, (0, 0) outside
+// mu_0^1) and the radius-2 pairs of the workspace; writes P and idx
 hipError_t launch_assemble_nd(lsp_problem* p, const double2* act1, int leaf, double* P,
                               int32_t* idx);
 // Green's sums (num_shifts = requested |S|); every block of the launch forms
@@ -245,7 +245,8 @@ int expand_gram_host(int d, int t, const double* packed, double* full);
 // also clears *clear_counter (a kernel store, not a memset) when it is non-null
 hipError_t launch_null_vectors(lsp_problem* p, int num_shifts, int* clear_counter = nullptr);
 // one launch: the radius-2 tables into the workspace and the radius-1 tables
-// into t1, both from the radius-2 Green's partial sums (p->t must be 2)
+// into t1 (its (alpha, C) pairs in the radius-2 layout), both from the
+// radius-2 Green's partial sums (p->t must be 2)
 hipError_t launch_null_nd(lsp_problem* p, int num_shifts, const NdTables1& t1);
 // P: float64 rows, or float32 rows when fp32
 hipError_t launch_assemble(lsp_problem* p, void* P, bool fp32, int32_t* idx);

@@ -22,11 +22,13 @@ using lsp::Pow;
 
 // A block owns TW consecutive points of one grid row (as the uniform
 // assembly tiles): the potential on the row segment plus a halo of 2 in
-// every direction, the shift list and per point its shift and radius are
-// staged in LDS. The tile's rows form one span of TW * 5^d entries, written
-// in steps of a whole number of points by the first TACT = 256 - 256 % M2
-// threads; each thread's VEC = 2 entries per step keep their offsets, so
-// the offset-dependent parts (radius-1 position, inner flag, halo position,
+// every direction, the shift list and per point its shift and its row of
+// the (alpha, C) table of its radius are staged in LDS (the radius-1 pairs
+// are stored in the radius-2 layout, (0, 0) outside mu_0^1, so both radii
+// read one layout). The tile's rows form one span of TW * 5^d entries,
+// written in steps of a whole number of points by the first TACT = 256 -
+// 256 % M2 threads; each thread's VEC = 2 entries per step keep their
+// offsets, so the offset-dependent parts (table position, halo position,
 // point increment) are worked out once. P is written with 16-byte stores;
 // the C-apply reads C from the tables of the point's radius (no C rows are
 // stored).
@@ -39,15 +41,13 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
   constexpr int W2 = 5;
   constexpr int t = 2;
   constexpr int M2 = Pow<D, 5>::v;
-  constexpr int M1 = Pow<D, 3>::v;
   constexpr int PL = (D == 3) ? W2 : 1;
   constexpr int HR = 1 + 2 * t;
   constexpr int HC = TW + 2 * t;
   __shared__ double halo[PL * HR * HC];
   __shared__ double sS[lsp::kMaxShifts];
-  __shared__ double spS[TW];   // per point: s_j
-  __shared__ int spA[TW];      // per point: the row base of its table (M2 id or M1 id)
-  __shared__ int spT[TW];      // per point: t_j
+  __shared__ double spS[TW];            // per point: s_j
+  __shared__ const double2* spP[TW];    // per point: its (alpha, C) row (radius t_j)
   const int tid = threadIdx.x;
   const int nS = *nS_ptr;
   const int c0 = blockIdx.x * TW;
@@ -86,8 +86,7 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
     }
     const int tj = nd_radius<D>(cp, b, 2);
     spS[pt] = sS[id];
-    spT[pt] = tj;
-    spA[pt] = (tj >= 2) ? id * M2 : id * M1;
+    spP[pt] = ((tj >= 2) ? act2 : act1) + (int64_t)id * M2;
     if (idx_out) idx_out[pbase + pt] = id;
   }
   __syncthreads();
@@ -101,29 +100,20 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
   if (tid >= TACT) return;
   const int e0 = VEC * tid;
   const int pt0 = e0 / M2;
-  int a2[VEC], a1[VEC], hoff[VEC], pinc[VEC];
-  bool inner[VEC];
+  int a2[VEC], hoff[VEC], pinc[VEC];
 #pragma unroll
   for (int h = 0; h < VEC; ++h) {
     const int e = e0 + h;
     pinc[h] = e / M2 - pt0;
     const int a = e % M2;
     a2[h] = a;
-    // offsets of a (last axis fastest), its radius-1 index and halo position
-    int rem = a, i1 = 0, mul = 1, ho = 0, hm = 1;
-    bool in = true;
+    int rem = a, ho = 0, hm = 1;
 #pragma unroll
     for (int i = D - 1; i >= 0; --i) {
-      const int o = rem % W2;  // o - 2 in [-2, 2]
+      ho += (rem % W2) * hm;
       rem /= W2;
-      in = in && o >= 1 && o <= 3;
-      i1 += (o - 1) * mul;
-      mul *= 3;
-      ho += o * hm;
       hm *= (i == D - 1) ? HC : HR;
     }
-    inner[h] = in;
-    a1[h] = in ? i1 : 0;
     hoff[h] = ho + pinc[h];  // halo index = point + hoff
   }
   const int64_t rowbase = pbase * M2;
@@ -132,14 +122,12 @@ __global__ __launch_bounds__(256) void assemble_nd_kernel(
     double pv[VEC];
 #pragma unroll
     for (int h = 0; h < VEC; ++h) {
+      // both radii in the radius-2 layout; a radius-1 row's entries outside
+      // its window are (0, 0), giving 0 + 0 * (v - s) = +0
       const int q = pp + pinc[h];
-      const int tj = spT[q];
-      pv[h] = 0.0;
-      if (tj >= 2 || inner[h]) {
-        const double2 ac = (tj >= 2) ? act2[spA[q] + a2[h]] : act1[spA[q] + a1[h]];
-        const double va = halo[pp + hoff[h]];
-        pv[h] = ac.x + ac.y * (va - spS[q]);
-      }
+      const double2 ac = spP[q][a2[h]];
+      const double va = halo[pp + hoff[h]];
+      pv[h] = ac.x + ac.y * (va - spS[q]);
     }
     reinterpret_cast<double2*>(P + rowbase)[e >> 1] = make_double2(pv[0], pv[1]);
   }

@@ -474,8 +474,10 @@ __device__ __forceinline__ void partial_range(int si, int nS, int nblk, int sps,
 
 // WP: the window 2 WP - 1 of the Green's partial sums read (WP >= W); the
 // sums of a wider window hold every offset of [0, W - 1]^d, so the radius-1
-// tables can be formed from the radius-2 pass.
-template <int D, int W, int WP = W>
+// tables can be formed from the radius-2 pass. WA: the window of the
+// (alpha, C) pair table written (WA > W: the WA^d layout, (0, 0) outside the
+// W window, so that rows of both radii read one layout).
+template <int D, int W, int WP = W, int WA = W>
 __device__ __forceinline__ void null_body(
     NullShared<D, W>& sh, int si, const int* __restrict__ nS, const double* __restrict__ part,
     int nblk, int sps, int nwv, double invN, double* gtab, double* gamtab, double* Mtab,
@@ -637,7 +639,34 @@ __device__ __forceinline__ void null_body(
     cv *= sgn;
     alpha_out[(int64_t)si * M + lane] = av;
     C_out[(int64_t)si * M + lane] = cv;
-    reinterpret_cast<double2*>(actab)[(int64_t)si * M + lane] = make_double2(av, cv);
+    if constexpr (WA == W)
+      reinterpret_cast<double2*>(actab)[(int64_t)si * M + lane] = make_double2(av, cv);
+  }
+  if constexpr (WA != W) {
+    // entry k of the WA^d layout (lane k + 64 h writes it) takes offset src
+    // of the W^d layout (same digit order, last axis fastest), or (0, 0)
+    static_assert(WA > W && (WA - W) % 2 == 0, "a wider, centred window");
+    constexpr int MA = Pow<D, WA>::v;
+    constexpr int dt = (WA - W) / 2;
+#pragma unroll
+    for (int h = 0; h < (MA + 63) / 64; ++h) {
+      const int k = lane + 64 * h;
+      int rem = k, src = 0, mul = 1;
+      bool in = k < MA;
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int oi = rem % WA - dt;
+        rem /= WA;
+        in = in && oi >= 0 && oi < W;
+        src += oi * mul;
+        mul *= W;
+      }
+      if (!in) src = 0;
+      const double a = __shfl(av, src), c = __shfl(cv, src);
+      if (k < MA)
+        reinterpret_cast<double2*>(actab)[(int64_t)si * MA + k] =
+            in ? make_double2(a, c) : make_double2(0.0, 0.0);
+    }
   }
   }
   if (wid != 0) return;
@@ -691,9 +720,9 @@ __global__ __launch_bounds__(64 * (1 << D)) void null_nd_kernel(
                     nwv, invN, t2.gtab, t2.gamtab, t2.Mtab, t2.alpha, t2.C, t2.sigma, t2.rho,
                     t2.actab, t2.status, nullptr);
   } else {
-    null_body<D, 3, 5>(*reinterpret_cast<NullShared<D, 3>*>(raw), blockIdx.x - nreq, nS, part,
-                       nblk, sps, nwv, invN, t1.gtab, t1.gamtab, t1.Mtab, t1.alpha, t1.C,
-                       t1.sigma, t1.rho, t1.actab, t1.status, nullptr);
+    null_body<D, 3, 5, 5>(*reinterpret_cast<NullShared<D, 3>*>(raw), blockIdx.x - nreq, nS,
+                          part, nblk, sps, nwv, invN, t1.gtab, t1.gamtab, t1.Mtab, t1.alpha,
+                          t1.C, t1.sigma, t1.rho, t1.actab, t1.status, nullptr);
   }
 }
 
